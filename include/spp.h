@@ -1,0 +1,165 @@
+/*
+ * spp.h -- C ABI of the MI355X sparsifying-preconditioner library.
+ *
+ * The library solves the periodic pseudospectral systems of
+ *   L. Ying, "Sparsifying preconditioner for pseudospectral approximations of
+ *   indefinite systems on periodic structures" (arXiv:1409.0297):
+ * the Helmholtz equation (-Delta - omega^2 / c(x)^2) u = f on [0,1)^d (eq. helm)
+ * and the rescaled Schroedinger equation (-Delta + ell^2 V(ell y) - ell^2 E) u = f
+ * (eq. schr), both written as (-Delta - s + q) u = f (eq. Dsq) and discretised
+ * on an n^d grid as (L - s + q) u = f (eq. Lsq).  It solves the equivalent
+ * integral form (I + G q) u = G f with G = (L - s)^{-1} (eq. G, Section 2.2)
+ * by flexible GMRES in FP64, right-preconditioned with M = P^{-1} Q, where Q
+ * is the sparsifying stencil operator and P = Q + C q its sparse truncation
+ * (Sections 2.2-2.3), factorised by nested-dissection multifrontal LU.
+ *
+ * Conventions for every entry point
+ *  - Grid functions are C-order arrays over j in [0,n)^d (last axis fastest).
+ *    Complex data is interleaved (re, im) double, i.e. C99 double complex.
+ *    A batch of nrhs grid functions is stored [nrhs][n^d].
+ *  - Pointers documented as DEVICE point to GPU memory owned by the caller
+ *    (typically allocated by PyTorch); HOST pointers to CPU memory.  The
+ *    library never frees caller memory.  It owns only what a spp_factor
+ *    holds (factors, stencils, work space), released by spp_destroy.
+ *  - All GPU work is ordered on the hipStream_t passed in (0 = the null
+ *    stream).  Calls returning host outputs synchronise that stream.
+ *  - Every function returns SPP_OK (0) or a negative error code; no C++
+ *    exception crosses this boundary.  spp_last_error() gives a message for
+ *    the most recent failure on the calling thread.
+ *  - A spp_factor is not thread-safe; distinct handles are independent.
+ */
+#ifndef SPP_H_
+#define SPP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* spp_stream_t; /* same type as hipStream_t */
+
+enum {
+  SPP_OK = 0,
+  SPP_EINVAL = -1,           /* bad dim/n/b, null pointer, non-finite input   */
+  SPP_ESINGULAR_SHIFT = -2,  /* L - s could not be moved off singularity      */
+  SPP_EBREAKDOWN = -3,       /* zero or non-finite pivot in a front           */
+  SPP_NOT_CONVERGED = -4,    /* max_iter reached; u, iters, relres still valid */
+  SPP_ENOMEM = -5,           /* device allocation failed                       */
+  SPP_EHIP = -6,             /* a HIP runtime call failed                      */
+  SPP_ENOTIMPL = -7          /* combination of options not implemented         */
+};
+
+typedef enum { SPP_HELMHOLTZ = 0, SPP_SCHRODINGER = 1 } spp_kind;
+
+/* Arithmetic of the frontal matrices and the triangular solves. */
+typedef enum {
+  SPP_C128 = 0,        /* complex128 fronts, FP64 MFMA                         */
+  SPP_C64_FRONTS = 1   /* complex64 fronts and substitution, FP32 MFMA; the
+                          operator apply, residuals and GMRES stay FP64        */
+} spp_prec;
+
+/* Order in which nested-dissection boxes merge above the leaves (Section 2.3,
+   Figure 1): all 2^d children at once, or two at a time along the axes in
+   turn.  Both give the same P^{-1}; they differ in front sizes. */
+typedef enum { SPP_ORDER_OCTREE = 0, SPP_ORDER_BISECT = 1 } spp_order;
+
+typedef struct {
+  int32_t dim;          /* d in {2, 3}                                          */
+  int32_t n;            /* grid points per axis; even                            */
+  int32_t b;            /* leaf box width in grid steps; b | n, n/b = 2^L >= 2   */
+  int32_t kind;         /* spp_kind                                              */
+  double omega;         /* Helmholtz frequency omega (eq. helm)                  */
+  double ell, energy;   /* Schroedinger size ell and energy E (eq. schr)         */
+  const double* coeff;  /* DEVICE, n^d reals: c(x_j) for Helmholtz,
+                           V(ell x_j) for Schroedinger; read during setup only   */
+} spp_problem;
+
+#define SPP_F_UNPRECONDITIONED 1  /* GMRES with M = I (for comparisons)        */
+
+typedef struct {
+  int32_t prec;         /* spp_prec                                              */
+  int32_t order;        /* spp_order                                             */
+  double tol;           /* stop when the GMRES residual estimate of
+                           (I + G q) u = G f is <= tol * ||G f||                 */
+  int32_t max_iter;     /* Krylov dimension limit (no restarts)                  */
+  int32_t flags;        /* SPP_F_* bits                                          */
+} spp_options;
+
+typedef struct {
+  double s;             /* shift actually used (after any perturbation)         */
+  int32_t shift_moves;  /* how many times s was perturbed (Section 2.2)          */
+  int32_t n_fronts, n_levels, max_front;
+  int64_t factor_entries;   /* sum over fronts of p^2 + 2 p (F - p)              */
+  int64_t factor_bytes;     /* bytes the substitution reads per application      */
+  double factor_flops;      /* real flops of the partial factorisations          */
+  double t_setup_ms;        /* wall time of the last spp_setup                   */
+  double t_factor_ms;       /* of which the multifrontal factorisation           */
+  double t_solve_ms;        /* wall time of the last spp_solve                   */
+  int32_t last_iters;       /* GMRES iterations of the last solve (max over RHS) */
+  int32_t breakdown_front;  /* front index of a pivot breakdown, else -1         */
+} spp_stats_t;
+
+typedef struct spp_factor spp_factor;
+
+/* ---- setup: a1-a6 ----------------------------------------------------------
+ * Computes s and q (eq. Dsq, with s the grid mean and the perturbation rule of
+ * Section 2.2), the Green kernel (eq. G), the stencils T_S and C_S of every
+ * set type (eq. Qc and Section 2.3), assembles P = Q + C q directly into the
+ * nested-dissection fronts and factorises them.  On success *out owns all
+ * device memory of the factor.  Errors: SPP_EINVAL (bad sizes, null pointers,
+ * non-finite coeff), SPP_ESINGULAR_SHIFT, SPP_EBREAKDOWN, SPP_ENOMEM, SPP_EHIP. */
+int spp_setup(const spp_problem* problem, const spp_options* options,
+              spp_stream_t stream, spp_factor** out);
+
+/* ---- solve: a7-a11 ---------------------------------------------------------
+ * f: DEVICE complex128 [nrhs][n^d]; u: DEVICE complex128 [nrhs][n^d], written.
+ * iters: HOST int32[nrhs]; relres: HOST double[nrhs], the true relative
+ * residual ||G f - (I + G q) u|| / ||G f|| of each returned u.
+ * Returns SPP_NOT_CONVERGED (u still written) if any RHS missed tol. */
+int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u,
+              int32_t* iters, double* relres, spp_stream_t stream);
+
+/* ---- components of the hot path, exposed for testing and benchmarking ----- */
+
+/* w = (I + G q) z (Section 2.2); z, w DEVICE complex128 [nrhs][n^d]; may alias. */
+int spp_apply_operator(spp_factor* factor, const void* z, void* w, int32_t nrhs,
+                       spp_stream_t stream);
+
+/* g = G f (eq. G); DEVICE complex128 [nrhs][n^d]; may alias. */
+int spp_apply_green(spp_factor* factor, const void* f, void* g, int32_t nrhs,
+                    spp_stream_t stream);
+
+/* y = Q r, (Q r)_S = r_S - T_S r_beta(S) (Section 2.3); DEVICE; must not alias. */
+int spp_apply_q(spp_factor* factor, const void* r, void* y, int32_t nrhs,
+                spp_stream_t stream);
+
+/* z = P^{-1} Q r, the preconditioner (Section 2.2); DEVICE; may alias. */
+int spp_apply_precond(spp_factor* factor, const void* r, void* z, int32_t nrhs,
+                      spp_stream_t stream);
+
+/* Shift s (HOST double) and potential q (DEVICE double[n^d], may be NULL). */
+int spp_get_coefficients(const spp_factor* factor, double* s, double* q);
+
+/* Stencil of set type `type` (bit i set = axis i pinned to a leaf box face,
+   so 0 is the cell and 2^d - 1 the vertex; Section 2.3).  All HOST outputs,
+   each may be NULL: nS = |S|, nB = |beta(S)|; offsets: int32[(nS+nB)*dim],
+   the grid offsets of S then beta(S) from the set's leaf box corner (the
+   column order of Q(S, gamma(S)) = [I  -T_S]); T: complex128 [nS][nB];
+   C: complex128 [nS][nS+nB] = [I  -T_S] G(gamma(S), gamma(S)). */
+int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t* nB,
+                    int32_t* offsets, void* T, void* C);
+
+int spp_stats(const spp_factor* factor, spp_stats_t* out);
+
+/* Releases everything the factor owns (synchronises its last stream). */
+void spp_destroy(spp_factor* factor);
+
+const char* spp_error_string(int code);
+const char* spp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPP_H_ */

@@ -1,0 +1,260 @@
+"""ctypes binding of include/spp.h: the same entry points, argument marshalling only.
+
+Device arrays are PyTorch CUDA tensors (ROCm); their data pointers and the
+current stream are handed to the C ABI unchanged.  Every computation happens
+in libspp.so.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+SPP_OK, SPP_EINVAL, SPP_ESINGULAR_SHIFT, SPP_EBREAKDOWN = 0, -1, -2, -3
+SPP_NOT_CONVERGED, SPP_ENOMEM, SPP_EHIP, SPP_ENOTIMPL = -4, -5, -6, -7
+SPP_HELMHOLTZ, SPP_SCHRODINGER = 0, 1
+SPP_C128, SPP_C64_FRONTS = 0, 1
+SPP_ORDER_OCTREE, SPP_ORDER_BISECT = 0, 1
+SPP_F_UNPRECONDITIONED = 1
+
+
+class spp_problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("kind", ctypes.c_int32), ("omega", ctypes.c_double), ("ell", ctypes.c_double),
+                ("energy", ctypes.c_double), ("coeff", ctypes.c_void_p)]
+
+
+class spp_options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("order", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class spp_stats_t(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_double), ("shift_moves", ctypes.c_int32),
+                ("n_fronts", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("max_front", ctypes.c_int32), ("factor_entries", ctypes.c_int64),
+                ("factor_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int32),
+                ("breakdown_front", ctypes.c_int32)]
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libspp.so")
+
+
+def library():
+    """Loads libspp.so once; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, None
+    sig = {
+        "spp_setup": (I, [ctypes.POINTER(spp_problem), ctypes.POINTER(spp_options), P, ctypes.POINTER(P)]),
+        "spp_solve": (I, [P, P, I, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),
+        "spp_apply_operator": (I, [P, P, P, I, P]),
+        "spp_apply_green": (I, [P, P, P, I, P]),
+        "spp_apply_q": (I, [P, P, P, I, P]),
+        "spp_apply_precond": (I, [P, P, P, I, P]),
+        "spp_get_coefficients": (I, [P, ctypes.POINTER(D), P]),
+        "spp_get_stencil": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P]),
+        "spp_stats": (I, [P, ctypes.POINTER(spp_stats_t)]),
+        "spp_destroy": (V, [P]),
+        "spp_error_string": (ctypes.c_char_p, [I]),
+        "spp_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class SppError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = library()
+        msg = f"{where}: {lib.spp_error_string(code).decode()} ({lib.spp_last_error().decode()})"
+        super().__init__(msg)
+        self.code = code
+
+
+def _check(code: int, where: str, allow=(SPP_OK,)):
+    if code not in allow:
+        raise SppError(code, where)
+    return code
+
+
+# ----------------------------------------------------------------- raw entry points
+def spp_setup(problem: spp_problem, options: spp_options, stream: int) -> int:
+    h = ctypes.c_void_p()
+    code = library().spp_setup(ctypes.byref(problem), ctypes.byref(options), ctypes.c_void_p(stream),
+                               ctypes.byref(h))
+    if code != SPP_OK and h.value:
+        library().spp_destroy(h)
+    _check(code, "spp_setup")
+    return h.value
+
+
+def spp_solve(handle, f_ptr, nrhs, u_ptr, stream):
+    iters = (ctypes.c_int32 * nrhs)()
+    relres = (ctypes.c_double * nrhs)()
+    code = library().spp_solve(handle, f_ptr, nrhs, u_ptr, iters, relres, ctypes.c_void_p(stream))
+    _check(code, "spp_solve", allow=(SPP_OK, SPP_NOT_CONVERGED))
+    return code, list(iters), list(relres)
+
+
+def _apply(name, handle, a_ptr, b_ptr, nrhs, stream):
+    _check(getattr(library(), name)(handle, a_ptr, b_ptr, nrhs, ctypes.c_void_p(stream)), name)
+
+
+def spp_apply_operator(handle, z_ptr, w_ptr, nrhs, stream):
+    _apply("spp_apply_operator", handle, z_ptr, w_ptr, nrhs, stream)
+
+
+def spp_apply_green(handle, f_ptr, g_ptr, nrhs, stream):
+    _apply("spp_apply_green", handle, f_ptr, g_ptr, nrhs, stream)
+
+
+def spp_apply_q(handle, r_ptr, y_ptr, nrhs, stream):
+    _apply("spp_apply_q", handle, r_ptr, y_ptr, nrhs, stream)
+
+
+def spp_apply_precond(handle, r_ptr, z_ptr, nrhs, stream):
+    _apply("spp_apply_precond", handle, r_ptr, z_ptr, nrhs, stream)
+
+
+def spp_get_coefficients(handle, q_ptr):
+    s = ctypes.c_double()
+    _check(library().spp_get_coefficients(handle, ctypes.byref(s), q_ptr), "spp_get_coefficients")
+    return s.value
+
+
+def spp_get_stencil(handle, set_type, offsets=None, T=None, C=None):
+    nS, nB = ctypes.c_int32(), ctypes.c_int32()
+    _check(library().spp_get_stencil(handle, set_type, ctypes.byref(nS), ctypes.byref(nB),
+                                     offsets, T, C), "spp_get_stencil")
+    return nS.value, nB.value
+
+
+def spp_stats(handle) -> dict:
+    st = spp_stats_t()
+    _check(library().spp_stats(handle, ctypes.byref(st)), "spp_stats")
+    return {name: getattr(st, name) for name, _ in spp_stats_t._fields_}
+
+
+def spp_destroy(handle):
+    if handle:
+        library().spp_destroy(handle)
+
+
+def spp_error_string(code: int) -> str:
+    return library().spp_error_string(code).decode()
+
+
+def spp_last_error() -> str:
+    return library().spp_last_error().decode()
+
+
+# ----------------------------------------------------------------- convenience wrapper
+class Solver:
+    """One factorised problem: setup(grid, omega or E, c or V) -> factor; solve(f) -> u.
+
+    ``coeff``: c(x_j) (Helmholtz) or V(ell x_j) (Schroedinger) as a float64
+    tensor of shape (n,)*d on the GPU (numpy arrays are copied there).
+    """
+
+    def __init__(self, kind: str, n: int, d: int, b: int, coeff, omega: float = 0.0,
+                 ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
+                 tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False):
+        import torch
+        self.torch = torch
+        self.n, self.d, self.b = n, d, b
+        self.N = n ** d
+        dev = torch.device("cuda")
+        c = torch.as_tensor(coeff, dtype=torch.float64, device=dev).contiguous()
+        self._coeff = c
+        pb = spp_problem(dim=d, n=n, b=b, kind=SPP_HELMHOLTZ if kind == "helmholtz" else SPP_SCHRODINGER,
+                         omega=omega, ell=ell, energy=energy, coeff=c.data_ptr())
+        op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,
+                         order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
+                         tol=tol, max_iter=max_iter,
+                         flags=SPP_F_UNPRECONDITIONED if unpreconditioned else 0)
+        self.handle = spp_setup(pb, op, self._stream())
+
+    def _stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def _vec(self, x):
+        t = self.torch.as_tensor(x, dtype=self.torch.complex128, device="cuda").contiguous()
+        return t.reshape(-1, self.N) if t.numel() % self.N == 0 else t
+
+    def _out(self, like):
+        return self.torch.empty_like(like)
+
+    def solve(self, f):
+        fv = self._vec(f)
+        u = self._out(fv)
+        code, iters, relres = spp_solve(self.handle, fv.data_ptr(), fv.shape[0], u.data_ptr(), self._stream())
+        return u, iters, relres, code
+
+    def apply_operator(self, z):
+        zv = self._vec(z)
+        w = self._out(zv)
+        spp_apply_operator(self.handle, zv.data_ptr(), w.data_ptr(), zv.shape[0], self._stream())
+        return w
+
+    def apply_green(self, f):
+        fv = self._vec(f)
+        g = self._out(fv)
+        spp_apply_green(self.handle, fv.data_ptr(), g.data_ptr(), fv.shape[0], self._stream())
+        return g
+
+    def apply_q(self, r):
+        rv = self._vec(r)
+        y = self._out(rv)
+        spp_apply_q(self.handle, rv.data_ptr(), y.data_ptr(), rv.shape[0], self._stream())
+        return y
+
+    def apply_precond(self, r):
+        rv = self._vec(r)
+        z = self._out(rv)
+        spp_apply_precond(self.handle, rv.data_ptr(), z.data_ptr(), rv.shape[0], self._stream())
+        return z
+
+    def coefficients(self):
+        q = self.torch.empty(self.N, dtype=self.torch.float64, device="cuda")
+        s = spp_get_coefficients(self.handle, q.data_ptr())
+        self.torch.cuda.synchronize()
+        return s, q
+
+    def stencil(self, set_type: int):
+        import numpy as np
+        nS, nB = spp_get_stencil(self.handle, set_type)
+        off = np.zeros((nS + nB, self.d), dtype=np.int32)
+        T = np.zeros((nS, nB), dtype=np.complex128)
+        C = np.zeros((nS, nS + nB), dtype=np.complex128)
+        spp_get_stencil(self.handle, set_type, off.ctypes.data, T.ctypes.data, C.ctypes.data)
+        return off, T, C
+
+    def stats(self) -> dict:
+        return spp_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            spp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,570 @@
+// C ABI of the library (include/spp.h): handle management, setup and solve
+// drivers.  Host code only; every arithmetic step runs in the HIP kernels.
+#include "spp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace spp {
+
+void throw_hip(hipError_t e, const char* what, const char* file, int line) {
+  std::string m = std::string(hipGetErrorString(e)) + " in " + what + " (" + file + ":" + std::to_string(line) + ")";
+  if (e == hipErrorOutOfMemory) throw Error(SPP_ENOMEM, m);
+  throw Error(SPP_EHIP, m);
+}
+
+}  // namespace spp
+
+using namespace spp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct spp_factor {
+  Plan plan;
+  int kind = 0;
+  double omega = 0, ell = 1, energy = 0;
+  spp_options opt{};
+  double s = 0;
+  int shift_moves = 0;
+  std::vector<void*> allocs;
+  // grid data
+  double* q = nullptr;
+  double* sigma = nullptr;
+  double2* tw = nullptr;
+  // stencils
+  StencilDev sten[8]{};
+  // plan on the device
+  MfDev mf{};
+  void* arena = nullptr;
+  size_t csize = 16;  // bytes per complex front entry
+  std::vector<int> level_begin, level_maxF, level_maxP;
+  // solve work (grown on demand)
+  int cap_rhs = 0, cap_iter = 0;
+  double2* tmp = nullptr;      // FFT scratch, nrhs * N
+  double2* qr = nullptr;       // Q r, nrhs * N
+  void* wv = nullptr;          // front vectors
+  void* zv = nullptr;
+  void* xc = nullptr;          // reduced-precision solve vector (complex64 fronts)
+  double2 *V = nullptr, *Z = nullptr, *H = nullptr, *gv = nullptr, *sn = nullptr, *y = nullptr, *g0 = nullptr,
+          *wk = nullptr, *h2 = nullptr, *dpart = nullptr;
+  double *cs = nullptr, *rpart = nullptr, *resid = nullptr, *norms = nullptr;
+  int* kvec = nullptr;
+  double* h_resid = nullptr;   // pinned host copy of residual estimates
+  spp_stats_t stats{};
+  hipStream_t last_stream = nullptr;
+
+  template <typename T> T* dalloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    SPP_HIP(hipMalloc(&p, count * sizeof(T)));
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) allocs.erase(it);
+    (void)hipFree(p);
+  }
+  ~spp_factor() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_resid) (void)hipHostFree(h_resid);
+  }
+};
+
+namespace {
+
+int fail(const Error& e) {
+  g_last_error = e.what();
+  return e.code;
+}
+
+template <typename F> int guarded(F&& fn) {
+  try {
+    return fn();
+  } catch (const Error& e) {
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return SPP_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return SPP_EHIP;
+  }
+}
+
+// min over the Fourier grid of |4 pi^2 |k|^2 - s| / |s| (how close L - s is to singular).
+double shift_gap(int d, int n, double s) {
+  const double c = 4.0 * M_PI * M_PI;
+  double best = INFINITY;
+  const int h = n / 2;
+  if (d == 2) {
+    for (int a = -h; a < h; ++a)
+      for (int b = -h; b < h; ++b) best = std::min(best, std::fabs(c * (double)(a * a + b * b) - s));
+  } else {
+    for (int a = -h; a < h; ++a)
+      for (int b = -h; b < h; ++b) {
+        const double rest = s / c - (double)(a * a + b * b);
+        // nearest k3^2 to rest
+        int k3 = rest > 0 ? (int)std::floor(std::sqrt(rest)) : 0;
+        for (int t = std::max(0, k3 - 1); t <= std::min(h, k3 + 2); ++t)
+          best = std::min(best, std::fabs(c * (double)(a * a + b * b + t * t) - s));
+      }
+  }
+  return best / std::fabs(s);
+}
+
+void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
+  if (nrhs <= F->cap_rhs && iters <= F->cap_iter) return;
+  const int r = std::max(nrhs, F->cap_rhs), it = std::max(iters, F->cap_iter);
+  for (void* p : {(void*)F->tmp, (void*)F->qr, F->wv, F->zv, F->xc, (void*)F->V, (void*)F->Z, (void*)F->H,
+                  (void*)F->gv, (void*)F->sn, (void*)F->y, (void*)F->g0, (void*)F->wk, (void*)F->h2,
+                  (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec})
+    F->dfree(p);
+  if (F->h_resid) { (void)hipHostFree(F->h_resid); F->h_resid = nullptr; }
+  const int64_t N = F->plan.N;
+  F->tmp = F->dalloc<double2>((size_t)r * N);
+  F->qr = F->dalloc<double2>((size_t)r * N);
+  F->wv = F->dalloc<char>((size_t)F->plan.vec_elems * r * F->csize);
+  F->zv = F->dalloc<char>((size_t)F->plan.vec_elems * r * F->csize);
+  F->xc = F->dalloc<char>((size_t)N * r * F->csize);
+  F->V = F->dalloc<double2>((size_t)(it + 1) * r * N);
+  F->Z = F->dalloc<double2>((size_t)it * r * N);
+  const size_t ld = it + 1;
+  F->H = F->dalloc<double2>(ld * it * r);
+  F->gv = F->dalloc<double2>(ld * r);
+  F->sn = F->dalloc<double2>(ld * r);
+  F->y = F->dalloc<double2>(ld * r);
+  F->cs = F->dalloc<double>(ld * r);
+  F->g0 = F->dalloc<double2>((size_t)r * N);
+  F->wk = F->dalloc<double2>((size_t)r * N);
+  F->h2 = F->dalloc<double2>(ld * r);
+  const int64_t nblk = (N + 1023) / 1024;
+  F->dpart = F->dalloc<double2>((size_t)nblk * r * (it + 1));
+  F->rpart = F->dalloc<double>((size_t)(256 + 1) * r + 64);
+  F->resid = F->dalloc<double>(r);
+  F->norms = F->dalloc<double>(r);
+  F->kvec = F->dalloc<int>(r);
+  SPP_HIP(hipHostMalloc(reinterpret_cast<void**>(&F->h_resid), sizeof(double) * r));
+  F->cap_rhs = r;
+  F->cap_iter = it;
+}
+
+void apply_operator(spp_factor* F, const double2* z, double2* w, int nrhs, hipStream_t st) {
+  fft_multi(st, z, w, F->tmp, F->tw, F->plan.d, F->plan.n, nrhs, F->q, F->sigma, z);
+}
+
+void apply_green(spp_factor* F, const double2* f, double2* g, int nrhs, hipStream_t st) {
+  fft_multi(st, f, g, F->tmp, F->tw, F->plan.d, F->plan.n, nrhs, nullptr, F->sigma, nullptr);
+}
+
+void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st) {
+  q_apply(st, F->mf, r, F->qr, nrhs);
+  const int nl = static_cast<int>(F->plan.levels.size());
+  if (F->opt.prec == SPP_C128) {
+    mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(),
+                     F->level_maxF.data(), F->level_maxP.data(), nl);
+  } else {
+    const int64_t cnt = (int64_t)nrhs * F->plan.N;
+    cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
+    mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(),
+                    F->level_maxF.data(), F->level_maxP.data(), nl);
+    cast_vectors<float>(st, F->xc, z, cnt, 1);
+  }
+}
+
+int do_setup(const spp_problem* pb, const spp_options* op, hipStream_t st, spp_factor** out) {
+  if (!pb || !op || !out) throw Error(SPP_EINVAL, "null argument");
+  *out = nullptr;
+  if (!pb->coeff) throw Error(SPP_EINVAL, "coeff is null");
+  if (pb->kind != SPP_HELMHOLTZ && pb->kind != SPP_SCHRODINGER) throw Error(SPP_EINVAL, "unknown problem kind");
+  if (op->prec != SPP_C128 && op->prec != SPP_C64_FRONTS) throw Error(SPP_EINVAL, "unknown precision");
+  if (op->order != SPP_ORDER_OCTREE && op->order != SPP_ORDER_BISECT) throw Error(SPP_EINVAL, "unknown ordering");
+  if (!(op->tol > 0) || op->max_iter < 1 || op->max_iter > 500) throw Error(SPP_EINVAL, "tol > 0 and 1 <= max_iter <= 500");
+  if (pb->kind == SPP_HELMHOLTZ && !(std::isfinite(pb->omega) && pb->omega > 0)) throw Error(SPP_EINVAL, "omega");
+  if (pb->kind == SPP_SCHRODINGER && !(std::isfinite(pb->ell) && pb->ell > 0 && std::isfinite(pb->energy)))
+    throw Error(SPP_EINVAL, "ell / energy");
+  if (!fft_supported(pb->n)) throw Error(SPP_EINVAL, "n must be of the form 2^a 3^b");
+  const double t0 = now_ms();
+  auto F = std::make_unique<spp_factor>();
+  F->kind = pb->kind;
+  F->omega = pb->omega;
+  F->ell = pb->ell;
+  F->energy = pb->energy;
+  F->opt = *op;
+  F->csize = (op->prec == SPP_C128) ? sizeof(double2) : sizeof(float2);
+  F->last_stream = st;
+  std::string err = build_plan(pb->dim, pb->n, pb->b, op->order, F->plan);
+  if (!err.empty()) throw Error(SPP_EINVAL, err);
+  const Plan& P = F->plan;
+  const int d = P.d, n = P.n;
+  const int64_t N = P.N;
+
+  // a1: shift and potential (eq. Dsq).
+  F->q = F->dalloc<double>(N);
+  F->sigma = F->dalloc<double>(N);
+  F->tw = F->dalloc<double2>(n);
+  fft_make_twiddles(F->tw, n, st);
+  const int nblk = coeff_reduce_blocks(N);
+  double* red = F->dalloc<double>(2 * nblk + 2);
+  coeff_reduce(st, pb->kind, pb->coeff, N, pb->omega, pb->ell, red, nblk, red + 2 * nblk);
+  double hred[2];
+  SPP_HIP(hipMemcpyAsync(hred, red + 2 * nblk, sizeof(hred), hipMemcpyDeviceToHost, st));
+  SPP_HIP(hipStreamSynchronize(st));
+  F->dfree(red);
+  if (hred[1] != 0) throw Error(SPP_EINVAL, "coeff has non-finite (or, for Helmholtz, non-positive) entries");
+  const double mean_w = hred[0] / (double)N;
+  double s = (pb->kind == SPP_HELMHOLTZ) ? mean_w : pb->ell * pb->ell * pb->energy - mean_w;
+  int moves = 0;
+  while (shift_gap(d, n, s) < 1e-6) {
+    if (moves == 10) throw Error(SPP_ESINGULAR_SHIFT, "L - s stays singular after 10 perturbations");
+    s += 4.0 * M_PI * M_PI * 1e-3;
+    ++moves;
+  }
+  F->s = s;
+  F->shift_moves = moves;
+  double2* sig_c = F->dalloc<double2>(N);
+  double2* sig2_c = F->dalloc<double2>(N);
+  coeff_finish(st, pb->kind, pb->coeff, N, d, n, pb->omega, pb->ell, pb->energy, s, F->q, F->sigma, sig_c, sig2_c);
+
+  // a2: kernels of G and G G^H.
+  double2* g = F->dalloc<double2>(N);
+  double2* g2 = F->dalloc<double2>(N);
+  fft_inverse_all(st, sig_c, g, F->tw, d, n);
+  fft_inverse_all(st, sig2_c, g2, F->tw, d, n);
+  F->dfree(sig_c);
+  F->dfree(sig2_c);
+
+  // a3-a4: stencils per set type.
+  int* info = F->dalloc<int>(64);
+  SPP_HIP(hipMemsetAsync(info, 0, 64 * sizeof(int), st));
+  size_t work_elems = 0;
+  for (const SetType& T : P.types)
+    work_elems = std::max(work_elems, (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS));
+  double2* swork = F->dalloc<double2>(work_elems);
+  for (size_t t = 0; t < P.types.size(); ++t) {
+    const SetType& T = P.types[t];
+    StencilDev& S = F->sten[t];
+    S.nS = T.nS; S.nB = T.nB; S.nG = T.nG;
+    int* off = F->dalloc<int>(T.off.size());
+    SPP_HIP(hipMemcpyAsync(off, T.off.data(), T.off.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    S.off = off;
+    S.T = F->dalloc<double2>((size_t)T.nS * T.nB);
+    S.C = F->dalloc<double2>((size_t)T.nS * T.nG);
+    S.Tt = F->dalloc<double2>((size_t)T.nS * T.nB);
+    stencil_build(st, d, n, g, g2, S, swork, info + 1 + (int)t);
+  }
+  F->dfree(g);
+  F->dfree(g2);
+
+  // a5-a6: plan upload, assembly and factorisation.
+  std::vector<FrontDev> fd(P.fronts.size());
+  int perm_total = 0;
+  int64_t xwork_elems = 0;
+  for (const Level& L : P.levels) {
+    int64_t xo = 0;
+    for (int fi = L.begin; fi < L.end; ++fi) {
+      const Front& f = P.fronts[fi];
+      FrontDev& g_ = fd[fi];
+      g_.off = f.off; g_.voff = f.voff; g_.xoff = xo;
+      g_.F = f.F; g_.p = f.p; g_.idx = f.idx; g_.map = f.map; g_.perm = perm_total;
+      g_.nchild = static_cast<int>(f.children.size());
+      if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
+      for (int c = 0; c < g_.nchild; ++c) g_.child[c] = f.children[c];
+      perm_total += f.p;
+      xo += 2LL * f.p * f.p;
+    }
+    xwork_elems = std::max(xwork_elems, xo);
+  }
+  std::vector<AsmBlockDev> bd(P.blocks.size());
+  for (size_t i = 0; i < P.blocks.size(); ++i)
+    bd[i] = AsmBlockDev{P.blocks[i].front, P.blocks[i].type, P.blocks[i].anchor, P.blocks[i].rowpos, P.blocks[i].colpos};
+  auto upload = [&](const void* src, size_t bytes) {
+    void* p = F->dalloc<char>(bytes);
+    SPP_HIP(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, st));
+    return p;
+  };
+  MfDev& mf = F->mf;
+  mf.d = d; mf.n = n; mf.b = P.b; mf.m = P.m; mf.N = N;
+  mf.fronts = static_cast<const FrontDev*>(upload(fd.data(), fd.size() * sizeof(FrontDev)));
+  mf.blocks = static_cast<const AsmBlockDev*>(upload(bd.data(), bd.size() * sizeof(AsmBlockDev)));
+  mf.pos = static_cast<const int*>(upload(P.pos.data(), P.pos.size() * sizeof(int)));
+  mf.idx = static_cast<const int*>(upload(P.idx.data(), P.idx.size() * sizeof(int)));
+  mf.map = static_cast<const int*>(upload(P.map.data(), std::max<size_t>(1, P.map.size()) * sizeof(int)));
+  mf.perm = F->dalloc<int>(perm_total);
+  mf.ipiv = F->dalloc<int>(perm_total);
+  mf.q = F->q;
+  mf.info = info;
+  for (size_t t = 0; t < P.types.size(); ++t) {
+    const StencilDev& S = F->sten[t];
+    mf.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt};
+  }
+  F->level_begin.clear();
+  for (const Level& L : P.levels) {
+    F->level_begin.push_back(L.begin);
+    F->level_maxF.push_back(L.maxF);
+    F->level_maxP.push_back(L.maxP);
+  }
+  F->level_begin.push_back(static_cast<int>(P.fronts.size()));
+
+  F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
+  void* xwork = F->dalloc<char>((size_t)xwork_elems * F->csize);
+  SPP_HIP(hipStreamSynchronize(st));
+  const double tf0 = now_ms();
+  for (size_t l = 0; l < P.levels.size(); ++l) {
+    const Level& L = P.levels[l];
+    const Front& first = P.fronts[L.begin];
+    const Front& last = P.fronts[L.end - 1];
+    const int64_t span = last.off + (int64_t)last.F * last.F - first.off;
+    SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + first.off * F->csize, 0, span * F->csize, st));
+    if (F->opt.prec == SPP_C128)
+      mf_factor_level<double>(st, mf, F->arena, xwork, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
+                              L.max_children, l > 0 ? P.levels[l - 1].begin : 0);
+    else
+      mf_factor_level<float>(st, mf, F->arena, xwork, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
+                             L.max_children, l > 0 ? P.levels[l - 1].begin : 0);
+  }
+  int hinfo[16];
+  SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  SPP_HIP(hipStreamSynchronize(st));
+  const double tf1 = now_ms();
+  F->dfree(xwork);
+  F->dfree(swork);
+  for (size_t t = 0; t < P.types.size(); ++t)
+    if (hinfo[1 + t]) throw Error(SPP_EBREAKDOWN, "singular Gram matrix in the stencil least-squares problem");
+  F->stats.breakdown_front = hinfo[0] ? hinfo[0] - 1 : -1;
+  F->stats.s = s;
+  F->stats.shift_moves = moves;
+  F->stats.n_fronts = static_cast<int>(P.fronts.size());
+  F->stats.n_levels = static_cast<int>(P.levels.size());
+  F->stats.max_front = P.max_front;
+  F->stats.factor_entries = P.factor_entries;
+  F->stats.factor_bytes = P.factor_entries * (int64_t)F->csize;
+  F->stats.factor_flops = P.factor_flops;
+  F->stats.t_factor_ms = tf1 - tf0;
+  F->stats.t_setup_ms = now_ms() - t0;
+  F->stats.last_iters = 0;
+  if (hinfo[0]) {
+    g_last_error = "zero or non-finite pivot in front " + std::to_string(hinfo[0] - 1);
+    *out = F.release();
+    return SPP_EBREAKDOWN;
+  }
+  *out = F.release();
+  return SPP_OK;
+}
+
+int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, double* relres, hipStream_t st) {
+  if (!F || !fv || !uv || !iters || !relres || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
+  const double t0 = now_ms();
+  F->last_stream = st;
+  const int maxit = F->opt.max_iter;
+  ensure_solve_buffers(F, nrhs, maxit);
+  const int64_t N = F->plan.N;
+  const int64_t vstride = (int64_t)nrhs * N;
+  const int ld = F->cap_iter + 1;           // Hessenberg column stride and per-RHS vector stride
+  const int hrhs = ld * F->cap_iter;        // Hessenberg stride between right-hand sides
+  const double2* f = static_cast<const double2*>(fv);
+  double2* u = static_cast<double2*>(uv);
+  const bool precond = !(F->opt.flags & SPP_F_UNPRECONDITIONED);
+
+  // a7: g = G f; beta = ||g||.
+  apply_green(F, f, F->g0, nrhs, st);
+  kr_norms(st, F->g0, nrhs, N, F->rpart, F->norms);
+  std::vector<double> beta(nrhs);
+  SPP_HIP(hipMemcpyAsync(beta.data(), F->norms, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  kr_scale_init(st, F->g0, F->V, F->norms, nrhs, N, F->gv, ld);
+  SPP_HIP(hipStreamSynchronize(st));
+  std::vector<int> k(nrhs, 0);
+  int done = 0;
+  for (int r = 0; r < nrhs; ++r)
+    if (beta[r] == 0) { k[r] = 0; ++done; }
+  std::vector<bool> conv(nrhs, false);
+  for (int r = 0; r < nrhs; ++r) conv[r] = beta[r] == 0;
+  int j = 0;
+  for (; j < maxit && done < nrhs; ++j) {
+    double2* vj = F->V + (int64_t)j * vstride;
+    double2* zj = F->Z + (int64_t)j * vstride;
+    // a9: z_j = M v_j
+    if (precond) apply_precond(F, vj, zj, nrhs, st);
+    else SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
+    // a8: w = (I + G q) z_j
+    apply_operator(F, zj, F->wk, nrhs, st);
+    // CGS2 against v_0 .. v_j; H(:, j) per right-hand side.
+    double2* hcol = F->H + (int64_t)j * ld;
+    kr_dots(st, F->V, vstride, j + 1, F->wk, nrhs, N, F->dpart, hcol, hrhs, 0, nullptr, 0);
+    kr_update(st, F->V, vstride, j + 1, F->wk, nrhs, N, hcol, hrhs);
+    kr_dots(st, F->V, vstride, j + 1, F->wk, nrhs, N, F->dpart, F->h2, ld, 0, hcol, hrhs);
+    kr_update(st, F->V, vstride, j + 1, F->wk, nrhs, N, F->h2, ld);
+    kr_norm_scale(st, F->wk, F->V + (int64_t)(j + 1) * vstride, nrhs, N, F->rpart, hcol + (j + 1), hrhs);
+    // a10: Givens update of the least-squares problem.
+    kr_givens(st, F->H, ld, hrhs, F->cs, F->sn, F->gv, j, nrhs, ld, F->resid, nullptr);
+    SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    SPP_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) {
+      if (conv[r]) continue;
+      if (!(F->h_resid[r] > F->opt.tol * beta[r])) {
+        conv[r] = true;
+        k[r] = j + 1;
+        ++done;
+      }
+    }
+  }
+  bool all_conv = true;
+  for (int r = 0; r < nrhs; ++r)
+    if (!conv[r]) { k[r] = j; all_conv = false; }
+  // a11: u = Z y, then the true residual ||g - (I + G q) u|| / ||g||.
+  SPP_HIP(hipMemcpyAsync(F->kvec, k.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+  kr_backsolve(st, F->H, ld, hrhs, F->gv, ld, F->y, 0, nrhs, F->kvec);
+  kr_combine(st, F->Z, vstride, std::max(1, *std::max_element(k.begin(), k.end())), F->y, ld, u, nrhs, N, F->kvec);
+  apply_operator(F, u, F->wk, nrhs, st);
+  kr_sub(st, F->g0, F->wk, F->wk, vstride);
+  kr_norms(st, F->wk, nrhs, N, F->rpart, F->norms);
+  std::vector<double> rn(nrhs);
+  SPP_HIP(hipMemcpyAsync(rn.data(), F->norms, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  SPP_HIP(hipStreamSynchronize(st));
+  int kmax = 0;
+  for (int r = 0; r < nrhs; ++r) {
+    iters[r] = k[r];
+    relres[r] = beta[r] > 0 ? rn[r] / beta[r] : 0.0;
+    kmax = std::max(kmax, k[r]);
+  }
+  F->stats.last_iters = kmax;
+  F->stats.t_solve_ms = now_ms() - t0;
+  if (!all_conv) {
+    g_last_error = "GMRES reached max_iter before the tolerance";
+    return SPP_NOT_CONVERGED;
+  }
+  return SPP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spp_setup(const spp_problem* problem, const spp_options* options, spp_stream_t stream, spp_factor** out) {
+  return guarded([&] { return do_setup(problem, options, reinterpret_cast<hipStream_t>(stream), out); });
+}
+
+int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u, int32_t* iters, double* relres,
+              spp_stream_t stream) {
+  return guarded([&] { return do_solve(factor, f, nrhs, u, iters, relres, reinterpret_cast<hipStream_t>(stream)); });
+}
+
+int spp_apply_operator(spp_factor* factor, const void* z, void* w, int32_t nrhs, spp_stream_t stream) {
+  return guarded([&] {
+    if (!factor || !z || !w || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
+    ensure_solve_buffers(factor, nrhs, factor->opt.max_iter);
+    apply_operator(factor, static_cast<const double2*>(z), static_cast<double2*>(w), nrhs,
+                   reinterpret_cast<hipStream_t>(stream));
+    return SPP_OK;
+  });
+}
+
+int spp_apply_green(spp_factor* factor, const void* f, void* g, int32_t nrhs, spp_stream_t stream) {
+  return guarded([&] {
+    if (!factor || !f || !g || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
+    ensure_solve_buffers(factor, nrhs, factor->opt.max_iter);
+    apply_green(factor, static_cast<const double2*>(f), static_cast<double2*>(g), nrhs,
+                reinterpret_cast<hipStream_t>(stream));
+    return SPP_OK;
+  });
+}
+
+int spp_apply_q(spp_factor* factor, const void* r, void* y, int32_t nrhs, spp_stream_t stream) {
+  return guarded([&] {
+    if (!factor || !r || !y || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
+    if (r == y) throw Error(SPP_EINVAL, "spp_apply_q: r and y must not alias");
+    q_apply(reinterpret_cast<hipStream_t>(stream), factor->mf, static_cast<const double2*>(r),
+            static_cast<double2*>(y), nrhs);
+    return SPP_OK;
+  });
+}
+
+int spp_apply_precond(spp_factor* factor, const void* r, void* z, int32_t nrhs, spp_stream_t stream) {
+  return guarded([&] {
+    if (!factor || !r || !z || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
+    ensure_solve_buffers(factor, nrhs, factor->opt.max_iter);
+    apply_precond(factor, static_cast<const double2*>(r), static_cast<double2*>(z), nrhs,
+                  reinterpret_cast<hipStream_t>(stream));
+    return SPP_OK;
+  });
+}
+
+int spp_get_coefficients(const spp_factor* factor, double* s, double* q) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (s) *s = factor->s;
+    if (q) {
+      SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * factor->plan.N, hipMemcpyDeviceToDevice));
+    }
+    return SPP_OK;
+  });
+}
+
+int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t* nB, int32_t* offsets, void* T,
+                    void* C) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (type < 0 || type >= (1 << factor->plan.d)) throw Error(SPP_EINVAL, "set type out of range");
+    const SetType& ST = factor->plan.types[type];
+    const StencilDev& S = factor->sten[type];
+    if (nS) *nS = ST.nS;
+    if (nB) *nB = ST.nB;
+    if (offsets) std::memcpy(offsets, ST.off.data(), ST.off.size() * sizeof(int));
+    if (T) SPP_HIP(hipMemcpy(T, S.T, sizeof(double2) * ST.nS * ST.nB, hipMemcpyDeviceToHost));
+    if (C) SPP_HIP(hipMemcpy(C, S.C, sizeof(double2) * ST.nS * ST.nG, hipMemcpyDeviceToHost));
+    return SPP_OK;
+  });
+}
+
+int spp_stats(const spp_factor* factor, spp_stats_t* out) {
+  return guarded([&] {
+    if (!factor || !out) throw Error(SPP_EINVAL, "null argument");
+    *out = factor->stats;
+    return SPP_OK;
+  });
+}
+
+void spp_destroy(spp_factor* factor) {
+  if (!factor) return;
+  if (factor->last_stream) (void)hipStreamSynchronize(factor->last_stream);
+  else (void)hipDeviceSynchronize();
+  delete factor;
+}
+
+const char* spp_error_string(int code) {
+  switch (code) {
+    case SPP_OK: return "success";
+    case SPP_EINVAL: return "invalid argument";
+    case SPP_ESINGULAR_SHIFT: return "L - s is singular and could not be perturbed away";
+    case SPP_EBREAKDOWN: return "pivot breakdown in a frontal matrix";
+    case SPP_NOT_CONVERGED: return "GMRES did not reach the tolerance";
+    case SPP_ENOMEM: return "out of device memory";
+    case SPP_EHIP: return "HIP runtime error";
+    case SPP_ENOTIMPL: return "not implemented";
+    default: return "unknown error";
+  }
+}
+
+const char* spp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// Complex FP64 FFT passes for the pseudospectral operator (Section 2.1, eq. G).
+//
+// One kernel transforms all grid lines along one axis of a [batch][outer][n][inner]
+// array: each workgroup stages L lines in LDS (coalesced: along the line when
+// inner == 1, across neighbouring lines otherwise), runs a mixed radix-4/2/3
+// Stockham autosort FFT in LDS, and writes the lines back.  Optional fused
+// pointwise work at the edges of the pass:
+//   pre  : multiply the input by a real grid function (q in q .* z),
+//   mid  : forward transform, multiply by a real array in Fourier order
+//          (sigma_k / N), inverse transform -- the whole of G along the last
+//          axis pass of a multi-axis transform,
+//   add  : output = add + result (the "z +" of (I + G q) z).
+// Forward and inverse transforms are unnormalised; the 1/N of the unitary
+// pair F^{-1} (.) F is folded into the sigma array.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spp {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kMaxStages = 12;
+
+struct FftArgs {
+  int n;
+  int L;             // lines per workgroup
+  int64_t outer, inner;
+  int64_t N;         // grid size (batch stride)
+  int nstages;
+  int radix[kMaxStages];
+};
+
+__device__ inline double2 twiddle(const double2* tw, int m, int dir) {
+  double2 w = tw[m];
+  if (dir > 0) w.y = -w.y;
+  return w;
+}
+
+// One Stockham stage of radix R over L lines of length n held in LDS.
+template <int R>
+__device__ void stockham_stage(const double2* __restrict__ x, double2* __restrict__ y, int n, int L,
+                               int Ns, int dir, const double2* __restrict__ tw) {
+  const int nb = n / R;              // butterflies per line
+  const int stride_tw = n / (Ns * R);
+  for (int t = threadIdx.x; t < L * nb; t += blockDim.x) {
+    const int line = t / nb;
+    const int j = t - line * nb;
+    const double2* xl = x + line * n;
+    double2* yl = y + line * n;
+    const int k = j % Ns;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = xl[j + r * nb];
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle(tw, (r * k * stride_tw) % n, dir));
+    double2 o[R];
+    if constexpr (R == 2) {
+      o[0] = cadd(v[0], v[1]);
+      o[1] = csub(v[0], v[1]);
+    } else if constexpr (R == 4) {
+      // i^(dir) rotation: forward uses -i, inverse +i.
+      double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+      double2 c = cadd(v[1], v[3]), e = csub(v[1], v[3]);
+      double2 ie = (dir < 0) ? cmake<double2>(e.y, -e.x) : cmake<double2>(-e.y, e.x);
+      o[0] = cadd(a, c);
+      o[1] = cadd(b, ie);
+      o[2] = csub(a, c);
+      o[3] = csub(b, ie);
+    } else {  // R == 3
+      const double c1 = -0.5;
+      const double s1 = (dir < 0 ? -1.0 : 1.0) * 0.86602540378443864676;
+      double2 sum = cadd(v[1], v[2]), dif = csub(v[1], v[2]);
+      double2 m1 = cmake<double2>(v[0].x + c1 * sum.x, v[0].y + c1 * sum.y);
+      double2 m2 = cmake<double2>(-s1 * dif.y, s1 * dif.x);   // i s1 (v1 - v2)
+      o[0] = cadd(v[0], sum);
+      o[1] = cadd(m1, m2);
+      o[2] = csub(m1, m2);
+    }
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) yl[base + r * Ns] = o[r];
+  }
+}
+
+// Runs all stages; data starts in a, returns the buffer holding the result.
+__device__ double2* fft_lines(double2* a, double2* b, const FftArgs& g, int dir, const double2* tw) {
+  int Ns = 1;
+  for (int s = 0; s < g.nstages; ++s) {
+    const int R = g.radix[s];
+    __syncthreads();
+    if (R == 4) stockham_stage<4>(a, b, g.n, g.L, Ns, dir, tw);
+    else if (R == 2) stockham_stage<2>(a, b, g.n, g.L, Ns, dir, tw);
+    else stockham_stage<3>(a, b, g.n, g.L, Ns, dir, tw);
+    Ns *= R;
+    double2* t = a; a = b; b = t;
+  }
+  __syncthreads();
+  return a;
+}
+
+__global__ void __launch_bounds__(kFftThreads)
+fft_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw, FftArgs g,
+                int dir, const double* __restrict__ pre, const double* __restrict__ mid,
+                const double2* add) {
+  extern __shared__ double2 lds[];
+  double2* A = lds;
+  double2* B = lds + g.L * g.n;
+  const int64_t lines_per_batch = g.outer * g.inner;
+  const int64_t wg_per_batch = lines_per_batch / g.L;
+  const int64_t batch = blockIdx.x / wg_per_batch;
+  const int64_t line0 = (blockIdx.x - batch * wg_per_batch) * g.L;
+  const int64_t bofs = batch * g.N;
+  const int total = g.L * g.n;
+
+  auto addr = [&](int li, int k) -> int64_t {   // grid index (within one batch entry)
+    const int64_t line = line0 + li;
+    const int64_t o = line / g.inner, i = line - o * g.inner;
+    return o * g.n * g.inner + (int64_t)k * g.inner + i;
+  };
+  auto unpack = [&](int t, int& li, int& k) {
+    if (g.inner == 1) { li = t / g.n; k = t - li * g.n; }
+    else { k = t / g.L; li = t - k * g.L; }
+  };
+
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int li, k;
+    unpack(t, li, k);
+    const int64_t a = addr(li, k);
+    double2 v = in[bofs + a];
+    if (pre) { const double s = pre[a]; v.x *= s; v.y *= s; }
+    A[li * g.n + k] = v;
+  }
+  double2* res = fft_lines(A, B, g, dir, tw);
+  if (mid) {
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+      int li, k;
+      unpack(t, li, k);
+      const double s = mid[addr(li, k)];
+      double2& v = res[li * g.n + k];
+      v.x *= s; v.y *= s;
+    }
+    double2* other = (res == A) ? B : A;
+    res = fft_lines(res, other, g, -dir, tw);
+  }
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    int li, k;
+    unpack(t, li, k);
+    const int64_t a = addr(li, k);
+    double2 v = res[li * g.n + k];
+    if (add) v = cadd(v, add[bofs + a]);
+    out[bofs + a] = v;
+  }
+}
+
+__global__ void twiddle_kernel(double2* tw, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n) {
+    double s, c;
+    sincospi(2.0 * m / n, &s, &c);
+    tw[m] = cmake<double2>(c, -s);   // exp(-2 pi i m / n)
+  }
+}
+
+}  // namespace
+
+void fft_make_twiddles(double2* tw, int n, hipStream_t st) {
+  twiddle_kernel<<<ceil_div(n, 256), 256, 0, st>>>(tw, n);
+  SPP_LAUNCH_CHECK();
+}
+
+bool fft_supported(int n) {
+  while (n % 4 == 0) n /= 4;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw, int n,
+              int64_t outer, int64_t inner, int64_t N, int batch, int dir,
+              const double* pre, const double* mid, const double2* add) {
+  FftArgs g{};
+  g.n = n;
+  g.outer = outer;
+  g.inner = inner;
+  g.N = N;
+  int m = n, s = 0;
+  while (m % 4 == 0) { g.radix[s++] = 4; m /= 4; }
+  while (m % 2 == 0) { g.radix[s++] = 2; m /= 2; }
+  while (m % 3 == 0) { g.radix[s++] = 3; m /= 3; }
+  if (m != 1 || s > kMaxStages) throw Error(-7, "FFT length must be 2^a 3^b");
+  g.nstages = s;
+  // Lines per workgroup: fill ~2048 points of LDS per buffer, keep coalescing.
+  int L = 1;
+  while (2 * L * n <= 2048) L *= 2;
+  const int64_t lines = outer * inner;
+  while (L > 1 && (lines % L || (inner > 1 && inner % L))) L /= 2;
+  g.L = L;
+  const size_t lds = 2 * sizeof(double2) * L * n;
+  const unsigned blocks = static_cast<unsigned>(batch * (lines / L));
+  fft_axis_kernel<<<blocks, kFftThreads, lds, st>>>(in, out, tw, g, dir, pre, mid, add);
+  SPP_LAUNCH_CHECK();
+}
+
+// (I + G q) z, G f, or plain transforms, over all d axes of [batch][n]^d.
+void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, const double2* tw,
+               int d, int n, int batch, const double* pre, const double* sigma, const double2* add) {
+  const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
+  if (d == 2) {
+    fft_axis(st, in, tmp, tw, n, n, 1, N, batch, -1, pre, nullptr, nullptr);
+    fft_axis(st, tmp, tmp, tw, n, 1, n, N, batch, -1, nullptr, sigma, nullptr);
+    fft_axis(st, tmp, out, tw, n, n, 1, N, batch, +1, nullptr, nullptr, add);
+  } else {
+    fft_axis(st, in, tmp, tw, n, (int64_t)n * n, 1, N, batch, -1, pre, nullptr, nullptr);
+    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, -1, nullptr, nullptr, nullptr);
+    fft_axis(st, tmp, tmp, tw, n, 1, (int64_t)n * n, N, batch, -1, nullptr, sigma, nullptr);
+    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, +1, nullptr, nullptr, nullptr);
+    fft_axis(st, tmp, out, tw, n, (int64_t)n * n, 1, N, batch, +1, nullptr, nullptr, add);
+  }
+}
+
+// Unnormalised inverse transform over all axes (Green kernel construction).
+void fft_inverse_all(hipStream_t st, const double2* in, double2* out, const double2* tw, int d, int n) {
+  const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
+  if (d == 2) {
+    fft_axis(st, in, out, tw, n, n, 1, N, 1, +1, nullptr, nullptr, nullptr);
+    fft_axis(st, out, out, tw, n, 1, n, N, 1, +1, nullptr, nullptr, nullptr);
+  } else {
+    fft_axis(st, in, out, tw, n, (int64_t)n * n, 1, N, 1, +1, nullptr, nullptr, nullptr);
+    fft_axis(st, out, out, tw, n, n, n, N, 1, +1, nullptr, nullptr, nullptr);
+    fft_axis(st, out, out, tw, n, 1, (int64_t)n * n, N, 1, +1, nullptr, nullptr, nullptr);
+  }
+}
+
+}  // namespace spp

@@ -1,0 +1,117 @@
+// Host-callable launchers of the HIP kernels, grouped by source file.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spp {
+
+// ------------------------------------------------------------- fft.hip
+void fft_make_twiddles(double2* tw, int n, hipStream_t st);
+bool fft_supported(int n);
+void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw, int n,
+              int64_t outer, int64_t inner, int64_t N, int batch, int dir,
+              const double* pre, const double* mid, const double2* add);
+void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, const double2* tw,
+               int d, int n, int batch, const double* pre, const double* sigma, const double2* add);
+void fft_inverse_all(hipStream_t st, const double2* in, double2* out, const double2* tw, int d, int n);
+
+// ------------------------------------------------------------- stencil.hip
+// Sum of w_j = omega^2 / c_j^2 (Helmholtz, kind 0) or ell^2 V_j (kind 1) over
+// the grid, and a flag for non-finite or non-positive input; result written to
+// out[0] (sum) and out[1] (bad-entry count) in device memory.
+void coeff_reduce(hipStream_t st, int kind, const double* coeff, int64_t N, double omega,
+                  double ell, double* partial, int nblocks, double* out);
+int coeff_reduce_blocks(int64_t N);
+// q_j and sigma_k / N (FFT order), plus the complex arrays whose inverse
+// transforms are the kernels of G and of G G^H.
+void coeff_finish(hipStream_t st, int kind, const double* coeff, int64_t N, int d, int n,
+                  double omega, double ell, double energy, double s, double* q, double* sigma,
+                  double2* sig_c, double2* sig2_c);
+
+struct StencilDev {
+  int nS, nB, nG;
+  const int* off;      // nG * d offsets (device)
+  double2* T;          // nS x nB, row-major
+  double2* C;          // nS x nG, row-major
+  double2* Tt;         // nB x nS (T transposed), row-major
+};
+// Builds T_S and C_S for one set type from the kernels g (of G) and g2 (of G G^H).
+// work must hold 2 nG^2 + 2 nG nB + nB^2 + nS nB complex entries.
+void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2,
+                   StencilDev& S, double2* work, int* info);
+
+// ------------------------------------------------------------- mf.hip
+struct FrontDev {
+  int64_t off;         // F x F front (column-major) in the arena
+  int64_t voff;        // solve vector slot (positions)
+  int64_t xoff;        // inverse work slot (p x p), relative to the level's work base
+  int F, p;
+  int idx;             // global indices of the F front points (pivots first)
+  int map;             // F - p parent positions of the boundary points
+  int perm;            // p ints: pivot row permutation
+  int nchild;
+  int child[8];
+};
+
+struct AsmBlockDev { int front, type, anchor, rowpos, colpos; };
+
+struct TypeDev {       // per set type, for assembly / Q apply
+  int nS, nB, nG;
+  const int* off;
+  const double2* T;
+  const double2* C;
+  const double2* Tt;
+};
+
+struct MfDev {
+  int d, n, b, m;
+  int64_t N;
+  const FrontDev* fronts;
+  const AsmBlockDev* blocks;
+  const int* pos;
+  const int* idx;
+  const int* map;
+  int* perm;           // final row permutation of each front's pivot block
+  int* ipiv;           // LAPACK-style interchange record written by the panel
+  const double* q;
+  TypeDev types[8];
+  int* info;           // [0] = breakdown front + 1 (0 if none)
+};
+
+template <typename R>
+void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork,
+                     int f0, int f1, int maxF, int maxP, int blk0, int blk1,
+                     int max_children, int prev_f0);
+
+void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);
+
+template <typename R>
+void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void* z,
+              const void* x_in, void* x_out, int nrhs,
+              const int* level_begin, const int* level_maxF, const int* level_maxP, int nlevels);
+
+template <typename R>
+void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);
+
+// ------------------------------------------------------------- krylov.hip
+// h_out[i] (+)= V_i^H w per right-hand side; if h_acc, also h_acc[i] += V_i^H w.
+void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const double2* w,
+             int nrhs, int64_t N, double2* partial, double2* h_out, int hstride, int accumulate,
+             double2* h_acc, int acc_stride);
+void kr_update(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w,
+               int nrhs, int64_t N, const double2* h, int hstride);
+void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N,
+                   double* partial, double2* h_sub, int hstride);
+void kr_givens(hipStream_t st, double2* H, int hcol_stride, int hrhs_stride, double* cs, double2* sn,
+               double2* g, int j, int nrhs, int ldg, double* resid, const int* active);
+void kr_backsolve(hipStream_t st, const double2* H, int hcol_stride, int hrhs_stride, const double2* g,
+                  int ldg, double2* y, int k, int nrhs, const int* kvec);
+void kr_combine(hipStream_t st, const double2* Z, int64_t zstride, int nvec, const double2* y,
+                int ldy, double2* u, int nrhs, int64_t N, const int* kvec);
+void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* partial, double* out);
+void kr_sub(hipStream_t st, const double2* a, const double2* b, double2* out, int64_t count);
+void kr_scale_init(hipStream_t st, const double2* g, double2* v0, const double* norms, int nrhs,
+                   int64_t N, double2* gvec, int ldg);
+
+}  // namespace spp

@@ -1,0 +1,295 @@
+// FP64 kernels of flexible GMRES (right preconditioning, Section 3 of the paper;
+// Saad and Schultz) on (I + G q) u = G f, batched over right-hand sides.
+//
+// Arnoldi uses classical Gram-Schmidt applied twice (CGS2): the projections
+// onto all previous basis vectors are one pass of block dot products
+// (wavefront shuffles, then a cross-workgroup pass) and one fused update,
+// instead of j dependent dot/axpy pairs.  The Hessenberg columns, Givens
+// rotations and the small triangular solve live on the device as well; the
+// host only reads back the residual estimates to decide when to stop.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 4;
+constexpr int kMaxVec = 512;
+
+__device__ inline double2 wave_sum(double2 v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_down(v.x, o, 64);
+    v.y += __shfl_down(v.y, o, 64);
+  }
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// partial[(rhs * nblk + blk) * nvec + i] = sum over the block's chunk of conj(V_i) w.
+__global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                                const double2* __restrict__ w, int64_t N,
+                                                                double2* __restrict__ partial) {
+  const int rhs = blockIdx.y;
+  const int nblk = gridDim.x;
+  const int64_t chunk = (int64_t)kThreads * kPerThread;
+  const int64_t e0 = blockIdx.x * chunk + threadIdx.x;
+  const double2* wr = w + rhs * N;
+  double2 wl[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t e = e0 + (int64_t)k * kThreads;
+    wl[k] = (e < N) ? wr[e] : cmake<double2>(0, 0);
+  }
+  __shared__ double2 sh[kThreads / 64][kMaxVec];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = 0; i < nvec; ++i) {
+    const double2* vr = V + (int64_t)i * vstride + rhs * N;
+    double2 s = cmake<double2>(0, 0);
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t e = e0 + (int64_t)k * kThreads;
+      if (e < N) s = cadd(s, cconjmul(vr[e], wl[k]));
+    }
+    s = wave_sum(s);
+    if (lane == 0) sh[wave][i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nvec; i += kThreads) {
+    double2 s = cmake<double2>(0, 0);
+    for (int q = 0; q < kThreads / 64; ++q) s = cadd(s, sh[q][i]);
+    partial[((int64_t)rhs * nblk + blockIdx.x) * nvec + i] = s;
+  }
+}
+
+__global__ void dots_final_kernel(const double2* __restrict__ partial, int nblk, int nvec, double2* h, int hstride,
+                                  int accumulate, double2* h_acc, int acc_stride) {
+  const int rhs = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvec) return;
+  double2 s = cmake<double2>(0, 0);
+  for (int b = 0; b < nblk; ++b) s = cadd(s, partial[((int64_t)rhs * nblk + b) * nvec + i]);
+  double2* hr = h + (int64_t)rhs * hstride;
+  hr[i] = accumulate ? cadd(hr[i], s) : s;
+  if (h_acc) {
+    double2* ha = h_acc + (int64_t)rhs * acc_stride;
+    ha[i] = cadd(ha[i], s);
+  }
+}
+
+// w -= sum_i V_i h_i
+__global__ void __launch_bounds__(kThreads) update_kernel(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                          double2* __restrict__ w, int64_t N,
+                                                          const double2* __restrict__ h, int hstride) {
+  const int rhs = blockIdx.y;
+  __shared__ double2 hs[kMaxVec];
+  for (int i = threadIdx.x; i < nvec; i += kThreads) hs[i] = h[(int64_t)rhs * hstride + i];
+  __syncthreads();
+  const int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (e >= N) return;
+  double2 acc = w[rhs * N + e];
+  for (int i = 0; i < nvec; ++i) cfms(acc, V[(int64_t)i * vstride + rhs * N + e], hs[i]);
+  w[rhs * N + e] = acc;
+}
+
+__global__ void __launch_bounds__(kThreads) sumsq_partial_kernel(const double2* __restrict__ w, int64_t N,
+                                                                 double* __restrict__ partial) {
+  const int rhs = blockIdx.y;
+  double s = 0;
+  for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < N; e += (int64_t)gridDim.x * kThreads)
+    s += cabs2(w[rhs * N + e]);
+  s = wave_sum(s);
+  __shared__ double sh[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < kThreads / 64; ++q) t += sh[q];
+    partial[(int64_t)rhs * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// norms[rhs] = sqrt(sum of partials); optionally H entry = norm.
+__global__ void sumsq_final_kernel(const double* __restrict__ partial, int nblk, int nrhs, double* norms,
+                                   double2* h_sub, int hstride) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)rhs * nblk + b];
+  const double nrm = sqrt(s);
+  norms[rhs] = nrm;
+  if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
+}
+
+__global__ void scale_kernel(const double2* __restrict__ w, double2* __restrict__ v, const double* __restrict__ norms,
+                             int64_t N) {
+  const int rhs = blockIdx.y;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const double nrm = norms[rhs];
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  v[rhs * N + e] = cscale(w[rhs * N + e], inv);
+}
+
+// Complex Givens rotation G = [[c, s], [-conj(s), c]] with c real that maps
+// (a, b) to (r, 0): c = |a| / t, s = (a/|a|) conj(b) / t, r = (a/|a|) t.
+__device__ inline void make_givens(double2 a, double2 b, double& c, double2& s, double2& r) {
+  const double aa = sqrt(cabs2(a)), bb = sqrt(cabs2(b));
+  if (bb == 0) { c = 1; s = cmake<double2>(0, 0); r = a; return; }
+  if (aa == 0) { c = 0; s = cmake<double2>(b.x / bb, -b.y / bb); r = cmake<double2>(bb, 0); return; }
+  const double t = hypot(aa, bb);
+  const double2 ph = cmake<double2>(a.x / aa, a.y / aa);
+  c = aa / t;
+  s = cscale(cmul(ph, cmake<double2>(b.x, -b.y)), 1.0 / t);
+  r = cscale(ph, t);
+}
+
+__global__ void givens_kernel(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
+                              int nrhs, int ldg, double* resid, const int* active) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  if (active && !active[rhs]) return;
+  double2* h = H + (int64_t)rhs * hrhs + (int64_t)j * hcol;
+  double* c = cs + (int64_t)rhs * ldg;
+  double2* s = sn + (int64_t)rhs * ldg;
+  double2* gg = g + (int64_t)rhs * ldg;
+  for (int i = 0; i < j; ++i) {
+    const double2 hi = h[i], hi1 = h[i + 1];
+    const double2 t = cadd(cscale(hi, c[i]), cmul(s[i], hi1));
+    h[i + 1] = csub(cscale(hi1, c[i]), cconjmul(s[i], hi));
+    h[i] = t;
+  }
+  double cj;
+  double2 sj, r;
+  make_givens(h[j], h[j + 1], cj, sj, r);
+  c[j] = cj;
+  s[j] = sj;
+  h[j] = r;
+  h[j + 1] = cmake<double2>(0, 0);
+  const double2 gj = gg[j];
+  gg[j + 1] = cscale(cconjmul(sj, gj), -1.0);
+  gg[j] = cscale(gj, cj);
+  resid[rhs] = sqrt(cabs2(gg[j + 1]));
+}
+
+__global__ void backsolve_kernel(const double2* H, int hcol, int hrhs, const double2* g, int ldg, double2* y,
+                                 int k, int nrhs, const int* kvec) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  const int kk = kvec ? kvec[rhs] : k;
+  const double2* h = H + (int64_t)rhs * hrhs;
+  const double2* gg = g + (int64_t)rhs * ldg;
+  double2* yy = y + (int64_t)rhs * ldg;
+  for (int i = kk - 1; i >= 0; --i) {
+    double2 s = gg[i];
+    for (int l = i + 1; l < kk; ++l) cfms(s, h[(int64_t)l * hcol + i], yy[l]);
+    yy[i] = cdiv(s, h[(int64_t)i * hcol + i]);
+  }
+  for (int i = kk; i < ldg; ++i) yy[i] = cmake<double2>(0, 0);
+}
+
+__global__ void combine_kernel(const double2* __restrict__ Z, int64_t zstride, int nvec, const double2* __restrict__ y,
+                               int ldy, double2* __restrict__ u, int64_t N, const int* kvec) {
+  const int rhs = blockIdx.y;
+  __shared__ double2 ys[kMaxVec];
+  const int kk = kvec ? kvec[rhs] : nvec;
+  for (int i = threadIdx.x; i < kk; i += blockDim.x) ys[i] = y[(int64_t)rhs * ldy + i];
+  __syncthreads();
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  double2 acc = cmake<double2>(0, 0);
+  for (int i = 0; i < kk; ++i) cfma(acc, Z[(int64_t)i * zstride + rhs * N + e], ys[i]);
+  u[rhs * N + e] = acc;
+}
+
+__global__ void sub_kernel(const double2* a, const double2* b, double2* out, int64_t count) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < count) out[e] = csub(a[e], b[e]);
+}
+
+__global__ void init_g_kernel(const double* norms, int nrhs, double2* gvec, int ldg) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  for (int i = 0; i < ldg; ++i) gvec[(int64_t)rhs * ldg + i] = cmake<double2>(0, 0);
+  gvec[(int64_t)rhs * ldg] = cmake<double2>(norms[rhs], 0.0);
+}
+
+int dot_blocks(int64_t N) { return (int)ceil_div(N, (int64_t)kThreads * kPerThread); }
+
+}  // namespace
+
+void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const double2* w, int nrhs, int64_t N,
+             double2* partial, double2* h_out, int hstride, int accumulate, double2* h_acc, int acc_stride) {
+  if (nvec > kMaxVec) throw Error(-7, "Krylov dimension exceeds the kernel limit");
+  const int nblk = dot_blocks(N);
+  dots_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, partial);
+  SPP_LAUNCH_CHECK();
+  dots_final_kernel<<<dim3(ceil_div(nvec, 64), nrhs), 64, 0, st>>>(partial, nblk, nvec, h_out, hstride, accumulate,
+                                                                       h_acc, acc_stride);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_update(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w, int nrhs, int64_t N,
+               const double2* h, int hstride) {
+  update_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, h, hstride);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* partial, double* out) {
+  const int nblk = 256;
+  sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(v, N, partial);
+  SPP_LAUNCH_CHECK();
+  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, out, nullptr, 0);
+  SPP_LAUNCH_CHECK();
+}
+
+// v = w / ||w|| and h_sub = ||w|| per right-hand side; norms kept in partial[0..nrhs).
+void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N, double* partial,
+                   double2* h_sub, int hstride) {
+  const int nblk = 256;
+  double* norms = partial + (int64_t)nblk * nrhs;
+  sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(w, N, partial);
+  SPP_LAUNCH_CHECK();
+  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, norms, h_sub, hstride);
+  SPP_LAUNCH_CHECK();
+  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, norms, N);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_givens(hipStream_t st, double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j, int nrhs,
+               int ldg, double* resid, const int* active) {
+  givens_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(H, hcol, hrhs, cs, sn, g, j, nrhs, ldg, resid, active);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_backsolve(hipStream_t st, const double2* H, int hcol, int hrhs, const double2* g, int ldg, double2* y, int k,
+                  int nrhs, const int* kvec) {
+  backsolve_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(H, hcol, hrhs, g, ldg, y, k, nrhs, kvec);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_combine(hipStream_t st, const double2* Z, int64_t zstride, int nvec, const double2* y, int ldy, double2* u,
+                int nrhs, int64_t N, const int* kvec) {
+  if (nvec > kMaxVec) throw Error(-7, "Krylov dimension exceeds the kernel limit");
+  combine_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(Z, zstride, nvec, y, ldy, u, N, kvec);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_sub(hipStream_t st, const double2* a, const double2* b, double2* out, int64_t count) {
+  sub_kernel<<<ceil_div(count, kThreads), kThreads, 0, st>>>(a, b, out, count);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_scale_init(hipStream_t st, const double2* g, double2* v0, const double* norms, int nrhs, int64_t N,
+                   double2* gvec, int ldg) {
+  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(g, v0, norms, N);
+  SPP_LAUNCH_CHECK();
+  init_g_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(norms, nrhs, gvec, ldg);
+  SPP_LAUNCH_CHECK();
+}
+
+}  // namespace spp

@@ -1,0 +1,304 @@
+// Nested-dissection plan construction (host).  See plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdlib>
+#include <sstream>
+
+namespace spp {
+
+namespace {
+
+int64_t ipow(int64_t a, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= a;
+  return r;
+}
+
+// Box widths per level, leaves first.
+std::vector<std::vector<int>> level_shapes(int d, int n, int b, int order) {
+  std::vector<std::vector<int>> shapes;
+  std::vector<int> w(d, b);
+  shapes.push_back(w);
+  if (order == 0) {
+    while (w[0] < n) {
+      for (int i = 0; i < d; ++i) w[i] *= 2;
+      shapes.push_back(w);
+    }
+  } else {
+    int axis = 0;
+    for (;;) {
+      bool done = true;
+      for (int i = 0; i < d; ++i) done = done && (w[i] >= n);
+      if (done) break;
+      while (w[axis] >= n) axis = (axis + 1) % d;
+      w[axis] *= 2;
+      shapes.push_back(w);
+      axis = (axis + 1) % d;
+    }
+  }
+  return shapes;
+}
+
+SetType make_type(int d, int b, int mask) {
+  SetType t;
+  t.mask = mask;
+  std::vector<int> lo(d), hi(d);
+  for (int i = 0; i < d; ++i) {
+    bool pinned = (mask >> i) & 1;
+    lo[i] = pinned ? -1 : 0;
+    hi[i] = pinned ? 1 : b;
+  }
+  auto in_S = [&](const std::vector<int>& o) {
+    for (int i = 0; i < d; ++i) {
+      bool pinned = (mask >> i) & 1;
+      if (pinned ? (o[i] != 0) : (o[i] < 1 || o[i] > b - 1)) return false;
+    }
+    return true;
+  };
+  std::vector<int> S, B;
+  std::vector<int> o(lo);
+  for (;;) {
+    std::vector<int>& dst = in_S(o) ? S : B;
+    dst.insert(dst.end(), o.begin(), o.end());
+    int i = d - 1;
+    while (i >= 0 && o[i] == hi[i]) { o[i] = lo[i]; --i; }
+    if (i < 0) break;
+    ++o[i];
+  }
+  t.nS = static_cast<int>(S.size()) / d;
+  t.nB = static_cast<int>(B.size()) / d;
+  t.nG = t.nS + t.nB;
+  t.off = S;
+  t.off.insert(t.off.end(), B.begin(), B.end());
+  return t;
+}
+
+}  // namespace
+
+std::string build_plan(int d, int n, int b, int order, Plan& P) {
+  std::ostringstream err;
+  if (d != 2 && d != 3) return "dim must be 2 or 3";
+  if (n < 4 || (n & 1)) return "n must be even and >= 4";
+  if (b < 2 || n % b) return "b must be >= 2 and divide n";
+  int m = n / b;
+  if (m < 2 || (m & (m - 1))) return "n / b must be a power of two >= 2";
+  P = Plan();
+  P.d = d; P.n = n; P.b = b; P.m = m; P.order = order;
+  P.N = ipow(n, d);
+  const int64_t N = P.N;
+  const int ntypes = 1 << d;
+  const int64_t nanchor = ipow(m, d);
+  for (int t = 0; t < ntypes; ++t) P.types.push_back(make_type(d, b, t));
+
+  std::vector<int> owner(N, -1), posmap(N, -1);
+  std::vector<int> set_stamp(static_cast<size_t>(ntypes * nanchor), -1);
+  std::vector<std::vector<int>> front_lo;
+  auto shapes = level_shapes(d, n, b, order);
+
+  std::vector<int> coord(d), crd(d);
+  auto ravel = [&](const std::vector<int>& x) {
+    int64_t g = 0;
+    for (int i = 0; i < d; ++i) g = g * n + x[i];
+    return g;
+  };
+  auto set_of = [&](int64_t g, int& type, int& anchor) {
+    int64_t r = g;
+    int msk = 0;
+    int64_t an = 0, mul = 1;
+    for (int i = d - 1; i >= 0; --i) {
+      int x = static_cast<int>(r % n);
+      r /= n;
+      if (x % b == 0) msk |= 1 << i;
+      an += mul * (x / b);
+      mul *= m;
+    }
+    type = msk;
+    anchor = static_cast<int>(an);
+  };
+  // Global index of offset `o` of a set anchored at box `anchor`.
+  auto point_of = [&](int anchor, const int* o) {
+    int64_t g = 0;
+    int64_t a = anchor;
+    std::vector<int> ac(d);
+    for (int i = d - 1; i >= 0; --i) { ac[i] = static_cast<int>(a % m); a /= m; }
+    for (int i = 0; i < d; ++i) g = g * n + ((ac[i] * b + o[i]) % n + n) % n;
+    return g;
+  };
+
+  for (size_t lv = 0; lv < shapes.size(); ++lv) {
+    const std::vector<int>& w = shapes[lv];
+    Level L;
+    L.begin = static_cast<int>(P.fronts.size());
+    L.blk_begin = static_cast<int>(P.blocks.size());
+    std::vector<int> nbox(d);
+    int64_t boxes = 1;
+    for (int i = 0; i < d; ++i) { nbox[i] = n / w[i]; boxes *= nbox[i]; }
+    for (int64_t bx = 0; bx < boxes; ++bx) {
+      std::vector<int> lo(d), len(d);
+      int64_t r = bx;
+      for (int i = d - 1; i >= 0; --i) {
+        int bi = static_cast<int>(r % nbox[i]);
+        r /= nbox[i];
+        bool full = (w[i] == n);
+        lo[i] = full ? 0 : bi * w[i];
+        len[i] = full ? n : w[i] + 1;
+      }
+      std::vector<int> piv, bnd;
+      std::vector<int> u(d, 0);
+      for (;;) {
+        bool interior = true;
+        for (int i = 0; i < d; ++i) {
+          int ui = lo[i] + u[i];
+          crd[i] = ui % n;
+          if (w[i] != n && (u[i] == 0 || u[i] == len[i] - 1)) interior = false;
+        }
+        int64_t g = ravel(crd);
+        if (owner[g] < 0) (interior ? piv : bnd).push_back(static_cast<int>(g));
+        int i = d - 1;
+        while (i >= 0 && u[i] == len[i] - 1) { u[i] = 0; --i; }
+        if (i < 0) break;
+        ++u[i];
+      }
+      if (piv.empty()) {
+        err << "box " << bx << " at level " << lv << " has no pivots";
+        return err.str();
+      }
+      Front f;
+      f.level = static_cast<int>(lv);
+      f.p = static_cast<int>(piv.size());
+      f.F = f.p + static_cast<int>(bnd.size());
+      f.idx = static_cast<int>(P.idx.size());
+      int fid = static_cast<int>(P.fronts.size());
+      P.idx.insert(P.idx.end(), piv.begin(), piv.end());
+      P.idx.insert(P.idx.end(), bnd.begin(), bnd.end());
+      for (int g : piv) owner[g] = fid;
+      for (int k = 0; k < f.F; ++k) posmap[P.idx[f.idx + k]] = k;
+
+      // Assembly blocks: block rows of the sets eliminated here (all their
+      // columns still alive), then block rows of boundary sets restricted to
+      // this front's pivot columns.  Each entry of P is assembled exactly once,
+      // into the front that eliminates its row or its column first.
+      std::vector<int> piv_sets;
+      for (int g : piv) {
+        int ty, an;
+        set_of(g, ty, an);
+        size_t sid = static_cast<size_t>(ty) * nanchor + an;
+        if (set_stamp[sid] != fid) { set_stamp[sid] = fid; piv_sets.push_back(static_cast<int>(sid)); }
+      }
+      auto emit = [&](int sid, bool full_rows) -> bool {
+        int ty = static_cast<int>(sid / nanchor), an = static_cast<int>(sid % nanchor);
+        const SetType& T = P.types[ty];
+        AsmBlock blk;
+        blk.front = fid; blk.type = ty; blk.anchor = an;
+        blk.rowpos = static_cast<int>(P.pos.size());
+        for (int i = 0; i < T.nS; ++i) {
+          int64_t g = point_of(an, &T.off[i * d]);
+          int ps = posmap[g];
+          if (ps < 0 || (full_rows ? ps >= f.p : ps < f.p)) return false;
+          P.pos.push_back(ps);
+        }
+        blk.colpos = static_cast<int>(P.pos.size());
+        for (int j = 0; j < T.nG; ++j) {
+          int64_t g = point_of(an, &T.off[j * d]);
+          int ps;
+          if (full_rows) {
+            ps = (owner[g] < 0 || owner[g] == fid) ? posmap[g] : -1;
+            if ((owner[g] < 0 || owner[g] == fid) && ps < 0) return false;
+          } else {
+            ps = (owner[g] == fid) ? posmap[g] : -1;
+          }
+          P.pos.push_back(ps);
+        }
+        P.blocks.push_back(blk);
+        return true;
+      };
+      for (int sid : piv_sets) {
+        if (!emit(sid, true)) { err << "pivot set outside front " << fid; return err.str(); }
+      }
+      for (int g : piv) {
+        int64_t rr = g;
+        for (int i = d - 1; i >= 0; --i) { coord[i] = static_cast<int>(rr % n); rr /= n; }
+        for (int nb3 = 0; nb3 < ipow(3, d); ++nb3) {
+          int t = nb3;
+          for (int i = d - 1; i >= 0; --i) { crd[i] = ((coord[i] + t % 3 - 1) % n + n) % n; t /= 3; }
+          int64_t g2 = ravel(crd);
+          if (owner[g2] >= 0) continue;  // row already eliminated: assembled there
+          int ty, an;
+          set_of(g2, ty, an);
+          size_t sid = static_cast<size_t>(ty) * nanchor + an;
+          if (set_stamp[sid] == fid) continue;
+          set_stamp[sid] = fid;
+          if (!emit(static_cast<int>(sid), false)) {
+            err << "boundary set of front " << fid << " not on its surface";
+            return err.str();
+          }
+        }
+      }
+      for (int k = 0; k < f.F; ++k) posmap[P.idx[f.idx + k]] = -1;
+      front_lo.push_back(lo);
+      P.fronts.push_back(f);
+      L.maxF = std::max(L.maxF, f.F);
+      L.maxP = std::max(L.maxP, f.p);
+    }
+    L.end = static_cast<int>(P.fronts.size());
+    L.blk_end = static_cast<int>(P.blocks.size());
+    P.levels.push_back(L);
+  }
+  for (int64_t g = 0; g < N; ++g)
+    if (owner[g] < 0) return "ordering left a point uneliminated";
+
+  // Parent links, child slots, boundary -> parent position maps.
+  for (size_t lv = 0; lv + 1 < P.levels.size(); ++lv) {
+    const std::vector<int>& W = shapes[lv + 1];
+    std::vector<int> nbox(d);
+    for (int i = 0; i < d; ++i) nbox[i] = n / W[i];
+    for (int fi = P.levels[lv].begin; fi < P.levels[lv].end; ++fi) {
+      int64_t pb = 0;
+      for (int i = 0; i < d; ++i) pb = pb * nbox[i] + (W[i] == n ? 0 : front_lo[fi][i] / W[i]);
+      int parent = P.levels[lv + 1].begin + static_cast<int>(pb);
+      Front& c = P.fronts[fi];
+      c.parent = parent;
+      c.slot = static_cast<int>(P.fronts[parent].children.size());
+      P.fronts[parent].children.push_back(fi);
+    }
+  }
+  for (auto& L : P.levels) {
+    for (int fi = L.begin; fi < L.end; ++fi)
+      L.max_children = std::max<int>(L.max_children, static_cast<int>(P.fronts[fi].children.size()));
+  }
+  for (size_t fi = 0; fi < P.fronts.size(); ++fi) {
+    Front& c = P.fronts[fi];
+    c.map = static_cast<int>(P.map.size());
+    if (c.parent < 0) {
+      if (c.F != c.p) return "root front has boundary points";
+      continue;
+    }
+    const Front& par = P.fronts[c.parent];
+    for (int k = 0; k < par.F; ++k) posmap[P.idx[par.idx + k]] = k;
+    for (int k = c.p; k < c.F; ++k) {
+      int ps = posmap[P.idx[c.idx + k]];
+      if (ps < 0) { err << "front " << fi << " boundary point missing from parent"; return err.str(); }
+      P.map.push_back(ps);
+    }
+    for (int k = 0; k < par.F; ++k) posmap[P.idx[par.idx + k]] = -1;
+  }
+
+  // Arena layout and counts.
+  int64_t off = 0, voff = 0;
+  for (auto& f : P.fronts) {
+    f.off = off;
+    off += (static_cast<int64_t>(f.F) * f.F + 15) / 16 * 16;
+    f.voff = voff;
+    voff += (f.F + 15) / 16 * 16;
+    double p = f.p, k = f.F - f.p;
+    P.factor_entries += static_cast<int64_t>(f.p) * f.p + 2LL * f.p * (f.F - f.p);
+    P.factor_flops += 8.0 * (p * p * p / 3.0 + p * p * k + p * k * k);
+    P.max_front = std::max(P.max_front, f.F);
+  }
+  P.arena_elems = off;
+  P.vec_elems = voff;
+  return std::string();
+}
+
+}  // namespace spp

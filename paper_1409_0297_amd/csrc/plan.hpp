@@ -1,0 +1,76 @@
+// Host-side nested-dissection plan: set types, fronts, index maps.
+//
+// Geometry of Section 2.3: leaf boxes of width b with boundaries on the grid
+// lines j_i = 0 (mod b); the leaf set partition into cells, faces, edges and
+// vertices; gamma(S) = S widened by one grid step in every direction (mod n).
+// Fronts follow the box hierarchy of Figure 1: a box eliminates the points of
+// its open interior that its sub-boxes left, against the remaining points on
+// its surface.  Boxes merge 2^d at a time (octree) or 2 at a time along the
+// axes in turn (bisection); the last box is the whole periodic domain.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace spp {
+
+// One orientation-resolved set type.  Bit i of `mask` set means axis i is
+// pinned to a leaf box face (cell: 0, vertex: 2^d - 1).
+struct SetType {
+  int mask = 0;
+  int nS = 0, nB = 0, nG = 0;   // |S|, |beta(S)|, |gamma(S)| = nS + nB
+  // Grid offsets from the leaf box corner (a_0 b, ..., a_{d-1} b): nG rows of
+  // d ints, S first (lexicographic), then beta(S) (lexicographic over gamma).
+  std::vector<int> off;
+};
+
+// Assembly of one set instance's block row P(S, gamma(S)) into one front.
+struct AsmBlock {
+  int front;      // front index
+  int type;       // set type index
+  int anchor;     // leaf box index (C order over m^d)
+  int rowpos;     // offset into Plan::pos of nS row positions (-1: skip)
+  int colpos;     // offset into Plan::pos of nG column positions (-1: skip)
+};
+
+struct Front {
+  int level = 0;
+  int F = 0, p = 0;             // front order and number of pivots
+  int parent = -1;
+  int slot = 0;                 // index among the parent's children
+  int idx = 0;                  // offset into Plan::idx (F global points, pivots first)
+  int map = 0;                  // offset into Plan::map (F - p parent positions)
+  int64_t off = 0;              // offset (complex elements) of the F x F front in the arena
+  int64_t voff = 0;             // offset (complex elements) of the front's solve vector
+  std::vector<int> children;
+};
+
+struct Level {
+  int begin = 0, end = 0;       // fronts [begin, end)
+  int maxF = 0, maxP = 0;
+  int max_children = 0;
+  int blk_begin = 0, blk_end = 0;   // assembly blocks of this level
+};
+
+struct Plan {
+  int d = 0, n = 0, b = 0, m = 0;
+  int64_t N = 0;
+  int order = 0;
+  std::vector<SetType> types;
+  std::vector<Front> fronts;
+  std::vector<Level> levels;
+  std::vector<AsmBlock> blocks;
+  std::vector<int> pos;         // row/column position pool for AsmBlocks
+  std::vector<int> idx;         // global point indices of every front
+  std::vector<int> map;         // boundary -> parent position maps
+  int64_t arena_elems = 0;      // sum of F^2 (complex elements, padded)
+  int64_t vec_elems = 0;        // sum of F (per right-hand side)
+  int64_t factor_entries = 0;   // sum of p^2 + 2 p (F - p)
+  double factor_flops = 0;      // real flops of all partial factorisations
+  int max_front = 0;
+};
+
+// Builds the plan; returns an empty string on success, else a message.
+std::string build_plan(int d, int n, int b, int order, Plan& plan);
+
+}  // namespace spp

@@ -1,0 +1,242 @@
+// Setup kernels: the shift split (eq. Dsq), the Fourier symbol of G (eq. G),
+// and the sparsifying stencils T_S and C_S of Section 2.3.
+//
+// T_S = G(S, gamma^c) G(beta, gamma^c)^+ is computed without forming the
+// N-wide blocks: for a full-row-rank A = G(beta, gamma^c) the pseudoinverse is
+// A^H (A A^H)^{-1}, and both products it needs are sums over gamma^c, i.e. a
+// sum over the whole grid minus a sum over gamma:
+//   G(X, gamma^c) G(Y, gamma^c)^H = (G G^H)(X, Y) - G(X, gamma) G(Y, gamma)^H.
+// G is the circulant with symbol sigma_k, so G G^H is the circulant with
+// symbol |sigma_k|^2, and for real sigma G(Y, gamma)^H = G(gamma, Y).  Hence
+//   T_S [ (G G^H)(beta, beta) - G(beta, gamma) G(gamma, beta) ]
+//       = (G G^H)(S, beta) - G(S, gamma) G(gamma, beta),
+// an |beta| x |beta| system, and C_S = [I  -T_S] G(gamma, gamma).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spp {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double coeff_w(int kind, double c, double omega, double ell) {
+  return kind == 0 ? omega * omega / (c * c) : ell * ell * c;
+}
+
+__global__ void coeff_partial_kernel(int kind, const double* __restrict__ coeff, int64_t N,
+                                     double omega, double ell, double* __restrict__ partial) {
+  __shared__ double sh[16];
+  double sum = 0, bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double c = coeff[i];
+    const double w = coeff_w(kind, c, omega, ell);
+    if (!isfinite(c) || !isfinite(w) || (kind == 0 && !(c > 0))) bad += 1;
+    else sum += w;
+  }
+  const double s = block_sum(sum, sh);
+  const double b = block_sum(bad, sh);
+  if (threadIdx.x == 0) { partial[2 * blockIdx.x] = s; partial[2 * blockIdx.x + 1] = b; }
+}
+
+__global__ void coeff_final_kernel(const double* __restrict__ partial, int nblocks, double* out) {
+  __shared__ double sh[16];
+  double s = 0, b = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) { s += partial[2 * i]; b += partial[2 * i + 1]; }
+  s = block_sum(s, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) { out[0] = s; out[1] = b; }
+}
+
+__global__ void coeff_finish_kernel(int kind, const double* __restrict__ coeff, int64_t N, int d, int n,
+                                    double omega, double ell, double energy, double s,
+                                    double* __restrict__ q, double* __restrict__ sigma,
+                                    double2* __restrict__ sig_c, double2* __restrict__ sig2_c) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double w = coeff_w(kind, coeff[j], omega, ell);
+  // Helmholtz: q = s - omega^2/c^2.  Schroedinger: q = ell^2 V - ell^2 E + s.
+  q[j] = (kind == 0) ? s - w : w - ell * ell * energy + s;
+  int64_t r = j;
+  double k2 = 0;
+  for (int i = 0; i < d; ++i) {
+    int ri = (int)(r % n);
+    r /= n;
+    int k = (ri >= n / 2) ? ri - n : ri;
+    k2 += (double)k * k;
+  }
+  const double pi = 3.14159265358979323846;
+  const double sg = 1.0 / (4.0 * pi * pi * k2 - s) / (double)N;   // sigma_k / N
+  sigma[j] = sg;
+  sig_c[j] = cmake<double2>(sg, 0.0);
+  sig2_c[j] = cmake<double2>(sg * sg * (double)N, 0.0);         // |sigma_k|^2 / N
+}
+
+// G-type block gather: out[i][j] = g[(off_rows[i] - off_cols[j]) mod n], row-major.
+__global__ void gather_block_kernel(const double2* __restrict__ g, int d, int n, const int* __restrict__ off,
+                                    int row0, int nrows, int col0, int ncols, double2* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncols) return;
+  const int i = t / ncols, j = t - i * ncols;
+  const int* a = off + (row0 + i) * d;
+  const int* b = off + (col0 + j) * d;
+  int64_t gi = 0;
+  for (int x = 0; x < d; ++x) gi = gi * n + (((a[x] - b[x]) % n) + n) % n;
+  out[t] = g[gi];
+}
+
+// C = beta C + alpha A B, all row-major, plain (setup-size) complex GEMM.
+__global__ void small_gemm_kernel(int m, int nn, int k, double2 alpha, const double2* __restrict__ A, int lda,
+                                  const double2* __restrict__ B, int ldb, double beta,
+                                  double2* __restrict__ C, int ldc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * nn) return;
+  const int i = t / nn, j = t - i * nn;
+  double2 acc = cmake<double2>(0, 0);
+  for (int l = 0; l < k; ++l) cfma(acc, A[i * lda + l], B[l * ldb + j]);
+  double2 c = (beta == 0.0) ? cmake<double2>(0, 0) : cscale(C[i * ldc + j], beta);
+  C[i * ldc + j] = cadd(c, cmul(alpha, acc));
+}
+
+// Solves X A = Bm for X (nS x nB) with A (nB x nB), both row-major, through
+// the transposed system A^T X^T = Bm^T: Gaussian elimination with partial
+// pivoting on the augmented [A^T | Bm^T] (nB x (nB + nS)), one workgroup.
+__global__ void right_solve_kernel(int nB, int nS, const double2* __restrict__ A, int lda,
+                                   const double2* __restrict__ Bm, int ldb, double2* aug,
+                                   double2* __restrict__ X, int ldx, int* info) {
+  const int W = nB + nS;
+  for (int t = threadIdx.x; t < nB * W; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    aug[t] = (c < nB) ? A[c * lda + r] : Bm[(c - nB) * ldb + r];
+  }
+  __shared__ double smax[1024];
+  __shared__ int sidx[1024];
+  __syncthreads();
+  for (int c = 0; c < nB; ++c) {
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + threadIdx.x; r < nB; r += blockDim.x) {
+      const double v = cabs2(aug[r * W + c]);
+      if (v > best) { best = v; bi = r; }
+    }
+    smax[threadIdx.x] = best;
+    sidx[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double o = smax[threadIdx.x + s];
+        const int oi = sidx[threadIdx.x + s];
+        if (o > smax[threadIdx.x] || (o == smax[threadIdx.x] && oi < sidx[threadIdx.x])) {
+          smax[threadIdx.x] = o;
+          sidx[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = sidx[0];
+    if (!(smax[0] > 0.0) && threadIdx.x == 0) *info = 1;
+    __syncthreads();
+    if (piv != c)
+      for (int t = threadIdx.x; t < W; t += blockDim.x) {
+        double2 a = aug[c * W + t];
+        aug[c * W + t] = aug[piv * W + t];
+        aug[piv * W + t] = a;
+      }
+    __syncthreads();
+    const double2 inv = crecip(aug[c * W + c]);
+    const int rows = nB - c - 1, cols = W - c - 1;
+    for (int t = threadIdx.x; t < rows * cols; t += blockDim.x) {
+      const int r = c + 1 + t / cols, cc = c + 1 + t % cols;
+      const double2 f = cmul(aug[r * W + c], inv);
+      cfms(aug[r * W + cc], f, aug[c * W + cc]);
+    }
+    __syncthreads();
+  }
+  for (int c = nB - 1; c >= 0; --c) {
+    const double2 inv = crecip(aug[c * W + c]);
+    for (int t = threadIdx.x; t < nS; t += blockDim.x) aug[c * W + nB + t] = cmul(aug[c * W + nB + t], inv);
+    __syncthreads();
+    for (int t = threadIdx.x; t < c * nS; t += blockDim.x) {
+      const int r = t / nS, cc = nB + t % nS;
+      cfms(aug[r * W + cc], aug[r * W + c], aug[c * W + cc]);
+    }
+    __syncthreads();
+  }
+  // X^T = aug[:, nB:], so X[i][j] = aug[j][nB + i].
+  for (int t = threadIdx.x; t < nS * nB; t += blockDim.x) {
+    const int i = t / nB, j = t - i * nB;
+    X[i * ldx + j] = aug[j * W + nB + i];
+  }
+}
+
+__global__ void transpose_kernel(const double2* __restrict__ A, int rows, int cols, double2* __restrict__ At) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int i = t / cols, j = t - i * cols;
+  At[j * rows + i] = A[t];
+}
+
+}  // namespace
+
+int coeff_reduce_blocks(int64_t N) {
+  int64_t b = (N + kRedThreads * 8 - 1) / (kRedThreads * 8);
+  return static_cast<int>(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+void coeff_reduce(hipStream_t st, int kind, const double* coeff, int64_t N, double omega, double ell,
+                  double* partial, int nblocks, double* out) {
+  coeff_partial_kernel<<<nblocks, kRedThreads, 0, st>>>(kind, coeff, N, omega, ell, partial);
+  SPP_LAUNCH_CHECK();
+  coeff_final_kernel<<<1, kRedThreads, 0, st>>>(partial, nblocks, out);
+  SPP_LAUNCH_CHECK();
+}
+
+void coeff_finish(hipStream_t st, int kind, const double* coeff, int64_t N, int d, int n, double omega,
+                  double ell, double energy, double s, double* q, double* sigma, double2* sig_c,
+                  double2* sig2_c) {
+  coeff_finish_kernel<<<ceil_div(N, 256), 256, 0, st>>>(kind, coeff, N, d, n, omega, ell, energy, s, q,
+                                                        sigma, sig_c, sig2_c);
+  SPP_LAUNCH_CHECK();
+}
+
+void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2, StencilDev& S,
+                   double2* work, int* info) {
+  const int nS = S.nS, nB = S.nB, nG = S.nG;
+  double2* Ggg = work;                       // nG x nG
+  double2* M = Ggg + (size_t)nG * nG;        // nG x nB: (G G^H)(gamma, beta) - G(gamma,gamma) G(gamma,beta)
+  double2* aug = M + (size_t)nG * nB;        // nB x (nB + nS)
+  const int T = 256;
+  gather_block_kernel<<<ceil_div((int64_t)nG * nG, T), T, 0, st>>>(g, d, n, S.off, 0, nG, 0, nG, Ggg);
+  SPP_LAUNCH_CHECK();
+  gather_block_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(g2, d, n, S.off, 0, nG, nS, nB, M);
+  SPP_LAUNCH_CHECK();
+  small_gemm_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(
+      nG, nB, nG, cmake<double2>(-1.0, 0.0), Ggg, nG, Ggg + nS, nG, 1.0, M, nB);
+  SPP_LAUNCH_CHECK();
+  // T_S M(beta, :) = M(S, :)
+  right_solve_kernel<<<1, 1024, 0, st>>>(nB, nS, M + (size_t)nS * nB, nB, M, nB, aug, S.T, nB, info);
+  SPP_LAUNCH_CHECK();
+  // C_S = G(S, gamma) - T_S G(beta, gamma)
+  SPP_HIP(hipMemcpy2DAsync(S.C, sizeof(double2) * nG, Ggg, sizeof(double2) * nG, sizeof(double2) * nG, nS,
+                           hipMemcpyDeviceToDevice, st));
+  small_gemm_kernel<<<ceil_div((int64_t)nS * nG, T), T, 0, st>>>(
+      nS, nG, nB, cmake<double2>(-1.0, 0.0), S.T, nB, Ggg + (size_t)nS * nG, nG, 1.0, S.C, nG);
+  SPP_LAUNCH_CHECK();
+  transpose_kernel<<<ceil_div((int64_t)nS * nB, T), T, 0, st>>>(S.T, nS, nB, S.Tt);
+  SPP_LAUNCH_CHECK();
+}
+
+}  // namespace spp

@@ -1,0 +1,84 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every entry
+point declared in include/spp.h, and rejects bad arguments before touching
+the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1409_0297_amd as spp
+from paper_1409_0297_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "spp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = spp.library()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert "spp_setup" in names and "spp_solve" in names
+
+
+def test_error_strings():
+    for code in range(-7, 1):
+        assert spp.spp_error_string(code)
+    assert spp.spp_error_string(99) == "unknown error"
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(binding.spp_problem) == 48
+    assert binding.spp_problem.coeff.offset == 40
+    assert ctypes.sizeof(binding.spp_options) == 24
+    assert binding.spp_stats_t.breakdown_front.offset == 76
+
+
+@pytest.mark.parametrize("dim,n,b", [(4, 32, 8), (2, 30, 8), (2, 48, 16), (2, 32, 32), (2, 7, 1), (2, 96, 8)])
+def test_setup_rejects_bad_grids_on_host(dim, n, b):
+    """dim in {2,3}; n even; b | n; n / b a power of two >= 2 -- checked before any GPU call.
+    (n = 96, b = 8 gives 12 leaf boxes per axis: not a power of two.)"""
+    coeff = np.ones(4)
+    pb = binding.spp_problem(dim=dim, n=n, b=b, kind=0, omega=1.0, ell=1.0, energy=0.0,
+                             coeff=coeff.ctypes.data)
+    op = binding.spp_options(prec=0, order=0, tol=1e-8, max_iter=10, flags=0)
+    with pytest.raises(spp.SppError) as e:
+        spp.spp_setup(pb, op, 0)
+    assert e.value.code == spp.SPP_EINVAL
+
+
+def test_setup_rejects_null_and_bad_options():
+    pb = binding.spp_problem(dim=2, n=32, b=8, kind=0, omega=1.0, ell=1.0, energy=0.0, coeff=None)
+    op = binding.spp_options(prec=0, order=0, tol=1e-8, max_iter=10, flags=0)
+    with pytest.raises(spp.SppError) as e:
+        spp.spp_setup(pb, op, 0)
+    assert e.value.code == spp.SPP_EINVAL
+    coeff = np.ones(32 * 32)
+    pb.coeff = coeff.ctypes.data
+    for bad in (dict(tol=0.0), dict(max_iter=0), dict(prec=5), dict(order=9)):
+        o = binding.spp_options(prec=0, order=0, tol=1e-8, max_iter=10, flags=0)
+        for k, v in bad.items():
+            setattr(o, k, v)
+        with pytest.raises(spp.SppError) as e:
+            spp.spp_setup(pb, o, 0)
+        assert e.value.code == spp.SPP_EINVAL
+    pb.kind = 0
+    pb.omega = -1.0
+    with pytest.raises(spp.SppError):
+        spp.spp_setup(pb, op, 0)
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = spp.library()
+    assert lib.spp_solve(None, None, 1, None, None, None, None) == spp.SPP_EINVAL
+    assert lib.spp_apply_operator(None, None, None, 1, None) == spp.SPP_EINVAL
+    assert lib.spp_stats(None, None) == spp.SPP_EINVAL
+    lib.spp_destroy(None)
