@@ -77,6 +77,8 @@ typedef struct {
 } spp_problem;
 
 #define SPP_F_UNPRECONDITIONED 1  /* GMRES with M = I (for comparisons)        */
+#define SPP_F_TIMING 2            /* bracket the launches of each kernel class
+                                     with HIP events (see spp_kernel_timing)   */
 
 typedef struct {
   int32_t prec;         /* spp_prec                                              */
@@ -152,6 +154,24 @@ int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t
                     int32_t* offsets, void* T, void* C);
 
 int spp_stats(const spp_factor* factor, spp_stats_t* out);
+
+/* Kernel classes timed under SPP_F_TIMING. */
+enum {
+  SPP_K_FFT = 0,     /* FFT passes of the operator / Green apply (a2, a7, a8)        */
+  SPP_K_GEMV = 1,    /* substitution products with the inverted pivot blocks (a9)     */
+  SPP_K_TRI = 2,     /* in-workgroup triangular solves of small fronts (a9)           */
+  SPP_K_GEMM = 3,    /* MFMA trailing updates / Schur complements of the fronts (a6)  */
+  SPP_K_PANEL = 4,   /* pivoted panel factorisation (a6)                              */
+  SPP_K_QAPPLY = 5   /* sparsifying stencil apply Q r (a9)                            */
+};
+/* Totals since setup (or the last reset) for one kernel class, all HOST
+   outputs, each may be NULL: summed event time of its launches (ms, measured
+   on the launch stream), number of launches, and the algorithmic bytes and
+   real flops those launches had to move / perform.  Synchronises on the
+   recorded events.  Zeros if the factor was set up without SPP_F_TIMING. */
+int spp_kernel_timing(const spp_factor* factor, int32_t kclass, double* total_ms,
+                      int64_t* launches, double* bytes, double* flops);
+int spp_kernel_timing_reset(spp_factor* factor);
 
 /* Releases everything the factor owns (synchronises its last stream). */
 void spp_destroy(spp_factor* factor);

@@ -17,6 +17,9 @@ SPP_HELMHOLTZ, SPP_SCHRODINGER = 0, 1
 SPP_C128, SPP_C64_FRONTS = 0, 1
 SPP_ORDER_OCTREE, SPP_ORDER_BISECT = 0, 1
 SPP_F_UNPRECONDITIONED = 1
+SPP_F_TIMING = 2
+SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
+KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
 
 
 class spp_problem(ctypes.Structure):
@@ -67,6 +70,9 @@ def library():
         "spp_get_coefficients": (I, [P, ctypes.POINTER(D), P]),
         "spp_get_stencil": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), P, P, P]),
         "spp_stats": (I, [P, ctypes.POINTER(spp_stats_t)]),
+        "spp_kernel_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
+                                  ctypes.POINTER(D)]),
+        "spp_kernel_timing_reset": (I, [P]),
         "spp_destroy": (V, [P]),
         "spp_error_string": (ctypes.c_char_p, [I]),
         "spp_last_error": (ctypes.c_char_p, []),
@@ -151,6 +157,17 @@ def spp_stats(handle) -> dict:
     return {name: getattr(st, name) for name, _ in spp_stats_t._fields_}
 
 
+def spp_kernel_timing(handle, kclass: int) -> dict:
+    ms, n, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(library().spp_kernel_timing(handle, kclass, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by),
+                                       ctypes.byref(fl)), "spp_kernel_timing")
+    return {"ms": ms.value, "launches": n.value, "bytes": by.value, "flops": fl.value}
+
+
+def spp_kernel_timing_reset(handle):
+    _check(library().spp_kernel_timing_reset(handle), "spp_kernel_timing_reset")
+
+
 def spp_destroy(handle):
     if handle:
         library().spp_destroy(handle)
@@ -174,7 +191,8 @@ class Solver:
 
     def __init__(self, kind: str, n: int, d: int, b: int, coeff, omega: float = 0.0,
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
-                 tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False):
+                 tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
+                 timing: bool = False):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -187,7 +205,8 @@ class Solver:
         op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,
                          order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
                          tol=tol, max_iter=max_iter,
-                         flags=SPP_F_UNPRECONDITIONED if unpreconditioned else 0)
+                         flags=(SPP_F_UNPRECONDITIONED if unpreconditioned else 0)
+                         | (SPP_F_TIMING if timing else 0))
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:

@@ -8,7 +8,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -17,6 +20,40 @@
 #include "plan.hpp"
 
 namespace spp {
+
+struct KernelTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KC_COUNT];
+  double bytes[KC_COUNT] = {0};
+  double flops[KC_COUNT] = {0};
+  int64_t launches[KC_COUNT] = {0};
+  hipEvent_t pending[KC_COUNT] = {nullptr};
+  ~KernelTimer() {
+    for (auto& v : ev)
+      for (auto& pr : v) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+  }
+};
+
+thread_local KernelTimer* g_timer = nullptr;
+
+void timer_begin(int cls, hipStream_t st) {
+  if (!g_timer) return;
+  hipEvent_t e;
+  SPP_HIP(hipEventCreate(&e));
+  SPP_HIP(hipEventRecord(e, st));
+  g_timer->pending[cls] = e;
+}
+
+void timer_end(int cls, hipStream_t st, double bytes, double flops) {
+  if (!g_timer || !g_timer->pending[cls]) return;
+  hipEvent_t e;
+  SPP_HIP(hipEventCreate(&e));
+  SPP_HIP(hipEventRecord(e, st));
+  g_timer->ev[cls].emplace_back(g_timer->pending[cls], e);
+  g_timer->pending[cls] = nullptr;
+  g_timer->bytes[cls] += bytes;
+  g_timer->flops[cls] += flops;
+  g_timer->launches[cls] += 1;
+}
 
 void throw_hip(hipError_t e, const char* what, const char* file, int line) {
   std::string m = std::string(hipGetErrorString(e)) + " in " + what + " (" + file + ":" + std::to_string(line) + ")";
@@ -32,6 +69,85 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// A nested-dissection plan and its device-side index arrays.  Plans depend
+// only on (device, d, n, b, ordering), so they are built once per process and
+// shared by every factor with that geometry (read-only on the device).
+struct PlanDevice {
+  Plan plan;
+  int device = 0;
+  FrontDev* fronts = nullptr;
+  AsmBlockDev* blocks = nullptr;
+  int *pos = nullptr, *idx = nullptr, *map = nullptr;
+  int* off[8] = {nullptr};
+  std::vector<int> level_inv;
+  int perm_total = 0;
+  int64_t xwork_elems = 0;
+  std::vector<void*> mem;
+  ~PlanDevice() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    for (void* p : mem) (void)hipFree(p);
+    (void)hipSetDevice(cur);
+  }
+};
+
+std::mutex g_plan_mu;
+// Never destroyed: device memory of cached plans is released with the process,
+// not by a static destructor running after the HIP runtime has shut down.
+auto& g_plans = *new std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<PlanDevice>>();
+
+std::shared_ptr<PlanDevice> get_plan(int d, int n, int b, int order) {
+  int dev = 0;
+  SPP_HIP(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, d, n, b, order);
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) return it->second;
+  auto pd = std::make_shared<PlanDevice>();
+  pd->device = dev;
+  std::string err = build_plan(d, n, b, order, pd->plan);
+  if (!err.empty()) throw Error(SPP_EINVAL, err);
+  const Plan& P = pd->plan;
+  std::vector<FrontDev> fd(P.fronts.size());
+  for (const Level& L : P.levels) {
+    int64_t xo = 0;
+    const bool inv = mf_level_uses_inverse(L.end - L.begin, L.maxP);
+    pd->level_inv.push_back(inv ? 1 : 0);
+    for (int fi = L.begin; fi < L.end; ++fi) {
+      const Front& f = P.fronts[fi];
+      FrontDev& g_ = fd[fi];
+      g_.off = f.off; g_.voff = f.voff; g_.xoff = xo;
+      g_.F = f.F; g_.p = f.p; g_.idx = f.idx; g_.map = f.map; g_.perm = pd->perm_total;
+      g_.nchild = static_cast<int>(f.children.size());
+      if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
+      for (int c = 0; c < g_.nchild; ++c) g_.child[c] = f.children[c];
+      pd->perm_total += f.p;
+      if (inv) xo += 2LL * f.p * f.p;
+    }
+    pd->xwork_elems = std::max(pd->xwork_elems, xo);
+  }
+  std::vector<AsmBlockDev> bd(P.blocks.size());
+  for (size_t i = 0; i < P.blocks.size(); ++i)
+    bd[i] = AsmBlockDev{P.blocks[i].front, P.blocks[i].type, P.blocks[i].anchor, P.blocks[i].rowpos, P.blocks[i].colpos};
+  auto upload = [&](const void* src, size_t bytes) {
+    void* p = nullptr;
+    SPP_HIP(hipMalloc(&p, std::max<size_t>(bytes, 4)));
+    pd->mem.push_back(p);
+    if (bytes) SPP_HIP(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
+    return p;
+  };
+  pd->fronts = static_cast<FrontDev*>(upload(fd.data(), fd.size() * sizeof(FrontDev)));
+  pd->blocks = static_cast<AsmBlockDev*>(upload(bd.data(), bd.size() * sizeof(AsmBlockDev)));
+  pd->pos = static_cast<int*>(upload(P.pos.data(), P.pos.size() * sizeof(int)));
+  pd->idx = static_cast<int*>(upload(P.idx.data(), P.idx.size() * sizeof(int)));
+  pd->map = static_cast<int*>(upload(P.map.data(), P.map.size() * sizeof(int)));
+  for (size_t t = 0; t < P.types.size(); ++t)
+    pd->off[t] = static_cast<int*>(upload(P.types[t].off.data(), P.types[t].off.size() * sizeof(int)));
+  g_plans[key] = pd;
+  return pd;
+}
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -39,7 +155,8 @@ double now_ms() {
 }  // namespace
 
 struct spp_factor {
-  Plan plan;
+  std::shared_ptr<PlanDevice> pd;   // shared, read-only plan (see get_plan)
+  const Plan* planp = nullptr;
   int kind = 0;
   double omega = 0, ell = 1, energy = 0;
   spp_options opt{};
@@ -56,7 +173,9 @@ struct spp_factor {
   MfDev mf{};
   void* arena = nullptr;
   size_t csize = 16;  // bytes per complex front entry
-  std::vector<int> level_begin, level_maxF, level_maxP;
+  std::vector<int> level_begin, level_maxF, level_maxP, level_inv;
+  void* gpart = nullptr;       // split-K partial sums of the substitution
+  int64_t gpart_cap = 0;
   // solve work (grown on demand)
   int cap_rhs = 0, cap_iter = 0;
   double2* tmp = nullptr;      // FFT scratch, nrhs * N
@@ -71,6 +190,7 @@ struct spp_factor {
   double* h_resid = nullptr;   // pinned host copy of residual estimates
   spp_stats_t stats{};
   hipStream_t last_stream = nullptr;
+  std::unique_ptr<KernelTimer> timer;
 
   template <typename T> T* dalloc(size_t count) {
     void* p = nullptr;
@@ -92,6 +212,13 @@ struct spp_factor {
 };
 
 namespace {
+
+// Makes the factor's kernel timer current for the duration of one ABI call.
+struct TimerScope {
+  KernelTimer* prev;
+  explicit TimerScope(spp_factor* F) : prev(g_timer) { g_timer = (F && F->timer) ? F->timer.get() : nullptr; }
+  ~TimerScope() { g_timer = prev; }
+};
 
 int fail(const Error& e) {
   g_last_error = e.what();
@@ -136,17 +263,19 @@ double shift_gap(int d, int n, double s) {
 void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   if (nrhs <= F->cap_rhs && iters <= F->cap_iter) return;
   const int r = std::max(nrhs, F->cap_rhs), it = std::max(iters, F->cap_iter);
-  for (void* p : {(void*)F->tmp, (void*)F->qr, F->wv, F->zv, F->xc, (void*)F->V, (void*)F->Z, (void*)F->H,
+  for (void* p : {(void*)F->tmp, (void*)F->qr, F->wv, F->zv, F->xc, F->gpart, (void*)F->V, (void*)F->Z, (void*)F->H,
                   (void*)F->gv, (void*)F->sn, (void*)F->y, (void*)F->g0, (void*)F->wk, (void*)F->h2,
                   (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec})
     F->dfree(p);
   if (F->h_resid) { (void)hipHostFree(F->h_resid); F->h_resid = nullptr; }
-  const int64_t N = F->plan.N;
+  const int64_t N = F->planp->N;
   F->tmp = F->dalloc<double2>((size_t)r * N);
   F->qr = F->dalloc<double2>((size_t)r * N);
-  F->wv = F->dalloc<char>((size_t)F->plan.vec_elems * r * F->csize);
-  F->zv = F->dalloc<char>((size_t)F->plan.vec_elems * r * F->csize);
+  F->wv = F->dalloc<char>((size_t)F->planp->vec_elems * r * F->csize);
+  F->zv = F->dalloc<char>((size_t)F->planp->vec_elems * r * F->csize);
   F->xc = F->dalloc<char>((size_t)N * r * F->csize);
+  F->gpart_cap = (int64_t)131072 * r;
+  F->gpart = F->dalloc<char>((size_t)F->gpart_cap * F->csize);
   F->V = F->dalloc<double2>((size_t)(it + 1) * r * N);
   F->Z = F->dalloc<double2>((size_t)it * r * N);
   const size_t ld = it + 1;
@@ -170,24 +299,24 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
 }
 
 void apply_operator(spp_factor* F, const double2* z, double2* w, int nrhs, hipStream_t st) {
-  fft_multi(st, z, w, F->tmp, F->tw, F->plan.d, F->plan.n, nrhs, F->q, F->sigma, z);
+  fft_multi(st, z, w, F->tmp, F->tw, F->planp->d, F->planp->n, nrhs, F->q, F->sigma, z);
 }
 
 void apply_green(spp_factor* F, const double2* f, double2* g, int nrhs, hipStream_t st) {
-  fft_multi(st, f, g, F->tmp, F->tw, F->plan.d, F->plan.n, nrhs, nullptr, F->sigma, nullptr);
+  fft_multi(st, f, g, F->tmp, F->tw, F->planp->d, F->planp->n, nrhs, nullptr, F->sigma, nullptr);
 }
 
 void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st) {
   q_apply(st, F->mf, r, F->qr, nrhs);
-  const int nl = static_cast<int>(F->plan.levels.size());
+  const int nl = static_cast<int>(F->planp->levels.size());
   if (F->opt.prec == SPP_C128) {
     mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(),
-                     F->level_maxF.data(), F->level_maxP.data(), nl);
+                     F->level_maxF.data(), F->level_maxP.data(), F->level_inv.data(), nl, F->gpart, F->gpart_cap);
   } else {
-    const int64_t cnt = (int64_t)nrhs * F->plan.N;
+    const int64_t cnt = (int64_t)nrhs * F->planp->N;
     cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
     mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(),
-                    F->level_maxF.data(), F->level_maxP.data(), nl);
+                    F->level_maxF.data(), F->level_maxP.data(), F->level_inv.data(), nl, F->gpart, F->gpart_cap);
     cast_vectors<float>(st, F->xc, z, cnt, 1);
   }
 }
@@ -213,9 +342,21 @@ int do_setup(const spp_problem* pb, const spp_options* op, hipStream_t st, spp_f
   F->opt = *op;
   F->csize = (op->prec == SPP_C128) ? sizeof(double2) : sizeof(float2);
   F->last_stream = st;
-  std::string err = build_plan(pb->dim, pb->n, pb->b, op->order, F->plan);
-  if (!err.empty()) throw Error(SPP_EINVAL, err);
-  const Plan& P = F->plan;
+  if (op->flags & SPP_F_TIMING) F->timer = std::make_unique<KernelTimer>();
+  TimerScope timer_scope(F.get());
+  {
+    std::string err = validate_grid(pb->dim, pb->n, pb->b);
+    if (!err.empty()) throw Error(SPP_EINVAL, err);
+  }
+  {
+    // Leaf sets are assembled and applied by one workgroup with their
+    // neighbourhood staged in LDS: |gamma(S)| <= 1024 (2D: b <= 30, 3D: b <= 9).
+    const int g = (pb->dim == 2) ? (pb->b + 1) * (pb->b + 1) : (pb->b + 1) * (pb->b + 1) * (pb->b + 1);
+    if (g > 1024) throw Error(SPP_ENOTIMPL, "leaf box too large: (b + 1)^d must be <= 1024");
+  }
+  F->pd = get_plan(pb->dim, pb->n, pb->b, op->order);
+  F->planp = &F->pd->plan;
+  const Plan& P = *F->planp;
   const int d = P.d, n = P.n;
   const int64_t N = P.N;
 
@@ -265,58 +406,33 @@ int do_setup(const spp_problem* pb, const spp_options* op, hipStream_t st, spp_f
     const SetType& T = P.types[t];
     StencilDev& S = F->sten[t];
     S.nS = T.nS; S.nB = T.nB; S.nG = T.nG;
-    int* off = F->dalloc<int>(T.off.size());
-    SPP_HIP(hipMemcpyAsync(off, T.off.data(), T.off.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    S.off = off;
+    S.off = F->pd->off[t];
     S.T = F->dalloc<double2>((size_t)T.nS * T.nB);
     S.C = F->dalloc<double2>((size_t)T.nS * T.nG);
     S.Tt = F->dalloc<double2>((size_t)T.nS * T.nB);
+    S.Ct = F->dalloc<double2>((size_t)T.nS * T.nG);
     stencil_build(st, d, n, g, g2, S, swork, info + 1 + (int)t);
   }
   F->dfree(g);
   F->dfree(g2);
 
-  // a5-a6: plan upload, assembly and factorisation.
-  std::vector<FrontDev> fd(P.fronts.size());
-  int perm_total = 0;
-  int64_t xwork_elems = 0;
-  for (const Level& L : P.levels) {
-    int64_t xo = 0;
-    for (int fi = L.begin; fi < L.end; ++fi) {
-      const Front& f = P.fronts[fi];
-      FrontDev& g_ = fd[fi];
-      g_.off = f.off; g_.voff = f.voff; g_.xoff = xo;
-      g_.F = f.F; g_.p = f.p; g_.idx = f.idx; g_.map = f.map; g_.perm = perm_total;
-      g_.nchild = static_cast<int>(f.children.size());
-      if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
-      for (int c = 0; c < g_.nchild; ++c) g_.child[c] = f.children[c];
-      perm_total += f.p;
-      xo += 2LL * f.p * f.p;
-    }
-    xwork_elems = std::max(xwork_elems, xo);
-  }
-  std::vector<AsmBlockDev> bd(P.blocks.size());
-  for (size_t i = 0; i < P.blocks.size(); ++i)
-    bd[i] = AsmBlockDev{P.blocks[i].front, P.blocks[i].type, P.blocks[i].anchor, P.blocks[i].rowpos, P.blocks[i].colpos};
-  auto upload = [&](const void* src, size_t bytes) {
-    void* p = F->dalloc<char>(bytes);
-    SPP_HIP(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, st));
-    return p;
-  };
+  // a5-a6: assembly and factorisation on the shared plan.
+  const int perm_total = F->pd->perm_total;
+  const int64_t xwork_elems = F->pd->xwork_elems;
   MfDev& mf = F->mf;
   mf.d = d; mf.n = n; mf.b = P.b; mf.m = P.m; mf.N = N;
-  mf.fronts = static_cast<const FrontDev*>(upload(fd.data(), fd.size() * sizeof(FrontDev)));
-  mf.blocks = static_cast<const AsmBlockDev*>(upload(bd.data(), bd.size() * sizeof(AsmBlockDev)));
-  mf.pos = static_cast<const int*>(upload(P.pos.data(), P.pos.size() * sizeof(int)));
-  mf.idx = static_cast<const int*>(upload(P.idx.data(), P.idx.size() * sizeof(int)));
-  mf.map = static_cast<const int*>(upload(P.map.data(), std::max<size_t>(1, P.map.size()) * sizeof(int)));
+  mf.fronts = F->pd->fronts;
+  mf.blocks = F->pd->blocks;
+  mf.pos = F->pd->pos;
+  mf.idx = F->pd->idx;
+  mf.map = F->pd->map;
   mf.perm = F->dalloc<int>(perm_total);
   mf.ipiv = F->dalloc<int>(perm_total);
   mf.q = F->q;
   mf.info = info;
   for (size_t t = 0; t < P.types.size(); ++t) {
     const StencilDev& S = F->sten[t];
-    mf.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt};
+    mf.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
   }
   F->level_begin.clear();
   for (const Level& L : P.levels) {
@@ -324,6 +440,7 @@ int do_setup(const spp_problem* pb, const spp_options* op, hipStream_t st, spp_f
     F->level_maxF.push_back(L.maxF);
     F->level_maxP.push_back(L.maxP);
   }
+  F->level_inv = F->pd->level_inv;
   F->level_begin.push_back(static_cast<int>(P.fronts.size()));
 
   F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
@@ -338,10 +455,10 @@ int do_setup(const spp_problem* pb, const spp_options* op, hipStream_t st, spp_f
     SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + first.off * F->csize, 0, span * F->csize, st));
     if (F->opt.prec == SPP_C128)
       mf_factor_level<double>(st, mf, F->arena, xwork, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                              L.max_children, l > 0 ? P.levels[l - 1].begin : 0);
+                              L.max_children, F->level_inv[l] != 0);
     else
       mf_factor_level<float>(st, mf, F->arena, xwork, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                             L.max_children, l > 0 ? P.levels[l - 1].begin : 0);
+                             L.max_children, F->level_inv[l] != 0);
   }
   int hinfo[16];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
@@ -376,9 +493,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   if (!F || !fv || !uv || !iters || !relres || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
   const double t0 = now_ms();
   F->last_stream = st;
+  TimerScope timer_scope(F);
   const int maxit = F->opt.max_iter;
   ensure_solve_buffers(F, nrhs, maxit);
-  const int64_t N = F->plan.N;
+  const int64_t N = F->planp->N;
   const int64_t vstride = (int64_t)nrhs * N;
   const int ld = F->cap_iter + 1;           // Hessenberg column stride and per-RHS vector stride
   const int hrhs = ld * F->cap_iter;        // Hessenberg stride between right-hand sides
@@ -473,6 +591,7 @@ int spp_apply_operator(spp_factor* factor, const void* z, void* w, int32_t nrhs,
   return guarded([&] {
     if (!factor || !z || !w || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
     ensure_solve_buffers(factor, nrhs, factor->opt.max_iter);
+    TimerScope timer_scope(factor);
     apply_operator(factor, static_cast<const double2*>(z), static_cast<double2*>(w), nrhs,
                    reinterpret_cast<hipStream_t>(stream));
     return SPP_OK;
@@ -483,6 +602,7 @@ int spp_apply_green(spp_factor* factor, const void* f, void* g, int32_t nrhs, sp
   return guarded([&] {
     if (!factor || !f || !g || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
     ensure_solve_buffers(factor, nrhs, factor->opt.max_iter);
+    TimerScope timer_scope(factor);
     apply_green(factor, static_cast<const double2*>(f), static_cast<double2*>(g), nrhs,
                 reinterpret_cast<hipStream_t>(stream));
     return SPP_OK;
@@ -493,6 +613,7 @@ int spp_apply_q(spp_factor* factor, const void* r, void* y, int32_t nrhs, spp_st
   return guarded([&] {
     if (!factor || !r || !y || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
     if (r == y) throw Error(SPP_EINVAL, "spp_apply_q: r and y must not alias");
+    TimerScope timer_scope(factor);
     q_apply(reinterpret_cast<hipStream_t>(stream), factor->mf, static_cast<const double2*>(r),
             static_cast<double2*>(y), nrhs);
     return SPP_OK;
@@ -503,6 +624,7 @@ int spp_apply_precond(spp_factor* factor, const void* r, void* z, int32_t nrhs, 
   return guarded([&] {
     if (!factor || !r || !z || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
     ensure_solve_buffers(factor, nrhs, factor->opt.max_iter);
+    TimerScope timer_scope(factor);
     apply_precond(factor, static_cast<const double2*>(r), static_cast<double2*>(z), nrhs,
                   reinterpret_cast<hipStream_t>(stream));
     return SPP_OK;
@@ -514,7 +636,7 @@ int spp_get_coefficients(const spp_factor* factor, double* s, double* q) {
     if (!factor) throw Error(SPP_EINVAL, "null factor");
     if (s) *s = factor->s;
     if (q) {
-      SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * factor->plan.N, hipMemcpyDeviceToDevice));
+      SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * factor->planp->N, hipMemcpyDeviceToDevice));
     }
     return SPP_OK;
   });
@@ -524,8 +646,8 @@ int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t
                     void* C) {
   return guarded([&] {
     if (!factor) throw Error(SPP_EINVAL, "null factor");
-    if (type < 0 || type >= (1 << factor->plan.d)) throw Error(SPP_EINVAL, "set type out of range");
-    const SetType& ST = factor->plan.types[type];
+    if (type < 0 || type >= (1 << factor->planp->d)) throw Error(SPP_EINVAL, "set type out of range");
+    const SetType& ST = factor->planp->types[type];
     const StencilDev& S = factor->sten[type];
     if (nS) *nS = ST.nS;
     if (nB) *nB = ST.nB;
@@ -540,6 +662,42 @@ int spp_stats(const spp_factor* factor, spp_stats_t* out) {
   return guarded([&] {
     if (!factor || !out) throw Error(SPP_EINVAL, "null argument");
     *out = factor->stats;
+    return SPP_OK;
+  });
+}
+
+int spp_kernel_timing(const spp_factor* factor, int32_t kclass, double* total_ms, int64_t* launches, double* bytes,
+                      double* flops) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (kclass < 0 || kclass >= KC_COUNT) throw Error(SPP_EINVAL, "kernel class out of range");
+    double ms = 0;
+    int64_t n = 0;
+    double by = 0, fl = 0;
+    if (factor->timer) {
+      KernelTimer& T = *factor->timer;
+      for (auto& pr : T.ev[kclass]) {
+        SPP_HIP(hipEventSynchronize(pr.second));
+        float t = 0;
+        SPP_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+        ms += t;
+      }
+      n = T.launches[kclass];
+      by = T.bytes[kclass];
+      fl = T.flops[kclass];
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
+    return SPP_OK;
+  });
+}
+
+int spp_kernel_timing_reset(spp_factor* factor) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (factor->timer) factor->timer = std::make_unique<KernelTimer>();
     return SPP_OK;
   });
 }

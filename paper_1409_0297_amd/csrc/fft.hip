@@ -198,8 +198,14 @@ void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw
   g.L = L;
   const size_t lds = 2 * sizeof(double2) * L * n;
   const unsigned blocks = static_cast<unsigned>(batch * (lines / L));
+  // Algorithmic bytes: read and write every complex point once, plus the
+  // fused real multipliers and the added vector.
+  const double pts = (double)N * batch;
+  const double bytes = pts * 32.0 + (pre ? 8.0 * N : 0.0) + (mid ? 8.0 * N : 0.0) + (add ? 16.0 * pts : 0.0);
+  timer_begin(KC_FFT, st);
   fft_axis_kernel<<<blocks, kFftThreads, lds, st>>>(in, out, tw, g, dir, pre, mid, add);
   SPP_LAUNCH_CHECK();
+  timer_end(KC_FFT, st, bytes, 0.0);
 }
 
 // (I + G q) z, G f, or plain transforms, over all d axes of [batch][n]^d.

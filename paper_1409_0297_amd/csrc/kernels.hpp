@@ -6,6 +6,17 @@
 
 namespace spp {
 
+// ------------------------------------------------------------- timing
+// Optional per-kernel-class HIP event timing (enabled per factor by
+// SPP_F_TIMING).  The launchers bracket the launches of each class with
+// events on the launch stream and record the algorithmic bytes and flops of
+// that launch; spp_kernel_timing() reads the totals back.
+enum KernelClass { KC_FFT = 0, KC_GEMV = 1, KC_TRI = 2, KC_GEMM = 3, KC_PANEL = 4, KC_QAPPLY = 5, KC_COUNT = 6 };
+struct KernelTimer;
+extern thread_local KernelTimer* g_timer;
+void timer_begin(int cls, hipStream_t st);
+void timer_end(int cls, hipStream_t st, double bytes, double flops);
+
 // ------------------------------------------------------------- fft.hip
 void fft_make_twiddles(double2* tw, int n, hipStream_t st);
 bool fft_supported(int n);
@@ -35,6 +46,7 @@ struct StencilDev {
   double2* T;          // nS x nB, row-major
   double2* C;          // nS x nG, row-major
   double2* Tt;         // nB x nS (T transposed), row-major
+  double2* Ct;         // nG x nS (C transposed), row-major
 };
 // Builds T_S and C_S for one set type from the kernels g (of G) and g2 (of G G^H).
 // work must hold 2 nG^2 + 2 nG nB + nB^2 + nS nB complex entries.
@@ -62,6 +74,7 @@ struct TypeDev {       // per set type, for assembly / Q apply
   const double2* T;
   const double2* C;
   const double2* Tt;
+  const double2* Ct;
 };
 
 struct MfDev {
@@ -82,14 +95,18 @@ struct MfDev {
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
-                     int max_children, int prev_f0);
+                     int max_children, bool invert);
+// Whether a level keeps explicit inverses of its pivot-block factors (few large
+// fronts) or solves with the LU in place (many small fronts).
+bool mf_level_uses_inverse(int nfronts, int maxP);
 
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);
 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void* z,
               const void* x_in, void* x_out, int nrhs,
-              const int* level_begin, const int* level_maxF, const int* level_maxP, int nlevels);
+              const int* level_begin, const int* level_maxF, const int* level_maxP,
+              const int* level_inv, int nlevels, void* partial, int64_t partial_cap);
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);

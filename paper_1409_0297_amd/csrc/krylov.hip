@@ -66,13 +66,17 @@ __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* _
   }
 }
 
+// One wavefront per (vector, right-hand side) sums the per-block partials.
 __global__ void dots_final_kernel(const double2* __restrict__ partial, int nblk, int nvec, double2* h, int hstride,
                                   int accumulate, double2* h_acc, int acc_stride) {
   const int rhs = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= nvec) return;
   double2 s = cmake<double2>(0, 0);
-  for (int b = 0; b < nblk; ++b) s = cadd(s, partial[((int64_t)rhs * nblk + b) * nvec + i]);
+  for (int b = lane; b < nblk; b += 64) s = cadd(s, partial[((int64_t)rhs * nblk + b) * nvec + i]);
+  s = wave_sum(s);
+  if (lane != 0) return;
   double2* hr = h + (int64_t)rhs * hstride;
   hr[i] = accumulate ? cadd(hr[i], s) : s;
   if (h_acc) {
@@ -228,7 +232,7 @@ void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const 
   const int nblk = dot_blocks(N);
   dots_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, partial);
   SPP_LAUNCH_CHECK();
-  dots_final_kernel<<<dim3(ceil_div(nvec, 64), nrhs), 64, 0, st>>>(partial, nblk, nvec, h_out, hstride, accumulate,
+  dots_final_kernel<<<dim3(ceil_div(nvec, 4), nrhs), 256, 0, st>>>(partial, nblk, nvec, h_out, hstride, accumulate,
                                                                        h_acc, acc_stride);
   SPP_LAUNCH_CHECK();
 }

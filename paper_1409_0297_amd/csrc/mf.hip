@@ -17,6 +17,8 @@
 //              product.
 // The solve runs forward elimination leaves -> root (children's update
 // vectors pulled by the parent) and back substitution root -> leaves.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -52,24 +54,35 @@ __device__ inline int anchor_point(const MfDev& mf, int anchor, const int* off) 
 
 // ------------------------------------------------------------------ assembly
 template <typename R>
-__global__ void assemble_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int blk0) {
+__global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int blk0) {
   using C = cplx_t<R>;
   const AsmBlockDev B = mf.blocks[blk0 + blockIdx.x];
   const FrontDev f = mf.fronts[B.front];
   const TypeDev T = mf.types[B.type];
   C* A = arena + f.off;
+  // Column data of this block once per workgroup: front position and q at
+  // every point of gamma(S).
+  __shared__ int cpos[1024];
+  __shared__ double qg[1024];
+  __shared__ int rpos[1024];
+  for (int j = threadIdx.x; j < T.nG; j += blockDim.x) {
+    cpos[j] = mf.pos[B.colpos + j];
+    qg[j] = mf.q[anchor_point(mf, B.anchor, T.off + j * mf.d)];
+  }
+  for (int i = threadIdx.x; i < T.nS; i += blockDim.x) rpos[i] = mf.pos[B.rowpos + i];
+  __syncthreads();
+  // Consecutive threads take consecutive rows of one column: coalesced reads
+  // of the transposed stencils and coalesced writes into the column-major front.
   const int total = T.nS * T.nG;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int i = t / T.nG, j = t - i * T.nG;
-    const int rp = mf.pos[B.rowpos + i];
-    const int cp = mf.pos[B.colpos + j];
+    const int j = t / T.nS, i = t - j * T.nS;
+    const int rp = rpos[i], cp = cpos[j];
     if (rp < 0 || cp < 0) continue;
-    const int g = anchor_point(mf, B.anchor, T.off + j * mf.d);
-    double2 v = cscale(T.C[i * T.nG + j], mf.q[g]);
+    double2 v = cscale(T.Ct[(int64_t)j * T.nS + i], qg[j]);
     if (j < T.nS) {
       if (j == i) v.x += 1.0;
     } else {
-      v = csub(v, T.T[i * T.nB + (j - T.nS)]);
+      v = csub(v, T.Tt[(int64_t)(j - T.nS) * T.nS + i]);
     }
     C& dst = A[(int64_t)cp * f.F + rp];
     dst = cadd(dst, cconvert<C>(v));
@@ -159,6 +172,210 @@ __global__ void __launch_bounds__(256) panel_kernel(MfDev mf, cplx_t<R>* __restr
     }
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------------ register panel LU
+// Factors the panel columns [k0, k0 + kb) over rows [k0, F) of one front per
+// workgroup.  The panel is processed in sub-panels of 8 columns held in
+// registers (thread t owns rows c0 + t + i NT); per column: argmax over the
+// fully-summed rows by wave shuffles and one LDS round, the pivot row swap
+// through LDS, then scaling and the rank-1 update entirely in registers (two
+// barriers per column).  Interchanges are applied here only to the panel's own
+// columns; laswp_kernel applies them to the rest of the front.  After each
+// sub-panel the remaining panel columns receive its U rows and rank-8 update.
+constexpr int kSW = 8;
+
+template <typename R, int NT, int RPT>
+__global__ void __launch_bounds__(NT) panel2_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
+                                                    int f0, int k0, int nb) {
+  using C = cplx_t<R>;
+  constexpr int NW = NT / 64;
+  const int fi = f0 + blockIdx.x;
+  const FrontDev f = mf.fronts[fi];
+  if (k0 >= f.p) return;
+  const int kb = min(nb, f.p - k0);
+  const int F = f.F, p = f.p;
+  C* A = arena + f.off;
+  __shared__ R red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ C prow[kSW], jrow[kSW];
+  __shared__ C Ub[kSW][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  C a[RPT][kSW];
+  for (int c0 = k0; c0 < k0 + kb; c0 += kSW) {
+    const int sw = min(kSW, k0 + kb - c0);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = c0 + tid + i * NT;
+#pragma unroll
+      for (int jj = 0; jj < kSW; ++jj)
+        a[i][jj] = (r < F && jj < sw) ? A[(int64_t)(c0 + jj) * F + r] : cmake<C>(0, 0);
+    }
+#pragma unroll
+    for (int jj = 0; jj < kSW; ++jj) {
+      if (jj >= sw) break;   // sw is uniform over the workgroup
+      const int j = c0 + jj;
+      R best = -1;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = c0 + tid + i * NT;
+        if (r >= j && r < p) {
+          const R v = cabs2(a[i][jj]);
+          if (v > best) { best = v; bi = r; }
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const R ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (lane == 0) { red_v[wave] = best; red_i[wave] = bi; }
+      __syncthreads();
+      best = red_v[0];
+      bi = red_i[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const R ov = red_v[w];
+        const int oi = red_i[w];
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      const bool ok = best > R(0) && isfinite(best);
+      const int piv = ok ? bi : j;
+      const int tp = (piv - c0) % NT, ip = (piv - c0) / NT;
+      const int tj = (j - c0) % NT, ij = (j - c0) / NT;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        if (tid == tp && i == ip)
+#pragma unroll
+          for (int x = 0; x < kSW; ++x) prow[x] = a[i][x];
+        if (tid == tj && i == ij)
+#pragma unroll
+          for (int x = 0; x < kSW; ++x) jrow[x] = a[i][x];
+      }
+      if (piv != j) {
+        // Other columns of this outer panel (outside the register sub-panel).
+        for (int c = tid; c < kb - sw; c += NT) {
+          const int col = (c < c0 - k0) ? k0 + c : c0 + sw + (c - (c0 - k0));
+          C* cp = A + (int64_t)col * F;
+          const C t = cp[j]; cp[j] = cp[piv]; cp[piv] = t;
+        }
+      }
+      if (tid == 0) {
+        ipiv[f.perm + j] = piv;
+        if (!ok) atomicCAS(mf.info, 0, fi + 1);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        if (tid == tj && i == ij)
+#pragma unroll
+          for (int x = 0; x < kSW; ++x) a[i][x] = prow[x];
+        if (piv != j && tid == tp && i == ip)
+#pragma unroll
+          for (int x = 0; x < kSW; ++x) a[i][x] = jrow[x];
+      }
+      const C inv = ok ? crecip(prow[jj]) : cmake<C>(0, 0);
+      C pr[kSW];
+#pragma unroll
+      for (int x = 0; x < kSW; ++x) pr[x] = prow[x];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = c0 + tid + i * NT;
+        if (r > j && r < F) {
+          C l;
+#pragma unroll
+          for (int x = 0; x < kSW; ++x) {
+            if (x == jj) { l = cmul(a[i][x], inv); a[i][x] = l; }
+          }
+#pragma unroll
+          for (int x = 0; x < kSW; ++x)
+            if (x > jj && x < sw) cfms(a[i][x], l, pr[x]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = c0 + tid + i * NT;
+      if (r < F)
+#pragma unroll
+        for (int jj = 0; jj < kSW; ++jj)
+          if (jj < sw) A[(int64_t)(c0 + jj) * F + r] = a[i][jj];
+    }
+    __syncthreads();
+    const int rw = k0 + kb - (c0 + sw);
+    if (rw > 0) {
+      // U rows of this sub-panel for the remaining panel columns.
+      for (int c = tid; c < rw; c += NT) {
+        C* cp = A + (int64_t)(c0 + sw + c) * F + c0;
+        C x[kSW];
+#pragma unroll
+        for (int jj = 0; jj < kSW; ++jj) x[jj] = (jj < sw) ? cp[jj] : cmake<C>(0, 0);
+#pragma unroll
+        for (int jj = 1; jj < kSW; ++jj)
+#pragma unroll
+          for (int l = 0; l < kSW; ++l)
+            if (l < jj && jj < sw) cfms(x[jj], A[(int64_t)(c0 + l) * F + c0 + jj], x[l]);
+#pragma unroll
+        for (int jj = 0; jj < kSW; ++jj)
+          if (jj < sw) { cp[jj] = x[jj]; Ub[jj][c] = x[jj]; }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = c0 + tid + i * NT;
+        if (r >= c0 + sw && r < F) {
+          for (int c = 0; c < rw; ++c) {
+            C& d = A[(int64_t)(c0 + sw + c) * F + r];
+            C s = d;
+#pragma unroll
+            for (int jj = 0; jj < kSW; ++jj)
+              if (jj < sw) cfms(s, a[i][jj], Ub[jj][c]);
+            d = s;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Applies the interchanges of panel [k0, k0 + kb) to the columns outside it:
+// the net permutation of the touched rows is built once per workgroup, then
+// every column gathers its touched rows and scatters them back.
+template <typename R>
+__global__ void __launch_bounds__(64) laswp_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, const int* __restrict__ ipiv,
+                                                   int f0, int k0, int nb) {
+  using C = cplx_t<R>;
+  const FrontDev f = mf.fronts[f0 + blockIdx.y];
+  if (k0 >= f.p) return;
+  const int kb = min(nb, f.p - k0);
+  __shared__ int rows[128], lab[128], cnt;
+  __shared__ C tmp[64][65];
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int j = k0; j < k0 + kb; ++j) {
+      const int pv = ipiv[f.perm + j];
+      if (pv == j) continue;
+      int a = -1, b = -1;
+      for (int x = 0; x < n; ++x) { if (rows[x] == j) a = x; if (rows[x] == pv) b = x; }
+      if (a < 0) { rows[n] = j; lab[n] = j; a = n++; }
+      if (b < 0) { rows[n] = pv; lab[n] = pv; b = n++; }
+      const int t = lab[a]; lab[a] = lab[b]; lab[b] = t;
+    }
+    int m = 0;
+    for (int x = 0; x < n; ++x)
+      if (lab[x] != rows[x]) { rows[m] = rows[x]; lab[m] = lab[x]; ++m; }
+    cnt = m;
+  }
+  __syncthreads();
+  const int n = cnt;   // at most 2 kb <= 64 touched rows (nb <= 32)
+  if (n == 0 || n > 64) return;
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  if (col >= f.F || (col >= k0 && col < k0 + kb)) return;
+  C* cp = arena + f.off + (int64_t)col * f.F;
+  for (int x = 0; x < n; ++x) tmp[threadIdx.x][x] = cp[lab[x]];
+  for (int x = 0; x < n; ++x) cp[rows[x]] = tmp[threadIdx.x][x];
 }
 
 // ------------------------------------------------------------------ row-block TRSM
@@ -364,16 +581,22 @@ __global__ void merge_inverse_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, co
   }
 }
 
-__global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0, int f1) {
-  const int fi = f0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (fi >= f1) return;
-  const FrontDev f = mf.fronts[fi];
-  int* perm = mf.perm + f.perm;
-  for (int i = 0; i < f.p; ++i) perm[i] = i;
-  for (int j = 0; j < f.p; ++j) {
-    const int r = ipiv[f.perm + j];
-    const int t = perm[j]; perm[j] = perm[r]; perm[r] = t;
-  }
+// Final row permutation of each front's pivot block from the interchange
+// record: one workgroup per front, the bookkeeping done in LDS.
+__global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0) {
+  const FrontDev f = mf.fronts[f0 + blockIdx.x];
+  extern __shared__ int sp[];
+  int* perm = sp;
+  int* piv = sp + f.p;
+  for (int i = threadIdx.x; i < f.p; i += blockDim.x) { perm[i] = i; piv[i] = ipiv[f.perm + i]; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < f.p; ++j) {
+      const int r = piv[j];
+      const int t = perm[j]; perm[j] = perm[r]; perm[r] = t;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < f.p; i += blockDim.x) mf.perm[f.perm + i] = perm[i];
 }
 
 // ------------------------------------------------------------------ Q apply
@@ -431,12 +654,14 @@ __global__ void fwd_gather_kernel(MfDev mf, cplx_t<R>* __restrict__ W, const cpl
 template <typename R, int NR>
 __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ W,
                                                    cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout, int nrhs,
-                                                   int r0, int f0, int mode) {
+                                                   int r0, int f0, int mode, int nchunks, cplx_t<R>* __restrict__ partial,
+                                                   int prow) {
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   const int F = f.F, p = f.p;
   const int nrows = (mode == 1) ? F - p : p;
-  const int row0 = blockIdx.x * 64;
+  const int chunk = blockIdx.x % nchunks;
+  const int row0 = (blockIdx.x / nchunks) * 64;
   if (row0 >= nrows) return;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int row = row0 + lane;
@@ -450,6 +675,11 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   else if (mode == 1) { jlo = 0; jhi = p; }
   else if (mode == 2) { jlo = 0; jhi = F - p; }
   else { jlo = row0; jhi = p; }
+  if (nchunks > 1) {
+    const int span = jhi - jlo, csz = (span + nchunks - 1) / nchunks;
+    jlo = jlo + chunk * csz;
+    jhi = min(jhi, jlo + csz);
+  }
   C acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmake<C>(0, 0);
@@ -483,7 +713,9 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
     if (r0 + r >= nrhs) break;
     C s = cadd(cadd(red[0][lane][r], red[1][lane][r]), cadd(red[2][lane][r], red[3][lane][r]));
     const int rr = r0 + r;
-    if (mode == 0) {
+    if (nchunks > 1) {
+      partial[(((int64_t)blockIdx.y * nchunks + chunk) * prow + row) * nrhs + rr] = s;
+    } else if (mode == 0) {
       z[row * nrhs + rr] = cadd(s, w[perm[row] * nrhs + rr]);
     } else if (mode == 1) {
       C& d = w[(p + row) * nrhs + rr];
@@ -494,6 +726,174 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
     } else {
       xout[(int64_t)rr * mf.N + idx[row]] = s;
     }
+  }
+}
+
+// In-workgroup triangular solves with the pivot block kept in LU form, for
+// levels with many small fronts (one workgroup per front, 64-row blocks: the
+// diagonal block is solved by one wave with shuffles, the rows beyond it are
+// updated by the whole workgroup; the vector lives in LDS).
+//   fwd: z = L11^{-1} (P w_piv)          bwd: x(piv) = U11^{-1} z
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) fwd_tri_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ W,
+                                                      cplx_t<R>* __restrict__ Z, int nrhs, int r0, int f0) {
+  using C = cplx_t<R>;
+  constexpr int BS = 32;
+  const FrontDev f = mf.fronts[f0 + blockIdx.x];
+  const int F = f.F, p = f.p;
+  const C* A = arena + f.off;
+  const int* perm = mf.perm + f.perm;
+  const C* w = W + f.voff * nrhs;
+  C* z = Z + f.voff * nrhs;
+  const int nr = min(NR, nrhs - r0);
+  __shared__ C D[BS][BS + 1];
+  extern __shared__ unsigned char smem[];
+  C* y = reinterpret_cast<C*>(smem);          // p x NR
+  for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
+    const int i = t / NR, r = t - i * NR;
+    y[t] = (r < nr) ? w[perm[i] * nrhs + r0 + r] : cmake<C>(0, 0);
+  }
+  const int lane = threadIdx.x & 63;
+  for (int b0 = 0; b0 < p; b0 += BS) {
+    const int bs = min(BS, p - b0);
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int jj = t / BS, i = t - jj * BS;
+      D[i][jj] = (i < bs && jj < bs) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      C yi[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) yi[r] = (lane < bs) ? y[(b0 + lane) * NR + r] : cmake<C>(0, 0);
+      for (int jj = 0; jj < bs; ++jj) {
+        const C l = (lane > jj && lane < bs) ? D[lane][jj] : cmake<C>(0, 0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          C zj;
+          zj.x = __shfl(yi[r].x, jj, 64);
+          zj.y = __shfl(yi[r].y, jj, 64);
+          cfms(yi[r], l, zj);
+        }
+      }
+      if (lane < bs)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) y[(b0 + lane) * NR + r] = yi[r];
+    }
+    __syncthreads();
+    for (int i = b0 + bs + threadIdx.x; i < p; i += blockDim.x) {
+      C acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
+      for (int jj = 0; jj < bs; ++jj) {
+        const C l = A[(int64_t)(b0 + jj) * F + i];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfms(acc[r], l, y[(b0 + jj) * NR + r]);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) y[i * NR + r] = acc[r];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
+    const int i = t / NR, r = t - i * NR;
+    if (r < nr) z[i * nrhs + r0 + r] = y[t];
+  }
+}
+
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) bwd_tri_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ Z,
+                                                      cplx_t<R>* __restrict__ xout, int nrhs, int r0, int f0) {
+  using C = cplx_t<R>;
+  constexpr int BS = 32;
+  const FrontDev f = mf.fronts[f0 + blockIdx.x];
+  const int F = f.F, p = f.p;
+  const C* A = arena + f.off;
+  const int* idx = mf.idx + f.idx;
+  const C* z = Z + f.voff * nrhs;
+  const int nr = min(NR, nrhs - r0);
+  __shared__ C D[BS][BS + 1];
+  extern __shared__ unsigned char smem[];
+  C* y = reinterpret_cast<C*>(smem);
+  for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
+    const int i = t / NR, r = t - i * NR;
+    y[t] = (r < nr) ? z[i * nrhs + r0 + r] : cmake<C>(0, 0);
+  }
+  const int lane = threadIdx.x & 63;
+  for (int b0 = ((p - 1) / BS) * BS; b0 >= 0; b0 -= BS) {
+    const int bs = min(BS, p - b0);
+    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+      const int jj = t / BS, i = t - jj * BS;
+      D[i][jj] = (i < bs && jj < bs) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      C yi[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) yi[r] = (lane < bs) ? y[(b0 + lane) * NR + r] : cmake<C>(0, 0);
+      for (int jj = bs - 1; jj >= 0; --jj) {
+        const C u = (lane <= jj) ? D[lane][jj] : cmake<C>(0, 0);
+        const C dinv = (lane == jj && cabs2(u) > 0) ? crecip(u) : cmake<C>(0, 0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (lane == jj) yi[r] = cmul(yi[r], dinv);
+          C xj;
+          xj.x = __shfl(yi[r].x, jj, 64);
+          xj.y = __shfl(yi[r].y, jj, 64);
+          if (lane < jj) cfms(yi[r], u, xj);
+        }
+      }
+      if (lane < bs)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) y[(b0 + lane) * NR + r] = yi[r];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < b0; i += blockDim.x) {
+      C acc[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
+      for (int jj = 0; jj < bs; ++jj) {
+        const C u = A[(int64_t)(b0 + jj) * F + i];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfms(acc[r], u, y[(b0 + jj) * NR + r]);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) y[i * NR + r] = acc[r];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
+    const int i = t / NR, r = t - i * NR;
+    if (r < nr) xout[(int64_t)(r0 + r) * mf.N + idx[i]] = y[t];
+  }
+}
+
+// Sums the split-K partial products of gemv_kernel and applies the mode's
+// finishing step (see gemv_kernel).
+template <typename R>
+__global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z,
+                                   cplx_t<R>* __restrict__ xout, int nrhs, int f0, int mode, int nchunks,
+                                   const cplx_t<R>* __restrict__ partial, int prow) {
+  using C = cplx_t<R>;
+  const FrontDev f = mf.fronts[f0 + blockIdx.y];
+  const int nrows = (mode == 1) ? f.F - f.p : f.p;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * nrhs) return;
+  const int row = t / nrhs, rr = t - row * nrhs;
+  C s = cmake<C>(0, 0);
+  for (int c = 0; c < nchunks; ++c)
+    s = cadd(s, partial[(((int64_t)blockIdx.y * nchunks + c) * prow + row) * nrhs + rr]);
+  C* w = W + f.voff * nrhs;
+  C* z = Z + f.voff * nrhs;
+  if (mode == 0) {
+    z[row * nrhs + rr] = cadd(s, w[mf.perm[f.perm + row] * nrhs + rr]);
+  } else if (mode == 1) {
+    C& d = w[(f.p + row) * nrhs + rr];
+    d = csub(d, s);
+  } else if (mode == 2) {
+    C& d = z[row * nrhs + rr];
+    d = csub(d, s);
+  } else {
+    xout[(int64_t)rr * mf.N + mf.idx[f.idx + row]] = s;
   }
 }
 
@@ -511,9 +911,8 @@ constexpr int kNB = 32;
 
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, int f0, int f1, int maxF,
-                     int maxP, int blk0, int blk1, int max_children, int prev_f0) {
+                     int maxP, int blk0, int blk1, int max_children, bool invert) {
   using C = cplx_t<R>;
-  (void)prev_f0;
   C* arena = static_cast<C*>(arena_v);
   C* xwork = static_cast<C*>(xwork_v);
   const int nf = f1 - f0;
@@ -530,17 +929,35 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   const int steps = (maxP + kNB - 1) / kNB;
   const int tiles = (int)ceil_div(maxF, kBM);
   for (int s = 0; s < steps; ++s) {
-    panel_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, s * kNB, kNB, 0);
+    const int k0 = s * kNB;
+    timer_begin(KC_PANEL, st);
+    if (maxF <= 512) panel2_kernel<R, 256, 2><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+    else if (maxF <= 1024) panel2_kernel<R, 512, 2><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+    else if (maxF <= 2048) panel2_kernel<R, 512, 4><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+    else if (maxF <= 4096) panel2_kernel<R, 1024, 4><<<nf, 1024, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+    else panel_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB, 0);
     SPP_LAUNCH_CHECK();
+    timer_end(KC_PANEL, st, 0.0, 0.0);
+    if (maxF <= 4096) {
+      laswp_kernel<R><<<dim3(ceil_div(maxF, 64), nf), 64, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+      SPP_LAUNCH_CHECK();
+    }
     trsm_kernel<R><<<dim3(ceil_div(maxF, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0);
     SPP_LAUNCH_CHECK();
-    gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0, tiles);
-    SPP_LAUNCH_CHECK();
+    {
+      // Trailing update of this step for the level's largest front (all fronts
+      // of a level have the same size in the orderings used): 8 m n k flops.
+      const double kb = std::min(kNB, maxP - k0), mn = maxF - k0 - kb;
+      timer_begin(KC_GEMM, st);
+      gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0, tiles);
+      SPP_LAUNCH_CHECK();
+      timer_end(KC_GEMM, st, 0.0, 8.0 * nf * mn * mn * kb);
+    }
   }
-  (void)maxP;
-  perm_kernel<<<ceil_div(nf, 64), 64, 0, st>>>(mf, mf.ipiv, f0, f1);
+  perm_kernel<<<nf, 256, 2 * sizeof(int) * maxP, st>>>(mf, mf.ipiv, f0);
   SPP_LAUNCH_CHECK();
-  // Inverses of L11 and U11.
+  if (!invert) return;
+  // Inverses of L11 and U11 for levels solved by matrix-vector products.
   const int ptiles = (int)ceil_div(maxP, kBM);
   identity_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, f0);
   SPP_LAUNCH_CHECK();
@@ -560,50 +977,104 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   SPP_LAUNCH_CHECK();
 }
 
+bool mf_level_uses_inverse(int nfronts, int maxP) {
+  // Many small fronts: one workgroup per front solves with the LU in place
+  // (its vector block, maxP x 4 complex values, must fit in LDS).
+  // Few large fronts: explicit inverses so every row of every front runs in parallel.
+  return !(nfronts >= 32 && maxP <= 512);
+}
+
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
   const int ntypes = 1 << mf.d;
   const int anchors = (int)(mf.N / ((int64_t)mf.b * (mf.d == 3 ? (int64_t)mf.b * mf.b : mf.b)));
+  timer_begin(KC_QAPPLY, st);
   for (int t = 0; t < ntypes; ++t) {
     q_apply_kernel<<<dim3(anchors, nrhs), 256, sizeof(double2) * mf.types[t].nB, st>>>(mf, r, y, nrhs, t);
     SPP_LAUNCH_CHECK();
   }
+  timer_end(KC_QAPPLY, st, 32.0 * mf.N * nrhs, 0.0);
 }
 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
               void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxP,
-              int nlevels) {
+              const int* level_inv, int nlevels, void* partial_v, int64_t partial_cap) {
   using C = cplx_t<R>;
   const C* arena = static_cast<const C*>(arena_v);
   C* W = static_cast<C*>(w_v);
   C* Z = static_cast<C*>(z_v);
   const C* xin = static_cast<const C*>(x_in);
   C* xout = static_cast<C*>(x_out);
-  auto gemv = [&](int f0, int nf, int rows, int mode) {
-    dim3 grid(ceil_div(rows, 64), nf);
+  C* partial = static_cast<C*>(partial_v);
+  // Row-tiled products; large fronts split their columns over several
+  // workgroups (deterministic partial sums, then gemv_finish_kernel).
+  auto gemv = [&](int f0, int nf, int rows, int cols, int mode) {
+    const int rtiles = (int)ceil_div(rows, 64);
+    int nchunks = 1;
+    if ((int64_t)rtiles * nf < 1024) {
+      nchunks = (int)std::min<int64_t>(std::max(1, cols / 64), 2048 / ((int64_t)rtiles * nf));
+      if (nchunks < 1) nchunks = 1;
+      while (nchunks > 1 && (int64_t)nf * nchunks * rows * nrhs > partial_cap) --nchunks;
+    }
+    dim3 grid(rtiles * nchunks, nf);
+    // Factor entries read per pass over the right-hand sides.
+    const double ent = (mode == 0) ? 0.5 * rows * (rows - 1.0) : (mode == 3) ? 0.5 * rows * (rows + 1.0)
+                                                                            : (double)rows * cols;
+    const double passes = (nrhs / 4) + (nrhs % 4);
+    timer_begin(KC_GEMV, st);
     int r0 = 0;
     while (r0 < nrhs) {
       if (nrhs - r0 >= 4) {
-        gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode);
+        gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
         r0 += 4;
       } else {
-        gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode);
+        gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
         r0 += 1;
       }
       SPP_LAUNCH_CHECK();
     }
+    if (nchunks > 1) {
+      gemv_finish_kernel<R><<<dim3(ceil_div((int64_t)rows * nrhs, 256), nf), 256, 0, st>>>(
+          mf, W, Z, xout, nrhs, f0, mode, nchunks, partial, rows);
+      SPP_LAUNCH_CHECK();
+    }
+    timer_end(KC_GEMV, st, nf * ent * passes * sizeof(C), 8.0 * nf * ent * nrhs);
+  };
+  auto tri = [&](int f0, int nf, int maxP, bool fwd) {
+    const double ent = fwd ? 0.5 * maxP * (maxP - 1.0) : 0.5 * maxP * (maxP + 1.0);
+    const double passes = (nrhs / 4) + (nrhs % 4);
+    timer_begin(KC_TRI, st);
+    int r0 = 0;
+    while (r0 < nrhs) {
+      const int nr = (nrhs - r0 >= 4) ? 4 : 1;
+      const size_t lds = sizeof(C) * (size_t)maxP * nr;
+      if (fwd) {
+        if (nr == 4) fwd_tri_kernel<R, 4><<<nf, 256, lds, st>>>(mf, arena, W, Z, nrhs, r0, f0);
+        else fwd_tri_kernel<R, 1><<<nf, 256, lds, st>>>(mf, arena, W, Z, nrhs, r0, f0);
+      } else {
+        if (nr == 4) bwd_tri_kernel<R, 4><<<nf, 256, lds, st>>>(mf, arena, Z, xout, nrhs, r0, f0);
+        else bwd_tri_kernel<R, 1><<<nf, 256, lds, st>>>(mf, arena, Z, xout, nrhs, r0, f0);
+      }
+      SPP_LAUNCH_CHECK();
+      r0 += nr;
+    }
+    timer_end(KC_TRI, st, nf * ent * passes * sizeof(C), 8.0 * nf * ent * nrhs);
   };
   for (int l = 0; l < nlevels; ++l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
+    const int mF = level_maxF[l], mP = level_maxP[l];
     fwd_gather_kernel<R><<<nf, 256, 0, st>>>(mf, W, xin, nrhs, f0);
     SPP_LAUNCH_CHECK();
-    gemv(f0, nf, level_maxP[l], 0);
-    gemv(f0, nf, level_maxF[l], 1);
+    if (level_inv[l]) gemv(f0, nf, mP, mP, 0);
+    else tri(f0, nf, mP, true);
+    if (mF > mP) gemv(f0, nf, mF - mP, mP, 1);
   }
   for (int l = nlevels - 1; l >= 0; --l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
-    gemv(f0, nf, level_maxP[l], 2);
-    gemv(f0, nf, level_maxP[l], 3);
+    const int mF = level_maxF[l], mP = level_maxP[l];
+    if (mF > mP) gemv(f0, nf, mP, mF - mP, 2);
+    if (level_inv[l]) gemv(f0, nf, mP, mP, 3);
+    else tri(f0, nf, mP, false);
   }
 }
 
@@ -613,12 +1084,12 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
   SPP_LAUNCH_CHECK();
 }
 
-template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, int, int, int, int, int, int, int, int);
-template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, int, int, int, int, int, int, int, int);
+template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, int, int, int, int, int, int, int, bool);
+template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, int, int, int, int, int, int, int, bool);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
-                               const int*, const int*, const int*, int);
+                               const int*, const int*, const int*, const int*, int, void*, int64_t);
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
-                              const int*, const int*, const int*, int);
+                              const int*, const int*, const int*, const int*, int, void*, int64_t);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
 

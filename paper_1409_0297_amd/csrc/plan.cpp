@@ -76,13 +76,22 @@ SetType make_type(int d, int b, int mask) {
 
 }  // namespace
 
-std::string build_plan(int d, int n, int b, int order, Plan& P) {
-  std::ostringstream err;
+std::string validate_grid(int d, int n, int b) {
   if (d != 2 && d != 3) return "dim must be 2 or 3";
   if (n < 4 || (n & 1)) return "n must be even and >= 4";
   if (b < 2 || n % b) return "b must be >= 2 and divide n";
-  int m = n / b;
+  const int m = n / b;
   if (m < 2 || (m & (m - 1))) return "n / b must be a power of two >= 2";
+  return std::string();
+}
+
+std::string build_plan(int d, int n, int b, int order, Plan& P) {
+  std::ostringstream err;
+  {
+    std::string v = validate_grid(d, n, b);
+    if (!v.empty()) return v;
+  }
+  int m = n / b;
   P = Plan();
   P.d = d; P.n = n; P.b = b; P.m = m; P.order = order;
   P.N = ipow(n, d);

@@ -70,6 +70,10 @@ struct Plan {
   int max_front = 0;
 };
 
+// Checks d in {2,3}, n even, b | n and n / b a power of two >= 2; returns an
+// empty string if valid, else a message.
+std::string validate_grid(int d, int n, int b);
+
 // Builds the plan; returns an empty string on success, else a message.
 std::string build_plan(int d, int n, int b, int order, Plan& plan);
 

@@ -237,6 +237,8 @@ void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2
   SPP_LAUNCH_CHECK();
   transpose_kernel<<<ceil_div((int64_t)nS * nB, T), T, 0, st>>>(S.T, nS, nB, S.Tt);
   SPP_LAUNCH_CHECK();
+  transpose_kernel<<<ceil_div((int64_t)nS * nG, T), T, 0, st>>>(S.C, nS, nG, S.Ct);
+  SPP_LAUNCH_CHECK();
 }
 
 }  // namespace spp
