@@ -79,6 +79,9 @@ typedef struct {
 #define SPP_F_UNPRECONDITIONED 1  /* GMRES with M = I (for comparisons)        */
 #define SPP_F_TIMING 2            /* bracket the launches of each kernel class
                                      with HIP events (see spp_kernel_timing)   */
+#define SPP_F_PARTIAL_PIVOTING 4  /* pivot over all remaining fully-summed rows
+                                     of a front; default: pivot within each
+                                     32-row diagonal block of the front        */
 
 typedef struct {
   int32_t prec;         /* spp_prec                                              */
@@ -115,6 +118,23 @@ typedef struct spp_factor spp_factor;
 int spp_setup(const spp_problem* problem, const spp_options* options,
               spp_stream_t stream, spp_factor** out);
 
+/* ---- batched setup ---------------------------------------------------------
+ * Sets up `count` independent problems (1 <= count <= 4096) in one factor,
+ * e.g. several media, frequencies or grid sizes (Sections 3.1-3.2 solve one
+ * such family at a time).  All problems must have the same dim; n, b, kind,
+ * omega, ell, energy and coeff may differ.  Their nested-dissection fronts
+ * are factorised level by level in shared launches, and spp_solve then runs
+ * one FGMRES per (problem, right-hand side) pair in lock step, each with its
+ * own stopping test.  Batch vectors are the problems' vectors one after the
+ * other: problem i occupies [nrhs][n_i^d] starting at nrhs * sum_{j<i} n_j^d
+ * complex entries; iters / relres are indexed problem * nrhs + rhs.  The
+ * component calls below apply to the whole batch in the same layout.
+ * Errors as for spp_setup; on error no factor is returned (*out = NULL),
+ * except SPP_EBREAKDOWN as for spp_setup.  spp_setup(p, o, s, out) is
+ * spp_setup_batch(p, 1, o, s, out). */
+int spp_setup_batch(const spp_problem* problems, int32_t count, const spp_options* options,
+                    spp_stream_t stream, spp_factor** out);
+
 /* ---- solve: a7-a11 ---------------------------------------------------------
  * f: DEVICE complex128 [nrhs][n^d]; u: DEVICE complex128 [nrhs][n^d], written.
  * iters: HOST int32[nrhs]; relres: HOST double[nrhs], the true relative
@@ -141,10 +161,15 @@ int spp_apply_q(spp_factor* factor, const void* r, void* y, int32_t nrhs,
 int spp_apply_precond(spp_factor* factor, const void* r, void* z, int32_t nrhs,
                       spp_stream_t stream);
 
-/* Shift s (HOST double) and potential q (DEVICE double[n^d], may be NULL). */
+/* Shift s of the first problem (HOST double) and potential q of every problem
+   (DEVICE double[sum n_i^d] in the batch layout with nrhs = 1; may be NULL). */
 int spp_get_coefficients(const spp_factor* factor, double* s, double* q);
 
-/* Stencil of set type `type` (bit i set = axis i pinned to a leaf box face,
+/* Shift s used by problem `problem` of a batch and how many times the rule of
+   Section 2.2 perturbed it (HOST outputs, each may be NULL). */
+int spp_get_shift(const spp_factor* factor, int32_t problem, double* s, int32_t* moves);
+
+/* Stencil of set type `type` of the first problem (bit i set = axis i pinned to a leaf box face,
    so 0 is the cell and 2^d - 1 the vertex; Section 2.3).  All HOST outputs,
    each may be NULL: nS = |S|, nB = |beta(S)|; offsets: int32[(nS+nB)*dim],
    the grid offsets of S then beta(S) from the set's leaf box corner (the

@@ -18,6 +18,7 @@ SPP_C128, SPP_C64_FRONTS = 0, 1
 SPP_ORDER_OCTREE, SPP_ORDER_BISECT = 0, 1
 SPP_F_UNPRECONDITIONED = 1
 SPP_F_TIMING = 2
+SPP_F_PARTIAL_PIVOTING = 4
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
 KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
 
@@ -62,6 +63,8 @@ def library():
     P, I, D, V = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, None
     sig = {
         "spp_setup": (I, [ctypes.POINTER(spp_problem), ctypes.POINTER(spp_options), P, ctypes.POINTER(P)]),
+        "spp_setup_batch": (I, [ctypes.POINTER(spp_problem), I, ctypes.POINTER(spp_options), P, ctypes.POINTER(P)]),
+        "spp_get_shift": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "spp_solve": (I, [P, P, I, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),
         "spp_apply_operator": (I, [P, P, P, I, P]),
         "spp_apply_green": (I, [P, P, P, I, P]),
@@ -110,9 +113,28 @@ def spp_setup(problem: spp_problem, options: spp_options, stream: int) -> int:
     return h.value
 
 
-def spp_solve(handle, f_ptr, nrhs, u_ptr, stream):
-    iters = (ctypes.c_int32 * nrhs)()
-    relres = (ctypes.c_double * nrhs)()
+def spp_setup_batch(problems, options: spp_options, stream: int) -> int:
+    arr = (spp_problem * len(problems))(*problems)
+    h = ctypes.c_void_p()
+    code = library().spp_setup_batch(arr, len(problems), ctypes.byref(options), ctypes.c_void_p(stream),
+                                     ctypes.byref(h))
+    if code != SPP_OK and h.value:
+        library().spp_destroy(h)
+    _check(code, "spp_setup_batch")
+    return h.value
+
+
+def spp_get_shift(handle, problem: int):
+    s = ctypes.c_double()
+    moves = ctypes.c_int32()
+    _check(library().spp_get_shift(handle, problem, ctypes.byref(s), ctypes.byref(moves)), "spp_get_shift")
+    return s.value, moves.value
+
+
+def spp_solve(handle, f_ptr, nrhs, u_ptr, stream, nproblems: int = 1):
+    """iters / relres are returned per (problem, right-hand side), problem-major."""
+    iters = (ctypes.c_int32 * (nrhs * nproblems))()
+    relres = (ctypes.c_double * (nrhs * nproblems))()
     code = library().spp_solve(handle, f_ptr, nrhs, u_ptr, iters, relres, ctypes.c_void_p(stream))
     _check(code, "spp_solve", allow=(SPP_OK, SPP_NOT_CONVERGED))
     return code, list(iters), list(relres)
@@ -192,7 +214,7 @@ class Solver:
     def __init__(self, kind: str, n: int, d: int, b: int, coeff, omega: float = 0.0,
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
-                 timing: bool = False):
+                 timing: bool = False, partial_pivoting: bool = False):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -206,7 +228,8 @@ class Solver:
                          order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
                          tol=tol, max_iter=max_iter,
                          flags=(SPP_F_UNPRECONDITIONED if unpreconditioned else 0)
-                         | (SPP_F_TIMING if timing else 0))
+                         | (SPP_F_TIMING if timing else 0)
+                         | (SPP_F_PARTIAL_PIVOTING if partial_pivoting else 0))
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:
@@ -263,6 +286,85 @@ class Solver:
         C = np.zeros((nS, nS + nB), dtype=np.complex128)
         spp_get_stencil(self.handle, set_type, off.ctypes.data, T.ctypes.data, C.ctypes.data)
         return off, T, C
+
+    def stats(self) -> dict:
+        return spp_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            spp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Several independent problems factorised and solved together.
+
+    ``problems``: list of dicts with keys kind ("helmholtz" / "schrodinger"),
+    n, d, b, coeff and omega or ell / energy.  Every problem must have the
+    same d.  ``solve(fs)`` takes one (nrhs, n_i^d) right-hand-side array per
+    problem (the same nrhs for all) and returns per-problem solutions,
+    iteration counts and true relative residuals.
+    """
+
+    def __init__(self, problems, prec: str = "c128", order: str = "octree", tol: float = 1e-10,
+                 max_iter: int = 200, timing: bool = False):
+        import torch
+        self.torch = torch
+        self.sizes = [p["n"] ** p["d"] for p in problems]
+        self.offsets = [0]
+        for N in self.sizes:
+            self.offsets.append(self.offsets[-1] + N)
+        self._coeffs = []
+        pbs = []
+        for p in problems:
+            c = torch.as_tensor(p["coeff"], dtype=torch.float64, device="cuda").contiguous().reshape(-1)
+            self._coeffs.append(c)
+            pbs.append(spp_problem(dim=p["d"], n=p["n"], b=p["b"],
+                                   kind=SPP_HELMHOLTZ if p["kind"] == "helmholtz" else SPP_SCHRODINGER,
+                                   omega=p.get("omega", 0.0), ell=p.get("ell", 1.0), energy=p.get("energy", 0.0),
+                                   coeff=c.data_ptr()))
+        op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,
+                         order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
+                         tol=tol, max_iter=max_iter, flags=SPP_F_TIMING if timing else 0)
+        self.handle = spp_setup_batch(pbs, op, torch.cuda.current_stream().cuda_stream)
+
+    def _stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def pack(self, xs):
+        """Per-problem (nrhs, N_i) arrays -> one batch vector [problem][nrhs][N_i]."""
+        parts = [self.torch.as_tensor(x, dtype=self.torch.complex128, device="cuda").reshape(-1, N)
+                 for x, N in zip(xs, self.sizes)]
+        nrhs = parts[0].shape[0]
+        return self.torch.cat([p.reshape(-1) for p in parts]).contiguous(), nrhs
+
+    def unpack(self, v, nrhs):
+        return [v[nrhs * o0:nrhs * o1].reshape(nrhs, o1 - o0)
+                for o0, o1 in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def solve(self, fs):
+        fv, nrhs = self.pack(fs)
+        u = self.torch.empty_like(fv)
+        code, iters, relres = spp_solve(self.handle, fv.data_ptr(), nrhs, u.data_ptr(), self._stream(),
+                                        nproblems=len(self.sizes))
+        per = lambda a: [a[i * nrhs:(i + 1) * nrhs] for i in range(len(self.sizes))]
+        return self.unpack(u, nrhs), per(iters), per(relres), code
+
+    def apply(self, name, xs):
+        xv, nrhs = self.pack(xs)
+        y = self.torch.empty_like(xv)
+        {"operator": spp_apply_operator, "green": spp_apply_green, "q": spp_apply_q,
+         "precond": spp_apply_precond}[name](self.handle, xv.data_ptr(), y.data_ptr(), nrhs, self._stream())
+        return self.unpack(y, nrhs)
+
+    def shift(self, i: int):
+        return spp_get_shift(self.handle, i)
 
     def stats(self) -> dict:
         return spp_stats(self.handle)

@@ -1,5 +1,10 @@
 // C ABI of the library (include/spp.h): handle management, setup and solve
 // drivers.  Host code only; every arithmetic step runs in the HIP kernels.
+//
+// A factor always describes a batch of problems (one problem is a batch of
+// one): their fronts are concatenated level by level so that each kernel
+// launch of the factorisation and of the substitution covers every problem,
+// and grid vectors are stored problem after problem, [nrhs][N_i] each.
 #include "spp.h"
 
 #include <hip/hip_runtime.h>
@@ -11,8 +16,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
-#include <tuple>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -69,18 +74,29 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// A nested-dissection plan and its device-side index arrays.  Plans depend
-// only on (device, d, n, b, ordering), so they are built once per process and
-// shared by every factor with that geometry (read-only on the device).
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+using Geom = std::tuple<int, int, int, int>;   // d, n, b, ordering
+
+// A nested-dissection plan (of one problem or of a batch) and its device-side
+// index arrays.  Plans depend only on the geometries, so they are built once
+// per process and device and shared by every factor with those geometries
+// (read-only on the device).
 struct PlanDevice {
   Plan plan;
+  std::vector<int> front_inst;
   int device = 0;
   FrontDev* fronts = nullptr;
   AsmBlockDev* blocks = nullptr;
   int *pos = nullptr, *idx = nullptr, *map = nullptr;
-  int* off[8] = {nullptr};
+  std::vector<int*> type_off;      // per problem, per set type: device offsets
   std::vector<int> level_inv;
+  std::vector<double> level_ent;   // 3 per level, see mf_solve
+  std::vector<std::vector<int>> level_F, level_p;
   int perm_total = 0;
+  int dblk_total = 0;              // 32-column diagonal blocks over all fronts
   int64_t xwork_elems = 0;
   std::vector<void*> mem;
   ~PlanDevice() {
@@ -95,36 +111,77 @@ struct PlanDevice {
 std::mutex g_plan_mu;
 // Never destroyed: device memory of cached plans is released with the process,
 // not by a static destructor running after the HIP runtime has shut down.
-auto& g_plans = *new std::map<std::tuple<int, int, int, int, int>, std::shared_ptr<PlanDevice>>();
+auto& g_plans = *new std::map<std::pair<int, std::vector<Geom>>, std::shared_ptr<PlanDevice>>();
+auto& g_host_plans = *new std::map<Geom, std::shared_ptr<Plan>>();
 
-std::shared_ptr<PlanDevice> get_plan(int d, int n, int b, int order) {
+// Host plan of one geometry (caller holds g_plan_mu).
+std::shared_ptr<Plan> host_plan_locked(const Geom& g) {
+  auto it = g_host_plans.find(g);
+  if (it != g_host_plans.end()) return it->second;
+  auto P = std::make_shared<Plan>();
+  std::string err = build_plan(std::get<0>(g), std::get<1>(g), std::get<2>(g), std::get<3>(g), *P);
+  if (!err.empty()) throw Error(SPP_EINVAL, err);
+  g_host_plans[g] = P;
+  return P;
+}
+
+std::shared_ptr<Plan> host_plan(const Geom& g) {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  return host_plan_locked(g);
+}
+
+std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
   int dev = 0;
   SPP_HIP(hipGetDevice(&dev));
-  const auto key = std::make_tuple(dev, d, n, b, order);
+  const auto key = std::make_pair(dev, geoms);
   std::lock_guard<std::mutex> lock(g_plan_mu);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) return it->second;
   auto pd = std::make_shared<PlanDevice>();
   pd->device = dev;
-  std::string err = build_plan(d, n, b, order, pd->plan);
-  if (!err.empty()) throw Error(SPP_EINVAL, err);
+  std::vector<std::shared_ptr<Plan>> parts;
+  std::vector<const Plan*> raw;
+  for (const Geom& g : geoms) {
+    parts.push_back(host_plan_locked(g));
+    raw.push_back(parts.back().get());
+  }
+  if (raw.size() == 1) {
+    pd->plan = *raw[0];
+    pd->front_inst.assign(pd->plan.fronts.size(), 0);
+  } else {
+    std::string err = combine_plans(raw, pd->plan, pd->front_inst);
+    if (!err.empty()) throw Error(SPP_EINVAL, err);
+  }
   const Plan& P = pd->plan;
   std::vector<FrontDev> fd(P.fronts.size());
   for (const Level& L : P.levels) {
     int64_t xo = 0;
     const bool inv = mf_level_uses_inverse(L.end - L.begin, L.maxP);
     pd->level_inv.push_back(inv ? 1 : 0);
+    double e0 = 0, e1 = 0, e2 = 0;
+    std::vector<int> hF, hP;
     for (int fi = L.begin; fi < L.end; ++fi) {
       const Front& f = P.fronts[fi];
       FrontDev& g_ = fd[fi];
       g_.off = f.off; g_.voff = f.voff; g_.xoff = xo;
       g_.F = f.F; g_.p = f.p; g_.idx = f.idx; g_.map = f.map; g_.perm = pd->perm_total;
+      g_.dblk = pd->dblk_total;
+      g_.inst = pd->front_inst[fi];
+      pd->dblk_total += (f.p + 31) / 32;
       g_.nchild = static_cast<int>(f.children.size());
       if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
       for (int c = 0; c < g_.nchild; ++c) g_.child[c] = f.children[c];
       pd->perm_total += f.p;
       if (inv) xo += 2LL * f.p * f.p;
+      e0 += 0.5 * f.p * (f.p - 1.0);
+      e1 += 0.5 * f.p * (f.p + 1.0);
+      e2 += (double)(f.F - f.p) * f.p;
+      hF.push_back(f.F);
+      hP.push_back(f.p);
     }
+    pd->level_ent.insert(pd->level_ent.end(), {e0, e1, e2});
+    pd->level_F.push_back(hF);
+    pd->level_p.push_back(hP);
     pd->xwork_elems = std::max(pd->xwork_elems, xo);
   }
   std::vector<AsmBlockDev> bd(P.blocks.size());
@@ -142,44 +199,58 @@ std::shared_ptr<PlanDevice> get_plan(int d, int n, int b, int order) {
   pd->pos = static_cast<int*>(upload(P.pos.data(), P.pos.size() * sizeof(int)));
   pd->idx = static_cast<int*>(upload(P.idx.data(), P.idx.size() * sizeof(int)));
   pd->map = static_cast<int*>(upload(P.map.data(), P.map.size() * sizeof(int)));
-  for (size_t t = 0; t < P.types.size(); ++t)
-    pd->off[t] = static_cast<int*>(upload(P.types[t].off.data(), P.types[t].off.size() * sizeof(int)));
+  for (const Plan* part : raw)
+    for (const SetType& T : part->types)
+      pd->type_off.push_back(static_cast<int*>(upload(T.off.data(), T.off.size() * sizeof(int))));
   g_plans[key] = pd;
   return pd;
 }
 
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
 }  // namespace
+
+// One problem of the batch.
+struct SppInstance {
+  int kind = 0;
+  double omega = 0, ell = 1, energy = 0, s = 0;
+  int moves = 0;
+  int d = 0, n = 0, b = 0, m = 0;
+  int64_t N = 0, Noff = 0;
+  std::shared_ptr<Plan> plan;        // the problem's own plan (set types)
+  StencilDev sten[8]{};
+  const double2* tw = nullptr;
+};
+
+// A run of consecutive problems with the same grid: one contiguous
+// [ninst * nrhs][N] block of a batch vector.
+struct SppGroup {
+  int inst0 = 0, ninst = 0;
+  int d = 0, n = 0;
+  int64_t N = 0, Noff = 0;
+  const double2* tw = nullptr;
+};
 
 struct spp_factor {
   std::shared_ptr<PlanDevice> pd;   // shared, read-only plan (see get_plan)
   const Plan* planp = nullptr;
-  int kind = 0;
-  double omega = 0, ell = 1, energy = 0;
+  std::vector<SppInstance> inst;
+  std::vector<SppGroup> groups;
+  int64_t Ntot = 0;
   spp_options opt{};
-  double s = 0;
-  int shift_moves = 0;
   std::vector<void*> allocs;
-  // grid data
-  double* q = nullptr;
-  double* sigma = nullptr;
-  double2* tw = nullptr;
-  // stencils
-  StencilDev sten[8]{};
-  // plan on the device
+  double* q = nullptr;               // every problem's q, concatenated
+  double* sigma = nullptr;           // every problem's Green symbol / N, concatenated
+  std::map<int, double2*> tw_by_n;
+  InstDev* inst_dev = nullptr;
   MfDev mf{};
   void* arena = nullptr;
   size_t csize = 16;  // bytes per complex front entry
-  std::vector<int> level_begin, level_maxF, level_maxP, level_inv;
+  std::vector<int> level_begin, level_maxK, level_maxP, level_inv;
   void* gpart = nullptr;       // split-K partial sums of the substitution
   int64_t gpart_cap = 0;
   // solve work (grown on demand)
   int cap_rhs = 0, cap_iter = 0;
-  double2* tmp = nullptr;      // FFT scratch, nrhs * N
-  double2* qr = nullptr;       // Q r, nrhs * N
+  double2* tmp = nullptr;      // FFT scratch, nrhs * Ntot
+  double2* qr = nullptr;       // Q r, nrhs * Ntot
   void* wv = nullptr;          // front vectors
   void* zv = nullptr;
   void* xc = nullptr;          // reduced-precision solve vector (complex64 fronts)
@@ -260,6 +331,8 @@ double shift_gap(int d, int n, double s) {
   return best / std::fabs(s);
 }
 
+int total_cols(const spp_factor* F, int nrhs) { return static_cast<int>(F->inst.size()) * nrhs; }
+
 void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   if (nrhs <= F->cap_rhs && iters <= F->cap_iter) return;
   const int r = std::max(nrhs, F->cap_rhs), it = std::max(iters, F->cap_iter);
@@ -268,7 +341,8 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
                   (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec})
     F->dfree(p);
   if (F->h_resid) { (void)hipHostFree(F->h_resid); F->h_resid = nullptr; }
-  const int64_t N = F->planp->N;
+  const int64_t N = F->Ntot;
+  const int cols = total_cols(F, r);
   F->tmp = F->dalloc<double2>((size_t)r * N);
   F->qr = F->dalloc<double2>((size_t)r * N);
   F->wv = F->dalloc<char>((size_t)F->planp->vec_elems * r * F->csize);
@@ -279,198 +353,257 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->V = F->dalloc<double2>((size_t)(it + 1) * r * N);
   F->Z = F->dalloc<double2>((size_t)it * r * N);
   const size_t ld = it + 1;
-  F->H = F->dalloc<double2>(ld * it * r);
-  F->gv = F->dalloc<double2>(ld * r);
-  F->sn = F->dalloc<double2>(ld * r);
-  F->y = F->dalloc<double2>(ld * r);
-  F->cs = F->dalloc<double>(ld * r);
+  F->H = F->dalloc<double2>(ld * it * cols);
+  F->gv = F->dalloc<double2>(ld * cols);
+  F->sn = F->dalloc<double2>(ld * cols);
+  F->y = F->dalloc<double2>(ld * cols);
+  F->cs = F->dalloc<double>(ld * cols);
   F->g0 = F->dalloc<double2>((size_t)r * N);
   F->wk = F->dalloc<double2>((size_t)r * N);
-  F->h2 = F->dalloc<double2>(ld * r);
-  const int64_t nblk = (N + 1023) / 1024;
-  F->dpart = F->dalloc<double2>((size_t)nblk * r * (it + 1));
-  F->rpart = F->dalloc<double>((size_t)(256 + 1) * r + 64);
-  F->resid = F->dalloc<double>(r);
-  F->norms = F->dalloc<double>(r);
-  F->kvec = F->dalloc<int>(r);
-  SPP_HIP(hipHostMalloc(reinterpret_cast<void**>(&F->h_resid), sizeof(double) * r));
+  F->h2 = F->dalloc<double2>(ld * cols);
+  int64_t nblk = 1;
+  for (const SppGroup& g : F->groups) nblk = std::max<int64_t>(nblk, (g.N + 1023) / 1024);
+  F->dpart = F->dalloc<double2>((size_t)nblk * cols * (it + 1));
+  F->rpart = F->dalloc<double>((size_t)(256 + 1) * cols + 64);
+  F->resid = F->dalloc<double>(cols);
+  F->norms = F->dalloc<double>(cols);
+  F->kvec = F->dalloc<int>(cols);
+  SPP_HIP(hipHostMalloc(reinterpret_cast<void**>(&F->h_resid), sizeof(double) * cols));
   F->cap_rhs = r;
   F->cap_iter = it;
 }
 
+// w = (I + G q) z; one FFT call per group of equal grids, q and sigma per problem.
 void apply_operator(spp_factor* F, const double2* z, double2* w, int nrhs, hipStream_t st) {
-  fft_multi(st, z, w, F->tmp, F->tw, F->planp->d, F->planp->n, nrhs, F->q, F->sigma, z);
+  for (const SppGroup& g : F->groups) {
+    const int64_t o = g.Noff * nrhs;
+    fft_multi(st, z + o, w + o, F->tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, F->q + g.Noff, F->sigma + g.Noff, z + o,
+              nrhs);
+  }
 }
 
-void apply_green(spp_factor* F, const double2* f, double2* g, int nrhs, hipStream_t st) {
-  fft_multi(st, f, g, F->tmp, F->tw, F->planp->d, F->planp->n, nrhs, nullptr, F->sigma, nullptr);
+void apply_green(spp_factor* F, const double2* f, double2* gout, int nrhs, hipStream_t st) {
+  for (const SppGroup& g : F->groups) {
+    const int64_t o = g.Noff * nrhs;
+    fft_multi(st, f + o, gout + o, F->tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, nullptr, F->sigma + g.Noff, nullptr,
+              nrhs);
+  }
 }
 
 void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st) {
   q_apply(st, F->mf, r, F->qr, nrhs);
   const int nl = static_cast<int>(F->planp->levels.size());
+  const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
-    mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(),
-                     F->level_maxF.data(), F->level_maxP.data(), F->level_inv.data(), nl, F->gpart, F->gpart_cap);
+    mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxK.data(),
+                     F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap);
   } else {
-    const int64_t cnt = (int64_t)nrhs * F->planp->N;
+    const int64_t cnt = (int64_t)nrhs * F->Ntot;
     cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
-    mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(),
-                    F->level_maxF.data(), F->level_maxP.data(), F->level_inv.data(), nl, F->gpart, F->gpart_cap);
+    mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxK.data(),
+                    F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap);
     cast_vectors<float>(st, F->xc, z, cnt, 1);
   }
 }
 
-int do_setup(const spp_problem* pb, const spp_options* op, hipStream_t st, spp_factor** out) {
-  if (!pb || !op || !out) throw Error(SPP_EINVAL, "null argument");
-  *out = nullptr;
+void validate_problem(const spp_problem* pb) {
   if (!pb->coeff) throw Error(SPP_EINVAL, "coeff is null");
   if (pb->kind != SPP_HELMHOLTZ && pb->kind != SPP_SCHRODINGER) throw Error(SPP_EINVAL, "unknown problem kind");
-  if (op->prec != SPP_C128 && op->prec != SPP_C64_FRONTS) throw Error(SPP_EINVAL, "unknown precision");
-  if (op->order != SPP_ORDER_OCTREE && op->order != SPP_ORDER_BISECT) throw Error(SPP_EINVAL, "unknown ordering");
-  if (!(op->tol > 0) || op->max_iter < 1 || op->max_iter > 500) throw Error(SPP_EINVAL, "tol > 0 and 1 <= max_iter <= 500");
   if (pb->kind == SPP_HELMHOLTZ && !(std::isfinite(pb->omega) && pb->omega > 0)) throw Error(SPP_EINVAL, "omega");
   if (pb->kind == SPP_SCHRODINGER && !(std::isfinite(pb->ell) && pb->ell > 0 && std::isfinite(pb->energy)))
     throw Error(SPP_EINVAL, "ell / energy");
   if (!fft_supported(pb->n)) throw Error(SPP_EINVAL, "n must be of the form 2^a 3^b");
+  std::string err = validate_grid(pb->dim, pb->n, pb->b);
+  if (!err.empty()) throw Error(SPP_EINVAL, err);
+  // Leaf sets are assembled and applied by one workgroup with their
+  // neighbourhood staged in LDS: |gamma(S)| <= 1024 (2D: b <= 30, 3D: b <= 9).
+  const int g = (pb->dim == 2) ? (pb->b + 1) * (pb->b + 1) : (pb->b + 1) * (pb->b + 1) * (pb->b + 1);
+  if (g > 1024) throw Error(SPP_ENOTIMPL, "leaf box too large: (b + 1)^d must be <= 1024");
+}
+
+int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream_t st, spp_factor** out) {
+  if (!pbs || !op || !out) throw Error(SPP_EINVAL, "null argument");
+  *out = nullptr;
+  if (count < 1 || count > 4096) throw Error(SPP_EINVAL, "batch size must be in [1, 4096]");
+  if (op->prec != SPP_C128 && op->prec != SPP_C64_FRONTS) throw Error(SPP_EINVAL, "unknown precision");
+  if (op->order != SPP_ORDER_OCTREE && op->order != SPP_ORDER_BISECT) throw Error(SPP_EINVAL, "unknown ordering");
+  if (!(op->tol > 0) || op->max_iter < 1 || op->max_iter > 500) throw Error(SPP_EINVAL, "tol > 0 and 1 <= max_iter <= 500");
+  for (int i = 0; i < count; ++i) {
+    validate_problem(&pbs[i]);
+    if (pbs[i].dim != pbs[0].dim) throw Error(SPP_EINVAL, "all problems of a batch must have the same dimension");
+  }
   const double t0 = now_ms();
   auto F = std::make_unique<spp_factor>();
-  F->kind = pb->kind;
-  F->omega = pb->omega;
-  F->ell = pb->ell;
-  F->energy = pb->energy;
   F->opt = *op;
   F->csize = (op->prec == SPP_C128) ? sizeof(double2) : sizeof(float2);
   F->last_stream = st;
   if (op->flags & SPP_F_TIMING) F->timer = std::make_unique<KernelTimer>();
   TimerScope timer_scope(F.get());
-  {
-    std::string err = validate_grid(pb->dim, pb->n, pb->b);
-    if (!err.empty()) throw Error(SPP_EINVAL, err);
-  }
-  {
-    // Leaf sets are assembled and applied by one workgroup with their
-    // neighbourhood staged in LDS: |gamma(S)| <= 1024 (2D: b <= 30, 3D: b <= 9).
-    const int g = (pb->dim == 2) ? (pb->b + 1) * (pb->b + 1) : (pb->b + 1) * (pb->b + 1) * (pb->b + 1);
-    if (g > 1024) throw Error(SPP_ENOTIMPL, "leaf box too large: (b + 1)^d must be <= 1024");
-  }
-  F->pd = get_plan(pb->dim, pb->n, pb->b, op->order);
+  std::vector<Geom> geoms;
+  for (int i = 0; i < count; ++i) geoms.emplace_back(pbs[i].dim, pbs[i].n, pbs[i].b, op->order);
+  F->pd = get_plan(geoms);
   F->planp = &F->pd->plan;
   const Plan& P = *F->planp;
-  const int d = P.d, n = P.n;
-  const int64_t N = P.N;
 
-  // a1: shift and potential (eq. Dsq).
-  F->q = F->dalloc<double>(N);
-  F->sigma = F->dalloc<double>(N);
-  F->tw = F->dalloc<double2>(n);
-  fft_make_twiddles(F->tw, n, st);
-  const int nblk = coeff_reduce_blocks(N);
-  double* red = F->dalloc<double>(2 * nblk + 2);
-  coeff_reduce(st, pb->kind, pb->coeff, N, pb->omega, pb->ell, red, nblk, red + 2 * nblk);
-  double hred[2];
-  SPP_HIP(hipMemcpyAsync(hred, red + 2 * nblk, sizeof(hred), hipMemcpyDeviceToHost, st));
-  SPP_HIP(hipStreamSynchronize(st));
-  F->dfree(red);
-  if (hred[1] != 0) throw Error(SPP_EINVAL, "coeff has non-finite (or, for Helmholtz, non-positive) entries");
-  const double mean_w = hred[0] / (double)N;
-  double s = (pb->kind == SPP_HELMHOLTZ) ? mean_w : pb->ell * pb->ell * pb->energy - mean_w;
-  int moves = 0;
-  while (shift_gap(d, n, s) < 1e-6) {
-    if (moves == 10) throw Error(SPP_ESINGULAR_SHIFT, "L - s stays singular after 10 perturbations");
-    s += 4.0 * M_PI * M_PI * 1e-3;
-    ++moves;
+  // Problems, and groups of consecutive problems with equal grids.
+  int64_t Noff = 0;
+  for (int i = 0; i < count; ++i) {
+    SppInstance I;
+    I.kind = pbs[i].kind; I.omega = pbs[i].omega; I.ell = pbs[i].ell; I.energy = pbs[i].energy;
+    I.d = pbs[i].dim; I.n = pbs[i].n; I.b = pbs[i].b; I.m = I.n / I.b;
+    I.N = (I.d == 2) ? (int64_t)I.n * I.n : (int64_t)I.n * I.n * I.n;
+    I.Noff = Noff;
+    I.plan = host_plan(geoms[i]);
+    Noff += I.N;
+    F->inst.push_back(std::move(I));
   }
-  F->s = s;
-  F->shift_moves = moves;
-  double2* sig_c = F->dalloc<double2>(N);
-  double2* sig2_c = F->dalloc<double2>(N);
-  coeff_finish(st, pb->kind, pb->coeff, N, d, n, pb->omega, pb->ell, pb->energy, s, F->q, F->sigma, sig_c, sig2_c);
+  F->Ntot = Noff;
+  for (int i = 0; i < count; ++i) {
+    const SppInstance& I = F->inst[i];
+    if (F->groups.empty() || F->groups.back().n != I.n) {
+      SppGroup g;
+      g.inst0 = i; g.d = I.d; g.n = I.n; g.N = I.N; g.Noff = I.Noff;
+      F->groups.push_back(g);
+    }
+    F->groups.back().ninst += 1;
+  }
+  F->q = F->dalloc<double>(F->Ntot);
+  F->sigma = F->dalloc<double>(F->Ntot);
+  for (SppInstance& I : F->inst) {
+    auto it = F->tw_by_n.find(I.n);
+    if (it == F->tw_by_n.end()) {
+      double2* tw = F->dalloc<double2>(I.n);
+      fft_make_twiddles(tw, I.n, st);
+      it = F->tw_by_n.emplace(I.n, tw).first;
+    }
+    I.tw = it->second;
+  }
+  for (SppGroup& g : F->groups) g.tw = F->inst[g.inst0].tw;
 
-  // a2: kernels of G and G G^H.
-  double2* g = F->dalloc<double2>(N);
-  double2* g2 = F->dalloc<double2>(N);
-  fft_inverse_all(st, sig_c, g, F->tw, d, n);
-  fft_inverse_all(st, sig2_c, g2, F->tw, d, n);
-  F->dfree(sig_c);
-  F->dfree(sig2_c);
-
-  // a3-a4: stencils per set type.
   int* info = F->dalloc<int>(64);
   SPP_HIP(hipMemsetAsync(info, 0, 64 * sizeof(int), st));
   size_t work_elems = 0;
-  for (const SetType& T : P.types)
-    work_elems = std::max(work_elems, (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS));
-  double2* swork = F->dalloc<double2>(work_elems);
-  for (size_t t = 0; t < P.types.size(); ++t) {
-    const SetType& T = P.types[t];
-    StencilDev& S = F->sten[t];
-    S.nS = T.nS; S.nB = T.nB; S.nG = T.nG;
-    S.off = F->pd->off[t];
-    S.T = F->dalloc<double2>((size_t)T.nS * T.nB);
-    S.C = F->dalloc<double2>((size_t)T.nS * T.nG);
-    S.Tt = F->dalloc<double2>((size_t)T.nS * T.nB);
-    S.Ct = F->dalloc<double2>((size_t)T.nS * T.nG);
-    stencil_build(st, d, n, g, g2, S, swork, info + 1 + (int)t);
+  int64_t Nmax = 0;
+  for (const SppInstance& I : F->inst) {
+    Nmax = std::max(Nmax, I.N);
+    for (const SetType& T : I.plan->types)
+      work_elems = std::max(work_elems, (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS));
   }
-  F->dfree(g);
-  F->dfree(g2);
+  double2* swork = F->dalloc<double2>(work_elems);
+  const int nblk_max = coeff_reduce_blocks(Nmax);
+  double* red = F->dalloc<double>(2 * nblk_max + 2);
+  double* red_out = red + 2 * nblk_max;
+  double2* sig_c = F->dalloc<double2>(Nmax);
+  double2* sig2_c = F->dalloc<double2>(Nmax);
+  double2* g = F->dalloc<double2>(Nmax);
+  double2* g2 = F->dalloc<double2>(Nmax);
+  std::vector<InstDev> idev(count);
+  for (int i = 0; i < count; ++i) {
+    SppInstance& I = F->inst[i];
+    const spp_problem& pb = pbs[i];
+    // a1: shift and potential (eq. Dsq).
+    // (per-problem block count: the same summation order as a batch of one)
+    coeff_reduce(st, pb.kind, pb.coeff, I.N, pb.omega, pb.ell, red, coeff_reduce_blocks(I.N), red_out);
+    double hred[2];
+    SPP_HIP(hipMemcpyAsync(hred, red_out, sizeof(hred), hipMemcpyDeviceToHost, st));
+    SPP_HIP(hipStreamSynchronize(st));
+    if (hred[1] != 0) throw Error(SPP_EINVAL, "coeff has non-finite (or, for Helmholtz, non-positive) entries");
+    const double mean_w = hred[0] / (double)I.N;
+    double s = (pb.kind == SPP_HELMHOLTZ) ? mean_w : pb.ell * pb.ell * pb.energy - mean_w;
+    int moves = 0;
+    while (shift_gap(I.d, I.n, s) < 1e-6) {
+      if (moves == 10) throw Error(SPP_ESINGULAR_SHIFT, "L - s stays singular after 10 perturbations");
+      s += 4.0 * M_PI * M_PI * 1e-3;
+      ++moves;
+    }
+    I.s = s;
+    I.moves = moves;
+    coeff_finish(st, pb.kind, pb.coeff, I.N, I.d, I.n, pb.omega, pb.ell, pb.energy, s, F->q + I.Noff,
+                 F->sigma + I.Noff, sig_c, sig2_c);
+    // a2: kernels of G and G G^H.
+    fft_inverse_all(st, sig_c, g, I.tw, I.d, I.n);
+    fft_inverse_all(st, sig2_c, g2, I.tw, I.d, I.n);
+    // a3-a4: stencils per set type.
+    InstDev& D = idev[i];
+    D.d = I.d; D.n = I.n; D.b = I.b; D.m = I.m; D.N = I.N; D.Noff = I.Noff; D.q = F->q + I.Noff;
+    const size_t ntypes = I.plan->types.size();
+    for (size_t t = 0; t < ntypes; ++t) {
+      const SetType& T = I.plan->types[t];
+      StencilDev& S = I.sten[t];
+      S.nS = T.nS; S.nB = T.nB; S.nG = T.nG;
+      S.off = F->pd->type_off[i * ntypes + t];
+      S.T = F->dalloc<double2>((size_t)T.nS * T.nB);
+      S.C = F->dalloc<double2>((size_t)T.nS * T.nG);
+      S.Tt = F->dalloc<double2>((size_t)T.nS * T.nB);
+      S.Ct = F->dalloc<double2>((size_t)T.nS * T.nG);
+      stencil_build(st, I.d, I.n, g, g2, S, swork, info + 1 + (int)t);
+      D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
+    }
+  }
+  F->inst_dev = F->dalloc<InstDev>(count);
+  SPP_HIP(hipMemcpyAsync(F->inst_dev, idev.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, st));
 
   // a5-a6: assembly and factorisation on the shared plan.
-  const int perm_total = F->pd->perm_total;
-  const int64_t xwork_elems = F->pd->xwork_elems;
   MfDev& mf = F->mf;
-  mf.d = d; mf.n = n; mf.b = P.b; mf.m = P.m; mf.N = N;
   mf.fronts = F->pd->fronts;
   mf.blocks = F->pd->blocks;
   mf.pos = F->pd->pos;
   mf.idx = F->pd->idx;
   mf.map = F->pd->map;
-  mf.perm = F->dalloc<int>(perm_total);
-  mf.ipiv = F->dalloc<int>(perm_total);
-  mf.q = F->q;
+  mf.perm = F->dalloc<int>(F->pd->perm_total);
+  mf.ipiv = F->dalloc<int>(F->pd->perm_total);
   mf.info = info;
-  for (size_t t = 0; t < P.types.size(); ++t) {
-    const StencilDev& S = F->sten[t];
-    mf.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
+  mf.inst = F->inst_dev;
+  mf.ninst = count;
+  mf.d = pbs[0].dim;
+  mf.anchors_max = 0;
+  mf.Ntot = F->Ntot;
+  for (int t = 0; t < 8; ++t) mf.nB_max[t] = 0;
+  for (const SppInstance& I : F->inst) {
+    int64_t a = 1;
+    for (int x = 0; x < I.d; ++x) a *= I.m;
+    mf.anchors_max = std::max(mf.anchors_max, a);
+    for (size_t t = 0; t < I.plan->types.size(); ++t) mf.nB_max[t] = std::max(mf.nB_max[t], I.plan->types[t].nB);
   }
-  F->level_begin.clear();
   for (const Level& L : P.levels) {
     F->level_begin.push_back(L.begin);
-    F->level_maxF.push_back(L.maxF);
+    F->level_maxK.push_back(L.maxK);
     F->level_maxP.push_back(L.maxP);
   }
-  F->level_inv = F->pd->level_inv;
   F->level_begin.push_back(static_cast<int>(P.fronts.size()));
+  F->level_inv = F->pd->level_inv;
 
   F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
-  void* xwork = F->dalloc<char>((size_t)xwork_elems * F->csize);
+  void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);
+  const bool partial_pivoting = (F->opt.flags & SPP_F_PARTIAL_PIVOTING) != 0;
+  void* dinv = F->dalloc<char>((size_t)2 * 32 * 32 * F->pd->dblk_total * F->csize);
   SPP_HIP(hipStreamSynchronize(st));
+  for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p);
   const double tf0 = now_ms();
+  SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
   for (size_t l = 0; l < P.levels.size(); ++l) {
     const Level& L = P.levels[l];
-    const Front& first = P.fronts[L.begin];
-    const Front& last = P.fronts[L.end - 1];
-    const int64_t span = last.off + (int64_t)last.F * last.F - first.off;
-    SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + first.off * F->csize, 0, span * F->csize, st));
+    const int* hF = F->pd->level_F[l].data();
+    const int* hP = F->pd->level_p[l].data();
     if (F->opt.prec == SPP_C128)
-      mf_factor_level<double>(st, mf, F->arena, xwork, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                              L.max_children, F->level_inv[l] != 0);
+      mf_factor_level<double>(st, mf, F->arena, xwork, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
+                              L.max_children, F->level_inv[l] != 0, partial_pivoting, hF, hP);
     else
-      mf_factor_level<float>(st, mf, F->arena, xwork, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                             L.max_children, F->level_inv[l] != 0);
+      mf_factor_level<float>(st, mf, F->arena, xwork, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
+                             L.max_children, F->level_inv[l] != 0, partial_pivoting, hF, hP);
   }
   int hinfo[16];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
   const double tf1 = now_ms();
   F->dfree(xwork);
+  F->dfree(dinv);
   F->dfree(swork);
-  for (size_t t = 0; t < P.types.size(); ++t)
+  for (int t = 0; t < 8; ++t)
     if (hinfo[1 + t]) throw Error(SPP_EBREAKDOWN, "singular Gram matrix in the stencil least-squares problem");
   F->stats.breakdown_front = hinfo[0] ? hinfo[0] - 1 : -1;
-  F->stats.s = s;
-  F->stats.shift_moves = moves;
+  F->stats.s = F->inst[0].s;
+  F->stats.shift_moves = F->inst[0].moves;
   F->stats.n_fronts = static_cast<int>(P.fronts.size());
   F->stats.n_levels = static_cast<int>(P.levels.size());
   F->stats.max_front = P.max_front;
@@ -496,29 +629,32 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   TimerScope timer_scope(F);
   const int maxit = F->opt.max_iter;
   ensure_solve_buffers(F, nrhs, maxit);
-  const int64_t N = F->planp->N;
-  const int64_t vstride = (int64_t)nrhs * N;
-  const int ld = F->cap_iter + 1;           // Hessenberg column stride and per-RHS vector stride
-  const int hrhs = ld * F->cap_iter;        // Hessenberg stride between right-hand sides
+  const int64_t vstride = (int64_t)nrhs * F->Ntot;   // one Krylov vector of the whole batch
+  const int ld = F->cap_iter + 1;                     // Hessenberg column stride, per-column vector stride
+  const int hrhs = ld * F->cap_iter;                  // Hessenberg stride between columns
+  const int cols = total_cols(F, nrhs);               // (problem, right-hand side) pairs
   const double2* f = static_cast<const double2*>(fv);
   double2* u = static_cast<double2*>(uv);
   const bool precond = !(F->opt.flags & SPP_F_UNPRECONDITIONED);
 
-  // a7: g = G f; beta = ||g||.
+  // a7: g = G f; beta = ||g|| per column.
   apply_green(F, f, F->g0, nrhs, st);
-  kr_norms(st, F->g0, nrhs, N, F->rpart, F->norms);
-  std::vector<double> beta(nrhs);
-  SPP_HIP(hipMemcpyAsync(beta.data(), F->norms, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-  kr_scale_init(st, F->g0, F->V, F->norms, nrhs, N, F->gv, ld);
+  for (const SppGroup& g : F->groups) {
+    const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+    const int64_t o = g.Noff * nrhs;
+    kr_norms(st, F->g0 + o, nc, g.N, F->rpart, F->norms + c0);
+    kr_scale_init(st, F->g0 + o, F->V + o, F->norms + c0, nc, g.N, F->gv + (int64_t)c0 * ld, ld);
+  }
+  std::vector<double> beta(cols);
+  SPP_HIP(hipMemcpyAsync(beta.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
-  std::vector<int> k(nrhs, 0);
+  std::vector<int> k(cols, 0);
+  std::vector<bool> conv(cols, false);
   int done = 0;
-  for (int r = 0; r < nrhs; ++r)
-    if (beta[r] == 0) { k[r] = 0; ++done; }
-  std::vector<bool> conv(nrhs, false);
-  for (int r = 0; r < nrhs; ++r) conv[r] = beta[r] == 0;
+  for (int c = 0; c < cols; ++c)
+    if (beta[c] == 0) { conv[c] = true; ++done; }
   int j = 0;
-  for (; j < maxit && done < nrhs; ++j) {
+  for (; j < maxit && done < cols; ++j) {
     double2* vj = F->V + (int64_t)j * vstride;
     double2* zj = F->Z + (int64_t)j * vstride;
     // a9: z_j = M v_j
@@ -526,44 +662,57 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     else SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
     // a8: w = (I + G q) z_j
     apply_operator(F, zj, F->wk, nrhs, st);
-    // CGS2 against v_0 .. v_j; H(:, j) per right-hand side.
-    double2* hcol = F->H + (int64_t)j * ld;
-    kr_dots(st, F->V, vstride, j + 1, F->wk, nrhs, N, F->dpart, hcol, hrhs, 0, nullptr, 0);
-    kr_update(st, F->V, vstride, j + 1, F->wk, nrhs, N, hcol, hrhs);
-    kr_dots(st, F->V, vstride, j + 1, F->wk, nrhs, N, F->dpart, F->h2, ld, 0, hcol, hrhs);
-    kr_update(st, F->V, vstride, j + 1, F->wk, nrhs, N, F->h2, ld);
-    kr_norm_scale(st, F->wk, F->V + (int64_t)(j + 1) * vstride, nrhs, N, F->rpart, hcol + (j + 1), hrhs);
-    // a10: Givens update of the least-squares problem.
-    kr_givens(st, F->H, ld, hrhs, F->cs, F->sn, F->gv, j, nrhs, ld, F->resid, nullptr);
-    SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    // CGS2 against v_0 .. v_j; H(:, j) per column.
+    for (const SppGroup& g : F->groups) {
+      const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+      const int64_t o = g.Noff * nrhs;
+      double2* hcol = F->H + (int64_t)c0 * hrhs + (int64_t)j * ld;
+      double2* h2 = F->h2 + (int64_t)c0 * ld;
+      kr_dots(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, F->dpart, hcol, hrhs, 0, nullptr, 0);
+      kr_update(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, hcol, hrhs);
+      kr_dots(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, F->dpart, h2, ld, 0, hcol, hrhs);
+      kr_update(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, h2, ld);
+      kr_norm_scale(st, F->wk + o, F->V + (int64_t)(j + 1) * vstride + o, nc, g.N, F->rpart, hcol + (j + 1), hrhs);
+    }
+    // a10: Givens update of the least-squares problem (all columns at once).
+    kr_givens(st, F->H, ld, hrhs, F->cs, F->sn, F->gv, j, cols, ld, F->resid, nullptr);
+    SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
     SPP_HIP(hipStreamSynchronize(st));
-    for (int r = 0; r < nrhs; ++r) {
-      if (conv[r]) continue;
-      if (!(F->h_resid[r] > F->opt.tol * beta[r])) {
-        conv[r] = true;
-        k[r] = j + 1;
+    for (int c = 0; c < cols; ++c) {
+      if (conv[c]) continue;
+      if (!(F->h_resid[c] > F->opt.tol * beta[c])) {
+        conv[c] = true;
+        k[c] = j + 1;
         ++done;
       }
     }
   }
   bool all_conv = true;
-  for (int r = 0; r < nrhs; ++r)
-    if (!conv[r]) { k[r] = j; all_conv = false; }
+  for (int c = 0; c < cols; ++c)
+    if (!conv[c]) { k[c] = j; all_conv = false; }
   // a11: u = Z y, then the true residual ||g - (I + G q) u|| / ||g||.
-  SPP_HIP(hipMemcpyAsync(F->kvec, k.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-  kr_backsolve(st, F->H, ld, hrhs, F->gv, ld, F->y, 0, nrhs, F->kvec);
-  kr_combine(st, F->Z, vstride, std::max(1, *std::max_element(k.begin(), k.end())), F->y, ld, u, nrhs, N, F->kvec);
+  SPP_HIP(hipMemcpyAsync(F->kvec, k.data(), sizeof(int) * cols, hipMemcpyHostToDevice, st));
+  kr_backsolve(st, F->H, ld, hrhs, F->gv, ld, F->y, 0, cols, F->kvec);
+  const int kmax_all = std::max(1, *std::max_element(k.begin(), k.end()));
+  for (const SppGroup& g : F->groups) {
+    const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+    const int64_t o = g.Noff * nrhs;
+    kr_combine(st, F->Z + o, vstride, kmax_all, F->y + (int64_t)c0 * ld, ld, u + o, nc, g.N, F->kvec + c0);
+  }
   apply_operator(F, u, F->wk, nrhs, st);
   kr_sub(st, F->g0, F->wk, F->wk, vstride);
-  kr_norms(st, F->wk, nrhs, N, F->rpart, F->norms);
-  std::vector<double> rn(nrhs);
-  SPP_HIP(hipMemcpyAsync(rn.data(), F->norms, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  for (const SppGroup& g : F->groups) {
+    const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+    kr_norms(st, F->wk + g.Noff * nrhs, nc, g.N, F->rpart, F->norms + c0);
+  }
+  std::vector<double> rn(cols);
+  SPP_HIP(hipMemcpyAsync(rn.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
   int kmax = 0;
-  for (int r = 0; r < nrhs; ++r) {
-    iters[r] = k[r];
-    relres[r] = beta[r] > 0 ? rn[r] / beta[r] : 0.0;
-    kmax = std::max(kmax, k[r]);
+  for (int c = 0; c < cols; ++c) {
+    iters[c] = k[c];
+    relres[c] = beta[c] > 0 ? rn[c] / beta[c] : 0.0;
+    kmax = std::max(kmax, k[c]);
   }
   F->stats.last_iters = kmax;
   F->stats.t_solve_ms = now_ms() - t0;
@@ -579,7 +728,12 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
 extern "C" {
 
 int spp_setup(const spp_problem* problem, const spp_options* options, spp_stream_t stream, spp_factor** out) {
-  return guarded([&] { return do_setup(problem, options, reinterpret_cast<hipStream_t>(stream), out); });
+  return guarded([&] { return do_setup(problem, 1, options, reinterpret_cast<hipStream_t>(stream), out); });
+}
+
+int spp_setup_batch(const spp_problem* problems, int32_t count, const spp_options* options, spp_stream_t stream,
+                    spp_factor** out) {
+  return guarded([&] { return do_setup(problems, count, options, reinterpret_cast<hipStream_t>(stream), out); });
 }
 
 int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u, int32_t* iters, double* relres,
@@ -634,10 +788,18 @@ int spp_apply_precond(spp_factor* factor, const void* r, void* z, int32_t nrhs, 
 int spp_get_coefficients(const spp_factor* factor, double* s, double* q) {
   return guarded([&] {
     if (!factor) throw Error(SPP_EINVAL, "null factor");
-    if (s) *s = factor->s;
-    if (q) {
-      SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * factor->planp->N, hipMemcpyDeviceToDevice));
-    }
+    if (s) *s = factor->inst[0].s;
+    if (q) SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * factor->Ntot, hipMemcpyDeviceToDevice));
+    return SPP_OK;
+  });
+}
+
+int spp_get_shift(const spp_factor* factor, int32_t problem, double* s, int32_t* moves) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (problem < 0 || problem >= (int)factor->inst.size()) throw Error(SPP_EINVAL, "problem index out of range");
+    if (s) *s = factor->inst[problem].s;
+    if (moves) *moves = factor->inst[problem].moves;
     return SPP_OK;
   });
 }
@@ -646,9 +808,10 @@ int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t
                     void* C) {
   return guarded([&] {
     if (!factor) throw Error(SPP_EINVAL, "null factor");
-    if (type < 0 || type >= (1 << factor->planp->d)) throw Error(SPP_EINVAL, "set type out of range");
-    const SetType& ST = factor->planp->types[type];
-    const StencilDev& S = factor->sten[type];
+    const SppInstance& I = factor->inst[0];
+    if (type < 0 || type >= (1 << I.d)) throw Error(SPP_EINVAL, "set type out of range");
+    const SetType& ST = I.plan->types[type];
+    const StencilDev& S = I.sten[type];
     if (nS) *nS = ST.nS;
     if (nB) *nB = ST.nB;
     if (offsets) std::memcpy(offsets, ST.off.data(), ST.off.size() * sizeof(int));

@@ -102,7 +102,7 @@ __device__ double2* fft_lines(double2* a, double2* b, const FftArgs& g, int dir,
 __global__ void __launch_bounds__(kFftThreads)
 fft_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw, FftArgs g,
                 int dir, const double* __restrict__ pre, const double* __restrict__ mid,
-                const double2* add) {
+                const double2* add, int per) {
   extern __shared__ double2 lds[];
   double2* A = lds;
   double2* B = lds + g.L * g.n;
@@ -111,6 +111,7 @@ fft_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw,
   const int64_t batch = blockIdx.x / wg_per_batch;
   const int64_t line0 = (blockIdx.x - batch * wg_per_batch) * g.L;
   const int64_t bofs = batch * g.N;
+  const int64_t aofs = (batch / per) * g.N;   // per-instance multiplier arrays
   const int total = g.L * g.n;
 
   auto addr = [&](int li, int k) -> int64_t {   // grid index (within one batch entry)
@@ -128,7 +129,7 @@ fft_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw,
     unpack(t, li, k);
     const int64_t a = addr(li, k);
     double2 v = in[bofs + a];
-    if (pre) { const double s = pre[a]; v.x *= s; v.y *= s; }
+    if (pre) { const double s = pre[aofs + a]; v.x *= s; v.y *= s; }
     A[li * g.n + k] = v;
   }
   double2* res = fft_lines(A, B, g, dir, tw);
@@ -136,7 +137,7 @@ fft_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw,
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
       int li, k;
       unpack(t, li, k);
-      const double s = mid[addr(li, k)];
+      const double s = mid[aofs + addr(li, k)];
       double2& v = res[li * g.n + k];
       v.x *= s; v.y *= s;
     }
@@ -178,7 +179,7 @@ bool fft_supported(int n) {
 
 void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw, int n,
               int64_t outer, int64_t inner, int64_t N, int batch, int dir,
-              const double* pre, const double* mid, const double2* add) {
+              const double* pre, const double* mid, const double2* add, int per) {
   FftArgs g{};
   g.n = n;
   g.outer = outer;
@@ -201,27 +202,28 @@ void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw
   // Algorithmic bytes: read and write every complex point once, plus the
   // fused real multipliers and the added vector.
   const double pts = (double)N * batch;
-  const double bytes = pts * 32.0 + (pre ? 8.0 * N : 0.0) + (mid ? 8.0 * N : 0.0) + (add ? 16.0 * pts : 0.0);
+  const double ninst = (double)((batch + per - 1) / per);
+  const double bytes = pts * 32.0 + (pre ? 8.0 * N * ninst : 0.0) + (mid ? 8.0 * N * ninst : 0.0) + (add ? 16.0 * pts : 0.0);
   timer_begin(KC_FFT, st);
-  fft_axis_kernel<<<blocks, kFftThreads, lds, st>>>(in, out, tw, g, dir, pre, mid, add);
+  fft_axis_kernel<<<blocks, kFftThreads, lds, st>>>(in, out, tw, g, dir, pre, mid, add, per > 0 ? per : batch);
   SPP_LAUNCH_CHECK();
   timer_end(KC_FFT, st, bytes, 0.0);
 }
 
 // (I + G q) z, G f, or plain transforms, over all d axes of [batch][n]^d.
 void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, const double2* tw,
-               int d, int n, int batch, const double* pre, const double* sigma, const double2* add) {
+               int d, int n, int batch, const double* pre, const double* sigma, const double2* add, int per) {
   const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
   if (d == 2) {
-    fft_axis(st, in, tmp, tw, n, n, 1, N, batch, -1, pre, nullptr, nullptr);
-    fft_axis(st, tmp, tmp, tw, n, 1, n, N, batch, -1, nullptr, sigma, nullptr);
-    fft_axis(st, tmp, out, tw, n, n, 1, N, batch, +1, nullptr, nullptr, add);
+    fft_axis(st, in, tmp, tw, n, n, 1, N, batch, -1, pre, nullptr, nullptr, per);
+    fft_axis(st, tmp, tmp, tw, n, 1, n, N, batch, -1, nullptr, sigma, nullptr, per);
+    fft_axis(st, tmp, out, tw, n, n, 1, N, batch, +1, nullptr, nullptr, add, per);
   } else {
-    fft_axis(st, in, tmp, tw, n, (int64_t)n * n, 1, N, batch, -1, pre, nullptr, nullptr);
-    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, -1, nullptr, nullptr, nullptr);
-    fft_axis(st, tmp, tmp, tw, n, 1, (int64_t)n * n, N, batch, -1, nullptr, sigma, nullptr);
-    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, +1, nullptr, nullptr, nullptr);
-    fft_axis(st, tmp, out, tw, n, (int64_t)n * n, 1, N, batch, +1, nullptr, nullptr, add);
+    fft_axis(st, in, tmp, tw, n, (int64_t)n * n, 1, N, batch, -1, pre, nullptr, nullptr, per);
+    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, -1, nullptr, nullptr, nullptr, per);
+    fft_axis(st, tmp, tmp, tw, n, 1, (int64_t)n * n, N, batch, -1, nullptr, sigma, nullptr, per);
+    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, +1, nullptr, nullptr, nullptr, per);
+    fft_axis(st, tmp, out, tw, n, (int64_t)n * n, 1, N, batch, +1, nullptr, nullptr, add, per);
   }
 }
 
@@ -229,12 +231,12 @@ void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, co
 void fft_inverse_all(hipStream_t st, const double2* in, double2* out, const double2* tw, int d, int n) {
   const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
   if (d == 2) {
-    fft_axis(st, in, out, tw, n, n, 1, N, 1, +1, nullptr, nullptr, nullptr);
-    fft_axis(st, out, out, tw, n, 1, n, N, 1, +1, nullptr, nullptr, nullptr);
+    fft_axis(st, in, out, tw, n, n, 1, N, 1, +1, nullptr, nullptr, nullptr, 1);
+    fft_axis(st, out, out, tw, n, 1, n, N, 1, +1, nullptr, nullptr, nullptr, 1);
   } else {
-    fft_axis(st, in, out, tw, n, (int64_t)n * n, 1, N, 1, +1, nullptr, nullptr, nullptr);
-    fft_axis(st, out, out, tw, n, n, n, N, 1, +1, nullptr, nullptr, nullptr);
-    fft_axis(st, out, out, tw, n, 1, (int64_t)n * n, N, 1, +1, nullptr, nullptr, nullptr);
+    fft_axis(st, in, out, tw, n, (int64_t)n * n, 1, N, 1, +1, nullptr, nullptr, nullptr, 1);
+    fft_axis(st, out, out, tw, n, n, n, N, 1, +1, nullptr, nullptr, nullptr, 1);
+    fft_axis(st, out, out, tw, n, 1, (int64_t)n * n, N, 1, +1, nullptr, nullptr, nullptr, 1);
   }
 }
 

@@ -20,11 +20,14 @@ void timer_end(int cls, hipStream_t st, double bytes, double flops);
 // ------------------------------------------------------------- fft.hip
 void fft_make_twiddles(double2* tw, int n, hipStream_t st);
 bool fft_supported(int n);
+// pre and mid are per-instance real arrays of N entries; batch entry b uses
+// array b / per (per = right-hand sides per instance).
 void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw, int n,
               int64_t outer, int64_t inner, int64_t N, int batch, int dir,
-              const double* pre, const double* mid, const double2* add);
+              const double* pre, const double* mid, const double2* add, int per);
 void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, const double2* tw,
-               int d, int n, int batch, const double* pre, const double* sigma, const double2* add);
+               int d, int n, int batch, const double* pre, const double* sigma, const double2* add,
+               int per);
 void fft_inverse_all(hipStream_t st, const double2* in, double2* out, const double2* tw, int d, int n);
 
 // ------------------------------------------------------------- stencil.hip
@@ -62,6 +65,8 @@ struct FrontDev {
   int idx;             // global indices of the F front points (pivots first)
   int map;             // F - p parent positions of the boundary points
   int perm;            // p ints: pivot row permutation
+  int dblk;            // first diagonal-block slot (ceil(p / 32) slots of 2 x 32 x 32 entries)
+  int inst;            // problem instance the front belongs to
   int nchild;
   int child[8];
 };
@@ -77,9 +82,18 @@ struct TypeDev {       // per set type, for assembly / Q apply
   const double2* Ct;
 };
 
-struct MfDev {
+// One problem of a batch: its grid, potential and stencils.  Grid vectors of
+// a batch are stored instance after instance, [nrhs][N] each, so instance i
+// starts at Noff * nrhs.
+struct InstDev {
   int d, n, b, m;
-  int64_t N;
+  int64_t N;           // grid points
+  int64_t Noff;        // sum of N over the earlier instances
+  const double* q;
+  TypeDev types[8];
+};
+
+struct MfDev {
   const FrontDev* fronts;
   const AsmBlockDev* blocks;
   const int* pos;
@@ -87,26 +101,33 @@ struct MfDev {
   const int* map;
   int* perm;           // final row permutation of each front's pivot block
   int* ipiv;           // LAPACK-style interchange record written by the panel
-  const double* q;
-  TypeDev types[8];
   int* info;           // [0] = breakdown front + 1 (0 if none)
+  const InstDev* inst; // device array, one entry per instance
+  // Host-side summary (launch geometry).
+  int ninst, d;
+  int64_t anchors_max; // largest (n / b)^d over the instances
+  int64_t Ntot;        // sum of N
+  int nB_max[8];       // largest |beta| per set type
 };
 
 template <typename R>
-void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork,
+void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* dinv,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
-                     int max_children, bool invert);
+                     int max_children, bool invert, bool partial_pivoting,
+                     const int* hF, const int* hP);   // host: F and p of the level's fronts
 // Whether a level keeps explicit inverses of its pivot-block factors (few large
 // fronts) or solves with the LU in place (many small fronts).
 bool mf_level_uses_inverse(int nfronts, int maxP);
 
+// y = Q r for every instance of the batch (vectors in the batch layout).
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);
 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void* z,
               const void* x_in, void* x_out, int nrhs,
-              const int* level_begin, const int* level_maxF, const int* level_maxP,
-              const int* level_inv, int nlevels, void* partial, int64_t partial_cap);
+              const int* level_begin, const int* level_maxK, const int* level_maxP,
+              const double* level_ent, const int* level_inv, int nlevels, void* partial,
+              int64_t partial_cap);
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);

@@ -18,6 +18,7 @@
 // The solve runs forward elimination leaves -> root (children's update
 // vectors pulled by the parent) and back substitution root -> leaves.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -43,12 +44,13 @@ __device__ inline f4v mfma16(float a, float b, f4v c) {
 __device__ inline int mfma_row(double, int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ inline int mfma_row(float, int lane, int r) { return 4 * (lane >> 4) + r; }
 
-__device__ inline int anchor_point(const MfDev& mf, int anchor, const int* off) {
+// Grid index of offset `off` from the corner of leaf box `anchor` of instance I.
+__device__ inline int anchor_point(const InstDev& I, int anchor, const int* off) {
   int ac[3];
   int a = anchor;
-  for (int i = mf.d - 1; i >= 0; --i) { ac[i] = a % mf.m; a /= mf.m; }
+  for (int i = I.d - 1; i >= 0; --i) { ac[i] = a % I.m; a /= I.m; }
   int g = 0;
-  for (int i = 0; i < mf.d; ++i) g = g * mf.n + (((ac[i] * mf.b + off[i]) % mf.n) + mf.n) % mf.n;
+  for (int i = 0; i < I.d; ++i) g = g * I.n + (((ac[i] * I.b + off[i]) % I.n) + I.n) % I.n;
   return g;
 }
 
@@ -58,7 +60,8 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
   using C = cplx_t<R>;
   const AsmBlockDev B = mf.blocks[blk0 + blockIdx.x];
   const FrontDev f = mf.fronts[B.front];
-  const TypeDev T = mf.types[B.type];
+  const InstDev& I = mf.inst[f.inst];
+  const TypeDev& T = I.types[B.type];
   C* A = arena + f.off;
   // Column data of this block once per workgroup: front position and q at
   // every point of gamma(S).
@@ -67,7 +70,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
   __shared__ int rpos[1024];
   for (int j = threadIdx.x; j < T.nG; j += blockDim.x) {
     cpos[j] = mf.pos[B.colpos + j];
-    qg[j] = mf.q[anchor_point(mf, B.anchor, T.off + j * mf.d)];
+    qg[j] = I.q[anchor_point(I, B.anchor, T.off + j * I.d)];
   }
   for (int i = threadIdx.x; i < T.nS; i += blockDim.x) rpos[i] = mf.pos[B.rowpos + i];
   __syncthreads();
@@ -93,9 +96,9 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
 template <typename R>
 __global__ void extend_add_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int f0, int slot, int cols_per_wg) {
   using C = cplx_t<R>;
-  const FrontDev par = mf.fronts[f0 + blockIdx.y];
+  const FrontDev& par = mf.fronts[f0 + blockIdx.y];   // by reference: child[] indexed at run time
   if (slot >= par.nchild) return;
-  const FrontDev ch = mf.fronts[par.child[slot]];
+  const FrontDev& ch = mf.fronts[par.child[slot]];
   const int K = ch.F - ch.p;
   const int* map = mf.map + ch.map;
   const C* S = arena + ch.off;
@@ -378,6 +381,133 @@ __global__ void __launch_bounds__(64) laswp_kernel(MfDev mf, cplx_t<R>* __restri
   for (int x = 0; x < n; ++x) cp[rows[x]] = tmp[threadIdx.x][x];
 }
 
+// ------------------------------------------------------------------ block-local pivoting LU
+// Default factorisation step (block-local pivoting): the pivot of column j is
+// the largest-modulus entry among the rows of the current kb x kb diagonal
+// block (kb <= 32), so the whole pivot search and elimination of a step runs
+// in LDS inside one wavefront.  The block's L and U are written back, their
+// inverses Linv_kk, Uinv_kk (kb x kb, column-major) go to dinv, and the other
+// two products of the step become dense, dependency-free multiplications:
+// L21 = A21 Uinv_kk (l21_kernel) and U12 = Linv_kk P A12 (rowblock_kernel).
+constexpr int kDB = 32;
+
+template <typename R>
+__global__ void __launch_bounds__(128) diag_lu_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
+                                                      cplx_t<R>* __restrict__ dinv, int f0, int k0, int nb) {
+  using C = cplx_t<R>;
+  const int fi = f0 + blockIdx.x;
+  const FrontDev f = mf.fronts[fi];
+  if (k0 >= f.p) return;
+  const int kb = min(nb, f.p - k0);
+  const int F = f.F;
+  C* A = arena + f.off + (int64_t)k0 * F + k0;   // block origin, leading dimension F
+  __shared__ C D[kDB][kDB + 1];
+  __shared__ C prow[kDB], jrow[kDB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // Wave 0, lane i owns row i of the block in registers.
+  C a[kDB];
+  if (wave == 0) {
+#pragma unroll
+    for (int c = 0; c < kDB; ++c) a[c] = (lane < kb && c < kb) ? A[(int64_t)c * F + lane] : cmake<C>(0, 0);
+  }
+  // Column steps unrolled with literal indices so the row stays in registers.
+#define SPP_DIAG_LU_STEP(J) { \
+    constexpr int j = (J); \
+    const bool act = j < kb; /* uniform over the workgroup */ \
+    int piv = j; \
+    bool ok = true; \
+    if (act && wave == 0) { \
+      R v = (lane >= j && lane < kb) ? cabs2(a[j]) : R(-1); \
+      int bi = lane; \
+      for (int o = 32; o > 0; o >>= 1) { \
+        const R ov = __shfl_xor(v, o, 64); \
+        const int oi = __shfl_xor(bi, o, 64); \
+        if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; } \
+      } \
+      ok = v > R(0) && isfinite(v); \
+      piv = ok ? bi : j; \
+      if (lane == piv) \
+_Pragma("unroll") \
+        for (int c = 0; c < kDB; ++c) prow[c] = a[c]; \
+      if (lane == j) \
+_Pragma("unroll") \
+        for (int c = 0; c < kDB; ++c) jrow[c] = a[c]; \
+      if (lane == 0) { \
+        ipiv[f.perm + k0 + j] = k0 + piv; \
+        if (!ok) atomicCAS(mf.info, 0, fi + 1); \
+      } \
+    } \
+    __syncthreads(); \
+    if (act && wave == 0) { \
+      if (lane == j) { \
+_Pragma("unroll") \
+        for (int c = 0; c < kDB; ++c) a[c] = prow[c]; \
+      } else if (lane == piv) { \
+_Pragma("unroll") \
+        for (int c = 0; c < kDB; ++c) a[c] = jrow[c]; \
+      } \
+      if (lane > j && lane < kb) { \
+        const C pj = prow[j]; \
+        const C l = (cabs2(pj) > R(0)) ? cdiv(a[j], pj) : cmake<C>(0, 0); \
+        a[j] = l; \
+_Pragma("unroll") \
+        for (int c = j + 1; c < kDB; ++c) cfms(a[c], l, prow[c]); \
+      } \
+    } \
+    __syncthreads(); \
+  }
+  SPP_DIAG_LU_STEP(0) SPP_DIAG_LU_STEP(1) SPP_DIAG_LU_STEP(2) SPP_DIAG_LU_STEP(3) SPP_DIAG_LU_STEP(4) SPP_DIAG_LU_STEP(5) SPP_DIAG_LU_STEP(6) SPP_DIAG_LU_STEP(7) SPP_DIAG_LU_STEP(8) SPP_DIAG_LU_STEP(9) SPP_DIAG_LU_STEP(10) SPP_DIAG_LU_STEP(11) SPP_DIAG_LU_STEP(12) SPP_DIAG_LU_STEP(13) SPP_DIAG_LU_STEP(14) SPP_DIAG_LU_STEP(15) SPP_DIAG_LU_STEP(16) SPP_DIAG_LU_STEP(17) SPP_DIAG_LU_STEP(18) SPP_DIAG_LU_STEP(19) SPP_DIAG_LU_STEP(20) SPP_DIAG_LU_STEP(21) SPP_DIAG_LU_STEP(22) SPP_DIAG_LU_STEP(23) SPP_DIAG_LU_STEP(24) SPP_DIAG_LU_STEP(25) SPP_DIAG_LU_STEP(26) SPP_DIAG_LU_STEP(27) SPP_DIAG_LU_STEP(28) SPP_DIAG_LU_STEP(29) SPP_DIAG_LU_STEP(30) SPP_DIAG_LU_STEP(31)
+#undef SPP_DIAG_LU_STEP
+  if (wave == 0 && lane < kb) {
+#pragma unroll
+    for (int c = 0; c < kDB; ++c) {
+      D[lane][c] = a[c];
+      if (c < kb) A[(int64_t)c * F + lane] = a[c];
+    }
+  }
+  __syncthreads();
+  // Wave 0: Linv_kk, wave 1: Uinv_kk, lane = column.
+  C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
+  C* Ui = Li + kDB * kDB;
+  const int c = lane;
+  if (c < kb) {
+    C x[kDB];
+    if (wave == 0) {
+#pragma unroll
+      for (int i = 0; i < kDB; ++i) {
+        if (i < c || i >= kb) x[i] = cmake<C>(0, 0);
+        else if (i == c) x[i] = cmake<C>(1, 0);
+        else {
+          C s = cmake<C>(0, 0);
+#pragma unroll
+          for (int l = 0; l < kDB; ++l)
+            if (l < i && l >= c) cfms(s, D[i][l], x[l]);
+          x[i] = s;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kDB; ++i)
+        if (i < kb) Li[c * kDB + i] = x[i];
+    } else {
+#pragma unroll
+      for (int i = kDB - 1; i >= 0; --i) {
+        if (i > c || i >= kb) x[i] = cmake<C>(0, 0);
+        else {
+          C s = cmake<C>(i == c ? 1 : 0, 0);
+#pragma unroll
+          for (int l = 0; l < kDB; ++l)
+            if (l > i && l <= c) cfms(s, D[i][l], x[l]);
+          const C dd = D[i][i];
+          x[i] = (cabs2(dd) > R(0)) ? cdiv(s, dd) : cmake<C>(0, 0);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kDB; ++i)
+        if (i < kb) Ui[c * kDB + i] = x[i];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ row-block TRSM
 // mode 0: LU row block  front[k0:k0+kb, k0+kb:F] = L_kk^{-1} (.)
 // mode 1: L inverse     XL[k0:k0+kb, 0:k0+kb]    = L_kk^{-1} (.)
@@ -463,18 +593,46 @@ constexpr int kBM = 64, kBN = 64, kBK = 16;
 
 template <typename R>
 __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
-                                                   int f0, int step, int nb, int mode, int tiles_m) {
+                                                   const cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode,
+                                                   int tiles_m) {
   using C = cplx_t<R>;
   using V = typename Acc<R>::type;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   int k0, kb;
-  if (!step_range<R>(f, mode, step, nb, k0, kb)) return;
+  if (!step_range<R>(f, (mode == 2 || mode == 6) ? 2 : 0, step, nb, k0, kb)) return;
   const int F = f.F, p = f.p;
   C* base = arena + f.off;
   const C *Ap, *Bp;
   C* Cp;
   int m, n, k, lda, ldb, ldc;
-  if (mode == 0) {
+  // Modes 3-6 overwrite C with A B (C aliases an input; every workgroup reads
+  // all of its own input block before it writes it back).
+  const bool assign = mode >= 3;
+  const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
+  const C* Ui = Li + kDB * kDB;
+  if (mode == 3) {            // U12 = Linv_kk (P A12)
+    m = kb; n = F - k0 - kb; k = kb;
+    Ap = Li; lda = kDB;
+    Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
+    Cp = base + (int64_t)(k0 + kb) * F + k0; ldc = F;
+  } else if (mode == 4) {     // L21 = A21 Uinv_kk
+    m = F - k0 - kb; n = kb; k = kb;
+    Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
+    Bp = Ui; ldb = kDB;
+    Cp = base + (int64_t)k0 * F + (k0 + kb); ldc = F;
+  } else if (mode == 5) {     // XL rows = Linv_kk XL rows
+    C* XL = xwork + f.xoff;
+    m = kb; n = k0 + kb; k = kb;
+    Ap = Li; lda = kDB;
+    Bp = XL + k0; ldb = p;
+    Cp = XL + k0; ldc = p;
+  } else if (mode == 6) {     // XU rows = Uinv_kk XU rows
+    C* XU = xwork + f.xoff + (int64_t)p * p;
+    m = kb; n = p - k0; k = kb;
+    Ap = Ui; lda = kDB;
+    Bp = XU + (int64_t)k0 * p + k0; ldb = p;
+    Cp = XU + (int64_t)k0 * p + k0; ldc = p;
+  } else if (mode == 0) {
     m = n = F - k0 - kb; k = kb;
     Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
     Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
@@ -547,8 +705,13 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
         const int col = n0 + wn + 16 * b + (lane & 15);
         if (row < m && col < n) {
           C& c = Cp[(int64_t)col * ldc + row];
-          c.x -= rr[a][b][r] - ii[a][b][r];
-          c.y -= ri[a][b][r] + ir[a][b][r];
+          if (assign) {
+            c.x = rr[a][b][r] - ii[a][b][r];
+            c.y = ri[a][b][r] + ir[a][b][r];
+          } else {
+            c.x -= rr[a][b][r] - ii[a][b][r];
+            c.y -= ri[a][b][r] + ir[a][b][r];
+          }
         }
       }
 }
@@ -602,17 +765,22 @@ __global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0) {
 // ------------------------------------------------------------------ Q apply
 // (Q r)_S = r_S - T_S r_beta(S) for every set instance (Section 2.3).
 __global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2* __restrict__ y, int nrhs, int type) {
-  const TypeDev T = mf.types[type];
+  const InstDev& I = mf.inst[blockIdx.z];
+  int anchors = 1;
+  for (int i = 0; i < I.d; ++i) anchors *= I.m;
   const int anchor = blockIdx.x;
+  if (anchor >= anchors) return;
+  const TypeDev& T = I.types[type];
   const int rhs = blockIdx.y;
-  const double2* rr = r + (int64_t)rhs * mf.N;
-  double2* yy = y + (int64_t)rhs * mf.N;
+  const int64_t base = I.Noff * nrhs + (int64_t)rhs * I.N;
+  const double2* rr = r + base;
+  double2* yy = y + base;
   extern __shared__ double2 rb[];
   for (int j = threadIdx.x; j < T.nB; j += blockDim.x)
-    rb[j] = rr[anchor_point(mf, anchor, T.off + (T.nS + j) * mf.d)];
+    rb[j] = rr[anchor_point(I, anchor, T.off + (T.nS + j) * I.d)];
   __syncthreads();
   for (int i = threadIdx.x; i < T.nS; i += blockDim.x) {
-    const int g = anchor_point(mf, anchor, T.off + i * mf.d);
+    const int g = anchor_point(I, anchor, T.off + i * I.d);
     double2 s = rr[g];
     for (int j = 0; j < T.nB; ++j) cfms(s, T.Tt[(int64_t)j * T.nS + i], rb[j]);
     yy[g] = s;
@@ -627,13 +795,16 @@ __global__ void fwd_gather_kernel(MfDev mf, cplx_t<R>* __restrict__ W, const cpl
   const FrontDev f = mf.fronts[f0 + blockIdx.x];
   C* w = W + f.voff * nrhs;
   const int* idx = mf.idx + f.idx;
+  const InstDev& I = mf.inst[f.inst];
+  const C* xi = x + I.Noff * nrhs;
   for (int t = threadIdx.x; t < f.F * nrhs; t += blockDim.x) {
     const int i = t / nrhs, r = t - i * nrhs;
-    w[t] = (i < f.p) ? x[(int64_t)r * mf.N + idx[i]] : cmake<C>(0, 0);
+    w[t] = (i < f.p) ? xi[(int64_t)r * I.N + idx[i]] : cmake<C>(0, 0);
   }
   __syncthreads();
+  const int* children = mf.fronts[f0 + blockIdx.x].child;   // global, indexed at run time
   for (int c = 0; c < f.nchild; ++c) {
-    const FrontDev ch = mf.fronts[f.child[c]];
+    const FrontDev& ch = mf.fronts[children[c]];
     const int K = ch.F - ch.p;
     const int* map = mf.map + ch.map;
     const C* wc = W + (ch.voff + ch.p) * nrhs;
@@ -670,6 +841,9 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   const int* perm = mf.perm + f.perm;
   C* w = W + f.voff * nrhs;
   C* z = Z + f.voff * nrhs;
+  const InstDev& I = mf.inst[f.inst];
+  C* xo = xout + I.Noff * nrhs;
+  const int64_t NI = I.N;
   int jlo, jhi;
   if (mode == 0) { jlo = 0; jhi = min(p, row0 + 64); }
   else if (mode == 1) { jlo = 0; jhi = p; }
@@ -698,7 +872,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
       C v;
       if (mode == 0) v = w[perm[j] * nrhs + r0 + r];
       else if (mode == 1) v = z[j * nrhs + r0 + r];
-      else if (mode == 2) v = xout[(int64_t)(r0 + r) * mf.N + idx[p + j]];
+      else if (mode == 2) v = xo[(int64_t)(r0 + r) * NI + idx[p + j]];
       else v = z[j * nrhs + r0 + r];
       cfma(acc[r], a, v);
     }
@@ -724,7 +898,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
       C& d = z[row * nrhs + rr];
       d = csub(d, s);
     } else {
-      xout[(int64_t)rr * mf.N + idx[row]] = s;
+      xo[(int64_t)rr * NI + idx[row]] = s;
     }
   }
 }
@@ -861,9 +1035,11 @@ __global__ void __launch_bounds__(256) bwd_tri_kernel(MfDev mf, const cplx_t<R>*
     }
     __syncthreads();
   }
+  const InstDev& I = mf.inst[f.inst];
+  C* xo = xout + I.Noff * nrhs;
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
-    if (r < nr) xout[(int64_t)(r0 + r) * mf.N + idx[i]] = y[t];
+    if (r < nr) xo[(int64_t)(r0 + r) * I.N + idx[i]] = y[t];
   }
 }
 
@@ -893,7 +1069,8 @@ __global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R
     C& d = z[row * nrhs + rr];
     d = csub(d, s);
   } else {
-    xout[(int64_t)rr * mf.N + mf.idx[f.idx + row]] = s;
+    const InstDev& I = mf.inst[f.inst];
+    xout[I.Noff * nrhs + (int64_t)rr * I.N + mf.idx[f.idx + row]] = s;
   }
 }
 
@@ -910,11 +1087,13 @@ constexpr int kNB = 32;
 }  // namespace
 
 template <typename R>
-void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, int f0, int f1, int maxF,
-                     int maxP, int blk0, int blk1, int max_children, bool invert) {
+void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* dinv_v, int f0, int f1,
+                     int maxF, int maxP, int blk0, int blk1, int max_children, bool invert, bool partial_pivoting,
+                     const int* hF, const int* hP) {
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
   C* xwork = static_cast<C*>(xwork_v);
+  C* dinv = static_cast<C*>(dinv_v);
   const int nf = f1 - f0;
   if (blk1 > blk0) {
     assemble_kernel<R><<<blk1 - blk0, 256, 0, st>>>(mf, arena, blk0);
@@ -931,27 +1110,46 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   for (int s = 0; s < steps; ++s) {
     const int k0 = s * kNB;
     timer_begin(KC_PANEL, st);
-    if (maxF <= 512) panel2_kernel<R, 256, 2><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
-    else if (maxF <= 1024) panel2_kernel<R, 512, 2><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
-    else if (maxF <= 2048) panel2_kernel<R, 512, 4><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
-    else if (maxF <= 4096) panel2_kernel<R, 1024, 4><<<nf, 1024, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
-    else panel_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB, 0);
+    if (partial_pivoting) {
+      // Pivot search over all remaining fully-summed rows of the column.
+      if (maxF <= 512) panel2_kernel<R, 256, 2><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+      else if (maxF <= 1024) panel2_kernel<R, 512, 2><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+      else if (maxF <= 2048) panel2_kernel<R, 512, 4><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+      else if (maxF <= 4096) panel2_kernel<R, 1024, 4><<<nf, 1024, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+      else panel_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB, 0);
+    } else {
+      diag_lu_kernel<R><<<nf, 128, 0, st>>>(mf, arena, mf.ipiv, dinv, f0, k0, kNB);
+    }
     SPP_LAUNCH_CHECK();
     timer_end(KC_PANEL, st, 0.0, 0.0);
-    if (maxF <= 4096) {
+    if (partial_pivoting && maxF > 4096) {
+      // the global-memory panel applies its interchanges itself
+    } else {
       laswp_kernel<R><<<dim3(ceil_div(maxF, 64), nf), 64, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
       SPP_LAUNCH_CHECK();
     }
-    trsm_kernel<R><<<dim3(ceil_div(maxF, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0);
+    if (partial_pivoting) {
+      trsm_kernel<R><<<dim3(ceil_div(maxF, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0);
+    } else {
+      // L21 = A21 Uinv_kk and U12 = Linv_kk P A12 on MFMA (one 64-wide tile strip each).
+      gemm_kernel<R><<<dim3(tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 4, tiles);
+      SPP_LAUNCH_CHECK();
+      gemm_kernel<R><<<dim3(tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 3, 1);
+    }
     SPP_LAUNCH_CHECK();
     {
-      // Trailing update of this step for the level's largest front (all fronts
-      // of a level have the same size in the orderings used): 8 m n k flops.
-      const double kb = std::min(kNB, maxP - k0), mn = maxF - k0 - kb;
+      // Trailing updates of this step, 8 m n k real flops per front.
+      double fl = 0;
+      if (g_timer)
+        for (int i = 0; i < nf; ++i) {
+          if (k0 >= hP[i]) continue;
+          const double kb = std::min(kNB, hP[i] - k0), mn = hF[i] - k0 - kb;
+          fl += 8.0 * mn * mn * kb;
+        }
       timer_begin(KC_GEMM, st);
-      gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0, tiles);
+      gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 0, tiles);
       SPP_LAUNCH_CHECK();
-      timer_end(KC_GEMM, st, 0.0, 8.0 * nf * mn * mn * kb);
+      timer_end(KC_GEMM, st, 0.0, fl);
     }
   }
   perm_kernel<<<nf, 256, 2 * sizeof(int) * maxP, st>>>(mf, mf.ipiv, f0);
@@ -961,17 +1159,16 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   const int ptiles = (int)ceil_div(maxP, kBM);
   identity_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, f0);
   SPP_LAUNCH_CHECK();
-  for (int s = 0; s < steps; ++s) {
-    trsm_kernel<R><<<dim3(ceil_div(maxP, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 1);
-    SPP_LAUNCH_CHECK();
-    gemm_kernel<R><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 1, ptiles);
-    SPP_LAUNCH_CHECK();
-  }
-  for (int s = 0; s < steps; ++s) {
-    trsm_kernel<R><<<dim3(ceil_div(maxP, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 2);
-    SPP_LAUNCH_CHECK();
-    gemm_kernel<R><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 2, ptiles);
-    SPP_LAUNCH_CHECK();
+  for (int mode = 1; mode <= 2; ++mode) {
+    for (int s = 0; s < steps; ++s) {
+      if (partial_pivoting)
+        trsm_kernel<R><<<dim3(ceil_div(maxP, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, mode);
+      else
+        gemm_kernel<R><<<dim3(ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, mode + 4, 1);
+      SPP_LAUNCH_CHECK();
+      gemm_kernel<R><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, mode, ptiles);
+      SPP_LAUNCH_CHECK();
+    }
   }
   merge_inverse_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, arena, xwork, f0);
   SPP_LAUNCH_CHECK();
@@ -986,19 +1183,19 @@ bool mf_level_uses_inverse(int nfronts, int maxP) {
 
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
   const int ntypes = 1 << mf.d;
-  const int anchors = (int)(mf.N / ((int64_t)mf.b * (mf.d == 3 ? (int64_t)mf.b * mf.b : mf.b)));
   timer_begin(KC_QAPPLY, st);
   for (int t = 0; t < ntypes; ++t) {
-    q_apply_kernel<<<dim3(anchors, nrhs), 256, sizeof(double2) * mf.types[t].nB, st>>>(mf, r, y, nrhs, t);
+    dim3 grid((unsigned)mf.anchors_max, nrhs, mf.ninst);
+    q_apply_kernel<<<grid, 256, sizeof(double2) * mf.nB_max[t], st>>>(mf, r, y, nrhs, t);
     SPP_LAUNCH_CHECK();
   }
-  timer_end(KC_QAPPLY, st, 32.0 * mf.N * nrhs, 0.0);
+  timer_end(KC_QAPPLY, st, 32.0 * mf.Ntot * nrhs, 0.0);
 }
 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
-              void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxP,
-              const int* level_inv, int nlevels, void* partial_v, int64_t partial_cap) {
+              void* x_out, int nrhs, const int* level_begin, const int* level_maxK, const int* level_maxP,
+              const double* level_ent, const int* level_inv, int nlevels, void* partial_v, int64_t partial_cap) {
   using C = cplx_t<R>;
   const C* arena = static_cast<const C*>(arena_v);
   C* W = static_cast<C*>(w_v);
@@ -1008,7 +1205,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
   C* partial = static_cast<C*>(partial_v);
   // Row-tiled products; large fronts split their columns over several
   // workgroups (deterministic partial sums, then gemv_finish_kernel).
-  auto gemv = [&](int f0, int nf, int rows, int cols, int mode) {
+  auto gemv = [&](int f0, int nf, int rows, int cols, int mode, double ent) {
     const int rtiles = (int)ceil_div(rows, 64);
     int nchunks = 1;
     if ((int64_t)rtiles * nf < 1024) {
@@ -1017,9 +1214,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       while (nchunks > 1 && (int64_t)nf * nchunks * rows * nrhs > partial_cap) --nchunks;
     }
     dim3 grid(rtiles * nchunks, nf);
-    // Factor entries read per pass over the right-hand sides.
-    const double ent = (mode == 0) ? 0.5 * rows * (rows - 1.0) : (mode == 3) ? 0.5 * rows * (rows + 1.0)
-                                                                            : (double)rows * cols;
+    // ent: factor entries of the level read per pass over the right-hand sides.
     const double passes = (nrhs / 4) + (nrhs % 4);
     timer_begin(KC_GEMV, st);
     int r0 = 0;
@@ -1038,10 +1233,9 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
           mf, W, Z, xout, nrhs, f0, mode, nchunks, partial, rows);
       SPP_LAUNCH_CHECK();
     }
-    timer_end(KC_GEMV, st, nf * ent * passes * sizeof(C), 8.0 * nf * ent * nrhs);
+    timer_end(KC_GEMV, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
   };
-  auto tri = [&](int f0, int nf, int maxP, bool fwd) {
-    const double ent = fwd ? 0.5 * maxP * (maxP - 1.0) : 0.5 * maxP * (maxP + 1.0);
+  auto tri = [&](int f0, int nf, int maxP, bool fwd, double ent) {
     const double passes = (nrhs / 4) + (nrhs % 4);
     timer_begin(KC_TRI, st);
     int r0 = 0;
@@ -1058,23 +1252,26 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       SPP_LAUNCH_CHECK();
       r0 += nr;
     }
-    timer_end(KC_TRI, st, nf * ent * passes * sizeof(C), 8.0 * nf * ent * nrhs);
+    timer_end(KC_TRI, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
   };
+  // level_ent per level: sum over fronts of p (p - 1) / 2, p (p + 1) / 2 and (F - p) p.
   for (int l = 0; l < nlevels; ++l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
-    const int mF = level_maxF[l], mP = level_maxP[l];
+    const int mK = level_maxK[l], mP = level_maxP[l];
+    const double* e = level_ent + 3 * l;
     fwd_gather_kernel<R><<<nf, 256, 0, st>>>(mf, W, xin, nrhs, f0);
     SPP_LAUNCH_CHECK();
-    if (level_inv[l]) gemv(f0, nf, mP, mP, 0);
-    else tri(f0, nf, mP, true);
-    if (mF > mP) gemv(f0, nf, mF - mP, mP, 1);
+    if (level_inv[l]) gemv(f0, nf, mP, mP, 0, e[0]);
+    else tri(f0, nf, mP, true, e[0]);
+    if (mK > 0) gemv(f0, nf, mK, mP, 1, e[2]);
   }
   for (int l = nlevels - 1; l >= 0; --l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
-    const int mF = level_maxF[l], mP = level_maxP[l];
-    if (mF > mP) gemv(f0, nf, mP, mF - mP, 2);
-    if (level_inv[l]) gemv(f0, nf, mP, mP, 3);
-    else tri(f0, nf, mP, false);
+    const int mK = level_maxK[l], mP = level_maxP[l];
+    const double* e = level_ent + 3 * l;
+    if (mK > 0) gemv(f0, nf, mP, mK, 2, e[2]);
+    if (level_inv[l]) gemv(f0, nf, mP, mP, 3, e[1]);
+    else tri(f0, nf, mP, false, e[1]);
   }
 }
 
@@ -1084,12 +1281,14 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
   SPP_LAUNCH_CHECK();
 }
 
-template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, int, int, int, int, int, int, int, bool);
-template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, int, int, int, int, int, int, int, bool);
+template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, int, int, int, int, int, int, int, bool,
+                                      bool, const int*, const int*);
+template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, int, int, int, int, int, int, int, bool,
+                                     bool, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
-                               const int*, const int*, const int*, const int*, int, void*, int64_t);
+                               const int*, const int*, const int*, const double*, const int*, int, void*, int64_t);
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
-                              const int*, const int*, const int*, const int*, int, void*, int64_t);
+                              const int*, const int*, const int*, const double*, const int*, int, void*, int64_t);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
 

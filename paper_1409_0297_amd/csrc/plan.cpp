@@ -249,6 +249,7 @@ std::string build_plan(int d, int n, int b, int order, Plan& P) {
       P.fronts.push_back(f);
       L.maxF = std::max(L.maxF, f.F);
       L.maxP = std::max(L.maxP, f.p);
+      L.maxK = std::max(L.maxK, f.F - f.p);
     }
     L.end = static_cast<int>(P.fronts.size());
     L.blk_end = static_cast<int>(P.blocks.size());
@@ -307,6 +308,82 @@ std::string build_plan(int d, int n, int b, int order, Plan& P) {
   }
   P.arena_elems = off;
   P.vec_elems = voff;
+  return std::string();
+}
+
+std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std::vector<int>& front_inst) {
+  if (plans.empty()) return "empty batch";
+  out = Plan();
+  front_inst.clear();
+  const Plan& p0 = *plans[0];
+  out.d = p0.d; out.n = p0.n; out.b = p0.b; out.m = p0.m; out.order = p0.order;
+  out.types = p0.types;
+  size_t nlev = 0;
+  for (const Plan* P : plans) {
+    if (P->d != p0.d) return "all problems of a batch must have the same dimension";
+    nlev = std::max(nlev, P->levels.size());
+    out.N += P->N;
+  }
+  const size_t ni = plans.size();
+  std::vector<std::vector<int>> newid(ni);
+  std::vector<int> idx_base(ni), map_base(ni), pos_base(ni);
+  std::vector<int64_t> off_base(ni), voff_base(ni);
+  for (size_t i = 0; i < ni; ++i) {
+    newid[i].assign(plans[i]->fronts.size(), -1);
+    idx_base[i] = static_cast<int>(out.idx.size());
+    out.idx.insert(out.idx.end(), plans[i]->idx.begin(), plans[i]->idx.end());
+    map_base[i] = static_cast<int>(out.map.size());
+    out.map.insert(out.map.end(), plans[i]->map.begin(), plans[i]->map.end());
+    pos_base[i] = static_cast<int>(out.pos.size());
+    out.pos.insert(out.pos.end(), plans[i]->pos.begin(), plans[i]->pos.end());
+    off_base[i] = out.arena_elems;
+    out.arena_elems += plans[i]->arena_elems;
+    voff_base[i] = out.vec_elems;
+    out.vec_elems += plans[i]->vec_elems;
+    out.factor_entries += plans[i]->factor_entries;
+    out.factor_flops += plans[i]->factor_flops;
+    out.max_front = std::max(out.max_front, plans[i]->max_front);
+  }
+  for (size_t l = 0; l < nlev; ++l) {
+    Level L;
+    L.begin = static_cast<int>(out.fronts.size());
+    L.blk_begin = static_cast<int>(out.blocks.size());
+    for (size_t i = 0; i < ni; ++i) {
+      const Plan& P = *plans[i];
+      if (l >= P.levels.size()) continue;
+      const Level& PL = P.levels[l];
+      for (int fi = PL.begin; fi < PL.end; ++fi) {
+        Front f = P.fronts[fi];
+        f.level = static_cast<int>(l);
+        f.idx += idx_base[i];
+        f.map += map_base[i];
+        f.off += off_base[i];
+        f.voff += voff_base[i];
+        for (int& c : f.children) {
+          c = newid[i][c];
+          if (c < 0) return "child front of a batch problem placed after its parent";
+        }
+        f.parent = -1;
+        newid[i][fi] = static_cast<int>(out.fronts.size());
+        out.fronts.push_back(f);
+        front_inst.push_back(static_cast<int>(i));
+        L.maxF = std::max(L.maxF, f.F);
+        L.maxP = std::max(L.maxP, f.p);
+        L.maxK = std::max(L.maxK, f.F - f.p);
+        L.max_children = std::max<int>(L.max_children, static_cast<int>(f.children.size()));
+      }
+      for (int bi = PL.blk_begin; bi < PL.blk_end; ++bi) {
+        AsmBlock B = P.blocks[bi];
+        B.front = newid[i][B.front];
+        if (B.rowpos >= 0) B.rowpos += pos_base[i];
+        if (B.colpos >= 0) B.colpos += pos_base[i];
+        out.blocks.push_back(B);
+      }
+    }
+    L.end = static_cast<int>(out.fronts.size());
+    L.blk_end = static_cast<int>(out.blocks.size());
+    out.levels.push_back(L);
+  }
   return std::string();
 }
 

@@ -48,6 +48,7 @@ struct Front {
 struct Level {
   int begin = 0, end = 0;       // fronts [begin, end)
   int maxF = 0, maxP = 0;
+  int maxK = 0;                 // largest F - p (fronts of a batch level differ)
   int max_children = 0;
   int blk_begin = 0, blk_end = 0;   // assembly blocks of this level
 };
@@ -76,5 +77,12 @@ std::string validate_grid(int d, int n, int b);
 
 // Builds the plan; returns an empty string on success, else a message.
 std::string build_plan(int d, int n, int b, int order, Plan& plan);
+
+// Concatenates the plans of a batch of problems level by level, aligned at
+// the leaves, so that one launch per level covers the fronts of every
+// problem.  front_inst[f] is the problem of combined front f.  Index pools
+// stay problem-local (grid indices, front positions); front, child, arena and
+// vector offsets are renumbered.  All plans must have the same dimension.
+std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std::vector<int>& front_inst);
 
 }  // namespace spp
