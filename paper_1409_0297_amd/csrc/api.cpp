@@ -156,7 +156,7 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
   std::vector<FrontDev> fd(P.fronts.size());
   for (const Level& L : P.levels) {
     int64_t xo = 0;
-    const bool inv = mf_level_uses_inverse(L.end - L.begin, L.maxP);
+    const bool inv = mf_level_uses_inverse(L.end - L.begin, L.maxF, L.maxP);
     pd->level_inv.push_back(inv ? 1 : 0);
     double e0 = 0, e1 = 0, e2 = 0;
     std::vector<int> hF, hP;
@@ -244,7 +244,7 @@ struct spp_factor {
   MfDev mf{};
   void* arena = nullptr;
   size_t csize = 16;  // bytes per complex front entry
-  std::vector<int> level_begin, level_maxK, level_maxP, level_inv;
+  std::vector<int> level_begin, level_maxF, level_maxK, level_maxP, level_inv;
   void* gpart = nullptr;       // split-K partial sums of the substitution
   int64_t gpart_cap = 0;
   // solve work (grown on demand)
@@ -395,12 +395,12 @@ void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStr
   const int nl = static_cast<int>(F->planp->levels.size());
   const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
-    mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxK.data(),
+    mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
                      F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap);
   } else {
     const int64_t cnt = (int64_t)nrhs * F->Ntot;
     cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
-    mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxK.data(),
+    mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
                     F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap);
     cast_vectors<float>(st, F->xc, z, cnt, 1);
   }
@@ -567,6 +567,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   }
   for (const Level& L : P.levels) {
     F->level_begin.push_back(L.begin);
+    F->level_maxF.push_back(L.maxF);
     F->level_maxK.push_back(L.maxK);
     F->level_maxP.push_back(L.maxP);
   }

@@ -117,7 +117,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, 
                      const int* hF, const int* hP);   // host: F and p of the level's fronts
 // Whether a level keeps explicit inverses of its pivot-block factors (few large
 // fronts) or solves with the LU in place (many small fronts).
-bool mf_level_uses_inverse(int nfronts, int maxP);
+bool mf_level_uses_inverse(int nfronts, int maxF, int maxP);
 
 // y = Q r for every instance of the batch (vectors in the batch layout).
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);
@@ -125,9 +125,9 @@ void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void* z,
               const void* x_in, void* x_out, int nrhs,
-              const int* level_begin, const int* level_maxK, const int* level_maxP,
-              const double* level_ent, const int* level_inv, int nlevels, void* partial,
-              int64_t partial_cap);
+              const int* level_begin, const int* level_maxF, const int* level_maxK,
+              const int* level_maxP, const double* level_ent, const int* level_inv, int nlevels,
+              void* partial, int64_t partial_cap);
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);

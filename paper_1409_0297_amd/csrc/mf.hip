@@ -392,118 +392,94 @@ __global__ void __launch_bounds__(64) laswp_kernel(MfDev mf, cplx_t<R>* __restri
 constexpr int kDB = 32;
 
 template <typename R>
-__global__ void __launch_bounds__(128) diag_lu_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
+__global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
                                                       cplx_t<R>* __restrict__ dinv, int f0, int k0, int nb) {
   using C = cplx_t<R>;
   const int fi = f0 + blockIdx.x;
-  const FrontDev f = mf.fronts[fi];
-  if (k0 >= f.p) return;
-  const int kb = min(nb, f.p - k0);
+  const FrontDev& f = mf.fronts[fi];
+  const int p = f.p;
+  if (k0 >= p) return;
+  const int kb = min(nb, p - k0);
   const int F = f.F;
   C* A = arena + f.off + (int64_t)k0 * F + k0;   // block origin, leading dimension F
+  // D: the block (row-major), overwritten by its L (unit, strictly lower) and U.
+  // X: Linv_kk in the strictly lower part (unit diagonal implied), Uinv_kk in
+  // the upper part with the diagonal.
   __shared__ C D[kDB][kDB + 1];
-  __shared__ C prow[kDB], jrow[kDB];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // Wave 0, lane i owns row i of the block in registers.
-  C a[kDB];
-  if (wave == 0) {
-#pragma unroll
-    for (int c = 0; c < kDB; ++c) a[c] = (lane < kb && c < kb) ? A[(int64_t)c * F + lane] : cmake<C>(0, 0);
-  }
-  // Column steps unrolled with literal indices so the row stays in registers.
-#define SPP_DIAG_LU_STEP(J) { \
-    constexpr int j = (J); \
-    const bool act = j < kb; /* uniform over the workgroup */ \
-    int piv = j; \
-    bool ok = true; \
-    if (act && wave == 0) { \
-      R v = (lane >= j && lane < kb) ? cabs2(a[j]) : R(-1); \
-      int bi = lane; \
-      for (int o = 32; o > 0; o >>= 1) { \
-        const R ov = __shfl_xor(v, o, 64); \
-        const int oi = __shfl_xor(bi, o, 64); \
-        if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; } \
-      } \
-      ok = v > R(0) && isfinite(v); \
-      piv = ok ? bi : j; \
-      if (lane == piv) \
-_Pragma("unroll") \
-        for (int c = 0; c < kDB; ++c) prow[c] = a[c]; \
-      if (lane == j) \
-_Pragma("unroll") \
-        for (int c = 0; c < kDB; ++c) jrow[c] = a[c]; \
-      if (lane == 0) { \
-        ipiv[f.perm + k0 + j] = k0 + piv; \
-        if (!ok) atomicCAS(mf.info, 0, fi + 1); \
-      } \
-    } \
-    __syncthreads(); \
-    if (act && wave == 0) { \
-      if (lane == j) { \
-_Pragma("unroll") \
-        for (int c = 0; c < kDB; ++c) a[c] = prow[c]; \
-      } else if (lane == piv) { \
-_Pragma("unroll") \
-        for (int c = 0; c < kDB; ++c) a[c] = jrow[c]; \
-      } \
-      if (lane > j && lane < kb) { \
-        const C pj = prow[j]; \
-        const C l = (cabs2(pj) > R(0)) ? cdiv(a[j], pj) : cmake<C>(0, 0); \
-        a[j] = l; \
-_Pragma("unroll") \
-        for (int c = j + 1; c < kDB; ++c) cfms(a[c], l, prow[c]); \
-      } \
-    } \
-    __syncthreads(); \
-  }
-  SPP_DIAG_LU_STEP(0) SPP_DIAG_LU_STEP(1) SPP_DIAG_LU_STEP(2) SPP_DIAG_LU_STEP(3) SPP_DIAG_LU_STEP(4) SPP_DIAG_LU_STEP(5) SPP_DIAG_LU_STEP(6) SPP_DIAG_LU_STEP(7) SPP_DIAG_LU_STEP(8) SPP_DIAG_LU_STEP(9) SPP_DIAG_LU_STEP(10) SPP_DIAG_LU_STEP(11) SPP_DIAG_LU_STEP(12) SPP_DIAG_LU_STEP(13) SPP_DIAG_LU_STEP(14) SPP_DIAG_LU_STEP(15) SPP_DIAG_LU_STEP(16) SPP_DIAG_LU_STEP(17) SPP_DIAG_LU_STEP(18) SPP_DIAG_LU_STEP(19) SPP_DIAG_LU_STEP(20) SPP_DIAG_LU_STEP(21) SPP_DIAG_LU_STEP(22) SPP_DIAG_LU_STEP(23) SPP_DIAG_LU_STEP(24) SPP_DIAG_LU_STEP(25) SPP_DIAG_LU_STEP(26) SPP_DIAG_LU_STEP(27) SPP_DIAG_LU_STEP(28) SPP_DIAG_LU_STEP(29) SPP_DIAG_LU_STEP(30) SPP_DIAG_LU_STEP(31)
-#undef SPP_DIAG_LU_STEP
-  if (wave == 0 && lane < kb) {
-#pragma unroll
-    for (int c = 0; c < kDB; ++c) {
-      D[lane][c] = a[c];
-      if (c < kb) A[(int64_t)c * F + lane] = a[c];
-    }
+  __shared__ C X[kDB][kDB + 1];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = tid; t < kDB * kDB; t += 256) {
+    const int c = t / kDB, i = t - c * kDB;
+    D[i][c] = (i < kb && c < kb) ? A[(int64_t)c * F + i] : cmake<C>(0, 0);
+    X[i][c] = cmake<C>(i == c ? 1 : 0, 0);
   }
   __syncthreads();
-  // Wave 0: Linv_kk, wave 1: Uinv_kk, lane = column.
+  // Thread layout of the rank-1 updates: row i = tid / 8, columns cg, cg + 8, ...
+  const int ri = tid >> 3, cg = tid & 7;
+  for (int j = 0; j < kb; ++j) {
+    if (wave == 0) {
+      R v = (lane >= j && lane < kb) ? cabs2(D[lane][j]) : R(-1);
+      int bi = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const R ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
+      }
+      const bool ok = v > R(0) && isfinite(v);
+      const int pv = ok ? bi : j;
+      if (pv != j && lane < kDB) {
+        const C t = D[j][lane];
+        D[j][lane] = D[pv][lane];
+        D[pv][lane] = t;
+      }
+      if (lane == 0) {
+        piv_s = pv;
+        ipiv[f.perm + k0 + j] = k0 + pv;
+        if (!ok) atomicCAS(mf.info, 0, fi + 1);
+      }
+    }
+    __syncthreads();
+    C l = cmake<C>(0, 0);
+    const bool row_active = ri > j && ri < kb;
+    if (row_active) {
+      const C pj = D[j][j];
+      l = (cabs2(pj) > R(0)) ? cdiv(D[ri][j], pj) : cmake<C>(0, 0);
+    }
+    __syncthreads();
+    if (row_active) {
+      if (cg == 0) D[ri][j] = l;
+      for (int c = j + 1 + cg; c < kb; c += 8) cfms(D[ri][c], l, D[j][c]);
+    }
+    __syncthreads();
+  }
+  // Inverses by column sweeps, both in the same kb steps: Linv with pivot
+  // column l = t (rows below it), Uinv with pivot row u = kb - 1 - t.
+  for (int t = 0; t < kb; ++t) {
+    const int u = kb - 1 - t;
+    if (tid < kDB) {
+      const int c = tid;
+      if (c >= u && c < kb) {
+        const C dd = D[u][u];
+        X[u][c] = (cabs2(dd) > R(0)) ? cdiv(X[u][c], dd) : cmake<C>(0, 0);
+      }
+    }
+    __syncthreads();
+    for (int c = cg; c < kb; c += 8) {
+      if (ri > t && ri < kb && c < t) cfms(X[ri][c], D[ri][t], X[t][c]);     // Linv rows below t (c < t)
+      if (ri > t && ri < kb && c == t) X[ri][c] = cmake<C>(-D[ri][t].x, -D[ri][t].y);   // unit diagonal of row t
+      if (ri < u && c >= u && c < kb) cfms(X[ri][c], D[ri][u], X[u][c]);      // Uinv rows above u
+    }
+    __syncthreads();
+  }
   C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
   C* Ui = Li + kDB * kDB;
-  const int c = lane;
-  if (c < kb) {
-    C x[kDB];
-    if (wave == 0) {
-#pragma unroll
-      for (int i = 0; i < kDB; ++i) {
-        if (i < c || i >= kb) x[i] = cmake<C>(0, 0);
-        else if (i == c) x[i] = cmake<C>(1, 0);
-        else {
-          C s = cmake<C>(0, 0);
-#pragma unroll
-          for (int l = 0; l < kDB; ++l)
-            if (l < i && l >= c) cfms(s, D[i][l], x[l]);
-          x[i] = s;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < kDB; ++i)
-        if (i < kb) Li[c * kDB + i] = x[i];
-    } else {
-#pragma unroll
-      for (int i = kDB - 1; i >= 0; --i) {
-        if (i > c || i >= kb) x[i] = cmake<C>(0, 0);
-        else {
-          C s = cmake<C>(i == c ? 1 : 0, 0);
-#pragma unroll
-          for (int l = 0; l < kDB; ++l)
-            if (l > i && l <= c) cfms(s, D[i][l], x[l]);
-          const C dd = D[i][i];
-          x[i] = (cabs2(dd) > R(0)) ? cdiv(s, dd) : cmake<C>(0, 0);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < kDB; ++i)
-        if (i < kb) Ui[c * kDB + i] = x[i];
+  for (int t = tid; t < kDB * kDB; t += 256) {
+    const int c = t / kDB, i = t - c * kDB;
+    if (i < kb && c < kb) {
+      A[(int64_t)c * F + i] = D[i][c];
+      Li[c * kDB + i] = (i > c) ? X[i][c] : cmake<C>(i == c ? 1 : 0, 0);
+      Ui[c * kDB + i] = (i <= c) ? X[i][c] : cmake<C>(0, 0);
     }
   }
 }
@@ -658,17 +634,31 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
   __shared__ C Bs[kBK][kBN + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  V rr[2][2], ii[2][2], ri[2][2], ir[2][2];
+  // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
+  // im = sum (ar bi + ai br).  Update modes start from C and accumulate with A
+  // negated (stored negated in LDS), so C -= A B needs no extra pass.
+  V re[2][2], im[2][2];
+  const R sgn = assign ? R(1) : R(-1);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) { rr[a][b] = V{}; ii[a][b] = V{}; ri[a][b] = V{}; ir[a][b] = V{}; }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
+        const int col = n0 + wn + 16 * b + (lane & 15);
+        C c0 = cmake<C>(0, 0);
+        if (!assign && row < m && col < n) c0 = Cp[(int64_t)col * ldc + row];
+        re[a][b][r] = c0.x;
+        im[a][b][r] = c0.y;
+      }
 
   for (int kk0 = 0; kk0 < k; kk0 += kBK) {
     for (int e = threadIdx.x; e < kBM * kBK; e += 256) {
       const int row = e % kBM, kk = e / kBM;
       const int gr = m0 + row, gk = kk0 + kk;
-      As[kk][row] = (gr < m && gk < k) ? Ap[(int64_t)gk * lda + gr] : cmake<C>(0, 0);
+      const C v = (gr < m && gk < k) ? Ap[(int64_t)gk * lda + gr] : cmake<C>(0, 0);
+      As[kk][row] = cmake<C>(sgn * v.x, sgn * v.y);
     }
     for (int e = threadIdx.x; e < kBK * kBN; e += 256) {
       const int kk = e % kBK, col = e / kBK;
@@ -687,10 +677,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          rr[a][b] = mfma16(av[a].x, bv[b].x, rr[a][b]);
-          ii[a][b] = mfma16(av[a].y, bv[b].y, ii[a][b]);
-          ri[a][b] = mfma16(av[a].x, bv[b].y, ri[a][b]);
-          ir[a][b] = mfma16(av[a].y, bv[b].x, ir[a][b]);
+          re[a][b] = mfma16(av[a].x, bv[b].x, re[a][b]);
+          re[a][b] = mfma16(-av[a].y, bv[b].y, re[a][b]);
+          im[a][b] = mfma16(av[a].x, bv[b].y, im[a][b]);
+          im[a][b] = mfma16(av[a].y, bv[b].x, im[a][b]);
         }
     }
     __syncthreads();
@@ -703,16 +693,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
         const int col = n0 + wn + 16 * b + (lane & 15);
-        if (row < m && col < n) {
-          C& c = Cp[(int64_t)col * ldc + row];
-          if (assign) {
-            c.x = rr[a][b][r] - ii[a][b][r];
-            c.y = ri[a][b][r] + ir[a][b][r];
-          } else {
-            c.x -= rr[a][b][r] - ii[a][b][r];
-            c.y -= ri[a][b][r] + ir[a][b][r];
-          }
-        }
+        if (row < m && col < n) Cp[(int64_t)col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
       }
 }
 
@@ -858,24 +839,35 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmake<C>(0, 0);
   const bool live = row < nrows;
-  for (int j = jlo + grp; j < jhi; j += 4) {
-    C a;
-    bool use;
-    if (mode == 0) { use = live && j < row; a = use ? A[(int64_t)j * F + row] : cmake<C>(0, 0); }
-    else if (mode == 1) { use = live; a = use ? A[(int64_t)j * F + p + row] : cmake<C>(0, 0); }
-    else if (mode == 2) { use = live; a = use ? A[(int64_t)(p + j) * F + row] : cmake<C>(0, 0); }
-    else { use = live && j >= row; a = use ? A[(int64_t)j * F + row] : cmake<C>(0, 0); }
-    if (!use) continue;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (r0 + r >= nrhs) break;
-      C v;
-      if (mode == 0) v = w[perm[j] * nrhs + r0 + r];
-      else if (mode == 1) v = z[j * nrhs + r0 + r];
-      else if (mode == 2) v = xo[(int64_t)(r0 + r) * NI + idx[p + j]];
-      else v = z[j * nrhs + r0 + r];
-      cfma(acc[r], a, v);
+  // Matrix column j of this product starts at A + coff + j * F (row offset
+  // included); the vector entries of a tile of kVT columns are staged in LDS
+  // first (their gathers go through perm / idx), so the main loop only streams
+  // the matrix, several loads in flight per lane.
+  const int64_t coff = (mode == 1) ? p + row : (mode == 2) ? (int64_t)p * F + row : row;
+  constexpr int kVT = 256;
+  __shared__ C vs[kVT][NR];
+  for (int jt = jlo; jt < jhi; jt += kVT) {
+    const int jn = min(kVT, jhi - jt);
+    for (int t = threadIdx.x; t < jn * NR; t += 256) {
+      const int jj = t / NR, r = t - jj * NR, j = jt + jj;
+      C v = cmake<C>(0, 0);
+      if (r0 + r < nrhs) {
+        if (mode == 0) v = w[perm[j] * nrhs + r0 + r];
+        else if (mode == 2) v = xo[(int64_t)(r0 + r) * NI + idx[p + j]];
+        else v = z[j * nrhs + r0 + r];
+      }
+      vs[jj][r] = v;
     }
+    __syncthreads();
+#pragma unroll 8
+    for (int jj = grp; jj < jn; jj += 4) {
+      const int j = jt + jj;
+      const bool use = live && (mode == 0 ? j < row : mode == 3 ? j >= row : true);
+      const C a = use ? A[coff + (int64_t)j * F] : cmake<C>(0, 0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfma(acc[r], a, vs[jj][r]);
+    }
+    __syncthreads();
   }
   __shared__ C red[4][64][NR];
 #pragma unroll
@@ -903,36 +895,95 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   }
 }
 
-// In-workgroup triangular solves with the pivot block kept in LU form, for
-// levels with many small fronts (one workgroup per front, 64-row blocks: the
-// diagonal block is solved by one wave with shuffles, the rows beyond it are
-// updated by the whole workgroup; the vector lives in LDS).
-//   fwd: z = L11^{-1} (P w_piv)          bwd: x(piv) = U11^{-1} z
+// Whole-front substitution steps for levels with many small fronts (one
+// workgroup per front, vectors in LDS, the pivot block kept in LU form).
+//   forward:  w = gather(x, children's boundary updates); y = L11^{-1} P w_piv;
+//             w_bnd -= L21 y; writes z = y and the updated w_bnd.
+//   backward: y = z - U12 x_bnd; x_piv = U11^{-1} y.
+// The triangular solves go in 32-row blocks: one wave solves the diagonal
+// block with shuffles, the whole workgroup updates the rows beyond it.
+constexpr int kTriBS = 32;
+
+// acc[r] (r < NR) for rows [row0, row0 + 64) of an F-strided column-major
+// matrix M (rows of the product, `cols` columns) times the LDS vector v
+// (cols x NR): four groups of 64 lanes split the columns, then reduce.
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) fwd_tri_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ W,
-                                                      cplx_t<R>* __restrict__ Z, int nrhs, int r0, int f0) {
+__device__ inline void wg_matvec_rows(const cplx_t<R>* __restrict__ M, int ld, int nrows, int row0, int cols,
+                                      const cplx_t<R>* v, cplx_t<R> (*red)[64][NR], cplx_t<R>* out) {
   using C = cplx_t<R>;
-  constexpr int BS = 32;
-  const FrontDev f = mf.fronts[f0 + blockIdx.x];
-  const int F = f.F, p = f.p;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int row = row0 + lane;
+  const bool live = row < nrows;
+  C acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = cmake<C>(0, 0);
+#pragma unroll 8
+  for (int j = grp; j < cols; j += 4) {
+    const C a = live ? M[(int64_t)j * ld + row] : cmake<C>(0, 0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cfma(acc[r], a, v[j * NR + r]);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[grp][lane][r] = acc[r];
+  __syncthreads();
+  if (grp == 0 && live)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      out[r] = cadd(cadd(red[0][lane][r], red[1][lane][r]), cadd(red[2][lane][r], red[3][lane][r]));
+  __syncthreads();
+}
+
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) fwd_front_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                        cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z,
+                                                        const cplx_t<R>* __restrict__ x, int nrhs, int r0, int f0) {
+  using C = cplx_t<R>;
+  constexpr int BS = kTriBS;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.x];
+  const int F = f.F, p = f.p, K = F - p;
   const C* A = arena + f.off;
   const int* perm = mf.perm + f.perm;
-  const C* w = W + f.voff * nrhs;
+  const int* idx = mf.idx + f.idx;
+  const InstDev& I = mf.inst[f.inst];
+  const C* xi = x + I.Noff * nrhs;
+  C* w = W + f.voff * nrhs;
   C* z = Z + f.voff * nrhs;
   const int nr = min(NR, nrhs - r0);
   __shared__ C D[BS][BS + 1];
+  __shared__ C red[4][64][NR];
   extern __shared__ unsigned char smem[];
-  C* y = reinterpret_cast<C*>(smem);          // p x NR
+  C* wv = reinterpret_cast<C*>(smem);   // F x NR: the front vector
+  C* y = wv + F * NR;                   // p x NR: permuted pivot part, solved in place
+  for (int t = threadIdx.x; t < F * NR; t += blockDim.x) {
+    const int i = t / NR, r = t - i * NR;
+    wv[t] = (i < p && r < nr) ? xi[(int64_t)(r0 + r) * I.N + idx[i]] : cmake<C>(0, 0);
+  }
+  __syncthreads();
+  for (int c = 0; c < f.nchild; ++c) {
+    const FrontDev& ch = mf.fronts[f.child[c]];
+    const int Kc = ch.F - ch.p;
+    const int* map = mf.map + ch.map;
+    const C* wc = W + (ch.voff + ch.p) * nrhs;
+    for (int t = threadIdx.x; t < Kc * NR; t += blockDim.x) {
+      const int i = t / NR, r = t - i * NR;
+      if (r < nr) {
+        C& d = wv[map[i] * NR + r];
+        d = cadd(d, wc[(int64_t)i * nrhs + r0 + r]);
+      }
+    }
+    __syncthreads();
+  }
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
-    y[t] = (r < nr) ? w[perm[i] * nrhs + r0 + r] : cmake<C>(0, 0);
+    y[t] = wv[perm[i] * NR + r];
   }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   for (int b0 = 0; b0 < p; b0 += BS) {
     const int bs = min(BS, p - b0);
     for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
       const int jj = t / BS, i = t - jj * BS;
-      D[i][jj] = (i < bs && jj < bs) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
+      D[i][jj] = (i < bs && jj < bs && i > jj) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -958,6 +1009,7 @@ __global__ void __launch_bounds__(256) fwd_tri_kernel(MfDev mf, const cplx_t<R>*
       C acc[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
+#pragma unroll 8
       for (int jj = 0; jj < bs; ++jj) {
         const C l = A[(int64_t)(b0 + jj) * F + i];
 #pragma unroll
@@ -968,36 +1020,75 @@ __global__ void __launch_bounds__(256) fwd_tri_kernel(MfDev mf, const cplx_t<R>*
     }
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
+  // w_bnd -= L21 y
+  for (int row0 = 0; row0 < K; row0 += 64) {
+    C s[NR];
+    wg_matvec_rows<R, NR>(A + p, F, K, row0, p, y, red, s);
+    const int row = row0 + lane;
+    if (threadIdx.x < 64 && row < K)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        C& d = wv[(p + row) * NR + r];
+        d = csub(d, s[r]);
+      }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < F * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
-    if (r < nr) z[i * nrhs + r0 + r] = y[t];
+    if (r >= nr) continue;
+    if (i < p) z[i * nrhs + r0 + r] = y[t];
+    else w[i * nrhs + r0 + r] = wv[t];
   }
 }
 
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) bwd_tri_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ Z,
-                                                      cplx_t<R>* __restrict__ xout, int nrhs, int r0, int f0) {
+__global__ void __launch_bounds__(256) bwd_front_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                        const cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout,
+                                                        int nrhs, int r0, int f0) {
   using C = cplx_t<R>;
-  constexpr int BS = 32;
-  const FrontDev f = mf.fronts[f0 + blockIdx.x];
-  const int F = f.F, p = f.p;
+  constexpr int BS = kTriBS;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.x];
+  const int F = f.F, p = f.p, K = F - p;
   const C* A = arena + f.off;
   const int* idx = mf.idx + f.idx;
   const C* z = Z + f.voff * nrhs;
+  const InstDev& I = mf.inst[f.inst];
+  C* xo = xout + I.Noff * nrhs;
   const int nr = min(NR, nrhs - r0);
   __shared__ C D[BS][BS + 1];
   extern __shared__ unsigned char smem[];
-  C* y = reinterpret_cast<C*>(smem);
+  C* y = reinterpret_cast<C*>(smem);    // p x NR
+  C* xb = y + p * NR;                   // K x NR: solution at the boundary points
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
     y[t] = (r < nr) ? z[i * nrhs + r0 + r] : cmake<C>(0, 0);
   }
+  for (int t = threadIdx.x; t < K * NR; t += blockDim.x) {
+    const int j = t / NR, r = t - j * NR;
+    xb[t] = (r < nr) ? xo[(int64_t)(r0 + r) * I.N + idx[p + j]] : cmake<C>(0, 0);
+  }
+  __syncthreads();
+  // y -= U12 x_bnd
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    C acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
+#pragma unroll 8
+    for (int j = 0; j < K; ++j) {
+      const C u = A[(int64_t)(p + j) * F + i];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfms(acc[r], u, xb[j * NR + r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) y[i * NR + r] = acc[r];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   for (int b0 = ((p - 1) / BS) * BS; b0 >= 0; b0 -= BS) {
     const int bs = min(BS, p - b0);
     for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
       const int jj = t / BS, i = t - jj * BS;
-      D[i][jj] = (i < bs && jj < bs) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
+      D[i][jj] = (i < bs && jj < bs && i <= jj) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -1025,6 +1116,7 @@ __global__ void __launch_bounds__(256) bwd_tri_kernel(MfDev mf, const cplx_t<R>*
       C acc[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
+#pragma unroll 8
       for (int jj = 0; jj < bs; ++jj) {
         const C u = A[(int64_t)(b0 + jj) * F + i];
 #pragma unroll
@@ -1035,8 +1127,6 @@ __global__ void __launch_bounds__(256) bwd_tri_kernel(MfDev mf, const cplx_t<R>*
     }
     __syncthreads();
   }
-  const InstDev& I = mf.inst[f.inst];
-  C* xo = xout + I.Noff * nrhs;
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
     if (r < nr) xo[(int64_t)(r0 + r) * I.N + idx[i]] = y[t];
@@ -1118,7 +1208,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       else if (maxF <= 4096) panel2_kernel<R, 1024, 4><<<nf, 1024, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
       else panel_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB, 0);
     } else {
-      diag_lu_kernel<R><<<nf, 128, 0, st>>>(mf, arena, mf.ipiv, dinv, f0, k0, kNB);
+      diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, dinv, f0, k0, kNB);
     }
     SPP_LAUNCH_CHECK();
     timer_end(KC_PANEL, st, 0.0, 0.0);
@@ -1174,11 +1264,11 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   SPP_LAUNCH_CHECK();
 }
 
-bool mf_level_uses_inverse(int nfronts, int maxP) {
+bool mf_level_uses_inverse(int nfronts, int maxF, int maxP) {
   // Many small fronts: one workgroup per front solves with the LU in place
-  // (its vector block, maxP x 4 complex values, must fit in LDS).
+  // (its vectors, (F + p) x 4 complex128 values, stay within 64 KB of LDS).
   // Few large fronts: explicit inverses so every row of every front runs in parallel.
-  return !(nfronts >= 32 && maxP <= 512);
+  return !(nfronts >= 32 && maxP <= 512 && maxF + maxP <= 1024);
 }
 
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
@@ -1194,8 +1284,9 @@ void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int 
 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
-              void* x_out, int nrhs, const int* level_begin, const int* level_maxK, const int* level_maxP,
-              const double* level_ent, const int* level_inv, int nlevels, void* partial_v, int64_t partial_cap) {
+              void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxK,
+              const int* level_maxP, const double* level_ent, const int* level_inv, int nlevels, void* partial_v,
+              int64_t partial_cap) {
   using C = cplx_t<R>;
   const C* arena = static_cast<const C*>(arena_v);
   C* W = static_cast<C*>(w_v);
@@ -1235,19 +1326,21 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     }
     timer_end(KC_GEMV, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
   };
-  auto tri = [&](int f0, int nf, int maxP, bool fwd, double ent) {
+  // Whole-front kernels of the levels solved with the LU in place.
+  auto front = [&](int f0, int nf, int maxF, int maxP, int maxK, bool fwd, double ent) {
     const double passes = (nrhs / 4) + (nrhs % 4);
     timer_begin(KC_TRI, st);
     int r0 = 0;
     while (r0 < nrhs) {
       const int nr = (nrhs - r0 >= 4) ? 4 : 1;
-      const size_t lds = sizeof(C) * (size_t)maxP * nr;
       if (fwd) {
-        if (nr == 4) fwd_tri_kernel<R, 4><<<nf, 256, lds, st>>>(mf, arena, W, Z, nrhs, r0, f0);
-        else fwd_tri_kernel<R, 1><<<nf, 256, lds, st>>>(mf, arena, W, Z, nrhs, r0, f0);
+        const size_t lds = sizeof(C) * (size_t)(maxF + maxP) * nr;
+        if (nr == 4) fwd_front_kernel<R, 4><<<nf, 256, lds, st>>>(mf, arena, W, Z, xin, nrhs, r0, f0);
+        else fwd_front_kernel<R, 1><<<nf, 256, lds, st>>>(mf, arena, W, Z, xin, nrhs, r0, f0);
       } else {
-        if (nr == 4) bwd_tri_kernel<R, 4><<<nf, 256, lds, st>>>(mf, arena, Z, xout, nrhs, r0, f0);
-        else bwd_tri_kernel<R, 1><<<nf, 256, lds, st>>>(mf, arena, Z, xout, nrhs, r0, f0);
+        const size_t lds = sizeof(C) * (size_t)(maxP + maxK) * nr;
+        if (nr == 4) bwd_front_kernel<R, 4><<<nf, 256, lds, st>>>(mf, arena, Z, xout, nrhs, r0, f0);
+        else bwd_front_kernel<R, 1><<<nf, 256, lds, st>>>(mf, arena, Z, xout, nrhs, r0, f0);
       }
       SPP_LAUNCH_CHECK();
       r0 += nr;
@@ -1259,19 +1352,25 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
+    if (!level_inv[l]) {
+      front(f0, nf, level_maxF[l], mP, mK, true, e[0] + e[2]);
+      continue;
+    }
     fwd_gather_kernel<R><<<nf, 256, 0, st>>>(mf, W, xin, nrhs, f0);
     SPP_LAUNCH_CHECK();
-    if (level_inv[l]) gemv(f0, nf, mP, mP, 0, e[0]);
-    else tri(f0, nf, mP, true, e[0]);
+    gemv(f0, nf, mP, mP, 0, e[0]);
     if (mK > 0) gemv(f0, nf, mK, mP, 1, e[2]);
   }
   for (int l = nlevels - 1; l >= 0; --l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
+    if (!level_inv[l]) {
+      front(f0, nf, level_maxF[l], mP, mK, false, e[1] + e[2]);
+      continue;
+    }
     if (mK > 0) gemv(f0, nf, mP, mK, 2, e[2]);
-    if (level_inv[l]) gemv(f0, nf, mP, mP, 3, e[1]);
-    else tri(f0, nf, mP, false, e[1]);
+    gemv(f0, nf, mP, mP, 3, e[1]);
   }
 }
 
@@ -1286,9 +1385,11 @@ template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, v
 template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, int, int, int, int, int, int, int, bool,
                                      bool, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
-                               const int*, const int*, const int*, const double*, const int*, int, void*, int64_t);
+                               const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
+                               int64_t);
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
-                              const int*, const int*, const int*, const double*, const int*, int, void*, int64_t);
+                              const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
+                              int64_t);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
 
