@@ -576,6 +576,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
 
   F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
   void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);
+  void* tbuf = F->dalloc<char>((size_t)(F->pd->xwork_elems / 2) * F->csize);
   const bool partial_pivoting = (F->opt.flags & SPP_F_PARTIAL_PIVOTING) != 0;
   void* dinv = F->dalloc<char>((size_t)2 * 32 * 32 * F->pd->dblk_total * F->csize);
   SPP_HIP(hipStreamSynchronize(st));
@@ -587,10 +588,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     const int* hF = F->pd->level_F[l].data();
     const int* hP = F->pd->level_p[l].data();
     if (F->opt.prec == SPP_C128)
-      mf_factor_level<double>(st, mf, F->arena, xwork, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
+      mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
                               L.max_children, F->level_inv[l] != 0, partial_pivoting, hF, hP);
     else
-      mf_factor_level<float>(st, mf, F->arena, xwork, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
+      mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
                              L.max_children, F->level_inv[l] != 0, partial_pivoting, hF, hP);
   }
   int hinfo[16];
@@ -598,6 +599,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   SPP_HIP(hipStreamSynchronize(st));
   const double tf1 = now_ms();
   F->dfree(xwork);
+  F->dfree(tbuf);
   F->dfree(dinv);
   F->dfree(swork);
   for (int t = 0; t < 8; ++t)

@@ -111,7 +111,7 @@ struct MfDev {
 };
 
 template <typename R>
-void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* dinv,
+void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* tbuf, void* dinv,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
                      int max_children, bool invert, bool partial_pivoting,
                      const int* hF, const int* hP);   // host: F and p of the level's fronts

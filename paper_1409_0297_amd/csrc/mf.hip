@@ -384,12 +384,30 @@ __global__ void __launch_bounds__(64) laswp_kernel(MfDev mf, cplx_t<R>* __restri
 // ------------------------------------------------------------------ block-local pivoting LU
 // Default factorisation step (block-local pivoting): the pivot of column j is
 // the largest-modulus entry among the rows of the current kb x kb diagonal
-// block (kb <= 32), so the whole pivot search and elimination of a step runs
-// in LDS inside one wavefront.  The block's L and U are written back, their
-// inverses Linv_kk, Uinv_kk (kb x kb, column-major) go to dinv, and the other
-// two products of the step become dense, dependency-free multiplications:
-// L21 = A21 Uinv_kk (l21_kernel) and U12 = Linv_kk P A12 (rowblock_kernel).
+// block (kb <= 32), so the pivot search and elimination of a step stay in one
+// workgroup's LDS.  The block's L and U are written back, their inverses
+// Linv_kk, Uinv_kk (kb x kb, column-major) go to dinv, and the other two
+// products of the step become dense, dependency-free MFMA multiplications:
+// L21 = A21 Uinv_kk and U12 = Linv_kk P A12 (gemm_kernel modes 4 and 3).
 constexpr int kDB = 32;
+
+// Pivot search key: for v >= 0 the IEEE bits order like integers; the low 6
+// bits carry 63 - row, so the largest key is the largest modulus, ties to
+// the lowest row.
+template <typename R> __device__ inline unsigned long long piv_key(R v, int row);
+template <> __device__ inline unsigned long long piv_key<double>(double v, int row) {
+  return ((unsigned long long)__double_as_longlong(v) & ~0x3FULL) | (unsigned long long)(63 - row);
+}
+template <> __device__ inline unsigned long long piv_key<float>(float v, int row) {
+  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(63 - row);
+}
+template <typename R> __device__ inline R piv_key_value(unsigned long long k);
+template <> __device__ inline double piv_key_value<double>(unsigned long long k) {
+  return __longlong_as_double((long long)(k & ~0x3FULL));
+}
+template <> __device__ inline float piv_key_value<float>(unsigned long long k) {
+  return __uint_as_float((unsigned)(k >> 32));
+}
 
 template <typename R>
 __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
@@ -402,73 +420,122 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
   const int kb = min(nb, p - k0);
   const int F = f.F;
   C* A = arena + f.off + (int64_t)k0 * F + k0;   // block origin, leading dimension F
-  // D: the block (row-major), overwritten by its L (unit, strictly lower) and U.
-  // X: Linv_kk in the strictly lower part (unit diagonal implied), Uinv_kk in
-  // the upper part with the diagonal.
-  __shared__ C D[kDB][kDB + 1];
-  __shared__ C X[kDB][kDB + 1];
-  __shared__ int piv_s;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // The block is padded to 32 x 32 with the identity so that every step is
+  // uniform.  Rows stay where they are (physical order); the pivot chosen at
+  // step j is recorded in rsel[j] and the LU is written back in pivot order.
+  __shared__ C D[kDB][kDB + 1];    // working rows; their U part ends here; later the inverses
+  __shared__ C Lm[kDB][kDB + 1];   // multipliers of each physical row; later products
+  __shared__ C X[kDB][kDB + 1];    // the LU in pivot order
+  __shared__ unsigned long long keys[kDB + 1];
+  __shared__ int rsel[kDB];
+  const int tid = threadIdx.x;
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
-    D[i][c] = (i < kb && c < kb) ? A[(int64_t)c * F + i] : cmake<C>(0, 0);
-    X[i][c] = cmake<C>(i == c ? 1 : 0, 0);
+    D[i][c] = (i < kb && c < kb) ? A[(int64_t)c * F + i] : cmake<C>(i == c ? 1 : 0, 0);
+    Lm[i][c] = cmake<C>(0, 0);
+  }
+  if (tid <= kDB) keys[tid] = 0;
+  __syncthreads();
+  if (tid < kDB) atomicMax(&keys[0], piv_key<R>(cabs2(D[tid][0]), tid));
+  __syncthreads();
+  // One barrier per step: the pivot search of column j + 1 is fused into the
+  // update of step j (the thread updating that column posts its row's key).
+  const int ri = tid >> 3, cg = tid & 7;
+  unsigned done = 0;
+  for (int j = 0; j < kDB; ++j) {
+    const unsigned long long key = keys[j];
+    const int r = 63 - (int)(key & 63);
+    if (tid == 0) {
+      rsel[j] = r;
+      const R best = piv_key_value<R>(key);
+      if (j < kb && !(best > R(0) && isfinite(best))) atomicCAS(mf.info, 0, fi + 1);
+    }
+    done |= 1u << r;
+    if (!((done >> ri) & 1u)) {
+      const C pv = D[r][j];
+      const C l = cabs2(pv) > R(0) ? cdiv(D[ri][j], pv) : cmake<C>(0, 0);
+      if (cg == 0) Lm[ri][j] = l;
+      for (int c = j + 1 + cg; c < kDB; c += 8) {
+        C& d = D[ri][c];
+        cfms(d, l, D[r][c]);
+        if (c == j + 1) atomicMax(&keys[j + 1], piv_key<R>(cabs2(d), ri));
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < kDB * kDB; t += 256) {
+    const int c = t / kDB, k = t - c * kDB;
+    const int pr = rsel[k];
+    X[k][c] = (c >= k) ? D[pr][c] : Lm[pr][c];
   }
   __syncthreads();
-  // Thread layout of the rank-1 updates: row i = tid / 8, columns cg, cg + 8, ...
-  const int ri = tid >> 3, cg = tid & 7;
-  for (int j = 0; j < kb; ++j) {
-    if (wave == 0) {
-      R v = (lane >= j && lane < kb) ? cabs2(D[lane][j]) : R(-1);
-      int bi = lane;
-      for (int o = 32; o > 0; o >>= 1) {
-        const R ov = __shfl_xor(v, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ov > v || (ov == v && oi < bi)) { v = ov; bi = oi; }
-      }
-      const bool ok = v > R(0) && isfinite(v);
-      const int pv = ok ? bi : j;
-      if (pv != j && lane < kDB) {
-        const C t = D[j][lane];
-        D[j][lane] = D[pv][lane];
-        D[pv][lane] = t;
-      }
-      if (lane == 0) {
-        piv_s = pv;
-        ipiv[f.perm + k0 + j] = k0 + pv;
-        if (!ok) atomicCAS(mf.info, 0, fi + 1);
-      }
+  if (tid == 0) {
+    // The same permutation as a LAPACK-style interchange sequence.
+    int cur[kDB], where[kDB];
+    for (int i = 0; i < kDB; ++i) { cur[i] = i; where[i] = i; }
+    for (int j = 0; j < kb; ++j) {
+      const int q = where[rsel[j]];
+      ipiv[f.perm + k0 + j] = k0 + q;
+      const int a = cur[j], b = cur[q];
+      cur[j] = b; cur[q] = a; where[b] = j; where[a] = q;
     }
-    __syncthreads();
-    C l = cmake<C>(0, 0);
-    const bool row_active = ri > j && ri < kb;
-    if (row_active) {
-      const C pj = D[j][j];
-      l = (cabs2(pj) > R(0)) ? cdiv(D[ri][j], pj) : cmake<C>(0, 0);
-    }
-    __syncthreads();
-    if (row_active) {
-      if (cg == 0) D[ri][j] = l;
-      for (int c = j + 1 + cg; c < kb; c += 8) cfms(D[ri][c], l, D[j][c]);
-    }
-    __syncthreads();
   }
-  // Inverses by column sweeps, both in the same kb steps: Linv with pivot
-  // column l = t (rows below it), Uinv with pivot row u = kb - 1 - t.
-  for (int t = 0; t < kb; ++t) {
-    const int u = kb - 1 - t;
-    if (tid < kDB) {
-      const int c = tid;
-      if (c >= u && c < kb) {
-        const C dd = D[u][u];
-        X[u][c] = (cabs2(dd) > R(0)) ? cdiv(X[u][c], dd) : cmake<C>(0, 0);
+  for (int t = tid; t < kDB * kDB; t += 256) {
+    const int c = t / kDB, i = t - c * kDB;
+    if (i < kb && c < kb) A[(int64_t)c * F + i] = X[i][c];
+    D[i][c] = cmake<C>(i == c ? 1 : 0, 0);
+  }
+  __syncthreads();
+  // Inverses into D (strictly lower: Linv with unit diagonal implied; upper
+  // with the diagonal: Uinv).  First the four 8 x 8 diagonal blocks of each
+  // triangle by column sweeps, then two doubling stages:
+  //   [A 0; C B]^{-1} has lower-left block -B^{-1} (C A^{-1}),
+  //   [A C; 0 B]^{-1} has upper-right block -A^{-1} (C B^{-1}).
+  {
+    const int blk = tid >> 6, i = (tid >> 3) & 7, c = tid & 7;
+    const int o = 8 * blk;
+    for (int t = 0; t < 8; ++t) {
+      const int u = 7 - t;
+      if (i == u && c >= u) {
+        const C dd = X[o + u][o + u];
+        D[o + u][o + c] = cabs2(dd) > R(0) ? cdiv(D[o + u][o + c], dd) : cmake<C>(0, 0);
+      }
+      __syncthreads();
+      if (i > t && c < t) cfms(D[o + i][o + c], X[o + i][o + t], D[o + t][o + c]);
+      if (i > t && c == t) D[o + i][o + c] = cmake<C>(-X[o + i][o + t].x, -X[o + i][o + t].y);
+      if (i < u && c >= u) cfms(D[o + i][o + c], X[o + i][o + u], D[o + u][o + c]);
+      __syncthreads();
+    }
+  }
+  for (int h = 8; h < kDB; h *= 2) {
+    const int npair = kDB / (2 * h), per = npair * h * h, items = 2 * per;
+    // products C A^{-1} (lower pairs) and C B^{-1} (upper pairs) into Lm
+    for (int w = tid; w < items; w += 256) {
+      const int which = w / per, rem = w - which * per;
+      const int pr = rem / (h * h), e = rem - pr * h * h;
+      const int a = e / h, b = e - a * h, o = pr * 2 * h;
+      C acc = cmake<C>(0, 0);
+      if (which == 0) {
+        for (int k = b; k < h; ++k) cfma(acc, X[o + h + a][o + k], k == b ? cmake<C>(1, 0) : D[o + k][o + b]);
+        Lm[o + h + a][o + b] = acc;
+      } else {
+        for (int k = 0; k <= b; ++k) cfma(acc, X[o + a][o + h + k], D[o + h + k][o + h + b]);
+        Lm[o + a][o + h + b] = acc;
       }
     }
     __syncthreads();
-    for (int c = cg; c < kb; c += 8) {
-      if (ri > t && ri < kb && c < t) cfms(X[ri][c], D[ri][t], X[t][c]);     // Linv rows below t (c < t)
-      if (ri > t && ri < kb && c == t) X[ri][c] = cmake<C>(-D[ri][t].x, -D[ri][t].y);   // unit diagonal of row t
-      if (ri < u && c >= u && c < kb) cfms(X[ri][c], D[ri][u], X[u][c]);      // Uinv rows above u
+    for (int w = tid; w < items; w += 256) {
+      const int which = w / per, rem = w - which * per;
+      const int pr = rem / (h * h), e = rem - pr * h * h;
+      const int a = e / h, b = e - a * h, o = pr * 2 * h;
+      C acc = cmake<C>(0, 0);
+      if (which == 0) {
+        for (int k = 0; k <= a; ++k) cfms(acc, k == a ? cmake<C>(1, 0) : D[o + h + a][o + h + k], Lm[o + h + k][o + b]);
+        D[o + h + a][o + b] = acc;
+      } else {
+        for (int k = a; k < h; ++k) cfms(acc, D[o + a][o + k], Lm[o + k][o + h + b]);
+        D[o + a][o + h + b] = acc;
+      }
     }
     __syncthreads();
   }
@@ -477,9 +544,8 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
     if (i < kb && c < kb) {
-      A[(int64_t)c * F + i] = D[i][c];
-      Li[c * kDB + i] = (i > c) ? X[i][c] : cmake<C>(i == c ? 1 : 0, 0);
-      Ui[c * kDB + i] = (i <= c) ? X[i][c] : cmake<C>(0, 0);
+      Li[c * kDB + i] = (i > c) ? D[i][c] : cmake<C>(i == c ? 1 : 0, 0);
+      Ui[c * kDB + i] = (i <= c) ? D[i][c] : cmake<C>(0, 0);
     }
   }
 }
@@ -567,12 +633,85 @@ __global__ void __launch_bounds__(256) trsm_kernel(MfDev mf, cplx_t<R>* __restri
 // mode 2: U inverse update   XU[0:k0, k0:p]       -= U[0:k0, k0:k0+kb]    XU[k0:k0+kb, k0:p]
 constexpr int kBM = 64, kBN = 64, kBK = 16;
 
+// One 64 x 64 tile (rows m0.., columns n0..) of C = from_c ? C + sgn A B : sgn A B,
+// complex column-major operands, k restricted to [kbeg, kend).
+template <typename R>
+__device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, const cplx_t<R>* __restrict__ Bp, int ldb,
+                                 cplx_t<R>* __restrict__ Cp, int ldc, int m, int n, int k, int m0, int n0, bool from_c,
+                                 R sgn, int kbeg, int kend) {
+  using C = cplx_t<R>;
+  using V = typename Acc<R>::type;
+  __shared__ C As[kBK][kBM + 1];
+  __shared__ C Bs[kBK][kBN + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
+  // im = sum (ar bi + ai br).  Updates start from C and take A scaled by sgn
+  // when it is staged in LDS, so C -= A B needs no extra pass.
+  V re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
+        const int col = n0 + wn + 16 * b + (lane & 15);
+        C c0 = cmake<C>(0, 0);
+        if (from_c && row < m && col < n) c0 = Cp[(int64_t)col * ldc + row];
+        re[a][b][r] = c0.x;
+        im[a][b][r] = c0.y;
+      }
+  kend = min(kend, k);
+  for (int kk0 = kbeg; kk0 < kend; kk0 += kBK) {
+    for (int e = threadIdx.x; e < kBM * kBK; e += 256) {
+      const int row = e % kBM, kk = e / kBM;
+      const int gr = m0 + row, gk = kk0 + kk;
+      const C v = (gr < m && gk < kend) ? Ap[(int64_t)gk * lda + gr] : cmake<C>(0, 0);
+      As[kk][row] = cmake<C>(sgn * v.x, sgn * v.y);
+    }
+    for (int e = threadIdx.x; e < kBK * kBN; e += 256) {
+      const int kk = e % kBK, col = e / kBK;
+      const int gk = kk0 + kk, gc = n0 + col;
+      Bs[kk][col] = (gk < kend && gc < n) ? Bp[(int64_t)gc * ldb + gk] : cmake<C>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 4) {
+      C av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wm + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wn + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          re[a][b] = mfma16(av[a].x, bv[b].x, re[a][b]);
+          re[a][b] = mfma16(-av[a].y, bv[b].y, re[a][b]);
+          im[a][b] = mfma16(av[a].x, bv[b].y, im[a][b]);
+          im[a][b] = mfma16(av[a].y, bv[b].x, im[a][b]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
+        const int col = n0 + wn + 16 * b + (lane & 15);
+        if (row < m && col < n) Cp[(int64_t)col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
+      }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                                    const cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode,
                                                    int tiles_m) {
   using C = cplx_t<R>;
-  using V = typename Acc<R>::type;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   int k0, kb;
   if (!step_range<R>(f, (mode == 2 || mode == 6) ? 2 : 0, step, nb, k0, kb)) return;
@@ -629,72 +768,77 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
   const int m0 = tm * kBM, n0 = tn * kBN;
   if (m <= 0 || n <= 0 || k <= 0 || m0 >= m || n0 >= n) return;
+  gemm_tile<R>(Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign, assign ? R(1) : R(-1), 0, k);
+}
 
-  __shared__ C As[kBK][kBM + 1];
-  __shared__ C Bs[kBK][kBN + 1];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
-  // im = sum (ar bi + ai br).  Update modes start from C and accumulate with A
-  // negated (stored negated in LDS), so C -= A B needs no extra pass.
-  V re[2][2], im[2][2];
-  const R sgn = assign ? R(1) : R(-1);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
-        const int col = n0 + wn + 16 * b + (lane & 15);
-        C c0 = cmake<C>(0, 0);
-        if (!assign && row < m && col < n) c0 = Cp[(int64_t)col * ldc + row];
-        re[a][b][r] = c0.x;
-        im[a][b][r] = c0.y;
-      }
-
-  for (int kk0 = 0; kk0 < k; kk0 += kBK) {
-    for (int e = threadIdx.x; e < kBM * kBK; e += 256) {
-      const int row = e % kBM, kk = e / kBM;
-      const int gr = m0 + row, gk = kk0 + kk;
-      const C v = (gr < m && gk < k) ? Ap[(int64_t)gk * lda + gr] : cmake<C>(0, 0);
-      As[kk][row] = cmake<C>(sgn * v.x, sgn * v.y);
+// Triangular inverses of a front's pivot block by recursive doubling over
+// its 32-column diagonal blocks (whose inverses the diagonal-block LU left in
+// dinv).  For the pair of diagonal blocks A = [o, o + h), B = [o + h, o + h + nb):
+//   phase 0:  TL = L(B, A) XL(A, A)        TU = U(A, B) XU(B, B)
+//   phase 1:  XL(B, A) = -XL(B, B) TL      XU(A, B) = -XU(A, A) TU
+// XL / XU are the lower / upper inverses (p x p, column-major, in xwork), TL
+// and TU sit at the same positions of the p x p temporary tbuf.  blockIdx.z =
+// 2 pair + (0: L, 1: U); k is cut to where the triangular factor is nonzero.
+template <typename R>
+__global__ void __launch_bounds__(256) inv_gemm_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                       cplx_t<R>* __restrict__ xwork, cplx_t<R>* __restrict__ tbuf,
+                                                       int f0, int h, int phase, int tiles_m) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int p = f.p, F = f.F;
+  const int pair = blockIdx.z >> 1, upper = blockIdx.z & 1;
+  const int o = 2 * h * pair;
+  if (o + h >= p) return;
+  const int nb = min(h, p - o - h);
+  const C* LU = arena + f.off;
+  C* XL = xwork + f.xoff;
+  C* XU = XL + (int64_t)p * p;
+  C* T = tbuf + f.xoff / 2;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int64_t oA = o, oB = o + h;
+  if (!upper) {
+    if (phase == 0) {   // TL (nb x h) = L(B, A) (nb x h) XL(A, A) (h x h, lower)
+      if (m0 >= nb || n0 >= h) return;
+      gemm_tile<R>(LU + oA * F + oB, F, XL + oA * p + oA, p, T + oA * p + oB, p, nb, h, h, m0, n0, false, R(1), n0, h);
+    } else {            // XL(B, A) (nb x h) = -XL(B, B) (nb x nb, lower) TL (nb x h)
+      if (m0 >= nb || n0 >= h) return;
+      gemm_tile<R>(XL + oB * p + oB, p, T + oA * p + oB, p, XL + oA * p + oB, p, nb, h, nb, m0, n0, false, R(-1), 0,
+                   m0 + kBM);
     }
-    for (int e = threadIdx.x; e < kBK * kBN; e += 256) {
-      const int kk = e % kBK, col = e / kBK;
-      const int gk = kk0 + kk, gc = n0 + col;
-      Bs[kk][col] = (gk < k && gc < n) ? Bp[(int64_t)gc * ldb + gk] : cmake<C>(0, 0);
+  } else {
+    if (phase == 0) {   // TU (h x nb) = U(A, B) (h x nb) XU(B, B) (nb x nb, upper)
+      if (m0 >= h || n0 >= nb) return;
+      gemm_tile<R>(LU + oB * F + oA, F, XU + oB * p + oB, p, T + oB * p + oA, p, h, nb, nb, m0, n0, false, R(1), 0,
+                   n0 + kBN);
+    } else {            // XU(A, B) (h x nb) = -XU(A, A) (h x h, upper) TU (h x nb)
+      if (m0 >= h || n0 >= nb) return;
+      gemm_tile<R>(XU + oA * p + oA, p, T + oB * p + oA, p, XU + oB * p + oA, p, h, nb, h, m0, n0, false, R(-1), m0, h);
     }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
-      C av[2], bv[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wm + 16 * a + (lane & 15)];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wn + 16 * b + (lane & 15)];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          re[a][b] = mfma16(av[a].x, bv[b].x, re[a][b]);
-          re[a][b] = mfma16(-av[a].y, bv[b].y, re[a][b]);
-          im[a][b] = mfma16(av[a].x, bv[b].y, im[a][b]);
-          im[a][b] = mfma16(av[a].y, bv[b].x, im[a][b]);
-        }
-    }
-    __syncthreads();
   }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
-        const int col = n0 + wn + 16 * b + (lane & 15);
-        if (row < m && col < n) Cp[(int64_t)col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
-      }
+}
+
+// XL, XU of every front of a level: zero, with the diagonal 32 x 32 blocks
+// taken from dinv.
+template <typename R>
+__global__ void inv_init_kernel(MfDev mf, cplx_t<R>* __restrict__ xwork, const cplx_t<R>* __restrict__ dinv, int f0) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int p = f.p;
+  const int64_t pp = (int64_t)p * p;
+  C* X = xwork + f.xoff;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < pp; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % p), j = (int)(t / p);
+    C l = cmake<C>(0, 0), u = cmake<C>(0, 0);
+    if (i / kDB == j / kDB) {
+      const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + j / kDB);
+      const int bi = i % kDB, bj = j % kDB;
+      l = Li[bj * kDB + bi];
+      u = Li[kDB * kDB + bj * kDB + bi];
+    }
+    X[t] = l;
+    X[pp + t] = u;
+  }
 }
 
 // ------------------------------------------------------------------ inverse helpers
@@ -1177,9 +1321,9 @@ constexpr int kNB = 32;
 }  // namespace
 
 template <typename R>
-void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* dinv_v, int f0, int f1,
-                     int maxF, int maxP, int blk0, int blk1, int max_children, bool invert, bool partial_pivoting,
-                     const int* hF, const int* hP) {
+void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* tbuf_v, void* dinv_v,
+                     int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, bool invert,
+                     bool partial_pivoting, const int* hF, const int* hP) {
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
   C* xwork = static_cast<C*>(xwork_v);
@@ -1247,17 +1391,37 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   if (!invert) return;
   // Inverses of L11 and U11 for levels solved by matrix-vector products.
   const int ptiles = (int)ceil_div(maxP, kBM);
-  identity_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, f0);
-  SPP_LAUNCH_CHECK();
-  for (int mode = 1; mode <= 2; ++mode) {
-    for (int s = 0; s < steps; ++s) {
-      if (partial_pivoting)
+  if (!partial_pivoting) {
+    inv_init_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, dinv, f0);
+    SPP_LAUNCH_CHECK();
+    C* tbuf = static_cast<C*>(tbuf_v);
+    for (int h = kDB; h < maxP; h *= 2) {
+      const int pairs = (int)ceil_div(maxP, 2 * h);
+      const int ht = (int)ceil_div(h, kBM);
+      double fl = 0;
+      if (g_timer)
+        for (int i = 0; i < nf; ++i)
+          for (int o = 0; o + h < hP[i]; o += 2 * h) {
+            const double nbv = std::min(h, hP[i] - o - h);
+            fl += 2 * 8.0 * nbv * h * (h + nbv) / 2;   // both triangles, products cut to the nonzero half
+          }
+      timer_begin(KC_GEMM, st);
+      for (int phase = 0; phase < 2; ++phase) {
+        inv_gemm_kernel<R><<<dim3(ht * ht, nf, 2 * pairs), 256, 0, st>>>(mf, arena, xwork, tbuf, f0, h, phase, ht);
+        SPP_LAUNCH_CHECK();
+      }
+      timer_end(KC_GEMM, st, 0.0, fl);
+    }
+  } else {
+    identity_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, f0);
+    SPP_LAUNCH_CHECK();
+    for (int mode = 1; mode <= 2; ++mode) {
+      for (int s = 0; s < steps; ++s) {
         trsm_kernel<R><<<dim3(ceil_div(maxP, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, mode);
-      else
-        gemm_kernel<R><<<dim3(ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, mode + 4, 1);
-      SPP_LAUNCH_CHECK();
-      gemm_kernel<R><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, mode, ptiles);
-      SPP_LAUNCH_CHECK();
+        SPP_LAUNCH_CHECK();
+        gemm_kernel<R><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, mode, ptiles);
+        SPP_LAUNCH_CHECK();
+      }
     }
   }
   merge_inverse_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, arena, xwork, f0);
@@ -1380,10 +1544,10 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
   SPP_LAUNCH_CHECK();
 }
 
-template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, int, int, int, int, int, int, int, bool,
-                                      bool, const int*, const int*);
-template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, int, int, int, int, int, int, int, bool,
-                                     bool, const int*, const int*);
+template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, void*, int, int, int, int, int, int,
+                                      int, bool, bool, const int*, const int*);
+template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, void*, int, int, int, int, int, int,
+                                     int, bool, bool, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
                                int64_t);

@@ -1,0 +1,56 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+2D Helmholtz on a 512^2 grid, omega = 2 pi 64, 64 Gaussian bumps, b = 16,
+one Gaussian source, FGMRES to 1e-10, one spp_setup + spp_solve as the
+benchmark times them.  The oracle's solution (FGMRES to 1e-13, written by
+tests/golden/make_large_2d_samples.py) is stored at 1024 seeded grid points;
+the GPU solution must match it there to 1e-8 relative error, for complex128
+and for complex64 fronts.  The differential residual of the whole GPU
+solution is checked with the oracle's spectral operator.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pipeline, spectral
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_2d_u_samples.txt")
+
+
+def load_samples():
+    idx, vals = [], []
+    with open(GOLD) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            i, re, im = line.split()
+            idx.append(int(i))
+            vals.append(complex(float(re), float(im)))
+    return np.array(idx), np.array(vals)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_large_2d_matches_oracle_samples(prec):
+    from paper_1409_0297_amd import Solver
+    W = workloads.large_2d()
+    S = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, prec=prec, tol=1e-10, max_iter=200)
+    u, iters, relres, code = S.solve(W.rhs)
+    st = S.stats()
+    S.close()
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().reshape(W.n, W.n)
+    assert code == 0 and relres[0] <= 1e-10, (code, relres)
+    assert 10 <= iters[0] <= 30, iters
+    idx, ref = load_samples()
+    err = np.linalg.norm(u.reshape(-1)[idx] - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, (prec, err)
+    s, q, _ = pipeline.coefficients(W.kind, W.n, W.d, W.coeff, W.omega)
+    assert abs(st["s"] - s) <= 1e-12 * s
+    r = W.rhs[0] - spectral.apply_differential(u, W.d, s, q)
+    dres = np.linalg.norm(r) / np.linalg.norm(W.rhs[0])
+    assert dres <= 1e-7, dres
