@@ -198,6 +198,57 @@ int spp_kernel_timing(const spp_factor* factor, int32_t kclass, double* total_ms
                       int64_t* launches, double* bytes, double* flops);
 int spp_kernel_timing_reset(spp_factor* factor);
 
+/* ---- learned flexible-GMRES stage (a small CNN) ------------------------------
+ * A 3 x 3 circular convolutional network, bias-free, ReLU after every layer
+ * but the last, mapping a complex grid function (real and imaginary parts as
+ * two channels) on an n x n grid to another.  It is trained on pairs
+ * (v, M v) of Krylov vectors and sparsifying-preconditioner outputs, and used
+ * as a cheap preconditioner stage inside FGMRES (Section 2.2 uses M = P^{-1} Q
+ * for every iteration; flexible GMRES allows M to change per iteration).
+ * Activations and MFMA inputs are bf16 (SPP_CNN_BF16) or fp32 (SPP_CNN_F32);
+ * accumulation and master weights are fp32.  Weights are float arrays in
+ * (Cout, Cin, 3, 3) layout per layer, layers concatenated; the taps are
+ * w[o][c][dy + 1][dx + 1] acting on x[c][(i + dy) mod n][(j + dx) mod n]. */
+enum { SPP_CNN_BF16 = 0, SPP_CNN_F32 = 1 };
+typedef struct spp_cnn spp_cnn;
+
+/* channels: HOST int32[nlayers + 1], first and last 2, all in [1, 32];
+   n: a multiple of 16; max_batch: samples per call.  Weights start at 0. */
+int spp_cnn_create(int32_t n, int32_t nlayers, const int32_t* channels, int32_t dtype,
+                   int32_t max_batch, spp_cnn** out);
+/* Sets (w_in) and/or reads (w_out) the fp32 master weights, HOST float[count];
+   setting them resets the Adam state.  count (HOST, may be NULL) = number of weights. */
+int spp_cnn_weights(spp_cnn* net, const float* w_in, float* w_out, int64_t* count);
+/* y = net(x) per sample; x, y DEVICE complex128 [batch][n^2]. */
+int spp_cnn_forward(spp_cnn* net, const void* x, int32_t batch, void* y, spp_stream_t stream);
+/* Forward and backward pass of loss = mean_b ||net(x_b) - t_b||^2 / ||t_b||^2;
+   x, t DEVICE complex128 [batch][n^2].  Keeps the gradient on the device for
+   spp_cnn_adam_step; loss (HOST double) and grads (HOST float[count], the
+   weight layout) may be NULL. */
+int spp_cnn_loss_grad(spp_cnn* net, const void* x, const void* t, int32_t batch,
+                      double* loss, float* grads, spp_stream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+   last gradient. */
+int spp_cnn_adam_step(spp_cnn* net, float lr, spp_stream_t stream);
+void spp_cnn_destroy(spp_cnn* net);
+const char* spp_cnn_last_error(void);
+
+/* Uses net as the first preconditioner stage of every FGMRES iteration of
+   spp_solve: z = s^{-1} net(s v) with s = sqrt(n^2) (v has unit norm), judged
+   by the sparsifying preconditioner's standard: the step is kept when every
+   column's residual estimate falls to at most rho times its previous value,
+   otherwise it is discarded and redone with z = P^{-1} Q v.  After three
+   discarded steps in a row the network is not tried again in that solve.
+   net = NULL detaches.  Requires a single 2D problem of the network's n and
+   max_batch >= nrhs.  The factor does not own net. */
+int spp_attach_cnn(spp_factor* factor, spp_cnn* net, double rho);
+/* Steps of the last spp_solve that used the network (accepted) or redid the
+   step with the sparsifying preconditioner (rejected). HOST outputs. */
+int spp_learned_stats(const spp_factor* factor, int32_t* accepted, int32_t* rejected);
+/* Copies the j-th Arnoldi vector v_j and its preconditioned z_j of the last
+   spp_solve (DEVICE complex128, the batch vector layout), j < iterations. */
+int spp_get_krylov(const spp_factor* factor, int32_t j, void* v, void* z);
+
 /* Releases everything the factor owns (synchronises its last stream). */
 void spp_destroy(spp_factor* factor);
 

@@ -12,4 +12,6 @@ from .binding import (SPP_C128, SPP_C64_FRONTS, SPP_EBREAKDOWN, SPP_EHIP, SPP_EI
                       library_path, spp_apply_green, spp_apply_operator, spp_apply_precond,
                       spp_apply_q, spp_destroy, spp_error_string, spp_get_coefficients,
                       spp_get_stencil, spp_kernel_timing, spp_kernel_timing_reset, spp_last_error,
-                      spp_setup, spp_setup_batch, spp_get_shift, spp_solve, spp_stats)
+                      spp_setup, spp_setup_batch, spp_get_shift, spp_solve, spp_stats,
+                      CNN, CnnError, SPP_CNN_BF16, SPP_CNN_F32, spp_attach_cnn, spp_learned_stats,
+                      spp_get_krylov)

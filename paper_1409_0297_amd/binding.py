@@ -78,6 +78,16 @@ def library():
         "spp_kernel_timing_reset": (I, [P]),
         "spp_destroy": (V, [P]),
         "spp_error_string": (ctypes.c_char_p, [I]),
+        "spp_cnn_create": (I, [I, I, ctypes.POINTER(I), I, I, ctypes.POINTER(P)]),
+        "spp_cnn_weights": (I, [P, P, P, ctypes.POINTER(ctypes.c_int64)]),
+        "spp_cnn_forward": (I, [P, P, I, P, P]),
+        "spp_cnn_loss_grad": (I, [P, P, P, I, ctypes.POINTER(D), P, P]),
+        "spp_cnn_adam_step": (I, [P, ctypes.c_float, P]),
+        "spp_cnn_destroy": (V, [P]),
+        "spp_cnn_last_error": (ctypes.c_char_p, []),
+        "spp_attach_cnn": (I, [P, P, D]),
+        "spp_learned_stats": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "spp_get_krylov": (I, [P, I, P, P]),
         "spp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -290,6 +300,21 @@ class Solver:
     def stats(self) -> dict:
         return spp_stats(self.handle)
 
+    def attach_cnn(self, cnn, rho: float = 0.9):
+        """Use a trained CNN as the first preconditioner stage (None detaches)."""
+        self._cnn = cnn
+        spp_attach_cnn(self.handle, cnn.handle if cnn is not None else None, rho)
+
+    def learned_stats(self):
+        return spp_learned_stats(self.handle)
+
+    def krylov(self, j: int, nrhs: int = 1):
+        """(v_j, z_j) of the last solve as (nrhs, N) complex tensors."""
+        v = self.torch.empty((nrhs, self.N), dtype=self.torch.complex128, device="cuda")
+        z = self.torch.empty_like(v)
+        spp_get_krylov(self.handle, j, v.data_ptr(), z.data_ptr())
+        return v, z
+
     def close(self):
         if getattr(self, "handle", None):
             spp_destroy(self.handle)
@@ -379,3 +404,110 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- learned stage
+SPP_CNN_BF16 = 0
+SPP_CNN_F32 = 1
+
+
+class CnnError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = library()
+        super().__init__(f"{where}: {lib.spp_error_string(code).decode()} ({lib.spp_cnn_last_error().decode()})")
+        self.code = code
+
+
+def _cnn_check(code: int, where: str):
+    if code != SPP_OK:
+        raise CnnError(code, where)
+
+
+class CNN:
+    """The learned preconditioner network on the GPU (weights in (Cout, Cin, 3, 3) per layer)."""
+
+    def __init__(self, n: int, channels=(2, 32, 32, 32, 32, 32, 2), dtype: str = "bf16", max_batch: int = 32):
+        import numpy as np
+        import torch
+        self.torch, self.np = torch, np
+        self.n, self.channels, self.max_batch = n, tuple(channels), max_batch
+        ch = (ctypes.c_int32 * len(channels))(*channels)
+        h = ctypes.c_void_p()
+        _cnn_check(library().spp_cnn_create(n, len(channels) - 1, ch, SPP_CNN_BF16 if dtype == "bf16" else SPP_CNN_F32,
+                                            max_batch, ctypes.byref(h)), "spp_cnn_create")
+        self.handle = h.value
+        cnt = ctypes.c_int64()
+        _cnn_check(library().spp_cnn_weights(self.handle, None, None, ctypes.byref(cnt)), "spp_cnn_weights")
+        self.count = cnt.value
+        self.shapes = [(co, ci, 3, 3) for ci, co in zip(channels[:-1], channels[1:])]
+
+    def _stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def set_weights(self, ws):
+        flat = self.np.concatenate([self.np.asarray(w, dtype=self.np.float32).reshape(-1) for w in ws])
+        assert flat.size == self.count
+        flat = self.np.ascontiguousarray(flat)
+        _cnn_check(library().spp_cnn_weights(self.handle, flat.ctypes.data, None, None), "spp_cnn_weights")
+
+    def _split(self, flat):
+        out, o = [], 0
+        for s in self.shapes:
+            k = int(self.np.prod(s))
+            out.append(flat[o:o + k].reshape(s))
+            o += k
+        return out
+
+    def get_weights(self):
+        flat = self.np.zeros(self.count, dtype=self.np.float32)
+        _cnn_check(library().spp_cnn_weights(self.handle, None, flat.ctypes.data, None), "spp_cnn_weights")
+        return self._split(flat)
+
+    def _dev(self, x):
+        t = self.torch.as_tensor(x, dtype=self.torch.complex128, device="cuda").contiguous()
+        return t.reshape(-1, self.n * self.n)
+
+    def forward(self, x):
+        xv = self._dev(x)
+        y = self.torch.empty_like(xv)
+        _cnn_check(library().spp_cnn_forward(self.handle, xv.data_ptr(), xv.shape[0], y.data_ptr(),
+                                             ctypes.c_void_p(self._stream())), "spp_cnn_forward")
+        return y
+
+    def loss_grad(self, x, t, want_grads: bool = False):
+        xv, tv = self._dev(x), self._dev(t)
+        loss = ctypes.c_double()
+        g = self.np.zeros(self.count, dtype=self.np.float32) if want_grads else None
+        _cnn_check(library().spp_cnn_loss_grad(self.handle, xv.data_ptr(), tv.data_ptr(), xv.shape[0],
+                                               ctypes.byref(loss), g.ctypes.data if want_grads else None,
+                                               ctypes.c_void_p(self._stream())), "spp_cnn_loss_grad")
+        return (loss.value, self._split(g)) if want_grads else loss.value
+
+    def adam_step(self, lr: float = 1e-3):
+        _cnn_check(library().spp_cnn_adam_step(self.handle, ctypes.c_float(lr), ctypes.c_void_p(self._stream())),
+                   "spp_cnn_adam_step")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().spp_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spp_attach_cnn(handle, cnn_handle, rho: float = 0.9):
+    _check(library().spp_attach_cnn(handle, cnn_handle, ctypes.c_double(rho)), "spp_attach_cnn")
+
+
+def spp_learned_stats(handle):
+    a, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(library().spp_learned_stats(handle, ctypes.byref(a), ctypes.byref(r)), "spp_learned_stats")
+    return a.value, r.value
+
+
+def spp_get_krylov(handle, j: int, v_ptr, z_ptr):
+    _check(library().spp_get_krylov(handle, j, v_ptr, z_ptr), "spp_get_krylov")

@@ -260,6 +260,12 @@ struct spp_factor {
   int* kvec = nullptr;
   double* h_resid = nullptr;   // pinned host copy of residual estimates
   spp_stats_t stats{};
+  spp_cnn* cnn = nullptr;      // learned FGMRES stage (not owned)
+  double cnn_rho = 0.9;
+  int cnn_accepted = 0, cnn_rejected = 0;
+  double2* gsave = nullptr;    // Givens right-hand side before a learned step
+  int last_iters_all = 0;      // Krylov vectors kept from the last solve
+  int last_nrhs = 0;
   hipStream_t last_stream = nullptr;
   std::unique_ptr<KernelTimer> timer;
 
@@ -338,7 +344,8 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   const int r = std::max(nrhs, F->cap_rhs), it = std::max(iters, F->cap_iter);
   for (void* p : {(void*)F->tmp, (void*)F->qr, F->wv, F->zv, F->xc, F->gpart, (void*)F->V, (void*)F->Z, (void*)F->H,
                   (void*)F->gv, (void*)F->sn, (void*)F->y, (void*)F->g0, (void*)F->wk, (void*)F->h2,
-                  (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec})
+                  (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec,
+                  (void*)F->gsave})
     F->dfree(p);
   if (F->h_resid) { (void)hipHostFree(F->h_resid); F->h_resid = nullptr; }
   const int64_t N = F->Ntot;
@@ -361,6 +368,7 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->g0 = F->dalloc<double2>((size_t)r * N);
   F->wk = F->dalloc<double2>((size_t)r * N);
   F->h2 = F->dalloc<double2>(ld * cols);
+  F->gsave = F->dalloc<double2>(ld * cols);
   int64_t nblk = 1;
   for (const SppGroup& g : F->groups) nblk = std::max<int64_t>(nblk, (g.N + 1023) / 1024);
   F->dpart = F->dalloc<double2>((size_t)nblk * cols * (it + 1));
@@ -656,13 +664,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   int done = 0;
   for (int c = 0; c < cols; ++c)
     if (beta[c] == 0) { conv[c] = true; ++done; }
-  int j = 0;
-  for (; j < maxit && done < cols; ++j) {
-    double2* vj = F->V + (int64_t)j * vstride;
+  // One Arnoldi step with z_j already in Z: w = A z_j, CGS2, Givens; returns
+  // the residual estimates in F->h_resid.
+  auto arnoldi_step = [&](int j) {
     double2* zj = F->Z + (int64_t)j * vstride;
-    // a9: z_j = M v_j
-    if (precond) apply_precond(F, vj, zj, nrhs, st);
-    else SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
     // a8: w = (I + G q) z_j
     apply_operator(F, zj, F->wk, nrhs, st);
     // CGS2 against v_0 .. v_j; H(:, j) per column.
@@ -681,6 +686,43 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     kr_givens(st, F->H, ld, hrhs, F->cs, F->sn, F->gv, j, cols, ld, F->resid, nullptr);
     SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
     SPP_HIP(hipStreamSynchronize(st));
+  };
+  const bool learned = F->cnn != nullptr && precond;
+  F->cnn_accepted = F->cnn_rejected = 0;
+  int reject_run = 0;
+  std::vector<double> prev(beta);
+  const double sN = std::sqrt((double)F->Ntot);
+  int j = 0;
+  for (; j < maxit && done < cols; ++j) {
+    double2* vj = F->V + (int64_t)j * vstride;
+    double2* zj = F->Z + (int64_t)j * vstride;
+    bool have = false;
+    if (learned && reject_run < 3) {
+      // Learned stage: z_j = net(v_j), kept only if every column's residual
+      // estimate drops to rho times its previous value.
+      SPP_HIP(hipMemcpyAsync(F->gsave, F->gv, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));
+      cnn_apply(F->cnn, vj, zj, cols, sN, 1.0 / sN, st);
+      arnoldi_step(j);
+      bool ok = true;
+      for (int c = 0; c < cols; ++c)
+        if (!conv[c] && !(F->h_resid[c] <= F->cnn_rho * prev[c])) ok = false;
+      if (ok) {
+        ++F->cnn_accepted;
+        reject_run = 0;
+        have = true;
+      } else {
+        ++F->cnn_rejected;
+        ++reject_run;
+        SPP_HIP(hipMemcpyAsync(F->gv, F->gsave, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));
+      }
+    }
+    if (!have) {
+      // a9: z_j = M v_j
+      if (precond) apply_precond(F, vj, zj, nrhs, st);
+      else SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
+      arnoldi_step(j);
+    }
+    for (int c = 0; c < cols; ++c) prev[c] = F->h_resid[c];
     for (int c = 0; c < cols; ++c) {
       if (conv[c]) continue;
       if (!(F->h_resid[c] > F->opt.tol * beta[c])) {
@@ -719,6 +761,8 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   }
   F->stats.last_iters = kmax;
   F->stats.t_solve_ms = now_ms() - t0;
+  F->last_iters_all = j;
+  F->last_nrhs = nrhs;
   if (!all_conv) {
     g_last_error = "GMRES reached max_iter before the tolerance";
     return SPP_NOT_CONVERGED;
@@ -820,6 +864,43 @@ int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t
     if (offsets) std::memcpy(offsets, ST.off.data(), ST.off.size() * sizeof(int));
     if (T) SPP_HIP(hipMemcpy(T, S.T, sizeof(double2) * ST.nS * ST.nB, hipMemcpyDeviceToHost));
     if (C) SPP_HIP(hipMemcpy(C, S.C, sizeof(double2) * ST.nS * ST.nG, hipMemcpyDeviceToHost));
+    return SPP_OK;
+  });
+}
+
+int spp_attach_cnn(spp_factor* factor, spp_cnn* net, double rho) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (!net) {
+      factor->cnn = nullptr;
+      return SPP_OK;
+    }
+    if (!(rho > 0 && rho <= 1)) throw Error(SPP_EINVAL, "rho must be in (0, 1]");
+    if (factor->inst.size() != 1 || factor->inst[0].d != 2 || factor->inst[0].n != cnn_grid(net))
+      throw Error(SPP_EINVAL, "the learned stage needs a single 2D problem on the network's grid");
+    factor->cnn = net;
+    factor->cnn_rho = rho;
+    return SPP_OK;
+  });
+}
+
+int spp_learned_stats(const spp_factor* factor, int32_t* accepted, int32_t* rejected) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (accepted) *accepted = factor->cnn_accepted;
+    if (rejected) *rejected = factor->cnn_rejected;
+    return SPP_OK;
+  });
+}
+
+int spp_get_krylov(const spp_factor* factor, int32_t j, void* v, void* z) {
+  return guarded([&] {
+    if (!factor) throw Error(SPP_EINVAL, "null factor");
+    if (j < 0 || j >= factor->last_iters_all) throw Error(SPP_EINVAL, "j must be below the last solve's iterations");
+    const size_t bytes = sizeof(double2) * (size_t)factor->last_nrhs * factor->Ntot;
+    const int64_t vstride = (int64_t)factor->last_nrhs * factor->Ntot;
+    if (v) SPP_HIP(hipMemcpy(v, factor->V + (int64_t)j * vstride, bytes, hipMemcpyDeviceToDevice));
+    if (z) SPP_HIP(hipMemcpy(z, factor->Z + (int64_t)j * vstride, bytes, hipMemcpyDeviceToDevice));
     return SPP_OK;
   });
 }

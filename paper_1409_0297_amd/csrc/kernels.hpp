@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+struct spp_cnn;
+
 namespace spp {
 
 // ------------------------------------------------------------- timing
@@ -151,5 +153,12 @@ void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* par
 void kr_sub(hipStream_t st, const double2* a, const double2* b, double2* out, int64_t count);
 void kr_scale_init(hipStream_t st, const double2* g, double2* v0, const double* norms, int nrhs,
                    int64_t N, double2* gvec, int ldg);
+
+// ------------------------------------------------------------- cnn.hip
+// Learned preconditioner stage: y = out_scale * net(in_scale * x) per sample,
+// x, y complex128 [batch][n^2].
+void cnn_apply(struct ::spp_cnn* net, const double2* x, double2* y, int batch, double in_scale, double out_scale,
+               hipStream_t st);
+int cnn_grid(const struct ::spp_cnn* net);
 
 }  // namespace spp
