@@ -82,6 +82,11 @@ typedef struct {
 #define SPP_F_PARTIAL_PIVOTING 4  /* pivot over all remaining fully-summed rows
                                      of a front; default: pivot within each
                                      32-row diagonal block of the front        */
+#define SPP_F_GRAPHS 8            /* capture one FGMRES iteration in a HIP graph
+                                     (once per factor and nrhs) and replay it
+                                     with the step index in device memory;
+                                     ignored with SPP_F_TIMING or a learned
+                                     stage attached                            */
 
 typedef struct {
   int32_t prec;         /* spp_prec                                              */

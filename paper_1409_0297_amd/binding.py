@@ -19,6 +19,7 @@ SPP_ORDER_OCTREE, SPP_ORDER_BISECT = 0, 1
 SPP_F_UNPRECONDITIONED = 1
 SPP_F_TIMING = 2
 SPP_F_PARTIAL_PIVOTING = 4
+SPP_F_GRAPHS = 8
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
 KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
 
@@ -224,7 +225,7 @@ class Solver:
     def __init__(self, kind: str, n: int, d: int, b: int, coeff, omega: float = 0.0,
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
-                 timing: bool = False, partial_pivoting: bool = False):
+                 timing: bool = False, partial_pivoting: bool = False, graphs: bool = False):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -239,7 +240,8 @@ class Solver:
                          tol=tol, max_iter=max_iter,
                          flags=(SPP_F_UNPRECONDITIONED if unpreconditioned else 0)
                          | (SPP_F_TIMING if timing else 0)
-                         | (SPP_F_PARTIAL_PIVOTING if partial_pivoting else 0))
+                         | (SPP_F_PARTIAL_PIVOTING if partial_pivoting else 0)
+                         | (SPP_F_GRAPHS if graphs else 0))
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:
@@ -338,7 +340,7 @@ class BatchSolver:
     """
 
     def __init__(self, problems, prec: str = "c128", order: str = "octree", tol: float = 1e-10,
-                 max_iter: int = 200, timing: bool = False):
+                 max_iter: int = 200, timing: bool = False, graphs: bool = False):
         import torch
         self.torch = torch
         self.sizes = [p["n"] ** p["d"] for p in problems]
@@ -356,7 +358,8 @@ class BatchSolver:
                                    coeff=c.data_ptr()))
         op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,
                          order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
-                         tol=tol, max_iter=max_iter, flags=SPP_F_TIMING if timing else 0)
+                         tol=tol, max_iter=max_iter,
+                         flags=(SPP_F_TIMING if timing else 0) | (SPP_F_GRAPHS if graphs else 0))
         self.handle = spp_setup_batch(pbs, op, torch.cuda.current_stream().cuda_stream)
 
     def _stream(self) -> int:

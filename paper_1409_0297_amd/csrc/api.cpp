@@ -266,6 +266,19 @@ struct spp_factor {
   double2* gsave = nullptr;    // Givens right-hand side before a learned step
   int last_iters_all = 0;      // Krylov vectors kept from the last solve
   int last_nrhs = 0;
+  // Captured FGMRES iteration (SPP_F_GRAPHS): one graph replayed per step with
+  // the step index in device memory.
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t gstream = nullptr;
+  int graph_nrhs = 0;
+  bool graph_precond = true;
+  int* dj = nullptr;
+  double2 *vfix = nullptr, *zfix = nullptr;
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    graph_nrhs = 0;
+  }
   hipStream_t last_stream = nullptr;
   std::unique_ptr<KernelTimer> timer;
 
@@ -283,6 +296,8 @@ struct spp_factor {
     (void)hipFree(p);
   }
   ~spp_factor() {
+    drop_graph();
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (void* p : allocs) (void)hipFree(p);
     if (h_resid) (void)hipHostFree(h_resid);
   }
@@ -341,11 +356,12 @@ int total_cols(const spp_factor* F, int nrhs) { return static_cast<int>(F->inst.
 
 void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   if (nrhs <= F->cap_rhs && iters <= F->cap_iter) return;
+  F->drop_graph();
   const int r = std::max(nrhs, F->cap_rhs), it = std::max(iters, F->cap_iter);
   for (void* p : {(void*)F->tmp, (void*)F->qr, F->wv, F->zv, F->xc, F->gpart, (void*)F->V, (void*)F->Z, (void*)F->H,
                   (void*)F->gv, (void*)F->sn, (void*)F->y, (void*)F->g0, (void*)F->wk, (void*)F->h2,
                   (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec,
-                  (void*)F->gsave})
+                  (void*)F->gsave, (void*)F->vfix, (void*)F->zfix, (void*)F->dj})
     F->dfree(p);
   if (F->h_resid) { (void)hipHostFree(F->h_resid); F->h_resid = nullptr; }
   const int64_t N = F->Ntot;
@@ -369,6 +385,9 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->wk = F->dalloc<double2>((size_t)r * N);
   F->h2 = F->dalloc<double2>(ld * cols);
   F->gsave = F->dalloc<double2>(ld * cols);
+  F->vfix = F->dalloc<double2>((size_t)r * N);
+  F->zfix = F->dalloc<double2>((size_t)r * N);
+  F->dj = F->dalloc<int>(1);
   int64_t nblk = 1;
   for (const SppGroup& g : F->groups) nblk = std::max<int64_t>(nblk, (g.N + 1023) / 1024);
   F->dpart = F->dalloc<double2>((size_t)nblk * cols * (it + 1));
@@ -687,7 +706,56 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
     SPP_HIP(hipStreamSynchronize(st));
   };
+  // The same step for graph replays: every launch reads j from F->dj, the
+  // vectors go through fixed buffers, and the residual estimates are copied
+  // to pinned memory inside the graph.
+  auto graph_body = [&](hipStream_t s) {
+    const int* dj = F->dj;
+    kr_copy_j(s, F->V, vstride, F->vfix, 0, vstride, dj);
+    if (precond) apply_precond(F, F->vfix, F->zfix, nrhs, s);
+    else kr_copy_j(s, F->V, vstride, F->zfix, 0, vstride, dj);
+    kr_copy_j(s, F->zfix, 0, F->Z, vstride, vstride, dj);
+    apply_operator(F, F->zfix, F->wk, nrhs, s);
+    for (const SppGroup& g : F->groups) {
+      const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+      const int64_t o = g.Noff * nrhs;
+      double2* hbase = F->H + (int64_t)c0 * hrhs;
+      double2* h2 = F->h2 + (int64_t)c0 * ld;
+      kr_dots(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, F->dpart, hbase, hrhs, 0, nullptr, 0, dj, ld, 0);
+      kr_update(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, hbase, hrhs, dj, ld);
+      kr_dots(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, F->dpart, h2, ld, 0, hbase, hrhs, dj, 0, ld);
+      kr_update(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, h2, ld, dj, 0);
+      kr_norm_scale(s, F->wk + o, F->V + vstride + o, nc, g.N, F->rpart, hbase + 1, hrhs, dj, vstride, ld + 1);
+    }
+    kr_givens(s, F->H, ld, hrhs, F->cs, F->sn, F->gv, 0, cols, ld, F->resid, nullptr, dj);
+    SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, s));
+    kr_set_counter(s, F->dj, 1, true);
+  };
   const bool learned = F->cnn != nullptr && precond;
+  const bool use_graph = (F->opt.flags & SPP_F_GRAPHS) && !F->timer && !learned;
+  if (use_graph && (!F->graph_exec || F->graph_nrhs != nrhs || F->graph_precond != precond)) {
+    F->drop_graph();
+    if (!F->gstream) SPP_HIP(hipStreamCreateWithFlags(&F->gstream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    SPP_HIP(hipStreamBeginCapture(F->gstream, hipStreamCaptureModeThreadLocal));
+    try {
+      graph_body(F->gstream);
+    } catch (...) {
+      (void)hipStreamEndCapture(F->gstream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    SPP_HIP(hipStreamEndCapture(F->gstream, &graph));
+    const hipError_t ie = hipGraphInstantiate(&F->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      F->graph_exec = nullptr;
+      throw_hip(ie, "hipGraphInstantiate", __FILE__, __LINE__);
+    }
+    F->graph_nrhs = nrhs;
+    F->graph_precond = precond;
+  }
+  if (use_graph) kr_set_counter(st, F->dj, 0, false);
   F->cnn_accepted = F->cnn_rejected = 0;
   int reject_run = 0;
   std::vector<double> prev(beta);
@@ -697,7 +765,11 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     double2* vj = F->V + (int64_t)j * vstride;
     double2* zj = F->Z + (int64_t)j * vstride;
     bool have = false;
-    if (learned && reject_run < 3) {
+    if (use_graph) {
+      SPP_HIP(hipGraphLaunch(F->graph_exec, st));
+      SPP_HIP(hipStreamSynchronize(st));
+      have = true;
+    } else if (learned && reject_run < 3) {
       // Learned stage: z_j = net(v_j), kept only if every column's residual
       // estimate drops to rho times its previous value.
       SPP_HIP(hipMemcpyAsync(F->gsave, F->gv, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));

@@ -136,15 +136,21 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
 
 // ------------------------------------------------------------- krylov.hip
 // h_out[i] (+)= V_i^H w per right-hand side; if h_acc, also h_acc[i] += V_i^H w.
+// dj (optional, for graph replays): the iteration index j in device memory;
+// then nvec = j + 1 and h_out / h_acc / v / h_sub are offset by j * jstride.
 void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const double2* w,
              int nrhs, int64_t N, double2* partial, double2* h_out, int hstride, int accumulate,
-             double2* h_acc, int acc_stride);
+             double2* h_acc, int acc_stride, const int* dj = nullptr, int64_t h_jstride = 0,
+             int64_t acc_jstride = 0);
 void kr_update(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w,
-               int nrhs, int64_t N, const double2* h, int hstride);
+               int nrhs, int64_t N, const double2* h, int hstride, const int* dj = nullptr,
+               int64_t h_jstride = 0);
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N,
-                   double* partial, double2* h_sub, int hstride);
+                   double* partial, double2* h_sub, int hstride, const int* dj = nullptr,
+                   int64_t v_jstride = 0, int64_t h_jstride = 0);
 void kr_givens(hipStream_t st, double2* H, int hcol_stride, int hrhs_stride, double* cs, double2* sn,
-               double2* g, int j, int nrhs, int ldg, double* resid, const int* active);
+               double2* g, int j, int nrhs, int ldg, double* resid, const int* active,
+               const int* dj = nullptr);
 void kr_backsolve(hipStream_t st, const double2* H, int hcol_stride, int hrhs_stride, const double2* g,
                   int ldg, double2* y, int k, int nrhs, const int* kvec);
 void kr_combine(hipStream_t st, const double2* Z, int64_t zstride, int nvec, const double2* y,
@@ -153,6 +159,11 @@ void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* par
 void kr_sub(hipStream_t st, const double2* a, const double2* b, double2* out, int64_t count);
 void kr_scale_init(hipStream_t st, const double2* g, double2* v0, const double* norms, int nrhs,
                    int64_t N, double2* gvec, int ldg);
+// dst + j dst_jstride <- src + j src_jstride (count values), j = *dj.
+void kr_copy_j(hipStream_t st, const double2* src, int64_t src_jstride, double2* dst,
+               int64_t dst_jstride, int64_t count, const int* dj);
+// *c = value, or *c += value (a kernel, so that it can sit in a captured graph).
+void kr_set_counter(hipStream_t st, int* c, int value, bool add);
 
 // ------------------------------------------------------------- cnn.hip
 // Learned preconditioner stage: y = out_scale * net(in_scale * x) per sample,

@@ -31,9 +31,12 @@ __device__ inline double wave_sum(double v) {
 }
 
 // partial[(rhs * nblk + blk) * nvec + i] = sum over the block's chunk of conj(V_i) w.
+// dj (optional): the iteration index j in device memory (graph replays);
+// then nvec = j + 1 and every j-dependent pointer is base + j * jstride.
 __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* __restrict__ V, int64_t vstride, int nvec,
                                                                 const double2* __restrict__ w, int64_t N,
-                                                                double2* __restrict__ partial) {
+                                                                double2* __restrict__ partial, const int* dj) {
+  if (dj) nvec = *dj + 1;
   const int rhs = blockIdx.y;
   const int nblk = gridDim.x;
   const int64_t chunk = (int64_t)kThreads * kPerThread;
@@ -68,7 +71,14 @@ __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* _
 
 // One wavefront per (vector, right-hand side) sums the per-block partials.
 __global__ void dots_final_kernel(const double2* __restrict__ partial, int nblk, int nvec, double2* h, int hstride,
-                                  int accumulate, double2* h_acc, int acc_stride) {
+                                  int accumulate, double2* h_acc, int acc_stride, const int* dj, int64_t h_jstride,
+                                  int64_t acc_jstride) {
+  if (dj) {
+    const int j = *dj;
+    nvec = j + 1;
+    h += j * h_jstride;
+    if (h_acc) h_acc += j * acc_jstride;
+  }
   const int rhs = blockIdx.y;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -88,7 +98,12 @@ __global__ void dots_final_kernel(const double2* __restrict__ partial, int nblk,
 // w -= sum_i V_i h_i
 __global__ void __launch_bounds__(kThreads) update_kernel(const double2* __restrict__ V, int64_t vstride, int nvec,
                                                           double2* __restrict__ w, int64_t N,
-                                                          const double2* __restrict__ h, int hstride) {
+                                                          const double2* __restrict__ h, int hstride, const int* dj,
+                                                          int64_t h_jstride) {
+  if (dj) {
+    nvec = *dj + 1;
+    h += *dj * h_jstride;
+  }
   const int rhs = blockIdx.y;
   __shared__ double2 hs[kMaxVec];
   for (int i = threadIdx.x; i < nvec; i += kThreads) hs[i] = h[(int64_t)rhs * hstride + i];
@@ -119,7 +134,8 @@ __global__ void __launch_bounds__(kThreads) sumsq_partial_kernel(const double2* 
 
 // norms[rhs] = sqrt(sum of partials); optionally H entry = norm.
 __global__ void sumsq_final_kernel(const double* __restrict__ partial, int nblk, int nrhs, double* norms,
-                                   double2* h_sub, int hstride) {
+                                   double2* h_sub, int hstride, const int* dj, int64_t h_jstride) {
+  if (dj && h_sub) h_sub += *dj * h_jstride;
   const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
   if (rhs >= nrhs) return;
   double s = 0;
@@ -130,7 +146,8 @@ __global__ void sumsq_final_kernel(const double* __restrict__ partial, int nblk,
 }
 
 __global__ void scale_kernel(const double2* __restrict__ w, double2* __restrict__ v, const double* __restrict__ norms,
-                             int64_t N) {
+                             int64_t N, const int* dj, int64_t v_jstride) {
+  if (dj) v += *dj * v_jstride;
   const int rhs = blockIdx.y;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= N) return;
@@ -153,7 +170,8 @@ __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s, 
 }
 
 __global__ void givens_kernel(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
-                              int nrhs, int ldg, double* resid, const int* active) {
+                              int nrhs, int ldg, double* resid, const int* active, const int* dj) {
+  if (dj) j = *dj;
   const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
   if (rhs >= nrhs) return;
   if (active && !active[rhs]) return;
@@ -222,24 +240,39 @@ __global__ void init_g_kernel(const double* norms, int nrhs, double2* gvec, int 
   gvec[(int64_t)rhs * ldg] = cmake<double2>(norms[rhs], 0.0);
 }
 
+// dst + j * dst_jstride = src + j * src_jstride (count complex values), j = *dj.
+__global__ void copy_j_kernel(const double2* __restrict__ src, int64_t src_jstride, double2* __restrict__ dst,
+                              int64_t dst_jstride, int64_t count, const int* dj) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int j = *dj;
+  dst[j * dst_jstride + e] = src[j * src_jstride + e];
+}
+
+__global__ void set_counter_kernel(int* c, int value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = add ? *c + value : value;
+}
+
 int dot_blocks(int64_t N) { return (int)ceil_div(N, (int64_t)kThreads * kPerThread); }
 
 }  // namespace
 
 void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const double2* w, int nrhs, int64_t N,
-             double2* partial, double2* h_out, int hstride, int accumulate, double2* h_acc, int acc_stride) {
+             double2* partial, double2* h_out, int hstride, int accumulate, double2* h_acc, int acc_stride,
+             const int* dj, int64_t h_jstride, int64_t acc_jstride) {
   if (nvec > kMaxVec) throw Error(-7, "Krylov dimension exceeds the kernel limit");
   const int nblk = dot_blocks(N);
-  dots_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, partial);
+  dots_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, partial, dj);
   SPP_LAUNCH_CHECK();
   dots_final_kernel<<<dim3(ceil_div(nvec, 4), nrhs), 256, 0, st>>>(partial, nblk, nvec, h_out, hstride, accumulate,
-                                                                       h_acc, acc_stride);
+                                                                       h_acc, acc_stride, dj, h_jstride, acc_jstride);
   SPP_LAUNCH_CHECK();
 }
 
 void kr_update(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w, int nrhs, int64_t N,
-               const double2* h, int hstride) {
-  update_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, h, hstride);
+               const double2* h, int hstride, const int* dj, int64_t h_jstride) {
+  update_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, h, hstride, dj,
+                                                                         h_jstride);
   SPP_LAUNCH_CHECK();
 }
 
@@ -247,26 +280,26 @@ void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* par
   const int nblk = 256;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(v, N, partial);
   SPP_LAUNCH_CHECK();
-  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, out, nullptr, 0);
+  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, out, nullptr, 0, nullptr, 0);
   SPP_LAUNCH_CHECK();
 }
 
 // v = w / ||w|| and h_sub = ||w|| per right-hand side; norms kept in partial[0..nrhs).
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N, double* partial,
-                   double2* h_sub, int hstride) {
+                   double2* h_sub, int hstride, const int* dj, int64_t v_jstride, int64_t h_jstride) {
   const int nblk = 256;
   double* norms = partial + (int64_t)nblk * nrhs;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(w, N, partial);
   SPP_LAUNCH_CHECK();
-  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, norms, h_sub, hstride);
+  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, norms, h_sub, hstride, dj, h_jstride);
   SPP_LAUNCH_CHECK();
-  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, norms, N);
+  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, norms, N, dj, v_jstride);
   SPP_LAUNCH_CHECK();
 }
 
 void kr_givens(hipStream_t st, double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j, int nrhs,
-               int ldg, double* resid, const int* active) {
-  givens_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(H, hcol, hrhs, cs, sn, g, j, nrhs, ldg, resid, active);
+               int ldg, double* resid, const int* active, const int* dj) {
+  givens_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(H, hcol, hrhs, cs, sn, g, j, nrhs, ldg, resid, active, dj);
   SPP_LAUNCH_CHECK();
 }
 
@@ -290,9 +323,20 @@ void kr_sub(hipStream_t st, const double2* a, const double2* b, double2* out, in
 
 void kr_scale_init(hipStream_t st, const double2* g, double2* v0, const double* norms, int nrhs, int64_t N,
                    double2* gvec, int ldg) {
-  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(g, v0, norms, N);
+  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(g, v0, norms, N, nullptr, 0);
   SPP_LAUNCH_CHECK();
   init_g_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(norms, nrhs, gvec, ldg);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_copy_j(hipStream_t st, const double2* src, int64_t src_jstride, double2* dst, int64_t dst_jstride,
+               int64_t count, const int* dj) {
+  copy_j_kernel<<<ceil_div(count, kThreads), kThreads, 0, st>>>(src, src_jstride, dst, dst_jstride, count, dj);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_set_counter(hipStream_t st, int* c, int value, bool add) {
+  set_counter_kernel<<<1, 64, 0, st>>>(c, value, add ? 1 : 0);
   SPP_LAUNCH_CHECK();
 }
 
