@@ -82,6 +82,10 @@ typedef struct {
 #define SPP_F_PARTIAL_PIVOTING 4  /* pivot over all remaining fully-summed rows
                                      of a front; default: pivot within each
                                      32-row diagonal block of the front        */
+#define SPP_F_PERSISTENT 16       /* substitution of runs of consecutive
+                                     small-front levels as one cooperative
+                                     launch with grid barriers between levels
+                                     (not inside graph replays)               */
 #define SPP_F_GRAPHS 8            /* capture one FGMRES iteration in a HIP graph
                                      (once per factor and nrhs) and replay it
                                      with the step index in device memory;

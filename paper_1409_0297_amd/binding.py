@@ -20,6 +20,7 @@ SPP_F_UNPRECONDITIONED = 1
 SPP_F_TIMING = 2
 SPP_F_PARTIAL_PIVOTING = 4
 SPP_F_GRAPHS = 8
+SPP_F_PERSISTENT = 16
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
 KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
 
@@ -225,7 +226,8 @@ class Solver:
     def __init__(self, kind: str, n: int, d: int, b: int, coeff, omega: float = 0.0,
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
-                 timing: bool = False, partial_pivoting: bool = False, graphs: bool = False):
+                 timing: bool = False, partial_pivoting: bool = False, graphs: bool = False,
+                 persistent: bool = False):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -241,7 +243,8 @@ class Solver:
                          flags=(SPP_F_UNPRECONDITIONED if unpreconditioned else 0)
                          | (SPP_F_TIMING if timing else 0)
                          | (SPP_F_PARTIAL_PIVOTING if partial_pivoting else 0)
-                         | (SPP_F_GRAPHS if graphs else 0))
+                         | (SPP_F_GRAPHS if graphs else 0)
+                         | (SPP_F_PERSISTENT if persistent else 0))
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:

@@ -154,6 +154,9 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
   }
   const Plan& P = pd->plan;
   std::vector<FrontDev> fd(P.fronts.size());
+  std::vector<int> parent(P.fronts.size(), -1);
+  for (size_t fi = 0; fi < P.fronts.size(); ++fi)
+    for (int c : P.fronts[fi].children) parent[c] = static_cast<int>(fi);
   for (const Level& L : P.levels) {
     int64_t xo = 0;
     const bool inv = mf_level_uses_inverse(L.end - L.begin, L.maxF, L.maxP);
@@ -167,6 +170,7 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
       g_.F = f.F; g_.p = f.p; g_.idx = f.idx; g_.map = f.map; g_.perm = pd->perm_total;
       g_.dblk = pd->dblk_total;
       g_.inst = pd->front_inst[fi];
+      g_.parent = parent[fi];
       pd->dblk_total += (f.p + 31) / 32;
       g_.nchild = static_cast<int>(f.children.size());
       if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
@@ -417,18 +421,21 @@ void apply_green(spp_factor* F, const double2* f, double2* gout, int nrhs, hipSt
   }
 }
 
-void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st) {
+// persistent: cooperative launches for runs of small-front levels (not inside
+// a graph capture).
+void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st, bool persistent = true) {
+  persistent = persistent && (F->opt.flags & SPP_F_PERSISTENT);
   q_apply(st, F->mf, r, F->qr, nrhs);
   const int nl = static_cast<int>(F->planp->levels.size());
   const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
     mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
-                     F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap);
+                     F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap, persistent);
   } else {
     const int64_t cnt = (int64_t)nrhs * F->Ntot;
     cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
     mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
-                    F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap);
+                    F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap, persistent);
     cast_vectors<float>(st, F->xc, z, cnt, 1);
   }
 }
@@ -712,7 +719,7 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   auto graph_body = [&](hipStream_t s) {
     const int* dj = F->dj;
     kr_copy_j(s, F->V, vstride, F->vfix, 0, vstride, dj);
-    if (precond) apply_precond(F, F->vfix, F->zfix, nrhs, s);
+    if (precond) apply_precond(F, F->vfix, F->zfix, nrhs, s, false);
     else kr_copy_j(s, F->V, vstride, F->zfix, 0, vstride, dj);
     kr_copy_j(s, F->zfix, 0, F->Z, vstride, vstride, dj);
     apply_operator(F, F->zfix, F->wk, nrhs, s);

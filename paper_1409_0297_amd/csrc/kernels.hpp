@@ -69,6 +69,7 @@ struct FrontDev {
   int perm;            // p ints: pivot row permutation
   int dblk;            // first diagonal-block slot (ceil(p / 32) slots of 2 x 32 x 32 entries)
   int inst;            // problem instance the front belongs to
+  int parent;          // parent front (-1 at a root)
   int nchild;
   int child[8];
 };
@@ -129,7 +130,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void*
               const void* x_in, void* x_out, int nrhs,
               const int* level_begin, const int* level_maxF, const int* level_maxK,
               const int* level_maxP, const double* level_ent, const int* level_inv, int nlevels,
-              void* partial, int64_t partial_cap);
+              void* partial, int64_t partial_cap, bool persistent);
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);

@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -1078,12 +1080,12 @@ __device__ inline void wg_matvec_rows(const cplx_t<R>* __restrict__ M, int ld, i
 }
 
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) fwd_front_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
-                                                        cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z,
-                                                        const cplx_t<R>* __restrict__ x, int nrhs, int r0, int f0) {
+__device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ W,
+                                      cplx_t<R>* __restrict__ Z, const cplx_t<R>* __restrict__ x, int nrhs, int r0,
+                                      int fi) {
   using C = cplx_t<R>;
   constexpr int BS = kTriBS;
-  const FrontDev& f = mf.fronts[f0 + blockIdx.x];
+  const FrontDev& f = mf.fronts[fi];
   const int F = f.F, p = f.p, K = F - p;
   const C* A = arena + f.off;
   const int* perm = mf.perm + f.perm;
@@ -1186,12 +1188,12 @@ __global__ void __launch_bounds__(256) fwd_front_kernel(MfDev mf, const cplx_t<R
 }
 
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) bwd_front_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
-                                                        const cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout,
-                                                        int nrhs, int r0, int f0) {
+__device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restrict__ arena,
+                                      const cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout, int nrhs, int r0,
+                                      int fi) {
   using C = cplx_t<R>;
   constexpr int BS = kTriBS;
-  const FrontDev& f = mf.fronts[f0 + blockIdx.x];
+  const FrontDev& f = mf.fronts[fi];
   const int F = f.F, p = f.p, K = F - p;
   const C* A = arena + f.off;
   const int* idx = mf.idx + f.idx;
@@ -1274,6 +1276,48 @@ __global__ void __launch_bounds__(256) bwd_front_kernel(MfDev mf, const cplx_t<R
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
     if (r < nr) xo[(int64_t)(r0 + r) * I.N + idx[i]] = y[t];
+  }
+}
+
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) fwd_front_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                        cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z,
+                                                        const cplx_t<R>* __restrict__ x, int nrhs, int r0, int f0) {
+  fwd_front_body<R, NR>(mf, arena, W, Z, x, nrhs, r0, f0 + blockIdx.x);
+}
+
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) bwd_front_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                        const cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout,
+                                                        int nrhs, int r0, int f0) {
+  bwd_front_body<R, NR>(mf, arena, Z, xout, nrhs, r0, f0 + blockIdx.x);
+}
+
+// Persistent form of the whole-front kernels for a run of consecutive
+// small-front levels: one cooperative launch whose workgroups stride over the
+// fronts of a level, with a grid-wide barrier between levels (forward: leaves
+// up; backward: top down).  The runtime guarantees that all workgroups of a
+// cooperative launch are resident, so the barrier always completes.
+constexpr int kMaxRunLevels = 16;
+struct LevelRun {
+  int nlev;
+  int begin[kMaxRunLevels + 1];
+};
+
+template <typename R, int NR, bool FWD>
+__global__ void __launch_bounds__(256) front_levels_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                           cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z,
+                                                           const cplx_t<R>* __restrict__ x, cplx_t<R>* __restrict__ xout,
+                                                           int nrhs, int r0, LevelRun run) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int t = 0; t < run.nlev; ++t) {
+    const int l = FWD ? t : run.nlev - 1 - t;
+    for (int fi = run.begin[l] + blockIdx.x; fi < run.begin[l + 1]; fi += gridDim.x) {
+      if (FWD) fwd_front_body<R, NR>(mf, arena, W, Z, x, nrhs, r0, fi);
+      else bwd_front_body<R, NR>(mf, arena, Z, xout, nrhs, r0, fi);
+      __syncthreads();
+    }
+    grid.sync();
   }
 }
 
@@ -1450,7 +1494,7 @@ template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
               void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxK,
               const int* level_maxP, const double* level_ent, const int* level_inv, int nlevels, void* partial_v,
-              int64_t partial_cap) {
+              int64_t partial_cap, bool persistent) {
   using C = cplx_t<R>;
   const C* arena = static_cast<const C*>(arena_v);
   C* W = static_cast<C*>(w_v);
@@ -1511,12 +1555,74 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     }
     timer_end(KC_TRI, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
   };
+  // A run of consecutive small-front levels [l0, l1) as one cooperative launch
+  // (false if it does not apply: too many levels, too much LDS, or the device
+  // cannot hold enough workgroups).
+  auto front_run = [&](int l0, int l1, bool fwd) {
+    if (!persistent || l1 - l0 < 2 || l1 - l0 > kMaxRunLevels) return false;
+    LevelRun run;
+    run.nlev = l1 - l0;
+    int mF = 0, mP = 0, mK = 0, mN = 0;
+    double ent = 0;
+    for (int l = l0; l < l1; ++l) {
+      run.begin[l - l0] = level_begin[l];
+      mF = std::max(mF, level_maxF[l]);
+      mP = std::max(mP, level_maxP[l]);
+      mK = std::max(mK, level_maxK[l]);
+      mN = std::max(mN, level_begin[l + 1] - level_begin[l]);
+      ent += fwd ? level_ent[3 * l] + level_ent[3 * l + 2] : level_ent[3 * l + 1] + level_ent[3 * l + 2];
+    }
+    run.begin[run.nlev] = level_begin[l1];
+    const size_t lds_row = sizeof(C) * (size_t)(fwd ? mF + mP : mP + mK);
+    if (lds_row * (nrhs >= 4 ? 4 : 1) > 65536) return false;
+    int dev = 0, cus = 0;
+    SPP_HIP(hipGetDevice(&dev));
+    SPP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    auto kernel_of = [&](int nr) {
+      return fwd ? (nr == 4 ? (const void*)front_levels_kernel<R, 4, true> : (const void*)front_levels_kernel<R, 1, true>)
+                 : (nr == 4 ? (const void*)front_levels_kernel<R, 4, false> : (const void*)front_levels_kernel<R, 1, false>);
+    };
+    for (int nr : {1, 4}) {
+      if (nr == 4 && nrhs < 4) continue;
+      int per_cu = 0;
+      SPP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_of(nr), 256, lds_row * nr));
+      if (per_cu < 1) return false;
+    }
+    const double passes = (nrhs / 4) + (nrhs % 4);
+    timer_begin(KC_TRI, st);
+    int r0 = 0;
+    while (r0 < nrhs) {
+      const int nr = (nrhs - r0 >= 4) ? 4 : 1;
+      const void* f = kernel_of(nr);
+      int per_cu = 0;
+      SPP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, lds_row * nr));
+      const unsigned grid = (unsigned)std::min<int64_t>((int64_t)per_cu * cus, mN);
+      MfDev mfv = mf;
+      const C* a = arena;
+      C* w = W;
+      C* z = Z;
+      const C* xi = xin;
+      C* xo = xout;
+      int nrhs_v = nrhs, r0_v = r0;
+      void* args[] = {&mfv, &a, &w, &z, &xi, &xo, &nrhs_v, &r0_v, &run};
+      SPP_HIP(hipLaunchCooperativeKernel(f, dim3(grid), dim3(256), args, (unsigned)(lds_row * nr), st));
+      r0 += nr;
+    }
+    timer_end(KC_TRI, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
+    return true;
+  };
   // level_ent per level: sum over fronts of p (p - 1) / 2, p (p + 1) / 2 and (F - p) p.
   for (int l = 0; l < nlevels; ++l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
     if (!level_inv[l]) {
+      int l1 = l + 1;
+      while (l1 < nlevels && !level_inv[l1]) ++l1;
+      if (front_run(l, l1, true)) {
+        l = l1 - 1;
+        continue;
+      }
       front(f0, nf, level_maxF[l], mP, mK, true, e[0] + e[2]);
       continue;
     }
@@ -1530,6 +1636,12 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
     if (!level_inv[l]) {
+      int l0 = l;
+      while (l0 > 0 && !level_inv[l0 - 1]) --l0;
+      if (front_run(l0, l + 1, false)) {
+        l = l0;
+        continue;
+      }
       front(f0, nf, level_maxF[l], mP, mK, false, e[1] + e[2]);
       continue;
     }
@@ -1550,10 +1662,10 @@ template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, vo
                                      int, bool, bool, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
-                               int64_t);
+                               int64_t, bool);
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                               const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
-                              int64_t);
+                              int64_t, bool);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
 

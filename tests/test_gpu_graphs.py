@@ -63,3 +63,25 @@ def test_graph_replays_for_an_uneven_batch():
             assert np.linalg.norm(cpu(a) - cpu(b)) <= 1e-13 * np.linalg.norm(cpu(b))
     E.close()
     G.close()
+
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_cooperative_substitution_matches_level_launches(prec):
+    """SPP_F_PERSISTENT runs consecutive small-front levels of the
+    substitution as one cooperative launch with grid barriers between levels;
+    the fronts see the same arithmetic, so the results must agree."""
+    from paper_1409_0297_amd import Solver
+    W = workloads.helmholtz_workload("mid", 5, 128, 2, 16.0, 16, 0.05, 8, nrhs=5)
+    A = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, prec=prec, tol=1e-11, max_iter=100, persistent=True)
+    B = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, prec=prec, tol=1e-11, max_iter=100)
+    rng = np.random.default_rng(21)
+    r = rng.standard_normal((5, W.n * W.n)) + 1j * rng.standard_normal((5, W.n * W.n))
+    za, zb = cpu(A.apply_precond(r)), cpu(B.apply_precond(r))
+    assert np.linalg.norm(za - zb) <= 1e-13 * np.linalg.norm(zb)
+    ua, ia, _, ca = A.solve(W.rhs)
+    ub, ib, _, cb = B.solve(W.rhs)
+    assert ca == cb == 0 and ia == ib
+    assert np.linalg.norm(cpu(ua) - cpu(ub)) <= 1e-13 * np.linalg.norm(cpu(ub))
+    A.close()
+    B.close()
