@@ -4,10 +4,14 @@ One step = one full pass of the hot path on one right-hand side: setup
 (shift and potential, Green kernel, stencils, assembly, nested-dissection
 multifrontal factorisation) followed by the preconditioned FGMRES solve and
 its true-residual check, on the 2D Helmholtz workload of a 512 x 512 grid,
-omega = 2 pi 64 (8 points per wavelength), 64 Gaussian bumps, b = 16.
-Inputs are generated once and are resident in GPU memory before timing.
+omega = 2 pi 64 (8 points per wavelength), 64 Gaussian bumps, b = 16,
+FGMRES to 1e-10 (the tolerance at which the solution matches the FP64 oracle
+to 1e-8, checked by tests/test_gpu_full_size.py).  Inputs are generated once
+and resident in GPU memory before timing.
 
-Prints one JSON line (see the design doc for the fields).
+The headline is the mixed-precision path (complex64 fronts, FP64 operator,
+residuals and GMRES); the same K steps are also timed with complex128 fronts
+and reported beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -30,42 +34,72 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", choices=["c128", "c64"], default="c128")
+    ap.add_argument("--prec", choices=["c64", "c128"], default="c64",
+                    help="front precision of the headline value")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--graphs", action="store_true", help="replay FGMRES iterations from a HIP graph")
+    ap.add_argument("--persistent", action="store_true",
+                    help="cooperative launch for runs of small-front substitution levels")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip tuning launch parameters in the warm-up step (SPP_F_AUTOTUNE)")
     ap.add_argument("--cpu-baseline", choices=["sample", "off"], default="sample")
     ap.add_argument("--profile-only", action="store_true",
-                    help="run the timed steps only (for rocprofv3), no baseline")
+                    help="run the timed steps only (for rocprofv3): no timing pass, no other precision, no baseline")
     return ap.parse_args()
 
 
-def cpu_baseline(W, gpu_iters):
-    """The oracle (plain FP64 numpy/scipy) on a bounded sample of the same workload.
+def cpu_baseline(gpu_iters, stats512, stats256):
+    """The oracle (plain FP64 numpy/scipy) timed on a bounded sample.
 
-    Sample: the complete oracle setup on the full 512^2 problem (shift,
-    stencils by explicit SVD pseudoinverse, sparse P, nested-dissection
-    elimination), the right-hand-side transform, and two FGMRES iterations of
-    the preconditioned solve; the per-iteration time is scaled to the
-    iteration count the GPU needed.  Returns a dict for the JSON line.
+    Sample: the complete oracle (shift, explicit-SVD stencils, sparse P,
+    nested-dissection elimination, G f, two FGMRES iterations) on the 256^2
+    member of the same family (omega = 2 pi 32, so the same 8 points per
+    wavelength and the same b = 16).  Each component is scaled to 512^2 by
+    what drives its cost: N for coefficients, stencils (their least-squares
+    matrices have N - |gamma| columns), assembly and G f; the factorisation
+    flops of the two nested-dissection plans for the elimination; the factor
+    entries for an FGMRES iteration, times the GPU's iteration count.
     """
-    from oracle import gmres, pipeline, spectral
+    import workloads
+    from oracle import gmres, nested, pipeline, spectral, stencil
+    W = workloads.helmholtz_workload("helmholtz2d_n256_w32", 2, 256, 2, 32.0, 64, 0.05, 16)
+    t = {}
     t0 = time.perf_counter()
-    o = pipeline.setup_workload(W)
-    t1 = time.perf_counter()
+    s, q, _ = pipeline.coefficients(W.kind, W.n, W.d, W.coeff, W.omega)
+    t["coefficients"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st = stencil.Stencils(W.n, W.d, W.b, s)
+    t["stencils"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P = st.P_matrix(q)
+    t["assembly"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fac = nested.NDFactor(P, nested.nd_levels(W.n, W.d, W.b, "octree"))
+    t["factorisation"] = time.perf_counter() - t0
+    o = pipeline.OracleSetup(n=W.n, d=W.d, b=W.b, s=s, q=q, shift_moves=0, stencils=st, P=P, factor=fac)
+    t0 = time.perf_counter()
     g = pipeline.rhs_transform(o, W.rhs[0])
-    t2 = time.perf_counter()
+    t["rhs"] = time.perf_counter() - t0
     A = lambda z: spectral.apply_integral(z, o.d, o.s, o.q)
     M = lambda r: pipeline.precondition(o, r)
+    t0 = time.perf_counter()
     _, its, _ = gmres.fgmres(A, g, M, tol=1e-300, max_iter=2)
-    t3 = time.perf_counter()
-    t_iter = (t3 - t2) / its
-    t_total = (t1 - t0) + (t2 - t1) + t_iter * gpu_iters
+    t["iteration"] = (time.perf_counter() - t0) / its
+    rN = 4.0
+    rF = stats512["factor_flops"] / stats256["factor_flops"]
+    rE = stats512["factor_entries"] / stats256["factor_entries"]
+    est = ((t["coefficients"] + t["stencils"] + t["assembly"] + t["rhs"]) * rN + t["factorisation"] * rF
+           + t["iteration"] * rE * gpu_iters)
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         threads = os.cpu_count()
-    return {"value": 1.0 / t_total, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle setup on the full problem ({t1 - t0:.1f} s) + G f ({t2 - t1:.2f} s) + "
-                      f"2 FGMRES iterations ({t_iter:.2f} s each) scaled to the GPU's {gpu_iters}"}
+    sample = ("oracle on the 256^2 member of the workload family (omega = 2 pi 32, b = 16): "
+              + ", ".join(f"{k} {v:.2f} s" for k, v in t.items())
+              + f"; scaled to 512^2 by N (x{rN:.0f}), factorisation flops (x{rF:.2f}) and factor entries"
+              f" (x{rE:.2f}) times {gpu_iters} iterations")
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": threads, "kind": "oracle", "sample": sample,
+            "est_seconds_per_solve": est}
 
 
 KCLASS_BOUND = {"fft": "hbm", "gemv": "hbm", "tri": "hbm", "qapply": "hbm", "gemm": "mfma"}
@@ -100,7 +134,6 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import workloads
@@ -114,8 +147,11 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     pb = spp.binding.spp_problem(dim=W.d, n=W.n, b=W.b, kind=spp.SPP_HELMHOLTZ, omega=W.omega,
                                  ell=1.0, energy=0.0, coeff=coeff.data_ptr())
-    def options(flags):
-        return spp.binding.spp_options(prec=spp.SPP_C128 if args.prec == "c128" else spp.SPP_C64_FRONTS,
+    base_flags = ((spp.SPP_F_GRAPHS if args.graphs else 0) | (spp.SPP_F_PERSISTENT if args.persistent else 0)
+                  | (spp.SPP_F_AUTOTUNE if args.autotune else 0))
+
+    def options(prec, flags):
+        return spp.binding.spp_options(prec=spp.SPP_C128 if prec == "c128" else spp.SPP_C64_FRONTS,
                                        order=spp.SPP_ORDER_OCTREE, tol=args.tol, max_iter=200, flags=flags)
 
     def step(op):
@@ -123,24 +159,28 @@ def main():
         code, iters, relres = spp.spp_solve(h, f.data_ptr(), 1, u.data_ptr(), stream)
         return h, iters[0], relres[0]
 
-    plain = options(0)
-    for _ in range(args.warmup):
-        spp.spp_destroy(step(plain)[0])
-    torch.cuda.synchronize()
-    # Timed region: K full steps (setup + solve), inputs already in HBM.
-    t0 = time.perf_counter()
-    rec = [step(plain) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    st = spp.spp_stats(rec[-1][0])
-    iters = [r[1] for r in rec]
-    for h, _, _ in rec:
-        spp.spp_destroy(h)
-    # Same K steps again with per-kernel-class HIP events on the launch stream.
+    def timed_run(prec):
+        plain = options(prec, base_flags)
+        for _ in range(args.warmup):
+            spp.spp_destroy(step(plain)[0])
+        torch.cuda.synchronize()
+        # Timed region: K full steps (setup + solve), inputs already in HBM.
+        t0 = time.perf_counter()
+        rec = [step(plain) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = spp.spp_stats(rec[-1][0])
+        for h, _, _ in rec:
+            spp.spp_destroy(h)
+        return dt, st, rec[-1][1], rec[-1][2]
+
+    dt, st, iters, relres = timed_run(args.prec)
+    # The same K steps again with per-kernel-class HIP events on the launch stream.
     timing = None
+    other = None
     if not args.profile_only:
         timing = {k: {"ms": 0.0, "launches": 0, "bytes": 0.0, "flops": 0.0} for k in spp.KERNEL_CLASSES}
-        timed = options(spp.SPP_F_TIMING)
+        timed = options(args.prec, spp.SPP_F_TIMING | (base_flags & (spp.SPP_F_PERSISTENT | spp.SPP_F_AUTOTUNE)))
         for _ in range(args.steps):
             h, _, _ = step(timed)
             for name, kc in spp.KERNEL_CLASSES.items():
@@ -148,6 +188,10 @@ def main():
                 for key in timing[name]:
                     timing[name][key] += t[key]
             spp.spp_destroy(h)
+        oprec = "c128" if args.prec == "c64" else "c64"
+        odt, ost, oit, orr = timed_run(oprec)
+        other = {"fronts": oprec, "value": 1.0 / odt, "ms_per_step": odt * 1e3, "gmres_iters": oit,
+                 "relres": orr, "t_setup_ms": ost["t_setup_ms"], "t_solve_ms": ost["t_solve_ms"]}
     out = {
         "metric": "solves/sec to rel. err 1e-8 (mixed vs FP64), GMRES iters, HBM/MFMA % peak",
         "value": 1.0 / dt,
@@ -159,25 +203,34 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "c128" else "c64-fronts/f64",
+        "dtype": "c64-fronts/f64" if args.prec == "c64" else "f64",
         "data": "synthetic",
         "config": {"workload": W.name, "grid": [W.n, W.n], "omega_over_2pi": 64, "b": W.b,
                    "bumps": 64, "nrhs": 1, "tol": args.tol, "ordering": "octree",
-                   "fronts": args.prec},
-        "gmres_iters": iters[-1],
-        "relres": rec[-1][2],
+                   "fronts": args.prec, "outer": "f64", "graphs": args.graphs,
+                   "persistent": args.persistent, "autotune": args.autotune},
+        "gmres_iters": iters,
+        "relres": relres,
         "t_setup_ms": st["t_setup_ms"],
         "t_factor_ms": st["t_factor_ms"],
         "t_solve_ms": st["t_solve_ms"],
         "factor_gb": st["factor_bytes"] / 1e9,
         "factor_gflop": st["factor_flops"] / 1e9,
+        "other_precision": other,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in timing.items()} if timing else None,
         "roofline": roofline(timing, args.prec) if timing else None,
         "cpu_baseline": None,
     }
     if not args.profile_only and args.cpu_baseline == "sample":
-        print("bench: timing the CPU oracle baseline (about a minute)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(W, iters[-1])
+        print("bench: timing the CPU oracle baseline (about half a minute)", file=sys.stderr, flush=True)
+        W2 = workloads.helmholtz_workload("helmholtz2d_n256_w32", 2, 256, 2, 32.0, 64, 0.05, 16)
+        c2 = torch.as_tensor(W2.coeff, dtype=torch.float64, device=dev).contiguous()
+        pb2 = spp.binding.spp_problem(dim=2, n=256, b=16, kind=spp.SPP_HELMHOLTZ, omega=W2.omega,
+                                      ell=1.0, energy=0.0, coeff=c2.data_ptr())
+        h2 = spp.spp_setup(pb2, options("c128", 0), stream)
+        st256 = spp.spp_stats(h2)
+        spp.spp_destroy(h2)
+        out["cpu_baseline"] = cpu_baseline(iters, st, st256)
     print(json.dumps(out), flush=True)
 
 

@@ -86,6 +86,8 @@ typedef struct {
                                      small-front levels as one cooperative
                                      launch with grid barriers between levels
                                      (not inside graph replays)               */
+#define SPP_F_AUTOTUNE 32         /* run spp_autotune before the first solve of
+                                     each right-hand-side count               */
 #define SPP_F_GRAPHS 8            /* capture one FGMRES iteration in a HIP graph
                                      (once per factor and nrhs) and replay it
                                      with the step index in device memory;
@@ -151,6 +153,14 @@ int spp_setup_batch(const spp_problem* problems, int32_t count, const spp_option
  * Returns SPP_NOT_CONVERGED (u still written) if any RHS missed tol. */
 int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u,
               int32_t* iters, double* relres, spp_stream_t stream);
+
+/* Times candidate launch parameters on this factor's shapes (lines per
+   workgroup of each FFT pass, column chunks of each substitution product with
+   explicit inverses) for nrhs right-hand sides and keeps the fastest in a
+   process-wide table keyed by kernel, architecture and shape; later factors
+   with the same shapes use it.  If the environment variable SPP_TUNE_CACHE
+   names a file, the table is read from it at first use and rewritten here. */
+int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream);
 
 /* ---- components of the hot path, exposed for testing and benchmarking ----- */
 

@@ -21,6 +21,7 @@ SPP_F_TIMING = 2
 SPP_F_PARTIAL_PIVOTING = 4
 SPP_F_GRAPHS = 8
 SPP_F_PERSISTENT = 16
+SPP_F_AUTOTUNE = 32
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
 KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
 
@@ -90,6 +91,7 @@ def library():
         "spp_attach_cnn": (I, [P, P, D]),
         "spp_learned_stats": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "spp_get_krylov": (I, [P, I, P, P]),
+        "spp_autotune": (I, [P, I, P]),
         "spp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -227,7 +229,7 @@ class Solver:
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
                  timing: bool = False, partial_pivoting: bool = False, graphs: bool = False,
-                 persistent: bool = False):
+                 persistent: bool = False, autotune: bool = False):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -244,7 +246,8 @@ class Solver:
                          | (SPP_F_TIMING if timing else 0)
                          | (SPP_F_PARTIAL_PIVOTING if partial_pivoting else 0)
                          | (SPP_F_GRAPHS if graphs else 0)
-                         | (SPP_F_PERSISTENT if persistent else 0))
+                         | (SPP_F_PERSISTENT if persistent else 0)
+                         | (SPP_F_AUTOTUNE if autotune else 0))
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:
@@ -517,3 +520,7 @@ def spp_learned_stats(handle):
 
 def spp_get_krylov(handle, j: int, v_ptr, z_ptr):
     _check(library().spp_get_krylov(handle, j, v_ptr, z_ptr), "spp_get_krylov")
+
+
+def spp_autotune(handle, nrhs: int, stream: int):
+    _check(library().spp_autotune(handle, nrhs, ctypes.c_void_p(stream)), "spp_autotune")

@@ -264,6 +264,7 @@ struct spp_factor {
   int* kvec = nullptr;
   double* h_resid = nullptr;   // pinned host copy of residual estimates
   spp_stats_t stats{};
+  int tuned_nrhs = 0;          // right-hand-side count the last autotune covered
   spp_cnn* cnn = nullptr;      // learned FGMRES stage (not owned)
   double cnn_rho = 0.9;
   int cnn_accepted = 0, cnn_rejected = 0;
@@ -453,6 +454,77 @@ void validate_problem(const spp_problem* pb) {
   // neighbourhood staged in LDS: |gamma(S)| <= 1024 (2D: b <= 30, 3D: b <= 9).
   const int g = (pb->dim == 2) ? (pb->b + 1) * (pb->b + 1) : (pb->b + 1) * (pb->b + 1) * (pb->b + 1);
   if (g > 1024) throw Error(SPP_ENOTIMPL, "leaf box too large: (b + 1)^d must be <= 1024");
+}
+
+// Times the candidate launch parameters of this factor's FFT passes and
+// substitution products (right-hand-side count nrhs) and stores the fastest
+// in the process-wide tuning table (and its file, if SPP_TUNE_CACHE is set).
+void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
+  ensure_solve_buffers(F, nrhs, F->opt.max_iter);
+  KernelTimer* saved = g_timer;
+  g_timer = nullptr;
+  const int64_t vstride = (int64_t)nrhs * F->Ntot;
+  SPP_HIP(hipMemsetAsync(F->wk, 0, sizeof(double2) * vstride, st));
+  SPP_HIP(hipMemsetAsync(F->tmp, 0, sizeof(double2) * vstride, st));
+  SPP_HIP(hipMemsetAsync(F->qr, 0, sizeof(double2) * vstride, st));
+  SPP_HIP(hipMemsetAsync(F->wv, 0, (size_t)F->planp->vec_elems * nrhs * F->csize, st));
+  SPP_HIP(hipMemsetAsync(F->zv, 0, (size_t)F->planp->vec_elems * nrhs * F->csize, st));
+  SPP_HIP(hipMemsetAsync(F->xc, 0, (size_t)F->Ntot * nrhs * F->csize, st));
+  for (const SppGroup& g : F->groups) {
+    const int batch = g.ninst * nrhs;
+    const int64_t o = g.Noff * nrhs, n = g.n;
+    std::vector<std::pair<int64_t, int64_t>> axes;
+    if (g.d == 2) axes = {{n, 1}, {1, n}};
+    else axes = {{n * n, 1}, {n, n}, {1, n * n}};
+    for (const auto& ax : axes) {
+      const std::string key = fft_tune_key(g.n, ax.first, ax.second, batch);
+      if (tune_has(key)) continue;
+      int best = fft_lines_default(g.n, ax.first, ax.second);
+      float bt = 1e30f;
+      for (int L = 1; (int64_t)L * n <= 4096; L *= 2) {
+        if (!fft_lines_valid(g.n, ax.first, ax.second, L)) continue;
+        tune_force(key, L);
+        const float t = tune_time(st, 3, [&] {
+          fft_axis(st, F->wk + o, F->tmp + o, g.tw, g.n, ax.first, ax.second, g.N, batch, -1, nullptr, nullptr,
+                   nullptr, nrhs);
+        });
+        if (t < bt) { bt = t; best = L; }
+      }
+      tune_force(key, -1);
+      tune_set(key, best);
+    }
+  }
+  const Plan& P = *F->planp;
+  for (size_t l = 0; l < P.levels.size(); ++l) {
+    if (!F->level_inv[l]) continue;
+    const Level& L = P.levels[l];
+    const int nf = L.end - L.begin, mP = L.maxP, mK = L.maxK;
+    struct Prod { int rows, cols, mode; };
+    std::vector<Prod> prods = {{mP, mP, 0}, {mP, mP, 3}};
+    if (mK > 0) { prods.push_back({mK, mP, 1}); prods.push_back({mP, mK, 2}); }
+    for (const Prod& pr : prods) {
+      const std::string key = gemv_tune_key(pr.rows, pr.cols, nf, pr.mode, nrhs, (int)F->csize);
+      if (tune_has(key)) continue;
+      int best = gemv_chunks_default(pr.rows, pr.cols, nf, nrhs, F->gpart_cap);
+      float bt = 1e30f;
+      for (int c = 1; c <= std::max(1, pr.cols / 16) && c <= 256; c *= 2) {
+        if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
+        const float t = tune_time(st, 3, [&] {
+          if (F->opt.prec == SPP_C128)
+            mf_gemv<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
+                            0.0, F->gpart, F->gpart_cap, c);
+          else
+            mf_gemv<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
+                           0.0, F->gpart, F->gpart_cap, c);
+        });
+        if (t < bt) { bt = t; best = c; }
+      }
+      tune_set(key, best);
+    }
+  }
+  tune_save();
+  g_timer = saved;
+  F->tuned_nrhs = nrhs;
 }
 
 int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream_t st, spp_factor** out) {
@@ -666,6 +738,7 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   TimerScope timer_scope(F);
   const int maxit = F->opt.max_iter;
   ensure_solve_buffers(F, nrhs, maxit);
+  if ((F->opt.flags & SPP_F_AUTOTUNE) && F->tuned_nrhs != nrhs) do_autotune(F, nrhs, st);
   const int64_t vstride = (int64_t)nrhs * F->Ntot;   // one Krylov vector of the whole batch
   const int ld = F->cap_iter + 1;                     // Hessenberg column stride, per-column vector stride
   const int hrhs = ld * F->cap_iter;                  // Hessenberg stride between columns
@@ -865,6 +938,14 @@ int spp_setup_batch(const spp_problem* problems, int32_t count, const spp_option
 int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u, int32_t* iters, double* relres,
               spp_stream_t stream) {
   return guarded([&] { return do_solve(factor, f, nrhs, u, iters, relres, reinterpret_cast<hipStream_t>(stream)); });
+}
+
+int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream) {
+  return guarded([&] {
+    if (!factor || nrhs < 1) throw Error(SPP_EINVAL, "null factor or nrhs < 1");
+    do_autotune(factor, nrhs, reinterpret_cast<hipStream_t>(stream));
+    return SPP_OK;
+  });
 }
 
 int spp_apply_operator(spp_factor* factor, const void* z, void* w, int32_t nrhs, spp_stream_t stream) {

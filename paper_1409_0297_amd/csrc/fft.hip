@@ -177,6 +177,26 @@ bool fft_supported(int n) {
   return n == 1;
 }
 
+// Lines per workgroup: a power of two dividing the line count (and the
+// inner stride), with two LDS buffers of L n complex values (<= 128 KB).
+bool fft_lines_valid(int n, int64_t outer, int64_t inner, int L) {
+  if (L < 1 || (L & (L - 1)) || (int64_t)L * n > 4096) return false;
+  const int64_t lines = outer * inner;
+  return lines % L == 0 && (inner == 1 || inner % L == 0);
+}
+
+// Default: fill about 2048 points of LDS per buffer.
+int fft_lines_default(int n, int64_t outer, int64_t inner) {
+  int L = 1;
+  while (2 * L * n <= 2048) L *= 2;
+  while (L > 1 && !fft_lines_valid(n, outer, inner, L)) L /= 2;
+  return L;
+}
+
+std::string fft_tune_key(int n, int64_t outer, int64_t inner, int batch) {
+  return tune_key("fft_lines", {n, outer, inner, batch});
+}
+
 void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw, int n,
               int64_t outer, int64_t inner, int64_t N, int batch, int dir,
               const double* pre, const double* mid, const double2* add, int per) {
@@ -191,11 +211,9 @@ void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw
   while (m % 3 == 0) { g.radix[s++] = 3; m /= 3; }
   if (m != 1 || s > kMaxStages) throw Error(-7, "FFT length must be 2^a 3^b");
   g.nstages = s;
-  // Lines per workgroup: fill ~2048 points of LDS per buffer, keep coalescing.
-  int L = 1;
-  while (2 * L * n <= 2048) L *= 2;
   const int64_t lines = outer * inner;
-  while (L > 1 && (lines % L || (inner > 1 && inner % L))) L /= 2;
+  int L = tune_get(fft_tune_key(n, outer, inner, batch), fft_lines_default(n, outer, inner));
+  if (!fft_lines_valid(n, outer, inner, L)) L = fft_lines_default(n, outer, inner);
   g.L = L;
   const size_t lds = 2 * sizeof(double2) * L * n;
   const unsigned blocks = static_cast<unsigned>(batch * (lines / L));

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
+#include <initializer_list>
+#include <string>
 
 struct spp_cnn;
 
@@ -165,6 +168,30 @@ void kr_copy_j(hipStream_t st, const double2* src, int64_t src_jstride, double2*
                int64_t dst_jstride, int64_t count, const int* dj);
 // *c = value, or *c += value (a kernel, so that it can sit in a captured graph).
 void kr_set_counter(hipStream_t st, int* c, int value, bool add);
+
+// ------------------------------------------------------------- tune.cpp
+// Tuned launch parameters (see tune.cpp): tune_get returns the tuned value of
+// a shape key, or fallback.
+std::string tune_key(const char* kind, std::initializer_list<int64_t> sizes);
+int tune_get(const std::string& key, int fallback);
+void tune_force(const std::string& key, int value);   // value < 0 clears
+void tune_set(const std::string& key, int value);
+bool tune_has(const std::string& key);
+void tune_save();
+float tune_time(hipStream_t st, int reps, const std::function<void()>& fn);
+
+// FFT lines per workgroup: heuristic, valid candidates, key (fft.hip).
+int fft_lines_default(int n, int64_t outer, int64_t inner);
+bool fft_lines_valid(int n, int64_t outer, int64_t inner, int L);
+std::string fft_tune_key(int n, int64_t outer, int64_t inner, int batch);
+
+// One substitution product (gemv_kernel mode) of a level of fronts with a
+// given split-K chunk count (0: tuned or heuristic); mf.hip.
+template <typename R>
+void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena, void* W, void* Z, void* xout, int nrhs, int f0, int nf,
+             int rows, int cols, int mode, double ent, void* partial, int64_t partial_cap, int nchunks);
+int gemv_chunks_default(int rows, int cols, int nf, int nrhs, int64_t partial_cap);
+std::string gemv_tune_key(int rows, int cols, int nf, int mode, int nrhs, int csize);
 
 // ------------------------------------------------------------- cnn.hip
 // Learned preconditioner stage: y = out_scale * net(in_scale * x) per sample,

@@ -1490,6 +1490,61 @@ void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int 
   timer_end(KC_QAPPLY, st, 32.0 * mf.Ntot * nrhs, 0.0);
 }
 
+int gemv_chunks_default(int rows, int cols, int nf, int nrhs, int64_t partial_cap) {
+  const int rtiles = (int)ceil_div(rows, 64);
+  int nchunks = 1;
+  if ((int64_t)rtiles * nf < 1024) {
+    nchunks = (int)std::min<int64_t>(std::max(1, cols / 64), 2048 / ((int64_t)rtiles * nf));
+    if (nchunks < 1) nchunks = 1;
+  }
+  while (nchunks > 1 && (int64_t)nf * nchunks * rows * nrhs > partial_cap) --nchunks;
+  return nchunks;
+}
+
+std::string gemv_tune_key(int rows, int cols, int nf, int mode, int nrhs, int csize) {
+  return tune_key("gemv_chunks", {rows, cols, nf, mode, nrhs, csize});
+}
+
+// Row-tiled products; large fronts split their columns over nchunks
+// workgroups (deterministic partial sums, then gemv_finish_kernel).
+template <typename R>
+void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, void* Z_v, void* xout_v, int nrhs, int f0,
+             int nf, int rows, int cols, int mode, double ent, void* partial_v, int64_t partial_cap, int nchunks) {
+  using C = cplx_t<R>;
+  const C* arena = static_cast<const C*>(arena_v);
+  C* W = static_cast<C*>(W_v);
+  C* Z = static_cast<C*>(Z_v);
+  C* xout = static_cast<C*>(xout_v);
+  C* partial = static_cast<C*>(partial_v);
+  const int rtiles = (int)ceil_div(rows, 64);
+  if (nchunks <= 0)
+    nchunks = tune_get(gemv_tune_key(rows, cols, nf, mode, nrhs, (int)sizeof(C)),
+                       gemv_chunks_default(rows, cols, nf, nrhs, partial_cap));
+  nchunks = std::max(1, std::min(nchunks, std::max(1, cols)));
+  while (nchunks > 1 && (int64_t)nf * nchunks * rows * nrhs > partial_cap) --nchunks;
+  dim3 grid(rtiles * nchunks, nf);
+  // ent: factor entries of the level read per pass over the right-hand sides.
+  const double passes = (nrhs / 4) + (nrhs % 4);
+  timer_begin(KC_GEMV, st);
+  int r0 = 0;
+  while (r0 < nrhs) {
+    if (nrhs - r0 >= 4) {
+      gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
+      r0 += 4;
+    } else {
+      gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
+      r0 += 1;
+    }
+    SPP_LAUNCH_CHECK();
+  }
+  if (nchunks > 1) {
+    gemv_finish_kernel<R><<<dim3(ceil_div((int64_t)rows * nrhs, 256), nf), 256, 0, st>>>(
+        mf, W, Z, xout, nrhs, f0, mode, nchunks, partial, rows);
+    SPP_LAUNCH_CHECK();
+  }
+  timer_end(KC_GEMV, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
+}
+
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
               void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxK,
@@ -1505,34 +1560,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
   // Row-tiled products; large fronts split their columns over several
   // workgroups (deterministic partial sums, then gemv_finish_kernel).
   auto gemv = [&](int f0, int nf, int rows, int cols, int mode, double ent) {
-    const int rtiles = (int)ceil_div(rows, 64);
-    int nchunks = 1;
-    if ((int64_t)rtiles * nf < 1024) {
-      nchunks = (int)std::min<int64_t>(std::max(1, cols / 64), 2048 / ((int64_t)rtiles * nf));
-      if (nchunks < 1) nchunks = 1;
-      while (nchunks > 1 && (int64_t)nf * nchunks * rows * nrhs > partial_cap) --nchunks;
-    }
-    dim3 grid(rtiles * nchunks, nf);
-    // ent: factor entries of the level read per pass over the right-hand sides.
-    const double passes = (nrhs / 4) + (nrhs % 4);
-    timer_begin(KC_GEMV, st);
-    int r0 = 0;
-    while (r0 < nrhs) {
-      if (nrhs - r0 >= 4) {
-        gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
-        r0 += 4;
-      } else {
-        gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
-        r0 += 1;
-      }
-      SPP_LAUNCH_CHECK();
-    }
-    if (nchunks > 1) {
-      gemv_finish_kernel<R><<<dim3(ceil_div((int64_t)rows * nrhs, 256), nf), 256, 0, st>>>(
-          mf, W, Z, xout, nrhs, f0, mode, nchunks, partial, rows);
-      SPP_LAUNCH_CHECK();
-    }
-    timer_end(KC_GEMV, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
+    mf_gemv<R>(st, mf, arena, W, Z, xout, nrhs, f0, nf, rows, cols, mode, ent, partial, partial_cap, 0);
   };
   // Whole-front kernels of the levels solved with the LU in place.
   auto front = [&](int f0, int nf, int maxF, int maxP, int maxK, bool fwd, double ent) {
@@ -1666,6 +1694,10 @@ template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, vo
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                               const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
                               int64_t, bool);
+template void mf_gemv<double>(hipStream_t, const MfDev&, const void*, void*, void*, void*, int, int, int, int, int, int,
+                              double, void*, int64_t, int);
+template void mf_gemv<float>(hipStream_t, const MfDev&, const void*, void*, void*, void*, int, int, int, int, int, int,
+                             double, void*, int64_t, int);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
 
