@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-baseline", choices=["sample", "off"], default="sample")
     ap.add_argument("--profile-only", action="store_true",
                     help="run the timed steps only (for rocprofv3): no timing pass, no other precision, no baseline")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the steps, copy a MIB-MiB device buffer once (a plain copy kernel of known "
+                         "size, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -105,6 +108,25 @@ def cpu_baseline(gpu_iters, stats512, stats256):
 KCLASS_BOUND = {"fft": "hbm", "gemv": "hbm", "tri": "hbm", "qapply": "hbm", "gemm": "mfma"}
 
 
+def measured_traffic(kernel_class, prec):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel
+    of known size), or None when there is none for this class or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"large2d_{prec}_front_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    fields = dict(re.findall(r"^(\w+): (\S+)$", text, flags=re.M))
+    src = os.path.join(ROOT, "paper_1409_0297_amd", "csrc", "mf.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_class") != kernel_class or fields.get("source_sha256") != sha:
+        return None
+    return float(fields["traffic_per_launch_bytes"])
+
+
 def roofline(timing, prec):
     """Dominant roofline-bound kernel class of the timed region."""
     best = None
@@ -124,7 +146,7 @@ def roofline(timing, prec):
         achieved = t["flops"] / sec / 1e12
         peak, unit = (FP64_PEAK_TFS if prec == "c128" else FP32_PEAK_TFS), "TFLOP/s"
     return {"bound": KCLASS_BOUND[best], "kernel_class": best, "achieved": achieved, "peak": peak,
-            "unit": unit, "frac": achieved / peak, "traffic": None,
+            "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(best, prec),
             "avg_launch_us": 1e3 * t["ms"] / t["launches"], "launches": t["launches"],
             "algorithmic_per_launch": (t["bytes"] if KCLASS_BOUND[best] == "hbm" else t["flops"]) / t["launches"]}
 
@@ -174,6 +196,15 @@ def main():
             spp.spp_destroy(h)
         return dt, st, rec[-1][1], rec[-1][2]
 
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: copied {nbytes} bytes device to device", file=sys.stderr, flush=True)
+        del src, dst
     dt, st, iters, relres = timed_run(args.prec)
     # The same K steps again with per-kernel-class HIP events on the launch stream.
     timing = None
