@@ -92,7 +92,6 @@ struct PlanDevice {
   AsmBlockDev* blocks = nullptr;
   int *pos = nullptr, *idx = nullptr, *map = nullptr;
   std::vector<int*> type_off;      // per problem, per set type: device offsets
-  std::vector<int> level_inv;
   std::vector<double> level_ent;   // 3 per level, see mf_solve
   std::vector<std::vector<int>> level_F, level_p;
   int perm_total = 0;
@@ -158,9 +157,10 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
   for (size_t fi = 0; fi < P.fronts.size(); ++fi)
     for (int c : P.fronts[fi].children) parent[c] = static_cast<int>(fi);
   for (const Level& L : P.levels) {
+    // Inverse work slots for every level (the precision decides which
+    // levels use them).
     int64_t xo = 0;
-    const bool inv = mf_level_uses_inverse(L.end - L.begin, L.maxF, L.maxP);
-    pd->level_inv.push_back(inv ? 1 : 0);
+    const bool inv = true;
     double e0 = 0, e1 = 0, e2 = 0;
     std::vector<int> hF, hP;
     for (int fi = L.begin; fi < L.end; ++fi) {
@@ -658,6 +658,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   mf.map = F->pd->map;
   mf.perm = F->dalloc<int>(F->pd->perm_total);
   mf.ipiv = F->dalloc<int>(F->pd->perm_total);
+  mf.prow = F->dalloc<int>(F->pd->perm_total);
   mf.info = info;
   mf.inst = F->inst_dev;
   mf.ninst = count;
@@ -678,7 +679,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     F->level_maxP.push_back(L.maxP);
   }
   F->level_begin.push_back(static_cast<int>(P.fronts.size()));
-  F->level_inv = F->pd->level_inv;
+  for (const Level& L : P.levels)
+    F->level_inv.push_back(mf_level_uses_inverse(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS) ? 1 : 0);
 
   F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
   void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);

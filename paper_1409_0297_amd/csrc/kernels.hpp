@@ -107,6 +107,7 @@ struct MfDev {
   const int* map;
   int* perm;           // final row permutation of each front's pivot block
   int* ipiv;           // LAPACK-style interchange record written by the panel
+  int* prow;           // block-local pivoting: row order of each 32-row block (front rows)
   int* info;           // [0] = breakdown front + 1 (0 if none)
   const InstDev* inst; // device array, one entry per instance
   // Host-side summary (launch geometry).
@@ -123,7 +124,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, 
                      const int* hF, const int* hP);   // host: F and p of the level's fronts
 // Whether a level keeps explicit inverses of its pivot-block factors (few large
 // fronts) or solves with the LU in place (many small fronts).
-bool mf_level_uses_inverse(int nfronts, int maxF, int maxP);
+bool mf_level_uses_inverse(int nfronts, int maxF, int maxP, bool c64);
 
 // y = Q r for every instance of the batch (vectors in the batch layout).
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);

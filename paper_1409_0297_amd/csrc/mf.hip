@@ -471,6 +471,7 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
     X[k][c] = (c >= k) ? D[pr][c] : Lm[pr][c];
   }
   __syncthreads();
+  if (tid < kb) mf.prow[f.perm + k0 + tid] = k0 + rsel[tid];
   if (tid == 0) {
     // The same permutation as a LAPACK-style interchange sequence.
     int cur[kDB], where[kDB];
@@ -636,11 +637,12 @@ __global__ void __launch_bounds__(256) trsm_kernel(MfDev mf, cplx_t<R>* __restri
 constexpr int kBM = 64, kBN = 64, kBK = 16;
 
 // One 64 x 64 tile (rows m0.., columns n0..) of C = from_c ? C + sgn A B : sgn A B,
-// complex column-major operands, k restricted to [kbeg, kend).
+// complex column-major operands, k restricted to [kbeg, kend).  brow (optional)
+// maps row gk of B to row brow[gk] - brow_off (a row permutation of B).
 template <typename R>
 __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, const cplx_t<R>* __restrict__ Bp, int ldb,
                                  cplx_t<R>* __restrict__ Cp, int ldc, int m, int n, int k, int m0, int n0, bool from_c,
-                                 R sgn, int kbeg, int kend) {
+                                 R sgn, int kbeg, int kend, const int* brow = nullptr, int brow_off = 0) {
   using C = cplx_t<R>;
   using V = typename Acc<R>::type;
   __shared__ C As[kBK][kBM + 1];
@@ -675,7 +677,8 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
     for (int e = threadIdx.x; e < kBK * kBN; e += 256) {
       const int kk = e % kBK, col = e / kBK;
       const int gk = kk0 + kk, gc = n0 + col;
-      Bs[kk][col] = (gk < kend && gc < n) ? Bp[(int64_t)gc * ldb + gk] : cmake<C>(0, 0);
+      const int br = brow ? brow[gk < kend ? gk : 0] - brow_off : gk;
+      Bs[kk][col] = (gk < kend && gc < n) ? Bp[(int64_t)gc * ldb + br] : cmake<C>(0, 0);
     }
     __syncthreads();
 #pragma unroll
@@ -709,6 +712,14 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
       }
 }
 
+// Front GEMMs of one elimination step (k0 = step block, kb <= 32 columns):
+//   mode 0: trailing update  A22 -= L21 U12
+//   mode 1: L inverse update XL[k0+kb:p, 0:k0+kb] -= L[k0+kb:p, k0:k0+kb] XL[k0:k0+kb, 0:k0+kb]
+//   mode 2: U inverse update XU[0:k0, k0:p]       -= U[0:k0, k0:k0+kb]    XU[k0:k0+kb, k0:p]
+//   mode 7: L21 = A21 Uinv_kk (first tiles_m workgroups) and U12 = Linv_kk P A12
+//           (the rest), P the step's row order from the diagonal-block LU,
+//           applied while loading A12.  Both overwrite their input block;
+//           every workgroup reads all of its own block before writing it.
 template <typename R>
 __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                                    const cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode,
@@ -716,61 +727,82 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   int k0, kb;
-  if (!step_range<R>(f, (mode == 2 || mode == 6) ? 2 : 0, step, nb, k0, kb)) return;
+  if (!step_range<R>(f, mode == 2 ? 2 : 0, step, nb, k0, kb)) return;
   const int F = f.F, p = f.p;
   C* base = arena + f.off;
   const C *Ap, *Bp;
   C* Cp;
   int m, n, k, lda, ldb, ldc;
-  // Modes 3-6 overwrite C with A B (C aliases an input; every workgroup reads
-  // all of its own input block before it writes it back).
-  const bool assign = mode >= 3;
-  const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
-  const C* Ui = Li + kDB * kDB;
-  if (mode == 3) {            // U12 = Linv_kk (P A12)
-    m = kb; n = F - k0 - kb; k = kb;
-    Ap = Li; lda = kDB;
-    Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
-    Cp = base + (int64_t)(k0 + kb) * F + k0; ldc = F;
-  } else if (mode == 4) {     // L21 = A21 Uinv_kk
-    m = F - k0 - kb; n = kb; k = kb;
-    Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
-    Bp = Ui; ldb = kDB;
-    Cp = base + (int64_t)k0 * F + (k0 + kb); ldc = F;
-  } else if (mode == 5) {     // XL rows = Linv_kk XL rows
-    C* XL = xwork + f.xoff;
-    m = kb; n = k0 + kb; k = kb;
-    Ap = Li; lda = kDB;
-    Bp = XL + k0; ldb = p;
-    Cp = XL + k0; ldc = p;
-  } else if (mode == 6) {     // XU rows = Uinv_kk XU rows
-    C* XU = xwork + f.xoff + (int64_t)p * p;
-    m = kb; n = p - k0; k = kb;
-    Ap = Ui; lda = kDB;
-    Bp = XU + (int64_t)k0 * p + k0; ldb = p;
-    Cp = XU + (int64_t)k0 * p + k0; ldc = p;
-  } else if (mode == 0) {
-    m = n = F - k0 - kb; k = kb;
-    Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
-    Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
-    Cp = base + (int64_t)(k0 + kb) * F + (k0 + kb); ldc = F;
-  } else if (mode == 1) {
-    C* XL = xwork + f.xoff;
-    m = p - k0 - kb; n = k0 + kb; k = kb;
-    Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
-    Bp = XL + k0; ldb = p;
-    Cp = XL + (k0 + kb); ldc = p;
+  int tm, tn;
+  const int* brow = nullptr;
+  bool assign = false;
+  if (mode == 7) {
+    const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
+    const C* Ui = Li + kDB * kDB;
+    assign = true;
+    if ((int)blockIdx.x < tiles_m) {   // L21 = A21 Uinv_kk
+      tm = blockIdx.x; tn = 0;
+      m = F - k0 - kb; n = kb; k = kb;
+      Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
+      Bp = Ui; ldb = kDB;
+      Cp = base + (int64_t)k0 * F + (k0 + kb); ldc = F;
+    } else {                           // U12 = Linv_kk (P A12)
+      tm = 0; tn = blockIdx.x - tiles_m;
+      m = kb; n = F - k0 - kb; k = kb;
+      Ap = Li; lda = kDB;
+      Bp = base + (int64_t)(k0 + kb) * F; ldb = F;
+      Cp = base + (int64_t)(k0 + kb) * F + k0; ldc = F;
+      brow = mf.prow + f.perm + k0;
+    }
   } else {
-    C* XU = xwork + f.xoff + (int64_t)p * p;
-    m = k0; n = p - k0; k = kb;
-    Ap = base + (int64_t)k0 * F; lda = F;
-    Bp = XU + (int64_t)k0 * p + k0; ldb = p;
-    Cp = XU + (int64_t)k0 * p; ldc = p;
+    tm = blockIdx.x % tiles_m;
+    tn = blockIdx.x / tiles_m;
+    if (mode == 0) {
+      m = n = F - k0 - kb; k = kb;
+      Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
+      Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
+      Cp = base + (int64_t)(k0 + kb) * F + (k0 + kb); ldc = F;
+    } else if (mode == 1) {
+      C* XL = xwork + f.xoff;
+      m = p - k0 - kb; n = k0 + kb; k = kb;
+      Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
+      Bp = XL + k0; ldb = p;
+      Cp = XL + (k0 + kb); ldc = p;
+    } else {
+      C* XU = xwork + f.xoff + (int64_t)p * p;
+      m = k0; n = p - k0; k = kb;
+      Ap = base + (int64_t)k0 * F; lda = F;
+      Bp = XU + (int64_t)k0 * p + k0; ldb = p;
+      Cp = XU + (int64_t)k0 * p; ldc = p;
+    }
   }
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
   const int m0 = tm * kBM, n0 = tn * kBN;
   if (m <= 0 || n <= 0 || k <= 0 || m0 >= m || n0 >= n) return;
-  gemm_tile<R>(Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign, assign ? R(1) : R(-1), 0, k);
+  gemm_tile<R>(Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign, assign ? R(1) : R(-1), 0, k, brow, 0);
+}
+
+// Row interchanges of every 32-row diagonal block of a level's fronts applied
+// to the columns left of the block (the L part written by earlier steps),
+// once after all steps: rows [k0, k0 + kb) of columns [0, k0) take the order
+// prow.  blockIdx.x = block, blockIdx.y = front; 32 rows x 8 columns per pass.
+template <typename R>
+__global__ void __launch_bounds__(256) leftswap_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int f0) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int k0 = blockIdx.x * kDB;
+  if (k0 >= f.p || k0 == 0) return;
+  const int kb = min(kDB, f.p - k0);
+  const int r = threadIdx.x & 31, cl = threadIdx.x >> 5;
+  const int src = (r < kb) ? mf.prow[f.perm + k0 + r] : 0;
+  C* A = arena + f.off;
+  for (int c0 = 0; c0 < k0; c0 += 8) {
+    const int c = c0 + cl;
+    C v = cmake<C>(0, 0);
+    if (r < kb && c < k0) v = A[(int64_t)c * f.F + src];
+    __syncthreads();
+    if (r < kb && c < k0) A[(int64_t)c * f.F + k0 + r] = v;
+    __syncthreads();
+  }
 }
 
 // Triangular inverses of a front's pivot block by recursive doubling over
@@ -1400,19 +1432,17 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     }
     SPP_LAUNCH_CHECK();
     timer_end(KC_PANEL, st, 0.0, 0.0);
-    if (partial_pivoting && maxF > 4096) {
-      // the global-memory panel applies its interchanges itself
-    } else {
-      laswp_kernel<R><<<dim3(ceil_div(maxF, 64), nf), 64, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
-      SPP_LAUNCH_CHECK();
-    }
     if (partial_pivoting) {
+      if (maxF <= 4096) {   // (the global-memory panel applies its interchanges itself)
+        laswp_kernel<R><<<dim3(ceil_div(maxF, 64), nf), 64, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
+        SPP_LAUNCH_CHECK();
+      }
       trsm_kernel<R><<<dim3(ceil_div(maxF, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0);
     } else {
-      // L21 = A21 Uinv_kk and U12 = Linv_kk P A12 on MFMA (one 64-wide tile strip each).
-      gemm_kernel<R><<<dim3(tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 4, tiles);
-      SPP_LAUNCH_CHECK();
-      gemm_kernel<R><<<dim3(tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 3, 1);
+      // L21 = A21 Uinv_kk and U12 = Linv_kk P A12 on MFMA in one launch (one
+      // 64-wide tile strip each); the block's row order P is applied while
+      // loading A12, the rows' L parts are reordered once after the last step.
+      gemm_kernel<R><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 7, tiles);
     }
     SPP_LAUNCH_CHECK();
     {
@@ -1429,6 +1459,10 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       SPP_LAUNCH_CHECK();
       timer_end(KC_GEMM, st, 0.0, fl);
     }
+  }
+  if (!partial_pivoting && steps > 1) {
+    leftswap_kernel<R><<<dim3(steps, nf), 256, 0, st>>>(mf, arena, f0);
+    SPP_LAUNCH_CHECK();
   }
   perm_kernel<<<nf, 256, 2 * sizeof(int) * maxP, st>>>(mf, mf.ipiv, f0);
   SPP_LAUNCH_CHECK();
@@ -1472,11 +1506,15 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   SPP_LAUNCH_CHECK();
 }
 
-bool mf_level_uses_inverse(int nfronts, int maxF, int maxP) {
-  // Many small fronts: one workgroup per front solves with the LU in place
-  // (its vectors, (F + p) x 4 complex128 values, stay within 64 KB of LDS).
-  // Few large fronts: explicit inverses so every row of every front runs in parallel.
-  return !(nfronts >= 32 && maxP <= 512 && maxF + maxP <= 1024);
+bool mf_level_uses_inverse(int nfronts, int maxF, int maxP, bool c64) {
+  // Explicit inverses turn every substitution step into row-parallel
+  // matrix-vector products (many workgroups per front).  Building them costs
+  // setup time: cheap on FP32 MFMA (complex64 fronts: always), dearer on
+  // FP64, where levels with very many small fronts keep the LU in place and
+  // run one workgroup per front (its vectors, (F + p) x 4 complex values,
+  // within 64 KB of LDS).
+  if (c64) return true;
+  return !(nfronts >= 512 && maxP <= 512 && maxF + maxP <= 1024);
 }
 
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
