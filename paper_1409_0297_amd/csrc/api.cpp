@@ -176,7 +176,8 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
       if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
       for (int c = 0; c < g_.nchild; ++c) g_.child[c] = f.children[c];
       pd->perm_total += f.p;
-      if (inv) xo += 2LL * f.p * f.p;
+      // XL, XU (p x p each), then Lt, Ut ((F - p) x p each).
+      if (inv) xo += 2LL * f.p * f.F;
       e0 += 0.5 * f.p * (f.p - 1.0);
       e1 += 0.5 * f.p * (f.p + 1.0);
       e2 += (double)(f.F - f.p) * f.p;
@@ -248,7 +249,7 @@ struct spp_factor {
   MfDev mf{};
   void* arena = nullptr;
   size_t csize = 16;  // bytes per complex front entry
-  std::vector<int> level_begin, level_maxF, level_maxK, level_maxP, level_inv;
+  std::vector<int> level_begin, level_maxF, level_maxK, level_maxP, level_form;
   void* gpart = nullptr;       // split-K partial sums of the substitution
   int64_t gpart_cap = 0;
   // solve work (grown on demand)
@@ -431,12 +432,12 @@ void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStr
   const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
     mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
-                     F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap, persistent);
+                     F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
   } else {
     const int64_t cnt = (int64_t)nrhs * F->Ntot;
     cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
     mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
-                    F->level_maxP.data(), ent, F->level_inv.data(), nl, F->gpart, F->gpart_cap, persistent);
+                    F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
     cast_vectors<float>(st, F->xc, z, cnt, 1);
   }
 }
@@ -496,12 +497,17 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
   }
   const Plan& P = *F->planp;
   for (size_t l = 0; l < P.levels.size(); ++l) {
-    if (!F->level_inv[l]) continue;
+    if (F->level_form[l] == kFormLU) continue;
     const Level& L = P.levels[l];
-    const int nf = L.end - L.begin, mP = L.maxP, mK = L.maxK;
+    const int nf = L.end - L.begin, mP = L.maxP, mF = L.maxF, mK = L.maxK;
     struct Prod { int rows, cols, mode; };
-    std::vector<Prod> prods = {{mP, mP, 0}, {mP, mP, 3}};
-    if (mK > 0) { prods.push_back({mK, mP, 1}); prods.push_back({mP, mK, 2}); }
+    std::vector<Prod> prods;
+    if (F->level_form[l] == kFormSide) {
+      prods = {{mF, mP, 4}, {mP, mF, 5}};
+    } else {
+      prods = {{mP, mP, 0}, {mP, mP, 3}};
+      if (mK > 0) { prods.push_back({mK, mP, 1}); prods.push_back({mP, mK, 2}); }
+    }
     for (const Prod& pr : prods) {
       const std::string key = gemv_tune_key(pr.rows, pr.cols, nf, pr.mode, nrhs, (int)F->csize);
       if (tune_has(key)) continue;
@@ -592,8 +598,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   int64_t Nmax = 0;
   for (const SppInstance& I : F->inst) {
     Nmax = std::max(Nmax, I.N);
+    size_t w = 0;
     for (const SetType& T : I.plan->types)
-      work_elems = std::max(work_elems, (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS));
+      w += (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS);
+    work_elems = std::max(work_elems, w);
   }
   double2* swork = F->dalloc<double2>(work_elems);
   const int nblk_max = coeff_reduce_blocks(Nmax);
@@ -642,9 +650,9 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       S.C = F->dalloc<double2>((size_t)T.nS * T.nG);
       S.Tt = F->dalloc<double2>((size_t)T.nS * T.nB);
       S.Ct = F->dalloc<double2>((size_t)T.nS * T.nG);
-      stencil_build(st, I.d, I.n, g, g2, S, swork, info + 1 + (int)t);
       D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
     }
+    stencil_build(st, I.d, I.n, g, g2, I.sten, (int)ntypes, swork, info + 1);
   }
   F->inst_dev = F->dalloc<InstDev>(count);
   SPP_HIP(hipMemcpyAsync(F->inst_dev, idev.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, st));
@@ -680,7 +688,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   }
   F->level_begin.push_back(static_cast<int>(P.fronts.size()));
   for (const Level& L : P.levels)
-    F->level_inv.push_back(mf_level_uses_inverse(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS) ? 1 : 0);
+    F->level_form.push_back(mf_level_solve_form(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS));
 
   F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
   void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);
@@ -697,10 +705,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     const int* hP = F->pd->level_p[l].data();
     if (F->opt.prec == SPP_C128)
       mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                              L.max_children, F->level_inv[l] != 0, partial_pivoting, hF, hP);
+                              L.max_children, F->level_form[l], partial_pivoting, hF, hP);
     else
       mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                             L.max_children, F->level_inv[l] != 0, partial_pivoting, hF, hP);
+                             L.max_children, F->level_form[l], partial_pivoting, hF, hP);
   }
   int hinfo[16];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));

@@ -20,6 +20,7 @@ template <typename C> __host__ __device__ inline C cmake(decltype(C::x) re, decl
 }
 template <typename C> __host__ __device__ inline C cadd(C a, C b) { return cmake<C>(a.x + b.x, a.y + b.y); }
 template <typename C> __host__ __device__ inline C csub(C a, C b) { return cmake<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __host__ __device__ inline C cneg(C a) { return cmake<C>(-a.x, -a.y); }
 template <typename C> __host__ __device__ inline C cmul(C a, C b) {
   return cmake<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -56,16 +56,19 @@ struct StencilDev {
   double2* Tt;         // nB x nS (T transposed), row-major
   double2* Ct;         // nG x nS (C transposed), row-major
 };
-// Builds T_S and C_S for one set type from the kernels g (of G) and g2 (of G G^H).
-// work must hold 2 nG^2 + 2 nG nB + nB^2 + nS nB complex entries.
+// Builds T_S and C_S for every set type from the kernels g (of G) and g2 (of
+// G G^H); the least-squares solves of all types run in one launch.  info[t]
+// is set for a singular Gram matrix of type t.
 void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2,
-                   StencilDev& S, double2* work, int* info);
+                   StencilDev* types, int ntypes, double2* work, int* info);
+// Work entries one set type needs (stencil_build needs their sum over the types).
+size_t stencil_work_elems(const StencilDev& S);
 
 // ------------------------------------------------------------- mf.hip
 struct FrontDev {
   int64_t off;         // F x F front (column-major) in the arena
   int64_t voff;        // solve vector slot (positions)
-  int64_t xoff;        // inverse work slot (p x p), relative to the level's work base
+  int64_t xoff;        // inverse work slot (2 p F: XL, XU, then Lt, Ut), relative to the level's work base
   int F, p;
   int idx;             // global indices of the F front points (pivots first)
   int map;             // F - p parent positions of the boundary points
@@ -120,11 +123,16 @@ struct MfDev {
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* tbuf, void* dinv,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
-                     int max_children, bool invert, bool partial_pivoting,
+                     int max_children, int form, bool partial_pivoting,
                      const int* hF, const int* hP);   // host: F and p of the level's fronts
-// Whether a level keeps explicit inverses of its pivot-block factors (few large
-// fronts) or solves with the LU in place (many small fronts).
-bool mf_level_uses_inverse(int nfronts, int maxF, int maxP, bool c64);
+// How a level's fronts are kept for the substitution:
+//  kFormLU:      LU in place, one workgroup per front solves;
+//  kFormInverse: L11^{-1}, U11^{-1} over the pivot block, L21 and U12 kept:
+//                four matrix-vector products per level and solve;
+//  kFormSide:    as kFormInverse with L21 L11^{-1} and U11^{-1} U12 over the
+//                side blocks: one product per level and direction.
+constexpr int kFormLU = 0, kFormInverse = 1, kFormSide = 2;
+int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64);
 
 // y = Q r for every instance of the batch (vectors in the batch layout).
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);
@@ -133,7 +141,7 @@ template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void* z,
               const void* x_in, void* x_out, int nrhs,
               const int* level_begin, const int* level_maxF, const int* level_maxK,
-              const int* level_maxP, const double* level_ent, const int* level_inv, int nlevels,
+              const int* level_maxP, const double* level_ent, const int* level_form, int nlevels,
               void* partial, int64_t partial_cap, bool persistent);
 
 template <typename R>

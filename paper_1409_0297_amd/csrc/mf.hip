@@ -412,28 +412,67 @@ template <> __device__ inline float piv_key_value<float>(unsigned long long k) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
-                                                      cplx_t<R>* __restrict__ dinv, int f0, int k0, int nb) {
+struct DiagLds {
+  cplx_t<R> D[kDB][kDB + 1];    // working rows; their U part ends here; later the inverses
+  cplx_t<R> Lm[kDB][kDB + 1];   // multipliers of each physical row; later products
+  cplx_t<R> X[kDB][kDB + 1];    // the LU in pivot order
+  unsigned long long keys[kDB + 1];
+  int rsel[kDB];
+};
+
+// Orders one wave's LDS accesses before the ones that follow (the lanes of a
+// wave see each other's LDS writes in issue order).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The diagonal-block LU of block [k0, k0 + kb) of front fi by one workgroup
+// of 256 threads.  With kprev >= 0 the block first takes the trailing update
+// of the previous step (full block at kprev): A_kk -= L(k, prev) U(prev, k),
+// read from the L21 and U12 that step wrote.
+template <typename R>
+__device__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ dinv, int fi,
+                              int k0, int nb, int kprev, DiagLds<R>& S) {
   using C = cplx_t<R>;
-  const int fi = f0 + blockIdx.x;
   const FrontDev& f = mf.fronts[fi];
   const int p = f.p;
   if (k0 >= p) return;
   const int kb = min(nb, p - k0);
   const int F = f.F;
   C* A = arena + f.off + (int64_t)k0 * F + k0;   // block origin, leading dimension F
+  auto& D = S.D;
+  auto& Lm = S.Lm;
+  auto& X = S.X;
+  auto& keys = S.keys;
+  auto& rsel = S.rsel;
+  const int tid = threadIdx.x;
+  if (kprev >= 0) {
+    const C* base = arena + f.off;
+    for (int t = tid; t < kDB * kDB; t += 256) {
+      const int c = t / kDB, i = t - c * kDB;
+      Lm[i][c] = (i < kb) ? base[(int64_t)(kprev + c) * F + k0 + i] : cmake<C>(0, 0);
+      X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + kprev + i] : cmake<C>(0, 0);
+    }
+    __syncthreads();
+  }
   // The block is padded to 32 x 32 with the identity so that every step is
   // uniform.  Rows stay where they are (physical order); the pivot chosen at
   // step j is recorded in rsel[j] and the LU is written back in pivot order.
-  __shared__ C D[kDB][kDB + 1];    // working rows; their U part ends here; later the inverses
-  __shared__ C Lm[kDB][kDB + 1];   // multipliers of each physical row; later products
-  __shared__ C X[kDB][kDB + 1];    // the LU in pivot order
-  __shared__ unsigned long long keys[kDB + 1];
-  __shared__ int rsel[kDB];
-  const int tid = threadIdx.x;
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
-    D[i][c] = (i < kb && c < kb) ? A[(int64_t)c * F + i] : cmake<C>(i == c ? 1 : 0, 0);
+    C v = cmake<C>(i == c ? 1 : 0, 0);
+    if (i < kb && c < kb) {
+      v = A[(int64_t)c * F + i];
+      if (kprev >= 0)
+        for (int u = 0; u < kDB; ++u) cfms(v, Lm[i][u], X[u][c]);
+    }
+    D[i][c] = v;
+  }
+  if (kprev >= 0) __syncthreads();
+  for (int t = tid; t < kDB * kDB; t += 256) {
+    const int c = t / kDB, i = t - c * kDB;
     Lm[i][c] = cmake<C>(0, 0);
   }
   if (tid <= kDB) keys[tid] = 0;
@@ -454,13 +493,26 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
     }
     done |= 1u << r;
     if (!((done >> ri) & 1u)) {
-      const C pv = D[r][j];
-      const C l = cabs2(pv) > R(0) ? cdiv(D[ri][j], pv) : cmake<C>(0, 0);
+      // All LDS reads of the step are issued together (fixed trip count).
+      const C pv = D[r][j], dj = D[ri][j];
+      C dr[4], rr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = j + 1 + cg + 8 * u;
+        if (c < kDB) { dr[u] = D[ri][c]; rr[u] = D[r][c]; }
+      }
+      const R m2 = cabs2(pv);
+      const R inv = m2 > R(0) ? R(1) / m2 : R(0);
+      const C l = cmake<C>((dj.x * pv.x + dj.y * pv.y) * inv, (dj.y * pv.x - dj.x * pv.y) * inv);
       if (cg == 0) Lm[ri][j] = l;
-      for (int c = j + 1 + cg; c < kDB; c += 8) {
-        C& d = D[ri][c];
-        cfms(d, l, D[r][c]);
-        if (c == j + 1) atomicMax(&keys[j + 1], piv_key<R>(cabs2(d), ri));
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = j + 1 + cg + 8 * u;
+        if (c < kDB) {
+          cfms(dr[u], l, rr[u]);
+          D[ri][c] = dr[u];
+          if (u == 0 && cg == 0) atomicMax(&keys[j + 1], piv_key<R>(cabs2(dr[0]), ri));
+        }
       }
     }
     __syncthreads();
@@ -470,19 +522,13 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
     const int pr = rsel[k];
     X[k][c] = (c >= k) ? D[pr][c] : Lm[pr][c];
   }
-  __syncthreads();
-  if (tid < kb) mf.prow[f.perm + k0 + tid] = k0 + rsel[tid];
-  if (tid == 0) {
-    // The same permutation as a LAPACK-style interchange sequence.
-    int cur[kDB], where[kDB];
-    for (int i = 0; i < kDB; ++i) { cur[i] = i; where[i] = i; }
-    for (int j = 0; j < kb; ++j) {
-      const int q = where[rsel[j]];
-      ipiv[f.perm + k0 + j] = k0 + q;
-      const int a = cur[j], b = cur[q];
-      cur[j] = b; cur[q] = a; where[b] = j; where[a] = q;
-    }
+  // Block-local pivoting keeps every interchange inside the block, so the
+  // row order is also the block's part of the front's final permutation.
+  if (tid < kb) {
+    mf.prow[f.perm + k0 + tid] = k0 + rsel[tid];
+    mf.perm[f.perm + k0 + tid] = k0 + rsel[tid];
   }
+  __syncthreads();
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
     if (i < kb && c < kb) A[(int64_t)c * F + i] = X[i][c];
@@ -490,8 +536,10 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
   }
   __syncthreads();
   // Inverses into D (strictly lower: Linv with unit diagonal implied; upper
-  // with the diagonal: Uinv).  First the four 8 x 8 diagonal blocks of each
-  // triangle by column sweeps, then two doubling stages:
+  // with the diagonal: Uinv); the doubling loops are kept rolled so that the
+  // block fits beside the MFMA tiles of the launch it shares.  First the four 8 x 8 diagonal blocks of each
+  // triangle by column sweeps (one wave per block, no workgroup barrier),
+  // then two doubling stages:
   //   [A 0; C B]^{-1} has lower-left block -B^{-1} (C A^{-1}),
   //   [A C; 0 B]^{-1} has upper-right block -A^{-1} (C B^{-1}).
   {
@@ -503,13 +551,14 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
         const C dd = X[o + u][o + u];
         D[o + u][o + c] = cabs2(dd) > R(0) ? cdiv(D[o + u][o + c], dd) : cmake<C>(0, 0);
       }
-      __syncthreads();
+      wave_lds_sync();
       if (i > t && c < t) cfms(D[o + i][o + c], X[o + i][o + t], D[o + t][o + c]);
       if (i > t && c == t) D[o + i][o + c] = cmake<C>(-X[o + i][o + t].x, -X[o + i][o + t].y);
       if (i < u && c >= u) cfms(D[o + i][o + c], X[o + i][o + u], D[o + u][o + c]);
-      __syncthreads();
+      wave_lds_sync();
     }
   }
+  __syncthreads();
   for (int h = 8; h < kDB; h *= 2) {
     const int npair = kDB / (2 * h), per = npair * h * h, items = 2 * per;
     // products C A^{-1} (lower pairs) and C B^{-1} (upper pairs) into Lm
@@ -519,9 +568,11 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
       const int a = e / h, b = e - a * h, o = pr * 2 * h;
       C acc = cmake<C>(0, 0);
       if (which == 0) {
+#pragma unroll 2
         for (int k = b; k < h; ++k) cfma(acc, X[o + h + a][o + k], k == b ? cmake<C>(1, 0) : D[o + k][o + b]);
         Lm[o + h + a][o + b] = acc;
       } else {
+#pragma unroll 2
         for (int k = 0; k <= b; ++k) cfma(acc, X[o + a][o + h + k], D[o + h + k][o + h + b]);
         Lm[o + a][o + h + b] = acc;
       }
@@ -533,9 +584,11 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
       const int a = e / h, b = e - a * h, o = pr * 2 * h;
       C acc = cmake<C>(0, 0);
       if (which == 0) {
+#pragma unroll 2
         for (int k = 0; k <= a; ++k) cfms(acc, k == a ? cmake<C>(1, 0) : D[o + h + a][o + h + k], Lm[o + h + k][o + b]);
         D[o + h + a][o + b] = acc;
       } else {
+#pragma unroll 2
         for (int k = a; k < h; ++k) cfms(acc, D[o + a][o + k], Lm[o + k][o + h + b]);
         D[o + a][o + h + b] = acc;
       }
@@ -551,6 +604,13 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
       Ui[c * kDB + i] = (i <= c) ? D[i][c] : cmake<C>(0, 0);
     }
   }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __restrict__ arena,
+                                                      cplx_t<R>* __restrict__ dinv, int f0, int k0, int nb) {
+  __shared__ DiagLds<R> S;
+  diag_lu_block<R>(mf, arena, dinv, f0 + blockIdx.x, k0, nb, -1, S);
 }
 
 // ------------------------------------------------------------------ row-block TRSM
@@ -640,13 +700,22 @@ constexpr int kBM = 64, kBN = 64, kBK = 16;
 // complex column-major operands, k restricted to [kbeg, kend).  brow (optional)
 // maps row gk of B to row brow[gk] - brow_off (a row permutation of B).
 template <typename R>
-__device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, const cplx_t<R>* __restrict__ Bp, int ldb,
-                                 cplx_t<R>* __restrict__ Cp, int ldc, int m, int n, int k, int m0, int n0, bool from_c,
-                                 R sgn, int kbeg, int kend, const int* brow = nullptr, int brow_off = 0) {
+struct GemmLds {
+  cplx_t<R> As[kBK][kBM + 1];
+  cplx_t<R> Bs[kBK][kBN + 1];
+};
+
+// skip > 0: entries with row < skip and column < skip are not stored (a
+// block another workgroup of the same launch owns).
+template <typename R>
+__device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict__ Ap, int lda,
+                                      const cplx_t<R>* __restrict__ Bp, int ldb, cplx_t<R>* __restrict__ Cp, int ldc,
+                                      int m, int n, int k, int m0, int n0, bool from_c, R sgn, int kbeg, int kend,
+                                      const int* brow, int brow_off, int skip) {
   using C = cplx_t<R>;
   using V = typename Acc<R>::type;
-  __shared__ C As[kBK][kBM + 1];
-  __shared__ C Bs[kBK][kBN + 1];
+  auto& As = L.As;
+  auto& Bs = L.Bs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
@@ -708,8 +777,17 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
         const int col = n0 + wn + 16 * b + (lane & 15);
-        if (row < m && col < n) Cp[(int64_t)col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
+        if (row < m && col < n && !(row < skip && col < skip))
+          Cp[(int64_t)col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
       }
+}
+
+template <typename R>
+__device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, const cplx_t<R>* __restrict__ Bp, int ldb,
+                                 cplx_t<R>* __restrict__ Cp, int ldc, int m, int n, int k, int m0, int n0, bool from_c,
+                                 R sgn, int kbeg, int kend, const int* brow = nullptr, int brow_off = 0) {
+  __shared__ GemmLds<R> L;
+  gemm_tile_core<R>(L, Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, from_c, sgn, kbeg, kend, brow, brow_off, 0);
 }
 
 // Front GEMMs of one elimination step (k0 = step block, kb <= 32 columns):
@@ -720,14 +798,28 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 //           (the rest), P the step's row order from the diagonal-block LU,
 //           applied while loading A12.  Both overwrite their input block;
 //           every workgroup reads all of its own block before writing it.
-template <typename R>
-__global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
-                                                   const cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode,
-                                                   int tiles_m) {
+// NEXT (mode 0 only): the launch's last workgroup column (blockIdx.x ==
+// gridDim.x - 1) factors the next diagonal block of each front, taking this
+// step's update of that block itself; the tile holding the block skips it.
+template <typename R, bool NEXT>
+__device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
+                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode, int tiles_m) {
   using C = cplx_t<R>;
+  constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > sizeof(GemmLds<R>) ? sizeof(DiagLds<R>) : sizeof(GemmLds<R>))
+                               : sizeof(GemmLds<R>);
+  __shared__ __align__(16) unsigned char lds[kLds];
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   int k0, kb;
   if (!step_range<R>(f, mode == 2 ? 2 : 0, step, nb, k0, kb)) return;
+  int skip = 0;
+  if (NEXT) {
+    const int k1 = k0 + kb;
+    if (blockIdx.x == gridDim.x - 1) {
+      if (k1 < f.p) diag_lu_block<R>(mf, arena, dinv, f0 + blockIdx.y, k1, nb, k0, *reinterpret_cast<DiagLds<R>*>(lds));
+      return;
+    }
+    if (k1 < f.p) skip = min(nb, f.p - k1);
+  }
   const int F = f.F, p = f.p;
   C* base = arena + f.off;
   const C *Ap, *Bp;
@@ -778,30 +870,53 @@ __global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restri
   }
   const int m0 = tm * kBM, n0 = tn * kBN;
   if (m <= 0 || n <= 0 || k <= 0 || m0 >= m || n0 >= n) return;
-  gemm_tile<R>(Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign, assign ? R(1) : R(-1), 0, k, brow, 0);
+  gemm_tile_core<R>(*reinterpret_cast<GemmLds<R>*>(lds), Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign,
+                    assign ? R(1) : R(-1), 0, k, brow, 0, skip);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
+                                                   cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode,
+                                                   int tiles_m) {
+  gemm_body<R, false>(mf, arena, xwork, dinv, f0, step, nb, mode, tiles_m);
+}
+
+// Trailing update with the next diagonal block (mode 0, NEXT above); asks
+// for 4 waves per SIMD so that the block's registers do not halve the tiles'
+// occupancy.
+template <typename R>
+__global__ void __launch_bounds__(256, 4) gemm_next_kernel(MfDev mf, cplx_t<R>* __restrict__ arena,
+                                                           cplx_t<R>* __restrict__ xwork, cplx_t<R>* __restrict__ dinv,
+                                                           int f0, int step, int nb, int tiles_m) {
+  gemm_body<R, true>(mf, arena, xwork, dinv, f0, step, nb, 0, tiles_m);
 }
 
 // Row interchanges of every 32-row diagonal block of a level's fronts applied
 // to the columns left of the block (the L part written by earlier steps),
 // once after all steps: rows [k0, k0 + kb) of columns [0, k0) take the order
-// prow.  blockIdx.x = block, blockIdx.y = front; 32 rows x 8 columns per pass.
+// prow.  blockIdx.x = (block, 64-column chunk), blockIdx.y = front; each
+// workgroup reads its 32 x 64 piece whole before writing it back.
 template <typename R>
-__global__ void __launch_bounds__(256) leftswap_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int f0) {
+__global__ void __launch_bounds__(256) leftswap_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int f0, int cchunks) {
   using C = cplx_t<R>;
   const FrontDev& f = mf.fronts[f0 + blockIdx.y];
-  const int k0 = blockIdx.x * kDB;
-  if (k0 >= f.p || k0 == 0) return;
+  const int k0 = (blockIdx.x / cchunks) * kDB, c0 = (blockIdx.x % cchunks) * 64;
+  if (k0 >= f.p || k0 == 0 || c0 >= k0) return;
   const int kb = min(kDB, f.p - k0);
   const int r = threadIdx.x & 31, cl = threadIdx.x >> 5;
   const int src = (r < kb) ? mf.prow[f.perm + k0 + r] : 0;
   C* A = arena + f.off;
-  for (int c0 = 0; c0 < k0; c0 += 8) {
-    const int c = c0 + cl;
-    C v = cmake<C>(0, 0);
-    if (r < kb && c < k0) v = A[(int64_t)c * f.F + src];
-    __syncthreads();
-    if (r < kb && c < k0) A[(int64_t)c * f.F + k0 + r] = v;
-    __syncthreads();
+  C v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = c0 + cl + 8 * u;
+    v[u] = (r < kb && c < k0) ? A[(int64_t)c * f.F + src] : cmake<C>(0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = c0 + cl + 8 * u;
+    if (r < kb && c < k0) A[(int64_t)c * f.F + k0 + r] = v[u];
   }
 }
 
@@ -890,16 +1005,58 @@ __global__ void identity_kernel(MfDev mf, cplx_t<R>* __restrict__ xwork, int f0)
   }
 }
 
+// Side blocks of the product form of the substitution, after XL = L11^{-1}
+// (unit lower) and XU = U11^{-1} (upper):
+//   Lt = L21 XL  ((F - p) x p, column-major, ld F - p)    blockIdx.z = 0
+//   Ut = XU U12  (p x (F - p), column-major, ld p)        blockIdx.z = 1
+// in the front's work slot after XL and XU; k is cut to the triangle.
 template <typename R>
-__global__ void merge_inverse_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ xwork, int f0) {
+__global__ void __launch_bounds__(256) inv_side_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                       cplx_t<R>* __restrict__ xwork, int f0, int tiles_m) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int p = f.p, F = f.F, K = F - p;
+  if (K <= 0 || p <= 0) return;
+  const C* LU = arena + f.off;
+  const C* XL = xwork + f.xoff;
+  const C* XU = XL + (int64_t)p * p;
+  C* Lt = xwork + f.xoff + 2 * (int64_t)p * p;
+  C* Ut = Lt + (int64_t)K * p;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  if (blockIdx.z == 0) {
+    if (m0 >= K || n0 >= p) return;
+    gemm_tile<R>(LU + p, F, XL, p, Lt, K, K, p, p, m0, n0, false, R(1), n0, p);
+  } else {
+    if (m0 >= p || n0 >= K) return;
+    gemm_tile<R>(XU, p, LU + (int64_t)p * F, F, Ut, p, p, K, p, m0, n0, false, R(1), m0, p);
+  }
+}
+
+// Writes XL (strictly lower) and XU (upper) over the front's pivot block and,
+// with side = true, Lt and Ut over L21 and U12.
+template <typename R>
+__global__ void merge_inverse_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ xwork, int f0,
+                                     bool side) {
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
-  const int64_t pp = (int64_t)f.p * f.p;
+  const int p = f.p, F = f.F, K = F - p;
+  const int64_t pp = (int64_t)p * p;
   const C* X = xwork + f.xoff;
   C* A = arena + f.off;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < pp; t += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(t % f.p), j = (int)(t / f.p);
-    A[(int64_t)j * f.F + i] = (i > j) ? X[t] : X[pp + t];
+    const int i = (int)(t % p), j = (int)(t / p);
+    A[(int64_t)j * F + i] = (i > j) ? X[t] : X[pp + t];
+  }
+  if (!side || K <= 0) return;
+  const int64_t kp = (int64_t)K * p;
+  const C* Lt = X + 2 * pp;
+  const C* Ut = Lt + kp;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < kp; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % K), j = (int)(t / K);
+    A[(int64_t)j * F + p + i] = Lt[t];
+    const int i2 = (int)(t % p), j2 = (int)(t / p);
+    A[(int64_t)(p + j2) * F + i2] = Ut[t];
   }
 }
 
@@ -976,11 +1133,17 @@ __global__ void fwd_gather_kernel(MfDev mf, cplx_t<R>* __restrict__ W, const cpl
   }
 }
 
-// Row-tiled complex GEMV for the four substitution products.
+// Row-tiled complex GEMV for the substitution products.
 //  mode 0: z = Linv (P w_piv)            rows [0,p),  cols j < row (+ unit diagonal)
 //  mode 1: w_bnd -= L21 z                rows [0,F-p), cols [0,p)
 //  mode 2: z -= U12 x(bnd)               rows [0,p),  cols [0,F-p)
 //  mode 3: x(piv) = Uinv z               rows [0,p),  cols j >= row
+// With the side blocks of a front replaced by Lt = L21 Linv and Ut = Uinv U12
+// (mf_factor_level does this for the levels solved by products), each
+// direction is one product over the front's pivot columns or pivot rows:
+//  mode 4: [z; w_bnd] = [Linv; -Lt] (P w_piv) + [0; w_bnd]
+//          rows [0,F), cols j < min(row, p) (+ unit diagonal for rows < p)
+//  mode 5: x(piv) = [Uinv, -Ut] [z; x(bnd)]  rows [0,p), cols [row, F)
 template <typename R, int NR>
 __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ W,
                                                    cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout, int nrhs,
@@ -989,7 +1152,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   const int F = f.F, p = f.p;
-  const int nrows = (mode == 1) ? F - p : p;
+  const int nrows = (mode == 1) ? F - p : (mode == 4) ? F : p;
   const int chunk = blockIdx.x % nchunks;
   const int row0 = (blockIdx.x / nchunks) * 64;
   if (row0 >= nrows) return;
@@ -1004,10 +1167,11 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   C* xo = xout + I.Noff * nrhs;
   const int64_t NI = I.N;
   int jlo, jhi;
-  if (mode == 0) { jlo = 0; jhi = min(p, row0 + 64); }
+  if (mode == 0 || mode == 4) { jlo = 0; jhi = min(p, row0 + 64); }
   else if (mode == 1) { jlo = 0; jhi = p; }
   else if (mode == 2) { jlo = 0; jhi = F - p; }
-  else { jlo = row0; jhi = p; }
+  else if (mode == 3) { jlo = row0; jhi = p; }
+  else { jlo = row0; jhi = F; }
   if (nchunks > 1) {
     const int span = jhi - jlo, csz = (span + nchunks - 1) / nchunks;
     jlo = jlo + chunk * csz;
@@ -1030,8 +1194,9 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
       const int jj = t / NR, r = t - jj * NR, j = jt + jj;
       C v = cmake<C>(0, 0);
       if (r0 + r < nrhs) {
-        if (mode == 0) v = w[perm[j] * nrhs + r0 + r];
+        if (mode == 0 || mode == 4) v = w[perm[j] * nrhs + r0 + r];
         else if (mode == 2) v = xo[(int64_t)(r0 + r) * NI + idx[p + j]];
+        else if (mode == 5 && j >= p) v = cneg(xo[(int64_t)(r0 + r) * NI + idx[j]]);
         else v = z[j * nrhs + r0 + r];
       }
       vs[jj][r] = v;
@@ -1040,7 +1205,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
 #pragma unroll 8
     for (int jj = grp; jj < jn; jj += 4) {
       const int j = jt + jj;
-      const bool use = live && (mode == 0 ? j < row : mode == 3 ? j >= row : true);
+      const bool use = live && ((mode == 0 || mode == 4) ? j < row : (mode == 3 || mode == 5) ? j >= row : true);
       const C a = use ? A[coff + (int64_t)j * F] : cmake<C>(0, 0);
 #pragma unroll
       for (int r = 0; r < NR; ++r) cfma(acc[r], a, vs[jj][r]);
@@ -1059,10 +1224,13 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
     const int rr = r0 + r;
     if (nchunks > 1) {
       partial[(((int64_t)blockIdx.y * nchunks + chunk) * prow + row) * nrhs + rr] = s;
-    } else if (mode == 0) {
+    } else if (mode == 0 || (mode == 4 && row < p)) {
       z[row * nrhs + rr] = cadd(s, w[perm[row] * nrhs + rr]);
     } else if (mode == 1) {
       C& d = w[(p + row) * nrhs + rr];
+      d = csub(d, s);
+    } else if (mode == 4) {
+      C& d = w[row * nrhs + rr];
       d = csub(d, s);
     } else if (mode == 2) {
       C& d = z[row * nrhs + rr];
@@ -1361,7 +1529,7 @@ __global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R
                                    const cplx_t<R>* __restrict__ partial, int prow) {
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
-  const int nrows = (mode == 1) ? f.F - f.p : f.p;
+  const int nrows = (mode == 1) ? f.F - f.p : (mode == 4) ? f.F : f.p;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows * nrhs) return;
   const int row = t / nrhs, rr = t - row * nrhs;
@@ -1370,10 +1538,13 @@ __global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R
     s = cadd(s, partial[(((int64_t)blockIdx.y * nchunks + c) * prow + row) * nrhs + rr]);
   C* w = W + f.voff * nrhs;
   C* z = Z + f.voff * nrhs;
-  if (mode == 0) {
+  if (mode == 0 || (mode == 4 && row < f.p)) {
     z[row * nrhs + rr] = cadd(s, w[mf.perm[f.perm + row] * nrhs + rr]);
   } else if (mode == 1) {
     C& d = w[(f.p + row) * nrhs + rr];
+    d = csub(d, s);
+  } else if (mode == 4) {
+    C& d = w[row * nrhs + rr];
     d = csub(d, s);
   } else if (mode == 2) {
     C& d = z[row * nrhs + rr];
@@ -1398,8 +1569,9 @@ constexpr int kNB = 32;
 
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* tbuf_v, void* dinv_v,
-                     int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, bool invert,
+                     int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, int form,
                      bool partial_pivoting, const int* hF, const int* hP) {
+  const bool invert = form != kFormLU;
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
   C* xwork = static_cast<C*>(xwork_v);
@@ -1417,22 +1589,32 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   }
   const int steps = (maxP + kNB - 1) / kNB;
   const int tiles = (int)ceil_div(maxF, kBM);
+  if (!partial_pivoting && steps > 0) {
+    // First diagonal block; each later one is factored inside the previous
+    // step's trailing-update launch (levels of few fronts) or on its own.
+    timer_begin(KC_PANEL, st);
+    diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, 0, kNB);
+    SPP_LAUNCH_CHECK();
+    timer_end(KC_PANEL, st, 0.0, 0.0);
+  }
   for (int s = 0; s < steps; ++s) {
     const int k0 = s * kNB;
-    timer_begin(KC_PANEL, st);
+    if (!partial_pivoting && s > 0 && nf > 64) {
+      timer_begin(KC_PANEL, st);
+      diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, k0, kNB);
+      SPP_LAUNCH_CHECK();
+      timer_end(KC_PANEL, st, 0.0, 0.0);
+    }
     if (partial_pivoting) {
+      timer_begin(KC_PANEL, st);
       // Pivot search over all remaining fully-summed rows of the column.
       if (maxF <= 512) panel2_kernel<R, 256, 2><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
       else if (maxF <= 1024) panel2_kernel<R, 512, 2><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
       else if (maxF <= 2048) panel2_kernel<R, 512, 4><<<nf, 512, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
       else if (maxF <= 4096) panel2_kernel<R, 1024, 4><<<nf, 1024, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
       else panel_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB, 0);
-    } else {
-      diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, mf.ipiv, dinv, f0, k0, kNB);
-    }
-    SPP_LAUNCH_CHECK();
-    timer_end(KC_PANEL, st, 0.0, 0.0);
-    if (partial_pivoting) {
+      SPP_LAUNCH_CHECK();
+      timer_end(KC_PANEL, st, 0.0, 0.0);
       if (maxF <= 4096) {   // (the global-memory panel applies its interchanges itself)
         laswp_kernel<R><<<dim3(ceil_div(maxF, 64), nf), 64, 0, st>>>(mf, arena, mf.ipiv, f0, k0, kNB);
         SPP_LAUNCH_CHECK();
@@ -1455,17 +1637,26 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
           fl += 8.0 * mn * mn * kb;
         }
       timer_begin(KC_GEMM, st);
-      gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 0, tiles);
+      // Levels of few fronts take the next diagonal block into the trailing
+      // launch (the step's serial part overlaps the update); wide levels
+      // already fill the device and keep the lighter kernel.
+      if (!partial_pivoting && s + 1 < steps && nf <= 64)
+        gemm_next_kernel<R><<<dim3(tiles * tiles + 1, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+      else
+        gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 0, tiles);
       SPP_LAUNCH_CHECK();
       timer_end(KC_GEMM, st, 0.0, fl);
     }
   }
   if (!partial_pivoting && steps > 1) {
-    leftswap_kernel<R><<<dim3(steps, nf), 256, 0, st>>>(mf, arena, f0);
+    const int cchunks = (int)ceil_div(maxP, 64);
+    leftswap_kernel<R><<<dim3(steps * cchunks, nf), 256, 0, st>>>(mf, arena, f0, cchunks);
     SPP_LAUNCH_CHECK();
   }
-  perm_kernel<<<nf, 256, 2 * sizeof(int) * maxP, st>>>(mf, mf.ipiv, f0);
-  SPP_LAUNCH_CHECK();
+  if (partial_pivoting) {   // (the diagonal-block LU writes the permutation itself)
+    perm_kernel<<<nf, 256, 2 * sizeof(int) * maxP, st>>>(mf, mf.ipiv, f0);
+    SPP_LAUNCH_CHECK();
+  }
   if (!invert) return;
   // Inverses of L11 and U11 for levels solved by matrix-vector products.
   const int ptiles = (int)ceil_div(maxP, kBM);
@@ -1502,19 +1693,34 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       }
     }
   }
-  merge_inverse_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, arena, xwork, f0);
+  // Lt = L21 XL and Ut = XU U12 replace the side blocks, so that each
+  // substitution direction is one product per front (gemv modes 4 and 5).
+  int maxK = 0;
+  if (form == kFormSide)
+    for (int i = 0; i < nf; ++i) maxK = std::max(maxK, hF[i] - hP[i]);
+  if (maxK > 0) {
+    const int tiles_m = (int)ceil_div(std::max(maxK, maxP), kBM);
+    inv_side_kernel<R><<<dim3(tiles_m * tiles_m, nf, 2), 256, 0, st>>>(mf, arena, xwork, f0, tiles_m);
+    SPP_LAUNCH_CHECK();
+  }
+  const int64_t merge_items = std::max<int64_t>((int64_t)maxP * maxP, (int64_t)maxK * maxP);
+  merge_inverse_kernel<R><<<dim3(ceil_div(merge_items, 256 * 4), nf), 256, 0, st>>>(mf, arena, xwork, f0, maxK > 0);
   SPP_LAUNCH_CHECK();
 }
 
-bool mf_level_uses_inverse(int nfronts, int maxF, int maxP, bool c64) {
+int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64) {
   // Explicit inverses turn every substitution step into row-parallel
   // matrix-vector products (many workgroups per front).  Building them costs
   // setup time: cheap on FP32 MFMA (complex64 fronts: always), dearer on
   // FP64, where levels with very many small fronts keep the LU in place and
   // run one workgroup per front (its vectors, (F + p) x 4 complex values,
   // within 64 KB of LDS).
-  if (c64) return true;
-  return !(nfronts >= 512 && maxP <= 512 && maxF + maxP <= 1024);
+  if (!c64 && nfronts >= 512 && maxP <= 512 && maxF + maxP <= 1024) return kFormLU;
+  // The side products Lt = L21 Linv and Ut = Uinv U12 halve the launches per
+  // level and direction; they pay where the level's products are short
+  // (few fronts: launch latency dominates), not on the wide leaf levels,
+  // whose substitution already streams at full width.
+  return nfronts < 512 ? kFormSide : kFormInverse;
 }
 
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
@@ -1586,7 +1792,7 @@ void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, vo
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
               void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxK,
-              const int* level_maxP, const double* level_ent, const int* level_inv, int nlevels, void* partial_v,
+              const int* level_maxP, const double* level_ent, const int* level_form, int nlevels, void* partial_v,
               int64_t partial_cap, bool persistent) {
   using C = cplx_t<R>;
   const C* arena = static_cast<const C*>(arena_v);
@@ -1682,9 +1888,9 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
-    if (!level_inv[l]) {
+    if (level_form[l] == kFormLU) {
       int l1 = l + 1;
-      while (l1 < nlevels && !level_inv[l1]) ++l1;
+      while (l1 < nlevels && level_form[l1] == kFormLU) ++l1;
       if (front_run(l, l1, true)) {
         l = l1 - 1;
         continue;
@@ -1694,16 +1900,20 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     }
     fwd_gather_kernel<R><<<nf, 256, 0, st>>>(mf, W, xin, nrhs, f0);
     SPP_LAUNCH_CHECK();
-    gemv(f0, nf, mP, mP, 0, e[0]);
-    if (mK > 0) gemv(f0, nf, mK, mP, 1, e[2]);
+    if (level_form[l] == kFormSide) {
+      gemv(f0, nf, level_maxF[l], mP, 4, e[0] + e[2]);
+    } else {
+      gemv(f0, nf, mP, mP, 0, e[0]);
+      if (mK > 0) gemv(f0, nf, mK, mP, 1, e[2]);
+    }
   }
   for (int l = nlevels - 1; l >= 0; --l) {
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
-    if (!level_inv[l]) {
+    if (level_form[l] == kFormLU) {
       int l0 = l;
-      while (l0 > 0 && !level_inv[l0 - 1]) --l0;
+      while (l0 > 0 && level_form[l0 - 1] == kFormLU) --l0;
       if (front_run(l0, l + 1, false)) {
         l = l0;
         continue;
@@ -1711,8 +1921,12 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       front(f0, nf, level_maxF[l], mP, mK, false, e[1] + e[2]);
       continue;
     }
-    if (mK > 0) gemv(f0, nf, mP, mK, 2, e[2]);
-    gemv(f0, nf, mP, mP, 3, e[1]);
+    if (level_form[l] == kFormSide) {
+      gemv(f0, nf, mP, level_maxF[l], 5, e[1] + e[2]);
+    } else {
+      if (mK > 0) gemv(f0, nf, mP, mK, 2, e[2]);
+      gemv(f0, nf, mP, mP, 3, e[1]);
+    }
   }
 }
 
@@ -1723,9 +1937,9 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
 }
 
 template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, void*, int, int, int, int, int, int,
-                                      int, bool, bool, const int*, const int*);
+                                      int, int, bool, const int*, const int*);
 template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, void*, int, int, int, int, int, int,
-                                     int, bool, bool, const int*, const int*);
+                                     int, int, bool, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
                                int64_t, bool);

@@ -11,6 +11,8 @@
 //   T_S [ (G G^H)(beta, beta) - G(beta, gamma) G(gamma, beta) ]
 //       = (G G^H)(S, beta) - G(S, gamma) G(gamma, beta),
 // an |beta| x |beta| system, and C_S = [I  -T_S] G(gamma, gamma).
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -114,9 +116,30 @@ __global__ void small_gemm_kernel(int m, int nn, int k, double2 alpha, const dou
 // Solves X A = Bm for X (nS x nB) with A (nB x nB), both row-major, through
 // the transposed system A^T X^T = Bm^T: Gaussian elimination with partial
 // pivoting on the augmented [A^T | Bm^T] (nB x (nB + nS)), one workgroup.
-__global__ void right_solve_kernel(int nB, int nS, const double2* __restrict__ A, int lda,
-                                   const double2* __restrict__ Bm, int ldb, double2* aug,
-                                   double2* __restrict__ X, int ldx, int* info) {
+struct SolveJob {
+  int nB, nS;
+  const double2* A;
+  int lda;
+  const double2* Bm;
+  int ldb;
+  double2* aug;
+  double2* X;
+  int ldx;
+  int* info;
+};
+struct SolveJobs {
+  SolveJob job[8];
+};
+
+// One workgroup per set type (blockIdx.x): the types' systems are independent.
+__global__ void right_solve_kernel(SolveJobs jobs) {
+  const SolveJob& J = jobs.job[blockIdx.x];
+  const int nB = J.nB, nS = J.nS, lda = J.lda, ldb = J.ldb, ldx = J.ldx;
+  const double2* __restrict__ A = J.A;
+  const double2* __restrict__ Bm = J.Bm;
+  double2* aug = J.aug;
+  double2* __restrict__ X = J.X;
+  int* info = J.info;
   const int W = nB + nS;
   for (int t = threadIdx.x; t < nB * W; t += blockDim.x) {
     const int r = t / W, c = t - r * W;
@@ -212,33 +235,52 @@ void coeff_finish(hipStream_t st, int kind, const double* coeff, int64_t N, int 
   SPP_LAUNCH_CHECK();
 }
 
-void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2, StencilDev& S,
+size_t stencil_work_elems(const StencilDev& S) {
+  return (size_t)S.nG * S.nG + (size_t)S.nG * S.nB + (size_t)S.nB * (S.nB + S.nS);
+}
+
+void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2, StencilDev* types, int ntypes,
                    double2* work, int* info) {
-  const int nS = S.nS, nB = S.nB, nG = S.nG;
-  double2* Ggg = work;                       // nG x nG
-  double2* M = Ggg + (size_t)nG * nG;        // nG x nB: (G G^H)(gamma, beta) - G(gamma,gamma) G(gamma,beta)
-  double2* aug = M + (size_t)nG * nB;        // nB x (nB + nS)
+  if (ntypes > 8) throw Error(-7, "at most 8 set types");
   const int T = 256;
-  gather_block_kernel<<<ceil_div((int64_t)nG * nG, T), T, 0, st>>>(g, d, n, S.off, 0, nG, 0, nG, Ggg);
+  SolveJobs jobs{};
+  std::vector<double2*> ggg(ntypes), mm(ntypes);
+  double2* w = work;
+  for (int t = 0; t < ntypes; ++t) {
+    StencilDev& S = types[t];
+    const int nS = S.nS, nB = S.nB, nG = S.nG;
+    double2* Ggg = w;                          // nG x nG
+    double2* M = Ggg + (size_t)nG * nG;        // nG x nB: (G G^H)(gamma, beta) - G(gamma,gamma) G(gamma,beta)
+    double2* aug = M + (size_t)nG * nB;        // nB x (nB + nS)
+    w += stencil_work_elems(S);
+    ggg[t] = Ggg;
+    mm[t] = M;
+    gather_block_kernel<<<ceil_div((int64_t)nG * nG, T), T, 0, st>>>(g, d, n, S.off, 0, nG, 0, nG, Ggg);
+    SPP_LAUNCH_CHECK();
+    gather_block_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(g2, d, n, S.off, 0, nG, nS, nB, M);
+    SPP_LAUNCH_CHECK();
+    small_gemm_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(
+        nG, nB, nG, cmake<double2>(-1.0, 0.0), Ggg, nG, Ggg + nS, nG, 1.0, M, nB);
+    SPP_LAUNCH_CHECK();
+    // T_S M(beta, :) = M(S, :)
+    jobs.job[t] = SolveJob{nB, nS, M + (size_t)nS * nB, nB, M, nB, aug, S.T, nB, info + t};
+  }
+  right_solve_kernel<<<ntypes, 1024, 0, st>>>(jobs);
   SPP_LAUNCH_CHECK();
-  gather_block_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(g2, d, n, S.off, 0, nG, nS, nB, M);
-  SPP_LAUNCH_CHECK();
-  small_gemm_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(
-      nG, nB, nG, cmake<double2>(-1.0, 0.0), Ggg, nG, Ggg + nS, nG, 1.0, M, nB);
-  SPP_LAUNCH_CHECK();
-  // T_S M(beta, :) = M(S, :)
-  right_solve_kernel<<<1, 1024, 0, st>>>(nB, nS, M + (size_t)nS * nB, nB, M, nB, aug, S.T, nB, info);
-  SPP_LAUNCH_CHECK();
-  // C_S = G(S, gamma) - T_S G(beta, gamma)
-  SPP_HIP(hipMemcpy2DAsync(S.C, sizeof(double2) * nG, Ggg, sizeof(double2) * nG, sizeof(double2) * nG, nS,
-                           hipMemcpyDeviceToDevice, st));
-  small_gemm_kernel<<<ceil_div((int64_t)nS * nG, T), T, 0, st>>>(
-      nS, nG, nB, cmake<double2>(-1.0, 0.0), S.T, nB, Ggg + (size_t)nS * nG, nG, 1.0, S.C, nG);
-  SPP_LAUNCH_CHECK();
-  transpose_kernel<<<ceil_div((int64_t)nS * nB, T), T, 0, st>>>(S.T, nS, nB, S.Tt);
-  SPP_LAUNCH_CHECK();
-  transpose_kernel<<<ceil_div((int64_t)nS * nG, T), T, 0, st>>>(S.C, nS, nG, S.Ct);
-  SPP_LAUNCH_CHECK();
+  for (int t = 0; t < ntypes; ++t) {
+    StencilDev& S = types[t];
+    const int nS = S.nS, nB = S.nB, nG = S.nG;
+    // C_S = G(S, gamma) - T_S G(beta, gamma)
+    SPP_HIP(hipMemcpy2DAsync(S.C, sizeof(double2) * nG, ggg[t], sizeof(double2) * nG, sizeof(double2) * nG, nS,
+                             hipMemcpyDeviceToDevice, st));
+    small_gemm_kernel<<<ceil_div((int64_t)nS * nG, T), T, 0, st>>>(
+        nS, nG, nB, cmake<double2>(-1.0, 0.0), S.T, nB, ggg[t] + (size_t)nS * nG, nG, 1.0, S.C, nG);
+    SPP_LAUNCH_CHECK();
+    transpose_kernel<<<ceil_div((int64_t)nS * nB, T), T, 0, st>>>(S.T, nS, nB, S.Tt);
+    SPP_LAUNCH_CHECK();
+    transpose_kernel<<<ceil_div((int64_t)nS * nG, T), T, 0, st>>>(S.C, nS, nG, S.Ct);
+    SPP_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace spp
