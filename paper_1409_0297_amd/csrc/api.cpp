@@ -377,7 +377,7 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->wv = F->dalloc<char>((size_t)F->planp->vec_elems * r * F->csize);
   F->zv = F->dalloc<char>((size_t)F->planp->vec_elems * r * F->csize);
   F->xc = F->dalloc<char>((size_t)N * r * F->csize);
-  F->gpart_cap = (int64_t)131072 * r;
+  F->gpart_cap = ((int64_t)1 << 20) * r;
   F->gpart = F->dalloc<char>((size_t)F->gpart_cap * F->csize);
   F->V = F->dalloc<double2>((size_t)(it + 1) * r * N);
   F->Z = F->dalloc<double2>((size_t)it * r * N);
@@ -395,7 +395,7 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->zfix = F->dalloc<double2>((size_t)r * N);
   F->dj = F->dalloc<int>(1);
   int64_t nblk = 1;
-  for (const SppGroup& g : F->groups) nblk = std::max<int64_t>(nblk, (g.N + 1023) / 1024);
+  for (const SppGroup& g : F->groups) nblk = std::max<int64_t>(nblk, kr_dot_slots(g.N));
   F->dpart = F->dalloc<double2>((size_t)nblk * cols * (it + 1));
   F->rpart = F->dalloc<double>((size_t)(256 + 1) * cols + 64);
   F->resid = F->dalloc<double>(cols);
@@ -496,6 +496,9 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
     }
   }
   const Plan& P = *F->planp;
+  // (the substitution candidates are timed with cold caches, see tune_time)
+  const size_t flush_bytes = (size_t)768 << 20;
+  void* flush = F->dalloc<char>(flush_bytes);
   for (size_t l = 0; l < P.levels.size(); ++l) {
     if (F->level_form[l] == kFormLU) continue;
     const Level& L = P.levels[l];
@@ -522,12 +525,14 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
           else
             mf_gemv<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
                            0.0, F->gpart, F->gpart_cap, c);
-        });
+        }, flush, flush_bytes);
         if (t < bt) { bt = t; best = c; }
       }
       tune_set(key, best);
     }
   }
+  SPP_HIP(hipStreamSynchronize(st));
+  F->dfree(flush);
   tune_save();
   g_timer = saved;
   F->tuned_nrhs = nrhs;

@@ -151,6 +151,8 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
 // h_out[i] (+)= V_i^H w per right-hand side; if h_acc, also h_acc[i] += V_i^H w.
 // dj (optional, for graph replays): the iteration index j in device memory;
 // then nvec = j + 1 and h_out / h_acc / v / h_sub are offset by j * jstride.
+// Partial-sum slots per vector and right-hand side that kr_dots needs.
+int64_t kr_dot_slots(int64_t N);
 void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const double2* w,
              int nrhs, int64_t N, double2* partial, double2* h_out, int hstride, int accumulate,
              double2* h_acc, int acc_stride, const int* dj = nullptr, int64_t h_jstride = 0,
@@ -187,7 +189,8 @@ void tune_force(const std::string& key, int value);   // value < 0 clears
 void tune_set(const std::string& key, int value);
 bool tune_has(const std::string& key);
 void tune_save();
-float tune_time(hipStream_t st, int reps, const std::function<void()>& fn);
+float tune_time(hipStream_t st, int reps, const std::function<void()>& fn, void* flush = nullptr,
+                size_t flush_bytes = 0);
 
 // FFT lines per workgroup: heuristic, valid candidates, key (fft.hip).
 int fft_lines_default(int n, int64_t outer, int64_t inner);

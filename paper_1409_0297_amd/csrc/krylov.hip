@@ -15,7 +15,7 @@ namespace spp {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPerThread = 4;
+constexpr int kPerThread = 2;
 constexpr int kMaxVec = 512;
 
 __device__ inline double2 wave_sum(double2 v) {
@@ -38,34 +38,41 @@ __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* _
                                                                 double2* __restrict__ partial, const int* dj) {
   if (dj) nvec = *dj + 1;
   const int rhs = blockIdx.y;
-  const int nblk = gridDim.x;
-  const int64_t chunk = (int64_t)kThreads * kPerThread;
-  const int64_t e0 = blockIdx.x * chunk + threadIdx.x;
+  const int nslot = gridDim.x * (kThreads / 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = blockIdx.x * (kThreads / 64) + wave;
+  // Each wave sums its own kPerThread * 64 entries and writes one partial
+  // per vector (no LDS: many small blocks keep enough loads in flight).
+  const int64_t e0 = (int64_t)slot * 64 * kPerThread + lane;
   const double2* wr = w + rhs * N;
   double2 wl[kPerThread];
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t e = e0 + (int64_t)k * kThreads;
+    const int64_t e = e0 + (int64_t)k * 64;
     wl[k] = (e < N) ? wr[e] : cmake<double2>(0, 0);
   }
-  __shared__ double2 sh[kThreads / 64][kMaxVec];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = 0; i < nvec; ++i) {
-    const double2* vr = V + (int64_t)i * vstride + rhs * N;
-    double2 s = cmake<double2>(0, 0);
+  // Four vectors per pass: their loads are all in flight before any sum.
+  constexpr int kG = 4;
+  for (int i0 = 0; i0 < nvec; i0 += kG) {
+    double2 s[kG];
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-      const int64_t e = e0 + (int64_t)k * kThreads;
-      if (e < N) s = cadd(s, cconjmul(vr[e], wl[k]));
+    for (int q = 0; q < kG; ++q) {
+      s[q] = cmake<double2>(0, 0);
+      if (i0 + q < nvec) {
+        const double2* vr = V + (int64_t)(i0 + q) * vstride + rhs * N;
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+          const int64_t e = e0 + (int64_t)k * 64;
+          if (e < N) s[q] = cadd(s[q], cconjmul(vr[e], wl[k]));
+        }
+      }
     }
-    s = wave_sum(s);
-    if (lane == 0) sh[wave][i] = s;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nvec; i += kThreads) {
-    double2 s = cmake<double2>(0, 0);
-    for (int q = 0; q < kThreads / 64; ++q) s = cadd(s, sh[q][i]);
-    partial[((int64_t)rhs * nblk + blockIdx.x) * nvec + i] = s;
+#pragma unroll
+    for (int q = 0; q < kG; ++q) {
+      if (i0 + q >= nvec) break;
+      const double2 t = wave_sum(s[q]);
+      if (lane == 0) partial[((int64_t)rhs * nslot + slot) * nvec + i0 + q] = t;
+    }
   }
 }
 
@@ -132,14 +139,18 @@ __global__ void __launch_bounds__(kThreads) sumsq_partial_kernel(const double2* 
   }
 }
 
-// norms[rhs] = sqrt(sum of partials); optionally H entry = norm.
-__global__ void sumsq_final_kernel(const double* __restrict__ partial, int nblk, int nrhs, double* norms,
-                                   double2* h_sub, int hstride, const int* dj, int64_t h_jstride) {
+// norms[rhs] = sqrt(sum of partials); optionally H entry = norm.  One
+// wavefront (blockIdx.x) per right-hand side.
+__global__ void __launch_bounds__(64) sumsq_final_kernel(const double* __restrict__ partial, int nblk, int nrhs,
+                                                         double* norms, double2* h_sub, int hstride, const int* dj,
+                                                         int64_t h_jstride) {
   if (dj && h_sub) h_sub += *dj * h_jstride;
-  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.x;
   if (rhs >= nrhs) return;
   double s = 0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)rhs * nblk + b];
+  for (int b = threadIdx.x; b < nblk; b += 64) s += partial[(int64_t)rhs * nblk + b];
+  s = wave_sum(s);
+  if (threadIdx.x != 0) return;
   const double nrm = sqrt(s);
   norms[rhs] = nrm;
   if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
@@ -257,6 +268,8 @@ int dot_blocks(int64_t N) { return (int)ceil_div(N, (int64_t)kThreads * kPerThre
 
 }  // namespace
 
+int64_t kr_dot_slots(int64_t N) { return (int64_t)dot_blocks(N) * (kThreads / 64); }
+
 void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const double2* w, int nrhs, int64_t N,
              double2* partial, double2* h_out, int hstride, int accumulate, double2* h_acc, int acc_stride,
              const int* dj, int64_t h_jstride, int64_t acc_jstride) {
@@ -264,7 +277,8 @@ void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const 
   const int nblk = dot_blocks(N);
   dots_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, partial, dj);
   SPP_LAUNCH_CHECK();
-  dots_final_kernel<<<dim3(ceil_div(nvec, 4), nrhs), 256, 0, st>>>(partial, nblk, nvec, h_out, hstride, accumulate,
+  const int nslot = (int)kr_dot_slots(N);
+  dots_final_kernel<<<dim3(ceil_div(nvec, 4), nrhs), 256, 0, st>>>(partial, nslot, nvec, h_out, hstride, accumulate,
                                                                        h_acc, acc_stride, dj, h_jstride, acc_jstride);
   SPP_LAUNCH_CHECK();
 }
@@ -280,7 +294,7 @@ void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* par
   const int nblk = 256;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(v, N, partial);
   SPP_LAUNCH_CHECK();
-  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, out, nullptr, 0, nullptr, 0);
+  sumsq_final_kernel<<<nrhs, 64, 0, st>>>(partial, nblk, nrhs, out, nullptr, 0, nullptr, 0);
   SPP_LAUNCH_CHECK();
 }
 
@@ -291,7 +305,7 @@ void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64
   double* norms = partial + (int64_t)nblk * nrhs;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(w, N, partial);
   SPP_LAUNCH_CHECK();
-  sumsq_final_kernel<<<ceil_div(nrhs, 64), 64, 0, st>>>(partial, nblk, nrhs, norms, h_sub, hstride, dj, h_jstride);
+  sumsq_final_kernel<<<nrhs, 64, 0, st>>>(partial, nblk, nrhs, norms, h_sub, hstride, dj, h_jstride);
   SPP_LAUNCH_CHECK();
   scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, norms, N, dj, v_jstride);
   SPP_LAUNCH_CHECK();

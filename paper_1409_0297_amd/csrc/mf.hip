@@ -1105,20 +1105,28 @@ __global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2*
 
 // ------------------------------------------------------------------ solve
 // Vectors per front: w and z arenas, position-major, nrhs consecutive values.
+// w of every front of a level: x at the pivots, zero elsewhere, plus the
+// children's boundary updates.  blockIdx.x = range of kGatherRows front
+// positions (each workgroup applies the children's updates that land in its
+// range, children in order, so the sums are deterministic), blockIdx.y = front.
+constexpr int kGatherRows = 256;
+
 template <typename R>
 __global__ void fwd_gather_kernel(MfDev mf, cplx_t<R>* __restrict__ W, const cplx_t<R>* __restrict__ x, int nrhs, int f0) {
   using C = cplx_t<R>;
-  const FrontDev f = mf.fronts[f0 + blockIdx.x];
+  const FrontDev f = mf.fronts[f0 + blockIdx.y];
+  const int lo = blockIdx.x * kGatherRows, hi = min(f.F, lo + kGatherRows);
+  if (lo >= hi) return;
   C* w = W + f.voff * nrhs;
   const int* idx = mf.idx + f.idx;
   const InstDev& I = mf.inst[f.inst];
   const C* xi = x + I.Noff * nrhs;
-  for (int t = threadIdx.x; t < f.F * nrhs; t += blockDim.x) {
-    const int i = t / nrhs, r = t - i * nrhs;
-    w[t] = (i < f.p) ? xi[(int64_t)r * I.N + idx[i]] : cmake<C>(0, 0);
+  for (int t = threadIdx.x; t < (hi - lo) * nrhs; t += blockDim.x) {
+    const int i = lo + t / nrhs, r = t % nrhs;
+    w[i * nrhs + r] = (i < f.p) ? xi[(int64_t)r * I.N + idx[i]] : cmake<C>(0, 0);
   }
   __syncthreads();
-  const int* children = mf.fronts[f0 + blockIdx.x].child;   // global, indexed at run time
+  const int* children = mf.fronts[f0 + blockIdx.y].child;   // global, indexed at run time
   for (int c = 0; c < f.nchild; ++c) {
     const FrontDev& ch = mf.fronts[children[c]];
     const int K = ch.F - ch.p;
@@ -1126,7 +1134,9 @@ __global__ void fwd_gather_kernel(MfDev mf, cplx_t<R>* __restrict__ W, const cpl
     const C* wc = W + (ch.voff + ch.p) * nrhs;
     for (int t = threadIdx.x; t < K * nrhs; t += blockDim.x) {
       const int i = t / nrhs, r = t - i * nrhs;
-      C& d = w[map[i] * nrhs + r];
+      const int pos = map[i];
+      if (pos < lo || pos >= hi) continue;
+      C& d = w[pos * nrhs + r];
       d = cadd(d, wc[t]);
     }
     __syncthreads();
@@ -1898,7 +1908,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       front(f0, nf, level_maxF[l], mP, mK, true, e[0] + e[2]);
       continue;
     }
-    fwd_gather_kernel<R><<<nf, 256, 0, st>>>(mf, W, xin, nrhs, f0);
+    fwd_gather_kernel<R><<<dim3(ceil_div(level_maxF[l], kGatherRows), nf), 256, 0, st>>>(mf, W, xin, nrhs, f0);
     SPP_LAUNCH_CHECK();
     if (level_form[l] == kFormSide) {
       gemv(f0, nf, level_maxF[l], mP, 4, e[0] + e[2]);

@@ -102,13 +102,18 @@ void tune_save() {
 }
 
 // Median-free minimum of `reps` timed runs of fn on stream st (milliseconds).
-float tune_time(hipStream_t st, int reps, const std::function<void()>& fn) {
+float tune_time(hipStream_t st, int reps, const std::function<void()>& fn, void* flush, size_t flush_bytes) {
   hipEvent_t a, b;
   SPP_HIP(hipEventCreate(&a));
   SPP_HIP(hipEventCreate(&b));
   fn();   // warm-up
   float best = 1e30f;
   for (int r = 0; r < reps; ++r) {
+    // Operands that stay in the last-level cache between repetitions would
+    // time a candidate faster than it runs inside a solve, where every level
+    // streams its factors from HBM: overwrite a buffer larger than that
+    // cache first.
+    if (flush) SPP_HIP(hipMemsetAsync(flush, r & 0xff, flush_bytes, st));
     SPP_HIP(hipEventRecord(a, st));
     fn();
     SPP_HIP(hipEventRecord(b, st));
