@@ -695,6 +695,9 @@ __global__ void __launch_bounds__(256) trsm_kernel(MfDev mf, cplx_t<R>* __restri
 // mode 1: L inverse update   XL[k0+kb:p, 0:k0+kb] -= L[k0+kb:p, k0:k0+kb] XL[k0:k0+kb, 0:k0+kb]
 // mode 2: U inverse update   XU[0:k0, k0:p]       -= U[0:k0, k0:k0+kb]    XU[k0:k0+kb, k0:p]
 constexpr int kBM = 64, kBN = 64, kBK = 16;
+// Minimum waves per SIMD asked of the GEMM kernels: 4 in FP32 (fits without
+// spills); none in FP64, whose accumulators and prefetch registers need more.
+template <typename R> constexpr int kGemmWaves = sizeof(R) == 4 ? 4 : 1;
 
 // One 64 x 64 tile (rows m0.., columns n0..) of C = from_c ? C + sgn A B : sgn A B,
 // complex column-major operands, k restricted to [kbeg, kend).  brow (optional)
@@ -721,6 +724,9 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
   // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
   // im = sum (ar bi + ai br).  Updates start from C and take A scaled by sgn
   // when it is staged in LDS, so C -= A B needs no extra pass.
+  // Addresses are a tile base (uniform) plus 32-bit offsets inside the tile.
+  C* __restrict__ Ct = Cp + (int64_t)n0 * ldc + m0;
+  const int mt = m - m0, nt = n - n0;
   V re[2][2], im[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -728,28 +734,47 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
-        const int col = n0 + wn + 16 * b + (lane & 15);
+        const int row = wm + 16 * a + mfma_row(R(0), lane, r);
+        const int col = wn + 16 * b + (lane & 15);
         C c0 = cmake<C>(0, 0);
-        if (from_c && row < m && col < n) c0 = Cp[(int64_t)col * ldc + row];
+        if (from_c && row < mt && col < nt) c0 = Ct[col * ldc + row];
         re[a][b][r] = c0.x;
         im[a][b][r] = c0.y;
       }
   kend = min(kend, k);
-  for (int kk0 = kbeg; kk0 < kend; kk0 += kBK) {
-    for (int e = threadIdx.x; e < kBM * kBK; e += 256) {
-      const int row = e % kBM, kk = e / kBM;
-      const int gr = m0 + row, gk = kk0 + kk;
-      const C v = (gr < m && gk < kend) ? Ap[(int64_t)gk * lda + gr] : cmake<C>(0, 0);
-      As[kk][row] = cmake<C>(sgn * v.x, sgn * v.y);
+  // Register prefetch: the next stage's operands are loaded while the
+  // current stage runs on MFMA (one LDS buffer, two barriers per stage).
+  constexpr int kPer = kBM * kBK / 256;
+  static_assert(kBN * kBK / 256 == kPer, "A and B stages must split alike");
+  C ra[kPer], rb[kPer];
+  const C* __restrict__ Bt = Bp + (int64_t)n0 * ldb;
+  auto load_stage = [&](int kk0) {
+    const C* __restrict__ At = Ap + (int64_t)kk0 * lda + m0;
+    const int kt = kend - kk0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      {
+        const int row = e % kBM, kk = e / kBM;
+        ra[u] = (row < mt && kk < kt) ? At[kk * lda + row] : cmake<C>(0, 0);
+      }
+      {
+        const int kk = e % kBK, col = e / kBK;
+        const int br = brow ? brow[kk < kt ? kk0 + kk : 0] - brow_off : kk0 + kk;
+        rb[u] = (kk < kt && col < nt) ? Bt[col * ldb + br] : cmake<C>(0, 0);
+      }
     }
-    for (int e = threadIdx.x; e < kBK * kBN; e += 256) {
-      const int kk = e % kBK, col = e / kBK;
-      const int gk = kk0 + kk, gc = n0 + col;
-      const int br = brow ? brow[gk < kend ? gk : 0] - brow_off : gk;
-      Bs[kk][col] = (gk < kend && gc < n) ? Bp[(int64_t)gc * ldb + br] : cmake<C>(0, 0);
+  };
+  if (kbeg < kend) load_stage(kbeg);
+  for (int kk0 = kbeg; kk0 < kend; kk0 += kBK) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      As[e / kBM][e % kBM] = cmake<C>(sgn * ra[u].x, sgn * ra[u].y);
+      Bs[e % kBK][e / kBK] = rb[u];
     }
     __syncthreads();
+    if (kk0 + kBK < kend) load_stage(kk0 + kBK);
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
       C av[2], bv[2];
@@ -775,10 +800,10 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + 16 * a + mfma_row(R(0), lane, r);
-        const int col = n0 + wn + 16 * b + (lane & 15);
-        if (row < m && col < n && !(row < skip && col < skip))
-          Cp[(int64_t)col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
+        const int row = wm + 16 * a + mfma_row(R(0), lane, r);
+        const int col = wn + 16 * b + (lane & 15);
+        if (row < mt && col < nt && !(m0 + row < skip && n0 + col < skip))
+          Ct[col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
       }
 }
 
@@ -801,9 +826,9 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 // NEXT (mode 0 only): the launch's last workgroup column (blockIdx.x ==
 // gridDim.x - 1) factors the next diagonal block of each front, taking this
 // step's update of that block itself; the tile holding the block skips it.
-template <typename R, bool NEXT>
+template <typename R, bool NEXT, int mode>
 __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
-                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode, int tiles_m) {
+                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m) {
   using C = cplx_t<R>;
   constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > sizeof(GemmLds<R>) ? sizeof(DiagLds<R>) : sizeof(GemmLds<R>))
                                : sizeof(GemmLds<R>);
@@ -828,7 +853,7 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
   int tm, tn;
   const int* brow = nullptr;
   bool assign = false;
-  if (mode == 7) {
+  if constexpr (mode == 7) {
     const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
     const C* Ui = Li + kDB * kDB;
     assign = true;
@@ -849,12 +874,12 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
   } else {
     tm = blockIdx.x % tiles_m;
     tn = blockIdx.x / tiles_m;
-    if (mode == 0) {
+    if constexpr (mode == 0) {
       m = n = F - k0 - kb; k = kb;
       Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
       Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
       Cp = base + (int64_t)(k0 + kb) * F + (k0 + kb); ldc = F;
-    } else if (mode == 1) {
+    } else if constexpr (mode == 1) {
       C* XL = xwork + f.xoff;
       m = p - k0 - kb; n = k0 + kb; k = kb;
       Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
@@ -874,11 +899,11 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
                     assign ? R(1) : R(-1), 0, k, brow, 0, skip);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
-                                                   cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int mode,
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256, kGemmWaves<R>) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
+                                                   cplx_t<R>* __restrict__ dinv, int f0, int step, int nb,
                                                    int tiles_m) {
-  gemm_body<R, false>(mf, arena, xwork, dinv, f0, step, nb, mode, tiles_m);
+  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m);
 }
 
 // Trailing update with the next diagonal block (mode 0, NEXT above); asks
@@ -888,7 +913,7 @@ template <typename R>
 __global__ void __launch_bounds__(256, 4) gemm_next_kernel(MfDev mf, cplx_t<R>* __restrict__ arena,
                                                            cplx_t<R>* __restrict__ xwork, cplx_t<R>* __restrict__ dinv,
                                                            int f0, int step, int nb, int tiles_m) {
-  gemm_body<R, true>(mf, arena, xwork, dinv, f0, step, nb, 0, tiles_m);
+  gemm_body<R, true, 0>(mf, arena, xwork, dinv, f0, step, nb, tiles_m);
 }
 
 // Row interchanges of every 32-row diagonal block of a level's fronts applied
@@ -929,7 +954,7 @@ __global__ void __launch_bounds__(256) leftswap_kernel(MfDev mf, cplx_t<R>* __re
 // and TU sit at the same positions of the p x p temporary tbuf.  blockIdx.z =
 // 2 pair + (0: L, 1: U); k is cut to where the triangular factor is nonzero.
 template <typename R>
-__global__ void __launch_bounds__(256) inv_gemm_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+__global__ void __launch_bounds__(256, kGemmWaves<R>) inv_gemm_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
                                                        cplx_t<R>* __restrict__ xwork, cplx_t<R>* __restrict__ tbuf,
                                                        int f0, int h, int phase, int tiles_m) {
   using C = cplx_t<R>;
@@ -1011,7 +1036,7 @@ __global__ void identity_kernel(MfDev mf, cplx_t<R>* __restrict__ xwork, int f0)
 //   Ut = XU U12  (p x (F - p), column-major, ld p)        blockIdx.z = 1
 // in the front's work slot after XL and XU; k is cut to the triangle.
 template <typename R>
-__global__ void __launch_bounds__(256) inv_side_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+__global__ void __launch_bounds__(256, kGemmWaves<R>) inv_side_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
                                                        cplx_t<R>* __restrict__ xwork, int f0, int tiles_m) {
   using C = cplx_t<R>;
   const FrontDev& f = mf.fronts[f0 + blockIdx.y];
@@ -1634,7 +1659,17 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       // L21 = A21 Uinv_kk and U12 = Linv_kk P A12 on MFMA in one launch (one
       // 64-wide tile strip each); the block's row order P is applied while
       // loading A12, the rows' L parts are reordered once after the last step.
-      gemm_kernel<R><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 7, tiles);
+      // 16 m kb^2 real flops per front (m = F - k0 - kb rows and columns).
+      double fl = 0;
+      if (g_timer)
+        for (int i = 0; i < nf; ++i) {
+          if (k0 >= hP[i]) continue;
+          const double kb = std::min(kNB, hP[i] - k0), m = hF[i] - k0 - kb;
+          fl += 16.0 * m * kb * kb;
+        }
+      timer_begin(KC_GEMM, st);
+      gemm_kernel<R, 7><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+      timer_end(KC_GEMM, st, 0.0, fl);
     }
     SPP_LAUNCH_CHECK();
     {
@@ -1653,7 +1688,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       if (!partial_pivoting && s + 1 < steps && nf <= 64)
         gemm_next_kernel<R><<<dim3(tiles * tiles + 1, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
       else
-        gemm_kernel<R><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, 0, tiles);
+        gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
       SPP_LAUNCH_CHECK();
       timer_end(KC_GEMM, st, 0.0, fl);
     }
@@ -1698,7 +1733,10 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       for (int s = 0; s < steps; ++s) {
         trsm_kernel<R><<<dim3(ceil_div(maxP, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, mode);
         SPP_LAUNCH_CHECK();
-        gemm_kernel<R><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, mode, ptiles);
+        if (mode == 1)
+          gemm_kernel<R, 1><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, ptiles);
+        else
+          gemm_kernel<R, 2><<<dim3(ptiles * ptiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, ptiles);
         SPP_LAUNCH_CHECK();
       }
     }
@@ -1709,9 +1747,15 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   if (form == kFormSide)
     for (int i = 0; i < nf; ++i) maxK = std::max(maxK, hF[i] - hP[i]);
   if (maxK > 0) {
+    // 8 (F - p) p^2 real flops per front (two products cut to the triangle).
+    double fl = 0;
+    if (g_timer)
+      for (int i = 0; i < nf; ++i) fl += 8.0 * (hF[i] - hP[i]) * (double)hP[i] * hP[i];
     const int tiles_m = (int)ceil_div(std::max(maxK, maxP), kBM);
+    timer_begin(KC_GEMM, st);
     inv_side_kernel<R><<<dim3(tiles_m * tiles_m, nf, 2), 256, 0, st>>>(mf, arena, xwork, f0, tiles_m);
     SPP_LAUNCH_CHECK();
+    timer_end(KC_GEMM, st, 0.0, fl);
   }
   const int64_t merge_items = std::max<int64_t>((int64_t)maxP * maxP, (int64_t)maxK * maxP);
   merge_inverse_kernel<R><<<dim3(ceil_div(merge_items, 256 * 4), nf), 256, 0, st>>>(mf, arena, xwork, f0, maxK > 0);
