@@ -115,7 +115,7 @@ def measured_traffic(kernel_class, prec):
     source has changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"large2d_{prec}_front_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"large2d_{prec}_{kernel_class}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()

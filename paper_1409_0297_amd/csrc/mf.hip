@@ -1719,12 +1719,12 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
             const double nbv = std::min(h, hP[i] - o - h);
             fl += 2 * 8.0 * nbv * h * (h + nbv) / 2;   // both triangles, products cut to the nonzero half
           }
-      timer_begin(KC_GEMM, st);
-      for (int phase = 0; phase < 2; ++phase) {
+      for (int phase = 0; phase < 2; ++phase) {   // (the two phases have equal flops)
+        timer_begin(KC_GEMM, st);
         inv_gemm_kernel<R><<<dim3(ht * ht, nf, 2 * pairs), 256, 0, st>>>(mf, arena, xwork, tbuf, f0, h, phase, ht);
         SPP_LAUNCH_CHECK();
+        timer_end(KC_GEMM, st, 0.0, fl / 2);
       }
-      timer_end(KC_GEMM, st, 0.0, fl);
     }
   } else {
     identity_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, f0);
