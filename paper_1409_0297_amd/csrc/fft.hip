@@ -154,6 +154,115 @@ fft_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw,
   }
 }
 
+// ------------------------------------------------------------------ radix-8
+// Lengths n = 8^S (64, 512, 4096): a register Stockham FFT.  T = n / 8 lanes
+// per line hold 8 points each; a stage is one radix-8 butterfly per lane in
+// registers, with an LDS exchange between stages (S stages, S - 1 exchanges
+// per transform).  A workgroup takes L lines: along the line (inner == 1,
+// lane = position-major) or L neighbouring lines of a strided axis (lane =
+// line-major, so a load of the L lines' entries at one position is one
+// contiguous L x 16 B piece).  Same fused options as fft_axis_kernel.
+__device__ inline double2 rot_i(double2 z, int dir) {   // dir * i * z
+  return (dir < 0) ? cmake<double2>(z.y, -z.x) : cmake<double2>(-z.y, z.x);
+}
+
+__device__ inline void dft8(double2* v, int dir) {
+  // Evens and odds by 4-point DFTs, then y_k = E_k + w^k O_k, y_{k+4} = E_k - w^k O_k.
+  const double2 t0 = cadd(v[0], v[4]), t1 = csub(v[0], v[4]);
+  const double2 t2 = cadd(v[2], v[6]), t3 = rot_i(csub(v[2], v[6]), dir);
+  const double2 e0 = cadd(t0, t2), e2 = csub(t0, t2), e1 = cadd(t1, t3), e3 = csub(t1, t3);
+  const double2 u0 = cadd(v[1], v[5]), u1 = csub(v[1], v[5]);
+  const double2 u2 = cadd(v[3], v[7]), u3 = rot_i(csub(v[3], v[7]), dir);
+  const double2 o0 = cadd(u0, u2), o2 = csub(u0, u2), o1 = cadd(u1, u3), o3 = csub(u1, u3);
+  constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
+  // w = exp(dir 2 pi i / 8): w^1 = (1 + dir i) h, w^2 = dir i, w^3 = (-1 + dir i) h
+  const double2 w1o1 = cmake<double2>(h * (o1.x - dir * o1.y), h * (o1.y + dir * o1.x));
+  const double2 w2o2 = rot_i(o2, dir);
+  const double2 w3o3 = cmake<double2>(h * (-o3.x - dir * o3.y), h * (-o3.y + dir * o3.x));
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, w1o1); v[5] = csub(e1, w1o1);
+  v[2] = cadd(e2, w2o2); v[6] = csub(e2, w2o2);
+  v[3] = cadd(e3, w3o3); v[7] = csub(e3, w3o3);
+}
+
+// LDS index of line position i: one pad entry per 8 (the stage writes go 8
+// or Ns apart per lane; the pad spreads them over the banks).
+__device__ inline int pad8(int i) { return i + (i >> 3); }
+
+// All S stages of one transform direction; on entry v[r] = x[t + T r], on
+// exit v[r] = y[t + T r] (the last stage's outputs land in natural order).
+// lds = this line's n + n / 8 entries.
+template <int S>
+__device__ inline void fft8_stages(double2* v, double2* lds, int t, int dir, const double2* __restrict__ tw) {
+  constexpr int n = 1 << (3 * S), T = n / 8;
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int Ns = 1 << (3 * st);
+    const int k = t & (Ns - 1);
+    if (st > 0) {
+      const int stride = n / (Ns * 8);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twiddle(tw, (r * k * stride) & (n - 1), dir));
+    }
+    dft8(v, dir);
+    if (st + 1 < S) {
+      const int base = (t / Ns) * Ns * 8 + k;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[pad8(base + r * Ns)] = v[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = lds[pad8(t + T * r)];
+    }
+  }
+}
+
+template <int S, int L, bool STRIDED>
+__global__ void __launch_bounds__((1 << (3 * S)) / 8 * L)
+fft8_axis_kernel(const double2* in, double2* out, const double2* __restrict__ tw, int64_t outer, int64_t inner,
+                 int64_t N, int dir, const double* __restrict__ pre, const double* __restrict__ mid,
+                 const double2* add, int per) {
+  constexpr int n = 1 << (3 * S), T = n / 8;
+  extern __shared__ double2 lds8[];
+  const int tid = threadIdx.x;
+  const int li = STRIDED ? tid % L : tid / T;
+  const int t = STRIDED ? tid / L : tid % T;
+  const int64_t lines_per_batch = outer * inner;
+  const int64_t wg_per_batch = lines_per_batch / L;
+  const int64_t batch = blockIdx.x / wg_per_batch;
+  const int64_t line = (blockIdx.x - batch * wg_per_batch) * L + li;
+  const int64_t bofs = batch * N;
+  const int64_t aofs = (batch / per) * N;
+  const int64_t o = line / inner, i = line - o * inner;
+  const int64_t lbase = o * n * inner + i;   // grid index of position 0 of this line
+  double2* my = lds8 + li * (n + n / 8);
+  double2 v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int64_t a = lbase + (int64_t)(t + T * r) * inner;
+    v[r] = in[bofs + a];
+    if (pre) { const double q = pre[aofs + a]; v[r].x *= q; v[r].y *= q; }
+  }
+  fft8_stages<S>(v, my, t, dir, tw);
+  if (mid) {
+    // Fourier-side multiplier, then the inverse transform of the same lines
+    // (the registers already hold the entries in the order it starts from).
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double m = mid[aofs + lbase + (int64_t)(t + T * r) * inner];
+      v[r].x *= m; v[r].y *= m;
+    }
+    fft8_stages<S>(v, my, t, -dir, tw);
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int64_t a = lbase + (int64_t)(t + T * r) * inner;
+    double2 y = v[r];
+    if (add) y = cadd(y, add[bofs + a]);
+    out[bofs + a] = y;
+  }
+}
+
 __global__ void twiddle_kernel(double2* tw, int n) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m < n) {
@@ -212,6 +321,44 @@ void fft_axis(hipStream_t st, const double2* in, double2* out, const double2* tw
   if (m != 1 || s > kMaxStages) throw Error(-7, "FFT length must be 2^a 3^b");
   g.nstages = s;
   const int64_t lines = outer * inner;
+  // Algorithmic bytes: read and write every complex point once, plus the
+  // fused real multipliers and the added vector.
+  {
+    const double pts = (double)N * batch;
+    const double ninst = (double)((batch + per - 1) / per);
+    const double bytes = pts * 32.0 + (pre ? 8.0 * N * ninst : 0.0) + (mid ? 8.0 * N * ninst : 0.0) +
+                         (add ? 16.0 * pts : 0.0);
+    const int perv = per > 0 ? per : batch;
+    // Radix-8 lengths: L lines per workgroup from the same tuning table as
+    // the general kernel (L in {1, 2, 4, 8} at n = 512, {8, 16, 32} at 64).
+    if ((n == 512 || n == 64) && (inner == 1 || inner % 8 == 0)) {
+      const bool strided = inner != 1;
+      int L8 = tune_get(fft_tune_key(n, outer, inner, batch), n == 512 ? (strided ? 4 : 2) : 32);
+      if (n == 512) L8 = std::min(std::max(L8, 1), 8);
+      else L8 = std::min(std::max(L8, 8), 32);
+      while (L8 > 1 && (lines % L8 != 0 || (strided && inner % L8 != 0))) L8 /= 2;
+      const size_t row = sizeof(double2) * (n + n / 8);
+      const unsigned blocks = (unsigned)(batch * (lines / L8));
+      const unsigned threads = (unsigned)(n / 8 * L8);
+      const void* kern = nullptr;
+#define SPP_FFT8(S_, L_)                                                                   \
+  if (n == (1 << (3 * S_)) && L8 == L_)                                                  \
+    kern = strided ? (const void*)fft8_axis_kernel<S_, L_, true> : (const void*)fft8_axis_kernel<S_, L_, false>;
+      SPP_FFT8(3, 1) SPP_FFT8(3, 2) SPP_FFT8(3, 4) SPP_FFT8(3, 8)
+      SPP_FFT8(2, 8) SPP_FFT8(2, 16) SPP_FFT8(2, 32)
+#undef SPP_FFT8
+      if (kern && threads >= 64 && threads <= 1024) {
+        int64_t outer_v = outer, inner_v = inner, N_v = N;
+        int dir_v = dir, per_v = perv;
+        void* args[] = {(void*)&in, (void*)&out, (void*)&tw, &outer_v, &inner_v, &N_v, &dir_v,
+                        (void*)&pre, (void*)&mid, (void*)&add, &per_v};
+        timer_begin(KC_FFT, st);
+        SPP_HIP(hipLaunchKernel(kern, dim3(blocks), dim3(threads), args, L8 * row, st));
+        timer_end(KC_FFT, st, bytes, 0.0);
+        return;
+      }
+    }
+  }
   int L = tune_get(fft_tune_key(n, outer, inner, batch), fft_lines_default(n, outer, inner));
   if (!fft_lines_valid(n, outer, inner, L)) L = fft_lines_default(n, outer, inner);
   g.L = L;
