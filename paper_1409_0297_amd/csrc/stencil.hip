@@ -145,46 +145,44 @@ __global__ void right_solve_kernel(SolveJobs jobs) {
     const int r = t / W, c = t - r * W;
     aug[t] = (c < nB) ? A[c * lda + r] : Bm[(c - nB) * ldb + r];
   }
-  __shared__ double smax[1024];
-  __shared__ int sidx[1024];
+  // Pivot keys: for v >= 0 the IEEE bits order like integers; the low 12
+  // bits carry 4095 - row (largest modulus, ties to the lowest row; nB <=
+  // 4096).  The search of column c + 1 is fused into the update of step c
+  // (the lanes updating that column post their rows' keys), so a step needs
+  // two barriers: after the row swap and after the update.  Two key slots
+  // alternate between columns.
+  __shared__ unsigned long long keys[2];
+  auto key_of = [](double v, int row) {
+    return ((unsigned long long)__double_as_longlong(v) & ~0xFFFULL) | (unsigned long long)(4095 - row);
+  };
+  if (threadIdx.x < 2) keys[threadIdx.x] = 0;
   __syncthreads();
+  for (int r = threadIdx.x; r < nB; r += blockDim.x) atomicMax(&keys[0], key_of(cabs2(aug[r * W]), r));
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6, ny = blockDim.x >> 6;
   for (int c = 0; c < nB; ++c) {
-    double best = -1.0;
-    int bi = c;
-    for (int r = c + threadIdx.x; r < nB; r += blockDim.x) {
-      const double v = cabs2(aug[r * W + c]);
-      if (v > best) { best = v; bi = r; }
+    const unsigned long long key = keys[c & 1];
+    const int piv = 4095 - (int)(key & 0xFFF);
+    if (threadIdx.x == 0) {
+      if (!(__longlong_as_double((long long)(key & ~0xFFFULL)) > 0.0)) *info = 1;
+      keys[(c + 1) & 1] = 0;   // (last read at step c - 1, before its barriers)
     }
-    smax[threadIdx.x] = best;
-    sidx[threadIdx.x] = bi;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        const double o = smax[threadIdx.x + s];
-        const int oi = sidx[threadIdx.x + s];
-        if (o > smax[threadIdx.x] || (o == smax[threadIdx.x] && oi < sidx[threadIdx.x])) {
-          smax[threadIdx.x] = o;
-          sidx[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int piv = sidx[0];
-    if (!(smax[0] > 0.0) && threadIdx.x == 0) *info = 1;
-    __syncthreads();
     if (piv != c)
-      for (int t = threadIdx.x; t < W; t += blockDim.x) {
-        double2 a = aug[c * W + t];
-        aug[c * W + t] = aug[piv * W + t];
-        aug[piv * W + t] = a;
+      for (int t = threadIdx.x; t < W - c; t += blockDim.x) {
+        const double2 a = aug[c * W + c + t];
+        aug[c * W + c + t] = aug[piv * W + c + t];
+        aug[piv * W + c + t] = a;
       }
     __syncthreads();
     const double2 inv = crecip(aug[c * W + c]);
-    const int rows = nB - c - 1, cols = W - c - 1;
-    for (int t = threadIdx.x; t < rows * cols; t += blockDim.x) {
-      const int r = c + 1 + t / cols, cc = c + 1 + t % cols;
+    // Rows over waves, columns over lanes (row-major: coalesced).
+    for (int r = c + 1 + ty; r < nB; r += ny) {
       const double2 f = cmul(aug[r * W + c], inv);
-      cfms(aug[r * W + cc], f, aug[c * W + cc]);
+      for (int cc = c + 1 + tx; cc < W; cc += 64) {
+        double2& d = aug[r * W + cc];
+        cfms(d, f, aug[c * W + cc]);
+        if (cc == c + 1) atomicMax(&keys[(c + 1) & 1], key_of(cabs2(d), r));
+      }
     }
     __syncthreads();
   }
@@ -242,6 +240,8 @@ size_t stencil_work_elems(const StencilDev& S) {
 void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2, StencilDev* types, int ntypes,
                    double2* work, int* info) {
   if (ntypes > 8) throw Error(-7, "at most 8 set types");
+  for (int t = 0; t < ntypes; ++t)
+    if (types[t].nB > 4096) throw Error(-7, "stencil boundary set larger than 4096 points");
   const int T = 256;
   SolveJobs jobs{};
   std::vector<double2*> ggg(ntypes), mm(ntypes);
