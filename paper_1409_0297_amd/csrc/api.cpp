@@ -84,6 +84,66 @@ using Geom = std::tuple<int, int, int, int>;   // d, n, b, ordering
 // index arrays.  Plans depend only on the geometries, so they are built once
 // per process and device and shared by every factor with those geometries
 // (read-only on the device).
+// Device (and pinned host) blocks released by factors wait here for the next
+// factor that asks for the same size on the same device: a setup per solve
+// would otherwise pay hipMalloc / hipFree for every buffer, milliseconds for
+// the multi-GB front arena.  Exact-size reuse; at most kMemCacheBytes held;
+// the cache is emptied when an allocation fails (then retried) or through
+// mem_trim.  Blocks enter the cache only once the device is idle.
+std::mutex g_mem_mu;
+auto& g_mem_free = *new std::multimap<std::pair<int, size_t>, void*>();
+size_t g_mem_cached = 0;
+constexpr size_t kMemCacheBytes = (size_t)64 << 30;
+constexpr int kPinnedDev = -1;
+
+void mem_trim() {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  for (auto& kv : g_mem_free) {
+    if (kv.first.first == kPinnedDev) (void)hipHostFree(kv.second);
+    else (void)hipFree(kv.second);
+  }
+  g_mem_free.clear();
+  g_mem_cached = 0;
+}
+
+void* mem_get(size_t bytes, bool pinned) {
+  int dev = kPinnedDev;
+  if (!pinned) SPP_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_mem_free.find({dev, bytes});
+    if (it != g_mem_free.end()) {
+      void* p = it->second;
+      g_mem_free.erase(it);
+      g_mem_cached -= bytes;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = pinned ? hipHostMalloc(&p, bytes) : hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    mem_trim();
+    if (pinned) SPP_HIP(hipHostMalloc(&p, bytes));
+    else SPP_HIP(hipMalloc(&p, bytes));
+  }
+  return p;
+}
+
+// The caller has made sure no queued work still uses p.
+void mem_put(void* p, size_t bytes, int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (g_mem_cached + bytes <= kMemCacheBytes) {
+      g_mem_free.emplace(std::make_pair(dev, bytes), p);
+      g_mem_cached += bytes;
+      return;
+    }
+  }
+  if (dev == kPinnedDev) (void)hipHostFree(p);
+  else (void)hipFree(p);
+}
+
 struct PlanDevice {
   Plan plan;
   std::vector<int> front_inst;
@@ -241,7 +301,8 @@ struct spp_factor {
   std::vector<SppGroup> groups;
   int64_t Ntot = 0;
   spp_options opt{};
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;   // (block, bytes)
+  int device = 0;
   double* q = nullptr;               // every problem's q, concatenated
   double* sigma = nullptr;           // every problem's Green symbol / N, concatenated
   std::map<int, double2*> tw_by_n;
@@ -264,6 +325,7 @@ struct spp_factor {
   double *cs = nullptr, *rpart = nullptr, *resid = nullptr, *norms = nullptr;
   int* kvec = nullptr;
   double* h_resid = nullptr;   // pinned host copy of residual estimates
+  size_t h_resid_bytes = 0;
   spp_stats_t stats{};
   int tuned_nrhs = 0;          // right-hand-side count the last autotune covered
   spp_cnn* cnn = nullptr;      // learned FGMRES stage (not owned)
@@ -289,23 +351,27 @@ struct spp_factor {
   std::unique_ptr<KernelTimer> timer;
 
   template <typename T> T* dalloc(size_t count) {
-    void* p = nullptr;
     if (count == 0) count = 1;
-    SPP_HIP(hipMalloc(&p, count * sizeof(T)));
-    allocs.push_back(p);
+    const size_t bytes = (count * sizeof(T) + 255) / 256 * 256;
+    void* p = mem_get(bytes, false);
+    allocs.push_back({p, bytes});
     return static_cast<T*>(p);
   }
   void dfree(void* p) {
     if (!p) return;
-    auto it = std::find(allocs.begin(), allocs.end(), p);
-    if (it != allocs.end()) allocs.erase(it);
-    (void)hipFree(p);
+    auto it = std::find_if(allocs.begin(), allocs.end(), [&](const std::pair<void*, size_t>& a) { return a.first == p; });
+    if (it == allocs.end()) return;
+    const size_t bytes = it->second;
+    allocs.erase(it);
+    (void)hipDeviceSynchronize();   // (nothing queued may still use the block)
+    mem_put(p, bytes, device);
   }
   ~spp_factor() {
     drop_graph();
     if (gstream) (void)hipStreamDestroy(gstream);
-    for (void* p : allocs) (void)hipFree(p);
-    if (h_resid) (void)hipHostFree(h_resid);
+    (void)hipDeviceSynchronize();
+    for (const auto& a : allocs) mem_put(a.first, a.second, device);
+    if (h_resid) mem_put(h_resid, h_resid_bytes, kPinnedDev);
   }
 };
 
@@ -369,7 +435,7 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
                   (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec,
                   (void*)F->gsave, (void*)F->vfix, (void*)F->zfix, (void*)F->dj})
     F->dfree(p);
-  if (F->h_resid) { (void)hipHostFree(F->h_resid); F->h_resid = nullptr; }
+  if (F->h_resid) { mem_put(F->h_resid, F->h_resid_bytes, kPinnedDev); F->h_resid = nullptr; }
   const int64_t N = F->Ntot;
   const int cols = total_cols(F, r);
   F->tmp = F->dalloc<double2>((size_t)r * N);
@@ -401,7 +467,8 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->resid = F->dalloc<double>(cols);
   F->norms = F->dalloc<double>(cols);
   F->kvec = F->dalloc<int>(cols);
-  SPP_HIP(hipHostMalloc(reinterpret_cast<void**>(&F->h_resid), sizeof(double) * cols));
+  F->h_resid_bytes = sizeof(double) * cols;
+  F->h_resid = static_cast<double*>(mem_get(F->h_resid_bytes, true));
   F->cap_rhs = r;
   F->cap_iter = it;
 }
@@ -551,6 +618,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   }
   const double t0 = now_ms();
   auto F = std::make_unique<spp_factor>();
+  SPP_HIP(hipGetDevice(&F->device));
   F->opt = *op;
   F->csize = (op->prec == SPP_C128) ? sizeof(double2) : sizeof(float2);
   F->last_stream = st;
