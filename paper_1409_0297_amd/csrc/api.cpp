@@ -326,6 +326,7 @@ struct spp_factor {
   int* kvec = nullptr;
   double* h_resid = nullptr;   // pinned host copy of residual estimates
   size_t h_resid_bytes = 0;
+  hipEvent_t resid_event = nullptr;   // marks the residual estimates' copy
   spp_stats_t stats{};
   int tuned_nrhs = 0;          // right-hand-side count the last autotune covered
   spp_cnn* cnn = nullptr;      // learned FGMRES stage (not owned)
@@ -372,6 +373,7 @@ struct spp_factor {
     (void)hipDeviceSynchronize();
     for (const auto& a : allocs) mem_put(a.first, a.second, device);
     if (h_resid) mem_put(h_resid, h_resid_bytes, kPinnedDev);
+    if (resid_event) (void)hipEventDestroy(resid_event);
   }
 };
 
@@ -404,22 +406,24 @@ template <typename F> int guarded(F&& fn) {
 }
 
 // min over the Fourier grid of |4 pi^2 |k|^2 - s| / |s| (how close L - s is to singular).
+// min over wave numbers k in [-n/2, n/2)^d of |4 pi^2 |k|^2 - s|, relative to
+// |s|: the last coordinate is taken next to the square root of what the
+// others leave, so the scan is O(n^(d-1)).
 double shift_gap(int d, int n, double s) {
   const double c = 4.0 * M_PI * M_PI;
-  double best = INFINITY;
   const int h = n / 2;
+  double best = INFINITY;
+  auto last = [&](double partial) {   // partial = sum of the other squares
+    const double rest = s / c - partial;
+    const int k = rest > 0 ? (int)std::floor(std::sqrt(rest)) : 0;
+    for (int t = std::max(0, k - 1); t <= std::min(h, k + 2); ++t)
+      best = std::min(best, std::fabs(c * (partial + (double)t * t) - s));
+  };
   if (d == 2) {
-    for (int a = -h; a < h; ++a)
-      for (int b = -h; b < h; ++b) best = std::min(best, std::fabs(c * (double)(a * a + b * b) - s));
+    for (int a = -h; a < h; ++a) last((double)a * a);
   } else {
     for (int a = -h; a < h; ++a)
-      for (int b = -h; b < h; ++b) {
-        const double rest = s / c - (double)(a * a + b * b);
-        // nearest k3^2 to rest
-        int k3 = rest > 0 ? (int)std::floor(std::sqrt(rest)) : 0;
-        for (int t = std::max(0, k3 - 1); t <= std::min(h, k3 + 2); ++t)
-          best = std::min(best, std::fabs(c * (double)(a * a + b * b + t * t) - s));
-      }
+      for (int b = -h; b < h; ++b) last((double)(a * a + b * b));
   }
   return best / std::fabs(s);
 }
@@ -492,21 +496,32 @@ void apply_green(spp_factor* F, const double2* f, double2* gout, int nrhs, hipSt
 
 // persistent: cooperative launches for runs of small-front levels (not inside
 // a graph capture).
-void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st, bool persistent = true) {
-  persistent = persistent && (F->opt.flags & SPP_F_PERSISTENT);
+// The preconditioner in two parts: the head (Q r, and its cast to the front
+// precision) fills scratch vectors only, so it can run ahead of the decision
+// whether its result is needed; the tail (the substitution and the cast
+// back) writes z.
+void precond_head(spp_factor* F, const double2* r, int nrhs, hipStream_t st) {
   q_apply(st, F->mf, r, F->qr, nrhs);
+  if (F->opt.prec != SPP_C128) cast_vectors<float>(st, F->qr, F->xc, (int64_t)nrhs * F->Ntot, 0);
+}
+
+void precond_tail(spp_factor* F, double2* z, int nrhs, hipStream_t st, bool persistent) {
+  persistent = persistent && (F->opt.flags & SPP_F_PERSISTENT);
   const int nl = static_cast<int>(F->planp->levels.size());
   const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
     mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
                      F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
   } else {
-    const int64_t cnt = (int64_t)nrhs * F->Ntot;
-    cast_vectors<float>(st, F->qr, F->xc, cnt, 0);
     mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
                     F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
-    cast_vectors<float>(st, F->xc, z, cnt, 1);
+    cast_vectors<float>(st, F->xc, z, (int64_t)nrhs * F->Ntot, 1);
   }
+}
+
+void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStream_t st, bool persistent = true) {
+  precond_head(F, r, nrhs, st);
+  precond_tail(F, z, nrhs, st, persistent);
 }
 
 void validate_problem(const spp_problem* pb) {
@@ -619,6 +634,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   const double t0 = now_ms();
   auto F = std::make_unique<spp_factor>();
   SPP_HIP(hipGetDevice(&F->device));
+  SPP_HIP(hipEventCreateWithFlags(&F->resid_event, hipEventDisableTiming));
   F->opt = *op;
   F->csize = (op->prec == SPP_C128) ? sizeof(double2) : sizeof(float2);
   F->last_stream = st;
@@ -848,7 +864,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     if (beta[c] == 0) { conv[c] = true; ++done; }
   // One Arnoldi step with z_j already in Z: w = A z_j, CGS2, Givens; returns
   // the residual estimates in F->h_resid.
-  auto arnoldi_step = [&](int j) {
+  // head_next: after the step, run the next iteration's preconditioner head
+  // on v_{j+1} while the host waits for the residual estimates.
+  bool head_ready = false;
+  auto arnoldi_step = [&](int j, bool head_next = false) {
     double2* zj = F->Z + (int64_t)j * vstride;
     // a8: w = (I + G q) z_j
     apply_operator(F, zj, F->wk, nrhs, st);
@@ -867,7 +886,14 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     // a10: Givens update of the least-squares problem (all columns at once).
     kr_givens(st, F->H, ld, hrhs, F->cs, F->sn, F->gv, j, cols, ld, F->resid, nullptr);
     SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
-    SPP_HIP(hipStreamSynchronize(st));
+    if (head_next) {
+      SPP_HIP(hipEventRecord(F->resid_event, st));
+      precond_head(F, F->V + (int64_t)(j + 1) * vstride, nrhs, st);
+      head_ready = true;
+      SPP_HIP(hipEventSynchronize(F->resid_event));
+    } else {
+      SPP_HIP(hipStreamSynchronize(st));
+    }
   };
   // The same step for graph replays: every launch reads j from F->dj, the
   // vectors go through fixed buffers, and the residual estimates are copied
@@ -952,10 +978,16 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
       }
     }
     if (!have) {
-      // a9: z_j = M v_j
-      if (precond) apply_precond(F, vj, zj, nrhs, st);
-      else SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
-      arnoldi_step(j);
+      // a9: z_j = M v_j (its head may already have run behind the previous
+      // step's residual check)
+      if (precond) {
+        if (!head_ready) precond_head(F, vj, nrhs, st);
+        precond_tail(F, zj, nrhs, st, true);
+      } else {
+        SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
+      }
+      head_ready = false;
+      arnoldi_step(j, precond && !learned && j + 1 < maxit);
     }
     for (int c = 0; c < cols; ++c) prev[c] = F->h_resid[c];
     for (int c = 0; c < cols; ++c) {
