@@ -1769,7 +1769,7 @@ int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64) {
   // FP64, where levels with very many small fronts keep the LU in place and
   // run one workgroup per front (its vectors, (F + p) x 4 complex values,
   // within 64 KB of LDS).
-  if (!c64 && nfronts >= 512 && maxP <= 512 && maxF + maxP <= 1024) return kFormLU;
+  if (nfronts >= 512 && maxP <= 512 && maxF + maxP <= 1024) return kFormLU;
   // The side products Lt = L21 Linv and Ut = Uinv U12 halve the launches per
   // level and direction; they pay where the level's products are short
   // (few fronts: launch latency dominates), not on the wide leaf levels,
