@@ -89,8 +89,10 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
     } else {
       v = csub(v, T.Tt[(int64_t)(j - T.nS) * T.nS + i]);
     }
-    C& dst = A[(int64_t)cp * f.F + rp];
-    dst = cadd(dst, cconvert<C>(v));
+    // Every row of P belongs to one set instance and every (row, column)
+    // pair of a block is distinct, so each front entry is written by at most
+    // one thread: a plain store (no read of the zeroed arena).
+    A[(int64_t)cp * f.F + rp] = cconvert<C>(v);
   }
 }
 
