@@ -88,6 +88,11 @@ typedef struct {
                                      (not inside graph replays)               */
 #define SPP_F_AUTOTUNE 32         /* run spp_autotune before the first solve of
                                      each right-hand-side count               */
+#define SPP_F_NO_SIDE 64          /* levels of few fronts keep L21 and U12 (four
+                                     substitution products per level and solve)
+                                     instead of L21 L11^-1 and U11^-1 U12 (one
+                                     product per level and direction): less
+                                     setup work, more launches per solve      */
 #define SPP_F_GRAPHS 8            /* capture one FGMRES iteration in a HIP graph
                                      (once per factor and nrhs) and replay it
                                      with the step index in device memory;

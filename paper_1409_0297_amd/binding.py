@@ -22,6 +22,7 @@ SPP_F_PARTIAL_PIVOTING = 4
 SPP_F_GRAPHS = 8
 SPP_F_PERSISTENT = 16
 SPP_F_AUTOTUNE = 32
+SPP_F_NO_SIDE = 64
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
 KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
 
@@ -229,7 +230,7 @@ class Solver:
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
                  timing: bool = False, partial_pivoting: bool = False, graphs: bool = False,
-                 persistent: bool = False, autotune: bool = False):
+                 persistent: bool = False, autotune: bool = False, side_products: bool = True):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -247,7 +248,8 @@ class Solver:
                          | (SPP_F_PARTIAL_PIVOTING if partial_pivoting else 0)
                          | (SPP_F_GRAPHS if graphs else 0)
                          | (SPP_F_PERSISTENT if persistent else 0)
-                         | (SPP_F_AUTOTUNE if autotune else 0))
+                         | (SPP_F_AUTOTUNE if autotune else 0)
+                         | (0 if side_products else SPP_F_NO_SIDE))
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:

@@ -776,8 +776,11 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     F->level_maxP.push_back(L.maxP);
   }
   F->level_begin.push_back(static_cast<int>(P.fronts.size()));
-  for (const Level& L : P.levels)
-    F->level_form.push_back(mf_level_solve_form(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS));
+  for (const Level& L : P.levels) {
+    int form = mf_level_solve_form(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS);
+    if (form == kFormSide && (op->flags & SPP_F_NO_SIDE)) form = kFormInverse;
+    F->level_form.push_back(form);
+  }
 
   F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
   void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);

@@ -228,6 +228,27 @@ def test_non_finite_coefficients_are_rejected():
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_side_products_and_four_product_substitution_agree(prec):
+    """Levels of few fronts solved with L21 L11^-1, U11^-1 U12 (one product per
+    direction) or with L21, U12 kept (four products): the same preconditioner,
+    so the same solution and iteration count within one."""
+    from paper_1409_0297_amd import Solver
+    W = workloads.helmholtz_workload("mid", 5, 128, 2, 16.0, 16, 0.05, 8)
+    f = W.rhs[0]
+    res = []
+    for side in (True, False):
+        S = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, tol=1e-11, max_iter=100,
+                   prec=prec, side_products=side)
+        u, iters, relres, code = S.solve(f)
+        res.append((cpu(u).reshape(f.shape), iters[0], relres[0], code))
+        S.close()
+    (u0, i0, r0, c0), (u1, i1, r1, c1) = res
+    assert c0 == 0 and c1 == 0 and abs(i0 - i1) <= 1, (i0, i1)
+    e = rel(u0, u1)
+    assert e <= 1e-9, e
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_partial_and_block_local_pivoting_agree(prec):
     """Both pivoting rules factor the same P: same solution, iterations within one."""
     from paper_1409_0297_amd import Solver
