@@ -131,9 +131,143 @@ struct SolveJobs {
   SolveJob job[8];
 };
 
+// Register-resident elimination for small systems (nB <= 64, nB + nS <= 320,
+// 1024 threads): wave w holds rows w, w + 16, ... and lane l columns l,
+// l + 64, ... of the augmented [A^T | Bm^T] (1024 threads measured faster
+// than 512 with twice the rows each); rows stay in place (the pivot
+// order is recorded) and each step exchanges only the pivot row and the
+// pivot column through LDS.
+constexpr int kRsWaves = 16, kRsRows = 4, kRsCols = 5;   // 1024 threads, nB <= 64, W <= 320
+
+__device__ void right_solve_regs(const SolveJob& J) {
+  const int nB = J.nB, nS = J.nS, W = nB + nS;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // ty < kRsWaves
+  __shared__ double2 prow[kRsCols * 64];
+  __shared__ double2 mcol[64];
+  __shared__ unsigned long long keys[2];
+  __shared__ int order[64], rstep[64];
+  auto key_of = [](double v, int row) {
+    return ((unsigned long long)__double_as_longlong(v) & ~0xFFFULL) | (unsigned long long)(4095 - row);
+  };
+  double2 v[kRsRows][kRsCols];
+#pragma unroll
+  for (int a = 0; a < kRsRows; ++a)
+#pragma unroll
+    for (int b = 0; b < kRsCols; ++b) {
+      const int r = ty + kRsWaves * a, c = tx + 64 * b;
+      double2 x = cmake<double2>(0, 0);
+      if (r < nB && c < W) x = (c < nB) ? J.A[c * J.lda + r] : J.Bm[(c - nB) * J.ldb + r];
+      v[a][b] = x;
+    }
+  if (threadIdx.x < 2) keys[threadIdx.x] = 0;
+  __syncthreads();
+  if (tx == 0)
+#pragma unroll
+    for (int a = 0; a < kRsRows; ++a)
+      if (ty + kRsWaves * a < nB) atomicMax(&keys[0], key_of(cabs2(v[a][0]), ty + kRsWaves * a));
+  __syncthreads();
+  unsigned long long done = 0;
+  for (int k = 0; k < nB; ++k) {
+    const unsigned long long key = keys[k & 1];
+    const int piv = 4095 - (int)(key & 0xFFF);
+    if (threadIdx.x == 0) {
+      if (!(__longlong_as_double((long long)(key & ~0xFFFULL)) > 0.0)) *J.info = 1;
+      keys[(k + 1) & 1] = 0;
+      order[k] = piv;
+      rstep[piv] = k;
+    }
+    // Publish the pivot row and column k.
+    if (ty == (piv % kRsWaves))
+#pragma unroll
+      for (int a = 0; a < kRsRows; ++a)
+        if (a == (piv / kRsWaves))
+#pragma unroll
+          for (int b = 0; b < kRsCols; ++b) prow[tx + 64 * b] = v[a][b];
+    if (tx == (k & 63))
+#pragma unroll
+      for (int b = 0; b < kRsCols; ++b)
+        if (b == (k >> 6))
+#pragma unroll
+          for (int a = 0; a < kRsRows; ++a) mcol[ty + kRsWaves * a] = v[a][b];
+    __syncthreads();
+    done |= 1ULL << piv;
+    const double2 pinv = crecip(prow[k]);
+#pragma unroll
+    for (int a = 0; a < kRsRows; ++a) {
+      const int r = ty + kRsWaves * a;
+      if (r >= nB || ((done >> r) & 1ULL)) continue;
+      const double2 f = cmul(mcol[r], pinv);
+#pragma unroll
+      for (int b = 0; b < kRsCols; ++b) {
+        const int c = tx + 64 * b;
+        if (c > k && c < W) {
+          cfms(v[a][b], f, prow[c]);
+          if (c == k + 1) atomicMax(&keys[(k + 1) & 1], key_of(cabs2(v[a][b]), r));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Back substitution on the right-hand-side columns, last pivot first:
+  // x_k = rhs(order[k]) / U(k, k), then the rows of earlier pivots lose
+  // U(m, k) x_k.
+  for (int k = nB - 1; k >= 0; --k) {
+    const int piv = order[k];
+    if (tx == (k & 63))
+#pragma unroll
+      for (int b = 0; b < kRsCols; ++b)
+        if (b == (k >> 6))
+#pragma unroll
+          for (int a = 0; a < kRsRows; ++a) mcol[ty + kRsWaves * a] = v[a][b];
+    __syncthreads();
+    const double2 uinv = crecip(mcol[piv]);
+    if (ty == (piv % kRsWaves))
+#pragma unroll
+      for (int a = 0; a < kRsRows; ++a)
+        if (a == (piv / kRsWaves))
+#pragma unroll
+          for (int b = 0; b < kRsCols; ++b) {
+            const int c = tx + 64 * b;
+            if (c >= nB && c < W) {
+              v[a][b] = cmul(v[a][b], uinv);
+              prow[c] = v[a][b];
+            }
+          }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < kRsRows; ++a) {
+      const int r = ty + kRsWaves * a;
+      if (r >= nB || rstep[r] >= k) continue;
+      const double2 f = mcol[r];
+#pragma unroll
+      for (int b = 0; b < kRsCols; ++b) {
+        const int c = tx + 64 * b;
+        if (c >= nB && c < W) cfms(v[a][b], f, prow[c]);
+      }
+    }
+    __syncthreads();
+  }
+  // X^T = the solved right-hand sides in pivot order: X[i][m] = x_m(nB + i).
+#pragma unroll
+  for (int a = 0; a < kRsRows; ++a) {
+    const int r = ty + kRsWaves * a;
+    if (r >= nB) continue;
+    const int m = rstep[r];
+#pragma unroll
+    for (int b = 0; b < kRsCols; ++b) {
+      const int c = tx + 64 * b;
+      if (c >= nB && c < W) J.X[(c - nB) * J.ldx + m] = v[a][b];
+    }
+  }
+}
+
 // One workgroup per set type (blockIdx.x): the types' systems are independent.
-__global__ void right_solve_kernel(SolveJobs jobs) {
+__global__ void __launch_bounds__(64 * kRsWaves) right_solve_kernel(SolveJobs jobs) {
   const SolveJob& J = jobs.job[blockIdx.x];
+  if (J.nB <= kRsWaves * kRsRows && J.nB + J.nS <= 64 * kRsCols) {   // (launched with 64 kRsWaves threads)
+    right_solve_regs(J);
+    return;
+  }
   const int nB = J.nB, nS = J.nS, lda = J.lda, ldb = J.ldb, ldx = J.ldx;
   const double2* __restrict__ A = J.A;
   const double2* __restrict__ Bm = J.Bm;
@@ -265,7 +399,7 @@ void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2
     // T_S M(beta, :) = M(S, :)
     jobs.job[t] = SolveJob{nB, nS, M + (size_t)nS * nB, nB, M, nB, aug, S.T, nB, info + t};
   }
-  right_solve_kernel<<<ntypes, 1024, 0, st>>>(jobs);
+  right_solve_kernel<<<ntypes, 64 * kRsWaves, 0, st>>>(jobs);
   SPP_LAUNCH_CHECK();
   for (int t = 0; t < ntypes; ++t) {
     StencilDev& S = types[t];
