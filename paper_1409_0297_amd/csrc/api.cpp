@@ -150,7 +150,8 @@ struct PlanDevice {
   int device = 0;
   FrontDev* fronts = nullptr;
   AsmBlockDev* blocks = nullptr;
-  int *pos = nullptr, *idx = nullptr, *map = nullptr;
+  int *pos = nullptr, *idx = nullptr, *map = nullptr, *gptr = nullptr;
+  int64_t* gsrc = nullptr;
   std::vector<int*> type_off;      // per problem, per set type: device offsets
   std::vector<double> level_ent;   // 3 per level, see mf_solve
   std::vector<std::vector<int>> level_F, level_p;
@@ -259,6 +260,35 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
     if (bytes) SPP_HIP(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
     return p;
   };
+  {
+    // Children's boundary rows by parent position (counting sort, children in
+    // order, so a position's sum keeps the order of the plain gather).
+    std::vector<int> gptr;
+    std::vector<int64_t> gsrc;
+    for (size_t fi = 0; fi < P.fronts.size(); ++fi) {
+      const Front& f = P.fronts[fi];
+      fd[fi].gptr = static_cast<int>(gptr.size());
+      std::vector<int> cnt(f.F + 1, 0);
+      for (int c : f.children) {
+        const Front& ch = P.fronts[c];
+        for (int jj = 0; jj < ch.F - ch.p; ++jj)
+          if (P.map[ch.map + jj] >= 0) ++cnt[P.map[ch.map + jj] + 1];
+      }
+      for (int i = 0; i < f.F; ++i) cnt[i + 1] += cnt[i];
+      const int64_t base = static_cast<int64_t>(gsrc.size());
+      for (int i = 0; i <= f.F; ++i) gptr.push_back(static_cast<int>(base + cnt[i]));
+      gsrc.resize(gsrc.size() + cnt[f.F]);
+      std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+      for (int c : f.children) {
+        const Front& ch = P.fronts[c];
+        for (int jj = 0; jj < ch.F - ch.p; ++jj)
+          if (P.map[ch.map + jj] >= 0) gsrc[base + fill[P.map[ch.map + jj]]++] = ch.voff + ch.p + jj;
+      }
+    }
+    if (gsrc.size() > (size_t)INT32_MAX) throw Error(SPP_EINVAL, "plan too large");
+    pd->gptr = static_cast<int*>(upload(gptr.data(), gptr.size() * sizeof(int)));
+    pd->gsrc = static_cast<int64_t*>(upload(gsrc.data(), gsrc.size() * sizeof(int64_t)));
+  }
   pd->fronts = static_cast<FrontDev*>(upload(fd.data(), fd.size() * sizeof(FrontDev)));
   pd->blocks = static_cast<AsmBlockDev*>(upload(bd.data(), bd.size() * sizeof(AsmBlockDev)));
   pd->pos = static_cast<int*>(upload(P.pos.data(), P.pos.size() * sizeof(int)));
@@ -602,10 +632,10 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
         if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
         const float t = tune_time(st, 3, [&] {
           if (F->opt.prec == SPP_C128)
-            mf_gemv<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
+            mf_gemv<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, F->qr, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
                             0.0, F->gpart, F->gpart_cap, c);
           else
-            mf_gemv<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
+            mf_gemv<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
                            0.0, F->gpart, F->gpart_cap, c);
         }, flush, flush_bytes);
         if (t < bt) { bt = t; best = c; }
@@ -753,6 +783,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   mf.pos = F->pd->pos;
   mf.idx = F->pd->idx;
   mf.map = F->pd->map;
+  mf.gptr = F->pd->gptr;
+  mf.gsrc = F->pd->gsrc;
   mf.perm = F->dalloc<int>(F->pd->perm_total);
   mf.ipiv = F->dalloc<int>(F->pd->perm_total);
   mf.prow = F->dalloc<int>(F->pd->perm_total);

@@ -78,6 +78,8 @@ struct FrontDev {
   int parent;          // parent front (-1 at a root)
   int nchild;
   int child[8];
+  int gptr;            // F + 1 offsets into MfDev::gsrc: the children's boundary
+                       // rows that land on each position (in child order)
 };
 
 struct AsmBlockDev { int front, type, anchor, rowpos, colpos; };
@@ -108,6 +110,8 @@ struct MfDev {
   const int* pos;
   const int* idx;
   const int* map;
+  const int* gptr;     // per front, F + 1 offsets (see FrontDev::gptr)
+  const int64_t* gsrc; // vector-arena position of each child boundary row
   int* perm;           // final row permutation of each front's pivot block
   int* ipiv;           // LAPACK-style interchange record written by the panel
   int* prow;           // block-local pivoting: row order of each 32-row block (front rows)
@@ -199,9 +203,10 @@ std::string fft_tune_key(int n, int64_t outer, int64_t inner, int batch);
 
 // One substitution product (gemv_kernel mode) of a level of fronts with a
 // given split-K chunk count (0: tuned or heuristic); mf.hip.
+// xin: the forward input (read by mode 4, which gathers its own vector).
 template <typename R>
-void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena, void* W, void* Z, void* xout, int nrhs, int f0, int nf,
-             int rows, int cols, int mode, double ent, void* partial, int64_t partial_cap, int nchunks);
+void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena, void* W, void* Z, void* xout, const void* xin, int nrhs,
+             int f0, int nf, int rows, int cols, int mode, double ent, void* partial, int64_t partial_cap, int nchunks);
 int gemv_chunks_default(int rows, int cols, int nf, int nrhs, int64_t partial_cap);
 std::string gemv_tune_key(int rows, int cols, int nf, int mode, int nrhs, int csize);
 

@@ -19,6 +19,7 @@
 // vectors pulled by the parent) and back substitution root -> leaves.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include <hip/hip_cooperative_groups.h>
 
@@ -395,30 +396,11 @@ __global__ void __launch_bounds__(64) laswp_kernel(MfDev mf, cplx_t<R>* __restri
 // L21 = A21 Uinv_kk and U12 = Linv_kk P A12 (gemm_kernel modes 4 and 3).
 constexpr int kDB = 32;
 
-// Pivot search key: for v >= 0 the IEEE bits order like integers; the low 6
-// bits carry 63 - row, so the largest key is the largest modulus, ties to
-// the lowest row.
-template <typename R> __device__ inline unsigned long long piv_key(R v, int row);
-template <> __device__ inline unsigned long long piv_key<double>(double v, int row) {
-  return ((unsigned long long)__double_as_longlong(v) & ~0x3FULL) | (unsigned long long)(63 - row);
-}
-template <> __device__ inline unsigned long long piv_key<float>(float v, int row) {
-  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(63 - row);
-}
-template <typename R> __device__ inline R piv_key_value(unsigned long long k);
-template <> __device__ inline double piv_key_value<double>(unsigned long long k) {
-  return __longlong_as_double((long long)(k & ~0x3FULL));
-}
-template <> __device__ inline float piv_key_value<float>(unsigned long long k) {
-  return __uint_as_float((unsigned)(k >> 32));
-}
-
 template <typename R>
 struct DiagLds {
-  cplx_t<R> D[kDB][kDB + 1];    // working rows; their U part ends here; later the inverses
-  cplx_t<R> Lm[kDB][kDB + 1];   // multipliers of each physical row; later products
+  cplx_t<R> D[kDB][kDB + 1];    // the block to factor; later the inverses
+  cplx_t<R> Lm[kDB][kDB + 1];   // the previous step's L part; later products
   cplx_t<R> X[kDB][kDB + 1];    // the LU in pivot order
-  unsigned long long keys[kDB + 1];
   int rsel[kDB];
 };
 
@@ -430,12 +412,212 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane exchanges of one wave: value of lane src (any lane), of a uniform lane,
+// rotation by N lanes inside each row of 16 lanes (DPP), and exchange with
+// lane ^ 16 inside each half of 32 lanes (swizzle, bitmask mode).
+__device__ inline float lane_get(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
+}
+__device__ inline double lane_get(double x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float lane_read(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+__device__ inline double lane_read(double x, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+  return __hiloint2double(hi, lo);
+}
+template <int N> __device__ inline float row_ror(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x120 + N, 0xF, 0xF, false));
+}
+template <int N> __device__ inline double row_ror(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x120 + N, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float xor16(float x) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
+}
+__device__ inline double xor16(double x) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+// Largest value over each half of the wave (every lane of the half gets it).
+template <typename R> __device__ inline R half_wave_max(R v) {
+  v = fmax(v, row_ror<1>(v));
+  v = fmax(v, row_ror<2>(v));
+  v = fmax(v, row_ror<4>(v));
+  v = fmax(v, row_ror<8>(v));
+  return fmax(v, xor16(v));
+}
+// c ? x : y on the components (a select of whole vector structs goes through
+// their addresses and keeps register arrays in memory).
+template <typename C> __device__ inline C csel(bool c, C x, C y) {
+  return cmake<C>(c ? x.x : y.x, c ? x.y : y.y);
+}
+template <typename C> __device__ inline C lane_get(C x, int src) {
+  return cmake<C>(lane_get(x.x, src), lane_get(x.y, src));
+}
+template <typename C> __device__ inline C lane_read(C x, int src) {
+  return cmake<C>(lane_read(x.x, src), lane_read(x.y, src));
+}
+
+// Slot K (column 2 K + h) of step J of wave_lu32: a -= l * (pivot row), or
+// the multiplier l itself in column J.
+template <typename R, int J, int K>
+__device__ __forceinline__ void wave_lu_slot(cplx_t<R> (&a)[kDB / 2], cplx_t<R> l, int src, int h, bool upd) {
+  using C = cplx_t<R>;
+  constexpr int js = J >> 1, jh = J & 1;
+  if constexpr (K >= js) {
+    const C pr = lane_get(a[K], src);                // pivot row at this lane's column
+    C nv = a[K];
+    cfms(nv, l, pr);
+    if constexpr (K > js) a[K] = csel(upd, nv, a[K]);
+    else a[K] = csel(upd && h > jh, nv, csel(upd && h == jh, l, a[K]));
+  }
+}
+template <typename R, int J, int... K>
+__device__ __forceinline__ void wave_lu_update(std::integer_sequence<int, K...>, cplx_t<R> (&a)[kDB / 2],
+                                               cplx_t<R> l, int src, int h, bool upd) {
+  (wave_lu_slot<R, J, K>(a, l, src, h, upd), ...);
+}
+
+// One elimination step (column J) of wave_lu32.
+template <typename R, int J>
+__device__ __forceinline__ void wave_lu_step(cplx_t<R> (&a)[kDB / 2], int lane, int r, int h, int kb, bool& done,
+                                             bool& bad, int& kr) {
+  using C = cplx_t<R>;
+  constexpr int js = J >> 1, jh = J & 1;
+  const C other = lane_get(a[js], lane ^ 32);
+  const C dj = csel(h == jh, a[js], other);          // d_rJ of this lane's row
+  const R v2 = done ? R(-1) : cabs2(dj);
+  const R m = half_wave_max(v2);
+  const unsigned hit = (unsigned)__ballot(!done && v2 == m);
+  const unsigned live = (unsigned)__ballot(!done);
+  // With every remaining entry NaN nothing matches: take the first remaining row.
+  const int rp = __builtin_ctz(hit ? hit : live);
+  if (J < kb && (!hit || !(m > R(0)) || !isfinite(m) || __ballot(!done && v2 != v2))) bad = true;
+  const C pv = lane_read(dj, rp);
+  const R p2 = cabs2(pv);
+  const R inv = p2 > R(0) ? R(1) / p2 : R(0);
+  const C l = cmake<C>((dj.x * pv.x + dj.y * pv.y) * inv, (dj.y * pv.x - dj.x * pv.y) * inv);
+  const bool upd = !done && r != rp;
+  if (r == rp) {
+    done = true;
+    kr = J;
+  }
+  wave_lu_update<R, J>(std::make_integer_sequence<int, kDB / 2>{}, a, l, rp + 32 * h, h, upd);
+}
+
+template <typename R, int... J>
+__device__ __forceinline__ void wave_lu_steps(std::integer_sequence<int, J...>, cplx_t<R> (&a)[kDB / 2], int lane,
+                                              int r, int h, int kb, bool& done, bool& bad, int& kr) {
+  (wave_lu_step<R, J>(a, lane, r, h, kb, done, bad, kr), ...);
+}
+
+// LU with row pivoting of the 32 x 32 block D by one wave, in registers.
+// Lane (r, h) = (lane & 31, lane >> 5) holds row r at the columns 2 k + h.
+// Step j takes as pivot the remaining row of largest |d_rj|^2 (ties to the
+// lowest row) and eliminates column j from the other remaining rows; each row
+// keeps its multipliers in place, so the row chosen at step k ends as row k
+// of the LU in pivot order: L left of column k, U from column k on.  Writes
+// that LU to X and the chosen rows to rsel; returns true if a pivot among the
+// first kb was zero or not finite.
+template <typename R>
+__device__ __forceinline__ bool wave_lu32(cplx_t<R> (*D)[kDB + 1], cplx_t<R> (*X)[kDB + 1], int* rsel, int kb) {
+  using C = cplx_t<R>;
+  const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+  C a[kDB / 2];
+#pragma unroll
+  for (int k = 0; k < kDB / 2; ++k) a[k] = D[r][2 * k + h];
+  bool done = false, bad = false;
+  int kr = 0;
+  wave_lu_steps<R>(std::make_integer_sequence<int, kDB>{}, a, lane, r, h, kb, done, bad, kr);
+#pragma unroll
+  for (int k = 0; k < kDB / 2; ++k) X[kr][2 * k + h] = a[k];
+  if (h == 0) rsel[kr] = r;
+  return bad;
+}
+
+// Inverses of the triangles of a 32 x 32 LU (X, pivot order) by column
+// sweeps over the identity, two waves per triangle.  Lane (i, g) holds row i
+// of the inverse at the columns 4 t + g (t < 8); the row needed at sweep step
+// j is row j of the lane's own group (lane j or j + 32 of the wave).
+//   L^{-1}: for j = 0 .. 30, rows i > j: z_i -= l_ij z_j  (z_j is final by then);
+//   U^{-1}: for j = 31 .. 1, rows i < j: z_i -= (u_ij / u_jj) z_j, and every
+//           row is divided by its own u_ii at the end.
+// Only the columns where row j can be nonzero are swept (c <= j for L^{-1},
+// c >= j for U^{-1}).
+template <typename R, bool LOWER, int J, int T>
+__device__ __forceinline__ void tri_inv_slot(cplx_t<R> (&z)[kDB / 4], cplx_t<R> m, int src, bool upd) {
+  if constexpr (LOWER ? T <= J / 4 : T >= J / 4) {
+    cplx_t<R> nv = z[T];
+    cfms(nv, m, lane_get(z[T], src));
+    z[T] = csel(upd, nv, z[T]);
+  }
+}
+template <typename R, int J, int... T>
+__device__ __forceinline__ void lower_inv_step(std::integer_sequence<int, T...>, cplx_t<R> (&z)[kDB / 4],
+                                               cplx_t<R> (*X)[kDB + 1], int i, int src0) {
+  const cplx_t<R> l = X[i][J];
+  (tri_inv_slot<R, true, J, T>(z, l, src0 + J, i > J), ...);
+}
+template <typename R, int J, int... T>
+__device__ __forceinline__ void upper_inv_step(std::integer_sequence<int, T...>, cplx_t<R> (&z)[kDB / 4],
+                                               cplx_t<R> (*X)[kDB + 1], int i, int src0) {
+  using C = cplx_t<R>;
+  const C d = X[J][J];
+  const R m2 = cabs2(d);
+  const R inv = m2 > R(0) ? R(1) / m2 : R(0);
+  const C u = cmul(X[i][J], cmake<C>(d.x * inv, -d.y * inv));
+  (tri_inv_slot<R, false, J, T>(z, u, src0 + J, i < J), ...);
+}
+template <typename R, int... Q>
+__device__ __forceinline__ void tri_inv_sweeps(std::integer_sequence<int, Q...>, cplx_t<R> (&z)[kDB / 4],
+                                               cplx_t<R> (*X)[kDB + 1], int i, int src0, bool lower) {
+  constexpr auto slots = std::make_integer_sequence<int, kDB / 4>{};
+  if (lower) (lower_inv_step<R, Q>(slots, z, X, i, src0), ...);
+  else (upper_inv_step<R, kDB - 1 - Q>(slots, z, X, i, src0), ...);
+}
+
+// Workgroup part: waves 0-1 invert L, waves 2-3 U; column-major results.
+template <typename R>
+__device__ __forceinline__ void tri_inv32(cplx_t<R> (*X)[kDB + 1], cplx_t<R>* __restrict__ Li,
+                                          cplx_t<R>* __restrict__ Ui, int kb) {
+  using C = cplx_t<R>;
+  const int w = threadIdx.x >> 6, gh = (threadIdx.x >> 5) & 1, i = threadIdx.x & 31;
+  const bool lower = w < 2;
+  const int g = 2 * (w & 1) + gh;
+  C z[kDB / 4];
+#pragma unroll
+  for (int t = 0; t < kDB / 4; ++t) z[t] = cmake<C>(4 * t + g == i ? 1 : 0, 0);
+  tri_inv_sweeps<R>(std::make_integer_sequence<int, kDB - 1>{}, z, X, i, 32 * gh, lower);
+  C* out = lower ? Li : Ui;
+  C s = cmake<C>(1, 0);
+  if (!lower) {
+    const C d = X[i][i];
+    const R m2 = cabs2(d);
+    const R inv = m2 > R(0) ? R(1) / m2 : R(0);
+    s = cmake<C>(d.x * inv, -d.y * inv);
+  }
+#pragma unroll
+  for (int t = 0; t < kDB / 4; ++t) {
+    const int c = 4 * t + g;
+    if (i < kb && c < kb) out[c * kDB + i] = cmul(z[t], s);
+  }
+}
+
 // The diagonal-block LU of block [k0, k0 + kb) of front fi by one workgroup
 // of 256 threads.  With kprev >= 0 the block first takes the trailing update
 // of the previous step (full block at kprev): A_kk -= L(k, prev) U(prev, k),
 // read from the L21 and U12 that step wrote.
 template <typename R>
-__device__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ dinv, int fi,
+__device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ dinv, int fi,
                               int k0, int nb, int kprev, DiagLds<R>& S) {
   using C = cplx_t<R>;
   const FrontDev& f = mf.fronts[fi];
@@ -447,7 +629,6 @@ __device__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __restrict__ arena, cp
   auto& D = S.D;
   auto& Lm = S.Lm;
   auto& X = S.X;
-  auto& keys = S.keys;
   auto& rsel = S.rsel;
   const int tid = threadIdx.x;
   if (kprev >= 0) {
@@ -472,140 +653,21 @@ __device__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __restrict__ arena, cp
     }
     D[i][c] = v;
   }
-  if (kprev >= 0) __syncthreads();
-  for (int t = tid; t < kDB * kDB; t += 256) {
-    const int c = t / kDB, i = t - c * kDB;
-    Lm[i][c] = cmake<C>(0, 0);
-  }
-  if (tid <= kDB) keys[tid] = 0;
   __syncthreads();
-  if (tid < kDB) atomicMax(&keys[0], piv_key<R>(cabs2(D[tid][0]), tid));
+  if (tid < 64 && wave_lu32<R>(D, X, rsel, kb) && tid == 0) atomicCAS(mf.info, 0, fi + 1);
   __syncthreads();
-  // One barrier per step: the pivot search of column j + 1 is fused into the
-  // update of step j (the thread updating that column posts its row's key).
-  const int ri = tid >> 3, cg = tid & 7;
-  unsigned done = 0;
-  for (int j = 0; j < kDB; ++j) {
-    const unsigned long long key = keys[j];
-    const int r = 63 - (int)(key & 63);
-    if (tid == 0) {
-      rsel[j] = r;
-      const R best = piv_key_value<R>(key);
-      if (j < kb && !(best > R(0) && isfinite(best))) atomicCAS(mf.info, 0, fi + 1);
-    }
-    done |= 1u << r;
-    if (!((done >> ri) & 1u)) {
-      // All LDS reads of the step are issued together (fixed trip count).
-      const C pv = D[r][j], dj = D[ri][j];
-      C dr[4], rr[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = j + 1 + cg + 8 * u;
-        if (c < kDB) { dr[u] = D[ri][c]; rr[u] = D[r][c]; }
-      }
-      const R m2 = cabs2(pv);
-      const R inv = m2 > R(0) ? R(1) / m2 : R(0);
-      const C l = cmake<C>((dj.x * pv.x + dj.y * pv.y) * inv, (dj.y * pv.x - dj.x * pv.y) * inv);
-      if (cg == 0) Lm[ri][j] = l;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = j + 1 + cg + 8 * u;
-        if (c < kDB) {
-          cfms(dr[u], l, rr[u]);
-          D[ri][c] = dr[u];
-          if (u == 0 && cg == 0) atomicMax(&keys[j + 1], piv_key<R>(cabs2(dr[0]), ri));
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int t = tid; t < kDB * kDB; t += 256) {
-    const int c = t / kDB, k = t - c * kDB;
-    const int pr = rsel[k];
-    X[k][c] = (c >= k) ? D[pr][c] : Lm[pr][c];
-  }
   // Block-local pivoting keeps every interchange inside the block, so the
   // row order is also the block's part of the front's final permutation.
   if (tid < kb) {
     mf.prow[f.perm + k0 + tid] = k0 + rsel[tid];
     mf.perm[f.perm + k0 + tid] = k0 + rsel[tid];
   }
-  __syncthreads();
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
     if (i < kb && c < kb) A[(int64_t)c * F + i] = X[i][c];
-    D[i][c] = cmake<C>(i == c ? 1 : 0, 0);
-  }
-  __syncthreads();
-  // Inverses into D (strictly lower: Linv with unit diagonal implied; upper
-  // with the diagonal: Uinv); the doubling loops are kept rolled so that the
-  // block fits beside the MFMA tiles of the launch it shares.  First the four 8 x 8 diagonal blocks of each
-  // triangle by column sweeps (one wave per block, no workgroup barrier),
-  // then two doubling stages:
-  //   [A 0; C B]^{-1} has lower-left block -B^{-1} (C A^{-1}),
-  //   [A C; 0 B]^{-1} has upper-right block -A^{-1} (C B^{-1}).
-  {
-    const int blk = tid >> 6, i = (tid >> 3) & 7, c = tid & 7;
-    const int o = 8 * blk;
-    for (int t = 0; t < 8; ++t) {
-      const int u = 7 - t;
-      if (i == u && c >= u) {
-        const C dd = X[o + u][o + u];
-        D[o + u][o + c] = cabs2(dd) > R(0) ? cdiv(D[o + u][o + c], dd) : cmake<C>(0, 0);
-      }
-      wave_lds_sync();
-      if (i > t && c < t) cfms(D[o + i][o + c], X[o + i][o + t], D[o + t][o + c]);
-      if (i > t && c == t) D[o + i][o + c] = cmake<C>(-X[o + i][o + t].x, -X[o + i][o + t].y);
-      if (i < u && c >= u) cfms(D[o + i][o + c], X[o + i][o + u], D[o + u][o + c]);
-      wave_lds_sync();
-    }
-  }
-  __syncthreads();
-  for (int h = 8; h < kDB; h *= 2) {
-    const int npair = kDB / (2 * h), per = npair * h * h, items = 2 * per;
-    // products C A^{-1} (lower pairs) and C B^{-1} (upper pairs) into Lm
-    for (int w = tid; w < items; w += 256) {
-      const int which = w / per, rem = w - which * per;
-      const int pr = rem / (h * h), e = rem - pr * h * h;
-      const int a = e / h, b = e - a * h, o = pr * 2 * h;
-      C acc = cmake<C>(0, 0);
-      if (which == 0) {
-#pragma unroll 2
-        for (int k = b; k < h; ++k) cfma(acc, X[o + h + a][o + k], k == b ? cmake<C>(1, 0) : D[o + k][o + b]);
-        Lm[o + h + a][o + b] = acc;
-      } else {
-#pragma unroll 2
-        for (int k = 0; k <= b; ++k) cfma(acc, X[o + a][o + h + k], D[o + h + k][o + h + b]);
-        Lm[o + a][o + h + b] = acc;
-      }
-    }
-    __syncthreads();
-    for (int w = tid; w < items; w += 256) {
-      const int which = w / per, rem = w - which * per;
-      const int pr = rem / (h * h), e = rem - pr * h * h;
-      const int a = e / h, b = e - a * h, o = pr * 2 * h;
-      C acc = cmake<C>(0, 0);
-      if (which == 0) {
-#pragma unroll 2
-        for (int k = 0; k <= a; ++k) cfms(acc, k == a ? cmake<C>(1, 0) : D[o + h + a][o + h + k], Lm[o + h + k][o + b]);
-        D[o + h + a][o + b] = acc;
-      } else {
-#pragma unroll 2
-        for (int k = a; k < h; ++k) cfms(acc, D[o + a][o + k], Lm[o + k][o + h + b]);
-        D[o + a][o + h + b] = acc;
-      }
-    }
-    __syncthreads();
   }
   C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
-  C* Ui = Li + kDB * kDB;
-  for (int t = tid; t < kDB * kDB; t += 256) {
-    const int c = t / kDB, i = t - c * kDB;
-    if (i < kb && c < kb) {
-      Li[c * kDB + i] = (i > c) ? D[i][c] : cmake<C>(i == c ? 1 : 0, 0);
-      Ui[c * kDB + i] = (i <= c) ? D[i][c] : cmake<C>(0, 0);
-    }
-  }
+  tri_inv32<R>(X, Li, Li + kDB * kDB, kb);
 }
 
 template <typename R>
@@ -1170,6 +1232,19 @@ __global__ void fwd_gather_kernel(MfDev mf, cplx_t<R>* __restrict__ W, const cpl
   }
 }
 
+// Entry i of a front's vector before its own products: the right-hand side
+// at a pivot position plus the boundary updates its children left for that
+// position, added in child order (as fwd_gather_kernel adds them).
+template <typename R>
+__device__ inline cplx_t<R> gathered(const MfDev& mf, const FrontDev& f, const cplx_t<R>* __restrict__ W,
+                                     const cplx_t<R>* __restrict__ xi, int64_t NI, int nrhs, int rr, int i) {
+  using C = cplx_t<R>;
+  C v = (i < f.p) ? xi[(int64_t)rr * NI + mf.idx[f.idx + i]] : cmake<C>(0, 0);
+  const int b = mf.gptr[f.gptr + i], e = mf.gptr[f.gptr + i + 1];
+  for (int t = b; t < e; ++t) v = cadd(v, W[mf.gsrc[t] * nrhs + rr]);
+  return v;
+}
+
 // Row-tiled complex GEMV for the substitution products.
 //  mode 0: z = Linv (P w_piv)            rows [0,p),  cols j < row (+ unit diagonal)
 //  mode 1: w_bnd -= L21 z                rows [0,F-p), cols [0,p)
@@ -1185,7 +1260,7 @@ template <typename R, int NR>
 __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ W,
                                                    cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout, int nrhs,
                                                    int r0, int f0, int mode, int nchunks, cplx_t<R>* __restrict__ partial,
-                                                   int prow) {
+                                                   int prow, const cplx_t<R>* __restrict__ xin) {
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   const int F = f.F, p = f.p;
@@ -1231,7 +1306,8 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
       const int jj = t / NR, r = t - jj * NR, j = jt + jj;
       C v = cmake<C>(0, 0);
       if (r0 + r < nrhs) {
-        if (mode == 0 || mode == 4) v = w[perm[j] * nrhs + r0 + r];
+        if (mode == 4) v = gathered<R>(mf, f, W, xin + I.Noff * nrhs, NI, nrhs, r0 + r, perm[j]);
+        else if (mode == 0) v = w[perm[j] * nrhs + r0 + r];
         else if (mode == 2) v = xo[(int64_t)(r0 + r) * NI + idx[p + j]];
         else if (mode == 5 && j >= p) v = cneg(xo[(int64_t)(r0 + r) * NI + idx[j]]);
         else v = z[j * nrhs + r0 + r];
@@ -1261,13 +1337,14 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
     const int rr = r0 + r;
     if (nchunks > 1) {
       partial[(((int64_t)blockIdx.y * nchunks + chunk) * prow + row) * nrhs + rr] = s;
-    } else if (mode == 0 || (mode == 4 && row < p)) {
+    } else if (mode == 4 && row < p) {
+      z[row * nrhs + rr] = cadd(s, gathered<R>(mf, f, W, xin + I.Noff * nrhs, NI, nrhs, rr, perm[row]));
+    } else if (mode == 4) {
+      w[row * nrhs + rr] = csub(gathered<R>(mf, f, W, xin + I.Noff * nrhs, NI, nrhs, rr, row), s);
+    } else if (mode == 0) {
       z[row * nrhs + rr] = cadd(s, w[perm[row] * nrhs + rr]);
     } else if (mode == 1) {
       C& d = w[(p + row) * nrhs + rr];
-      d = csub(d, s);
-    } else if (mode == 4) {
-      C& d = w[row * nrhs + rr];
       d = csub(d, s);
     } else if (mode == 2) {
       C& d = z[row * nrhs + rr];
@@ -1563,7 +1640,7 @@ __global__ void __launch_bounds__(256) front_levels_kernel(MfDev mf, const cplx_
 template <typename R>
 __global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z,
                                    cplx_t<R>* __restrict__ xout, int nrhs, int f0, int mode, int nchunks,
-                                   const cplx_t<R>* __restrict__ partial, int prow) {
+                                   const cplx_t<R>* __restrict__ partial, int prow, const cplx_t<R>* __restrict__ xin) {
   using C = cplx_t<R>;
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   const int nrows = (mode == 1) ? f.F - f.p : (mode == 4) ? f.F : f.p;
@@ -1575,19 +1652,21 @@ __global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R
     s = cadd(s, partial[(((int64_t)blockIdx.y * nchunks + c) * prow + row) * nrhs + rr]);
   C* w = W + f.voff * nrhs;
   C* z = Z + f.voff * nrhs;
-  if (mode == 0 || (mode == 4 && row < f.p)) {
+  const InstDev& I = mf.inst[f.inst];
+  if (mode == 4 && row < f.p) {
+    z[row * nrhs + rr] =
+        cadd(s, gathered<R>(mf, f, W, xin + I.Noff * nrhs, I.N, nrhs, rr, mf.perm[f.perm + row]));
+  } else if (mode == 4) {
+    w[row * nrhs + rr] = csub(gathered<R>(mf, f, W, xin + I.Noff * nrhs, I.N, nrhs, rr, row), s);
+  } else if (mode == 0) {
     z[row * nrhs + rr] = cadd(s, w[mf.perm[f.perm + row] * nrhs + rr]);
   } else if (mode == 1) {
     C& d = w[(f.p + row) * nrhs + rr];
-    d = csub(d, s);
-  } else if (mode == 4) {
-    C& d = w[row * nrhs + rr];
     d = csub(d, s);
   } else if (mode == 2) {
     C& d = z[row * nrhs + rr];
     d = csub(d, s);
   } else {
-    const InstDev& I = mf.inst[f.inst];
     xout[I.Noff * nrhs + (int64_t)rr * I.N + mf.idx[f.idx + row]] = s;
   }
 }
@@ -1808,13 +1887,15 @@ std::string gemv_tune_key(int rows, int cols, int nf, int mode, int nrhs, int cs
 // Row-tiled products; large fronts split their columns over nchunks
 // workgroups (deterministic partial sums, then gemv_finish_kernel).
 template <typename R>
-void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, void* Z_v, void* xout_v, int nrhs, int f0,
-             int nf, int rows, int cols, int mode, double ent, void* partial_v, int64_t partial_cap, int nchunks) {
+void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, void* Z_v, void* xout_v, const void* xin_v,
+             int nrhs, int f0, int nf, int rows, int cols, int mode, double ent, void* partial_v, int64_t partial_cap,
+             int nchunks) {
   using C = cplx_t<R>;
   const C* arena = static_cast<const C*>(arena_v);
   C* W = static_cast<C*>(W_v);
   C* Z = static_cast<C*>(Z_v);
   C* xout = static_cast<C*>(xout_v);
+  const C* xin = static_cast<const C*>(xin_v);
   C* partial = static_cast<C*>(partial_v);
   const int rtiles = (int)ceil_div(rows, 64);
   if (nchunks <= 0)
@@ -1829,17 +1910,17 @@ void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, vo
   int r0 = 0;
   while (r0 < nrhs) {
     if (nrhs - r0 >= 4) {
-      gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
+      gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows, xin);
       r0 += 4;
     } else {
-      gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows);
+      gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows, xin);
       r0 += 1;
     }
     SPP_LAUNCH_CHECK();
   }
   if (nchunks > 1) {
     gemv_finish_kernel<R><<<dim3(ceil_div((int64_t)rows * nrhs, 256), nf), 256, 0, st>>>(
-        mf, W, Z, xout, nrhs, f0, mode, nchunks, partial, rows);
+        mf, W, Z, xout, nrhs, f0, mode, nchunks, partial, rows, xin);
     SPP_LAUNCH_CHECK();
   }
   timer_end(KC_GEMV, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
@@ -1860,7 +1941,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
   // Row-tiled products; large fronts split their columns over several
   // workgroups (deterministic partial sums, then gemv_finish_kernel).
   auto gemv = [&](int f0, int nf, int rows, int cols, int mode, double ent) {
-    mf_gemv<R>(st, mf, arena, W, Z, xout, nrhs, f0, nf, rows, cols, mode, ent, partial, partial_cap, 0);
+    mf_gemv<R>(st, mf, arena, W, Z, xout, xin, nrhs, f0, nf, rows, cols, mode, ent, partial, partial_cap, 0);
   };
   // Whole-front kernels of the levels solved with the LU in place.
   auto front = [&](int f0, int nf, int maxF, int maxP, int maxK, bool fwd, double ent) {
@@ -1954,11 +2035,11 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       front(f0, nf, level_maxF[l], mP, mK, true, e[0] + e[2]);
       continue;
     }
-    fwd_gather_kernel<R><<<dim3(ceil_div(level_maxF[l], kGatherRows), nf), 256, 0, st>>>(mf, W, xin, nrhs, f0);
-    SPP_LAUNCH_CHECK();
     if (level_form[l] == kFormSide) {
-      gemv(f0, nf, level_maxF[l], mP, 4, e[0] + e[2]);
+      gemv(f0, nf, level_maxF[l], mP, 4, e[0] + e[2]);   // gathers its own input
     } else {
+      fwd_gather_kernel<R><<<dim3(ceil_div(level_maxF[l], kGatherRows), nf), 256, 0, st>>>(mf, W, xin, nrhs, f0);
+      SPP_LAUNCH_CHECK();
       gemv(f0, nf, mP, mP, 0, e[0]);
       if (mK > 0) gemv(f0, nf, mK, mP, 1, e[2]);
     }
@@ -2002,9 +2083,9 @@ template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, vo
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                               const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
                               int64_t, bool);
-template void mf_gemv<double>(hipStream_t, const MfDev&, const void*, void*, void*, void*, int, int, int, int, int, int,
+template void mf_gemv<double>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,
                               double, void*, int64_t, int);
-template void mf_gemv<float>(hipStream_t, const MfDev&, const void*, void*, void*, void*, int, int, int, int, int, int,
+template void mf_gemv<float>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,
                              double, void*, int64_t, int);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
