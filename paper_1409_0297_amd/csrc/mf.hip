@@ -18,6 +18,7 @@
 // The solve runs forward elimination leaves -> root (children's update
 // vectors pulled by the parent) and back substitution root -> leaves.
 #include <algorithm>
+#include <limits>
 #include <type_traits>
 #include <utility>
 
@@ -401,28 +402,14 @@ struct DiagLds {
   cplx_t<R> D[kDB][kDB + 1];    // the block to factor; later the inverses
   cplx_t<R> Lm[kDB][kDB + 1];   // the previous step's L part; later products
   cplx_t<R> X[kDB][kDB + 1];    // the LU in pivot order
-  int rsel[kDB];
+  cplx_t<R> lbuf[2][kDB];       // each row's multiplier of an elimination step
+  int rpbuf[2];                 // the step's pivot row
+  int kofr[kDB];                // step at which each row became the pivot
+  int rsel[kDB];                // pivot row of each step
 };
 
-// Orders one wave's LDS accesses before the ones that follow (the lanes of a
-// wave see each other's LDS writes in issue order).
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Lane exchanges of one wave: value of lane src (any lane), of a uniform lane,
-// rotation by N lanes inside each row of 16 lanes (DPP), and exchange with
-// lane ^ 16 inside each half of 32 lanes (swizzle, bitmask mode).
-__device__ inline float lane_get(float x, int src) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
-}
-__device__ inline double lane_get(double x, int src) {
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
+// Lane exchanges of one wave: the value of a uniform lane (a scalar read),
+// and rotation by N lanes inside each row of 16 lanes (DPP).
 __device__ inline float lane_read(float x, int src) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
 }
@@ -431,158 +418,182 @@ __device__ inline double lane_read(double x, int src) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
   return __hiloint2double(hi, lo);
 }
-template <int N> __device__ inline float row_ror(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x120 + N, 0xF, 0xF, false));
-}
 template <int N> __device__ inline double row_ror(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x120 + N, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x120 + N, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
-}
-__device__ inline float xor16(float x) {
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
-}
-__device__ inline double xor16(double x) {
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
-  return __hiloint2double(hi, lo);
-}
-// Largest value over each half of the wave (every lane of the half gets it).
-template <typename R> __device__ inline R half_wave_max(R v) {
-  v = fmax(v, row_ror<1>(v));
-  v = fmax(v, row_ror<2>(v));
-  v = fmax(v, row_ror<4>(v));
-  v = fmax(v, row_ror<8>(v));
-  return fmax(v, xor16(v));
 }
 // c ? x : y on the components (a select of whole vector structs goes through
 // their addresses and keeps register arrays in memory).
 template <typename C> __device__ inline C csel(bool c, C x, C y) {
   return cmake<C>(c ? x.x : y.x, c ? x.y : y.y);
 }
-template <typename C> __device__ inline C lane_get(C x, int src) {
-  return cmake<C>(lane_get(x.x, src), lane_get(x.y, src));
-}
 template <typename C> __device__ inline C lane_read(C x, int src) {
   return cmake<C>(lane_read(x.x, src), lane_read(x.y, src));
 }
 
-// Slot K (column 2 K + h) of step J of wave_lu32: a -= l * (pivot row), or
-// the multiplier l itself in column J.
-template <typename R, int J, int K>
-__device__ __forceinline__ void wave_lu_slot(cplx_t<R> (&a)[kDB / 2], cplx_t<R> l, int src, int h, bool upd) {
-  using C = cplx_t<R>;
-  constexpr int js = J >> 1, jh = J & 1;
-  if constexpr (K >= js) {
-    const C pr = lane_get(a[K], src);                // pivot row at this lane's column
-    C nv = a[K];
-    cfms(nv, l, pr);
-    if constexpr (K > js) a[K] = csel(upd, nv, a[K]);
-    else a[K] = csel(upd && h > jh, nv, csel(upd && h == jh, l, a[K]));
-  }
-}
-template <typename R, int J, int... K>
-__device__ __forceinline__ void wave_lu_update(std::integer_sequence<int, K...>, cplx_t<R> (&a)[kDB / 2],
-                                               cplx_t<R> l, int src, int h, bool upd) {
-  (wave_lu_slot<R, J, K>(a, l, src, h, upd), ...);
+// Bitwise equality of two values (true for two NaNs with the same bits).
+__device__ __forceinline__ bool memcmp_eq(float a, float b) { return __float_as_int(a) == __float_as_int(b); }
+__device__ __forceinline__ bool memcmp_eq(double a, double b) {
+  return __double_as_longlong(a) == __double_as_longlong(b);
 }
 
-// One elimination step (column J) of wave_lu32.
-template <typename R, int J>
-__device__ __forceinline__ void wave_lu_step(cplx_t<R> (&a)[kDB / 2], int lane, int r, int h, int kb, bool& done,
-                                             bool& bad, int& kr) {
-  using C = cplx_t<R>;
-  constexpr int js = J >> 1, jh = J & 1;
-  const C other = lane_get(a[js], lane ^ 32);
-  const C dj = csel(h == jh, a[js], other);          // d_rJ of this lane's row
-  const R v2 = done ? R(-1) : cabs2(dj);
-  const R m = half_wave_max(v2);
-  const unsigned hit = (unsigned)__ballot(!done && v2 == m);
-  const unsigned live = (unsigned)__ballot(!done);
-  // With every remaining entry NaN nothing matches: take the first remaining row.
-  const int rp = __builtin_ctz(hit ? hit : live);
-  if (J < kb && (!hit || !(m > R(0)) || !isfinite(m) || __ballot(!done && v2 != v2))) bad = true;
-  const C pv = lane_read(dj, rp);
-  const R p2 = cabs2(pv);
-  const R inv = p2 > R(0) ? R(1) / p2 : R(0);
-  const C l = cmake<C>((dj.x * pv.x + dj.y * pv.y) * inv, (dj.y * pv.x - dj.x * pv.y) * inv);
-  const bool upd = !done && r != rp;
-  if (r == rp) {
-    done = true;
-    kr = J;
+// a -= m * b as four fused multiply-adds (the negations are operand modifiers).
+template <typename C> __device__ __forceinline__ void cfms4(C& a, C m, C b) {
+  a.x = fma(-m.x, b.x, a.x);
+  a.x = fma(m.y, b.y, a.x);
+  a.y = fma(-m.x, b.y, a.y);
+  a.y = fma(-m.y, b.x, a.y);
+}
+// 1 / x for x > 0, else 0 (the single-precision reciprocal instruction is
+// accurate to 1 ulp, enough for a pivot's reciprocal).
+__device__ __forceinline__ float pos_recip(float x) { return x > 0.f ? __builtin_amdgcn_rcpf(x) : 0.f; }
+__device__ __forceinline__ double pos_recip(double x) { return x > 0.0 ? 1.0 / x : 0.0; }
+
+// Largest |d|^2 over the 32 rows of the wave (lanes r and r + 32 hold row r;
+// rows already used as pivots carry -1).  In single precision the bit
+// patterns are compared as integers: they order like the values for x >= 0,
+// -1 is below all of them, and a NaN is above every number, so a NaN entry
+// is the one chosen (and then reported).
+__device__ __forceinline__ float rows_max(float v) {
+  int m = __float_as_int(v);
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x121, 0xF, 0xF, false));
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x122, 0xF, 0xF, false));
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x124, 0xF, 0xF, false));
+  m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x128, 0xF, 0xF, false));
+  return __int_as_float(max(__builtin_amdgcn_readlane(m, 0), __builtin_amdgcn_readlane(m, 16)));
+}
+__device__ __forceinline__ double rows_max(double v) {
+  auto mx = [](double a, double b) { return (a > b || a != a) ? a : b; };
+  v = mx(v, row_ror<1>(v));
+  v = mx(v, row_ror<2>(v));
+  v = mx(v, row_ror<4>(v));
+  v = mx(v, row_ror<8>(v));
+  return mx(lane_read(v, 0), lane_read(v, 16));
+}
+
+// Slot S (column 4 S + w) of step J of wg_lu32 in wave w: a_S -= l * (pivot
+// row)_S for the columns right of J, the pivot row's entry read from its lane
+// (l is zero on the rows not to eliminate).
+template <typename R, int J, int S>
+__device__ __forceinline__ void wg_lu_slot(cplx_t<R> (&a)[kDB / 4], cplx_t<R> l, int rp, int w) {
+  if constexpr (4 * S + 3 > J) {
+    if (4 * S > J || 4 * S + w > J) cfms4(a[S], l, lane_read(a[S], rp));
   }
-  wave_lu_update<R, J>(std::make_integer_sequence<int, kDB / 2>{}, a, l, rp + 32 * h, h, upd);
+}
+template <typename R, int J, int... S>
+__device__ __forceinline__ void wg_lu_update(std::integer_sequence<int, S...>, cplx_t<R> (&a)[kDB / 4], cplx_t<R> l,
+                                             int rp, int w) {
+  (wg_lu_slot<R, J, S>(a, l, rp, w), ...);
+}
+
+// Step J of wg_lu32.  The wave owning column J picks the pivot, posts every
+// row's multiplier and the pivot row, and keeps the multipliers in column J;
+// after the barrier every wave eliminates its own columns right of J.
+template <typename R, int J>
+__device__ __forceinline__ void wg_lu_step(cplx_t<R> (&a)[kDB / 4], DiagLds<R>& S, int w, int lane, int r, int kb,
+                                           bool& done, bool& bad) {
+  using C = cplx_t<R>;
+  constexpr int owner = J & 3, js = J >> 2, b = J & 1;
+  C le = cmake<C>(0, 0);
+  if (w == owner) {
+    const C dj = a[js];
+    const R v2 = done ? R(-1) : cabs2(dj);
+    const R m = rows_max(v2);
+    // Equal bit patterns: exact ties go to the lowest row, a NaN maximum matches itself.
+    const unsigned hit = (unsigned)__builtin_amdgcn_ballot_w64(!done && memcmp_eq(v2, m));
+    const unsigned live = (unsigned)__builtin_amdgcn_ballot_w64(!done);
+    const int rp = __builtin_ctz(hit ? hit : live);
+    bad = bad | ((J < kb) & !(m > R(0) && m <= std::numeric_limits<R>::max()));
+    const C pv = lane_read(dj, rp);
+    const R inv = pos_recip(cabs2(pv));
+    const bool upd = !done && r != rp;
+    const C l = cmul(dj, cmake<C>(pv.x * inv, -pv.y * inv));
+    le = csel(upd, l, cmake<C>(0, 0));
+    a[js] = csel(upd, l, a[js]);
+    if (lane < 32) S.lbuf[b][r] = le;
+    if (lane == 0) {
+      S.rpbuf[b] = rp;
+      S.kofr[rp] = J;
+      S.rsel[J] = rp;
+    }
+  }
+  __syncthreads();
+  const C lb = S.lbuf[b][r];                          // both reads issued together
+  const int rp = __builtin_amdgcn_readfirstlane(S.rpbuf[b]);
+  if (w != owner) le = lb;
+  done = done || r == rp;
+  wg_lu_update<R, J>(std::make_integer_sequence<int, kDB / 4>{}, a, le, rp, w);
 }
 
 template <typename R, int... J>
-__device__ __forceinline__ void wave_lu_steps(std::integer_sequence<int, J...>, cplx_t<R> (&a)[kDB / 2], int lane,
-                                              int r, int h, int kb, bool& done, bool& bad, int& kr) {
-  (wave_lu_step<R, J>(a, lane, r, h, kb, done, bad, kr), ...);
+__device__ __forceinline__ void wg_lu_steps(std::integer_sequence<int, J...>, cplx_t<R> (&a)[kDB / 4], DiagLds<R>& S,
+                                            int w, int lane, int r, int kb, bool& done, bool& bad) {
+  (wg_lu_step<R, J>(a, S, w, lane, r, kb, done, bad), ...);
 }
 
-// LU with row pivoting of the 32 x 32 block D by one wave, in registers.
-// Lane (r, h) = (lane & 31, lane >> 5) holds row r at the columns 2 k + h.
-// Step j takes as pivot the remaining row of largest |d_rj|^2 (ties to the
-// lowest row) and eliminates column j from the other remaining rows; each row
-// keeps its multipliers in place, so the row chosen at step k ends as row k
-// of the LU in pivot order: L left of column k, U from column k on.  Writes
-// that LU to X and the chosen rows to rsel; returns true if a pivot among the
-// first kb was zero or not finite.
+// LU with row pivoting of the 32 x 32 block S.D by the four waves of the
+// workgroup: wave w keeps the columns 4 s + w (s < 8) of every row, lane r
+// (and its twin r + 32, which repeats the work) holding row r.  Step j takes
+// as pivot the remaining row of largest |d_rj|^2 (ties to the lowest row) and
+// eliminates column j from the other remaining rows; each row keeps its
+// multipliers in place, so the row chosen at step k ends as row k of the LU
+// in pivot order: L left of column k, U from column k on.  Writes that LU to
+// S.X and the chosen rows to S.rsel; returns true (in the waves that owned
+// such a step) if a pivot among the first kb was zero or not finite.
 template <typename R>
-__device__ __forceinline__ bool wave_lu32(cplx_t<R> (*D)[kDB + 1], cplx_t<R> (*X)[kDB + 1], int* rsel, int kb) {
+__device__ __forceinline__ bool wg_lu32(DiagLds<R>& S, int kb) {
   using C = cplx_t<R>;
-  const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
-  C a[kDB / 2];
+  const int lane = threadIdx.x & 63, r = lane & 31, w = threadIdx.x >> 6;
+  C a[kDB / 4];
 #pragma unroll
-  for (int k = 0; k < kDB / 2; ++k) a[k] = D[r][2 * k + h];
+  for (int s = 0; s < kDB / 4; ++s) a[s] = S.D[r][4 * s + w];
   bool done = false, bad = false;
-  int kr = 0;
-  wave_lu_steps<R>(std::make_integer_sequence<int, kDB>{}, a, lane, r, h, kb, done, bad, kr);
+  wg_lu_steps<R>(std::make_integer_sequence<int, kDB>{}, a, S, w, lane, r, kb, done, bad);
+  const int kr = S.kofr[r];
+  if (lane < 32) {
 #pragma unroll
-  for (int k = 0; k < kDB / 2; ++k) X[kr][2 * k + h] = a[k];
-  if (h == 0) rsel[kr] = r;
+    for (int s = 0; s < kDB / 4; ++s) S.X[kr][4 * s + w] = a[s];
+  }
   return bad;
 }
 
 // Inverses of the triangles of a 32 x 32 LU (X, pivot order) by column
 // sweeps over the identity, two waves per triangle.  Lane (i, g) holds row i
 // of the inverse at the columns 4 t + g (t < 8); the row needed at sweep step
-// j is row j of the lane's own group (lane j or j + 32 of the wave).
+// j is row j of the lane's own group, read from lane j or j + 32 of the wave.
 //   L^{-1}: for j = 0 .. 30, rows i > j: z_i -= l_ij z_j  (z_j is final by then);
 //   U^{-1}: for j = 31 .. 1, rows i < j: z_i -= (u_ij / u_jj) z_j, and every
 //           row is divided by its own u_ii at the end.
 // Only the columns where row j can be nonzero are swept (c <= j for L^{-1},
-// c >= j for U^{-1}).
+// c >= j for U^{-1}); rows outside a step's range take a zero multiplier.
 template <typename R, bool LOWER, int J, int T>
-__device__ __forceinline__ void tri_inv_slot(cplx_t<R> (&z)[kDB / 4], cplx_t<R> m, int src, bool upd) {
-  if constexpr (LOWER ? T <= J / 4 : T >= J / 4) {
-    cplx_t<R> nv = z[T];
-    cfms(nv, m, lane_get(z[T], src));
-    z[T] = csel(upd, nv, z[T]);
-  }
+__device__ __forceinline__ void tri_inv_slot(cplx_t<R> (&z)[kDB / 4], cplx_t<R> m, bool hi) {
+  if constexpr (LOWER ? T <= J / 4 : T >= J / 4)
+    cfms4(z[T], m, csel(hi, lane_read(z[T], J + 32), lane_read(z[T], J)));
 }
 template <typename R, int J, int... T>
 __device__ __forceinline__ void lower_inv_step(std::integer_sequence<int, T...>, cplx_t<R> (&z)[kDB / 4],
-                                               cplx_t<R> (*X)[kDB + 1], int i, int src0) {
-  const cplx_t<R> l = X[i][J];
-  (tri_inv_slot<R, true, J, T>(z, l, src0 + J, i > J), ...);
+                                               cplx_t<R> (*X)[kDB + 1], int i, bool hi) {
+  using C = cplx_t<R>;
+  const C l = csel(i > J, X[i][J], cmake<C>(0, 0));
+  (tri_inv_slot<R, true, J, T>(z, l, hi), ...);
 }
 template <typename R, int J, int... T>
 __device__ __forceinline__ void upper_inv_step(std::integer_sequence<int, T...>, cplx_t<R> (&z)[kDB / 4],
-                                               cplx_t<R> (*X)[kDB + 1], int i, int src0) {
+                                               cplx_t<R> (*X)[kDB + 1], int i, bool hi) {
   using C = cplx_t<R>;
   const C d = X[J][J];
-  const R m2 = cabs2(d);
-  const R inv = m2 > R(0) ? R(1) / m2 : R(0);
-  const C u = cmul(X[i][J], cmake<C>(d.x * inv, -d.y * inv));
-  (tri_inv_slot<R, false, J, T>(z, u, src0 + J, i < J), ...);
+  const R inv = pos_recip(cabs2(d));
+  const C u = csel(i < J, cmul(X[i][J], cmake<C>(d.x * inv, -d.y * inv)), cmake<C>(0, 0));
+  (tri_inv_slot<R, false, J, T>(z, u, hi), ...);
 }
 template <typename R, int... Q>
 __device__ __forceinline__ void tri_inv_sweeps(std::integer_sequence<int, Q...>, cplx_t<R> (&z)[kDB / 4],
-                                               cplx_t<R> (*X)[kDB + 1], int i, int src0, bool lower) {
+                                               cplx_t<R> (*X)[kDB + 1], int i, bool hi, bool lower) {
   constexpr auto slots = std::make_integer_sequence<int, kDB / 4>{};
-  if (lower) (lower_inv_step<R, Q>(slots, z, X, i, src0), ...);
-  else (upper_inv_step<R, kDB - 1 - Q>(slots, z, X, i, src0), ...);
+  if (lower) (lower_inv_step<R, Q>(slots, z, X, i, hi), ...);
+  else (upper_inv_step<R, kDB - 1 - Q>(slots, z, X, i, hi), ...);
 }
 
 // Workgroup part: waves 0-1 invert L, waves 2-3 U; column-major results.
@@ -596,13 +607,12 @@ __device__ __forceinline__ void tri_inv32(cplx_t<R> (*X)[kDB + 1], cplx_t<R>* __
   C z[kDB / 4];
 #pragma unroll
   for (int t = 0; t < kDB / 4; ++t) z[t] = cmake<C>(4 * t + g == i ? 1 : 0, 0);
-  tri_inv_sweeps<R>(std::make_integer_sequence<int, kDB - 1>{}, z, X, i, 32 * gh, lower);
+  tri_inv_sweeps<R>(std::make_integer_sequence<int, kDB - 1>{}, z, X, i, gh == 1, lower);
   C* out = lower ? Li : Ui;
   C s = cmake<C>(1, 0);
   if (!lower) {
     const C d = X[i][i];
-    const R m2 = cabs2(d);
-    const R inv = m2 > R(0) ? R(1) / m2 : R(0);
+    const R inv = pos_recip(cabs2(d));
     s = cmake<C>(d.x * inv, -d.y * inv);
   }
 #pragma unroll
@@ -654,7 +664,7 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     D[i][c] = v;
   }
   __syncthreads();
-  if (tid < 64 && wave_lu32<R>(D, X, rsel, kb) && tid == 0) atomicCAS(mf.info, 0, fi + 1);
+  if (wg_lu32<R>(S, kb) && (tid & 63) == 0) atomicCAS(mf.info, 0, fi + 1);
   __syncthreads();
   // Block-local pivoting keeps every interchange inside the block, so the
   // row order is also the block's part of the front's final permutation.
@@ -887,24 +897,25 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 //           (the rest), P the step's row order from the diagonal-block LU,
 //           applied while loading A12.  Both overwrite their input block;
 //           every workgroup reads all of its own block before writing it.
-// NEXT (mode 0 only): the launch's last workgroup column (blockIdx.x ==
-// gridDim.x - 1) factors the next diagonal block of each front, taking this
-// step's update of that block itself; the tile holding the block skips it.
+// NEXT (mode 0 only): a workgroup with bx < 0 factors the next diagonal
+// block of front by, taking this step's update of that block itself; the
+// tile holding the block skips it.
+// (bx, by) = (tile, front) of the workgroup.
 template <typename R, bool NEXT, int mode>
 __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
-                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m) {
+                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m, int bx, int by) {
   using C = cplx_t<R>;
   constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > sizeof(GemmLds<R>) ? sizeof(DiagLds<R>) : sizeof(GemmLds<R>))
                                : sizeof(GemmLds<R>);
   __shared__ __align__(16) unsigned char lds[kLds];
-  const FrontDev f = mf.fronts[f0 + blockIdx.y];
+  const FrontDev f = mf.fronts[f0 + by];
   int k0, kb;
   if (!step_range<R>(f, mode == 2 ? 2 : 0, step, nb, k0, kb)) return;
   int skip = 0;
   if (NEXT) {
     const int k1 = k0 + kb;
-    if (blockIdx.x == gridDim.x - 1) {
-      if (k1 < f.p) diag_lu_block<R>(mf, arena, dinv, f0 + blockIdx.y, k1, nb, k0, *reinterpret_cast<DiagLds<R>*>(lds));
+    if (bx < 0) {
+      if (k1 < f.p) diag_lu_block<R>(mf, arena, dinv, f0 + by, k1, nb, k0, *reinterpret_cast<DiagLds<R>*>(lds));
       return;
     }
     if (k1 < f.p) skip = min(nb, f.p - k1);
@@ -921,14 +932,14 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
     const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
     const C* Ui = Li + kDB * kDB;
     assign = true;
-    if ((int)blockIdx.x < tiles_m) {   // L21 = A21 Uinv_kk
-      tm = blockIdx.x; tn = 0;
+    if (bx < tiles_m) {                // L21 = A21 Uinv_kk
+      tm = bx; tn = 0;
       m = F - k0 - kb; n = kb; k = kb;
       Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
       Bp = Ui; ldb = kDB;
       Cp = base + (int64_t)k0 * F + (k0 + kb); ldc = F;
     } else {                           // U12 = Linv_kk (P A12)
-      tm = 0; tn = blockIdx.x - tiles_m;
+      tm = 0; tn = bx - tiles_m;
       m = kb; n = F - k0 - kb; k = kb;
       Ap = Li; lda = kDB;
       Bp = base + (int64_t)(k0 + kb) * F; ldb = F;
@@ -936,8 +947,8 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
       brow = mf.prow + f.perm + k0;
     }
   } else {
-    tm = blockIdx.x % tiles_m;
-    tn = blockIdx.x / tiles_m;
+    tm = bx % tiles_m;
+    tn = bx / tiles_m;
     if constexpr (mode == 0) {
       m = n = F - k0 - kb; k = kb;
       Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
@@ -967,17 +978,26 @@ template <typename R, int MODE>
 __global__ void __launch_bounds__(256, kGemmWaves<R>) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                                    cplx_t<R>* __restrict__ dinv, int f0, int step, int nb,
                                                    int tiles_m) {
-  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m);
+  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, blockIdx.x, blockIdx.y);
 }
 
 // Trailing update with the next diagonal block (mode 0, NEXT above); asks
 // for 4 waves per SIMD so that the block's registers do not halve the tiles'
-// occupancy.
+// occupancy.  Grid (tiles + 1, fronts): the first nf workgroups in launch
+// order factor the diagonal blocks (so that they start first and overlap the
+// tiles instead of waiting for free slots), the rest are the fronts' tiles.
 template <typename R>
 __global__ void __launch_bounds__(256, 4) gemm_next_kernel(MfDev mf, cplx_t<R>* __restrict__ arena,
                                                            cplx_t<R>* __restrict__ xwork, cplx_t<R>* __restrict__ dinv,
                                                            int f0, int step, int nb, int tiles_m) {
-  gemm_body<R, true, 0>(mf, arena, xwork, dinv, f0, step, nb, tiles_m);
+  const int nf = gridDim.y, per = gridDim.x - 1;
+  const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+  int bx = -1, by = lin;
+  if (lin >= nf) {
+    by = (lin - nf) / per;
+    bx = lin - nf - by * per;
+  }
+  gemm_body<R, true, 0>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, bx, by);
 }
 
 // Row interchanges of every 32-row diagonal block of a level's fronts applied
@@ -1363,6 +1383,9 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
 // The triangular solves go in 32-row blocks: one wave solves the diagonal
 // block with shuffles, the whole workgroup updates the rows beyond it.
 constexpr int kTriBS = 32;
+// Column loads in flight per thread in the strip products (more in FP32,
+// where they cost half the registers).
+template <typename R> constexpr int kStripUnroll = sizeof(R) == 4 ? 16 : 8;
 
 // acc[r] (r < NR) for rows [row0, row0 + 64) of an F-strided column-major
 // matrix M (rows of the product, `cols` columns) times the LDS vector v
@@ -1377,7 +1400,7 @@ __device__ inline void wg_matvec_rows(const cplx_t<R>* __restrict__ M, int ld, i
   C acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmake<C>(0, 0);
-#pragma unroll 8
+#pragma unroll kStripUnroll<R>
   for (int j = grp; j < cols; j += 4) {
     const C a = live ? M[(int64_t)j * ld + row] : cmake<C>(0, 0);
 #pragma unroll
@@ -1450,14 +1473,13 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
       C yi[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) yi[r] = (lane < bs) ? y[(b0 + lane) * NR + r] : cmake<C>(0, 0);
-      for (int jj = 0; jj < bs; ++jj) {
-        const C l = (lane > jj && lane < bs) ? D[lane][jj] : cmake<C>(0, 0);
+      // Column jj of the block: y_jj is final in lane jj, read as a scalar.
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          C zj;
-          zj.x = __shfl(yi[r].x, jj, 64);
-          zj.y = __shfl(yi[r].y, jj, 64);
-          cfms(yi[r], l, zj);
+      for (int jj = 0; jj < BS; ++jj) {
+        if (jj < bs) {
+          const C l = (lane > jj && lane < bs) ? D[lane][jj] : cmake<C>(0, 0);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfms(yi[r], l, lane_read(yi[r], jj));
         }
       }
       if (lane < bs)
@@ -1469,7 +1491,7 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
       C acc[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
-#pragma unroll 8
+#pragma unroll kStripUnroll<R>
       for (int jj = 0; jj < bs; ++jj) {
         const C l = A[(int64_t)(b0 + jj) * F + i];
 #pragma unroll
@@ -1533,7 +1555,7 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
     C acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
-#pragma unroll 8
+#pragma unroll kStripUnroll<R>
     for (int j = 0; j < K; ++j) {
       const C u = A[(int64_t)(p + j) * F + i];
 #pragma unroll
@@ -1555,16 +1577,19 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
       C yi[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) yi[r] = (lane < bs) ? y[(b0 + lane) * NR + r] : cmake<C>(0, 0);
-      for (int jj = bs - 1; jj >= 0; --jj) {
-        const C u = (lane <= jj) ? D[lane][jj] : cmake<C>(0, 0);
-        const C dinv = (lane == jj && cabs2(u) > 0) ? crecip(u) : cmake<C>(0, 0);
+      // Column jj from the last: x_jj = y_jj / u_jj in lane jj, read as a scalar.
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          if (lane == jj) yi[r] = cmul(yi[r], dinv);
-          C xj;
-          xj.x = __shfl(yi[r].x, jj, 64);
-          xj.y = __shfl(yi[r].y, jj, 64);
-          if (lane < jj) cfms(yi[r], u, xj);
+      for (int jj = BS - 1; jj >= 0; --jj) {
+        if (jj < bs) {
+          const C u = (lane < jj) ? D[lane][jj] : cmake<C>(0, 0);
+          const C d = D[jj][jj];
+          const C dinv = cabs2(d) > 0 ? crecip(d) : cmake<C>(0, 0);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const C xj = cmul(lane_read(yi[r], jj), dinv);
+            if (lane == jj) yi[r] = xj;
+            if (lane < jj) cfms(yi[r], u, xj);
+          }
         }
       }
       if (lane < bs)
@@ -1576,7 +1601,7 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
       C acc[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
-#pragma unroll 8
+#pragma unroll kStripUnroll<R>
       for (int jj = 0; jj < bs; ++jj) {
         const C u = A[(int64_t)(b0 + jj) * F + i];
 #pragma unroll
