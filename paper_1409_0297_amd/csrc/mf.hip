@@ -797,7 +797,10 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
   // im = sum (ar bi + ai br).  Updates start from C and take A scaled by sgn
-  // when it is staged in LDS, so C -= A B needs no extra pass.
+  // when it is staged in LDS, so C -= A B needs no extra pass.  The products
+  // are formed as (B^T A^T)^T: B takes the MFMA's first operand, so that the
+  // 16 lanes holding one output column hold 16 consecutive rows of C, and
+  // loads and stores of the column-major C tile are contiguous.
   // Addresses are a tile base (uniform) plus 32-bit offsets inside the tile.
   C* __restrict__ Ct = Cp + (int64_t)n0 * ldc + m0;
   const int mt = m - m0, nt = n - n0;
@@ -808,8 +811,8 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wm + 16 * a + mfma_row(R(0), lane, r);
-        const int col = wn + 16 * b + (lane & 15);
+        const int row = wm + 16 * a + (lane & 15);
+        const int col = wn + 16 * b + mfma_row(R(0), lane, r);
         C c0 = cmake<C>(0, 0);
         if (from_c && row < mt && col < nt) c0 = Ct[col * ldc + row];
         re[a][b][r] = c0.x;
@@ -860,10 +863,10 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          re[a][b] = mfma16(av[a].x, bv[b].x, re[a][b]);
-          re[a][b] = mfma16(-av[a].y, bv[b].y, re[a][b]);
-          im[a][b] = mfma16(av[a].x, bv[b].y, im[a][b]);
-          im[a][b] = mfma16(av[a].y, bv[b].x, im[a][b]);
+          re[a][b] = mfma16(bv[b].x, av[a].x, re[a][b]);
+          re[a][b] = mfma16(-bv[b].y, av[a].y, re[a][b]);
+          im[a][b] = mfma16(bv[b].y, av[a].x, im[a][b]);
+          im[a][b] = mfma16(bv[b].x, av[a].y, im[a][b]);
         }
     }
     __syncthreads();
@@ -874,8 +877,8 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wm + 16 * a + mfma_row(R(0), lane, r);
-        const int col = wn + 16 * b + (lane & 15);
+        const int row = wm + 16 * a + (lane & 15);
+        const int col = wn + 16 * b + mfma_row(R(0), lane, r);
         if (row < mt && col < nt && !(m0 + row < skip && n0 + col < skip))
           Ct[col * ldc + row] = cmake<C>(re[a][b][r], im[a][b][r]);
       }
