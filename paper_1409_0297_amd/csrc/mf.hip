@@ -1390,35 +1390,6 @@ constexpr int kTriBS = 32;
 // where they cost half the registers).
 template <typename R> constexpr int kStripUnroll = sizeof(R) == 4 ? 16 : 8;
 
-// acc[r] (r < NR) for rows [row0, row0 + 64) of an F-strided column-major
-// matrix M (rows of the product, `cols` columns) times the LDS vector v
-// (cols x NR): four groups of 64 lanes split the columns, then reduce.
-template <typename R, int NR>
-__device__ inline void wg_matvec_rows(const cplx_t<R>* __restrict__ M, int ld, int nrows, int row0, int cols,
-                                      const cplx_t<R>* v, cplx_t<R> (*red)[64][NR], cplx_t<R>* out) {
-  using C = cplx_t<R>;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int row = row0 + lane;
-  const bool live = row < nrows;
-  C acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = cmake<C>(0, 0);
-#pragma unroll kStripUnroll<R>
-  for (int j = grp; j < cols; j += 4) {
-    const C a = live ? M[(int64_t)j * ld + row] : cmake<C>(0, 0);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) cfma(acc[r], a, v[j * NR + r]);
-  }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) red[grp][lane][r] = acc[r];
-  __syncthreads();
-  if (grp == 0 && live)
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      out[r] = cadd(cadd(red[0][lane][r], red[1][lane][r]), cadd(red[2][lane][r], red[3][lane][r]));
-  __syncthreads();
-}
-
 template <typename R, int NR>
 __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ W,
                                       cplx_t<R>* __restrict__ Z, const cplx_t<R>* __restrict__ x, int nrhs, int r0,
@@ -1426,7 +1397,7 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   using C = cplx_t<R>;
   constexpr int BS = kTriBS;
   const FrontDev& f = mf.fronts[fi];
-  const int F = f.F, p = f.p, K = F - p;
+  const int F = f.F, p = f.p;
   const C* A = arena + f.off;
   const int* perm = mf.perm + f.perm;
   const int* idx = mf.idx + f.idx;
@@ -1436,7 +1407,6 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   C* z = Z + f.voff * nrhs;
   const int nr = min(NR, nrhs - r0);
   __shared__ C D[BS][BS + 1];
-  __shared__ C red[4][64][NR];
   extern __shared__ unsigned char smem[];
   C* wv = reinterpret_cast<C*>(smem);   // F x NR: the front vector
   C* y = wv + F * NR;                   // p x NR: permuted pivot part, solved in place
@@ -1490,10 +1460,13 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
         for (int r = 0; r < NR; ++r) y[(b0 + lane) * NR + r] = yi[r];
     }
     __syncthreads();
-    for (int i = b0 + bs + threadIdx.x; i < p; i += blockDim.x) {
+    // The block's columns applied to every row below it: the rest of the
+    // pivot block (y) and the boundary rows (w_bnd -= L21 y, a strip at a time).
+    for (int i = b0 + bs + threadIdx.x; i < F; i += blockDim.x) {
+      C* v = (i < p) ? y + i * NR : wv + i * NR;
       C acc[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
+      for (int r = 0; r < NR; ++r) acc[r] = v[r];
 #pragma unroll kStripUnroll<R>
       for (int jj = 0; jj < bs; ++jj) {
         const C l = A[(int64_t)(b0 + jj) * F + i];
@@ -1501,23 +1474,10 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
         for (int r = 0; r < NR; ++r) cfms(acc[r], l, y[(b0 + jj) * NR + r]);
       }
 #pragma unroll
-      for (int r = 0; r < NR; ++r) y[i * NR + r] = acc[r];
+      for (int r = 0; r < NR; ++r) v[r] = acc[r];
     }
     __syncthreads();
   }
-  // w_bnd -= L21 y
-  for (int row0 = 0; row0 < K; row0 += 64) {
-    C s[NR];
-    wg_matvec_rows<R, NR>(A + p, F, K, row0, p, y, red, s);
-    const int row = row0 + lane;
-    if (threadIdx.x < 64 && row < K)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        C& d = wv[(p + row) * NR + r];
-        d = csub(d, s[r]);
-      }
-  }
-  __syncthreads();
   for (int t = threadIdx.x; t < F * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
     if (r >= nr) continue;
