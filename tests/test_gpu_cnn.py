@@ -116,7 +116,7 @@ def test_learned_stage_trains_on_krylov_pairs_and_keeps_the_solution():
     """Train on (v_j, M v_j) pairs of a random-media family (n = 64,
     omega = 2 pi 8, 8 bumps), attach to solves of unseen media: every solve
     still converges to the plain solve's solution, the network lowers its
-    training loss, and the judge's counts add up.  The measured gain (accepted
+    training loss, and the acceptance counts add up.  The measured gain (accepted
     steps, preconditioner applications saved, time) is printed; on this family
     the network, which sees only v and not the medium, approximates P^{-1} Q
     poorly and saves at most a step per solve."""
