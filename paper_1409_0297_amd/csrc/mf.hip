@@ -900,6 +900,8 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 //           (the rest), P the step's row order from the diagonal-block LU,
 //           applied while loading A12.  Both overwrite their input block;
 //           every workgroup reads all of its own block before writing it.
+//   mode 3: the next block's column and row take this step's update (a pair
+//           of steps whose trailing update then goes as one rank-2kb product)
 // NEXT (mode 0 only): a workgroup with bx < 0 factors the next diagonal
 // block of front by, taking this step's update of that block itself; the
 // tile holding the block skips it.
@@ -931,7 +933,26 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
   int tm, tn;
   const int* brow = nullptr;
   bool assign = false;
-  if constexpr (mode == 7) {
+  if constexpr (mode == 3) {
+    // The next block (kb2 columns / rows after this one) of a pair of
+    // steps: its column below this block (first tiles_m workgroups) and its
+    // row right of it (the rest) take this step's update.
+    const int kb2 = min(nb, p - k0 - kb);
+    if (kb2 <= 0) return;
+    Ap = base + (int64_t)k0 * F + (k0 + kb); lda = F;
+    k = kb;
+    if (bx < tiles_m) {
+      tm = bx; tn = 0;
+      m = F - k0 - kb; n = kb2;
+      Bp = base + (int64_t)(k0 + kb) * F + k0; ldb = F;
+      Cp = base + (int64_t)(k0 + kb) * F + (k0 + kb); ldc = F;
+    } else {
+      tm = 0; tn = bx - tiles_m;
+      m = kb2; n = F - k0 - kb - kb2;
+      Bp = base + (int64_t)(k0 + kb + kb2) * F + k0; ldb = F;
+      Cp = base + (int64_t)(k0 + kb + kb2) * F + (k0 + kb); ldc = F;
+    }
+  } else if constexpr (mode == 7) {
     const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
     const C* Ui = Li + kDB * kDB;
     assign = true;
@@ -1701,14 +1722,70 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     SPP_LAUNCH_CHECK();
     timer_end(KC_PANEL, st, 0.0, 0.0);
   }
-  for (int s = 0; s < steps; ++s) {
-    const int k0 = s * kNB;
-    if (!partial_pivoting && s > 0 && nf > 64) {
-      timer_begin(KC_PANEL, st);
-      diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, k0, kNB);
+  // Wide levels (many fronts fill the device; their trailing updates move
+  // the front through HBM at every step) go two steps at a time: the second
+  // block's column and row take the first step's update on their own, then
+  // one rank-64 trailing update serves both steps, halving that traffic.
+  if (!partial_pivoting && nf > 64) {
+    // One kernel per timed interval (bench.py divides a class's time by its
+    // intervals): L21 / U12 of each step 16 m kb^2, the second block's
+    // column and row 8 kb kb2 (m + m - kb2), the trailing update 8 mn^2 w.
+    auto gemm_timed = [&](double fl, auto&& launch) {
+      timer_begin(KC_GEMM, st);
+      launch();
       SPP_LAUNCH_CHECK();
-      timer_end(KC_PANEL, st, 0.0, 0.0);
+      timer_end(KC_GEMM, st, 0.0, fl);
+    };
+    for (int s = 0; s < steps;) {
+      const int k0 = s * kNB;
+      const bool pair = s + 1 < steps;
+      double fl7a = 0, fl7b = 0, fln = 0, flt = 0;
+      if (g_timer)
+        for (int i = 0; i < nf; ++i) {
+          if (k0 >= hP[i]) continue;
+          const double kb = std::min(kNB, hP[i] - k0), m = hF[i] - k0 - kb;
+          const double kb2 = pair ? std::max(0, std::min(kNB, hP[i] - k0 - kNB)) : 0;
+          const double w = kb + kb2, mn = hF[i] - k0 - w;
+          fl7a += 16.0 * m * kb * kb;
+          fl7b += 16.0 * (m - kb2) * kb2 * kb2;
+          fln += 8.0 * kb * kb2 * (m + (m - kb2));
+          flt += 8.0 * mn * mn * w;
+        }
+      if (s > 0) {
+        timer_begin(KC_PANEL, st);
+        diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, k0, kNB);
+        SPP_LAUNCH_CHECK();
+        timer_end(KC_PANEL, st, 0.0, 0.0);
+      }
+      gemm_timed(fl7a, [&] {
+        gemm_kernel<R, 7><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+      });
+      if (pair) {
+        gemm_timed(fln, [&] {
+          gemm_kernel<R, 3><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+        });
+        timer_begin(KC_PANEL, st);
+        diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, k0 + kNB, kNB);
+        SPP_LAUNCH_CHECK();
+        timer_end(KC_PANEL, st, 0.0, 0.0);
+        gemm_timed(fl7b, [&] {
+          gemm_kernel<R, 7><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s + 1, kNB, tiles);
+        });
+        gemm_timed(flt, [&] {
+          gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s / 2, 2 * kNB,
+                                                                     tiles);
+        });
+        s += 2;
+      } else {
+        gemm_timed(flt, [&] {
+          gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+        });
+        s += 1;
+      }
     }
+  }
+  for (int s = 0; s < steps && (partial_pivoting || nf <= 64); ++s) {
+    const int k0 = s * kNB;
     if (partial_pivoting) {
       timer_begin(KC_PANEL, st);
       // Pivot search over all remaining fully-summed rows of the column.
