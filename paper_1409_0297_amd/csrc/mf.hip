@@ -1213,14 +1213,17 @@ __global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0) {
 
 // ------------------------------------------------------------------ Q apply
 // (Q r)_S = r_S - T_S r_beta(S) for every set instance (Section 2.3).
-__global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2* __restrict__ y, int nrhs, int type) {
+// blockIdx = (instance of the set type, right-hand side x set type, problem);
+// the set types cover disjoint points, so all of them go in one launch.
+__global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2* __restrict__ y, int nrhs) {
   const InstDev& I = mf.inst[blockIdx.z];
   int anchors = 1;
   for (int i = 0; i < I.d; ++i) anchors *= I.m;
   const int anchor = blockIdx.x;
   if (anchor >= anchors) return;
+  const int ntypes = 1 << I.d;
+  const int type = blockIdx.y % ntypes, rhs = blockIdx.y / ntypes;
   const TypeDev& T = I.types[type];
-  const int rhs = blockIdx.y;
   const int64_t base = I.Noff * nrhs + (int64_t)rhs * I.N;
   const double2* rr = r + base;
   double2* yy = y + base;
@@ -1925,12 +1928,12 @@ int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64) {
 
 void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
   const int ntypes = 1 << mf.d;
+  int nb = 0;
+  for (int t = 0; t < ntypes; ++t) nb = std::max(nb, mf.nB_max[t]);
   timer_begin(KC_QAPPLY, st);
-  for (int t = 0; t < ntypes; ++t) {
-    dim3 grid((unsigned)mf.anchors_max, nrhs, mf.ninst);
-    q_apply_kernel<<<grid, 256, sizeof(double2) * mf.nB_max[t], st>>>(mf, r, y, nrhs, t);
-    SPP_LAUNCH_CHECK();
-  }
+  dim3 grid((unsigned)mf.anchors_max, nrhs * ntypes, mf.ninst);
+  q_apply_kernel<<<grid, 256, sizeof(double2) * nb, st>>>(mf, r, y, nrhs);
+  SPP_LAUNCH_CHECK();
   timer_end(KC_QAPPLY, st, 32.0 * mf.Ntot * nrhs, 0.0);
 }
 
