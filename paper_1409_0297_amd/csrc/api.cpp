@@ -531,8 +531,8 @@ void apply_green(spp_factor* F, const double2* f, double2* gout, int nrhs, hipSt
 // whether its result is needed; the tail (the substitution and the cast
 // back) writes z.
 void precond_head(spp_factor* F, const double2* r, int nrhs, hipStream_t st) {
-  q_apply(st, F->mf, r, F->qr, nrhs);
-  if (F->opt.prec != SPP_C128) cast_vectors<float>(st, F->qr, F->xc, (int64_t)nrhs * F->Ntot, 0);
+  if (F->opt.prec == SPP_C128) q_apply(st, F->mf, r, F->qr, nrhs);
+  else q_apply(st, F->mf, r, F->xc, nrhs, true);   // rounded to complex64 on the store
 }
 
 void precond_tail(spp_factor* F, double2* z, int nrhs, hipStream_t st, bool persistent) {

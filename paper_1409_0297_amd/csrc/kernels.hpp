@@ -138,8 +138,9 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, 
 constexpr int kFormLU = 0, kFormInverse = 1, kFormSide = 2;
 int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64);
 
-// y = Q r for every instance of the batch (vectors in the batch layout).
-void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs);
+// y = Q r for every instance of the batch (vectors in the batch layout);
+// y is complex64 (float2) with to_float, else complex128.
+void q_apply(hipStream_t st, const MfDev& mf, const double2* r, void* y, int nrhs, bool to_float = false);
 
 template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void* z,

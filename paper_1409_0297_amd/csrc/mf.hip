@@ -1215,7 +1215,8 @@ __global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0) {
 // (Q r)_S = r_S - T_S r_beta(S) for every set instance (Section 2.3).
 // blockIdx = (instance of the set type, right-hand side x set type, problem);
 // the set types cover disjoint points, so all of them go in one launch.
-__global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2* __restrict__ y, int nrhs) {
+template <typename O>   // output: double2, or float2 for complex64 fronts
+__global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, O* __restrict__ y, int nrhs) {
   const InstDev& I = mf.inst[blockIdx.z];
   int anchors = 1;
   for (int i = 0; i < I.d; ++i) anchors *= I.m;
@@ -1226,7 +1227,7 @@ __global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2*
   const TypeDev& T = I.types[type];
   const int64_t base = I.Noff * nrhs + (int64_t)rhs * I.N;
   const double2* rr = r + base;
-  double2* yy = y + base;
+  O* yy = y + base;
   extern __shared__ double2 rb[];
   for (int j = threadIdx.x; j < T.nB; j += blockDim.x)
     rb[j] = rr[anchor_point(I, anchor, T.off + (T.nS + j) * I.d)];
@@ -1235,7 +1236,8 @@ __global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, double2*
     const int g = anchor_point(I, anchor, T.off + i * I.d);
     double2 s = rr[g];
     for (int j = 0; j < T.nB; ++j) cfms(s, T.Tt[(int64_t)j * T.nS + i], rb[j]);
-    yy[g] = s;
+    yy[g].x = s.x;
+    yy[g].y = s.y;
   }
 }
 
@@ -1926,13 +1928,16 @@ int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64) {
   return nfronts < 512 ? kFormSide : kFormInverse;
 }
 
-void q_apply(hipStream_t st, const MfDev& mf, const double2* r, double2* y, int nrhs) {
+void q_apply(hipStream_t st, const MfDev& mf, const double2* r, void* y, int nrhs, bool to_float) {
   const int ntypes = 1 << mf.d;
   int nb = 0;
   for (int t = 0; t < ntypes; ++t) nb = std::max(nb, mf.nB_max[t]);
   timer_begin(KC_QAPPLY, st);
   dim3 grid((unsigned)mf.anchors_max, nrhs * ntypes, mf.ninst);
-  q_apply_kernel<<<grid, 256, sizeof(double2) * nb, st>>>(mf, r, y, nrhs);
+  if (to_float)
+    q_apply_kernel<float2><<<grid, 256, sizeof(double2) * nb, st>>>(mf, r, static_cast<float2*>(y), nrhs);
+  else
+    q_apply_kernel<double2><<<grid, 256, sizeof(double2) * nb, st>>>(mf, r, static_cast<double2*>(y), nrhs);
   SPP_LAUNCH_CHECK();
   timer_end(KC_QAPPLY, st, 32.0 * mf.Ntot * nrhs, 0.0);
 }
