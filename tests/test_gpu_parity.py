@@ -166,6 +166,25 @@ def test_other_shapes_match_dense(case):
     assert e <= 1e-9, (case, e, iters)
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_wide_level_step_pairs_match_oracle(prec):
+    """Levels of more than 64 fronts take two elimination steps per trailing
+    update (the second block's column and row are updated on their own
+    first).  128^2 with 8-point boxes has 256 leaf fronts of 49 pivots: one
+    pair per front, its second block ragged (32 + 17 pivots)."""
+    from paper_1409_0297_amd import Solver
+    W = workloads.small(128, 2, 8, waves=8.0, bumps=4)
+    f = W.rhs[0]
+    o = pipeline.setup_workload(W)
+    u_o, _, _ = pipeline.solve(o, f, tol=1e-13)
+    S = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, tol=1e-12, max_iter=100, prec=prec)
+    u, iters, relres, code = S.solve(f)
+    S.close()
+    assert code == 0
+    e = rel(cpu(u).reshape(f.shape), np.asarray(u_o).reshape(f.shape))
+    assert e <= 1e-9, (prec, e, iters)
+
+
 def test_constant_medium_converges_in_one_iteration():
     from paper_1409_0297_amd import Solver
     n = 32
