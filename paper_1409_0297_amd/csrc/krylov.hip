@@ -30,7 +30,8 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// partial[(rhs * nblk + blk) * nvec + i] = sum over the block's chunk of conj(V_i) w.
+// partial[(rhs * nvec + i) * nslot + slot] = sum over the wave's chunk of conj(V_i) w
+// (vector-major, so that the final pass reads each vector's partials contiguously).
 // dj (optional): the iteration index j in device memory (graph replays);
 // then nvec = j + 1 and every j-dependent pointer is base + j * jstride.
 __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* __restrict__ V, int64_t vstride, int nvec,
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* _
     for (int q = 0; q < kG; ++q) {
       if (i0 + q >= nvec) break;
       const double2 t = wave_sum(s[q]);
-      if (lane == 0) partial[((int64_t)rhs * nslot + slot) * nvec + i0 + q] = t;
+      if (lane == 0) partial[((int64_t)rhs * nvec + i0 + q) * nslot + slot] = t;
     }
   }
 }
@@ -91,7 +92,9 @@ __global__ void dots_final_kernel(const double2* __restrict__ partial, int nblk,
   const int lane = threadIdx.x & 63;
   if (i >= nvec) return;
   double2 s = cmake<double2>(0, 0);
-  for (int b = lane; b < nblk; b += 64) s = cadd(s, partial[((int64_t)rhs * nblk + b) * nvec + i]);
+  const double2* pr = partial + ((int64_t)rhs * nvec + i) * nblk;
+#pragma unroll 8
+  for (int b = lane; b < nblk; b += 64) s = cadd(s, pr[b]);
   s = wave_sum(s);
   if (lane != 0) return;
   double2* hr = h + (int64_t)rhs * hstride;
@@ -154,6 +157,40 @@ __global__ void __launch_bounds__(64) sumsq_final_kernel(const double* __restric
   const double nrm = sqrt(s);
   norms[rhs] = nrm;
   if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
+}
+
+// v = w / ||w||, the norm summed from the nblk partials by every workgroup
+// (the same sum in the same order everywhere); workgroup 0 also stores the
+// norm and the Hessenberg entry.
+__global__ void __launch_bounds__(kThreads) norm_scale_kernel(const double2* __restrict__ w, double2* __restrict__ v,
+                                                              const double* __restrict__ partial, int nblk,
+                                                              double* norms, double2* h_sub, int hstride, int64_t N,
+                                                              const int* dj, int64_t v_jstride, int64_t h_jstride) {
+  if (dj) {
+    v += *dj * v_jstride;
+    if (h_sub) h_sub += *dj * h_jstride;
+  }
+  const int rhs = blockIdx.y;
+  __shared__ double nrm_s;
+  if (threadIdx.x < 64) {
+    double s = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += partial[(int64_t)rhs * nblk + b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) {
+      const double nrm = sqrt(s);
+      nrm_s = nrm;
+      if (blockIdx.x == 0) {
+        norms[rhs] = nrm;
+        if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const double nrm = nrm_s;
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  v[rhs * N + e] = cscale(w[rhs * N + e], inv);
 }
 
 __global__ void scale_kernel(const double2* __restrict__ w, double2* __restrict__ v, const double* __restrict__ norms,
@@ -305,9 +342,8 @@ void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64
   double* norms = partial + (int64_t)nblk * nrhs;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(w, N, partial);
   SPP_LAUNCH_CHECK();
-  sumsq_final_kernel<<<nrhs, 64, 0, st>>>(partial, nblk, nrhs, norms, h_sub, hstride, dj, h_jstride);
-  SPP_LAUNCH_CHECK();
-  scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, norms, N, dj, v_jstride);
+  norm_scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, partial, nblk, norms, h_sub, hstride,
+                                                                             N, dj, v_jstride, h_jstride);
   SPP_LAUNCH_CHECK();
 }
 
