@@ -391,16 +391,16 @@ __global__ void __launch_bounds__(64) laswp_kernel(MfDev mf, cplx_t<R>* __restri
 // Default factorisation step (block-local pivoting): the pivot of column j is
 // the largest-modulus entry among the rows of the current kb x kb diagonal
 // block (kb <= 32), so the pivot search and elimination of a step stay in one
-// workgroup's LDS.  The block's L and U are written back, their inverses
+// workgroup.  The block's L and U are written back, their inverses
 // Linv_kk, Uinv_kk (kb x kb, column-major) go to dinv, and the other two
 // products of the step become dense, dependency-free MFMA multiplications:
-// L21 = A21 Uinv_kk and U12 = Linv_kk P A12 (gemm_kernel modes 4 and 3).
+// L21 = A21 Uinv_kk and U12 = Linv_kk P A12 (gemm_kernel mode 7).
 constexpr int kDB = 32;
 
 template <typename R>
 struct DiagLds {
-  cplx_t<R> D[kDB][kDB + 1];    // the block to factor; later the inverses
-  cplx_t<R> Lm[kDB][kDB + 1];   // the previous step's L part; later products
+  cplx_t<R> D[kDB][kDB + 1];    // the block to factor
+  cplx_t<R> Lm[kDB][kDB + 1];   // the previous step's L part (rows of this block)
   cplx_t<R> X[kDB][kDB + 1];    // the LU in pivot order
   cplx_t<R> lbuf[2][kDB];       // each row's multiplier of an elimination step
   int rpbuf[2];                 // the step's pivot row
