@@ -916,10 +916,14 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
       kr_update(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, hcol, hrhs);
       kr_dots(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, F->dpart, h2, ld, 0, hcol, hrhs);
       kr_update(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, h2, ld);
-      kr_norm_scale(st, F->wk + o, F->V + (int64_t)(j + 1) * vstride + o, nc, g.N, F->rpart, hcol + (j + 1), hrhs);
+      // a10: the Givens update of the least-squares problem goes with the
+      // normalisation of v_{j+1} (one launch per group).
+      KrGivens gv;
+      gv.H = F->H; gv.hcol = ld; gv.hrhs = hrhs; gv.cs = F->cs; gv.sn = F->sn; gv.g = F->gv;
+      gv.j = j; gv.ldg = ld; gv.resid = F->resid; gv.c0 = c0;
+      kr_norm_scale(st, F->wk + o, F->V + (int64_t)(j + 1) * vstride + o, nc, g.N, F->rpart, hcol + (j + 1), hrhs,
+                    nullptr, 0, 0, gv);
     }
-    // a10: Givens update of the least-squares problem (all columns at once).
-    kr_givens(st, F->H, ld, hrhs, F->cs, F->sn, F->gv, j, cols, ld, F->resid, nullptr);
     SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
     if (head_next) {
       SPP_HIP(hipEventRecord(F->resid_event, st));
@@ -949,9 +953,11 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
       kr_update(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, hbase, hrhs, dj, ld);
       kr_dots(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, F->dpart, h2, ld, 0, hbase, hrhs, dj, 0, ld);
       kr_update(s, F->V + o, vstride, ld, F->wk + o, nc, g.N, h2, ld, dj, 0);
-      kr_norm_scale(s, F->wk + o, F->V + vstride + o, nc, g.N, F->rpart, hbase + 1, hrhs, dj, vstride, ld + 1);
+      KrGivens gv;
+      gv.H = F->H; gv.hcol = ld; gv.hrhs = hrhs; gv.cs = F->cs; gv.sn = F->sn; gv.g = F->gv;
+      gv.j = 0; gv.ldg = ld; gv.resid = F->resid; gv.c0 = c0;
+      kr_norm_scale(s, F->wk + o, F->V + vstride + o, nc, g.N, F->rpart, hbase + 1, hrhs, dj, vstride, ld + 1, gv);
     }
-    kr_givens(s, F->H, ld, hrhs, F->cs, F->sn, F->gv, 0, cols, ld, F->resid, nullptr, dj);
     SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, s));
     kr_set_counter(s, F->dj, 1, true);
   };

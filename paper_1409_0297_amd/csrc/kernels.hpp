@@ -165,9 +165,21 @@ void kr_dots(hipStream_t st, const double2* V, int64_t vstride, int nvec, const 
 void kr_update(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w,
                int nrhs, int64_t N, const double2* h, int hstride, const int* dj = nullptr,
                int64_t h_jstride = 0);
+// Givens step fused into kr_norm_scale (H null: none): for right-hand side r
+// of the launch, column c0 + r of H / cs / sn / g at iteration j (or *dj).
+struct KrGivens {
+  double2* H = nullptr;
+  int hcol = 0, hrhs = 0;
+  double* cs = nullptr;
+  double2* sn = nullptr;
+  double2* g = nullptr;
+  int j = 0, ldg = 0;
+  double* resid = nullptr;
+  int c0 = 0;
+};
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N,
                    double* partial, double2* h_sub, int hstride, const int* dj = nullptr,
-                   int64_t v_jstride = 0, int64_t h_jstride = 0);
+                   int64_t v_jstride = 0, int64_t h_jstride = 0, const KrGivens& gv = KrGivens());
 void kr_givens(hipStream_t st, double2* H, int hcol_stride, int hrhs_stride, double* cs, double2* sn,
                double2* g, int j, int nrhs, int ldg, double* resid, const int* active,
                const int* dj = nullptr);

@@ -159,16 +159,22 @@ __global__ void __launch_bounds__(64) sumsq_final_kernel(const double* __restric
   if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
 }
 
+__device__ inline void givens_column(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
+                                     int ldg, double* resid, int col);
+
 // v = w / ||w||, the norm summed from the nblk partials by every workgroup
 // (the same sum in the same order everywhere); workgroup 0 also stores the
-// norm and the Hessenberg entry.
+// norm and the Hessenberg entry and, with gv.H set, makes the column's
+// Givens rotation (column gv.c0 + right-hand side).
 __global__ void __launch_bounds__(kThreads) norm_scale_kernel(const double2* __restrict__ w, double2* __restrict__ v,
                                                               const double* __restrict__ partial, int nblk,
                                                               double* norms, double2* h_sub, int hstride, int64_t N,
-                                                              const int* dj, int64_t v_jstride, int64_t h_jstride) {
+                                                              const int* dj, int64_t v_jstride, int64_t h_jstride,
+                                                              KrGivens gv) {
   if (dj) {
     v += *dj * v_jstride;
     if (h_sub) h_sub += *dj * h_jstride;
+    gv.j = *dj;
   }
   const int rhs = blockIdx.y;
   __shared__ double nrm_s;
@@ -182,6 +188,7 @@ __global__ void __launch_bounds__(kThreads) norm_scale_kernel(const double2* __r
       if (blockIdx.x == 0) {
         norms[rhs] = nrm;
         if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
+        if (gv.H) givens_column(gv.H, gv.hcol, gv.hrhs, gv.cs, gv.sn, gv.g, gv.j, gv.ldg, gv.resid, gv.c0 + rhs);
       }
     }
   }
@@ -217,16 +224,14 @@ __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s, 
   r = cscale(ph, t);
 }
 
-__global__ void givens_kernel(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
-                              int nrhs, int ldg, double* resid, const int* active, const int* dj) {
-  if (dj) j = *dj;
-  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rhs >= nrhs) return;
-  if (active && !active[rhs]) return;
-  double2* h = H + (int64_t)rhs * hrhs + (int64_t)j * hcol;
-  double* c = cs + (int64_t)rhs * ldg;
-  double2* s = sn + (int64_t)rhs * ldg;
-  double2* gg = g + (int64_t)rhs * ldg;
+// Column `col` of the Hessenberg matrix: apply the earlier rotations, make
+// the new one, update g and the residual estimate |g_{j+1}|.
+__device__ inline void givens_column(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
+                                     int ldg, double* resid, int col) {
+  double2* h = H + (int64_t)col * hrhs + (int64_t)j * hcol;
+  double* c = cs + (int64_t)col * ldg;
+  double2* s = sn + (int64_t)col * ldg;
+  double2* gg = g + (int64_t)col * ldg;
   for (int i = 0; i < j; ++i) {
     const double2 hi = h[i], hi1 = h[i + 1];
     const double2 t = cadd(cscale(hi, c[i]), cmul(s[i], hi1));
@@ -243,7 +248,16 @@ __global__ void givens_kernel(double2* H, int hcol, int hrhs, double* cs, double
   const double2 gj = gg[j];
   gg[j + 1] = cscale(cconjmul(sj, gj), -1.0);
   gg[j] = cscale(gj, cj);
-  resid[rhs] = sqrt(cabs2(gg[j + 1]));
+  resid[col] = sqrt(cabs2(gg[j + 1]));
+}
+
+__global__ void givens_kernel(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
+                              int nrhs, int ldg, double* resid, const int* active, const int* dj) {
+  if (dj) j = *dj;
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  if (active && !active[rhs]) return;
+  givens_column(H, hcol, hrhs, cs, sn, g, j, ldg, resid, rhs);
 }
 
 __global__ void backsolve_kernel(const double2* H, int hcol, int hrhs, const double2* g, int ldg, double2* y,
@@ -337,13 +351,14 @@ void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* par
 
 // v = w / ||w|| and h_sub = ||w|| per right-hand side; norms kept in partial[0..nrhs).
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N, double* partial,
-                   double2* h_sub, int hstride, const int* dj, int64_t v_jstride, int64_t h_jstride) {
+                   double2* h_sub, int hstride, const int* dj, int64_t v_jstride, int64_t h_jstride,
+                   const KrGivens& gv) {
   const int nblk = 256;
   double* norms = partial + (int64_t)nblk * nrhs;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(w, N, partial);
   SPP_LAUNCH_CHECK();
   norm_scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, partial, nblk, norms, h_sub, hstride,
-                                                                             N, dj, v_jstride, h_jstride);
+                                                                             N, dj, v_jstride, h_jstride, gv);
   SPP_LAUNCH_CHECK();
 }
 
