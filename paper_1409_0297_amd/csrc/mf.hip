@@ -776,16 +776,19 @@ template <typename R> constexpr int kGemmWaves = sizeof(R) == 4 ? 4 : 1;
 // One 64 x 64 tile (rows m0.., columns n0..) of C = from_c ? C + sgn A B : sgn A B,
 // complex column-major operands, k restricted to [kbeg, kend).  brow (optional)
 // maps row gk of B to row brow[gk] - brow_off (a row permutation of B).
-template <typename R>
+// Tile shapes BM x BN of the four waves (each wave 32 x 32): 64 x 64 by
+// default, 128 x 32 and 32 x 128 for products with one side of at most 32
+// (L21 / U12 of a step, the second block's column and row of a pair).
+template <typename R, int BM = kBM, int BN = kBN>
 struct GemmLds {
-  cplx_t<R> As[kBK][kBM + 1];
-  cplx_t<R> Bs[kBK][kBN + 1];
+  cplx_t<R> As[kBK][BM + 1];
+  cplx_t<R> Bs[kBK][BN + 1];
 };
 
 // skip > 0: entries with row < skip and column < skip are not stored (a
 // block another workgroup of the same launch owns).
-template <typename R>
-__device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict__ Ap, int lda,
+template <typename R, int BM = kBM, int BN = kBN>
+__device__ inline void gemm_tile_core(GemmLds<R, BM, BN>& L, const cplx_t<R>* __restrict__ Ap, int lda,
                                       const cplx_t<R>* __restrict__ Bp, int ldb, cplx_t<R>* __restrict__ Cp, int ldc,
                                       int m, int n, int k, int m0, int n0, bool from_c, R sgn, int kbeg, int kend,
                                       const int* brow, int brow_off, int skip) {
@@ -794,7 +797,8 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
   auto& As = L.As;
   auto& Bs = L.Bs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  static_assert((BM / 32) * (BN / 32) == 4, "four waves of 32 x 32");
+  const int wm = (wave % (BM / 32)) * 32, wn = (wave / (BM / 32)) * 32;
   // Two real accumulators per 16 x 16 complex block: re = sum (ar br - ai bi),
   // im = sum (ar bi + ai br).  Updates start from C and take A scaled by sgn
   // when it is staged in LDS, so C -= A B needs no extra pass.  The products
@@ -821,33 +825,36 @@ __device__ inline void gemm_tile_core(GemmLds<R>& L, const cplx_t<R>* __restrict
   kend = min(kend, k);
   // Register prefetch: the next stage's operands are loaded while the
   // current stage runs on MFMA (one LDS buffer, two barriers per stage).
-  constexpr int kPer = kBM * kBK / 256;
-  static_assert(kBN * kBK / 256 == kPer, "A and B stages must split alike");
-  C ra[kPer], rb[kPer];
+  constexpr int kPerA = BM * kBK / 256, kPerB = BN * kBK / 256;
+  C ra[kPerA], rb[kPerB];
   const C* __restrict__ Bt = Bp + (int64_t)n0 * ldb;
   auto load_stage = [&](int kk0) {
     const C* __restrict__ At = Ap + (int64_t)kk0 * lda + m0;
     const int kt = kend - kk0;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
+    for (int u = 0; u < kPerA; ++u) {
       const int e = threadIdx.x + 256 * u;
-      {
-        const int row = e % kBM, kk = e / kBM;
-        ra[u] = (row < mt && kk < kt) ? At[kk * lda + row] : cmake<C>(0, 0);
-      }
-      {
-        const int kk = e % kBK, col = e / kBK;
-        const int br = brow ? brow[kk < kt ? kk0 + kk : 0] - brow_off : kk0 + kk;
-        rb[u] = (kk < kt && col < nt) ? Bt[col * ldb + br] : cmake<C>(0, 0);
-      }
+      const int row = e % BM, kk = e / BM;
+      ra[u] = (row < mt && kk < kt) ? At[kk * lda + row] : cmake<C>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPerB; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int kk = e % kBK, col = e / kBK;
+      const int br = brow ? brow[kk < kt ? kk0 + kk : 0] - brow_off : kk0 + kk;
+      rb[u] = (kk < kt && col < nt) ? Bt[col * ldb + br] : cmake<C>(0, 0);
     }
   };
   if (kbeg < kend) load_stage(kbeg);
   for (int kk0 = kbeg; kk0 < kend; kk0 += kBK) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
+    for (int u = 0; u < kPerA; ++u) {
       const int e = threadIdx.x + 256 * u;
-      As[e / kBM][e % kBM] = cmake<C>(sgn * ra[u].x, sgn * ra[u].y);
+      As[e / BM][e % BM] = cmake<C>(sgn * ra[u].x, sgn * ra[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < kPerB; ++u) {
+      const int e = threadIdx.x + 256 * u;
       Bs[e % kBK][e / kBK] = rb[u];
     }
     __syncthreads();
@@ -900,6 +907,7 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 //           (the rest), P the step's row order from the diagonal-block LU,
 //           applied while loading A12.  Both overwrite their input block;
 //           every workgroup reads all of its own block before writing it.
+//   mode 6: as mode 7 on 64 x 64 tiles
 //   mode 3: the next block's column and row take this step's update (a pair
 //           of steps whose trailing update then goes as one rank-2kb product)
 // NEXT (mode 0 only): a workgroup with bx < 0 factors the next diagonal
@@ -910,8 +918,14 @@ template <typename R, bool NEXT, int mode>
 __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                  cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m, int bx, int by) {
   using C = cplx_t<R>;
-  constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > sizeof(GemmLds<R>) ? sizeof(DiagLds<R>) : sizeof(GemmLds<R>))
-                               : sizeof(GemmLds<R>);
+  // Modes 3 and 7: products with one side of at most 32 take the 128 x 32
+  // (tall) or 32 x 128 (wide) tile; tiles_m then counts 128-row tiles.
+  // Mode 6 is mode 7 on 64 x 64 tiles (twice the workgroups, each with half
+  // its waves idle): shorter launches for levels of few fronts, where the
+  // step's latency rather than its throughput counts.
+  constexpr bool kNarrow = mode == 3 || mode == 7;
+  constexpr size_t kGemm = kNarrow ? sizeof(GemmLds<R, 128, 32>) : sizeof(GemmLds<R>);
+  constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > kGemm ? sizeof(DiagLds<R>) : kGemm) : kGemm;
   __shared__ __align__(16) unsigned char lds[kLds];
   const FrontDev f = mf.fronts[f0 + by];
   int k0, kb;
@@ -952,7 +966,7 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
       Bp = base + (int64_t)(k0 + kb + kb2) * F + k0; ldb = F;
       Cp = base + (int64_t)(k0 + kb + kb2) * F + (k0 + kb); ldc = F;
     }
-  } else if constexpr (mode == 7) {
+  } else if constexpr (mode == 7 || mode == 6) {
     const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
     const C* Ui = Li + kDB * kDB;
     assign = true;
@@ -992,10 +1006,24 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
       Cp = XU + (int64_t)k0 * p; ldc = p;
     }
   }
-  const int m0 = tm * kBM, n0 = tn * kBN;
-  if (m <= 0 || n <= 0 || k <= 0 || m0 >= m || n0 >= n) return;
-  gemm_tile_core<R>(*reinterpret_cast<GemmLds<R>*>(lds), Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign,
-                    assign ? R(1) : R(-1), 0, k, brow, 0, skip);
+  if constexpr (kNarrow) {
+    if (bx < tiles_m) {   // n <= 32: 128-row tiles
+      const int m0 = tm * 128;
+      if (m <= 0 || n <= 0 || k <= 0 || m0 >= m) return;
+      gemm_tile_core<R, 128, 32>(*reinterpret_cast<GemmLds<R, 128, 32>*>(lds), Ap, lda, Bp, ldb, Cp, ldc, m, n, k,
+                                 m0, 0, !assign, assign ? R(1) : R(-1), 0, k, brow, 0, 0);
+    } else {              // m <= 32: 128-column tiles
+      const int n0 = tn * 128;
+      if (m <= 0 || n <= 0 || k <= 0 || n0 >= n) return;
+      gemm_tile_core<R, 32, 128>(*reinterpret_cast<GemmLds<R, 32, 128>*>(lds), Ap, lda, Bp, ldb, Cp, ldc, m, n, k,
+                                 0, n0, !assign, assign ? R(1) : R(-1), 0, k, brow, 0, 0);
+    }
+  } else {
+    const int m0 = tm * kBM, n0 = tn * kBN;
+    if (m <= 0 || n <= 0 || k <= 0 || m0 >= m || n0 >= n) return;
+    gemm_tile_core<R>(*reinterpret_cast<GemmLds<R>*>(lds), Ap, lda, Bp, ldb, Cp, ldc, m, n, k, m0, n0, !assign,
+                      assign ? R(1) : R(-1), 0, k, brow, 0, skip);
+  }
 }
 
 template <typename R, int MODE>
@@ -1719,6 +1747,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   }
   const int steps = (maxP + kNB - 1) / kNB;
   const int tiles = (int)ceil_div(maxF, kBM);
+  const int tiles128 = (int)ceil_div(maxF, 128);   // tall / wide tiles of modes 3 and 7
   if (!partial_pivoting && steps > 0) {
     // First diagonal block; each later one is factored inside the previous
     // step's trailing-update launch (levels of few fronts) or on its own.
@@ -1763,18 +1792,18 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
         timer_end(KC_PANEL, st, 0.0, 0.0);
       }
       gemm_timed(fl7a, [&] {
-        gemm_kernel<R, 7><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+        gemm_kernel<R, 7><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128);
       });
       if (pair) {
         gemm_timed(fln, [&] {
-          gemm_kernel<R, 3><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+          gemm_kernel<R, 3><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128);
         });
         timer_begin(KC_PANEL, st);
         diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, k0 + kNB, kNB);
         SPP_LAUNCH_CHECK();
         timer_end(KC_PANEL, st, 0.0, 0.0);
         gemm_timed(fl7b, [&] {
-          gemm_kernel<R, 7><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s + 1, kNB, tiles);
+          gemm_kernel<R, 7><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s + 1, kNB, tiles128);
         });
         gemm_timed(flt, [&] {
           gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s / 2, 2 * kNB,
@@ -1819,7 +1848,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
           fl += 16.0 * m * kb * kb;
         }
       timer_begin(KC_GEMM, st);
-      gemm_kernel<R, 7><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+      gemm_kernel<R, 6><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
       timer_end(KC_GEMM, st, 0.0, fl);
     }
     SPP_LAUNCH_CHECK();
