@@ -355,6 +355,7 @@ struct spp_factor {
   double *cs = nullptr, *rpart = nullptr, *resid = nullptr, *norms = nullptr;
   int* kvec = nullptr;
   double* h_resid = nullptr;   // pinned host copy of residual estimates
+  double* h_resid_dev = nullptr;   // its device alias (written by the Givens step)
   size_t h_resid_bytes = 0;
   hipEvent_t resid_event = nullptr;   // marks the residual estimates' copy
   spp_stats_t stats{};
@@ -469,7 +470,7 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
                   (void*)F->dpart, (void*)F->cs, (void*)F->rpart, (void*)F->resid, (void*)F->norms, (void*)F->kvec,
                   (void*)F->gsave, (void*)F->vfix, (void*)F->zfix, (void*)F->dj})
     F->dfree(p);
-  if (F->h_resid) { mem_put(F->h_resid, F->h_resid_bytes, kPinnedDev); F->h_resid = nullptr; }
+  if (F->h_resid) { mem_put(F->h_resid, F->h_resid_bytes, kPinnedDev); F->h_resid = nullptr; F->h_resid_dev = nullptr; }
   const int64_t N = F->Ntot;
   const int cols = total_cols(F, r);
   F->tmp = F->dalloc<double2>((size_t)r * N);
@@ -503,6 +504,7 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
   F->kvec = F->dalloc<int>(cols);
   F->h_resid_bytes = sizeof(double) * cols;
   F->h_resid = static_cast<double*>(mem_get(F->h_resid_bytes, true));
+  SPP_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&F->h_resid_dev), F->h_resid, 0));
   F->cap_rhs = r;
   F->cap_iter = it;
 }
@@ -920,11 +922,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
       // normalisation of v_{j+1} (one launch per group).
       KrGivens gv;
       gv.H = F->H; gv.hcol = ld; gv.hrhs = hrhs; gv.cs = F->cs; gv.sn = F->sn; gv.g = F->gv;
-      gv.j = j; gv.ldg = ld; gv.resid = F->resid; gv.c0 = c0;
+      gv.j = j; gv.ldg = ld; gv.resid = F->resid; gv.resid_host = F->h_resid_dev; gv.c0 = c0;
       kr_norm_scale(st, F->wk + o, F->V + (int64_t)(j + 1) * vstride + o, nc, g.N, F->rpart, hcol + (j + 1), hrhs,
                     nullptr, 0, 0, gv);
     }
-    SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
     if (head_next) {
       SPP_HIP(hipEventRecord(F->resid_event, st));
       precond_head(F, F->V + (int64_t)(j + 1) * vstride, nrhs, st);

@@ -175,6 +175,7 @@ struct KrGivens {
   double2* g = nullptr;
   int j = 0, ldg = 0;
   double* resid = nullptr;
+  double* resid_host = nullptr;   // optional: device alias of pinned host memory
   int c0 = 0;
 };
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N,

@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(64) sumsq_final_kernel(const double* __restric
 }
 
 __device__ inline void givens_column(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
-                                     int ldg, double* resid, int col);
+                                     int ldg, double* resid, int col, double* resid_host = nullptr);
 
 // v = w / ||w||, the norm summed from the nblk partials by every workgroup
 // (the same sum in the same order everywhere); workgroup 0 also stores the
@@ -188,7 +188,9 @@ __global__ void __launch_bounds__(kThreads) norm_scale_kernel(const double2* __r
       if (blockIdx.x == 0) {
         norms[rhs] = nrm;
         if (h_sub) h_sub[(int64_t)rhs * hstride] = cmake<double2>(nrm, 0.0);
-        if (gv.H) givens_column(gv.H, gv.hcol, gv.hrhs, gv.cs, gv.sn, gv.g, gv.j, gv.ldg, gv.resid, gv.c0 + rhs);
+        if (gv.H)
+          givens_column(gv.H, gv.hcol, gv.hrhs, gv.cs, gv.sn, gv.g, gv.j, gv.ldg, gv.resid, gv.c0 + rhs,
+                        gv.resid_host);
       }
     }
   }
@@ -227,7 +229,7 @@ __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s, 
 // Column `col` of the Hessenberg matrix: apply the earlier rotations, make
 // the new one, update g and the residual estimate |g_{j+1}|.
 __device__ inline void givens_column(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
-                                     int ldg, double* resid, int col) {
+                                     int ldg, double* resid, int col, double* resid_host) {
   double2* h = H + (int64_t)col * hrhs + (int64_t)j * hcol;
   double* c = cs + (int64_t)col * ldg;
   double2* s = sn + (int64_t)col * ldg;
@@ -248,7 +250,9 @@ __device__ inline void givens_column(double2* H, int hcol, int hrhs, double* cs,
   const double2 gj = gg[j];
   gg[j + 1] = cscale(cconjmul(sj, gj), -1.0);
   gg[j] = cscale(gj, cj);
-  resid[col] = sqrt(cabs2(gg[j + 1]));
+  const double rj = sqrt(cabs2(gg[j + 1]));
+  resid[col] = rj;
+  if (resid_host) resid_host[col] = rj;   // read by the host after the launch's event
 }
 
 __global__ void givens_kernel(double2* H, int hcol, int hrhs, double* cs, double2* sn, double2* g, int j,
