@@ -1464,6 +1464,27 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   extern __shared__ unsigned char smem[];
   C* wv = reinterpret_cast<C*>(smem);   // F x NR: the front vector
   C* y = wv + F * NR;                   // p x NR: permuted pivot part, solved in place
+  // Each thread's entries of the next diagonal block (strictly lower part),
+  // loaded while the previous block's strip update runs and stored to LDS
+  // after it (workgroups of 256 threads).
+  constexpr int kDP = BS * BS / 256;
+  C dpre[kDP];
+  auto fetch_d = [&](int b) {
+    const int n = min(BS, p - b);
+#pragma unroll
+    for (int u = 0; u < kDP; ++u) {
+      const int t = threadIdx.x + 256 * u, jj = t / BS, i = t - jj * BS;
+      dpre[u] = (i < n && jj < n && i > jj) ? A[(int64_t)(b + jj) * F + b + i] : cmake<C>(0, 0);
+    }
+  };
+  auto store_d = [&] {
+#pragma unroll
+    for (int u = 0; u < kDP; ++u) {
+      const int t = threadIdx.x + 256 * u, jj = t / BS, i = t - jj * BS;
+      D[i][jj] = dpre[u];
+    }
+  };
+  fetch_d(0);
   for (int t = threadIdx.x; t < F * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
     wv[t] = (i < p && r < nr) ? xi[(int64_t)(r0 + r) * I.N + idx[i]] : cmake<C>(0, 0);
@@ -1487,15 +1508,11 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
     const int i = t / NR, r = t - i * NR;
     y[t] = wv[perm[i] * NR + r];
   }
+  store_d();
   __syncthreads();
   const int lane = threadIdx.x & 63;
   for (int b0 = 0; b0 < p; b0 += BS) {
     const int bs = min(BS, p - b0);
-    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
-      const int jj = t / BS, i = t - jj * BS;
-      D[i][jj] = (i < bs && jj < bs && i > jj) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
-    }
-    __syncthreads();
     if (threadIdx.x < 64) {
       C yi[NR];
 #pragma unroll
@@ -1514,6 +1531,7 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
         for (int r = 0; r < NR; ++r) y[(b0 + lane) * NR + r] = yi[r];
     }
     __syncthreads();
+    if (b0 + BS < p) fetch_d(b0 + BS);
     // The block's columns applied to every row below it: the rest of the
     // pivot block (y) and the boundary rows (w_bnd -= L21 y, a strip at a time).
     for (int i = b0 + bs + threadIdx.x; i < F; i += blockDim.x) {
@@ -1530,6 +1548,7 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
 #pragma unroll
       for (int r = 0; r < NR; ++r) v[r] = acc[r];
     }
+    if (b0 + BS < p) store_d();   // (the solve has read this block's D)
     __syncthreads();
   }
   for (int t = threadIdx.x; t < F * NR; t += blockDim.x) {
@@ -1558,6 +1577,27 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   extern __shared__ unsigned char smem[];
   C* y = reinterpret_cast<C*>(smem);    // p x NR
   C* xb = y + p * NR;                   // K x NR: solution at the boundary points
+  // Each thread's entries of the next diagonal block (upper part with the
+  // diagonal), loaded while the previous step runs and stored to LDS after it
+  // (workgroups of 256 threads).
+  constexpr int kDP = BS * BS / 256;
+  C dpre[kDP];
+  auto fetch_d = [&](int b) {
+    const int n = min(BS, p - b);
+#pragma unroll
+    for (int u = 0; u < kDP; ++u) {
+      const int t = threadIdx.x + 256 * u, jj = t / BS, i = t - jj * BS;
+      dpre[u] = (i < n && jj < n && i <= jj) ? A[(int64_t)(b + jj) * F + b + i] : cmake<C>(0, 0);
+    }
+  };
+  auto store_d = [&] {
+#pragma unroll
+    for (int u = 0; u < kDP; ++u) {
+      const int t = threadIdx.x + 256 * u, jj = t / BS, i = t - jj * BS;
+      D[i][jj] = dpre[u];
+    }
+  };
+  fetch_d(((p - 1) / BS) * BS);
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
     const int i = t / NR, r = t - i * NR;
     y[t] = (r < nr) ? z[i * nrhs + r0 + r] : cmake<C>(0, 0);
@@ -1581,15 +1621,11 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
 #pragma unroll
     for (int r = 0; r < NR; ++r) y[i * NR + r] = acc[r];
   }
+  store_d();
   __syncthreads();
   const int lane = threadIdx.x & 63;
   for (int b0 = ((p - 1) / BS) * BS; b0 >= 0; b0 -= BS) {
     const int bs = min(BS, p - b0);
-    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
-      const int jj = t / BS, i = t - jj * BS;
-      D[i][jj] = (i < bs && jj < bs && i <= jj) ? A[(int64_t)(b0 + jj) * F + b0 + i] : cmake<C>(0, 0);
-    }
-    __syncthreads();
     if (threadIdx.x < 64) {
       C yi[NR];
 #pragma unroll
@@ -1614,6 +1650,7 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
         for (int r = 0; r < NR; ++r) y[(b0 + lane) * NR + r] = yi[r];
     }
     __syncthreads();
+    if (b0 > 0) fetch_d(b0 - BS);
     for (int i = threadIdx.x; i < b0; i += blockDim.x) {
       C acc[NR];
 #pragma unroll
@@ -1627,6 +1664,7 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
 #pragma unroll
       for (int r = 0; r < NR; ++r) y[i * NR + r] = acc[r];
     }
+    if (b0 > 0) store_d();   // (the solve has read this block's D)
     __syncthreads();
   }
   for (int t = threadIdx.x; t < p * NR; t += blockDim.x) {
