@@ -1521,7 +1521,8 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
 #pragma unroll
       for (int jj = 0; jj < BS; ++jj) {
         if (jj < bs) {
-          const C l = (lane > jj && lane < bs) ? D[lane][jj] : cmake<C>(0, 0);
+          // D is zero on and above the diagonal and below row bs.
+          const C l = (lane < BS) ? D[lane][jj] : cmake<C>(0, 0);
 #pragma unroll
           for (int r = 0; r < NR; ++r) cfms(yi[r], l, lane_read(yi[r], jj));
         }
@@ -1573,7 +1574,8 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   const InstDev& I = mf.inst[f.inst];
   C* xo = xout + I.Noff * nrhs;
   const int nr = min(NR, nrhs - r0);
-  __shared__ C D[BS][BS + 1];
+  __shared__ C D[BS][BS + 1];   // strictly upper part of the diagonal block
+  __shared__ C Dd[BS];          // its diagonal
   extern __shared__ unsigned char smem[];
   C* y = reinterpret_cast<C*>(smem);    // p x NR
   C* xb = y + p * NR;                   // K x NR: solution at the boundary points
@@ -1594,7 +1596,8 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
 #pragma unroll
     for (int u = 0; u < kDP; ++u) {
       const int t = threadIdx.x + 256 * u, jj = t / BS, i = t - jj * BS;
-      D[i][jj] = dpre[u];
+      D[i][jj] = (i == jj) ? cmake<C>(0, 0) : dpre[u];
+      if (i == jj) Dd[i] = dpre[u];
     }
   };
   fetch_d(((p - 1) / BS) * BS);
@@ -1634,14 +1637,14 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
 #pragma unroll
       for (int jj = BS - 1; jj >= 0; --jj) {
         if (jj < bs) {
-          const C u = (lane < jj) ? D[lane][jj] : cmake<C>(0, 0);
-          const C d = D[jj][jj];
+          const C u = (lane < BS) ? D[lane][jj] : cmake<C>(0, 0);   // zero from the diagonal down
+          const C d = Dd[jj];
           const C dinv = cabs2(d) > 0 ? crecip(d) : cmake<C>(0, 0);
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const C xj = cmul(lane_read(yi[r], jj), dinv);
             if (lane == jj) yi[r] = xj;
-            if (lane < jj) cfms(yi[r], u, xj);
+            cfms(yi[r], u, xj);
           }
         }
       }
