@@ -1375,11 +1375,34 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   // first (their gathers go through perm / idx), so the main loop only streams
   // the matrix, several loads in flight per lane.
   const int64_t coff = (mode == 1) ? p + row : (mode == 2) ? (int64_t)p * F + row : row;
+  auto entry = [&](int j) {
+    const bool use = live && j < jhi && ((mode == 0 || mode == 4) ? j < row : (mode == 3 || mode == 5) ? j >= row : true);
+    return use ? A[coff + (int64_t)j * F] : cmake<C>(0, 0);
+  };
+  // Each wave's first kPre columns are loaded before the first tile's vector
+  // entries are gathered, so that the two latencies overlap.
+  constexpr int kPre = 8 / (NR == 4 ? 2 : 1) / (sizeof(R) == 8 ? 2 : 1);
+  C apre[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) apre[u] = entry(jlo + grp + 4 * u);
+  const int orow = ((mode == 3 || mode == 5) && live) ? idx[row] : 0;
+  // Mode 4 without split: the finishing step's gathered entries of the
+  // tile's rows are staged with the first tile (by the threads beyond its
+  // columns), not gathered after the products.
+  const bool fin4 = mode == 4 && nchunks == 1;
   constexpr int kVT = 256;
   __shared__ C vs[kVT][NR];
-  for (int jt = jlo; jt < jhi; jt += kVT) {
-    const int jn = min(kVT, jhi - jt);
-    for (int t = threadIdx.x; t < jn * NR; t += 256) {
+  __shared__ C gs[64][NR];
+  for (int jt = jlo; jt < jhi || (fin4 && jt == jlo); jt += kVT) {
+    const int jn = max(0, min(kVT, jhi - jt));
+    const int nst = jn * NR + ((fin4 && jt == jlo) ? 64 * NR : 0);
+    for (int t = threadIdx.x; t < nst; t += 256) {
+      if (t >= jn * NR) {
+        const int u = t - jn * NR, l = u / NR, r = u - l * NR, i = row0 + l;
+        if (r0 + r < nrhs && i < nrows)
+          gs[l][r] = gathered<R>(mf, f, W, xin + I.Noff * nrhs, NI, nrhs, r0 + r, i < p ? perm[i] : i);
+        continue;
+      }
       const int jj = t / NR, r = t - jj * NR, j = jt + jj;
       C v = cmake<C>(0, 0);
       if (r0 + r < nrhs) {
@@ -1392,11 +1415,20 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
       vs[jj][r] = v;
     }
     __syncthreads();
+    int jj0 = grp;
+    if (jt == jlo) {
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int jj = grp + 4 * u;
+        if (jj < jn)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma(acc[r], apre[u], vs[jj][r]);
+      }
+      jj0 = grp + 4 * kPre;
+    }
 #pragma unroll 8
-    for (int jj = grp; jj < jn; jj += 4) {
-      const int j = jt + jj;
-      const bool use = live && ((mode == 0 || mode == 4) ? j < row : (mode == 3 || mode == 5) ? j >= row : true);
-      const C a = use ? A[coff + (int64_t)j * F] : cmake<C>(0, 0);
+    for (int jj = jj0; jj < jn; jj += 4) {
+      const C a = entry(jt + jj);
 #pragma unroll
       for (int r = 0; r < NR; ++r) cfma(acc[r], a, vs[jj][r]);
     }
@@ -1415,9 +1447,9 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
     if (nchunks > 1) {
       partial[(((int64_t)blockIdx.y * nchunks + chunk) * prow + row) * nrhs + rr] = s;
     } else if (mode == 4 && row < p) {
-      z[row * nrhs + rr] = cadd(s, gathered<R>(mf, f, W, xin + I.Noff * nrhs, NI, nrhs, rr, perm[row]));
+      z[row * nrhs + rr] = cadd(s, gs[lane][r]);
     } else if (mode == 4) {
-      w[row * nrhs + rr] = csub(gathered<R>(mf, f, W, xin + I.Noff * nrhs, NI, nrhs, rr, row), s);
+      w[row * nrhs + rr] = csub(gs[lane][r], s);
     } else if (mode == 0) {
       z[row * nrhs + rr] = cadd(s, w[perm[row] * nrhs + rr]);
     } else if (mode == 1) {
@@ -1427,7 +1459,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
       C& d = z[row * nrhs + rr];
       d = csub(d, s);
     } else {
-      xo[(int64_t)rr * NI + idx[row]] = s;
+      xo[(int64_t)rr * NI + orow] = s;
     }
   }
 }
@@ -1730,17 +1762,20 @@ __global__ void gemv_finish_kernel(MfDev mf, cplx_t<R>* __restrict__ W, cplx_t<R
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows * nrhs) return;
   const int row = t / nrhs, rr = t - row * nrhs;
-  C s = cmake<C>(0, 0);
-  for (int c = 0; c < nchunks; ++c)
-    s = cadd(s, partial[(((int64_t)blockIdx.y * nchunks + c) * prow + row) * nrhs + rr]);
   C* w = W + f.voff * nrhs;
   C* z = Z + f.voff * nrhs;
   const InstDev& I = mf.inst[f.inst];
+  // (mode 4: the gathered entry's dependent loads go out before the partial sums)
+  const C g = (mode == 4) ? gathered<R>(mf, f, W, xin + I.Noff * nrhs, I.N, nrhs, rr,
+                                        row < f.p ? mf.perm[f.perm + row] : row)
+                          : cmake<C>(0, 0);
+  C s = cmake<C>(0, 0);
+  for (int c = 0; c < nchunks; ++c)
+    s = cadd(s, partial[(((int64_t)blockIdx.y * nchunks + c) * prow + row) * nrhs + rr]);
   if (mode == 4 && row < f.p) {
-    z[row * nrhs + rr] =
-        cadd(s, gathered<R>(mf, f, W, xin + I.Noff * nrhs, I.N, nrhs, rr, mf.perm[f.perm + row]));
+    z[row * nrhs + rr] = cadd(s, g);
   } else if (mode == 4) {
-    w[row * nrhs + rr] = csub(gathered<R>(mf, f, W, xin + I.Noff * nrhs, I.N, nrhs, rr, row), s);
+    w[row * nrhs + rr] = csub(g, s);
   } else if (mode == 0) {
     z[row * nrhs + rr] = cadd(s, w[mf.perm[f.perm + row] * nrhs + rr]);
   } else if (mode == 1) {
