@@ -348,7 +348,7 @@ class BatchSolver:
     """
 
     def __init__(self, problems, prec: str = "c128", order: str = "octree", tol: float = 1e-10,
-                 max_iter: int = 200, timing: bool = False, graphs: bool = False):
+                 max_iter: int = 200, timing: bool = False, graphs: bool = False, persistent: bool = False):
         import torch
         self.torch = torch
         self.sizes = [p["n"] ** p["d"] for p in problems]
@@ -367,7 +367,8 @@ class BatchSolver:
         op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,
                          order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
                          tol=tol, max_iter=max_iter,
-                         flags=(SPP_F_TIMING if timing else 0) | (SPP_F_GRAPHS if graphs else 0))
+                         flags=(SPP_F_TIMING if timing else 0) | (SPP_F_GRAPHS if graphs else 0)
+                         | (SPP_F_PERSISTENT if persistent else 0))
         self.handle = spp_setup_batch(pbs, op, torch.cuda.current_stream().cuda_stream)
 
     def _stream(self) -> int:

@@ -143,7 +143,7 @@ def test_unpreconditioned_and_mixed_precision_reach_same_solution():
         s.close()
 
 
-@pytest.mark.parametrize("case", ["3d_bisect", "3d_octree", "schrodinger", "radix3"])
+@pytest.mark.parametrize("case", ["3d_bisect", "3d_octree", "schrodinger", "schrodinger3d", "radix3"])
 def test_other_shapes_match_dense(case):
     from paper_1409_0297_amd import Solver
     if case.startswith("3d"):
@@ -151,6 +151,9 @@ def test_other_shapes_match_dense(case):
         order = "bisect" if case == "3d_bisect" else "octree"
     elif case == "schrodinger":
         W = workloads.schrodinger_workload(32, 2, 4, 8)
+        order = "octree"
+    elif case == "schrodinger3d":
+        W = workloads.schrodinger_workload(12, 3, 2, 3)
         order = "octree"
     else:
         W = workloads.small(48, 2, 6, waves=5.0, bumps=4)

@@ -1,0 +1,77 @@
+"""The batched 2D Schroedinger family at full size (Section 3.2's equation
+on a lattice of Gaussian wells): 48 instances, 16 each of n = 128, 192 and
+256 (ell = n / 8, b = n / 16), each with its own wells, energy and 16
+Gaussian sources, factored and solved together in one batch.
+
+Every one of the 768 solves must reach the FGMRES tolerance; the solutions
+of three instances (one per size) for their first and last sources must
+match the oracle's (FGMRES to 1e-13, stored at seeded grid points by
+tests/golden/make_schrodinger_batch_samples.py) to 1e-8, and their
+differential residuals are checked with the oracle's spectral operator.
+The complex64 case runs as the family is meant to run (cooperative launches
+for the many-front levels, graph-captured iterations); the complex128 case
+with plain launches.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pipeline, spectral
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "schrodinger_batch_u_samples.txt")
+NRHS = 16
+
+
+def load_samples():
+    out = {}
+    with open(GOLD) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            i, r, j, re, im = line.split()
+            out.setdefault((int(i), int(r)), ([], []))
+            out[(int(i), int(r))][0].append(int(j))
+            out[(int(i), int(r))][1].append(complex(float(re), float(im)))
+    return {k: (np.array(a), np.array(b)) for k, (a, b) in out.items()}
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return workloads.schrodinger_batch(nrhs=NRHS)
+
+
+@pytest.mark.parametrize("prec,fast", [("c64", True), ("c128", False)])
+def test_schrodinger_batch_full_size(batch, prec, fast):
+    from paper_1409_0297_amd import BatchSolver
+    probs = [dict(kind=W.kind, n=W.n, d=W.d, b=W.b, coeff=W.coeff, ell=W.ell, energy=W.energy) for W in batch]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = BatchSolver(probs, prec=prec, tol=1e-10, max_iter=40, graphs=fast, persistent=fast)
+    us, iters, relres, code = B.solve([W.rhs.reshape(NRHS, -1) for W in batch])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    shifts = [B.shift(i) for i in range(3)]
+    B.close()
+    it = np.concatenate([np.asarray(x) for x in iters])
+    rr = np.concatenate([np.asarray(x) for x in relres])
+    print(f"{prec}: {len(batch) * NRHS} solves in {dt:.3f} s (setup + solve), "
+          f"iterations {it.min()}-{it.max()}, max relres {rr.max():.2e}")
+    assert code == 0
+    assert rr.max() <= 1e-10, rr.max()
+    assert 1 <= it.min() and it.max() < 40
+    gold = load_samples()
+    for (i, r), (idx, ref) in sorted(gold.items()):
+        W = batch[i]
+        u = us[i][r].cpu().numpy().reshape((W.n,) * W.d)
+        err = np.linalg.norm(u.reshape(-1)[idx] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-8, (prec, i, r, err)
+        s, q, moves = pipeline.coefficients(W.kind, W.n, W.d, W.coeff, ell=W.ell, energy=W.energy)
+        assert shifts[i][0] == pytest.approx(s, rel=1e-12) and shifts[i][1] == moves
+        dres = np.linalg.norm(W.rhs[r] - spectral.apply_differential(u, W.d, s, q)) / np.linalg.norm(W.rhs[r])
+        assert dres <= 1e-7, (prec, i, r, dres)

@@ -117,11 +117,11 @@ def test_3d_and_schrodinger_reach_dense_solution():
     ref = pipeline.dense_solution(W.kind, W.n, W.d, W.coeff, W.rhs[0], W.omega)
     u, it, _ = pipeline.solve(o, W.rhs[0], tol=1e-12)
     assert np.linalg.norm(u - ref) <= 1e-9 * np.linalg.norm(ref)
-    S = workloads.schrodinger_workload(32, 2, 4, 8)
-    o = pipeline.setup_workload(S)
-    ref = pipeline.dense_solution(S.kind, S.n, S.d, S.coeff, S.rhs[0], ell=S.ell, energy=S.energy)
-    u, it, _ = pipeline.solve(o, S.rhs[0], tol=1e-12)
-    assert np.linalg.norm(u - ref) <= 1e-9 * np.linalg.norm(ref)
+    for S in (workloads.schrodinger_workload(32, 2, 4, 8), workloads.schrodinger_workload(12, 3, 2, 3)):
+        o = pipeline.setup_workload(S)
+        ref = pipeline.dense_solution(S.kind, S.n, S.d, S.coeff, S.rhs[0], ell=S.ell, energy=S.energy)
+        u, it, _ = pipeline.solve(o, S.rhs[0], tol=1e-12)
+        assert np.linalg.norm(u - ref) <= 1e-9 * np.linalg.norm(ref), S.name
 
 
 def paper_rows():

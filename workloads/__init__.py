@@ -120,12 +120,16 @@ def gaussian_well_lattice(n: int, d: int, ell: int, seed: int, width: float = 0.
     E = float(rng.uniform(energy[0], energy[1]))
     idx = np.stack(np.meshgrid(*([np.arange(ell)] * d), indexing="ij"), axis=-1).reshape(-1, d)
     centres = idx + 0.5 + jit
-    y = grid_points(n, d) * ell
-    V = np.zeros((n,) * d)
-    # Only wells within a few widths contribute; the loop stays cheap at the
-    # sizes used (<= 32^2 wells).
-    for Di, ci in zip(D, centres):
-        V -= Di * np.exp(-periodic_sq_dist(y, ci, period=float(ell)) / (2.0 * width * width))
+    # The periodic squared distance is a sum over axes, so each well is a
+    # product of one Gaussian factor per axis: V = -sum_i D_i prod_k E_k[i, x_k].
+    y = np.arange(n, dtype=np.float64) / n * ell
+    factors = []
+    for k in range(d):
+        delta = y[None, :] - centres[:, k:k + 1]
+        delta = delta - float(ell) * np.round(delta / float(ell))
+        factors.append(np.exp(-(delta * delta) / (2.0 * width * width)))
+    sub = "abcdefgh"[:d]
+    V = -np.einsum("i," + ",".join("i" + c for c in sub) + "->" + sub, D, *factors)
     return SchrodingerLattice(n=n, d=d, ell=float(ell), energy=E, V=V, depths=D, centres=centres)
 
 
@@ -183,3 +187,16 @@ def schrodinger_workload(n: int, d: int, ell: int, b: int, nrhs: int = 1, instan
     rhs = gaussian_sources(n, d, nrhs, 1.0 / 32, seed_for(config, instance) + 500)
     return Workload(name=f"schrodinger{d}d_n{n}_l{ell}", kind="schrodinger", n=n, d=d, b=b,
                     ell=float(ell), energy=lat.energy, coeff=lat.V, rhs=rhs, tol=tol)
+
+
+def schrodinger_batch(nrhs: int = 16, per_size: int = 16) -> list:
+    """Batched 2D Schroedinger family: per_size instances each of n = 128, 192
+    and 256 (ell = n / 8 unit cells per side, so 8 grid points per cell; boxes
+    of b = n / 16, so every instance has a 16 x 16 leaf grid and the same tree
+    depth), instance i of size n_i = (128, 192, 256)[i % 3], with its own
+    well lattice, energy and nrhs Gaussian sources."""
+    out = []
+    for i in range(3 * per_size):
+        n = (128, 192, 256)[i % 3]
+        out.append(schrodinger_workload(n, 2, n // 8, n // 16, nrhs=nrhs, instance=i, config=4))
+    return out
