@@ -52,21 +52,31 @@ __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* _
     const int64_t e = e0 + (int64_t)k * 64;
     wl[k] = (e < N) ? wr[e] : cmake<double2>(0, 0);
   }
-  // Four vectors per pass: their loads are all in flight before any sum.
+  // Four vectors per pass: their loads are all in flight before any sum,
+  // and the next pass's loads are issued before this pass's wave sums.
   constexpr int kG = 4;
+  double2 cur[kG][kPerThread];
+  auto load = [&](double2 (&b)[kG][kPerThread], int i0) {
+#pragma unroll
+    for (int q = 0; q < kG; ++q) {
+      const double2* vr = V + (int64_t)(i0 + q) * vstride + rhs * N;
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const int64_t e = e0 + (int64_t)k * 64;
+        b[q][k] = (i0 + q < nvec && e < N) ? vr[e] : cmake<double2>(0, 0);
+      }
+    }
+  };
+  load(cur, 0);
   for (int i0 = 0; i0 < nvec; i0 += kG) {
+    double2 nxt[kG][kPerThread];
+    load(nxt, i0 + kG);
     double2 s[kG];
 #pragma unroll
     for (int q = 0; q < kG; ++q) {
       s[q] = cmake<double2>(0, 0);
-      if (i0 + q < nvec) {
-        const double2* vr = V + (int64_t)(i0 + q) * vstride + rhs * N;
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-          const int64_t e = e0 + (int64_t)k * 64;
-          if (e < N) s[q] = cadd(s[q], cconjmul(vr[e], wl[k]));
-        }
-      }
+      for (int k = 0; k < kPerThread; ++k) s[q] = cadd(s[q], cconjmul(cur[q][k], wl[k]));
     }
 #pragma unroll
     for (int q = 0; q < kG; ++q) {
@@ -74,6 +84,10 @@ __global__ void __launch_bounds__(kThreads) dots_partial_kernel(const double2* _
       const double2 t = wave_sum(s[q]);
       if (lane == 0) partial[((int64_t)rhs * nvec + i0 + q) * nslot + slot] = t;
     }
+#pragma unroll
+    for (int q = 0; q < kG; ++q)
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) cur[q][k] = nxt[q][k];
   }
 }
 
