@@ -135,6 +135,7 @@ __global__ void __launch_bounds__(kThreads) update_kernel(const double2* __restr
   const int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (e >= N) return;
   double2 acc = w[rhs * N + e];
+#pragma unroll 8
   for (int i = 0; i < nvec; ++i) cfms(acc, V[(int64_t)i * vstride + rhs * N + e], hs[i]);
   w[rhs * N + e] = acc;
 }
