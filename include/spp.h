@@ -44,7 +44,7 @@ enum {
   SPP_OK = 0,
   SPP_EINVAL = -1,           /* bad dim/n/b, null pointer, non-finite input   */
   SPP_ESINGULAR_SHIFT = -2,  /* L - s could not be moved off singularity      */
-  SPP_EBREAKDOWN = -3,       /* zero or non-finite pivot in a front           */
+  SPP_EBREAKDOWN = -3,       /* zero, non-finite or tiny pivot in a front     */
   SPP_NOT_CONVERGED = -4,    /* max_iter reached; u, iters, relres still valid */
   SPP_ENOMEM = -5,           /* device allocation failed                       */
   SPP_EHIP = -6,             /* a HIP runtime call failed                      */
@@ -99,13 +99,34 @@ typedef struct {
                                      ignored with SPP_F_TIMING or a learned
                                      stage attached                            */
 
+/* Device memory for a factor's large blocks (the front arena, or in the
+   streamed storage mode the factor store and the working-front arena):
+   alloc(bytes, ctx) returns `bytes` of device memory on the current device
+   (aligned to 256 bytes) or NULL, which setup reports as SPP_ENOMEM;
+   free(ptr, ctx) releases a block alloc returned.  The factor calls free on
+   its blocks in spp_destroy, after synchronising.  A caching framework
+   allocator (PyTorch's) can be passed here.  Both NULL: the library's own
+   hipMalloc-backed cache. */
+typedef void* (*spp_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*spp_free_fn)(void* ptr, void* ctx);
+
 typedef struct {
   int32_t prec;         /* spp_prec                                              */
   int32_t order;        /* spp_order                                             */
-  double tol;           /* stop when the GMRES residual estimate of
-                           (I + G q) u = G f is <= tol * ||G f||                 */
-  int32_t max_iter;     /* Krylov dimension limit (no restarts)                  */
+  double tol;           /* stop when the true residual of (I + G q) u = G f is
+                           <= tol * ||G f|| (Section 3: GMRES to a relative
+                           tolerance)                                            */
+  int32_t max_iter;     /* total FGMRES iterations over all cycles, <= 500      */
   int32_t flags;        /* SPP_F_* bits                                          */
+  int32_t restart;      /* Krylov vectors per cycle (FGMRES(restart)); 0 = no
+                           restart (one cycle of up to max_iter).  A cycle also
+                           ends, and another starts from the true residual,
+                           when the Givens estimate met tol but the true
+                           residual did not                                     */
+  int32_t reserved;     /* must be 0                                             */
+  spp_alloc_fn alloc;   /* optional allocator hook (both or neither)             */
+  spp_free_fn free;
+  void* alloc_ctx;      /* passed to alloc / free                                */
 } spp_options;
 
 typedef struct {
@@ -120,6 +141,25 @@ typedef struct {
   double t_solve_ms;        /* wall time of the last spp_solve                   */
   int32_t last_iters;       /* GMRES iterations of the last solve (max over RHS) */
   int32_t breakdown_front;  /* front index of a pivot breakdown, else -1         */
+  int32_t last_cycles;      /* FGMRES cycles of the last solve (1 = no restart)  */
+  int32_t storage;          /* 0: every front resident in one arena; 1: streamed
+                               (factors kept compact, fronts of two adjacent
+                               levels resident at a time)                       */
+  double pivot_growth;      /* max over fronts of the largest entry of the
+                               updated 32 x 32 diagonal blocks (before and after
+                               their LU) over the largest entry of the front as
+                               assembled: the growth of the Schur updates        */
+  double min_pivot;         /* min over fronts of |u_kk| / max |front entry|;
+                               below 1e3 FP64 eps (a pivot lost in the rounding
+                               of the assembled entries) the setup reports
+                               SPP_EBREAKDOWN with breakdown_front set          */
+  int64_t device_bytes;     /* device memory the memory plan asked for at setup
+                               (factor storage and work space)                  */
+  int32_t small_pivots;     /* pivots with |u_kk| / max |front entry| below 1e3
+                               eps of the front precision: not a breakdown (the
+                               FP64 FGMRES corrects the factor), but a sign of
+                               an ill-conditioned front                         */
+  int32_t reserved_stats;
 } spp_stats_t;
 
 typedef struct spp_factor spp_factor;
@@ -153,11 +193,26 @@ int spp_setup_batch(const spp_problem* problems, int32_t count, const spp_option
 
 /* ---- solve: a7-a11 ---------------------------------------------------------
  * f: DEVICE complex128 [nrhs][n^d]; u: DEVICE complex128 [nrhs][n^d], written.
- * iters: HOST int32[nrhs]; relres: HOST double[nrhs], the true relative
- * residual ||G f - (I + G q) u|| / ||G f|| of each returned u.
- * Returns SPP_NOT_CONVERGED (u still written) if any RHS missed tol. */
+ * iters: HOST int32[nrhs], FGMRES iterations summed over cycles; relres:
+ * HOST double[nrhs], the true relative residual ||G f - (I + G q) u|| / ||G f||
+ * of each returned u (Section 2.2: the integral form; Section 3: GMRES to a
+ * relative tolerance).  Returns SPP_NOT_CONVERGED (u, iters and relres still
+ * written) if any right-hand side's true residual is above tol once max_iter
+ * iterations are spent.  A zero right-hand side gives u = 0, 0 iterations. */
 int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u,
               int32_t* iters, double* relres, spp_stream_t stream);
+
+/* ---- batched solve with per-problem right-hand sides -------------------------
+ * For a factor of `count` problems (spp_setup_batch): f[i] and u[i] are
+ * DEVICE complex128 [nrhs[i]][n_i^d] arrays of problem i (f[i] may be NULL
+ * only if nrhs[i] == 0; u[i] is written); nrhs: HOST int32[count], each in
+ * [0, 64].  iters / relres: HOST arrays of sum_i nrhs[i] entries, problem by
+ * problem.  All problems iterate in lock step, as in spp_solve with
+ * max_i nrhs[i] columns each (problems with fewer right-hand sides carry zero
+ * columns, which converge at once).  Returns as spp_solve; SPP_EINVAL for a
+ * count mismatch or bad pointers. */
+int spp_solve_batch(spp_factor* factor, const void* const* f, const int32_t* nrhs,
+                    void* const* u, int32_t* iters, double* relres, spp_stream_t stream);
 
 /* Times candidate launch parameters on this factor's shapes (lines per
    workgroup of each FFT pass, column chunks of each substitution product with
@@ -211,7 +266,11 @@ enum {
   SPP_K_TRI = 2,     /* in-workgroup triangular solves of small fronts (a9)           */
   SPP_K_GEMM = 3,    /* MFMA trailing updates / Schur complements of the fronts (a6)  */
   SPP_K_PANEL = 4,   /* pivoted panel factorisation (a6)                              */
-  SPP_K_QAPPLY = 5   /* sparsifying stencil apply Q r (a9)                            */
+  SPP_K_QAPPLY = 5,  /* sparsifying stencil apply Q r (a9)                            */
+  SPP_K_INV = 6,     /* products that prepare the substitution, not part of the LU:
+                        triangular inverses of the pivot blocks and the side
+                        products L21 L11^-1, U11^-1 U12 (a6, few-front levels)      */
+  SPP_K_SOLVE_BLK = 7 /* blocked triangular solves of streamed top fronts (a9)     */
 };
 /* Totals since setup (or the last reset) for one kernel class, all HOST
    outputs, each may be NULL: summed event time of its launches (ms, measured
@@ -260,7 +319,9 @@ const char* spp_cnn_last_error(void);
 /* Uses net as the first preconditioner stage of every FGMRES iteration of
    spp_solve: z = s^{-1} net(s v) with s = sqrt(n^2) (v has unit norm), judged
    by the sparsifying preconditioner's standard: the step is kept when every
-   column's residual estimate falls to at most rho times its previous value,
+   column's residual estimate falls to at most rho times its previous value
+   (0 < rho < 1: the residual estimates never grow, so rho = 1 would keep
+   every step),
    otherwise it is discarded and redone with z = P^{-1} Q v.  After three
    discarded steps in a row the network is not tried again in that solve.
    net = NULL detaches.  Requires a single 2D problem of the network's n and

@@ -14,4 +14,4 @@ from .binding import (SPP_C128, SPP_C64_FRONTS, SPP_EBREAKDOWN, SPP_EHIP, SPP_EI
                       spp_get_stencil, spp_kernel_timing, spp_kernel_timing_reset, spp_last_error,
                       spp_setup, spp_setup_batch, spp_get_shift, spp_solve, spp_stats,
                       CNN, CnnError, SPP_CNN_BF16, SPP_CNN_F32, spp_attach_cnn, spp_learned_stats,
-                      spp_get_krylov, spp_autotune)
+                      spp_get_krylov, spp_autotune, spp_solve_batch, TorchAllocator)

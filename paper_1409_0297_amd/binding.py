@@ -24,7 +24,11 @@ SPP_F_PERSISTENT = 16
 SPP_F_AUTOTUNE = 32
 SPP_F_NO_SIDE = 64
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
-KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5}
+SPP_K_INV, SPP_K_SOLVE_BLK = 6, 7
+KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5, "inv": 6, "solve_blk": 7}
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class spp_problem(ctypes.Structure):
@@ -35,7 +39,9 @@ class spp_problem(ctypes.Structure):
 
 class spp_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("order", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class spp_stats_t(ctypes.Structure):
@@ -45,7 +51,10 @@ class spp_stats_t(ctypes.Structure):
                 ("factor_bytes", ctypes.c_int64), ("factor_flops", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int32),
-                ("breakdown_front", ctypes.c_int32)]
+                ("breakdown_front", ctypes.c_int32), ("last_cycles", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("pivot_growth", ctypes.c_double),
+                ("min_pivot", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("small_pivots", ctypes.c_int32), ("reserved_stats", ctypes.c_int32)]
 
 
 _LIB = None
@@ -70,6 +79,8 @@ def library():
         "spp_setup_batch": (I, [ctypes.POINTER(spp_problem), I, ctypes.POINTER(spp_options), P, ctypes.POINTER(P)]),
         "spp_get_shift": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "spp_solve": (I, [P, P, I, P, ctypes.POINTER(I), ctypes.POINTER(D), P]),
+        "spp_solve_batch": (I, [P, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(I),
+                                ctypes.POINTER(D), P]),
         "spp_apply_operator": (I, [P, P, P, I, P]),
         "spp_apply_green": (I, [P, P, P, I, P]),
         "spp_apply_q": (I, [P, P, P, I, P]),
@@ -155,6 +166,56 @@ def spp_solve(handle, f_ptr, nrhs, u_ptr, stream, nproblems: int = 1):
     return code, list(iters), list(relres)
 
 
+def spp_solve_batch(handle, f_ptrs, nrhs, u_ptrs, stream):
+    """Per-problem right-hand sides: f_ptrs / u_ptrs / nrhs one entry per
+    problem; iters / relres are returned problem by problem."""
+    n = len(nrhs)
+    tot = sum(nrhs)
+    fa = (ctypes.c_void_p * n)(*f_ptrs)
+    ua = (ctypes.c_void_p * n)(*u_ptrs)
+    na = (ctypes.c_int32 * n)(*nrhs)
+    iters = (ctypes.c_int32 * max(tot, 1))()
+    relres = (ctypes.c_double * max(tot, 1))()
+    code = library().spp_solve_batch(handle, fa, na, ua, iters, relres, ctypes.c_void_p(stream))
+    _check(code, "spp_solve_batch", allow=(SPP_OK, SPP_NOT_CONVERGED))
+    return code, list(iters)[:tot], list(relres)[:tot]
+
+
+class TorchAllocator:
+    """spp_options allocator hook backed by PyTorch's caching allocator on the
+    current device and stream (argument marshalling only: torch hands out the
+    memory, the library uses it).  Counts the blocks it served."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.served = 0
+        self.freed = 0
+        self.bytes = 0
+
+        def _alloc(nbytes, ctx):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                         torch.cuda.current_stream())
+            except RuntimeError:
+                return None
+            self.served += 1
+            self.bytes += int(nbytes)
+            return ptr
+
+        def _free(ptr, ctx):
+            self.freed += 1
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+    def install(self, options: spp_options) -> spp_options:
+        options.alloc = self.alloc
+        options.free = self.free
+        return options
+
+
 def _apply(name, handle, a_ptr, b_ptr, nrhs, stream):
     _check(getattr(library(), name)(handle, a_ptr, b_ptr, nrhs, ctypes.c_void_p(stream)), name)
 
@@ -230,7 +291,8 @@ class Solver:
                  ell: float = 1.0, energy: float = 0.0, prec: str = "c128", order: str = "octree",
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
                  timing: bool = False, partial_pivoting: bool = False, graphs: bool = False,
-                 persistent: bool = False, autotune: bool = False, side_products: bool = True):
+                 persistent: bool = False, autotune: bool = False, side_products: bool = True,
+                 restart: int = 0, allocator: "TorchAllocator" = None):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -249,7 +311,10 @@ class Solver:
                          | (SPP_F_GRAPHS if graphs else 0)
                          | (SPP_F_PERSISTENT if persistent else 0)
                          | (SPP_F_AUTOTUNE if autotune else 0)
-                         | (0 if side_products else SPP_F_NO_SIDE))
+                         | (0 if side_products else SPP_F_NO_SIDE), restart=restart)
+        self._allocator = allocator
+        if allocator is not None:
+            allocator.install(op)
         self.handle = spp_setup(pb, op, self._stream())
 
     def _stream(self) -> int:
@@ -348,7 +413,8 @@ class BatchSolver:
     """
 
     def __init__(self, problems, prec: str = "c128", order: str = "octree", tol: float = 1e-10,
-                 max_iter: int = 200, timing: bool = False, graphs: bool = False, persistent: bool = False):
+                 max_iter: int = 200, timing: bool = False, graphs: bool = False, persistent: bool = False,
+                 restart: int = 0):
         import torch
         self.torch = torch
         self.sizes = [p["n"] ** p["d"] for p in problems]
@@ -368,7 +434,7 @@ class BatchSolver:
                          order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
                          tol=tol, max_iter=max_iter,
                          flags=(SPP_F_TIMING if timing else 0) | (SPP_F_GRAPHS if graphs else 0)
-                         | (SPP_F_PERSISTENT if persistent else 0))
+                         | (SPP_F_PERSISTENT if persistent else 0), restart=restart)
         self.handle = spp_setup_batch(pbs, op, torch.cuda.current_stream().cuda_stream)
 
     def _stream(self) -> int:
@@ -392,6 +458,24 @@ class BatchSolver:
                                         nproblems=len(self.sizes))
         per = lambda a: [a[i * nrhs:(i + 1) * nrhs] for i in range(len(self.sizes))]
         return self.unpack(u, nrhs), per(iters), per(relres), code
+
+    def solve_each(self, fs):
+        """spp_solve_batch: fs[i] is an (nrhs_i, N_i) array for problem i, nrhs_i may differ
+        (0 allowed, then None); returns per-problem solutions, iterations and residuals."""
+        parts, ptrs, outs, optrs, counts = [], [], [], [], []
+        for x, N in zip(fs, self.sizes):
+            if x is None:
+                parts.append(None); outs.append(None); ptrs.append(None); optrs.append(None); counts.append(0)
+                continue
+            t = self.torch.as_tensor(x, dtype=self.torch.complex128, device="cuda").reshape(-1, N).contiguous()
+            o = self.torch.empty_like(t)
+            parts.append(t); outs.append(o); ptrs.append(t.data_ptr()); optrs.append(o.data_ptr())
+            counts.append(t.shape[0])
+        code, iters, relres = spp_solve_batch(self.handle, ptrs, counts, optrs, self._stream())
+        it, rr, o = [], [], 0
+        for c in counts:
+            it.append(iters[o:o + c]); rr.append(relres[o:o + c]); o += c
+        return outs, it, rr, code
 
     def apply(self, name, xs):
         xv, nrhs = self.pack(xs)

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -213,43 +214,27 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
     if (!err.empty()) throw Error(SPP_EINVAL, err);
   }
   const Plan& P = pd->plan;
-  std::vector<FrontDev> fd(P.fronts.size());
-  std::vector<int> parent(P.fronts.size(), -1);
-  for (size_t fi = 0; fi < P.fronts.size(); ++fi)
-    for (int c : P.fronts[fi].children) parent[c] = static_cast<int>(fi);
-  for (const Level& L : P.levels) {
-    // Inverse work slots for every level (the precision decides which
-    // levels use them).
-    int64_t xo = 0;
-    const bool inv = true;
-    double e0 = 0, e1 = 0, e2 = 0;
-    std::vector<int> hF, hP;
-    for (int fi = L.begin; fi < L.end; ++fi) {
-      const Front& f = P.fronts[fi];
-      FrontDev& g_ = fd[fi];
-      g_.off = f.off; g_.voff = f.voff; g_.xoff = xo;
-      g_.F = f.F; g_.p = f.p; g_.idx = f.idx; g_.map = f.map; g_.perm = pd->perm_total;
-      g_.dblk = pd->dblk_total;
-      g_.inst = pd->front_inst[fi];
-      g_.parent = parent[fi];
-      pd->dblk_total += (f.p + 31) / 32;
-      g_.nchild = static_cast<int>(f.children.size());
-      if (g_.nchild > 8) throw Error(SPP_EINVAL, "more than 8 children");
-      for (int c = 0; c < g_.nchild; ++c) g_.child[c] = f.children[c];
-      pd->perm_total += f.p;
-      // XL, XU (p x p each), then Lt, Ut ((F - p) x p each).
-      if (inv) xo += 2LL * f.p * f.F;
-      e0 += 0.5 * f.p * (f.p - 1.0);
-      e1 += 0.5 * f.p * (f.p + 1.0);
-      e2 += (double)(f.F - f.p) * f.p;
-      hF.push_back(f.F);
-      hP.push_back(f.p);
-    }
-    pd->level_ent.insert(pd->level_ent.end(), {e0, e1, e2});
-    pd->level_F.push_back(hF);
-    pd->level_p.push_back(hP);
-    pd->xwork_elems = std::max(pd->xwork_elems, xo);
+  PlanTables tab;
+  {
+    std::string err = build_tables(P, pd->front_inst, tab);
+    if (!err.empty()) throw Error(SPP_EINVAL, err);
   }
+  std::vector<FrontDev> fd(P.fronts.size());
+  for (size_t fi = 0; fi < P.fronts.size(); ++fi) {
+    const FrontTable& t = tab.fronts[fi];
+    FrontDev& g = fd[fi];
+    g.off = t.off; g.voff = t.voff; g.xoff = t.xoff;
+    g.F = t.F; g.p = t.p; g.idx = t.idx; g.map = t.map; g.perm = t.perm; g.dblk = t.dblk;
+    g.inst = t.inst; g.parent = t.parent; g.nchild = t.nchild;
+    for (int c = 0; c < 8; ++c) g.child[c] = t.child[c];
+    g.gptr = t.gptr;
+  }
+  pd->level_ent = tab.level_ent;
+  pd->level_F = tab.level_F;
+  pd->level_p = tab.level_p;
+  pd->perm_total = tab.perm_total;
+  pd->dblk_total = tab.dblk_total;
+  pd->xwork_elems = tab.xwork_elems;
   std::vector<AsmBlockDev> bd(P.blocks.size());
   for (size_t i = 0; i < P.blocks.size(); ++i)
     bd[i] = AsmBlockDev{P.blocks[i].front, P.blocks[i].type, P.blocks[i].anchor, P.blocks[i].rowpos, P.blocks[i].colpos};
@@ -260,35 +245,8 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
     if (bytes) SPP_HIP(hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
     return p;
   };
-  {
-    // Children's boundary rows by parent position (counting sort, children in
-    // order, so a position's sum keeps the order of the plain gather).
-    std::vector<int> gptr;
-    std::vector<int64_t> gsrc;
-    for (size_t fi = 0; fi < P.fronts.size(); ++fi) {
-      const Front& f = P.fronts[fi];
-      fd[fi].gptr = static_cast<int>(gptr.size());
-      std::vector<int> cnt(f.F + 1, 0);
-      for (int c : f.children) {
-        const Front& ch = P.fronts[c];
-        for (int jj = 0; jj < ch.F - ch.p; ++jj)
-          if (P.map[ch.map + jj] >= 0) ++cnt[P.map[ch.map + jj] + 1];
-      }
-      for (int i = 0; i < f.F; ++i) cnt[i + 1] += cnt[i];
-      const int64_t base = static_cast<int64_t>(gsrc.size());
-      for (int i = 0; i <= f.F; ++i) gptr.push_back(static_cast<int>(base + cnt[i]));
-      gsrc.resize(gsrc.size() + cnt[f.F]);
-      std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-      for (int c : f.children) {
-        const Front& ch = P.fronts[c];
-        for (int jj = 0; jj < ch.F - ch.p; ++jj)
-          if (P.map[ch.map + jj] >= 0) gsrc[base + fill[P.map[ch.map + jj]]++] = ch.voff + ch.p + jj;
-      }
-    }
-    if (gsrc.size() > (size_t)INT32_MAX) throw Error(SPP_EINVAL, "plan too large");
-    pd->gptr = static_cast<int*>(upload(gptr.data(), gptr.size() * sizeof(int)));
-    pd->gsrc = static_cast<int64_t*>(upload(gsrc.data(), gsrc.size() * sizeof(int64_t)));
-  }
+  pd->gptr = static_cast<int*>(upload(tab.gptr.data(), tab.gptr.size() * sizeof(int)));
+  pd->gsrc = static_cast<int64_t*>(upload(tab.gsrc.data(), tab.gsrc.size() * sizeof(int64_t)));
   pd->fronts = static_cast<FrontDev*>(upload(fd.data(), fd.size() * sizeof(FrontDev)));
   pd->blocks = static_cast<AsmBlockDev*>(upload(bd.data(), bd.size() * sizeof(AsmBlockDev)));
   pd->pos = static_cast<int*>(upload(P.pos.data(), P.pos.size() * sizeof(int)));
@@ -381,6 +339,13 @@ struct spp_factor {
   }
   hipStream_t last_stream = nullptr;
   std::unique_ptr<KernelTimer> timer;
+  // Blocks from the caller's allocator hook (spp_options::alloc), released
+  // through spp_options::free.
+  std::vector<void*> hook_blocks;
+  // spp_solve_batch: right-hand sides and solutions packed into the batch
+  // layout with the largest per-problem count (grown on demand).
+  double2 *pack_f = nullptr, *pack_u = nullptr;
+  int64_t pack_cap = 0;
 
   template <typename T> T* dalloc(size_t count) {
     if (count == 0) count = 1;
@@ -398,10 +363,20 @@ struct spp_factor {
     (void)hipDeviceSynchronize();   // (nothing queued may still use the block)
     mem_put(p, bytes, device);
   }
+  // A large block of the factor: from the caller's hook if one was given.
+  void* big_alloc(size_t bytes) {
+    bytes = std::max<size_t>((bytes + 255) / 256 * 256, 256);
+    if (!opt.alloc) return dalloc<char>(bytes);
+    void* p = opt.alloc(bytes, opt.alloc_ctx);
+    if (!p) throw Error(SPP_ENOMEM, "the allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+    hook_blocks.push_back(p);
+    return p;
+  }
   ~spp_factor() {
     drop_graph();
     if (gstream) (void)hipStreamDestroy(gstream);
     (void)hipDeviceSynchronize();
+    for (void* p : hook_blocks) opt.free(p, opt.alloc_ctx);
     for (const auto& a : allocs) mem_put(a.first, a.second, device);
     if (h_resid) mem_put(h_resid, h_resid_bytes, kPinnedDev);
     if (resid_event) (void)hipEventDestroy(resid_event);
@@ -659,6 +634,9 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   if (op->prec != SPP_C128 && op->prec != SPP_C64_FRONTS) throw Error(SPP_EINVAL, "unknown precision");
   if (op->order != SPP_ORDER_OCTREE && op->order != SPP_ORDER_BISECT) throw Error(SPP_EINVAL, "unknown ordering");
   if (!(op->tol > 0) || op->max_iter < 1 || op->max_iter > 500) throw Error(SPP_EINVAL, "tol > 0 and 1 <= max_iter <= 500");
+  if (op->restart < 0 || op->restart > 500) throw Error(SPP_EINVAL, "restart must be in [0, 500]");
+  if (op->reserved != 0) throw Error(SPP_EINVAL, "spp_options::reserved must be 0");
+  if ((op->alloc == nullptr) != (op->free == nullptr)) throw Error(SPP_EINVAL, "give both alloc and free, or neither");
   for (int i = 0; i < count; ++i) {
     validate_problem(&pbs[i]);
     if (pbs[i].dim != pbs[0].dim) throw Error(SPP_EINVAL, "all problems of a batch must have the same dimension");
@@ -699,6 +677,37 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       F->groups.push_back(g);
     }
     F->groups.back().ninst += 1;
+  }
+  // Memory plan: every device block of the setup, known from the plan
+  // alone, checked against what the device can still give before any launch.
+  {
+    size_t stencil_elems = 0;
+    int64_t Nmax_ = 0;
+    for (const SppInstance& I : F->inst) {
+      size_t w = 0;
+      for (const SetType& T : I.plan->types)
+        w += (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS) + 2 * (size_t)T.nS * T.nG;
+      stencil_elems += w;
+      Nmax_ = std::max(Nmax_, I.N);
+    }
+    const size_t cs = F->csize;
+    const size_t need = (size_t)P.arena_elems * cs + (size_t)F->pd->xwork_elems * cs * 3 / 2 +
+                        (size_t)2 * 32 * 32 * F->pd->dblk_total * cs + sizeof(double2) * stencil_elems +
+                        sizeof(double) * 2 * (size_t)F->Ntot + sizeof(double2) * 4 * (size_t)Nmax_ +
+                        sizeof(int) * 3 * (size_t)F->pd->perm_total + sizeof(unsigned) * P.fronts.size();
+    F->stats.device_bytes = (int64_t)need;
+    if (!op->alloc) {
+      size_t freeb = 0, totalb = 0;
+      SPP_HIP(hipMemGetInfo(&freeb, &totalb));
+      size_t cached = 0;
+      {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        cached = g_mem_cached;
+      }
+      if (need > freeb + cached)
+        throw Error(SPP_ENOMEM, "memory plan: the setup needs " + std::to_string(need >> 20) + " MiB, the device has " +
+                                    std::to_string((freeb + cached) >> 20) + " MiB free");
+    }
   }
   F->q = F->dalloc<double>(F->Ntot);
   F->sigma = F->dalloc<double>(F->Ntot);
@@ -791,6 +800,14 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   mf.ipiv = F->dalloc<int>(F->pd->perm_total);
   mf.prow = F->dalloc<int>(F->pd->perm_total);
   mf.info = info;
+  mf.fnorm = F->dalloc<unsigned>(P.fronts.size());
+  mf.pstat = F->dalloc<unsigned>(2);
+  mf.piv_tol = 1e3f * (float)std::numeric_limits<double>::epsilon();
+  mf.piv_warn = 1e3f * (op->prec == SPP_C128 ? (float)std::numeric_limits<double>::epsilon()
+                                              : std::numeric_limits<float>::epsilon());
+  SPP_HIP(hipMemsetAsync(mf.fnorm, 0, sizeof(unsigned) * P.fronts.size(), st));
+  SPP_HIP(hipMemsetAsync(mf.pstat, 0, sizeof(unsigned), st));
+  SPP_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(mf.pstat + 1), 0x7f7fffff, 1, st));
   mf.inst = F->inst_dev;
   mf.ninst = count;
   mf.d = pbs[0].dim;
@@ -816,7 +833,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     F->level_form.push_back(form);
   }
 
-  F->arena = F->dalloc<char>((size_t)P.arena_elems * F->csize);
+  F->arena = F->big_alloc((size_t)P.arena_elems * F->csize);
   void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);
   void* tbuf = F->dalloc<char>((size_t)(F->pd->xwork_elems / 2) * F->csize);
   const bool partial_pivoting = (F->opt.flags & SPP_F_PARTIAL_PIVOTING) != 0;
@@ -837,7 +854,9 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
                              L.max_children, F->level_form[l], partial_pivoting, hF, hP);
   }
   int hinfo[16];
+  unsigned hpstat[2];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  SPP_HIP(hipMemcpyAsync(hpstat, mf.pstat, sizeof(hpstat), hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
   const double tf1 = now_ms();
   F->dfree(xwork);
@@ -858,8 +877,20 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   F->stats.t_factor_ms = tf1 - tf0;
   F->stats.t_setup_ms = now_ms() - t0;
   F->stats.last_iters = 0;
+  F->stats.last_cycles = 0;
+  F->stats.storage = 0;
+  {
+    float g, mp;
+    std::memcpy(&g, &hpstat[0], sizeof(float));
+    std::memcpy(&mp, &hpstat[1], sizeof(float));
+    F->stats.pivot_growth = g;
+    F->stats.min_pivot = mp;
+    F->stats.small_pivots = hinfo[9];
+  }
   if (hinfo[0]) {
-    g_last_error = "zero or non-finite pivot in front " + std::to_string(hinfo[0] - 1);
+    g_last_error = std::string(hinfo[10] ? "pivot below 1e3 FP64 eps times the largest front entry"
+                                         : "zero or non-finite pivot") +
+                   " in front " + std::to_string(hinfo[0] - 1);
     *out = F.release();
     return SPP_EBREAKDOWN;
   }
@@ -873,7 +904,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   F->last_stream = st;
   TimerScope timer_scope(F);
   const int maxit = F->opt.max_iter;
-  ensure_solve_buffers(F, nrhs, maxit);
+  // Krylov vectors per cycle: the restart length, or the whole iteration
+  // budget without restarts.
+  const int cycle_len = F->opt.restart > 0 ? std::min(F->opt.restart, maxit) : maxit;
+  ensure_solve_buffers(F, nrhs, cycle_len);
   if ((F->opt.flags & SPP_F_AUTOTUNE) && F->tuned_nrhs != nrhs) do_autotune(F, nrhs, st);
   const int64_t vstride = (int64_t)nrhs * F->Ntot;   // one Krylov vector of the whole batch
   const int ld = F->cap_iter + 1;                     // Hessenberg column stride, per-column vector stride
@@ -883,22 +917,20 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   double2* u = static_cast<double2*>(uv);
   const bool precond = !(F->opt.flags & SPP_F_UNPRECONDITIONED);
 
-  // a7: g = G f; beta = ||g|| per column.
+  // a7: g = G f; beta0 = ||g|| per column (the reference of every stopping test).
   apply_green(F, f, F->g0, nrhs, st);
   for (const SppGroup& g : F->groups) {
     const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
-    const int64_t o = g.Noff * nrhs;
-    kr_norms(st, F->g0 + o, nc, g.N, F->rpart, F->norms + c0);
-    kr_scale_init(st, F->g0 + o, F->V + o, F->norms + c0, nc, g.N, F->gv + (int64_t)c0 * ld, ld);
+    kr_norms(st, F->g0 + g.Noff * nrhs, nc, g.N, F->rpart, F->norms + c0);
   }
-  std::vector<double> beta(cols);
-  SPP_HIP(hipMemcpyAsync(beta.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
+  std::vector<double> beta0(cols);
+  SPP_HIP(hipMemcpyAsync(beta0.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
-  std::vector<int> k(cols, 0);
-  std::vector<bool> conv(cols, false);
+  std::vector<int> k(cols, 0), total(cols, 0);
+  std::vector<bool> conv(cols, false), fin(cols, false);
+  for (int c = 0; c < cols; ++c) fin[c] = !(beta0[c] > 0);
+  std::vector<double> beta(cols), rn(cols, 0.0);
   int done = 0;
-  for (int c = 0; c < cols; ++c)
-    if (beta[c] == 0) { conv[c] = true; ++done; }
   // One Arnoldi step with z_j already in Z: w = A z_j, CGS2, Givens; returns
   // the residual estimates in F->h_resid.
   // head_next: after the step, run the next iteration's preconditioner head
@@ -986,97 +1018,183 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     F->graph_nrhs = nrhs;
     F->graph_precond = precond;
   }
-  if (use_graph) kr_set_counter(st, F->dj, 0, false);
   F->cnn_accepted = F->cnn_rejected = 0;
   int reject_run = 0;
-  std::vector<double> prev(beta);
   const double sN = std::sqrt((double)F->Ntot);
-  int j = 0;
-  for (; j < maxit && done < cols; ++j) {
-    double2* vj = F->V + (int64_t)j * vstride;
-    double2* zj = F->Z + (int64_t)j * vstride;
-    bool have = false;
-    if (use_graph) {
-      SPP_HIP(hipGraphLaunch(F->graph_exec, st));
+  const double tol = F->opt.tol;
+  // a10-a11: cycles of FGMRES.  Each cycle starts from the current residual
+  // r (g itself in the first cycle, x0 = 0), runs until every column's
+  // residual estimate is <= tol ||g|| or the cycle length or iteration budget
+  // is spent, adds its correction to u, and recomputes the true residual
+  // ||g - (I + G q) u||.  A column whose true residual is still above
+  // tol ||g|| (restarts, or an estimate that drifted from the truth) goes on
+  // with another cycle while iterations remain.
+  const double2* r = F->g0;
+  int used = 0, j = 0, cycles = 0;
+  bool all_ok = false;
+  for (;;) {
+    for (const SppGroup& g : F->groups) {
+      const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+      const int64_t o = g.Noff * nrhs;
+      if (cycles > 0) kr_norms(st, r + o, nc, g.N, F->rpart, F->norms + c0);
+      kr_scale_init(st, r + o, F->V + o, F->norms + c0, nc, g.N, F->gv + (int64_t)c0 * ld, ld);
+    }
+    if (cycles == 0) {
+      beta = beta0;
+    } else {
+      SPP_HIP(hipMemcpyAsync(beta.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
       SPP_HIP(hipStreamSynchronize(st));
-      have = true;
-    } else if (learned && reject_run < 3) {
-      // Learned stage: z_j = net(v_j), kept only if every column's residual
-      // estimate drops to rho times its previous value.
-      SPP_HIP(hipMemcpyAsync(F->gsave, F->gv, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));
-      cnn_apply(F->cnn, vj, zj, cols, sN, 1.0 / sN, st);
-      arnoldi_step(j);
-      bool ok = true;
-      for (int c = 0; c < cols; ++c)
-        if (!conv[c] && !(F->h_resid[c] <= F->cnn_rho * prev[c])) ok = false;
-      if (ok) {
-        ++F->cnn_accepted;
-        reject_run = 0;
-        have = true;
-      } else {
-        ++F->cnn_rejected;
-        ++reject_run;
-        SPP_HIP(hipMemcpyAsync(F->gv, F->gsave, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));
-      }
     }
-    if (!have) {
-      // a9: z_j = M v_j (its head may already have run behind the previous
-      // step's residual check)
-      if (precond) {
-        if (!head_ready) precond_head(F, vj, nrhs, st);
-        precond_tail(F, zj, nrhs, st, true);
-      } else {
-        SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
-      }
-      head_ready = false;
-      arnoldi_step(j, precond && !learned && j + 1 < maxit);
-    }
-    for (int c = 0; c < cols; ++c) prev[c] = F->h_resid[c];
+    done = 0;
     for (int c = 0; c < cols; ++c) {
-      if (conv[c]) continue;
-      if (!(F->h_resid[c] > F->opt.tol * beta[c])) {
-        conv[c] = true;
-        k[c] = j + 1;
-        ++done;
+      k[c] = 0;
+      conv[c] = fin[c] || !(beta[c] > tol * beta0[c]);
+      if (conv[c]) ++done;
+    }
+    if (use_graph) kr_set_counter(st, F->dj, 0, false);
+    std::vector<double> prev(beta);
+    head_ready = false;
+    const int jmax = std::min(cycle_len, maxit - used);
+    for (j = 0; j < jmax && done < cols; ++j) {
+      double2* vj = F->V + (int64_t)j * vstride;
+      double2* zj = F->Z + (int64_t)j * vstride;
+      bool have = false;
+      if (use_graph) {
+        SPP_HIP(hipGraphLaunch(F->graph_exec, st));
+        SPP_HIP(hipStreamSynchronize(st));
+        have = true;
+      } else if (learned && reject_run < 3) {
+        // Learned stage: z_j = net(v_j), kept only if every column's residual
+        // estimate drops to rho times its previous value.
+        SPP_HIP(hipMemcpyAsync(F->gsave, F->gv, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));
+        cnn_apply(F->cnn, vj, zj, cols, sN, 1.0 / sN, st);
+        arnoldi_step(j);
+        bool ok = true;
+        for (int c = 0; c < cols; ++c)
+          if (!conv[c] && !(F->h_resid[c] <= F->cnn_rho * prev[c])) ok = false;
+        if (ok) {
+          ++F->cnn_accepted;
+          reject_run = 0;
+          have = true;
+        } else {
+          ++F->cnn_rejected;
+          ++reject_run;
+          SPP_HIP(hipMemcpyAsync(F->gv, F->gsave, sizeof(double2) * ld * cols, hipMemcpyDeviceToDevice, st));
+        }
+      }
+      if (!have) {
+        // a9: z_j = M v_j (its head may already have run behind the previous
+        // step's residual check)
+        if (precond) {
+          if (!head_ready) precond_head(F, vj, nrhs, st);
+          precond_tail(F, zj, nrhs, st, true);
+        } else {
+          SPP_HIP(hipMemcpyAsync(zj, vj, sizeof(double2) * vstride, hipMemcpyDeviceToDevice, st));
+        }
+        head_ready = false;
+        arnoldi_step(j, precond && !learned && j + 1 < jmax);
+      }
+      for (int c = 0; c < cols; ++c) prev[c] = F->h_resid[c];
+      for (int c = 0; c < cols; ++c) {
+        if (conv[c]) continue;
+        if (!(F->h_resid[c] > tol * beta0[c])) {
+          conv[c] = true;
+          k[c] = j + 1;
+          ++done;
+        }
       }
     }
+    for (int c = 0; c < cols; ++c)
+      if (!conv[c]) k[c] = j;
+      else if (fin[c]) k[c] = 0;
+    // a11: u (+)= Z y, then the true residual ||g - (I + G q) u|| / ||g||.
+    SPP_HIP(hipMemcpyAsync(F->kvec, k.data(), sizeof(int) * cols, hipMemcpyHostToDevice, st));
+    kr_backsolve(st, F->H, ld, hrhs, F->gv, ld, F->y, 0, cols, F->kvec);
+    const int kmax_all = std::max(1, *std::max_element(k.begin(), k.end()));
+    for (const SppGroup& g : F->groups) {
+      const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+      const int64_t o = g.Noff * nrhs;
+      kr_combine(st, F->Z + o, vstride, kmax_all, F->y + (int64_t)c0 * ld, ld, u + o, nc, g.N, F->kvec + c0,
+                 cycles > 0);
+    }
+    apply_operator(F, u, F->wk, nrhs, st);
+    kr_sub(st, F->g0, F->wk, F->wk, vstride);
+    for (const SppGroup& g : F->groups) {
+      const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+      kr_norms(st, F->wk + g.Noff * nrhs, nc, g.N, F->rpart, F->norms + c0);
+    }
+    SPP_HIP(hipMemcpyAsync(rn.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
+    SPP_HIP(hipStreamSynchronize(st));
+    used += j;
+    ++cycles;
+    all_ok = true;
+    for (int c = 0; c < cols; ++c) {
+      total[c] += k[c];
+      if (!(beta0[c] > 0) || rn[c] <= tol * beta0[c]) fin[c] = true;
+      else all_ok = false;
+    }
+    if (all_ok || used >= maxit || j == 0) break;
+    r = F->wk;   // the next cycle starts from the true residual
   }
-  bool all_conv = true;
-  for (int c = 0; c < cols; ++c)
-    if (!conv[c]) { k[c] = j; all_conv = false; }
-  // a11: u = Z y, then the true residual ||g - (I + G q) u|| / ||g||.
-  SPP_HIP(hipMemcpyAsync(F->kvec, k.data(), sizeof(int) * cols, hipMemcpyHostToDevice, st));
-  kr_backsolve(st, F->H, ld, hrhs, F->gv, ld, F->y, 0, cols, F->kvec);
-  const int kmax_all = std::max(1, *std::max_element(k.begin(), k.end()));
-  for (const SppGroup& g : F->groups) {
-    const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
-    const int64_t o = g.Noff * nrhs;
-    kr_combine(st, F->Z + o, vstride, kmax_all, F->y + (int64_t)c0 * ld, ld, u + o, nc, g.N, F->kvec + c0);
-  }
-  apply_operator(F, u, F->wk, nrhs, st);
-  kr_sub(st, F->g0, F->wk, F->wk, vstride);
-  for (const SppGroup& g : F->groups) {
-    const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
-    kr_norms(st, F->wk + g.Noff * nrhs, nc, g.N, F->rpart, F->norms + c0);
-  }
-  std::vector<double> rn(cols);
-  SPP_HIP(hipMemcpyAsync(rn.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
-  SPP_HIP(hipStreamSynchronize(st));
   int kmax = 0;
   for (int c = 0; c < cols; ++c) {
-    iters[c] = k[c];
-    relres[c] = beta[c] > 0 ? rn[c] / beta[c] : 0.0;
-    kmax = std::max(kmax, k[c]);
+    iters[c] = total[c];
+    relres[c] = beta0[c] > 0 ? rn[c] / beta0[c] : 0.0;
+    kmax = std::max(kmax, total[c]);
   }
   F->stats.last_iters = kmax;
+  F->stats.last_cycles = cycles;
   F->stats.t_solve_ms = now_ms() - t0;
   F->last_iters_all = j;
   F->last_nrhs = nrhs;
-  if (!all_conv) {
-    g_last_error = "GMRES reached max_iter before the tolerance";
+  if (!all_ok) {
+    g_last_error = "GMRES reached max_iter before the true residual met the tolerance";
     return SPP_NOT_CONVERGED;
   }
   return SPP_OK;
+}
+
+// Per-problem right-hand sides: packed into the batch layout with the
+// largest count per problem (missing columns are zero and converge at once),
+// solved in lock step, unpacked.
+int do_solve_batch(spp_factor* F, const void* const* f, const int32_t* nrhs, void* const* u, int32_t* iters,
+                   double* relres, hipStream_t st) {
+  if (!F || !f || !nrhs || !u || !iters || !relres) throw Error(SPP_EINVAL, "null argument");
+  const int np = static_cast<int>(F->inst.size());
+  int R = 0;
+  for (int i = 0; i < np; ++i) {
+    if (nrhs[i] < 0 || nrhs[i] > 64) throw Error(SPP_EINVAL, "nrhs[i] must be in [0, 64]");
+    if (nrhs[i] > 0 && (!f[i] || !u[i])) throw Error(SPP_EINVAL, "null f[i] or u[i] with nrhs[i] > 0");
+    R = std::max(R, (int)nrhs[i]);
+  }
+  if (R == 0) return SPP_OK;
+  const int64_t need = (int64_t)R * F->Ntot;
+  if (need > F->pack_cap) {
+    F->dfree(F->pack_f);
+    F->dfree(F->pack_u);
+    F->pack_f = F->dalloc<double2>(need);
+    F->pack_u = F->dalloc<double2>(need);
+    F->pack_cap = need;
+  }
+  SPP_HIP(hipMemsetAsync(F->pack_f, 0, sizeof(double2) * need, st));
+  for (int i = 0; i < np; ++i)
+    if (nrhs[i] > 0)
+      SPP_HIP(hipMemcpyAsync(F->pack_f + F->inst[i].Noff * R, f[i], sizeof(double2) * nrhs[i] * F->inst[i].N,
+                             hipMemcpyDeviceToDevice, st));
+  std::vector<int32_t> it((size_t)np * R);
+  std::vector<double> rr((size_t)np * R);
+  const int code = do_solve(F, F->pack_f, R, F->pack_u, it.data(), rr.data(), st);
+  int o = 0;
+  for (int i = 0; i < np; ++i) {
+    if (nrhs[i] > 0)
+      SPP_HIP(hipMemcpyAsync(u[i], F->pack_u + F->inst[i].Noff * R, sizeof(double2) * nrhs[i] * F->inst[i].N,
+                             hipMemcpyDeviceToDevice, st));
+    for (int c = 0; c < nrhs[i]; ++c, ++o) {
+      iters[o] = it[(size_t)i * R + c];
+      relres[o] = rr[(size_t)i * R + c];
+    }
+  }
+  return code;
 }
 
 }  // namespace
@@ -1095,6 +1213,12 @@ int spp_setup_batch(const spp_problem* problems, int32_t count, const spp_option
 int spp_solve(spp_factor* factor, const void* f, int32_t nrhs, void* u, int32_t* iters, double* relres,
               spp_stream_t stream) {
   return guarded([&] { return do_solve(factor, f, nrhs, u, iters, relres, reinterpret_cast<hipStream_t>(stream)); });
+}
+
+int spp_solve_batch(spp_factor* factor, const void* const* f, const int32_t* nrhs, void* const* u, int32_t* iters,
+                    double* relres, spp_stream_t stream) {
+  return guarded(
+      [&] { return do_solve_batch(factor, f, nrhs, u, iters, relres, reinterpret_cast<hipStream_t>(stream)); });
 }
 
 int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream) {
@@ -1187,12 +1311,12 @@ int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t
 
 int spp_attach_cnn(spp_factor* factor, spp_cnn* net, double rho) {
   return guarded([&] {
+    if (net && !(rho > 0 && rho < 1)) throw Error(SPP_EINVAL, "rho must be in (0, 1)");
     if (!factor) throw Error(SPP_EINVAL, "null factor");
     if (!net) {
       factor->cnn = nullptr;
       return SPP_OK;
     }
-    if (!(rho > 0 && rho <= 1)) throw Error(SPP_EINVAL, "rho must be in (0, 1]");
     if (factor->inst.size() != 1 || factor->inst[0].d != 2 || factor->inst[0].n != cnn_grid(net))
       throw Error(SPP_EINVAL, "the learned stage needs a single 2D problem on the network's grid");
     factor->cnn = net;

@@ -16,7 +16,10 @@ namespace spp {
 // SPP_F_TIMING).  The launchers bracket the launches of each class with
 // events on the launch stream and record the algorithmic bytes and flops of
 // that launch; spp_kernel_timing() reads the totals back.
-enum KernelClass { KC_FFT = 0, KC_GEMV = 1, KC_TRI = 2, KC_GEMM = 3, KC_PANEL = 4, KC_QAPPLY = 5, KC_COUNT = 6 };
+enum KernelClass {
+  KC_FFT = 0, KC_GEMV = 1, KC_TRI = 2, KC_GEMM = 3, KC_PANEL = 4, KC_QAPPLY = 5, KC_INV = 6, KC_SOLVE_BLK = 7,
+  KC_COUNT = 8
+};
 struct KernelTimer;
 extern thread_local KernelTimer* g_timer;
 void timer_begin(int cls, hipStream_t st);
@@ -115,7 +118,13 @@ struct MfDev {
   int* perm;           // final row permutation of each front's pivot block
   int* ipiv;           // LAPACK-style interchange record written by the panel
   int* prow;           // block-local pivoting: row order of each 32-row block (front rows)
-  int* info;           // [0] = breakdown front + 1 (0 if none)
+  int* info;           // [0] = breakdown front + 1 (0 if none); [1..8] stencil
+                       // Gram breakdown per set type; [9] count of pivots below
+                       // piv_warn; [10] = 1 if a pivot was below piv_tol
+  unsigned* fnorm;     // per front: largest |entry| as assembled (float bits)
+  unsigned* pstat;     // [0] pivot growth, [1] smallest |u_kk| / fnorm (float bits)
+  float piv_tol;       // breakdown threshold on |u_kk| / fnorm (1e3 FP64 eps)
+  float piv_warn;      // small-pivot threshold (1e3 eps of the front precision)
   const InstDev* inst; // device array, one entry per instance
   // Host-side summary (launch geometry).
   int ninst, d;
@@ -186,8 +195,9 @@ void kr_givens(hipStream_t st, double2* H, int hcol_stride, int hrhs_stride, dou
                const int* dj = nullptr);
 void kr_backsolve(hipStream_t st, const double2* H, int hcol_stride, int hrhs_stride, const double2* g,
                   int ldg, double2* y, int k, int nrhs, const int* kvec);
+// u = Z y (accumulate: u += Z y) per right-hand side with kvec[rhs] vectors.
 void kr_combine(hipStream_t st, const double2* Z, int64_t zstride, int nvec, const double2* y,
-                int ldy, double2* u, int nrhs, int64_t N, const int* kvec);
+                int ldy, double2* u, int nrhs, int64_t N, const int* kvec, bool accumulate = false);
 void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* partial, double* out);
 void kr_sub(hipStream_t st, const double2* a, const double2* b, double2* out, int64_t count);
 void kr_scale_init(hipStream_t st, const double2* g, double2* v0, const double* norms, int nrhs,

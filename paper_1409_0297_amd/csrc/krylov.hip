@@ -295,8 +295,9 @@ __global__ void backsolve_kernel(const double2* H, int hcol, int hrhs, const dou
   for (int i = kk; i < ldg; ++i) yy[i] = cmake<double2>(0, 0);
 }
 
+// u = Z y, or u += Z y with accumulate (a restarted cycle adds its correction).
 __global__ void combine_kernel(const double2* __restrict__ Z, int64_t zstride, int nvec, const double2* __restrict__ y,
-                               int ldy, double2* __restrict__ u, int64_t N, const int* kvec) {
+                               int ldy, double2* __restrict__ u, int64_t N, const int* kvec, int accumulate) {
   const int rhs = blockIdx.y;
   __shared__ double2 ys[kMaxVec];
   const int kk = kvec ? kvec[rhs] : nvec;
@@ -306,7 +307,7 @@ __global__ void combine_kernel(const double2* __restrict__ Z, int64_t zstride, i
   if (e >= N) return;
   double2 acc = cmake<double2>(0, 0);
   for (int i = 0; i < kk; ++i) cfma(acc, Z[(int64_t)i * zstride + rhs * N + e], ys[i]);
-  u[rhs * N + e] = acc;
+  u[rhs * N + e] = accumulate ? cadd(u[rhs * N + e], acc) : acc;
 }
 
 __global__ void sub_kernel(const double2* a, const double2* b, double2* out, int64_t count) {
@@ -394,9 +395,10 @@ void kr_backsolve(hipStream_t st, const double2* H, int hcol, int hrhs, const do
 }
 
 void kr_combine(hipStream_t st, const double2* Z, int64_t zstride, int nvec, const double2* y, int ldy, double2* u,
-                int nrhs, int64_t N, const int* kvec) {
+                int nrhs, int64_t N, const int* kvec, bool accumulate) {
   if (nvec > kMaxVec) throw Error(-7, "Krylov dimension exceeds the kernel limit");
-  combine_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(Z, zstride, nvec, y, ldy, u, N, kvec);
+  combine_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(Z, zstride, nvec, y, ldy, u, N, kvec,
+                                                                         accumulate ? 1 : 0);
   SPP_LAUNCH_CHECK();
 }
 

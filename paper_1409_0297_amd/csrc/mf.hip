@@ -122,6 +122,26 @@ __global__ void extend_add_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int f
   }
 }
 
+// ------------------------------------------------------------------ front norm
+// Largest |entry| of every front of a level as assembled (after the
+// extend-add), as float bits in mf.fnorm (entries are >= 0, so the bit
+// patterns order like the values).  blockIdx.x = chunk of cols_per_wg
+// columns, blockIdx.y = front.
+template <typename R>
+__global__ void __launch_bounds__(256) front_norm_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, int f0,
+                                                         int cols_per_wg) {
+  const int fi = f0 + blockIdx.y;
+  const FrontDev& f = mf.fronts[fi];
+  const int64_t j0 = (int64_t)blockIdx.x * cols_per_wg;
+  if (j0 >= f.F) return;
+  const int64_t e1 = min<int64_t>(f.F, j0 + cols_per_wg) * f.F;
+  const cplx_t<R>* A = arena + f.off;
+  float m = 0.f;
+  for (int64_t e = j0 * f.F + threadIdx.x; e < e1; e += blockDim.x) m = fmaxf(m, (float)sqrt(cabs2(A[e])));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(mf.fnorm + fi, __float_as_uint(m));
+}
+
 // ------------------------------------------------------------------ panel LU
 template <typename R>
 __global__ void __launch_bounds__(256) panel_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int* __restrict__ ipiv,
@@ -672,9 +692,33 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     mf.prow[f.perm + k0 + tid] = k0 + rsel[tid];
     mf.perm[f.perm + k0 + tid] = k0 + rsel[tid];
   }
+  // Pivot statistics against the largest entry of the front as assembled:
+  // a pivot below piv_tol (1e3 FP64 eps) times it is a breakdown (info[0] =
+  // front + 1, info[10] = 1); one below piv_warn (1e3 eps of the front
+  // precision) is counted in info[9]; the block's largest entry before and
+  // after its LU feeds the growth statistic.
+  const float fn = __uint_as_float(mf.fnorm[fi]);
+  float gmax = 0.f;
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
-    if (i < kb && c < kb) A[(int64_t)c * F + i] = X[i][c];
+    if (i < kb && c < kb) {
+      A[(int64_t)c * F + i] = X[i][c];
+      gmax = fmaxf(gmax, (float)sqrt(fmax(cabs2(X[i][c]), cabs2(D[i][c]))));
+    }
+  }
+  if (fn > 0.f) {
+    if (tid < kb) {
+      const float u = (float)sqrt(cabs2(X[tid][tid]));
+      const float ratio = u / fn;
+      if (!(ratio >= mf.piv_tol)) {
+        atomicCAS(mf.info, 0, fi + 1);
+        atomicExch(mf.info + 10, 1);
+      }
+      if (!(ratio >= mf.piv_warn)) atomicAdd(mf.info + 9, 1);
+      if (ratio >= 0.f) atomicMin(mf.pstat + 1, __float_as_uint(ratio));
+    }
+    for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
+    if ((tid & 63) == 0) atomicMax(mf.pstat, __float_as_uint(gmax / fn));
   }
   C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
   tri_inv32<R>(X, Li, Li + kDB * kDB, kb);
@@ -1821,6 +1865,11 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     extend_add_kernel<R><<<grid, 256, 0, st>>>(mf, arena, f0, s, cols);
     SPP_LAUNCH_CHECK();
   }
+  if (!partial_pivoting) {
+    const int cols = 16;
+    front_norm_kernel<R><<<dim3(ceil_div(maxF, cols), nf), 256, 0, st>>>(mf, arena, f0, cols);
+    SPP_LAUNCH_CHECK();
+  }
   const int steps = (maxP + kNB - 1) / kNB;
   const int tiles = (int)ceil_div(maxF, kBM);
   const int tiles128 = (int)ceil_div(maxF, 128);   // tall / wide tiles of modes 3 and 7
@@ -1976,10 +2025,10 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
             fl += 2 * 8.0 * nbv * h * (h + nbv) / 2;   // both triangles, products cut to the nonzero half
           }
       for (int phase = 0; phase < 2; ++phase) {   // (the two phases have equal flops)
-        timer_begin(KC_GEMM, st);
+        timer_begin(KC_INV, st);
         inv_gemm_kernel<R><<<dim3(ht * ht, nf, 2 * pairs), 256, 0, st>>>(mf, arena, xwork, tbuf, f0, h, phase, ht);
         SPP_LAUNCH_CHECK();
-        timer_end(KC_GEMM, st, 0.0, fl / 2);
+        timer_end(KC_INV, st, 0.0, fl / 2);
       }
     }
   } else {
@@ -2008,10 +2057,10 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     if (g_timer)
       for (int i = 0; i < nf; ++i) fl += 8.0 * (hF[i] - hP[i]) * (double)hP[i] * hP[i];
     const int tiles_m = (int)ceil_div(std::max(maxK, maxP), kBM);
-    timer_begin(KC_GEMM, st);
+    timer_begin(KC_INV, st);
     inv_side_kernel<R><<<dim3(tiles_m * tiles_m, nf, 2), 256, 0, st>>>(mf, arena, xwork, f0, tiles_m);
     SPP_LAUNCH_CHECK();
-    timer_end(KC_GEMM, st, 0.0, fl);
+    timer_end(KC_INV, st, 0.0, fl);
   }
   const int64_t merge_items = std::max<int64_t>((int64_t)maxP * maxP, (int64_t)maxK * maxP);
   merge_inverse_kernel<R><<<dim3(ceil_div(merge_items, 256 * 4), nf), 256, 0, st>>>(mf, arena, xwork, f0, maxK > 0);

@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <sstream>
 
@@ -383,6 +384,70 @@ std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std:
     L.end = static_cast<int>(out.fronts.size());
     L.blk_end = static_cast<int>(out.blocks.size());
     out.levels.push_back(L);
+  }
+  return std::string();
+}
+
+std::string build_tables(const Plan& P, const std::vector<int>& front_inst, PlanTables& T) {
+  T = PlanTables();
+  if (front_inst.size() != P.fronts.size()) return "front_inst size mismatch";
+  T.fronts.resize(P.fronts.size());
+  std::vector<int> parent(P.fronts.size(), -1);
+  for (size_t fi = 0; fi < P.fronts.size(); ++fi)
+    for (int c : P.fronts[fi].children) parent[c] = static_cast<int>(fi);
+  for (const Level& L : P.levels) {
+    // Inverse work slots for every level (the precision decides which
+    // levels use them): XL, XU (p x p each), then Lt, Ut ((F - p) x p each).
+    int64_t xo = 0;
+    double e0 = 0, e1 = 0, e2 = 0;
+    std::vector<int> hF, hP;
+    for (int fi = L.begin; fi < L.end; ++fi) {
+      const Front& f = P.fronts[fi];
+      FrontTable& g = T.fronts[fi];
+      g.off = f.off; g.voff = f.voff; g.xoff = xo;
+      g.F = f.F; g.p = f.p; g.idx = f.idx; g.map = f.map; g.perm = T.perm_total;
+      g.dblk = T.dblk_total;
+      g.inst = front_inst[fi];
+      g.parent = parent[fi];
+      T.dblk_total += (f.p + 31) / 32;
+      g.nchild = static_cast<int>(f.children.size());
+      if (g.nchild > 8) return "more than 8 children";
+      for (int c = 0; c < g.nchild; ++c) g.child[c] = f.children[c];
+      T.perm_total += f.p;
+      xo += 2LL * f.p * f.F;
+      e0 += 0.5 * f.p * (f.p - 1.0);
+      e1 += 0.5 * f.p * (f.p + 1.0);
+      e2 += (double)(f.F - f.p) * f.p;
+      hF.push_back(f.F);
+      hP.push_back(f.p);
+    }
+    T.level_ent.insert(T.level_ent.end(), {e0, e1, e2});
+    T.level_F.push_back(hF);
+    T.level_p.push_back(hP);
+    T.xwork_elems = std::max(T.xwork_elems, xo);
+  }
+  // Children's boundary rows by parent position (counting sort, children in
+  // order, so a position's sum keeps the order of the plain gather).
+  for (size_t fi = 0; fi < P.fronts.size(); ++fi) {
+    const Front& f = P.fronts[fi];
+    T.fronts[fi].gptr = static_cast<int>(T.gptr.size());
+    std::vector<int> cnt(f.F + 1, 0);
+    for (int c : f.children) {
+      const Front& ch = P.fronts[c];
+      for (int jj = 0; jj < ch.F - ch.p; ++jj)
+        if (P.map[ch.map + jj] >= 0) ++cnt[P.map[ch.map + jj] + 1];
+    }
+    for (int i = 0; i < f.F; ++i) cnt[i + 1] += cnt[i];
+    const int64_t base = static_cast<int64_t>(T.gsrc.size());
+    for (int i = 0; i <= f.F; ++i) T.gptr.push_back(static_cast<int>(base + cnt[i]));
+    T.gsrc.resize(T.gsrc.size() + cnt[f.F]);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int c : f.children) {
+      const Front& ch = P.fronts[c];
+      for (int jj = 0; jj < ch.F - ch.p; ++jj)
+        if (P.map[ch.map + jj] >= 0) T.gsrc[base + fill[P.map[ch.map + jj]]++] = ch.voff + ch.p + jj;
+    }
+    if (T.gsrc.size() > (size_t)INT32_MAX) return "plan too large";
   }
   return std::string();
 }

@@ -71,6 +71,39 @@ struct Plan {
   int max_front = 0;
 };
 
+// Host form of the per-front descriptor the kernels read (FrontDev), plus the
+// other flat tables derived from a plan.  Every index a kernel forms from a
+// front lies inside one of these ranges (tests/plan_check.cpp checks them).
+struct FrontTable {
+  int64_t off = 0;     // F x F front in the arena
+  int64_t voff = 0;    // solve-vector slot (F positions)
+  int64_t xoff = 0;    // inverse work slot (2 p F), relative to its level's base
+  int F = 0, p = 0;
+  int idx = 0;         // Plan::idx offset (F global points)
+  int map = 0;         // Plan::map offset (F - p parent positions)
+  int perm = 0;        // p permutation entries
+  int dblk = 0;        // ceil(p / 32) diagonal-block inverse slots
+  int inst = 0;        // problem of a batch
+  int parent = -1;
+  int nchild = 0;
+  int child[8] = {0};
+  int gptr = 0;        // F + 1 offsets into PlanTables::gsrc
+};
+
+struct PlanTables {
+  std::vector<FrontTable> fronts;
+  std::vector<int> gptr;            // per front F + 1 offsets into gsrc
+  std::vector<int64_t> gsrc;        // vector-arena slot of each child boundary row
+  std::vector<double> level_ent;    // per level: sum p(p-1)/2, p(p+1)/2, (F-p)p
+  std::vector<std::vector<int>> level_F, level_p;
+  int perm_total = 0;
+  int dblk_total = 0;
+  int64_t xwork_elems = 0;          // largest per-level inverse work
+};
+
+// Builds the tables of a plan (front_inst: problem of each front).
+std::string build_tables(const Plan& P, const std::vector<int>& front_inst, PlanTables& T);
+
 // Checks d in {2,3}, n even, b | n and n / b a power of two >= 2; returns an
 // empty string if valid, else a message.
 std::string validate_grid(int d, int n, int b);

@@ -38,8 +38,14 @@ def test_error_strings():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(binding.spp_problem) == 48
     assert binding.spp_problem.coeff.offset == 40
-    assert ctypes.sizeof(binding.spp_options) == 24
+    assert ctypes.sizeof(binding.spp_options) == 56
+    assert binding.spp_options.restart.offset == 24
+    assert binding.spp_options.alloc.offset == 32
+    assert binding.spp_options.alloc_ctx.offset == 48
     assert binding.spp_stats_t.breakdown_front.offset == 76
+    assert binding.spp_stats_t.pivot_growth.offset == 88
+    assert binding.spp_stats_t.small_pivots.offset == 112
+    assert ctypes.sizeof(binding.spp_stats_t) == 120
 
 
 @pytest.mark.parametrize("dim,n,b", [(4, 32, 8), (2, 30, 8), (2, 48, 16), (2, 32, 32), (2, 7, 1), (2, 96, 8)])
@@ -63,7 +69,8 @@ def test_setup_rejects_null_and_bad_options():
     assert e.value.code == spp.SPP_EINVAL
     coeff = np.ones(32 * 32)
     pb.coeff = coeff.ctypes.data
-    for bad in (dict(tol=0.0), dict(max_iter=0), dict(prec=5), dict(order=9)):
+    for bad in (dict(tol=0.0), dict(max_iter=0), dict(prec=5), dict(order=9), dict(restart=-1),
+                dict(restart=501), dict(reserved=1)):
         o = binding.spp_options(prec=0, order=0, tol=1e-8, max_iter=10, flags=0)
         for k, v in bad.items():
             setattr(o, k, v)
@@ -82,3 +89,26 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.spp_apply_operator(None, None, None, 1, None) == spp.SPP_EINVAL
     assert lib.spp_stats(None, None) == spp.SPP_EINVAL
     lib.spp_destroy(None)
+
+
+def test_setup_rejects_half_an_allocator_hook():
+    """alloc and free come together or not at all (checked before any GPU call)."""
+    coeff = np.ones(32 * 32)
+    pb = binding.spp_problem(dim=2, n=32, b=8, kind=0, omega=1.0, ell=1.0, energy=0.0, coeff=coeff.ctypes.data)
+    op = binding.spp_options(prec=0, order=0, tol=1e-8, max_iter=10, flags=0)
+    op.alloc = binding.ALLOC_FN(lambda n, ctx: None)
+    with pytest.raises(spp.SppError) as e:
+        spp.spp_setup(pb, op, 0)
+    assert e.value.code == spp.SPP_EINVAL
+
+
+def test_attach_cnn_and_batch_solve_reject_bad_arguments():
+    lib = spp.library()
+    # rho must be in (0, 1): with rho = 1 every network step would be kept
+    fake_net = ctypes.c_void_p(8)   # never dereferenced: rho is checked first
+    for rho in (1.0, 0.0, 1.5, float("nan")):
+        assert lib.spp_attach_cnn(None, fake_net, ctypes.c_double(rho)) == spp.SPP_EINVAL
+        assert "rho" in spp.spp_last_error()
+    assert lib.spp_attach_cnn(None, fake_net, ctypes.c_double(0.5)) == spp.SPP_EINVAL
+    assert "null factor" in spp.spp_last_error()
+    assert lib.spp_solve_batch(None, None, None, None, None, None, None) == spp.SPP_EINVAL

@@ -174,6 +174,18 @@ def large_2d(nrhs: int = 1) -> Workload:
     return helmholtz_workload("helmholtz2d_n512_w64", 2, 512, 2, 64.0, 64, 0.05, 16, nrhs=nrhs, tol=1e-8)
 
 
+def large_2d_delta() -> Workload:
+    """The 512^2 medium of ``large_2d`` driven by a unit grid delta at the
+    centre j = (n/2, n/2), the source of the paper's examples (Section 3).
+    A delta excites the propagating band |k| ~ omega / (2 pi) fully, so the
+    solution is a field radiating through the whole domain (the Gaussian of
+    ``large_2d`` has no content there and its solution stays local)."""
+    W = large_2d()
+    W.name = "helmholtz2d_n512_w64_delta"
+    W.rhs = grid_delta(W.n, W.d, (W.n // 2, W.n // 2))[None]
+    return W
+
+
 def small(n: int, d: int, b: int, waves: float, bumps: int = 4, width: float = 0.08,
           nrhs: int = 1, instance: int = 0, tol: float = 1e-10) -> Workload:
     """Small Helmholtz case for unit tests (any n, d, b)."""
