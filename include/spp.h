@@ -228,6 +228,19 @@ int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream);
 int spp_apply_operator(spp_factor* factor, const void* z, void* w, int32_t nrhs,
                        spp_stream_t stream);
 
+/* w = (I + G q) z exactly as spp_apply_operator computes it (same kernels),
+   for callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the FFT
+   intermediate lives in a library-owned static device scratch of 64 MiB per
+   GPU instead of the factor's grown work buffers, and the call makes no
+   allocation.  z, w DEVICE complex128 [nrhs][n^d] in the batch layout; may
+   alias.  Requires nrhs * (sum of n_i^d) * 16 bytes <= 64 MiB, else
+   SPP_EINVAL.  Every call on a GPU shares that GPU's scratch, so calls that
+   overlap on one GPU (different streams or threads) race; calls ordered on
+   one stream do not.  No kernel timing is recorded. */
+int spp_apply_operator_noalloc(spp_factor* factor, const void* z, void* w, int32_t nrhs,
+                               spp_stream_t stream);
+
 /* g = G f (eq. G); DEVICE complex128 [nrhs][n^d]; may alias. */
 int spp_apply_green(spp_factor* factor, const void* f, void* g, int32_t nrhs,
                     spp_stream_t stream);

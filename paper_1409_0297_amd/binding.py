@@ -82,6 +82,7 @@ def library():
         "spp_solve_batch": (I, [P, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(P), ctypes.POINTER(I),
                                 ctypes.POINTER(D), P]),
         "spp_apply_operator": (I, [P, P, P, I, P]),
+        "spp_apply_operator_noalloc": (I, [P, P, P, I, P]),
         "spp_apply_green": (I, [P, P, P, I, P]),
         "spp_apply_q": (I, [P, P, P, I, P]),
         "spp_apply_precond": (I, [P, P, P, I, P]),
@@ -222,6 +223,10 @@ def _apply(name, handle, a_ptr, b_ptr, nrhs, stream):
 
 def spp_apply_operator(handle, z_ptr, w_ptr, nrhs, stream):
     _apply("spp_apply_operator", handle, z_ptr, w_ptr, nrhs, stream)
+
+
+def spp_apply_operator_noalloc(handle, z_ptr, w_ptr, nrhs, stream):
+    _apply("spp_apply_operator_noalloc", handle, z_ptr, w_ptr, nrhs, stream)
 
 
 def spp_apply_green(handle, f_ptr, g_ptr, nrhs, stream):

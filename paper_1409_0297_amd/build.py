@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspp.so")
-SOURCES = ["api.cpp", "plan.cpp", "fft.hip", "stencil.hip", "mf.hip", "krylov.hip", "cnn.hip", "tune.cpp"]
+SOURCES = ["api.cpp", "plan.cpp", "fft.hip", "stencil.hip", "mf.hip", "krylov.hip", "cnn.hip", "tune.cpp", "scratch.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

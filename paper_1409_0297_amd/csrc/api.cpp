@@ -1240,6 +1240,31 @@ int spp_apply_operator(spp_factor* factor, const void* z, void* w, int32_t nrhs,
   });
 }
 
+int spp_apply_operator_noalloc(spp_factor* factor, const void* z, void* w, int32_t nrhs, spp_stream_t stream) {
+  return guarded([&] {
+    if (!factor || !z || !w || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");
+    const size_t need = sizeof(double2) * (size_t)nrhs * (size_t)factor->Ntot;
+    if (need > kNoAllocScratchBytes)
+      throw Error(SPP_EINVAL, "spp_apply_operator_noalloc: nrhs * N * 16 = " + std::to_string(need) +
+                                  " bytes exceeds the scratch of " + std::to_string(kNoAllocScratchBytes) + " bytes");
+    // The FFT intermediate goes to the library's static device scratch; no
+    // buffer of the factor is grown and no kernel timer is recorded.
+    double2* tmp = static_cast<double2*>(noalloc_scratch());
+    KernelTimer* saved = g_timer;
+    g_timer = nullptr;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const double2* zz = static_cast<const double2*>(z);
+    double2* ww = static_cast<double2*>(w);
+    for (const SppGroup& g : factor->groups) {
+      const int64_t o = g.Noff * nrhs;
+      fft_multi(st, zz + o, ww + o, tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, factor->q + g.Noff,
+                factor->sigma + g.Noff, zz + o, nrhs);
+    }
+    g_timer = saved;
+    return SPP_OK;
+  });
+}
+
 int spp_apply_green(spp_factor* factor, const void* f, void* g, int32_t nrhs, spp_stream_t stream) {
   return guarded([&] {
     if (!factor || !f || !g || nrhs < 1) throw Error(SPP_EINVAL, "null argument or nrhs < 1");

@@ -234,6 +234,13 @@ void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena, void* W, void* 
 int gemv_chunks_default(int rows, int cols, int nf, int nrhs, int64_t partial_cap);
 std::string gemv_tune_key(int rows, int cols, int nf, int mode, int nrhs, int csize);
 
+// ------------------------------------------------------------- scratch.hip
+// Device scratch of the no-allocation entry points: kNoAllocScratchBytes per
+// GPU in a file-scope device array; noalloc_scratch() returns its device
+// address on the current device (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+void* noalloc_scratch();
+
 // ------------------------------------------------------------- cnn.hip
 // Learned preconditioner stage: y = out_scale * net(in_scale * x) per sample,
 // x, y complex128 [batch][n^2].
