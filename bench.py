@@ -246,6 +246,48 @@ def batch_record(args, steps, warmup, precs):
     return rec
 
 
+def record_3d(args):
+    """One timed step of the 3D Helmholtz configuration: 128^3, omega = 2 pi 16
+    (8 points per wavelength), 32 Gaussian bumps of width 0.06, b = 8 (8^3
+    leaf boxes), bisection ordering, complex64 fronts in streamed storage,
+    FP64 FGMRES; setup + solve of 4 Gaussian sources to the bench tolerance.
+    The step runs once, without a warm-up (it holds about 230 GB while it
+    runs); its time includes building the host plan of this geometry."""
+    import torch
+
+    import workloads
+    import paper_1409_0297_amd as spp
+
+    W = workloads.helmholtz_3d(128, 8, nrhs=4)
+    dev = torch.device("cuda:0")
+    coeff = torch.as_tensor(W.coeff, dtype=torch.float64, device=dev).contiguous()
+    f = torch.as_tensor(W.rhs.reshape(4, -1), dtype=torch.complex128, device=dev).contiguous()
+    u = torch.empty_like(f)
+    stream = torch.cuda.current_stream().cuda_stream
+    pb = spp.binding.spp_problem(dim=3, n=W.n, b=W.b, kind=spp.SPP_HELMHOLTZ, omega=W.omega, ell=1.0, energy=0.0,
+                                 coeff=coeff.data_ptr())
+    op = spp.binding.spp_options(prec=spp.SPP_C64_FRONTS, order=spp.SPP_ORDER_BISECT, tol=args.tol, max_iter=80,
+                                 flags=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = spp.spp_setup(pb, op, stream)
+    code, iters, relres = spp.spp_solve(h, f.data_ptr(), 4, u.data_ptr(), stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = spp.spp_stats(h)
+    spp.spp_destroy(h)
+    del u, f, coeff
+    torch.cuda.empty_cache()
+    return {"workload": W.name, "grid": [W.n] * 3, "omega_over_2pi": 16, "b": W.b, "bumps": 32, "nrhs": 4,
+            "ordering": "bisect", "fronts": "c64", "storage": "streamed" if st["storage"] else "resident",
+            "tol": args.tol, "steps": 1, "warmup": 0, "value": 4.0 / dt, "unit": "solves/s", "s_per_step": dt,
+            "code": code, "gmres_iters": iters, "relres_max": max(relres), "t_setup_ms": st["t_setup_ms"],
+            "t_factor_ms": st["t_factor_ms"], "t_solve_ms": st["t_solve_ms"], "factor_gb": st["factor_bytes"] / 1e9,
+            "factor_tflop": st["factor_flops"] / 1e12,
+            "factor_tflops_achieved": st["factor_flops"] / (st["t_factor_ms"] / 1e3) / 1e12,
+            "max_front": st["max_front"]}
+
+
 def batch_main(args):
     rec = batch_record(args, args.steps, args.warmup, [args.prec, "c128" if args.prec == "c64" else "c64"])
     out = {
@@ -350,6 +392,9 @@ def main():
                 "steps": args.steps, "warmup": 1}
             print("bench: timing the batched Schroedinger family", file=sys.stderr, flush=True)
             records["schrodinger_batch"] = batch_record(args, 3, 1, [args.prec])
+            print("bench: timing one step of the 3D 128^3 configuration (about a minute)", file=sys.stderr,
+                  flush=True)
+            records["helmholtz3d_128"] = record_3d(args)
     out = {
         "metric": "solves/sec to rel. err 1e-8 (mixed vs FP64), GMRES iters, HBM/MFMA % peak",
         "value": 1.0 / dt,

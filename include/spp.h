@@ -93,6 +93,14 @@ typedef struct {
                                      instead of L21 L11^-1 and U11^-1 U12 (one
                                      product per level and direction): less
                                      setup work, more launches per solve      */
+#define SPP_F_STREAMED 128        /* streamed front storage even where every
+                                     front would fit: the arena holds the
+                                     fronts of two adjacent levels, factors
+                                     go to a compact store (p^2 + 2 p (F - p)
+                                     entries per front).  Chosen by itself
+                                     when the sum of F^2 over all fronts
+                                     would exceed 85% of free device memory
+                                     (3D grids such as 128^3)                  */
 #define SPP_F_GRAPHS 8            /* capture one FGMRES iteration in a HIP graph
                                      (once per factor and nrhs) and replay it
                                      with the step index in device memory;

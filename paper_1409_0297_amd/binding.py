@@ -23,6 +23,7 @@ SPP_F_GRAPHS = 8
 SPP_F_PERSISTENT = 16
 SPP_F_AUTOTUNE = 32
 SPP_F_NO_SIDE = 64
+SPP_F_STREAMED = 128
 SPP_K_FFT, SPP_K_GEMV, SPP_K_TRI, SPP_K_GEMM, SPP_K_PANEL, SPP_K_QAPPLY = 0, 1, 2, 3, 4, 5
 SPP_K_INV, SPP_K_SOLVE_BLK = 6, 7
 KERNEL_CLASSES = {"fft": 0, "gemv": 1, "tri": 2, "gemm": 3, "panel": 4, "qapply": 5, "inv": 6, "solve_blk": 7}
@@ -297,7 +298,7 @@ class Solver:
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
                  timing: bool = False, partial_pivoting: bool = False, graphs: bool = False,
                  persistent: bool = False, autotune: bool = False, side_products: bool = True,
-                 restart: int = 0, allocator: "TorchAllocator" = None):
+                 restart: int = 0, allocator: "TorchAllocator" = None, streamed: bool = False):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -316,7 +317,8 @@ class Solver:
                          | (SPP_F_GRAPHS if graphs else 0)
                          | (SPP_F_PERSISTENT if persistent else 0)
                          | (SPP_F_AUTOTUNE if autotune else 0)
-                         | (0 if side_products else SPP_F_NO_SIDE), restart=restart)
+                         | (0 if side_products else SPP_F_NO_SIDE)
+                         | (SPP_F_STREAMED if streamed else 0), restart=restart)
         self._allocator = allocator
         if allocator is not None:
             allocator.install(op)

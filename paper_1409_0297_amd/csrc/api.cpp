@@ -172,7 +172,7 @@ struct PlanDevice {
 std::mutex g_plan_mu;
 // Never destroyed: device memory of cached plans is released with the process,
 // not by a static destructor running after the HIP runtime has shut down.
-auto& g_plans = *new std::map<std::pair<int, std::vector<Geom>>, std::shared_ptr<PlanDevice>>();
+auto& g_plans = *new std::map<std::tuple<int, int, std::vector<Geom>>, std::shared_ptr<PlanDevice>>();
 auto& g_host_plans = *new std::map<Geom, std::shared_ptr<Plan>>();
 
 // Host plan of one geometry (caller holds g_plan_mu).
@@ -191,10 +191,11 @@ std::shared_ptr<Plan> host_plan(const Geom& g) {
   return host_plan_locked(g);
 }
 
-std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
+// storage: 0 resident, 1 streamed (layout_plan).
+std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms, int storage) {
   int dev = 0;
   SPP_HIP(hipGetDevice(&dev));
-  const auto key = std::make_pair(dev, geoms);
+  const auto key = std::make_tuple(dev, storage, geoms);
   std::lock_guard<std::mutex> lock(g_plan_mu);
   auto it = g_plans.find(key);
   if (it != g_plans.end()) return it->second;
@@ -213,6 +214,7 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
     std::string err = combine_plans(raw, pd->plan, pd->front_inst);
     if (!err.empty()) throw Error(SPP_EINVAL, err);
   }
+  layout_plan(pd->plan, storage);
   const Plan& P = pd->plan;
   PlanTables tab;
   {
@@ -224,6 +226,7 @@ std::shared_ptr<PlanDevice> get_plan(const std::vector<Geom>& geoms) {
     const FrontTable& t = tab.fronts[fi];
     FrontDev& g = fd[fi];
     g.off = t.off; g.voff = t.voff; g.xoff = t.xoff;
+    g.foff = t.foff; g.uoff = t.uoff; g.ldu = t.ldu;
     g.F = t.F; g.p = t.p; g.idx = t.idx; g.map = t.map; g.perm = t.perm; g.dblk = t.dblk;
     g.inst = t.inst; g.parent = t.parent; g.nchild = t.nchild;
     for (int c = 0; c < 8; ++c) g.child[c] = t.child[c];
@@ -296,9 +299,13 @@ struct spp_factor {
   std::map<int, double2*> tw_by_n;
   InstDev* inst_dev = nullptr;
   MfDev mf{};
-  void* arena = nullptr;
+  void* arena = nullptr;       // front arena (released after a streamed factorisation)
+  void* fstore = nullptr;      // factor store (streamed storage)
+  void* fac = nullptr;         // what the substitution reads: arena or fstore
+  void* dkeep = nullptr;       // diagonal-block inverses of blocked levels
   size_t csize = 16;  // bytes per complex front entry
   std::vector<int> level_begin, level_maxF, level_maxK, level_maxP, level_form;
+  int64_t xwork_elems = 0;     // inverse work of the levels solved by products
   void* gpart = nullptr;       // split-K partial sums of the substitution
   int64_t gpart_cap = 0;
   // solve work (grown on demand)
@@ -371,6 +378,17 @@ struct spp_factor {
     if (!p) throw Error(SPP_ENOMEM, "the allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
     hook_blocks.push_back(p);
     return p;
+  }
+  void big_free(void* p) {
+    if (!p) return;
+    auto it = std::find(hook_blocks.begin(), hook_blocks.end(), p);
+    if (it != hook_blocks.end()) {
+      (void)hipDeviceSynchronize();
+      hook_blocks.erase(it);
+      opt.free(p, opt.alloc_ctx);
+      return;
+    }
+    dfree(p);
   }
   ~spp_factor() {
     drop_graph();
@@ -517,10 +535,10 @@ void precond_tail(spp_factor* F, double2* z, int nrhs, hipStream_t st, bool pers
   const int nl = static_cast<int>(F->planp->levels.size());
   const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
-    mf_solve<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
+    mf_solve<double>(st, F->mf, F->fac, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
                      F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
   } else {
-    mf_solve<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
+    mf_solve<float>(st, F->mf, F->fac, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
                     F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
     cast_vectors<float>(st, F->xc, z, (int64_t)nrhs * F->Ntot, 1);
   }
@@ -594,7 +612,9 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
     const int nf = L.end - L.begin, mP = L.maxP, mF = L.maxF, mK = L.maxK;
     struct Prod { int rows, cols, mode; };
     std::vector<Prod> prods;
-    if (F->level_form[l] == kFormSide) {
+    if (F->level_form[l] == kFormBlocked) {
+      if (mK > 0) prods = {{mK, mP, 1}, {mP, mK, 2}};
+    } else if (F->level_form[l] == kFormSide) {
       prods = {{mF, mP, 4}, {mP, mF, 5}};
     } else {
       prods = {{mP, mP, 0}, {mP, mP, 3}};
@@ -609,10 +629,10 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
         if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
         const float t = tune_time(st, 3, [&] {
           if (F->opt.prec == SPP_C128)
-            mf_gemv<double>(st, F->mf, F->arena, F->wv, F->zv, F->qr, F->qr, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
+            mf_gemv<double>(st, F->mf, F->fac, F->wv, F->zv, F->qr, F->qr, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
                             0.0, F->gpart, F->gpart_cap, c);
           else
-            mf_gemv<float>(st, F->mf, F->arena, F->wv, F->zv, F->xc, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
+            mf_gemv<float>(st, F->mf, F->fac, F->wv, F->zv, F->xc, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
                            0.0, F->gpart, F->gpart_cap, c);
         }, flush, flush_bytes);
         if (t < bt) { bt = t; best = c; }
@@ -652,7 +672,23 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   TimerScope timer_scope(F.get());
   std::vector<Geom> geoms;
   for (int i = 0; i < count; ++i) geoms.emplace_back(pbs[i].dim, pbs[i].n, pbs[i].b, op->order);
-  F->pd = get_plan(geoms);
+  // Storage: every front resident unless asked for, or unless the resident
+  // arena (sum of F^2 over all fronts) would not fit in 85% of what the
+  // device has left.
+  int storage = (op->flags & SPP_F_STREAMED) ? 1 : 0;
+  if (!storage) {
+    int64_t resident = 0;
+    for (const Geom& g : geoms) resident += host_plan(g)->arena_elems;
+    size_t freeb = 0, totalb = 0;
+    SPP_HIP(hipMemGetInfo(&freeb, &totalb));
+    size_t cached = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_mem_mu);
+      cached = g_mem_cached;
+    }
+    if ((double)resident * F->csize > 0.85 * (double)(freeb + cached)) storage = 1;
+  }
+  F->pd = get_plan(geoms, storage);
   F->planp = &F->pd->plan;
   const Plan& P = *F->planp;
 
@@ -690,8 +726,18 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       stencil_elems += w;
       Nmax_ = std::max(Nmax_, I.N);
     }
+    for (const Level& L : P.levels) {
+      int form = mf_level_solve_form(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS, P.storage == 1);
+      if (form == kFormSide && (op->flags & SPP_F_NO_SIDE)) form = kFormInverse;
+      F->level_form.push_back(form);
+      if (form == kFormInverse || form == kFormSide) {
+        int64_t xo = 0;
+        for (int fi = L.begin; fi < L.end; ++fi) xo += 2LL * P.fronts[fi].p * P.fronts[fi].F;
+        F->xwork_elems = std::max(F->xwork_elems, xo);
+      }
+    }
     const size_t cs = F->csize;
-    const size_t need = (size_t)P.arena_elems * cs + (size_t)F->pd->xwork_elems * cs * 3 / 2 +
+    const size_t need = ((size_t)P.arena_elems + (size_t)P.fstore_elems) * cs + (size_t)F->xwork_elems * cs * 3 / 2 +
                         (size_t)2 * 32 * 32 * F->pd->dblk_total * cs + sizeof(double2) * stencil_elems +
                         sizeof(double) * 2 * (size_t)F->Ntot + sizeof(double2) * 4 * (size_t)Nmax_ +
                         sizeof(int) * 3 * (size_t)F->pd->perm_total + sizeof(unsigned) * P.fronts.size();
@@ -827,31 +873,50 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     F->level_maxP.push_back(L.maxP);
   }
   F->level_begin.push_back(static_cast<int>(P.fronts.size()));
-  for (const Level& L : P.levels) {
-    int form = mf_level_solve_form(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS);
-    if (form == kFormSide && (op->flags & SPP_F_NO_SIDE)) form = kFormInverse;
-    F->level_form.push_back(form);
-  }
-
-  F->arena = F->big_alloc((size_t)P.arena_elems * F->csize);
-  void* xwork = F->dalloc<char>((size_t)F->pd->xwork_elems * F->csize);
-  void* tbuf = F->dalloc<char>((size_t)(F->pd->xwork_elems / 2) * F->csize);
+  bool any_blocked = false;
+  for (int form : F->level_form) any_blocked = any_blocked || form == kFormBlocked;
   const bool partial_pivoting = (F->opt.flags & SPP_F_PARTIAL_PIVOTING) != 0;
+
+  const bool streamed = P.storage == 1;
+  F->arena = F->big_alloc((size_t)P.arena_elems * F->csize);
+  if (streamed) F->fstore = F->big_alloc((size_t)P.fstore_elems * F->csize);
+  F->fac = streamed ? F->fstore : F->arena;
+  void* xwork = F->dalloc<char>((size_t)F->xwork_elems * F->csize);
+  void* tbuf = F->dalloc<char>((size_t)(F->xwork_elems / 2) * F->csize);
   void* dinv = F->dalloc<char>((size_t)2 * 32 * 32 * F->pd->dblk_total * F->csize);
+  if (any_blocked) {
+    F->dkeep = dinv;
+    mf.dkeep = dinv;
+  }
   SPP_HIP(hipStreamSynchronize(st));
   for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p);
   const double tf0 = now_ms();
-  SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
+  if (!streamed) SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
   for (size_t l = 0; l < P.levels.size(); ++l) {
     const Level& L = P.levels[l];
     const int* hF = F->pd->level_F[l].data();
     const int* hP = F->pd->level_p[l].data();
+    // Streamed storage: this level's arena range held fronts two levels
+    // down, whose Schur complements the level below has already added.
+    if (streamed)
+      SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + (size_t)L.arena_lo * F->csize, 0,
+                             (size_t)(L.arena_hi - L.arena_lo) * F->csize, st));
+    // Large pivot blocks pivot over all their fully-summed rows: pivots
+    // chosen inside 32-row blocks let the multipliers below the block, and
+    // with them the growth of the Schur updates, grow with the front.
+    const bool pp = partial_pivoting || F->level_form[l] == kFormBlocked;
     if (F->opt.prec == SPP_C128)
       mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                              L.max_children, F->level_form[l], partial_pivoting, hF, hP);
+                              L.max_children, F->level_form[l], pp, hF, hP);
     else
       mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                             L.max_children, F->level_form[l], partial_pivoting, hF, hP);
+                             L.max_children, F->level_form[l], pp, hF, hP);
+    if (streamed) {
+      if (F->opt.prec == SPP_C128)
+        mf_store_factors<double>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
+      else
+        mf_store_factors<float>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
+    }
   }
   int hinfo[16];
   unsigned hpstat[2];
@@ -861,8 +926,12 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   const double tf1 = now_ms();
   F->dfree(xwork);
   F->dfree(tbuf);
-  F->dfree(dinv);
+  if (!any_blocked) F->dfree(dinv);
   F->dfree(swork);
+  if (streamed) {   // the substitution reads the factor store only
+    F->big_free(F->arena);
+    F->arena = nullptr;
+  }
   for (int t = 0; t < 8; ++t)
     if (hinfo[1 + t]) throw Error(SPP_EBREAKDOWN, "singular Gram matrix in the stencil least-squares problem");
   F->stats.breakdown_front = hinfo[0] ? hinfo[0] - 1 : -1;
@@ -878,7 +947,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   F->stats.t_setup_ms = now_ms() - t0;
   F->stats.last_iters = 0;
   F->stats.last_cycles = 0;
-  F->stats.storage = 0;
+  F->stats.storage = P.storage;
   {
     float g, mp;
     std::memcpy(&g, &hpstat[0], sizeof(float));

@@ -71,6 +71,9 @@ size_t stencil_work_elems(const StencilDev& S);
 struct FrontDev {
   int64_t off;         // F x F front (column-major) in the arena
   int64_t voff;        // solve vector slot (positions)
+  int64_t foff;        // factor for the substitution: first p columns (ld F) ...
+  int64_t uoff;        // ... and U12 (p x (F - p), ld ldu), in the factor base
+  int ldu;             // (arena when resident, factor store when streamed)
   int64_t xoff;        // inverse work slot (2 p F: XL, XU, then Lt, Ut), relative to the level's work base
   int F, p;
   int idx;             // global indices of the F front points (pivots first)
@@ -125,6 +128,7 @@ struct MfDev {
   unsigned* pstat;     // [0] pivot growth, [1] smallest |u_kk| / fnorm (float bits)
   float piv_tol;       // breakdown threshold on |u_kk| / fnorm (1e3 FP64 eps)
   float piv_warn;      // small-pivot threshold (1e3 eps of the front precision)
+  const void* dkeep;   // 32 x 32 diagonal-block inverses kept for blocked levels
   const InstDev* inst; // device array, one entry per instance
   // Host-side summary (launch geometry).
   int ninst, d;
@@ -144,8 +148,16 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, 
 //                four matrix-vector products per level and solve;
 //  kFormSide:    as kFormInverse with L21 L11^{-1} and U11^{-1} U12 over the
 //                side blocks: one product per level and direction.
-constexpr int kFormLU = 0, kFormInverse = 1, kFormSide = 2;
-int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64);
+//  kFormBlocked: LU in place, 32-row block steps over all fronts of the level
+//                with the diagonal-block inverses kept from the factorisation
+//                (few large fronts, whose explicit inverses would be too big).
+constexpr int kFormLU = 0, kFormInverse = 1, kFormSide = 2, kFormBlocked = 3;
+int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64, bool streamed);
+
+// Streamed storage: copies each front's factor part of a level from its
+// working front in the arena to the factor store (see layout_plan).
+template <typename R>
+void mf_store_factors(hipStream_t st, const MfDev& mf, const void* arena, void* store, int f0, int nf, int maxF);
 
 // y = Q r for every instance of the batch (vectors in the batch layout);
 // y is complex64 (float2) with to_float, else complex128.

@@ -1267,8 +1267,21 @@ __global__ void merge_inverse_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, co
 
 // Final row permutation of each front's pivot block from the interchange
 // record: one workgroup per front, the bookkeeping done in LDS.
-__global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0) {
+// lds: the record and the permutation fit in LDS (2 p ints); else the
+// interchanges are replayed in place in the global permutation array.
+__global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0, int lds) {
   const FrontDev f = mf.fronts[f0 + blockIdx.x];
+  if (!lds) {
+    int* perm = mf.perm + f.perm;
+    for (int i = threadIdx.x; i < f.p; i += blockDim.x) perm[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int j = 0; j < f.p; ++j) {
+        const int r = ipiv[f.perm + j];
+        const int t = perm[j]; perm[j] = perm[r]; perm[r] = t;
+      }
+    return;
+  }
   extern __shared__ int sp[];
   int* perm = sp;
   int* piv = sp + f.p;
@@ -1281,6 +1294,30 @@ __global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0) {
     }
   __syncthreads();
   for (int i = threadIdx.x; i < f.p; i += blockDim.x) mf.perm[f.perm + i] = perm[i];
+}
+
+// Inverses of the 32 x 32 diagonal blocks of a factored pivot block (L unit
+// lower, U upper, rows in final pivot order) into their dinv slots, for the
+// blocked substitution of levels factored with full partial pivoting (the
+// block-local form writes them during the factorisation).  blockIdx.x =
+// diagonal block, blockIdx.y = front.
+template <typename R>
+__global__ void __launch_bounds__(256) diag_inv_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                       cplx_t<R>* __restrict__ dinv, int f0) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int k0 = blockIdx.x * kDB;
+  if (k0 >= f.p) return;
+  const int kb = min(kDB, f.p - k0);
+  __shared__ DiagLds<R> S;
+  const C* A = arena + f.off + (int64_t)k0 * f.F + k0;
+  for (int t = threadIdx.x; t < kDB * kDB; t += 256) {
+    const int c = t / kDB, i = t - c * kDB;
+    S.X[i][c] = (i < kb && c < kb) ? A[(int64_t)c * f.F + i] : cmake<C>(i == c ? 1 : 0, 0);
+  }
+  __syncthreads();
+  C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
+  tri_inv32<R>(S.X, Li, Li + kDB * kDB, kb);
 }
 
 // ------------------------------------------------------------------ Q apply
@@ -1391,7 +1428,9 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   if (row0 >= nrows) return;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int row = row0 + lane;
-  const C* A = arena + f.off;
+  const C* A = arena + f.foff;   // first p columns, leading dimension F
+  const C* U = arena + f.uoff;   // U12, leading dimension ldu
+  const int ldu = f.ldu;
   const int* idx = mf.idx + f.idx;
   const int* perm = mf.perm + f.perm;
   C* w = W + f.voff * nrhs;
@@ -1418,10 +1457,14 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   // included); the vector entries of a tile of kVT columns are staged in LDS
   // first (their gathers go through perm / idx), so the main loop only streams
   // the matrix, several loads in flight per lane.
-  const int64_t coff = (mode == 1) ? p + row : (mode == 2) ? (int64_t)p * F + row : row;
+  // (U12 columns, mode 2 and the columns j >= p of mode 5, come from U.)
+  const int64_t coff = (mode == 1) ? p + row : row;
   auto entry = [&](int j) {
     const bool use = live && j < jhi && ((mode == 0 || mode == 4) ? j < row : (mode == 3 || mode == 5) ? j >= row : true);
-    return use ? A[coff + (int64_t)j * F] : cmake<C>(0, 0);
+    if (!use) return cmake<C>(0, 0);
+    if (mode == 2) return U[(int64_t)j * ldu + row];
+    if (mode == 5 && j >= p) return U[(int64_t)(j - p) * ldu + row];
+    return A[coff + (int64_t)j * F];
   };
   // Each wave's first kPre columns are loaded before the first tile's vector
   // entries are gathered, so that the two latencies overlap.
@@ -1528,7 +1571,7 @@ __device__ inline void fwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   constexpr int BS = kTriBS;
   const FrontDev& f = mf.fronts[fi];
   const int F = f.F, p = f.p;
-  const C* A = arena + f.off;
+  const C* A = arena + f.foff;   // first p columns of the factor, leading dimension F
   const int* perm = mf.perm + f.perm;
   const int* idx = mf.idx + f.idx;
   const InstDev& I = mf.inst[f.inst];
@@ -1644,7 +1687,9 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
   constexpr int BS = kTriBS;
   const FrontDev& f = mf.fronts[fi];
   const int F = f.F, p = f.p, K = F - p;
-  const C* A = arena + f.off;
+  const C* A = arena + f.foff;   // pivot block (first p columns, leading dimension F)
+  const C* U = arena + f.uoff;   // U12, leading dimension ldu
+  const int ldu = f.ldu;
   const int* idx = mf.idx + f.idx;
   const C* z = Z + f.voff * nrhs;
   const InstDev& I = mf.inst[f.inst];
@@ -1693,7 +1738,7 @@ __device__ inline void bwd_front_body(const MfDev& mf, const cplx_t<R>* __restri
     for (int r = 0; r < NR; ++r) acc[r] = y[i * NR + r];
 #pragma unroll kStripUnroll<R>
     for (int j = 0; j < K; ++j) {
-      const C u = A[(int64_t)(p + j) * F + i];
+      const C u = U[(int64_t)j * ldu + i];
 #pragma unroll
       for (int r = 0; r < NR; ++r) cfms(acc[r], u, xb[j * NR + r]);
     }
@@ -1794,6 +1839,123 @@ __global__ void __launch_bounds__(256) front_levels_kernel(MfDev mf, const cplx_
   }
 }
 
+// ------------------------------------------------------------------ factor store
+// Streamed storage: after a level is factored, each front's factor part goes
+// from its F x F working front to the compact store: the first p columns
+// (L11 / U11 and L21, F rows each) to foff with leading dimension F, and
+// the U12 rows [0, p) of columns [p, F) to uoff with leading dimension p.
+// blockIdx.x = chunk of cols_per_wg columns, blockIdx.y = front.
+template <typename R>
+__global__ void __launch_bounds__(256) factor_store_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                           cplx_t<R>* __restrict__ store, int f0, int cols_per_wg) {
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int j0 = blockIdx.x * cols_per_wg;
+  if (j0 >= f.F) return;
+  const int j1 = min(f.F, j0 + cols_per_wg);
+  const cplx_t<R>* A = arena + f.off;
+  for (int j = j0; j < j1; ++j) {
+    const cplx_t<R>* src = A + (int64_t)j * f.F;
+    if (j < f.p) {
+      cplx_t<R>* dst = store + f.foff + (int64_t)j * f.F;
+      for (int i = threadIdx.x; i < f.F; i += blockDim.x) dst[i] = src[i];
+    } else {
+      cplx_t<R>* dst = store + f.uoff + (int64_t)(j - f.p) * f.ldu;
+      for (int i = threadIdx.x; i < f.p; i += blockDim.x) dst[i] = src[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ blocked substitution
+// Levels of a few large fronts keep their LU in place and go through the
+// pivot rows in 32-row block steps, each step one launch over all fronts of
+// the level: every workgroup forms the block's solution from the 32 x 32
+// inverse the diagonal-block LU left in dinv (a product of 32 x 32 by the
+// block's vector, repeated per workgroup instead of a separate launch),
+// and applies the block's columns to its own tile of 256 rows.
+//   forward (lower, unit diagonal, rows in pivot order):
+//     blk_perm:  z_piv = P w_piv   (w: the gathered front vector)
+//     step k:    y_k = Linv_kk z_k;  z_i -= L_ik y_k for rows i beyond block k
+//                (y_k kept in w's pivot part, copied to z after the last step)
+//     then w_bnd -= L21 z (gemv_kernel mode 1)
+//   backward (upper), after z -= U12 x_bnd (gemv_kernel mode 2):
+//     step k (last block first): x_k = Uinv_kk z_k, written to the grid
+//                vector; z_i -= U_ik x_k for rows i before block k.
+template <typename R>
+__global__ void blk_perm_kernel(MfDev mf, const cplx_t<R>* __restrict__ W, cplx_t<R>* __restrict__ Z, int nrhs,
+                                int f0, int copy_back) {
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= f.p * nrhs) return;
+  const int i = t / nrhs, r = t - i * nrhs;
+  const int src = copy_back ? i : mf.perm[f.perm + i];
+  Z[(f.voff + i) * nrhs + r] = W[(f.voff + src) * nrhs + r];
+}
+
+constexpr int kBlkRows = 256;
+
+template <typename R, int NR, bool FWD>
+__global__ void __launch_bounds__(256) blk_step_kernel(MfDev mf, const cplx_t<R>* __restrict__ fac,
+                                                       const cplx_t<R>* __restrict__ dinv, cplx_t<R>* __restrict__ W,
+                                                       cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout,
+                                                       int nrhs, int r0, int f0, int k0) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  const int F = f.F, p = f.p;
+  if (k0 >= p) return;
+  const int kb = min(kDB, p - k0);
+  // rows of this workgroup: beyond the block (forward) or before it (backward)
+  const int rlo = FWD ? k0 + kb : 0, rhi = FWD ? p : k0;
+  const int row0 = rlo + blockIdx.x * kBlkRows;
+  if (blockIdx.x > 0 && row0 >= rhi) return;
+  const int nr = min(NR, nrhs - r0);
+  const C* Dk = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB) + (FWD ? 0 : kDB * kDB);
+  C* z = Z + f.voff * nrhs;
+  __shared__ C zk[kDB][NR];
+  __shared__ C ys[kDB][NR];
+  const int tid = threadIdx.x;
+  if (tid < kDB * NR) {
+    const int i = tid / NR, r = tid - i * NR;
+    zk[i][r] = (i < kb && r < nr) ? z[(k0 + i) * nrhs + r0 + r] : cmake<C>(0, 0);
+  }
+  __syncthreads();
+  if (tid < kDB * NR) {
+    // y_i = sum_c inv(i, c) zk_c over the block (column-major 32 x 32; the
+    // entries beyond kb are not set, so the sum stops at kb)
+    const int i = tid / NR, r = tid - i * NR;
+    C acc = cmake<C>(0, 0);
+    if (i < kb)
+      for (int c = 0; c < kb; ++c) cfma(acc, Dk[c * kDB + i], zk[c][r]);
+    ys[i][r] = acc;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && tid < kb * NR) {
+    const int i = tid / NR, r = tid - i * NR;
+    if (r < nr) {
+      if (FWD) {
+        W[(f.voff + k0 + i) * nrhs + r0 + r] = ys[i][r];
+      } else {
+        const InstDev& I = mf.inst[f.inst];
+        xout[I.Noff * nrhs + (int64_t)(r0 + r) * I.N + mf.idx[f.idx + k0 + i]] = ys[i][r];
+      }
+    }
+  }
+  const int row = row0 + tid;
+  if (row >= rhi) return;
+  const C* A = fac + f.foff + (int64_t)k0 * F + row;   // column k0 + c at A + c F
+  C acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = (r < nr) ? z[row * nrhs + r0 + r] : cmake<C>(0, 0);
+#pragma unroll 8
+  for (int c = 0; c < kb; ++c) {
+    const C a = A[(int64_t)c * F];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cfms(acc[r], a, ys[c][r]);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (r < nr) z[row * nrhs + r0 + r] = acc[r];
+}
+
 // Sums the split-K partial products of gemv_kernel and applies the mode's
 // finishing step (see gemv_kernel).
 template <typename R>
@@ -1849,7 +2011,7 @@ template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* tbuf_v, void* dinv_v,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, int form,
                      bool partial_pivoting, const int* hF, const int* hP) {
-  const bool invert = form != kFormLU;
+  const bool invert = form == kFormInverse || form == kFormSide;
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
   C* xwork = static_cast<C*>(xwork_v);
@@ -2004,8 +2166,13 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     SPP_LAUNCH_CHECK();
   }
   if (partial_pivoting) {   // (the diagonal-block LU writes the permutation itself)
-    perm_kernel<<<nf, 256, 2 * sizeof(int) * maxP, st>>>(mf, mf.ipiv, f0);
+    const bool lds = (size_t)2 * sizeof(int) * maxP <= 65536;
+    perm_kernel<<<nf, 256, lds ? 2 * sizeof(int) * maxP : 0, st>>>(mf, mf.ipiv, f0, lds ? 1 : 0);
     SPP_LAUNCH_CHECK();
+    if (form == kFormBlocked) {
+      diag_inv_kernel<R><<<dim3(ceil_div(maxP, kDB), nf), 256, 0, st>>>(mf, arena, dinv, f0);
+      SPP_LAUNCH_CHECK();
+    }
   }
   if (!invert) return;
   // Inverses of L11 and U11 for levels solved by matrix-vector products.
@@ -2067,14 +2234,17 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   SPP_LAUNCH_CHECK();
 }
 
-int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64) {
+int mf_level_solve_form(int nfronts, int maxF, int maxP, bool c64, bool streamed) {
   // Explicit inverses turn every substitution step into row-parallel
   // matrix-vector products (many workgroups per front).  Building them costs
   // setup time: cheap on FP32 MFMA (complex64 fronts: always), dearer on
   // FP64, where levels with very many small fronts keep the LU in place and
   // run one workgroup per front (its vectors, (F + p) x 4 complex values,
   // within 64 KB of LDS).
-  if (nfronts >= 512 && maxP <= 512 && maxF + maxP <= 1024) return kFormLU;
+  if (nfronts >= 512 && maxP <= 512 && (int64_t)(maxF + maxP) * 4 * (c64 ? 8 : 16) <= 65536) return kFormLU;
+  // Large pivot blocks: their inverse work (2 p F per front) would rival the
+  // factor itself, so they keep the LU and go in block steps.
+  if (maxP > (streamed ? 1024 : 4096)) return kFormBlocked;
   // The side products Lt = L21 Linv and Ut = Uinv U12 halve the launches per
   // level and direction; they pay where the level's products are short
   // (few fronts: launch latency dominates), not on the wide leaf levels,
@@ -2191,6 +2361,44 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     }
     timer_end(KC_TRI, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
   };
+  // Blocked levels: 32-row block steps (blk_step_kernel).  Forward: gather,
+  // permute into z, the steps (solutions kept in w's pivot part), copy back.
+  auto blocked = [&](int f0, int nf, int maxF, int maxP, int maxK, bool fwd, double ent) {
+    const C* dk = static_cast<const C*>(mf.dkeep);
+    const int pt = (int)ceil_div((int64_t)maxP * nrhs, 256);
+    if (fwd) {
+      fwd_gather_kernel<R><<<dim3(ceil_div(maxF, kGatherRows), nf), 256, 0, st>>>(mf, W, xin, nrhs, f0);
+      SPP_LAUNCH_CHECK();
+      blk_perm_kernel<R><<<dim3(pt, nf), 256, 0, st>>>(mf, W, Z, nrhs, f0, 0);
+      SPP_LAUNCH_CHECK();
+    }
+    const double passes = (nrhs / 4) + (nrhs % 4);
+    timer_begin(KC_SOLVE_BLK, st);
+    const int nblk = (maxP + kDB - 1) / kDB;
+    for (int s = 0; s < nblk; ++s) {
+      const int k0 = (fwd ? s : nblk - 1 - s) * kDB;
+      const int rows = fwd ? maxP - k0 - kDB : k0;
+      const unsigned gx = (unsigned)std::max<int64_t>(1, ceil_div(std::max(rows, 1), kBlkRows));
+      int r0 = 0;
+      while (r0 < nrhs) {
+        const int nr = (nrhs - r0 >= 4) ? 4 : 1;
+        if (fwd) {
+          if (nr == 4) blk_step_kernel<R, 4, true><<<dim3(gx, nf), 256, 0, st>>>(mf, arena, dk, W, Z, xout, nrhs, r0, f0, k0);
+          else blk_step_kernel<R, 1, true><<<dim3(gx, nf), 256, 0, st>>>(mf, arena, dk, W, Z, xout, nrhs, r0, f0, k0);
+        } else {
+          if (nr == 4) blk_step_kernel<R, 4, false><<<dim3(gx, nf), 256, 0, st>>>(mf, arena, dk, W, Z, xout, nrhs, r0, f0, k0);
+          else blk_step_kernel<R, 1, false><<<dim3(gx, nf), 256, 0, st>>>(mf, arena, dk, W, Z, xout, nrhs, r0, f0, k0);
+        }
+        SPP_LAUNCH_CHECK();
+        r0 += nr;
+      }
+    }
+    timer_end(KC_SOLVE_BLK, st, ent * passes * sizeof(C), 8.0 * ent * nrhs);
+    if (fwd) {
+      blk_perm_kernel<R><<<dim3(pt, nf), 256, 0, st>>>(mf, W, Z, nrhs, f0, 1);
+      SPP_LAUNCH_CHECK();
+    }
+  };
   // A run of consecutive small-front levels [l0, l1) as one cooperative launch
   // (false if it does not apply: too many levels, too much LDS, or the device
   // cannot hold enough workgroups).
@@ -2262,6 +2470,11 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       front(f0, nf, level_maxF[l], mP, mK, true, e[0] + e[2]);
       continue;
     }
+    if (level_form[l] == kFormBlocked) {
+      blocked(f0, nf, level_maxF[l], mP, mK, true, e[0]);
+      if (mK > 0) gemv(f0, nf, mK, mP, 1, e[2]);
+      continue;
+    }
     if (level_form[l] == kFormSide) {
       gemv(f0, nf, level_maxF[l], mP, 4, e[0] + e[2]);   // gathers its own input
     } else {
@@ -2285,6 +2498,11 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       front(f0, nf, level_maxF[l], mP, mK, false, e[1] + e[2]);
       continue;
     }
+    if (level_form[l] == kFormBlocked) {
+      if (mK > 0) gemv(f0, nf, mP, mK, 2, e[2]);
+      blocked(f0, nf, level_maxF[l], mP, mK, false, e[1]);
+      continue;
+    }
     if (level_form[l] == kFormSide) {
       gemv(f0, nf, mP, level_maxF[l], 5, e[1] + e[2]);
     } else {
@@ -2292,6 +2510,14 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
       gemv(f0, nf, mP, mP, 3, e[1]);
     }
   }
+}
+
+template <typename R>
+void mf_store_factors(hipStream_t st, const MfDev& mf, const void* arena, void* store, int f0, int nf, int maxF) {
+  const int cols = 4;
+  factor_store_kernel<R><<<dim3(ceil_div(maxF, cols), nf), 256, 0, st>>>(
+      mf, static_cast<const cplx_t<R>*>(arena), static_cast<cplx_t<R>*>(store), f0, cols);
+  SPP_LAUNCH_CHECK();
 }
 
 template <typename R>
@@ -2314,6 +2540,8 @@ template void mf_gemv<double>(hipStream_t, const MfDev&, const void*, void*, voi
                               double, void*, int64_t, int);
 template void mf_gemv<float>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,
                              double, void*, int64_t, int);
+template void mf_store_factors<double>(hipStream_t, const MfDev&, const void*, void*, int, int, int);
+template void mf_store_factors<float>(hipStream_t, const MfDev&, const void*, void*, int, int, int);
 template void cast_vectors<double>(hipStream_t, const void*, void*, int64_t, int);
 template void cast_vectors<float>(hipStream_t, const void*, void*, int64_t, int);
 

@@ -295,20 +295,7 @@ std::string build_plan(int d, int n, int b, int order, Plan& P) {
     for (int k = 0; k < par.F; ++k) posmap[P.idx[par.idx + k]] = -1;
   }
 
-  // Arena layout and counts.
-  int64_t off = 0, voff = 0;
-  for (auto& f : P.fronts) {
-    f.off = off;
-    off += (static_cast<int64_t>(f.F) * f.F + 15) / 16 * 16;
-    f.voff = voff;
-    voff += (f.F + 15) / 16 * 16;
-    double p = f.p, k = f.F - f.p;
-    P.factor_entries += static_cast<int64_t>(f.p) * f.p + 2LL * f.p * (f.F - f.p);
-    P.factor_flops += 8.0 * (p * p * p / 3.0 + p * p * k + p * k * k);
-    P.max_front = std::max(P.max_front, f.F);
-  }
-  P.arena_elems = off;
-  P.vec_elems = voff;
+  layout_plan(P, 0);
   return std::string();
 }
 
@@ -328,7 +315,6 @@ std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std:
   const size_t ni = plans.size();
   std::vector<std::vector<int>> newid(ni);
   std::vector<int> idx_base(ni), map_base(ni), pos_base(ni);
-  std::vector<int64_t> off_base(ni), voff_base(ni);
   for (size_t i = 0; i < ni; ++i) {
     newid[i].assign(plans[i]->fronts.size(), -1);
     idx_base[i] = static_cast<int>(out.idx.size());
@@ -337,13 +323,6 @@ std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std:
     out.map.insert(out.map.end(), plans[i]->map.begin(), plans[i]->map.end());
     pos_base[i] = static_cast<int>(out.pos.size());
     out.pos.insert(out.pos.end(), plans[i]->pos.begin(), plans[i]->pos.end());
-    off_base[i] = out.arena_elems;
-    out.arena_elems += plans[i]->arena_elems;
-    voff_base[i] = out.vec_elems;
-    out.vec_elems += plans[i]->vec_elems;
-    out.factor_entries += plans[i]->factor_entries;
-    out.factor_flops += plans[i]->factor_flops;
-    out.max_front = std::max(out.max_front, plans[i]->max_front);
   }
   for (size_t l = 0; l < nlev; ++l) {
     Level L;
@@ -358,8 +337,6 @@ std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std:
         f.level = static_cast<int>(l);
         f.idx += idx_base[i];
         f.map += map_base[i];
-        f.off += off_base[i];
-        f.voff += voff_base[i];
         for (int& c : f.children) {
           c = newid[i][c];
           if (c < 0) return "child front of a batch problem placed after its parent";
@@ -385,7 +362,61 @@ std::string combine_plans(const std::vector<const Plan*>& plans, Plan& out, std:
     L.blk_end = static_cast<int>(out.blocks.size());
     out.levels.push_back(L);
   }
+  layout_plan(out, 0);
   return std::string();
+}
+
+void layout_plan(Plan& P, int storage) {
+  auto pad = [](int64_t e) { return (e + 15) / 16 * 16; };
+  P.storage = storage;
+  P.factor_entries = 0;
+  P.factor_flops = 0;
+  P.max_front = 0;
+  int64_t voff = 0;
+  for (Front& f : P.fronts) {
+    f.voff = voff;
+    voff += pad(f.F);
+    const double p = f.p, k = f.F - f.p;
+    P.factor_entries += static_cast<int64_t>(f.p) * f.p + 2LL * f.p * (f.F - f.p);
+    P.factor_flops += 8.0 * (p * p * p / 3.0 + p * p * k + p * k * k);
+    P.max_front = std::max(P.max_front, f.F);
+  }
+  P.vec_elems = voff;
+  const size_t nl = P.levels.size();
+  std::vector<int64_t> S(nl, 0);
+  for (size_t l = 0; l < nl; ++l)
+    for (int fi = P.levels[l].begin; fi < P.levels[l].end; ++fi)
+      S[l] += pad(static_cast<int64_t>(P.fronts[fi].F) * P.fronts[fi].F);
+  int64_t A = 0;
+  if (storage == 0) {
+    for (size_t l = 0; l < nl; ++l) A += S[l];
+  } else {
+    for (size_t l = 0; l < nl; ++l) A = std::max(A, S[l] + (l ? S[l - 1] : 0));
+  }
+  int64_t off = 0, fo = 0;
+  for (size_t l = 0; l < nl; ++l) {
+    Level& L = P.levels[l];
+    if (storage == 1) off = (l % 2 == 0) ? 0 : A - S[l];
+    L.arena_lo = off;
+    for (int fi = L.begin; fi < L.end; ++fi) {
+      Front& f = P.fronts[fi];
+      f.off = off;
+      off += pad(static_cast<int64_t>(f.F) * f.F);
+      if (storage == 0) {
+        f.foff = f.off;
+        f.uoff = f.off + static_cast<int64_t>(f.p) * f.F;
+        f.ldu = f.F;
+      } else {
+        f.foff = fo;
+        f.uoff = fo + static_cast<int64_t>(f.p) * f.F;
+        f.ldu = f.p;
+        fo += pad(static_cast<int64_t>(f.p) * f.F + static_cast<int64_t>(f.p) * (f.F - f.p));
+      }
+    }
+    L.arena_hi = off;
+  }
+  P.arena_elems = A;
+  P.fstore_elems = fo;
 }
 
 std::string build_tables(const Plan& P, const std::vector<int>& front_inst, PlanTables& T) {
@@ -405,6 +436,7 @@ std::string build_tables(const Plan& P, const std::vector<int>& front_inst, Plan
       const Front& f = P.fronts[fi];
       FrontTable& g = T.fronts[fi];
       g.off = f.off; g.voff = f.voff; g.xoff = xo;
+      g.foff = f.foff; g.uoff = f.uoff; g.ldu = f.ldu;
       g.F = f.F; g.p = f.p; g.idx = f.idx; g.map = f.map; g.perm = T.perm_total;
       g.dblk = T.dblk_total;
       g.inst = front_inst[fi];

@@ -42,6 +42,12 @@ struct Front {
   int map = 0;                  // offset into Plan::map (F - p parent positions)
   int64_t off = 0;              // offset (complex elements) of the F x F front in the arena
   int64_t voff = 0;             // offset (complex elements) of the front's solve vector
+  // Where the substitution reads the factor (see layout_plan): the first p
+  // columns (F x p, leading dimension F) at foff, U12 (p x (F - p), leading
+  // dimension ldu) at uoff, in the arena (resident storage) or in the
+  // factor store (streamed storage).
+  int64_t foff = 0, uoff = 0;
+  int ldu = 0;
   std::vector<int> children;
 };
 
@@ -51,6 +57,7 @@ struct Level {
   int maxK = 0;                 // largest F - p (fronts of a batch level differ)
   int max_children = 0;
   int blk_begin = 0, blk_end = 0;   // assembly blocks of this level
+  int64_t arena_lo = 0, arena_hi = 0;   // arena range of the level's fronts
 };
 
 struct Plan {
@@ -64,7 +71,9 @@ struct Plan {
   std::vector<int> pos;         // row/column position pool for AsmBlocks
   std::vector<int> idx;         // global point indices of every front
   std::vector<int> map;         // boundary -> parent position maps
-  int64_t arena_elems = 0;      // sum of F^2 (complex elements, padded)
+  int storage = 0;              // 0 resident, 1 streamed (see layout_plan)
+  int64_t arena_elems = 0;      // front arena (complex elements, padded)
+  int64_t fstore_elems = 0;     // factor store (streamed storage), else 0
   int64_t vec_elems = 0;        // sum of F (per right-hand side)
   int64_t factor_entries = 0;   // sum of p^2 + 2 p (F - p)
   double factor_flops = 0;      // real flops of all partial factorisations
@@ -78,6 +87,8 @@ struct FrontTable {
   int64_t off = 0;     // F x F front in the arena
   int64_t voff = 0;    // solve-vector slot (F positions)
   int64_t xoff = 0;    // inverse work slot (2 p F), relative to its level's base
+  int64_t foff = 0, uoff = 0;   // factor read by the substitution (see Front)
+  int ldu = 0;
   int F = 0, p = 0;
   int idx = 0;         // Plan::idx offset (F global points)
   int map = 0;         // Plan::map offset (F - p parent positions)
@@ -100,6 +111,21 @@ struct PlanTables {
   int dblk_total = 0;
   int64_t xwork_elems = 0;          // largest per-level inverse work
 };
+
+// Storage of the fronts (complex elements, each block padded to 16):
+//  resident (0): every front F x F at its own arena offset for the whole
+//    factor's life; the substitution reads the factor in place (foff = off,
+//    uoff = off + p F, ldu = F).
+//  streamed (1): the arena holds the fronts of two adjacent levels only, the
+//    even levels from its start and the odd levels against its end, so a
+//    level's fronts never overlap its children's (whose Schur complements
+//    it adds) and overwrite only fronts two levels down; each front's factor
+//    part (its first p columns and the U12 rows) is copied to a compact
+//    factor store after the level is factored (foff, uoff = foff + p F,
+//    ldu = p).  The arena is max over levels of (this level + the level
+//    below) instead of the sum over all fronts.
+// Also sets the solve-vector offsets and the factor counts.
+void layout_plan(Plan& P, int storage);
 
 // Builds the tables of a plan (front_inst: problem of each front).
 std::string build_tables(const Plan& P, const std::vector<int>& front_inst, PlanTables& T);

@@ -9,7 +9,8 @@
 // overlap.  Small plans also check that every entry of P is assembled
 // exactly once.
 //
-// usage: plan_check d,n,b,order [d,n,b,order ...]   (several: one batch)
+// usage: plan_check [-s] [-v] d,n,b,order [d,n,b,order ...]   (several: one
+//        batch; -s: streamed storage, see layout_plan; -v: print the levels)
 // Prints "ok ..." and exits 0, or prints the first violation and exits 1.
 #include <algorithm>
 #include <cstdio>
@@ -53,15 +54,23 @@ bool disjoint(std::vector<std::pair<int64_t, int64_t>> r, int64_t limit, std::st
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc < 2) return fail("no geometry given");
-  std::vector<Plan> plans(argc - 1);
+  int first = 1, storage = 0;
+  bool verbose = false;
+  while (first < argc && argv[first][0] == '-') {
+    const std::string o = argv[first++];
+    if (o == "-s") storage = 1;
+    else if (o == "-v") verbose = true;
+    else return fail("unknown option " + o);
+  }
+  if (argc <= first) return fail("no geometry given");
+  std::vector<Plan> plans(argc - first);
   std::vector<int64_t> Ns;
-  for (int a = 1; a < argc; ++a) {
+  for (int a = first; a < argc; ++a) {
     int d, n, b, order;
     if (std::sscanf(argv[a], "%d,%d,%d,%d", &d, &n, &b, &order) != 4) return fail("bad geometry " + std::string(argv[a]));
-    std::string err = build_plan(d, n, b, order, plans[a - 1]);
+    std::string err = build_plan(d, n, b, order, plans[a - first]);
     if (!err.empty()) return fail("build_plan: " + err);
-    Ns.push_back(plans[a - 1].N);
+    Ns.push_back(plans[a - first].N);
   }
   Plan P;
   std::vector<int> inst;
@@ -74,6 +83,7 @@ int main(int argc, char** argv) {
     std::string err = combine_plans(raw, P, inst);
     if (!err.empty()) return fail("combine_plans: " + err);
   }
+  layout_plan(P, storage);
   PlanTables T;
   {
     std::string err = build_tables(P, inst, T);
@@ -136,7 +146,33 @@ int main(int argc, char** argv) {
   for (size_t i = 0; i < Ns.size(); ++i)
     for (int64_t g = 0; g < Ns[i]; ++g)
       if (owner[i][g] < 0) return fail("point never eliminated");
-  if (!disjoint(arena, P.arena_elems, why)) return fail("front arena: " + why);
+  if (storage == 0) {
+    if (!disjoint(arena, P.arena_elems, why)) return fail("front arena: " + why);
+    for (const Front& f : P.fronts)
+      if (f.foff != f.off || f.uoff != f.off + (int64_t)f.p * f.F || f.ldu != f.F) return fail("resident factor offsets");
+  } else {
+    // Each level's fronts lie in its own arena range, disjoint from the
+    // level below (whose Schur complements it adds); factors are compact.
+    for (size_t l = 0; l < P.levels.size(); ++l) {
+      std::vector<std::pair<int64_t, int64_t>> two;
+      for (size_t m = (l ? l - 1 : 0); m <= l; ++m) {
+        const Level& L = P.levels[m];
+        for (int fi = L.begin; fi < L.end; ++fi) {
+          const Front& f = P.fronts[fi];
+          if (f.off < L.arena_lo || f.off + (int64_t)f.F * f.F > L.arena_hi) return fail("front outside its level range");
+          two.emplace_back(f.off, (int64_t)f.F * f.F);
+        }
+      }
+      if (!disjoint(two, P.arena_elems, why)) return fail("levels " + std::to_string(l) + " and below: " + why);
+    }
+    std::vector<std::pair<int64_t, int64_t>> fac;
+    for (const Front& f : P.fronts) {
+      if (f.ldu != f.p || f.uoff != f.foff + (int64_t)f.p * f.F) return fail("streamed factor offsets");
+      fac.emplace_back(f.foff, (int64_t)f.p * f.F);
+      fac.emplace_back(f.uoff, (int64_t)f.p * (f.F - f.p));
+    }
+    if (!disjoint(fac, P.fstore_elems, why)) return fail("factor store: " + why);
+  }
   if (!disjoint(vec, P.vec_elems, why)) return fail("vector arena: " + why);
   if (!disjoint(perm, T.perm_total, why)) return fail("pivot permutation slots: " + why);
   if (!disjoint(dblk, T.dblk_total, why)) return fail("diagonal-block slots: " + why);
@@ -232,8 +268,13 @@ int main(int argc, char** argv) {
   }
   int64_t fmax = 0;
   for (const Front& f : P.fronts) fmax = std::max<int64_t>(fmax, f.F);
-  std::printf("ok fronts %d levels %zu max_front %lld arena %lld vec %lld dinv_slots %d blocks %zu%s\n", nf,
-              P.levels.size(), (long long)fmax, (long long)P.arena_elems, (long long)P.vec_elems, T.dblk_total,
-              P.blocks.size(), small ? " (P entries checked)" : "");
+  if (verbose)
+    for (size_t l = 0; l < P.levels.size(); ++l) {
+      const Level& L = P.levels[l];
+      std::printf("level %zu: %d fronts, max F %d, max p %d\n", l, L.end - L.begin, L.maxF, L.maxP);
+    }
+  std::printf("ok fronts %d levels %zu max_front %lld arena %lld store %lld vec %lld dinv_slots %d blocks %zu%s\n",
+              nf, P.levels.size(), (long long)fmax, (long long)P.arena_elems, (long long)P.fstore_elems,
+              (long long)P.vec_elems, T.dblk_total, P.blocks.size(), small ? " (P entries checked)" : "");
   return 0;
 }

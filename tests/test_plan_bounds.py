@@ -30,8 +30,9 @@ def checker(tmp_path_factory):
     return exe
 
 
-def run(exe, *geoms):
-    r = subprocess.run([exe] + [",".join(map(str, g)) for g in geoms], capture_output=True, text=True, timeout=600)
+def run(exe, *geoms, streamed=False):
+    r = subprocess.run([exe] + (["-s"] if streamed else []) + [",".join(map(str, g)) for g in geoms],
+                       capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
     return r.stdout
 
@@ -62,6 +63,25 @@ def test_schrodinger_family_batch(checker):
 
 def test_3d_batch(checker):
     run(checker, (3, 12, 3, OCT), (3, 8, 4, OCT))
+
+
+@pytest.mark.parametrize("geom", [(3, 12, 3, BIS), (3, 16, 4, BIS), (3, 24, 6, BIS), (3, 32, 4, BIS), (3, 48, 6, OCT),
+                                  (2, 64, 8, OCT), (2, 512, 16, OCT)])
+def test_streamed_storage_plans(checker, geom):
+    """Streamed storage: two adjacent levels never share arena space and the
+    compact factors do not overlap."""
+    run(checker, geom, streamed=True)
+
+
+def test_streamed_batch(checker):
+    run(checker, (2, 48, 6, OCT), (2, 32, 8, OCT), (2, 64, 8, OCT), streamed=True)
+
+
+def test_3d_128_bisection_plan(checker):
+    """The 3D Helmholtz configuration's plan (128^3, b = 8, bisection,
+    streamed): 8191 fronts up to 48896, every kernel range checked."""
+    out = run(checker, (3, 128, 8, BIS), streamed=True)
+    assert "fronts 8191" in out and "max_front 48896" in out, out
 
 
 def test_bad_geometry_is_reported(checker):

@@ -186,6 +186,16 @@ def large_2d_delta() -> Workload:
     return W
 
 
+def helmholtz_3d(n: int = 128, b: int = 8, nrhs: int = 4) -> Workload:
+    """3D Helmholtz on [0,1)^3 at 8 points per wavelength (omega = 2 pi n / 8),
+    32 Gaussian bumps of width 0.06 and amplitude U[-0.2, 0.2] in 1/c, nrhs
+    Gaussian sources of width 1/32 at seeded points; n = 128, b = 8 is the 3D
+    configuration (8^3 leaf boxes, one wavelength wide); smaller n keep the
+    same points per wavelength and leaf width in wavelengths when b = n / 16."""
+    return helmholtz_workload(f"helmholtz3d_n{n}_w{n // 8}", 3, n, 3, n / 8.0, 32, 0.06, b,
+                              nrhs=nrhs, tol=1e-8)
+
+
 def small(n: int, d: int, b: int, waves: float, bumps: int = 4, width: float = 0.08,
           nrhs: int = 1, instance: int = 0, tol: float = 1e-10) -> Workload:
     """Small Helmholtz case for unit tests (any n, d, b)."""
