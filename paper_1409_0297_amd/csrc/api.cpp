@@ -884,6 +884,11 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   void* xwork = F->dalloc<char>((size_t)F->xwork_elems * F->csize);
   void* tbuf = F->dalloc<char>((size_t)(F->xwork_elems / 2) * F->csize);
   void* dinv = F->dalloc<char>((size_t)2 * 32 * 32 * F->pd->dblk_total * F->csize);
+  int64_t tp_ints = 1;
+  for (size_t l = 0; l < P.levels.size(); ++l)
+    if (F->level_form[l] == kFormBlocked)
+      tp_ints = std::max(tp_ints, mf_tournament_ints(P.levels[l].end - P.levels[l].begin, P.levels[l].maxP));
+  int* tpbuf = F->dalloc<int>(tp_ints);
   if (any_blocked) {
     F->dkeep = dinv;
     mf.dkeep = dinv;
@@ -901,16 +906,18 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     if (streamed)
       SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + (size_t)L.arena_lo * F->csize, 0,
                              (size_t)(L.arena_hi - L.arena_lo) * F->csize, st));
-    // Large pivot blocks pivot over all their fully-summed rows: pivots
-    // chosen inside 32-row blocks let the multipliers below the block, and
-    // with them the growth of the Schur updates, grow with the front.
-    const bool pp = partial_pivoting || F->level_form[l] == kFormBlocked;
+    // Large pivot blocks choose their pivots over all their fully-summed
+    // rows (by tournament): pivots chosen inside 32-row blocks let the
+    // multipliers below the block, and with them the growth of the Schur
+    // updates, grow with the front.
+    const int piv = partial_pivoting ? kPivotPartial
+                    : F->level_form[l] == kFormBlocked ? kPivotTournament : kPivotBlockLocal;
     if (F->opt.prec == SPP_C128)
-      mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                              L.max_children, F->level_form[l], pp, hF, hP);
+      mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP, L.blk_begin,
+                              L.blk_end, L.max_children, F->level_form[l], piv, hF, hP);
     else
-      mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, L.begin, L.end, L.maxF, L.maxP, L.blk_begin, L.blk_end,
-                             L.max_children, F->level_form[l], pp, hF, hP);
+      mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP, L.blk_begin,
+                             L.blk_end, L.max_children, F->level_form[l], piv, hF, hP);
     if (streamed) {
       if (F->opt.prec == SPP_C128)
         mf_store_factors<double>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
@@ -926,6 +933,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   const double tf1 = now_ms();
   F->dfree(xwork);
   F->dfree(tbuf);
+  F->dfree(tpbuf);
   if (!any_blocked) F->dfree(dinv);
   F->dfree(swork);
   if (streamed) {   // the substitution reads the factor store only

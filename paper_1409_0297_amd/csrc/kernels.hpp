@@ -137,10 +137,22 @@ struct MfDev {
   int nB_max[8];       // largest |beta| per set type
 };
 
+// Pivoting of a level's partial LUs:
+//  kPivotBlockLocal: pivot within each 32-row diagonal block (default);
+//  kPivotPartial:    over all remaining fully-summed rows, column by column
+//                    (one-workgroup panel factorisation);
+//  kPivotTournament: the 32 pivot rows of each block chosen over all
+//                    remaining fully-summed rows by a tournament of LUs with
+//                    partial pivoting over row chunks, then factored as a
+//                    block (large fronts: many workgroups per front).
+constexpr int kPivotBlockLocal = 0, kPivotPartial = 1, kPivotTournament = 2;
+// Candidate-row buffer a tournament-pivoted level needs (ints).
+inline int64_t mf_tournament_ints(int nfronts, int maxP) { return 2LL * nfronts * ((maxP + 255) / 256) * 32; }
+
 template <typename R>
-void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* tbuf, void* dinv,
+void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* tbuf, void* dinv, int* tpbuf,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
-                     int max_children, int form, bool partial_pivoting,
+                     int max_children, int form, int pivoting,
                      const int* hF, const int* hP);   // host: F and p of the level's fronts
 // How a level's fronts are kept for the substitution:
 //  kFormLU:      LU in place, one workgroup per front solves;

@@ -731,6 +731,153 @@ __global__ void __launch_bounds__(256) diag_lu_kernel(MfDev mf, cplx_t<R>* __res
   diag_lu_block<R>(mf, arena, dinv, f0 + blockIdx.x, k0, nb, -1, S);
 }
 
+// ------------------------------------------------------------------ tournament pivoting
+// Pivot rows of a block [c, c + kb) of a large front chosen over all its
+// remaining fully-summed rows [c, p) by a tournament (communication-avoiding
+// LU): every chunk of 256 rows names kb candidates by LU with partial
+// pivoting of its copy of the block's columns, groups of 8 candidate sets
+// (256 rows) are reduced the same way until one set is left, and those kb
+// rows are swapped to the top of the block; the diagonal-block LU and the
+// L21 / U12 products then run on them as on any block.
+constexpr int kTpRows = 256, kTpFan = 8;
+
+// LU with partial pivoting of the rows `row` (one per thread, -1: none; at
+// most 256) restricted to the columns [c, c + kb) of the front at A (leading
+// dimension F); the positions of the kb pivot rows in pivot order go to
+// out[0 .. kb) (-1 where fewer rows remain).  Largest modulus first, ties to
+// the lowest position (the moduli compared in single precision).
+template <typename R>
+__device__ __forceinline__ void tp_pick(const cplx_t<R>* __restrict__ A, int F, int c, int kb, int row, int* out) {
+  using C = cplx_t<R>;
+  __shared__ unsigned long long key;
+  __shared__ C prow[kDB];
+  C a[kDB];
+#pragma unroll
+  for (int j = 0; j < kDB; ++j) a[j] = (row >= 0 && j < kb) ? A[(int64_t)(c + j) * F + row] : cmake<C>(0, 0);
+  bool live = row >= 0;
+#pragma unroll
+  for (int j = 0; j < kDB; ++j) {
+    if (j < kb) {
+      if (threadIdx.x == 0) key = 0;
+      __syncthreads();
+      unsigned long long k = 0;
+      if (live) {
+        const float v = (float)sqrt(cabs2(a[j]));
+        k = ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)row);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(k, o);
+        k = t > k ? t : k;
+      }
+      if ((threadIdx.x & 63) == 0 && k) atomicMax(&key, k);
+      __syncthreads();
+      const unsigned long long kk = key;
+      const int pr = kk ? (int)(0xFFFFFFFFu - (unsigned)(kk & 0xFFFFFFFFull)) : -1;
+      if (threadIdx.x == 0) out[j] = pr;
+      if (live && row == pr) {
+#pragma unroll
+        for (int t = 0; t < kDB; ++t) prow[t] = a[t];
+        live = false;
+      }
+      __syncthreads();
+      if (live && pr >= 0) {
+        const C d = prow[j];
+        const C l = cabs2(d) > R(0) ? cdiv(a[j], d) : cmake<C>(0, 0);
+#pragma unroll
+        for (int t = j + 1; t < kDB; ++t) cfms(a[t], l, prow[t]);
+      }
+    } else if (threadIdx.x == 0) {
+      out[j] = -1;
+    }
+  }
+}
+
+// Sets of level 0: chunk blockIdx.x of the rows [c, p) of front f0 +
+// blockIdx.y; cand[(front * maxsets + set) * 32 + j].
+template <typename R>
+__global__ void __launch_bounds__(256) tp_select_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                        int* __restrict__ cand, int f0, int c, int maxsets) {
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  if (c >= f.p) return;
+  const int r0 = c + blockIdx.x * kTpRows;
+  if (r0 >= f.p) return;
+  const int kb = min(kDB, f.p - c);
+  const int row = (r0 + (int)threadIdx.x < f.p) ? r0 + threadIdx.x : -1;
+  __shared__ int out[kDB];
+  tp_pick<R>(arena + f.off, f.F, c, kb, row, out);
+  __syncthreads();
+  if (threadIdx.x < kDB) cand[((int64_t)blockIdx.y * maxsets + blockIdx.x) * kDB + threadIdx.x] = out[threadIdx.x];
+}
+
+// Level lev >= 1: set blockIdx.x merges the sets [8 x, 8 x + 8) of level
+// lev - 1 (read from cin, written to cout); a front's set count at level
+// lev is its chunk count divided by 8 lev times, rounded up.
+template <typename R>
+__global__ void __launch_bounds__(256) tp_reduce_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena,
+                                                        const int* __restrict__ cin, int* __restrict__ cout, int f0,
+                                                        int c, int lev, int maxsets) {
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  if (c >= f.p) return;
+  int nin = (f.p - c + kTpRows - 1) / kTpRows;
+  for (int l = 1; l < lev; ++l) nin = (nin + kTpFan - 1) / kTpFan;
+  const int s0 = blockIdx.x * kTpFan;
+  if (s0 >= nin) return;
+  const int kb = min(kDB, f.p - c);
+  const int set = s0 + threadIdx.x / kDB, j = threadIdx.x % kDB;
+  const int row = set < nin ? cin[((int64_t)blockIdx.y * maxsets + set) * kDB + j] : -1;
+  __shared__ int out[kDB];
+  tp_pick<R>(arena + f.off, f.F, c, kb, row, out);
+  __syncthreads();
+  if (threadIdx.x < kDB) cout[((int64_t)blockIdx.y * maxsets + blockIdx.x) * kDB + threadIdx.x] = out[threadIdx.x];
+}
+
+// Swaps the winners win[front * maxsets * 32 + j] (positions >= c) to the
+// rows c + j of the whole front, as a sequence of interchanges recorded
+// LAPACK-style in ipiv (ipiv[c + j] = the row swapped with row c + j at step
+// j).  Every workgroup derives the same net permutation of the touched rows
+// (at most 64) and applies it to its 64 columns; blockIdx.y = front.
+template <typename R>
+__global__ void __launch_bounds__(64) tp_swap_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, const int* __restrict__ win,
+                                                     int* __restrict__ ipiv, int f0, int c, int maxsets) {
+  using C = cplx_t<R>;
+  const FrontDev& f = mf.fronts[f0 + blockIdx.y];
+  if (c >= f.p) return;
+  const int kb = min(kDB, f.p - c);
+  __shared__ int pos[2 * kDB], content[2 * kDB], cnt;
+  __shared__ C tmp[64][2 * kDB + 1];
+  if (threadIdx.x == 0) {
+    int n = 0;
+    const int* w = win + (int64_t)blockIdx.y * maxsets * kDB;
+    for (int j = 0; j < kb; ++j) {
+      const int a = c + j;
+      int wj = w[j];
+      if (wj < c || wj >= f.p) wj = a;   // (no candidate: keep the row)
+      // current position of the original row wj, and the slot of row a
+      int xw = -1, xa = -1;
+      for (int x = 0; x < n; ++x) {
+        if (content[x] == wj) xw = x;
+        if (pos[x] == a) xa = x;
+      }
+      if (xw < 0) {   // untouched: still at its own position
+        for (int x = 0; x < n; ++x)
+          if (pos[x] == wj) xw = x;
+        if (xw < 0) { pos[n] = wj; content[n] = wj; xw = n++; }
+      }
+      if (xa < 0) { pos[n] = a; content[n] = a; xa = n++; }
+      if (blockIdx.x == 0) ipiv[f.perm + a] = pos[xw];
+      const int t = content[xa]; content[xa] = content[xw]; content[xw] = t;
+    }
+    cnt = n;
+  }
+  __syncthreads();
+  const int n = cnt;
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  if (col >= f.F) return;
+  C* cp = arena + f.off + (int64_t)col * f.F;
+  for (int x = 0; x < n; ++x) tmp[threadIdx.x][x] = cp[content[x]];
+  for (int x = 0; x < n; ++x) cp[pos[x]] = tmp[threadIdx.x][x];
+}
+
 // ------------------------------------------------------------------ row-block TRSM
 // mode 0: LU row block  front[k0:k0+kb, k0+kb:F] = L_kk^{-1} (.)
 // mode 1: L inverse     XL[k0:k0+kb, 0:k0+kb]    = L_kk^{-1} (.)
@@ -958,16 +1105,22 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 // block of front by, taking this step's update of that block itself; the
 // tile holding the block skips it.
 // (bx, by) = (tile, front) of the workgroup.
+//   mode 8: column strip of block k0 (rows [k0, F), its kb columns) takes
+//           the updates of the steps [kf, k0) of an outer block
+//   mode 9: row strip of block k0 (its kb rows, columns [k0 + kb, F)) takes
+//           the same updates (left-looking inside an outer block whose
+//           trailing update then goes as one rank-(k0 - kf) product)
 template <typename R, bool NEXT, int mode>
 __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
-                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m, int bx, int by) {
+                                 cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m, int bx, int by,
+                                 int kf = 0) {
   using C = cplx_t<R>;
   // Modes 3 and 7: products with one side of at most 32 take the 128 x 32
   // (tall) or 32 x 128 (wide) tile; tiles_m then counts 128-row tiles.
   // Mode 6 is mode 7 on 64 x 64 tiles (twice the workgroups, each with half
   // its waves idle): shorter launches for levels of few fronts, where the
   // step's latency rather than its throughput counts.
-  constexpr bool kNarrow = mode == 3 || mode == 7;
+  constexpr bool kNarrow = mode == 3 || mode == 7 || mode == 8 || mode == 9;
   constexpr size_t kGemm = kNarrow ? sizeof(GemmLds<R, 128, 32>) : sizeof(GemmLds<R>);
   constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > kGemm ? sizeof(DiagLds<R>) : kGemm) : kGemm;
   __shared__ __align__(16) unsigned char lds[kLds];
@@ -991,7 +1144,25 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
   int tm, tn;
   const int* brow = nullptr;
   bool assign = false;
-  if constexpr (mode == 3) {
+  if constexpr (mode == 8 || mode == 9) {
+    // Strips of block k0 against the outer block's earlier steps [kf, k0);
+    // mode 8 uses the tall tiles (bx < tiles_m), mode 9 the wide ones.
+    k = k0 - kf;
+    Ap = base + (int64_t)kf * F + k0; lda = F;
+    if constexpr (mode == 8) {
+      if (bx >= tiles_m) return;
+      tm = bx; tn = 0;
+      m = F - k0; n = kb;
+      Bp = base + (int64_t)k0 * F + kf; ldb = F;
+      Cp = base + (int64_t)k0 * F + k0; ldc = F;
+    } else {
+      if (bx < tiles_m) return;
+      tm = 0; tn = bx - tiles_m;
+      m = kb; n = F - k0 - kb;
+      Bp = base + (int64_t)(k0 + kb) * F + kf; ldb = F;
+      Cp = base + (int64_t)(k0 + kb) * F + k0; ldc = F;
+    }
+  } else if constexpr (mode == 3) {
     // The next block (kb2 columns / rows after this one) of a pair of
     // steps: its column below this block (first tiles_m workgroups) and its
     // row right of it (the rest) take this step's update.
@@ -1073,8 +1244,8 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
 template <typename R, int MODE>
 __global__ void __launch_bounds__(256, kGemmWaves<R>) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                                    cplx_t<R>* __restrict__ dinv, int f0, int step, int nb,
-                                                   int tiles_m) {
-  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, blockIdx.x, blockIdx.y);
+                                                   int tiles_m, int kf = 0) {
+  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, blockIdx.x, blockIdx.y, kf);
 }
 
 // Trailing update with the next diagonal block (mode 0, NEXT above); asks
@@ -1269,7 +1440,11 @@ __global__ void merge_inverse_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, co
 // record: one workgroup per front, the bookkeeping done in LDS.
 // lds: the record and the permutation fit in LDS (2 p ints); else the
 // interchanges are replayed in place in the global permutation array.
-__global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0, int lds) {
+// compose: the interchanges moved whole rows to the tops of the 32-row
+// blocks, and the diagonal-block LU then ordered each block's rows (prow);
+// the final permutation is the replayed one read through prow (the ipiv
+// record, no longer needed, holds the intermediate).
+__global__ void perm_kernel(MfDev mf, int* __restrict__ ipiv, int f0, int lds, int compose) {
   const FrontDev f = mf.fronts[f0 + blockIdx.x];
   if (!lds) {
     int* perm = mf.perm + f.perm;
@@ -1280,6 +1455,12 @@ __global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0, int 
         const int r = ipiv[f.perm + j];
         const int t = perm[j]; perm[j] = perm[r]; perm[r] = t;
       }
+    __syncthreads();
+    if (compose) {
+      for (int i = threadIdx.x; i < f.p; i += blockDim.x) ipiv[f.perm + i] = perm[mf.prow[f.perm + i]];
+      __syncthreads();
+      for (int i = threadIdx.x; i < f.p; i += blockDim.x) perm[i] = ipiv[f.perm + i];
+    }
     return;
   }
   extern __shared__ int sp[];
@@ -1293,7 +1474,8 @@ __global__ void perm_kernel(MfDev mf, const int* __restrict__ ipiv, int f0, int 
       const int t = perm[j]; perm[j] = perm[r]; perm[r] = t;
     }
   __syncthreads();
-  for (int i = threadIdx.x; i < f.p; i += blockDim.x) mf.perm[f.perm + i] = perm[i];
+  for (int i = threadIdx.x; i < f.p; i += blockDim.x)
+    mf.perm[f.perm + i] = compose ? perm[mf.prow[f.perm + i]] : perm[i];
 }
 
 // Inverses of the 32 x 32 diagonal blocks of a factored pivot block (L unit
@@ -2004,13 +2186,16 @@ __global__ void cast_kernel(const void* in, void* out, int64_t count, int to_dou
 }
 
 constexpr int kNB = 32;
+constexpr int kOuterNB = 256;   // columns per outer block of the tournament-pivoted levels
 
 }  // namespace
 
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* tbuf_v, void* dinv_v,
-                     int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, int form,
-                     bool partial_pivoting, const int* hF, const int* hP) {
+                     int* tpbuf, int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, int form,
+                     int pivoting, const int* hF, const int* hP) {
+  const bool partial_pivoting = pivoting == kPivotPartial;
+  const bool tournament = pivoting == kPivotTournament;
   const bool invert = form == kFormInverse || form == kFormSide;
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
@@ -2035,7 +2220,80 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   const int steps = (maxP + kNB - 1) / kNB;
   const int tiles = (int)ceil_div(maxF, kBM);
   const int tiles128 = (int)ceil_div(maxF, 128);   // tall / wide tiles of modes 3 and 7
-  if (!partial_pivoting && steps > 0) {
+  auto gemm_timed = [&](double fl, auto&& launch) {
+    timer_begin(KC_GEMM, st);
+    launch();
+    SPP_LAUNCH_CHECK();
+    timer_end(KC_GEMM, st, 0.0, fl);
+  };
+  if (tournament) {
+    // Outer blocks of kOuterNB columns: inside one, each 32-column block
+    // takes the earlier blocks' updates on its column strip, has its pivot
+    // rows chosen by the tournament and swapped up, takes the updates on its
+    // row strip, then its diagonal-block LU and L21 / U12; the outer block's
+    // trailing update then goes as one rank-kOuterNB product.
+    const int maxsets = (int)ceil_div(maxP, kTpRows);
+    int* bufA = tpbuf;
+    int* bufB = tpbuf + (size_t)nf * maxsets * kDB;
+    for (int k0 = 0; k0 < maxP; k0 += kOuterNB) {
+      for (int c = k0; c < std::min(maxP, k0 + kOuterNB); c += kNB) {
+        const int s = c / kNB;
+        double fl8 = 0, fl9 = 0, fl7 = 0;
+        if (g_timer)
+          for (int i = 0; i < nf; ++i) {
+            if (c >= hP[i]) continue;
+            const double kb = std::min(kNB, hP[i] - c), m = hF[i] - c - kb, w = c - k0;
+            fl8 += 8.0 * (m + kb) * kb * w;
+            fl9 += 8.0 * kb * m * w;
+            fl7 += 16.0 * m * kb * kb;
+          }
+        if (c > k0)
+          gemm_timed(fl8, [&] {
+            gemm_kernel<R, 8><<<dim3(tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128, k0);
+          });
+        timer_begin(KC_PANEL, st);
+        int sets = (int)ceil_div(maxP - c, kTpRows);
+        tp_select_kernel<R><<<dim3(sets, nf), 256, 0, st>>>(mf, arena, bufA, f0, c, maxsets);
+        SPP_LAUNCH_CHECK();
+        int* in = bufA;
+        int* out = bufB;
+        for (int lev = 1; sets > 1; ++lev) {
+          const int next = (int)ceil_div(sets, kTpFan);
+          tp_reduce_kernel<R><<<dim3(next, nf), 256, 0, st>>>(mf, arena, in, out, f0, c, lev, maxsets);
+          SPP_LAUNCH_CHECK();
+          std::swap(in, out);
+          sets = next;
+        }
+        tp_swap_kernel<R><<<dim3(ceil_div(maxF, 64), nf), 64, 0, st>>>(mf, arena, in, mf.ipiv, f0, c, maxsets);
+        SPP_LAUNCH_CHECK();
+        timer_end(KC_PANEL, st, 0.0, 0.0);
+        if (c > k0)
+          gemm_timed(fl9, [&] {
+            gemm_kernel<R, 9><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128,
+                                                                       k0);
+          });
+        timer_begin(KC_PANEL, st);
+        diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, c, kNB);
+        SPP_LAUNCH_CHECK();
+        timer_end(KC_PANEL, st, 0.0, 0.0);
+        gemm_timed(fl7, [&] {
+          gemm_kernel<R, 7><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128);
+        });
+      }
+      double flt = 0;
+      if (g_timer)
+        for (int i = 0; i < nf; ++i) {
+          if (k0 >= hP[i]) continue;
+          const double w = std::min(kOuterNB, hP[i] - k0), mn = hF[i] - k0 - w;
+          flt += 8.0 * mn * mn * w;
+        }
+      gemm_timed(flt, [&] {
+        gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, k0 / kOuterNB,
+                                                                   kOuterNB, tiles);
+      });
+    }
+  }
+  if (!partial_pivoting && !tournament && steps > 0) {
     // First diagonal block; each later one is factored inside the previous
     // step's trailing-update launch (levels of few fronts) or on its own.
     timer_begin(KC_PANEL, st);
@@ -2047,16 +2305,10 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   // the front through HBM at every step) go two steps at a time: the second
   // block's column and row take the first step's update on their own, then
   // one rank-64 trailing update serves both steps, halving that traffic.
-  if (!partial_pivoting && nf > 64) {
+  if (!partial_pivoting && !tournament && nf > 64) {
     // One kernel per timed interval (bench.py divides a class's time by its
     // intervals): L21 / U12 of each step 16 m kb^2, the second block's
     // column and row 8 kb kb2 (m + m - kb2), the trailing update 8 mn^2 w.
-    auto gemm_timed = [&](double fl, auto&& launch) {
-      timer_begin(KC_GEMM, st);
-      launch();
-      SPP_LAUNCH_CHECK();
-      timer_end(KC_GEMM, st, 0.0, fl);
-    };
     for (int s = 0; s < steps;) {
       const int k0 = s * kNB;
       const bool pair = s + 1 < steps;
@@ -2105,7 +2357,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       }
     }
   }
-  for (int s = 0; s < steps && (partial_pivoting || nf <= 64); ++s) {
+  for (int s = 0; s < steps && !tournament && (partial_pivoting || nf <= 64); ++s) {
     const int k0 = s * kNB;
     if (partial_pivoting) {
       timer_begin(KC_PANEL, st);
@@ -2165,11 +2417,11 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     leftswap_kernel<R><<<dim3(steps * cchunks, nf), 256, 0, st>>>(mf, arena, f0, cchunks);
     SPP_LAUNCH_CHECK();
   }
-  if (partial_pivoting) {   // (the diagonal-block LU writes the permutation itself)
+  if (partial_pivoting || tournament) {   // (the block-local LU writes the permutation itself)
     const bool lds = (size_t)2 * sizeof(int) * maxP <= 65536;
-    perm_kernel<<<nf, 256, lds ? 2 * sizeof(int) * maxP : 0, st>>>(mf, mf.ipiv, f0, lds ? 1 : 0);
+    perm_kernel<<<nf, 256, lds ? 2 * sizeof(int) * maxP : 0, st>>>(mf, mf.ipiv, f0, lds ? 1 : 0, tournament ? 1 : 0);
     SPP_LAUNCH_CHECK();
-    if (form == kFormBlocked) {
+    if (form == kFormBlocked && partial_pivoting) {
       diag_inv_kernel<R><<<dim3(ceil_div(maxP, kDB), nf), 256, 0, st>>>(mf, arena, dinv, f0);
       SPP_LAUNCH_CHECK();
     }
@@ -2526,10 +2778,10 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
   SPP_LAUNCH_CHECK();
 }
 
-template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, void*, int, int, int, int, int, int,
-                                      int, int, bool, const int*, const int*);
-template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, void*, int, int, int, int, int, int,
-                                     int, int, bool, const int*, const int*);
+template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, void*, int*, int, int, int, int, int, int,
+                                      int, int, int, const int*, const int*);
+template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, void*, int*, int, int, int, int, int, int,
+                                     int, int, int, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
                                int64_t, bool);
