@@ -131,7 +131,11 @@ typedef struct {
                            ends, and another starts from the true residual,
                            when the Givens estimate met tol but the true
                            residual did not                                     */
-  int32_t reserved;     /* must be 0                                             */
+  int32_t pattern;      /* stencil sets of Q (Section 2.3): 0 = the cells,
+                           faces, edges and vertices of the leaf boxes (the
+                           paper's choice); 1 = every point its own set with
+                           the neighbourhood mu(j) = gamma({j}) (the pattern
+                           Section 2.3 sets aside; for comparisons)            */
   spp_alloc_fn alloc;   /* optional allocator hook (both or neither)             */
   spp_free_fn free;
   void* alloc_ctx;      /* passed to alloc / free                                */

@@ -37,16 +37,20 @@ def coefficients(kind: str, n: int, d: int, coeff, omega=0.0, ell=1.0, energy=0.
 
 
 def setup(kind: str, n: int, d: int, b: int, coeff, omega=0.0, ell=1.0, energy=0.0,
-          ordering: str = "octree") -> OracleSetup:
+          ordering: str = "octree", pattern: str = "sets") -> OracleSetup:
+    """pattern "sets": the stencils of the leaf boxes' cells, edges, faces and
+    vertices (Section 2.3); "points": every point with its own neighbourhood
+    mu(j) = gamma({j}).  The nested dissection uses leaf boxes of width b in
+    both cases."""
     s, q, moves = coefficients(kind, n, d, coeff, omega, ell, energy)
-    st = stencil.Stencils(n, d, b, s)
+    st = stencil.Stencils(n, d, b if pattern == "sets" else 1, s)
     P = st.P_matrix(q)
     fac = nested.NDFactor(P, nested.nd_levels(n, d, b, ordering))
     return OracleSetup(n=n, d=d, b=b, s=s, q=q, shift_moves=moves, stencils=st, P=P, factor=fac)
 
 
-def setup_workload(W, ordering: str = "octree") -> OracleSetup:
-    return setup(W.kind, W.n, W.d, W.b, W.coeff, W.omega, W.ell, W.energy, ordering)
+def setup_workload(W, ordering: str = "octree", pattern: str = "sets") -> OracleSetup:
+    return setup(W.kind, W.n, W.d, W.b, W.coeff, W.omega, W.ell, W.energy, ordering, pattern)
 
 
 def precondition(o: OracleSetup, r: np.ndarray) -> np.ndarray:

@@ -8,7 +8,9 @@ T_S = G(S, gamma^c) G(beta, gamma^c)^+ via an explicit pseudoinverse,
 Q(S, gamma(S)) = [I  -T_S] with columns ordered (S, beta(S))).
 
 Sets are labelled by a boolean mask over the d axes and a leaf-box anchor
-a in [0, n/b)^d.  Axis i of the set is pinned to the grid line a_i b when
+a in [0, n/b)^d.  With b = 1 every set is a single point, whose
+neighbourhood is mu(j) = gamma({j}) (the point pattern Section 2.3 weighs
+against the set pattern): only the all-True mask has points then.  Axis i of the set is pinned to the grid line a_i b when
 mask[i] is set and runs over the open interval a_i b + 1 .. a_i b + b - 1
 otherwise.  So the all-False mask is a cell, the all-True mask a vertex, one
 True axis an edge (2D) or a face (3D), two True axes an edge (3D).
@@ -140,7 +142,8 @@ class Stencils:
             raise ValueError("b must divide n with at least two leaf boxes per axis")
         self.n, self.d, self.b, self.s = n, d, b, s
         self.g = spectral.green_kernel(n, d, s)
-        self.masks = set_masks(d)
+        # (with b = 1 only the vertex mask, a single point, is not empty)
+        self.masks = [m for m in set_masks(d) if b > 1 or all(m)]
         self.T, self.C, self.S0, self.beta0 = {}, {}, {}, {}
         for mask in self.masks:
             T, S, beta = stencil_T(self.g, n, d, b, mask)

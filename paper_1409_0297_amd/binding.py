@@ -41,7 +41,7 @@ class spp_problem(ctypes.Structure):
 class spp_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("order", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("pattern", ctypes.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p)]
 
 
@@ -298,7 +298,8 @@ class Solver:
                  tol: float = 1e-10, max_iter: int = 200, unpreconditioned: bool = False,
                  timing: bool = False, partial_pivoting: bool = False, graphs: bool = False,
                  persistent: bool = False, autotune: bool = False, side_products: bool = True,
-                 restart: int = 0, allocator: "TorchAllocator" = None, streamed: bool = False):
+                 restart: int = 0, allocator: "TorchAllocator" = None, streamed: bool = False,
+                 pattern: str = "sets"):
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
@@ -318,7 +319,8 @@ class Solver:
                          | (SPP_F_PERSISTENT if persistent else 0)
                          | (SPP_F_AUTOTUNE if autotune else 0)
                          | (0 if side_products else SPP_F_NO_SIDE)
-                         | (SPP_F_STREAMED if streamed else 0), restart=restart)
+                         | (SPP_F_STREAMED if streamed else 0), restart=restart,
+                         pattern=0 if pattern == "sets" else 1)
         self._allocator = allocator
         if allocator is not None:
             allocator.install(op)

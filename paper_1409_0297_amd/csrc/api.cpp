@@ -79,7 +79,7 @@ double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-using Geom = std::tuple<int, int, int, int>;   // d, n, b, ordering
+using Geom = std::tuple<int, int, int, int, int>;   // d, n, b, ordering, stencil pattern
 
 // A nested-dissection plan (of one problem or of a batch) and its device-side
 // index arrays.  Plans depend only on the geometries, so they are built once
@@ -180,7 +180,7 @@ std::shared_ptr<Plan> host_plan_locked(const Geom& g) {
   auto it = g_host_plans.find(g);
   if (it != g_host_plans.end()) return it->second;
   auto P = std::make_shared<Plan>();
-  std::string err = build_plan(std::get<0>(g), std::get<1>(g), std::get<2>(g), std::get<3>(g), *P);
+  std::string err = build_plan(std::get<0>(g), std::get<1>(g), std::get<2>(g), std::get<3>(g), *P, std::get<4>(g));
   if (!err.empty()) throw Error(SPP_EINVAL, err);
   g_host_plans[g] = P;
   return P;
@@ -270,6 +270,7 @@ struct SppInstance {
   double omega = 0, ell = 1, energy = 0, s = 0;
   int moves = 0;
   int d = 0, n = 0, b = 0, m = 0;
+  int bs = 0;                        // box width of the stencil sets (b, or 1 for points)
   int64_t N = 0, Noff = 0;
   std::shared_ptr<Plan> plan;        // the problem's own plan (set types)
   StencilDev sten[8]{};
@@ -655,7 +656,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   if (op->order != SPP_ORDER_OCTREE && op->order != SPP_ORDER_BISECT) throw Error(SPP_EINVAL, "unknown ordering");
   if (!(op->tol > 0) || op->max_iter < 1 || op->max_iter > 500) throw Error(SPP_EINVAL, "tol > 0 and 1 <= max_iter <= 500");
   if (op->restart < 0 || op->restart > 500) throw Error(SPP_EINVAL, "restart must be in [0, 500]");
-  if (op->reserved != 0) throw Error(SPP_EINVAL, "spp_options::reserved must be 0");
+  if (op->pattern != 0 && op->pattern != 1) throw Error(SPP_EINVAL, "spp_options::pattern must be 0 or 1");
   if ((op->alloc == nullptr) != (op->free == nullptr)) throw Error(SPP_EINVAL, "give both alloc and free, or neither");
   for (int i = 0; i < count; ++i) {
     validate_problem(&pbs[i]);
@@ -671,7 +672,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   if (op->flags & SPP_F_TIMING) F->timer = std::make_unique<KernelTimer>();
   TimerScope timer_scope(F.get());
   std::vector<Geom> geoms;
-  for (int i = 0; i < count; ++i) geoms.emplace_back(pbs[i].dim, pbs[i].n, pbs[i].b, op->order);
+  for (int i = 0; i < count; ++i) geoms.emplace_back(pbs[i].dim, pbs[i].n, pbs[i].b, op->order, op->pattern);
   // Storage: every front resident unless asked for, or unless the resident
   // arena (sum of F^2 over all fronts) would not fit in 85% of what the
   // device has left.
@@ -698,6 +699,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     SppInstance I;
     I.kind = pbs[i].kind; I.omega = pbs[i].omega; I.ell = pbs[i].ell; I.energy = pbs[i].energy;
     I.d = pbs[i].dim; I.n = pbs[i].n; I.b = pbs[i].b; I.m = I.n / I.b;
+    I.bs = op->pattern == 1 ? 1 : I.b;
     I.N = (I.d == 2) ? (int64_t)I.n * I.n : (int64_t)I.n * I.n * I.n;
     I.Noff = Noff;
     I.plan = host_plan(geoms[i]);
@@ -815,7 +817,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     fft_inverse_all(st, sig2_c, g2, I.tw, I.d, I.n);
     // a3-a4: stencils per set type.
     InstDev& D = idev[i];
-    D.d = I.d; D.n = I.n; D.b = I.b; D.m = I.m; D.N = I.N; D.Noff = I.Noff; D.q = F->q + I.Noff;
+    // (the device side indexes stencil sets: boxes of the set width bs)
+    D.d = I.d; D.n = I.n; D.b = I.bs; D.m = I.n / I.bs; D.N = I.N; D.Noff = I.Noff; D.q = F->q + I.Noff;
     const size_t ntypes = I.plan->types.size();
     for (size_t t = 0; t < ntypes; ++t) {
       const SetType& T = I.plan->types[t];
@@ -862,7 +865,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   for (int t = 0; t < 8; ++t) mf.nB_max[t] = 0;
   for (const SppInstance& I : F->inst) {
     int64_t a = 1;
-    for (int x = 0; x < I.d; ++x) a *= I.m;
+    for (int x = 0; x < I.d; ++x) a *= I.n / I.bs;
     mf.anchors_max = std::max(mf.anchors_max, a);
     for (size_t t = 0; t < I.plan->types.size(); ++t) mf.nB_max[t] = std::max(mf.nB_max[t], I.plan->types[t].nB);
   }

@@ -68,6 +68,7 @@ SetType make_type(int d, int b, int mask) {
     ++o[i];
   }
   t.nS = static_cast<int>(S.size()) / d;
+  if (t.nS == 0) return t;   // a set type with no points (boxes of width 1)
   t.nB = static_cast<int>(B.size()) / d;
   t.nG = t.nS + t.nB;
   t.off = S;
@@ -86,20 +87,25 @@ std::string validate_grid(int d, int n, int b) {
   return std::string();
 }
 
-std::string build_plan(int d, int n, int b, int order, Plan& P) {
+std::string build_plan(int d, int n, int b, int order, Plan& P, int pattern) {
   std::ostringstream err;
   {
     std::string v = validate_grid(d, n, b);
     if (!v.empty()) return v;
   }
-  int m = n / b;
+  if (pattern != 0 && pattern != 1) return "pattern must be 0 (sets) or 1 (points)";
+  // The stencil sets partition the grid by boxes of width bs: the leaf
+  // boxes (b), or single points (bs = 1: every point its own set).
+  const int bs = pattern == 1 ? 1 : b;
+  const int m = n / bs;
   P = Plan();
-  P.d = d; P.n = n; P.b = b; P.m = m; P.order = order;
+  P.d = d; P.n = n; P.b = b; P.m = n / b; P.order = order;
+  P.pattern = pattern; P.bs = bs;
   P.N = ipow(n, d);
   const int64_t N = P.N;
   const int ntypes = 1 << d;
   const int64_t nanchor = ipow(m, d);
-  for (int t = 0; t < ntypes; ++t) P.types.push_back(make_type(d, b, t));
+  for (int t = 0; t < ntypes; ++t) P.types.push_back(make_type(d, bs, t));
 
   std::vector<int> owner(N, -1), posmap(N, -1);
   std::vector<int> set_stamp(static_cast<size_t>(ntypes * nanchor), -1);
@@ -119,8 +125,8 @@ std::string build_plan(int d, int n, int b, int order, Plan& P) {
     for (int i = d - 1; i >= 0; --i) {
       int x = static_cast<int>(r % n);
       r /= n;
-      if (x % b == 0) msk |= 1 << i;
-      an += mul * (x / b);
+      if (x % bs == 0) msk |= 1 << i;
+      an += mul * (x / bs);
       mul *= m;
     }
     type = msk;
@@ -132,7 +138,7 @@ std::string build_plan(int d, int n, int b, int order, Plan& P) {
     int64_t a = anchor;
     std::vector<int> ac(d);
     for (int i = d - 1; i >= 0; --i) { ac[i] = static_cast<int>(a % m); a /= m; }
-    for (int i = 0; i < d; ++i) g = g * n + ((ac[i] * b + o[i]) % n + n) % n;
+    for (int i = 0; i < d; ++i) g = g * n + ((ac[i] * bs + o[i]) % n + n) % n;
     return g;
   };
 

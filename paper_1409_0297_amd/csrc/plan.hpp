@@ -62,6 +62,7 @@ struct Level {
 
 struct Plan {
   int d = 0, n = 0, b = 0, m = 0;
+  int pattern = 0, bs = 0;      // stencil sets and their box width (see build_plan)
   int64_t N = 0;
   int order = 0;
   std::vector<SetType> types;
@@ -135,7 +136,11 @@ std::string build_tables(const Plan& P, const std::vector<int>& front_inst, Plan
 std::string validate_grid(int d, int n, int b);
 
 // Builds the plan; returns an empty string on success, else a message.
-std::string build_plan(int d, int n, int b, int order, Plan& plan);
+// pattern 0: stencil sets from the leaf boxes of width b (cells, faces,
+// edges, vertices; Section 2.3); 1: every point its own set with the
+// neighbourhood mu(j) = gamma({j}) (set boxes of width 1).  The fronts use
+// leaf boxes of width b either way.
+std::string build_plan(int d, int n, int b, int order, Plan& plan, int pattern = 0);
 
 // Concatenates the plans of a batch of problems level by level, aligned at
 // the leaves, so that one launch per level covers the fronts of every

@@ -264,6 +264,7 @@ __device__ void right_solve_regs(const SolveJob& J) {
 // One workgroup per set type (blockIdx.x): the types' systems are independent.
 __global__ void __launch_bounds__(64 * kRsWaves) right_solve_kernel(SolveJobs jobs) {
   const SolveJob& J = jobs.job[blockIdx.x];
+  if (J.nS == 0) return;   // (a set type with no points)
   if (J.nB <= kRsWaves * kRsRows && J.nB + J.nS <= 64 * kRsCols) {   // (launched with 64 kRsWaves threads)
     right_solve_regs(J);
     return;
@@ -383,6 +384,10 @@ void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2
   for (int t = 0; t < ntypes; ++t) {
     StencilDev& S = types[t];
     const int nS = S.nS, nB = S.nB, nG = S.nG;
+    if (nS == 0) {   // a set type with no points: nothing to solve
+      jobs.job[t] = SolveJob{0, 0, nullptr, 1, nullptr, 1, nullptr, S.T, 1, info + t};
+      continue;
+    }
     double2* Ggg = w;                          // nG x nG
     double2* M = Ggg + (size_t)nG * nG;        // nG x nB: (G G^H)(gamma, beta) - G(gamma,gamma) G(gamma,beta)
     double2* aug = M + (size_t)nG * nB;        // nB x (nB + nS)
@@ -404,6 +409,7 @@ void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2
   for (int t = 0; t < ntypes; ++t) {
     StencilDev& S = types[t];
     const int nS = S.nS, nB = S.nB, nG = S.nG;
+    if (nS == 0) continue;
     // C_S = G(S, gamma) - T_S G(beta, gamma)
     SPP_HIP(hipMemcpy2DAsync(S.C, sizeof(double2) * nG, ggg[t], sizeof(double2) * nG, sizeof(double2) * nG, nS,
                              hipMemcpyDeviceToDevice, st));

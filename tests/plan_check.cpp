@@ -9,8 +9,9 @@
 // overlap.  Small plans also check that every entry of P is assembled
 // exactly once.
 //
-// usage: plan_check [-s] [-v] d,n,b,order [d,n,b,order ...]   (several: one
-//        batch; -s: streamed storage, see layout_plan; -v: print the levels)
+// usage: plan_check [-s] [-p] [-v] d,n,b,order [d,n,b,order ...]   (several:
+//        one batch; -s: streamed storage, see layout_plan; -p: point stencil
+//        pattern, see build_plan; -v: print the levels)
 // Prints "ok ..." and exits 0, or prints the first violation and exits 1.
 #include <algorithm>
 #include <cstdio>
@@ -54,11 +55,12 @@ bool disjoint(std::vector<std::pair<int64_t, int64_t>> r, int64_t limit, std::st
 }  // namespace
 
 int main(int argc, char** argv) {
-  int first = 1, storage = 0;
+  int first = 1, storage = 0, pattern = 0;
   bool verbose = false;
   while (first < argc && argv[first][0] == '-') {
     const std::string o = argv[first++];
     if (o == "-s") storage = 1;
+    else if (o == "-p") pattern = 1;
     else if (o == "-v") verbose = true;
     else return fail("unknown option " + o);
   }
@@ -68,7 +70,7 @@ int main(int argc, char** argv) {
   for (int a = first; a < argc; ++a) {
     int d, n, b, order;
     if (std::sscanf(argv[a], "%d,%d,%d,%d", &d, &n, &b, &order) != 4) return fail("bad geometry " + std::string(argv[a]));
-    std::string err = build_plan(d, n, b, order, plans[a - first]);
+    std::string err = build_plan(d, n, b, order, plans[a - first], pattern);
     if (!err.empty()) return fail("build_plan: " + err);
     Ns.push_back(plans[a - first].N);
   }
@@ -239,7 +241,7 @@ int main(int argc, char** argv) {
     if (B.type < 0 || B.type >= static_cast<int>(own.types.size())) return fail("block set type");
     const SetType& ST = own.types[B.type];
     int64_t anchors = 1;
-    for (int i = 0; i < own.d; ++i) anchors *= own.m;
+    for (int i = 0; i < own.d; ++i) anchors *= own.n / own.bs;
     if (B.anchor < 0 || B.anchor >= anchors) return fail("block anchor");
     if (B.rowpos < 0 || B.rowpos + ST.nS > static_cast<int64_t>(P.pos.size())) return fail("block row positions");
     if (B.colpos < 0 || B.colpos + ST.nG > static_cast<int64_t>(P.pos.size())) return fail("block column positions");

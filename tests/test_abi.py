@@ -70,7 +70,7 @@ def test_setup_rejects_null_and_bad_options():
     coeff = np.ones(32 * 32)
     pb.coeff = coeff.ctypes.data
     for bad in (dict(tol=0.0), dict(max_iter=0), dict(prec=5), dict(order=9), dict(restart=-1),
-                dict(restart=501), dict(reserved=1)):
+                dict(restart=501), dict(pattern=2), dict(pattern=-1)):
         o = binding.spp_options(prec=0, order=0, tol=1e-8, max_iter=10, flags=0)
         for k, v in bad.items():
             setattr(o, k, v)

@@ -150,3 +150,20 @@ def test_iteration_counts_near_paper_tables(table, waves, n, b, n_p):
     o = pipeline.setup("helmholtz", n, 2, b, c, omega=2 * math.pi * waves)
     _, it, _ = pipeline.solve(o, workloads.grid_delta(n, 2, (n // 2, n // 2)), tol=1e-6)
     assert n_p / 2 <= it <= 2 * n_p
+
+
+def test_point_pattern_preconditioner_reaches_dense_solution():
+    """The point-neighbourhood pattern (mu(j) = gamma({j}), Section 2.3)
+    changes P, not u*: its preconditioned FGMRES reaches the dense solution,
+    and P z = Q r holds for the preconditioned vector."""
+    W = workloads.small(24, 2, 6, waves=3.0, bumps=3)
+    f = W.rhs[0]
+    u_star = pipeline.dense_solution(W.kind, W.n, W.d, W.coeff, f, W.omega)
+    o = pipeline.setup_workload(W, pattern="points")
+    u, it, hist = pipeline.solve(o, f, tol=1e-12, max_iter=200)
+    assert np.linalg.norm(u - u_star) / np.linalg.norm(u_star) <= 1e-9
+    r = np.random.default_rng(3).standard_normal(f.shape) + 0j
+    z = pipeline.precondition(o, r).reshape(-1)
+    from oracle import stencil
+    Qr = stencil.apply_Q(o.stencils, r).reshape(-1)
+    assert np.linalg.norm(o.P @ z - Qr) <= 1e-10 * np.linalg.norm(Qr)

@@ -154,3 +154,34 @@ def test_constant_medium_gives_P_equal_Q():
     st = stencil.Stencils(n, d, b, s)
     assert abs(st.P_matrix(q) - st.Q_matrix()).max() <= 1e-12
     assert abs(st.P_matrix(np.zeros_like(q)) - st.Q_matrix()).max() == 0
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+def test_point_pattern_stencil(d, n):
+    """The point pattern (every point its own set, mu(j) = gamma({j}), Section
+    2.3): one stencil of 3^d - 1 neighbours, least-squares optimal against an
+    independently built G, invariant under the reflections and axis swaps of
+    the grid, and the rows of Q = [1  -T] partition the grid one point each."""
+    s = 4 * math.pi ** 2 * (1.7 if d == 2 else 1.3)
+    st = stencil.Stencils(n, d, 1, s)
+    assert st.masks == [(True,) * d]
+    mask = st.masks[0]
+    T, S, beta = st.T[mask], st.S0[mask], st.beta0[mask]
+    assert T.shape == (1, 3 ** d - 1) and S.tolist() == [0]
+    G = dense_G(n, d, s)
+    gam = np.concatenate([S, beta])
+    out = np.setdiff1d(np.arange(n ** d), gam)
+    A, B = G[np.ix_(beta, out)], G[np.ix_(S, out)]
+    assert np.linalg.norm((B - T @ A) @ A.conj().T) <= 1e-10 * np.linalg.norm(B) * np.linalg.norm(A)
+    # symmetric neighbourhood and symmetric kernel: T(offset) = T(-offset) and
+    # T is invariant under axis permutations
+    offs = stencil.unravel(beta, n, d)
+    offs = np.where(offs > n // 2, offs - n, offs)
+    val = {tuple(o): T[0, i] for i, o in enumerate(offs)}
+    for o, v in val.items():
+        assert abs(val[tuple(-x for x in o)] - v) <= 1e-10 * abs(v)
+        assert abs(val[tuple(reversed(o))] - v) <= 1e-10 * abs(v)
+    rows, cols = st.instances(mask)
+    assert np.array_equal(np.sort(rows.reshape(-1)), np.arange(n ** d))
+    Q = st.Q_matrix()
+    assert Q.nnz == n ** d * 3 ** d

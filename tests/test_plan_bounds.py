@@ -30,9 +30,9 @@ def checker(tmp_path_factory):
     return exe
 
 
-def run(exe, *geoms, streamed=False):
-    r = subprocess.run([exe] + (["-s"] if streamed else []) + [",".join(map(str, g)) for g in geoms],
-                       capture_output=True, text=True, timeout=600)
+def run(exe, *geoms, streamed=False, points=False):
+    r = subprocess.run([exe] + (["-s"] if streamed else []) + (["-p"] if points else [])
+                       + [",".join(map(str, g)) for g in geoms], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
     return r.stdout
 
@@ -82,6 +82,15 @@ def test_3d_128_bisection_plan(checker):
     streamed): 8191 fronts up to 48896, every kernel range checked."""
     out = run(checker, (3, 128, 8, BIS), streamed=True)
     assert "fronts 8191" in out and "max_front 48896" in out, out
+
+
+@pytest.mark.parametrize("geom", [(2, 32, 8, OCT), (2, 64, 8, OCT), (3, 12, 3, BIS), (2, 512, 16, OCT)])
+def test_point_pattern_plans(checker, geom):
+    """Point stencil pattern (every point its own set): same fronts, one
+    assembly block per point, every entry of P assembled once."""
+    out = run(checker, geom, points=True)
+    if geom[1] <= 64:
+        assert "P entries checked" in out
 
 
 def test_bad_geometry_is_reported(checker):

@@ -211,6 +211,42 @@ def schrodinger_workload(n: int, d: int, ell: int, b: int, nrhs: int = 1, instan
                     ell=float(ell), energy=lat.energy, coeff=lat.V, rhs=rhs, tol=tol)
 
 
+def schrodinger_paper(n: int, d: int, example: str, seed: int = 0) -> Workload:
+    """Stand-in for the paper's Schroedinger examples (Section 3.2): ell = n
+    (one grid step per unit of the potential's length scale), E = 2.5 (about
+    4 points per wavelength), a unit grid delta at the centre.  The paper
+    describes its potentials only in words, so these are of the same kind:
+    V(y) = -sum_i D_i exp(-|y - y_i|^2_per / (2 * 1.5^2)) on [0, n)^d with one
+    well per 8^d cell of the domain.  example "random": the (n/8)^d wells at
+    uniformly random positions, D_i ~ U[1, 2] (draw order: positions, then
+    depths); "vacancy": the wells at the cell centres 8 i + 4, D_i = 1.5, the
+    one nearest the domain centre left out."""
+    rng = np.random.default_rng(seed_for(6, seed))
+    cells = (n // 8) ** d
+    if example == "random":
+        centres = rng.uniform(0.0, float(n), size=(cells, d))
+        D = rng.uniform(1.0, 2.0, size=cells)
+    elif example == "vacancy":
+        idx = np.stack(np.meshgrid(*([np.arange(n // 8)] * d), indexing="ij"), axis=-1).reshape(-1, d)
+        centres = 8.0 * idx + 4.0
+        far = np.argmin(np.sum((centres - n / 2.0) ** 2, axis=1))
+        centres = np.delete(centres, far, axis=0)
+        D = np.full(len(centres), 1.5)
+    else:
+        raise ValueError(example)
+    y = np.arange(n, dtype=np.float64)
+    factors = []
+    for k in range(d):
+        delta = y[None, :] - centres[:, k:k + 1]
+        delta = delta - float(n) * np.round(delta / float(n))
+        factors.append(np.exp(-(delta * delta) / (2.0 * 1.5 * 1.5)))
+    sub = "abcdefgh"[:d]
+    V = -np.einsum("i," + ",".join("i" + c for c in sub) + "->" + sub, D, *factors)
+    rhs = grid_delta(n, d, (n // 2,) * d)[None]
+    return Workload(name=f"schrodinger{d}d_paper_{example}_n{n}", kind="schrodinger", n=n, d=d, b=0,
+                    ell=float(n), energy=2.5, coeff=V, rhs=rhs, tol=1e-6)
+
+
 def schrodinger_batch(nrhs: int = 16, per_size: int = 16) -> list:
     """Batched 2D Schroedinger family: per_size instances each of n = 128, 192
     and 256 (ell = n / 8 unit cells per side, so 8 grid points per cell; boxes
