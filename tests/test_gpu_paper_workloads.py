@@ -10,9 +10,12 @@ the paper's n_p.  (Fewer is no defect of the method: at 384^2 the single
 central Gaussian of this medium takes 7 iterations where the paper's took
 28, whose medium evidently scattered more at that frequency.)  The 96^3 rows
 run with b = 6 instead of the paper's 12 (leaf closures of 13^3 points exceed
-the 1024-point stencil limit), in streamed storage with tournament-pivoted
-top fronts; their boxes are two wavelengths wide instead of four, so they
-are held to three times n_p.
+the 1024-point stencil limit), with tournament-pivoted top fronts and
+complex128 fronts; their boxes are two wavelengths wide instead of four, so
+they are held to three times n_p.  (With complex64 fronts the W31 row takes
+84 iterations instead of 8: at 3 points per wavelength and 32 wavelengths
+the FP32 factor is too inexact a preconditioner for the FP64 FGMRES to win
+the accuracy back cheaply.)
 
 The Schroedinger examples (Section 3.2, Figures S21, S22, S31, S32) use
 ell = n and E = 2.5 with potentials described only in words; the stand-ins
@@ -89,7 +92,7 @@ def test_paper_helmholtz_iteration_counts(table, d, waves, n, b, n_p):
     c = medium(table, n, d)
     omega = 2 * math.pi * waves
     order = "bisect" if n == 96 and d == 3 else "octree"
-    prec = "c64" if n == 96 and d == 3 else "c128"
+    prec = "c128"
     S = Solver("helmholtz", n, d, b, c, omega=omega, prec=prec, order=order, tol=1e-6, max_iter=200)
     f = workloads.grid_delta(n, d, (n // 2,) * d)
     u, iters, relres, code = S.solve(f[None])
