@@ -54,9 +54,10 @@ def parse():
                     help="keyed records beside the headline (Gaussian source, batched Schroedinger)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run the timed steps only (for rocprofv3): no timing pass, no other precision, no baseline")
-    ap.add_argument("--workload", choices=["large2d", "schrodinger-batch"], default="large2d",
+    ap.add_argument("--workload", choices=["large2d", "schrodinger-batch", "helmholtz3d"], default="large2d",
                     help="large2d: the 512^2 Helmholtz solve (default, with roofline and CPU baseline); "
-                         "schrodinger-batch: the 48-instance batched Schroedinger family, 16 sources each")
+                         "schrodinger-batch: the 48-instance batched Schroedinger family, 16 sources each; "
+                         "helmholtz3d: one step of the 128^3 3D configuration (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the steps, copy a MIB-MiB device buffer once (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -314,6 +315,15 @@ def main():
         sys.exit(2)
     if args.workload == "schrodinger-batch":
         return batch_main(args)
+    if args.workload == "helmholtz3d":
+        rec = record_3d(args)
+        print(json.dumps({"metric": "solves/sec to rel. err 1e-8 (mixed vs FP64), GMRES iters, HBM/MFMA % peak",
+                          "value": rec["value"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+                          "ms_per_step": rec["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "c64-fronts/f64", "data": "synthetic",
+                          "config": {"workload": rec["workload"]}, "record": rec, "roofline": None,
+                          "cpu_baseline": None}), flush=True)
+        return
     import torch
 
     import workloads
