@@ -234,6 +234,28 @@ int spp_solve_batch(spp_factor* factor, const void* const* f, const int32_t* nrh
    names a file, the table is read from it at first use and rewritten here. */
 int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream);
 
+/* The process-wide tuning table, entry by entry.  key: NUL-terminated text
+   "<kind>@<arch>:<size>:<size>...", as the table file holds it.  Kinds:
+     fft_lines    lines per workgroup of an FFT pass;
+     gemv_chunks  column chunks of a substitution product;
+     mf_form      solve form of a level, keyed by front bytes (8 complex64,
+                  16 complex128), fronts, largest F, largest p:
+                  0 LU in place, 1 inverses of L11 / U11, 2 side products;
+     mf_steps     step schedule of that level: bit 0 paired steps (one
+                  rank-64 update per two 32-column steps), bit 1 L21 / U12 on
+                  64 x 64 tiles (else 128 x 32 / 32 x 128).
+   Setups (with SPP_F_AUTOTUNE and resident storage) fill the mf_ entries by
+   timing every candidate on the factorisation itself; a level's solve form
+   counts its substitution as 20 preconditioner applies per factorisation.
+   Factors set up later use the table whether or not they tune; an entry that
+   does not apply to a level (LU in place on fronts whose vectors exceed the
+   solve kernels' LDS) is ignored there.
+   spp_tune_set: value >= 0 sets the entry, value < 0 removes it; not written
+   to the SPP_TUNE_CACHE file until the next tuning run saves the table.
+   spp_tune_get: *value = the entry, SPP_EINVAL if absent (or key null). */
+int spp_tune_set(const char* key, int32_t value);
+int spp_tune_get(const char* key, int32_t* value);
+
 /* ---- components of the hot path, exposed for testing and benchmarking ----- */
 
 /* w = (I + G q) z (Section 2.2); z, w DEVICE complex128 [nrhs][n^d]; may alias. */

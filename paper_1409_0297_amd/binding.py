@@ -106,6 +106,8 @@ def library():
         "spp_learned_stats": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "spp_get_krylov": (I, [P, I, P, P]),
         "spp_autotune": (I, [P, I, P]),
+        "spp_tune_set": (I, [ctypes.c_char_p, I]),
+        "spp_tune_get": (I, [ctypes.c_char_p, ctypes.POINTER(I)]),
         "spp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -620,3 +622,15 @@ def spp_get_krylov(handle, j: int, v_ptr, z_ptr):
 
 def spp_autotune(handle, nrhs: int, stream: int):
     _check(library().spp_autotune(handle, nrhs, ctypes.c_void_p(stream)), "spp_autotune")
+
+
+def spp_tune_set(key: str, value: int):
+    """Set (value >= 0) or remove (value < 0) one entry of the tuning table."""
+    _check(library().spp_tune_set(key.encode(), int(value)), "spp_tune_set")
+
+
+def spp_tune_get(key: str):
+    """The tuning table's entry for key, or None if it has none."""
+    v = ctypes.c_int32(0)
+    code = library().spp_tune_get(key.encode(), ctypes.byref(v))
+    return v.value if code == SPP_OK else None

@@ -306,6 +306,7 @@ struct spp_factor {
   void* dkeep = nullptr;       // diagonal-block inverses of blocked levels
   size_t csize = 16;  // bytes per complex front entry
   std::vector<int> level_begin, level_maxF, level_maxK, level_maxP, level_form;
+  std::vector<int> level_var;  // step schedule per level (kVarPair, kVarTile64)
   int64_t xwork_elems = 0;     // inverse work of the levels solved by products
   void* gpart = nullptr;       // split-K partial sums of the substitution
   int64_t gpart_cap = 0;
@@ -550,6 +551,29 @@ void apply_precond(spp_factor* F, const double2* r, double2* z, int nrhs, hipStr
   precond_tail(F, z, nrhs, st, persistent);
 }
 
+// Tuning-table keys of a level's solve form and step schedule: front
+// precision and the level's shape (fronts, largest F, largest p).
+std::string form_tune_key(size_t csize, const Level& L) {
+  return tune_key("mf_form", {(int64_t)csize, L.end - L.begin, L.maxF, L.maxP});
+}
+std::string var_tune_key(size_t csize, const Level& L) {
+  return tune_key("mf_steps", {(int64_t)csize, L.end - L.begin, L.maxF, L.maxP});
+}
+// Forms a tuned level may take: the whole-front solve kernels hold the
+// front's vectors of four right-hand sides and a 32 x 33 diagonal block in
+// 64 KB of LDS; the side products unless the caller turned them off.
+// (Blocked levels are not tuned.)
+bool form_valid(int form, const Level& L, size_t csize, int32_t flags) {
+  if (form == kFormLU) return ((int64_t)(L.maxF + L.maxP) * 4 + 32 * 33) * (int64_t)csize <= 65536;
+  if (form == kFormInverse) return true;
+  if (form == kFormSide) return !(flags & SPP_F_NO_SIDE);
+  return false;
+}
+// The tuning pass weighs a level's substitution time (forward and backward)
+// against its factorisation time as this many preconditioner applies per
+// factorisation.
+constexpr double kTuneAppliesPerFactor = 20.0;
+
 void validate_problem(const spp_problem* pb) {
   if (!pb->coeff) throw Error(SPP_EINVAL, "coeff is null");
   if (pb->kind != SPP_HELMHOLTZ && pb->kind != SPP_SCHRODINGER) throw Error(SPP_EINVAL, "unknown problem kind");
@@ -573,12 +597,20 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
   KernelTimer* saved = g_timer;
   g_timer = nullptr;
   const int64_t vstride = (int64_t)nrhs * F->Ntot;
-  SPP_HIP(hipMemsetAsync(F->wk, 0, sizeof(double2) * vstride, st));
-  SPP_HIP(hipMemsetAsync(F->tmp, 0, sizeof(double2) * vstride, st));
-  SPP_HIP(hipMemsetAsync(F->qr, 0, sizeof(double2) * vstride, st));
-  SPP_HIP(hipMemsetAsync(F->wv, 0, (size_t)F->planp->vec_elems * nrhs * F->csize, st));
-  SPP_HIP(hipMemsetAsync(F->zv, 0, (size_t)F->planp->vec_elems * nrhs * F->csize, st));
-  SPP_HIP(hipMemsetAsync(F->xc, 0, (size_t)F->Ntot * nrhs * F->csize, st));
+  // Scratch contents and the cache-flushing buffer are set up only when some
+  // key is missing (a factor whose shapes are all tuned costs nothing here).
+  const size_t flush_bytes = (size_t)768 << 20;
+  void* flush = nullptr;
+  auto prepare = [&] {
+    if (flush) return;
+    SPP_HIP(hipMemsetAsync(F->wk, 0, sizeof(double2) * vstride, st));
+    SPP_HIP(hipMemsetAsync(F->tmp, 0, sizeof(double2) * vstride, st));
+    SPP_HIP(hipMemsetAsync(F->qr, 0, sizeof(double2) * vstride, st));
+    SPP_HIP(hipMemsetAsync(F->wv, 0, (size_t)F->planp->vec_elems * nrhs * F->csize, st));
+    SPP_HIP(hipMemsetAsync(F->zv, 0, (size_t)F->planp->vec_elems * nrhs * F->csize, st));
+    SPP_HIP(hipMemsetAsync(F->xc, 0, (size_t)F->Ntot * nrhs * F->csize, st));
+    flush = F->dalloc<char>(flush_bytes);
+  };
   for (const SppGroup& g : F->groups) {
     const int batch = g.ninst * nrhs;
     const int64_t o = g.Noff * nrhs, n = g.n;
@@ -588,6 +620,7 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
     for (const auto& ax : axes) {
       const std::string key = fft_tune_key(g.n, ax.first, ax.second, batch);
       if (tune_has(key)) continue;
+      prepare();
       int best = fft_lines_default(g.n, ax.first, ax.second);
       float bt = 1e30f;
       for (int L = 1; (int64_t)L * n <= 4096; L *= 2) {
@@ -605,8 +638,6 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
   }
   const Plan& P = *F->planp;
   // (the substitution candidates are timed with cold caches, see tune_time)
-  const size_t flush_bytes = (size_t)768 << 20;
-  void* flush = F->dalloc<char>(flush_bytes);
   for (size_t l = 0; l < P.levels.size(); ++l) {
     if (F->level_form[l] == kFormLU) continue;
     const Level& L = P.levels[l];
@@ -624,6 +655,7 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
     for (const Prod& pr : prods) {
       const std::string key = gemv_tune_key(pr.rows, pr.cols, nf, pr.mode, nrhs, (int)F->csize);
       if (tune_has(key)) continue;
+      prepare();
       int best = gemv_chunks_default(pr.rows, pr.cols, nf, nrhs, F->gpart_cap);
       float bt = 1e30f;
       for (int c = 1; c <= std::max(1, pr.cols / 16) && c <= 256; c *= 2) {
@@ -641,11 +673,119 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
       tune_set(key, best);
     }
   }
-  SPP_HIP(hipStreamSynchronize(st));
-  F->dfree(flush);
-  tune_save();
+  if (flush) {
+    SPP_HIP(hipStreamSynchronize(st));
+    F->dfree(flush);
+    tune_save();
+  }
   g_timer = saved;
   F->tuned_nrhs = nrhs;
+}
+
+// Tuning pass of the factorisation (SPP_F_AUTOTUNE, resident storage): the
+// whole factorisation runs once per candidate, with HIP events around every
+// level, and each level keeps its fastest candidate (levels are timed
+// separately, so one run serves them all):
+//  1. each solve form (LU in place, inverses, side products) on every level
+//     where it is valid, scored as the level's factorisation time plus
+//     kTuneAppliesPerFactor times its substitution time (one right-hand
+//     side, forward and backward, the best of three);
+//  2. with those forms, each step schedule (single or paired steps, 64 x 64
+//     or 128 x 32 / 32 x 128 L21 / U12 tiles), scored by factorisation time.
+// The choices go to the tuning table (keys mf_form / mf_steps with the
+// level's shape) and into F's level_form / level_var.  factor_all(forms,
+// vars, events) assembles and factors every level.
+template <typename FactorAll>
+void tune_factorisation(spp_factor* F, FactorAll&& factor_all, hipStream_t st) {
+  const Plan& P = *F->planp;
+  const int nl = static_cast<int>(P.levels.size());
+  KernelTimer* saved_timer = g_timer;   // (tuning runs are not the caller's kernel time)
+  g_timer = nullptr;
+  std::vector<hipEvent_t> ev(4 * (size_t)nl);
+  for (hipEvent_t& e : ev) SPP_HIP(hipEventCreate(&e));
+  const size_t cs = F->csize;
+  void* tw = F->dalloc<char>((size_t)P.vec_elems * cs);
+  void* tz = F->dalloc<char>((size_t)P.vec_elems * cs);
+  void* tin = F->dalloc<char>((size_t)F->Ntot * cs);
+  void* tout = F->dalloc<char>((size_t)F->Ntot * cs);
+  const int64_t tcap = (int64_t)1 << 20;
+  void* tpart = F->dalloc<char>((size_t)tcap * cs);
+  for (void* b : {tw, tz})
+    SPP_HIP(hipMemsetAsync(b, 0, (size_t)P.vec_elems * cs, st));
+  for (void* b : {tin, tout}) SPP_HIP(hipMemsetAsync(b, 0, (size_t)F->Ntot * cs, st));
+  auto elapsed = [&](hipEvent_t a, hipEvent_t b) {
+    float ms = 0;
+    SPP_HIP(hipEventElapsedTime(&ms, a, b));
+    return (double)ms;
+  };
+  // (small factorisations run each candidate twice and keep the faster run)
+  const int reps = P.factor_flops < 2e11 ? 2 : 1;
+  auto factor_times = [&](const std::vector<int>& forms, const std::vector<int>& vars) {
+    std::vector<double> t(nl, 1e30);
+    for (int r = 0; r < reps; ++r) {
+      factor_all(forms, vars, ev.data());
+      SPP_HIP(hipStreamSynchronize(st));
+      for (int l = 0; l < nl; ++l) t[l] = std::min(t[l], elapsed(ev[2 * l], ev[2 * l + 1]));
+    }
+    return t;
+  };
+  auto solve_times = [&](const std::vector<int>& forms) {
+    std::vector<double> t(nl, 1e30);
+    const double* ent = F->pd->level_ent.data();
+    for (int r = 0; r < 3; ++r) {
+      if (F->opt.prec == SPP_C128)
+        mf_solve<double>(st, F->mf, F->arena, tw, tz, tin, tout, 1, F->level_begin.data(), F->level_maxF.data(),
+                         F->level_maxK.data(), F->level_maxP.data(), ent, forms.data(), nl, tpart, tcap, false,
+                         ev.data());
+      else
+        mf_solve<float>(st, F->mf, F->arena, tw, tz, tin, tout, 1, F->level_begin.data(), F->level_maxF.data(),
+                        F->level_maxK.data(), F->level_maxP.data(), ent, forms.data(), nl, tpart, tcap, false,
+                        ev.data());
+      SPP_HIP(hipStreamSynchronize(st));
+      for (int l = 0; l < nl; ++l)
+        t[l] = std::min(t[l], elapsed(ev[4 * l], ev[4 * l + 1]) + elapsed(ev[4 * l + 2], ev[4 * l + 3]));
+    }
+    return t;
+  };
+  std::vector<int> forms = F->level_form, vars = F->level_var;
+  std::vector<double> best(nl, 1e30);
+  std::vector<int> best_form = forms;
+  for (int cand : {kFormLU, kFormInverse, kFormSide}) {
+    std::vector<int> fc = forms;
+    bool any = false;
+    for (int l = 0; l < nl; ++l) {
+      if (forms[l] == kFormBlocked || !form_valid(cand, P.levels[l], cs, F->opt.flags)) continue;
+      fc[l] = cand;
+      any = true;
+    }
+    if (!any) continue;
+    const std::vector<double> tf = factor_times(fc, vars);
+    const std::vector<double> ts = solve_times(fc);
+    for (int l = 0; l < nl; ++l) {
+      if (fc[l] != cand) continue;
+      const double score = tf[l] + kTuneAppliesPerFactor * ts[l];
+      if (score < best[l]) { best[l] = score; best_form[l] = cand; }
+    }
+  }
+  std::vector<double> bt(nl, 1e30);
+  std::vector<int> best_var = vars;
+  for (int v : {kVarTile64, 0, kVarPair, kVarPair | kVarTile64}) {
+    const std::vector<int> vc(nl, v);
+    const std::vector<double> tf = factor_times(best_form, vc);
+    for (int l = 0; l < nl; ++l)
+      if (tf[l] < bt[l]) { bt[l] = tf[l]; best_var[l] = v; }
+  }
+  for (int l = 0; l < nl; ++l) {
+    if (forms[l] == kFormBlocked) continue;
+    tune_set(form_tune_key(cs, P.levels[l]), best_form[l]);
+    tune_set(var_tune_key(cs, P.levels[l]), best_var[l]);
+  }
+  tune_save();
+  F->level_form = best_form;
+  F->level_var = best_var;
+  for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
+  for (void* b : {tw, tz, tin, tout, tpart}) F->dfree(b);
+  g_timer = saved_timer;
 }
 
 int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream_t st, spp_factor** out) {
@@ -692,6 +832,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   F->pd = get_plan(geoms, storage);
   F->planp = &F->pd->plan;
   const Plan& P = *F->planp;
+  bool tune_fac = false;   // run the factorisation tuning pass (below)
 
   // Problems, and groups of consecutive problems with equal grids.
   int64_t Noff = 0;
@@ -728,21 +869,42 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       stencil_elems += w;
       Nmax_ = std::max(Nmax_, I.N);
     }
+    // Solve form and step schedule per level: the tuned choice where the
+    // tuning table has one for the level's shape, else the heuristic.  A
+    // tuning pass (SPP_F_AUTOTUNE, resident storage, some level untuned)
+    // tries the forms on every level, so its inverse work is sized for all.
+    tune_fac = (op->flags & SPP_F_AUTOTUNE) && P.storage == 0 && !(op->flags & SPP_F_PARTIAL_PIVOTING);
+    bool untuned = false;
+    int64_t xwork_all = 0;
     for (const Level& L : P.levels) {
-      int form = mf_level_solve_form(L.end - L.begin, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS, P.storage == 1);
+      const int nf = L.end - L.begin;
+      int form = mf_level_solve_form(nf, L.maxF, L.maxP, op->prec == SPP_C64_FRONTS, P.storage == 1);
+      int var = mf_default_variant(nf);
+      if (form != kFormBlocked && P.storage == 0) {
+        const int tf = tune_get(form_tune_key(F->csize, L), -1);
+        if (tf >= 0 && form_valid(tf, L, F->csize, op->flags)) form = tf;
+        else untuned = true;
+        const int tv = tune_get(var_tune_key(F->csize, L), -1);
+        if (tv >= 0 && tv <= (kVarPair | kVarTile64)) var = tv;
+        else untuned = true;
+      }
       if (form == kFormSide && (op->flags & SPP_F_NO_SIDE)) form = kFormInverse;
       F->level_form.push_back(form);
-      if (form == kFormInverse || form == kFormSide) {
-        int64_t xo = 0;
-        for (int fi = L.begin; fi < L.end; ++fi) xo += 2LL * P.fronts[fi].p * P.fronts[fi].F;
-        F->xwork_elems = std::max(F->xwork_elems, xo);
-      }
+      F->level_var.push_back(var);
+      int64_t xo = 0;
+      for (int fi = L.begin; fi < L.end; ++fi) xo += 2LL * P.fronts[fi].p * P.fronts[fi].F;
+      if (form == kFormInverse || form == kFormSide) F->xwork_elems = std::max(F->xwork_elems, xo);
+      if (form != kFormBlocked) xwork_all = std::max(xwork_all, xo);
     }
+    tune_fac = tune_fac && untuned;
     const size_t cs = F->csize;
-    const size_t need = ((size_t)P.arena_elems + (size_t)P.fstore_elems) * cs + (size_t)F->xwork_elems * cs * 3 / 2 +
-                        (size_t)2 * 32 * 32 * F->pd->dblk_total * cs + sizeof(double2) * stencil_elems +
-                        sizeof(double) * 2 * (size_t)F->Ntot + sizeof(double2) * 4 * (size_t)Nmax_ +
-                        sizeof(int) * 3 * (size_t)F->pd->perm_total + sizeof(unsigned) * P.fronts.size();
+    auto need_bytes = [&](int64_t xwork) {
+      return ((size_t)P.arena_elems + (size_t)P.fstore_elems) * cs + (size_t)xwork * cs * 3 / 2 +
+             (size_t)2 * 32 * 32 * F->pd->dblk_total * cs + sizeof(double2) * stencil_elems +
+             sizeof(double) * 2 * (size_t)F->Ntot + sizeof(double2) * 4 * (size_t)Nmax_ +
+             sizeof(int) * 3 * (size_t)F->pd->perm_total + sizeof(unsigned) * P.fronts.size();
+    };
+    size_t need = need_bytes(F->xwork_elems);
     F->stats.device_bytes = (int64_t)need;
     if (!op->alloc) {
       size_t freeb = 0, totalb = 0;
@@ -752,10 +914,18 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
         std::lock_guard<std::mutex> lk(g_mem_mu);
         cached = g_mem_cached;
       }
+      // (the tuning pass, with the inverse work of every level and its own
+      // solve vectors, runs only where that fits besides the rest)
+      const size_t tune_extra = (size_t)(2 * P.vec_elems + 2 * F->Ntot + (1 << 20)) * cs;
+      if (tune_fac && need_bytes(std::max(F->xwork_elems, xwork_all)) + tune_extra > (freeb + cached) * 0.9)
+        tune_fac = false;
       if (need > freeb + cached)
         throw Error(SPP_ENOMEM, "memory plan: the setup needs " + std::to_string(need >> 20) + " MiB, the device has " +
                                     std::to_string((freeb + cached) >> 20) + " MiB free");
+    } else {
+      tune_fac = false;   // (caller-owned memory: no extra blocks for tuning)
     }
+    if (tune_fac) F->xwork_elems = std::max(F->xwork_elems, xwork_all);
   }
   F->q = F->dalloc<double>(F->Ntot);
   F->sigma = F->dalloc<double>(F->Ntot);
@@ -898,36 +1068,50 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   }
   SPP_HIP(hipStreamSynchronize(st));
   for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p);
-  const double tf0 = now_ms();
-  if (!streamed) SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
-  for (size_t l = 0; l < P.levels.size(); ++l) {
-    const Level& L = P.levels[l];
-    const int* hF = F->pd->level_F[l].data();
-    const int* hP = F->pd->level_p[l].data();
-    // Streamed storage: this level's arena range held fronts two levels
-    // down, whose Schur complements the level below has already added.
-    if (streamed)
-      SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + (size_t)L.arena_lo * F->csize, 0,
-                             (size_t)(L.arena_hi - L.arena_lo) * F->csize, st));
-    // Large pivot blocks choose their pivots over all their fully-summed
-    // rows (by tournament): pivots chosen inside 32-row blocks let the
-    // multipliers below the block, and with them the growth of the Schur
-    // updates, grow with the front.
-    const int piv = partial_pivoting ? kPivotPartial
-                    : F->level_form[l] == kFormBlocked ? kPivotTournament : kPivotBlockLocal;
-    if (F->opt.prec == SPP_C128)
-      mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP, L.blk_begin,
-                              L.blk_end, L.max_children, F->level_form[l], piv, hF, hP);
-    else
-      mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP, L.blk_begin,
-                             L.blk_end, L.max_children, F->level_form[l], piv, hF, hP);
-    if (streamed) {
+  const int nl = static_cast<int>(P.levels.size());
+  // Assembly and factorisation of every level with the given solve forms and
+  // step schedules; fev (optional) gets two events per level around it.
+  auto factor_all = [&](const std::vector<int>& forms, const std::vector<int>& vars, hipEvent_t* fev) {
+    SPP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));           // breakdown front
+    SPP_HIP(hipMemsetAsync(mf.fnorm, 0, sizeof(unsigned) * P.fronts.size(), st));
+    SPP_HIP(hipMemsetAsync(info + 9, 0, 2 * sizeof(int), st));   // small pivots, fatal flag
+    SPP_HIP(hipMemsetAsync(mf.pstat, 0, sizeof(unsigned), st));
+    SPP_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(mf.pstat + 1), 0x7f7fffff, 1, st));
+    if (!streamed) SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
+    for (int l = 0; l < nl; ++l) {
+      const Level& L = P.levels[l];
+      const int* hF = F->pd->level_F[l].data();
+      const int* hP = F->pd->level_p[l].data();
+      if (fev) SPP_HIP(hipEventRecord(fev[2 * l], st));
+      // Streamed storage: this level's arena range held fronts two levels
+      // down, whose Schur complements the level below has already added.
+      if (streamed)
+        SPP_HIP(hipMemsetAsync(static_cast<char*>(F->arena) + (size_t)L.arena_lo * F->csize, 0,
+                               (size_t)(L.arena_hi - L.arena_lo) * F->csize, st));
+      // Large pivot blocks choose their pivots over all their fully-summed
+      // rows (by tournament): pivots chosen inside 32-row blocks let the
+      // multipliers below the block, and with them the growth of the Schur
+      // updates, grow with the front.
+      const int piv = partial_pivoting ? kPivotPartial
+                      : forms[l] == kFormBlocked ? kPivotTournament : kPivotBlockLocal;
       if (F->opt.prec == SPP_C128)
-        mf_store_factors<double>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
+        mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP,
+                                L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP);
       else
-        mf_store_factors<float>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
+        mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP,
+                               L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP);
+      if (streamed) {
+        if (F->opt.prec == SPP_C128)
+          mf_store_factors<double>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
+        else
+          mf_store_factors<float>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
+      }
+      if (fev) SPP_HIP(hipEventRecord(fev[2 * l + 1], st));
     }
-  }
+  };
+  if (tune_fac) tune_factorisation(F.get(), factor_all, st);
+  const double tf0 = now_ms();
+  factor_all(F->level_form, F->level_var, nullptr);
   int hinfo[16];
   unsigned hpstat[2];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
@@ -1305,6 +1489,23 @@ int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream) {
   return guarded([&] {
     if (!factor || nrhs < 1) throw Error(SPP_EINVAL, "null factor or nrhs < 1");
     do_autotune(factor, nrhs, reinterpret_cast<hipStream_t>(stream));
+    return SPP_OK;
+  });
+}
+
+int spp_tune_set(const char* key, int32_t value) {
+  return guarded([&] {
+    if (!key || !*key) throw Error(SPP_EINVAL, "null or empty tuning key");
+    tune_set(key, value);
+    return SPP_OK;
+  });
+}
+
+int spp_tune_get(const char* key, int32_t* value) {
+  return guarded([&] {
+    if (!key || !value) throw Error(SPP_EINVAL, "null tuning key or value");
+    if (!tune_has(key)) throw Error(SPP_EINVAL, std::string("no tuning entry ") + key);
+    *value = tune_get(key, -1);
     return SPP_OK;
   });
 }

@@ -149,10 +149,23 @@ constexpr int kPivotBlockLocal = 0, kPivotPartial = 1, kPivotTournament = 2;
 // Candidate-row buffer a tournament-pivoted level needs (ints).
 inline int64_t mf_tournament_ints(int nfronts, int maxP) { return 2LL * nfronts * ((maxP + 255) / 256) * 32; }
 
+// Step schedule of a block-locally pivoted level (bits of `variant`):
+//  kVarPair:   two elimination steps per trailing update (the second block's
+//              column and row take the first step's update on their own,
+//              then one rank-64 product); without it, one step per trailing
+//              update with the next diagonal block factored inside it;
+//  kVarTile64: L21 / U12 of each step on 64 x 64 tiles (twice the workgroups,
+//              shorter launches) instead of 128 x 32 / 32 x 128 tiles.
+// mf_default_variant is the untuned choice: pairs on levels of more than 64
+// fronts (they fill the device, their trailing updates stream the fronts),
+// single steps with 64 x 64 L21 / U12 tiles on the others.
+constexpr int kVarPair = 1, kVarTile64 = 2;
+inline int mf_default_variant(int nfronts) { return nfronts > 64 ? kVarPair : kVarTile64; }
+
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* tbuf, void* dinv, int* tpbuf,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
-                     int max_children, int form, int pivoting,
+                     int max_children, int form, int pivoting, int variant,
                      const int* hF, const int* hP);   // host: F and p of the level's fronts
 // How a level's fronts are kept for the substitution:
 //  kFormLU:      LU in place, one workgroup per front solves;
@@ -180,7 +193,8 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void*
               const void* x_in, void* x_out, int nrhs,
               const int* level_begin, const int* level_maxF, const int* level_maxK,
               const int* level_maxP, const double* level_ent, const int* level_form, int nlevels,
-              void* partial, int64_t partial_cap, bool persistent);
+              void* partial, int64_t partial_cap, bool persistent,
+              hipEvent_t* level_events = nullptr);   // optional: 4 per level, see mf_solve
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);

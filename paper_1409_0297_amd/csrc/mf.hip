@@ -125,21 +125,37 @@ __global__ void extend_add_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int f
 // ------------------------------------------------------------------ front norm
 // Largest |entry| of every front of a level as assembled (after the
 // extend-add), as float bits in mf.fnorm (entries are >= 0, so the bit
-// patterns order like the values).  blockIdx.x = chunk of cols_per_wg
-// columns, blockIdx.y = front.
+// patterns order like the values).
 template <typename R>
 __global__ void __launch_bounds__(256) front_norm_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, int f0,
-                                                         int cols_per_wg) {
+                                                         int64_t chunk) {
+  // Workgroup (x, y): entries [x chunk, (x + 1) chunk) of front f0 + y, read
+  // as one flat array (the front is F x F contiguous); four loads in flight
+  // per thread, squared magnitudes compared, one atomic per workgroup.
   const int fi = f0 + blockIdx.y;
   const FrontDev& f = mf.fronts[fi];
-  const int64_t j0 = (int64_t)blockIdx.x * cols_per_wg;
-  if (j0 >= f.F) return;
-  const int64_t e1 = min<int64_t>(f.F, j0 + cols_per_wg) * f.F;
+  const int64_t n = (int64_t)f.F * f.F;
+  const int64_t e0 = (int64_t)blockIdx.x * chunk;
+  if (e0 >= n) return;
+  const int64_t e1 = min(n, e0 + chunk);
   const cplx_t<R>* A = arena + f.off;
-  float m = 0.f;
-  for (int64_t e = j0 * f.F + threadIdx.x; e < e1; e += blockDim.x) m = fmaxf(m, (float)sqrt(cabs2(A[e])));
+  R m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+  int64_t e = e0 + threadIdx.x;
+  for (; e + 768 < e1; e += 1024) {
+    const cplx_t<R> a = A[e], b = A[e + 256], c = A[e + 512], d = A[e + 768];
+    m0 = fmax(m0, cabs2(a));
+    m1 = fmax(m1, cabs2(b));
+    m2 = fmax(m2, cabs2(c));
+    m3 = fmax(m3, cabs2(d));
+  }
+  for (; e < e1; e += 256) m0 = fmax(m0, cabs2(A[e]));
+  float m = (float)sqrt((double)fmax(fmax(m0, m1), fmax(m2, m3)));
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(mf.fnorm + fi, __float_as_uint(m));
+  __shared__ float wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(mf.fnorm + fi, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 // ------------------------------------------------------------------ panel LU
@@ -2193,9 +2209,11 @@ constexpr int kOuterNB = 256;   // columns per outer block of the tournament-piv
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* tbuf_v, void* dinv_v,
                      int* tpbuf, int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, int form,
-                     int pivoting, const int* hF, const int* hP) {
+                     int pivoting, int variant, const int* hF, const int* hP) {
   const bool partial_pivoting = pivoting == kPivotPartial;
   const bool tournament = pivoting == kPivotTournament;
+  const bool pair_steps = (variant & kVarPair) != 0;
+  const bool tile64 = (variant & kVarTile64) != 0;
   const bool invert = form == kFormInverse || form == kFormSide;
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
@@ -2213,8 +2231,9 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     SPP_LAUNCH_CHECK();
   }
   if (!partial_pivoting) {
-    const int cols = 16;
-    front_norm_kernel<R><<<dim3(ceil_div(maxF, cols), nf), 256, 0, st>>>(mf, arena, f0, cols);
+    const int64_t chunk = 16384;
+    front_norm_kernel<R><<<dim3((unsigned)ceil_div((int64_t)maxF * maxF, chunk), nf), 256, 0, st>>>(mf, arena, f0,
+                                                                                                   chunk);
     SPP_LAUNCH_CHECK();
   }
   const int steps = (maxP + kNB - 1) / kNB;
@@ -2301,11 +2320,22 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     SPP_LAUNCH_CHECK();
     timer_end(KC_PANEL, st, 0.0, 0.0);
   }
-  // Wide levels (many fronts fill the device; their trailing updates move
-  // the front through HBM at every step) go two steps at a time: the second
-  // block's column and row take the first step's update on their own, then
-  // one rank-64 trailing update serves both steps, halving that traffic.
-  if (!partial_pivoting && !tournament && nf > 64) {
+  // L21 / U12 of one step: 64 x 64 tiles (mode 6) or 128 x 32 / 32 x 128
+  // tiles (mode 7), as the level's variant says.
+  auto l21_u12 = [&](int s, double fl) {
+    gemm_timed(fl, [&] {
+      if (tile64)
+        gemm_kernel<R, 6><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
+      else
+        gemm_kernel<R, 7><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128);
+    });
+  };
+  // Paired steps (wide levels by default: many fronts fill the device, and
+  // their trailing updates move the front through HBM at every step): the
+  // second block's column and row take the first step's update on their
+  // own, then one rank-64 trailing update serves both steps, halving that
+  // traffic.
+  if (!partial_pivoting && !tournament && pair_steps) {
     // One kernel per timed interval (bench.py divides a class's time by its
     // intervals): L21 / U12 of each step 16 m kb^2, the second block's
     // column and row 8 kb kb2 (m + m - kb2), the trailing update 8 mn^2 w.
@@ -2330,9 +2360,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
         SPP_LAUNCH_CHECK();
         timer_end(KC_PANEL, st, 0.0, 0.0);
       }
-      gemm_timed(fl7a, [&] {
-        gemm_kernel<R, 7><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128);
-      });
+      l21_u12(s, fl7a);
       if (pair) {
         gemm_timed(fln, [&] {
           gemm_kernel<R, 3><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles128);
@@ -2341,9 +2369,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
         diag_lu_kernel<R><<<nf, 256, 0, st>>>(mf, arena, dinv, f0, k0 + kNB, kNB);
         SPP_LAUNCH_CHECK();
         timer_end(KC_PANEL, st, 0.0, 0.0);
-        gemm_timed(fl7b, [&] {
-          gemm_kernel<R, 7><<<dim3(2 * tiles128, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s + 1, kNB, tiles128);
-        });
+        l21_u12(s + 1, fl7b);
         gemm_timed(flt, [&] {
           gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s / 2, 2 * kNB,
                                                                      tiles);
@@ -2357,7 +2383,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       }
     }
   }
-  for (int s = 0; s < steps && !tournament && (partial_pivoting || nf <= 64); ++s) {
+  for (int s = 0; s < steps && !tournament && (partial_pivoting || !pair_steps); ++s) {
     const int k0 = s * kNB;
     if (partial_pivoting) {
       timer_begin(KC_PANEL, st);
@@ -2376,8 +2402,8 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       trsm_kernel<R><<<dim3(ceil_div(maxF, 256), nf), 256, 0, st>>>(mf, arena, xwork, f0, s, kNB, 0);
     } else {
       // L21 = A21 Uinv_kk and U12 = Linv_kk P A12 on MFMA in one launch (one
-      // 64-wide tile strip each); the block's row order P is applied while
-      // loading A12, the rows' L parts are reordered once after the last step.
+      // tile strip each); the block's row order P is applied while loading
+      // A12, the rows' L parts are reordered once after the last step.
       // 16 m kb^2 real flops per front (m = F - k0 - kb rows and columns).
       double fl = 0;
       if (g_timer)
@@ -2386,9 +2412,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
           const double kb = std::min(kNB, hP[i] - k0), m = hF[i] - k0 - kb;
           fl += 16.0 * m * kb * kb;
         }
-      timer_begin(KC_GEMM, st);
-      gemm_kernel<R, 6><<<dim3(2 * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
-      timer_end(KC_GEMM, st, 0.0, fl);
+      l21_u12(s, fl);
     }
     SPP_LAUNCH_CHECK();
     {
@@ -2401,10 +2425,9 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
           fl += 8.0 * mn * mn * kb;
         }
       timer_begin(KC_GEMM, st);
-      // Levels of few fronts take the next diagonal block into the trailing
-      // launch (the step's serial part overlaps the update); wide levels
-      // already fill the device and keep the lighter kernel.
-      if (!partial_pivoting && s + 1 < steps && nf <= 64)
+      // Single steps take the next diagonal block into the trailing launch
+      // (the step's serial part overlaps the update).
+      if (!partial_pivoting && s + 1 < steps)
         gemm_next_kernel<R><<<dim3(tiles * tiles + 1, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
       else
         gemm_kernel<R, 0><<<dim3(tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB, tiles);
@@ -2579,8 +2602,19 @@ template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
               void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxK,
               const int* level_maxP, const double* level_ent, const int* level_form, int nlevels, void* partial_v,
-              int64_t partial_cap, bool persistent) {
+              int64_t partial_cap, bool persistent, hipEvent_t* level_events) {
   using C = cplx_t<R>;
+  // level_events (tuning): events 4 l and 4 l + 1 bracket level l's forward
+  // part, 4 l + 2 and 4 l + 3 its backward part (levels one at a time).
+  if (level_events) persistent = false;
+  struct Mark {   // records its event (if any) when the level's iteration ends
+    hipEvent_t e;
+    hipStream_t s;
+    ~Mark() {
+      if (e) (void)hipEventRecord(e, s);
+    }
+  };
+  auto ev = [&](int l, int which) { return level_events ? level_events[4 * l + which] : nullptr; };
   const C* arena = static_cast<const C*>(arena_v);
   C* W = static_cast<C*>(w_v);
   C* Z = static_cast<C*>(z_v);
@@ -2712,6 +2746,8 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
+    if (level_events) SPP_HIP(hipEventRecord(ev(l, 0), st));
+    const Mark done{ev(l, 1), st};
     if (level_form[l] == kFormLU) {
       int l1 = l + 1;
       while (l1 < nlevels && level_form[l1] == kFormLU) ++l1;
@@ -2740,6 +2776,8 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
+    if (level_events) SPP_HIP(hipEventRecord(ev(l, 2), st));
+    const Mark done{ev(l, 3), st};
     if (level_form[l] == kFormLU) {
       int l0 = l;
       while (l0 > 0 && level_form[l0 - 1] == kFormLU) --l0;
@@ -2779,15 +2817,15 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
 }
 
 template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, void*, int*, int, int, int, int, int, int,
-                                      int, int, int, const int*, const int*);
+                                      int, int, int, int, const int*, const int*);
 template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, void*, int*, int, int, int, int, int, int,
-                                     int, int, int, const int*, const int*);
+                                     int, int, int, int, const int*, const int*);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
-                               int64_t, bool);
+                               int64_t, bool, hipEvent_t*);
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                               const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
-                              int64_t, bool);
+                              int64_t, bool, hipEvent_t*);
 template void mf_gemv<double>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,
                               double, void*, int64_t, int);
 template void mf_gemv<float>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,

@@ -80,7 +80,8 @@ void tune_force(const std::string& key, int value) {
 void tune_set(const std::string& key, int value) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   load_locked();
-  g_table[key] = value;
+  if (value < 0) g_table.erase(key);
+  else g_table[key] = value;
 }
 
 bool tune_has(const std::string& key) {

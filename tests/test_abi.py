@@ -112,3 +112,22 @@ def test_attach_cnn_and_batch_solve_reject_bad_arguments():
     assert lib.spp_attach_cnn(None, fake_net, ctypes.c_double(0.5)) == spp.SPP_EINVAL
     assert "null factor" in spp.spp_last_error()
     assert lib.spp_solve_batch(None, None, None, None, None, None, None) == spp.SPP_EINVAL
+
+
+def test_tuning_table_entries_round_trip(monkeypatch):
+    """spp_tune_set / spp_tune_get touch only the host table (no GPU call)."""
+    monkeypatch.delenv("SPP_TUNE_CACHE", raising=False)
+    lib = spp.library()
+    key = "mf_steps@test:8:1024:289:225"
+    assert binding.spp_tune_get(key) is None
+    binding.spp_tune_set(key, 3)
+    assert binding.spp_tune_get(key) == 3
+    binding.spp_tune_set(key, 1)
+    assert binding.spp_tune_get(key) == 1
+    binding.spp_tune_set(key, -1)
+    assert binding.spp_tune_get(key) is None
+    assert lib.spp_tune_set(None, 1) == spp.SPP_EINVAL
+    assert lib.spp_tune_set(b"", 1) == spp.SPP_EINVAL
+    v = ctypes.c_int32(0)
+    assert lib.spp_tune_get(None, ctypes.byref(v)) == spp.SPP_EINVAL
+    assert lib.spp_tune_get(key.encode(), None) == spp.SPP_EINVAL

@@ -1,4 +1,8 @@
-"""Autotuned launch parameters: same solution, a written tuning table."""
+"""Autotuned launch parameters and factorisation schedules: same solution,
+a written tuning table, and every schedule / solve form the tuner can pick
+giving the same solution as the untuned factor."""
+import itertools
+
 import numpy as np
 import pytest
 
@@ -8,24 +12,57 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
+def rel(a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
 def test_autotune_keeps_the_solution_and_writes_its_table(tmp_path, monkeypatch):
-    from paper_1409_0297_amd import Solver
+    from paper_1409_0297_amd import Solver, binding
     path = tmp_path / "tune.txt"
     monkeypatch.setenv("SPP_TUNE_CACHE", str(path))
     W = workloads.helmholtz_workload("mid", 5, 128, 2, 16.0, 16, 0.05, 8, nrhs=2)
-    A = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, tol=1e-11, max_iter=100, autotune=True)
-    B = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, tol=1e-11, max_iter=100)
-    ua, ia, ra, ca = A.solve(W.rhs)
+    kw = dict(omega=W.omega, tol=1e-11, max_iter=100)
+    B = Solver(W.kind, W.n, W.d, W.b, W.coeff, **kw)          # untuned: heuristic schedules
     ub, ib, rb, cb = B.solve(W.rhs)
-    A.close()
     B.close()
+    A = Solver(W.kind, W.n, W.d, W.b, W.coeff, autotune=True, **kw)
+    ua, ia, ra, ca = A.solve(W.rhs)
+    A.close()
     torch.cuda.synchronize()
     assert ca == cb == 0
     assert all(abs(x - y) <= 1 for x, y in zip(ia, ib))
-    d = float(torch.linalg.norm(ua - ub) / torch.linalg.norm(ub))
-    assert d <= 1e-9, d
+    assert rel(ua, ub) <= 1e-9
     text = path.read_text()
-    assert "fft_lines@" in text and "gemv_chunks@" in text
+    for kind in ("fft_lines@", "gemv_chunks@", "mf_form@", "mf_steps@"):
+        assert kind in text, kind
+    mf_keys = []
     for line in text.splitlines():
         key, value = line.split()
-        assert int(value) >= 1
+        if key.startswith("mf_form@"):
+            assert int(value) in (0, 1, 2)
+            mf_keys.append(key)
+        elif key.startswith("mf_steps@"):
+            assert 0 <= int(value) <= 3
+            mf_keys.append(key)
+        else:
+            assert int(value) >= 1
+        assert binding.spp_tune_get(key) == int(value)
+    # Every candidate the tuner times is a valid factorisation: force each
+    # schedule and solve form on every level and compare with the untuned
+    # solution (same tolerance, so equal to roundoff times the conditioning).
+    try:
+        for steps, form in itertools.product(range(4), range(3)):
+            for key in mf_keys:
+                binding.spp_tune_set(key, steps if key.startswith("mf_steps@") else form)
+            C = Solver(W.kind, W.n, W.d, W.b, W.coeff, **kw)
+            uc, ic, rc, cc = C.solve(W.rhs)
+            C.close()
+            torch.cuda.synchronize()
+            assert cc == 0, (steps, form)
+            assert all(abs(x - y) <= 1 for x, y in zip(ic, ib)), (steps, form, ic, ib)
+            e = rel(uc, ub)
+            print(f"steps {steps} form {form}: iterations {ic}, vs untuned {e:.1e}")
+            assert e <= 1e-9, (steps, form, e)
+    finally:
+        for key in mf_keys:
+            binding.spp_tune_set(key, -1)
