@@ -142,15 +142,15 @@ def gaussian_well_lattice(n: int, d: int, ell: int, seed: int, width: float = 0.
 @dataclasses.dataclass
 class Workload:
     name: str
-    kind: str               # "helmholtz" | "schrodinger"
+    kind: str               # "helmholtz" | "schrodinger" | "maxwell"
     n: int
     d: int
     b: int
     omega: float = 0.0
     ell: float = 1.0
     energy: float = 0.0
-    coeff: np.ndarray = None     # c(x_j) or V(ell x_j)
-    rhs: np.ndarray = None       # (nrhs,)+(n,)*d complex128
+    coeff: np.ndarray = None     # c(x_j), V(ell x_j) or eps(x_j)
+    rhs: np.ndarray = None       # (nrhs,)+(n,)*d complex128; Maxwell: (nrhs, d)+(n,)*d
     tol: float = 1e-10
 
 
@@ -201,6 +201,21 @@ def small(n: int, d: int, b: int, waves: float, bumps: int = 4, width: float = 0
     """Small Helmholtz case for unit tests (any n, d, b)."""
     return helmholtz_workload(f"helmholtz{d}d_n{n}_b{b}", 9, n, d, waves, bumps, width, b,
                               nrhs=nrhs, tol=tol, instance=instance)
+
+
+def maxwell_workload(n: int, d: int, b: int, waves: float, bumps: int = 4, width: float = 0.08,
+                     nrhs: int = 1, instance: int = 0, config: int = 10, tol: float = 1e-10) -> Workload:
+    """Maxwell (curl-curl) case: permittivity eps = 1 / c^2 of the Gaussian-bump
+    medium of ``gaussian_bump_medium`` (so omega^2 eps is the Helmholtz
+    omega^2 / c^2 of the same draw), omega = 2 pi waves; right-hand sides are
+    vector fields, shape (nrhs, d) + (n,)*d, every component an independent
+    Gaussian of width 1/32 (the d nrhs Gaussians of one ``gaussian_sources``
+    draw, right-hand side major)."""
+    omega = 2.0 * math.pi * waves
+    med = gaussian_bump_medium(n, d, omega, bumps, width, seed_for(config, instance))
+    rhs = gaussian_sources(n, d, nrhs * d, 1.0 / 32, seed_for(config, instance) + 500)
+    return Workload(name=f"maxwell{d}d_n{n}_b{b}", kind="maxwell", n=n, d=d, b=b, omega=omega,
+                    coeff=1.0 / med.c ** 2, rhs=rhs.reshape((nrhs, d) + (n,) * d), tol=tol)
 
 
 def schrodinger_workload(n: int, d: int, ell: int, b: int, nrhs: int = 1, instance: int = 0,
