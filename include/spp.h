@@ -13,10 +13,29 @@
  * is the sparsifying stencil operator and P = Q + C q its sparse truncation
  * (Sections 2.2-2.3), factorised by nested-dissection multifrontal LU.
  *
+ * Section 4 names the Maxwell equation for the electric field,
+ *   (curl curl - omega^2 eps(x)) E = f  (units with c = 1),
+ * as the method's next case without giving an algorithm; kind SPP_MAXWELL
+ * is this library's reading of it.  E and f have d components (2D: the
+ * in-plane field E_0, E_1 of a field independent of the third coordinate;
+ * 3D: all three; component a points along grid axis a).  curl is built from
+ * spectral first derivatives whose Nyquist wave number is dropped, so curl
+ * curl has the d x d symbol 4 pi^2 (|kt|^2 I - kt kt^T) per wave vector
+ * (kt_a = k_a, 0 at the index n/2).  With w = omega^2 eps the split of eq.
+ * (Dsq) gives s = mean(w), q = s - w, G = (curl curl - s)^{-1} with symbol
+ * (I - kt kt^T / |kt|^2) / (4 pi^2 |kt|^2 - s) - kt kt^T / (|kt|^2 s), and
+ * the same integral form (I + G q) E = G f.  The sets of Section 2.3 and the
+ * nested-dissection boxes are unchanged; a set's unknowns are all components
+ * of its points, T_S is the same least-squares fit over them, and a box
+ * eliminates its points with all their components.
+ *
  * Conventions for every entry point
  *  - Grid functions are C-order arrays over j in [0,n)^d (last axis fastest).
  *    Complex data is interleaved (re, im) double, i.e. C99 double complex.
- *    A batch of nrhs grid functions is stored [nrhs][n^d].
+ *    A batch of nrhs grid functions is stored [nrhs][n^d]; a Maxwell field
+ *    is d grid functions, component-major, so nrhs fields are stored
+ *    [nrhs][d][n^d] and every vector argument below holds d n^d entries per
+ *    right-hand side.
  *  - Pointers documented as DEVICE point to GPU memory owned by the caller
  *    (typically allocated by PyTorch); HOST pointers to CPU memory.  The
  *    library never frees caller memory.  It owns only what a spp_factor
@@ -51,7 +70,7 @@ enum {
   SPP_ENOTIMPL = -7          /* combination of options not implemented         */
 };
 
-typedef enum { SPP_HELMHOLTZ = 0, SPP_SCHRODINGER = 1 } spp_kind;
+typedef enum { SPP_HELMHOLTZ = 0, SPP_SCHRODINGER = 1, SPP_MAXWELL = 2 } spp_kind;
 
 /* Arithmetic of the frontal matrices and the triangular solves. */
 typedef enum {
@@ -70,10 +89,13 @@ typedef struct {
   int32_t n;            /* grid points per axis; even                            */
   int32_t b;            /* leaf box width in grid steps; b | n, n/b = 2^L >= 2   */
   int32_t kind;         /* spp_kind                                              */
-  double omega;         /* Helmholtz frequency omega (eq. helm)                  */
+  double omega;         /* Helmholtz / Maxwell frequency omega (eq. helm)        */
   double ell, energy;   /* Schroedinger size ell and energy E (eq. schr)         */
   const double* coeff;  /* DEVICE, n^d reals: c(x_j) for Helmholtz,
-                           V(ell x_j) for Schroedinger; read during setup only   */
+                           V(ell x_j) for Schroedinger, eps(x_j) > 0 for
+                           Maxwell; read during setup only.  Maxwell leaf
+                           boxes: d (b + 1)^d <= 1024 (2D b <= 21, 3D b <= 5),
+                           else SPP_ENOTIMPL                                    */
 } spp_problem;
 
 #define SPP_F_UNPRECONDITIONED 1  /* GMRES with M = I (for comparisons)        */
@@ -190,7 +212,8 @@ int spp_setup(const spp_problem* problem, const spp_options* options,
  * Sets up `count` independent problems (1 <= count <= 4096) in one factor,
  * e.g. several media, frequencies or grid sizes (Sections 3.1-3.2 solve one
  * such family at a time).  All problems must have the same dim; n, b, kind,
- * omega, ell, energy and coeff may differ.  Their nested-dissection fronts
+ * omega, ell, energy and coeff may differ.  Maxwell problems are set up one
+ * per factor (SPP_ENOTIMPL in a batch of more than one).  Their nested-dissection fronts
  * are factorised level by level in shared launches, and spp_solve then runs
  * one FGMRES per (problem, right-hand side) pair in lock step, each with its
  * own stopping test.  Batch vectors are the problems' vectors one after the
@@ -288,7 +311,8 @@ int spp_apply_precond(spp_factor* factor, const void* r, void* z, int32_t nrhs,
                       spp_stream_t stream);
 
 /* Shift s of the first problem (HOST double) and potential q of every problem
-   (DEVICE double[sum n_i^d] in the batch layout with nrhs = 1; may be NULL). */
+   (DEVICE double[sum n_i^d] in the batch layout with nrhs = 1; may be NULL).
+   q is per grid point for Maxwell too (every component shares it). */
 int spp_get_coefficients(const spp_factor* factor, double* s, double* q);
 
 /* Shift s used by problem `problem` of a batch and how many times the rule of
@@ -300,7 +324,10 @@ int spp_get_shift(const spp_factor* factor, int32_t problem, double* s, int32_t*
    each may be NULL: nS = |S|, nB = |beta(S)|; offsets: int32[(nS+nB)*dim],
    the grid offsets of S then beta(S) from the set's leaf box corner (the
    column order of Q(S, gamma(S)) = [I  -T_S]); T: complex128 [nS][nB];
-   C: complex128 [nS][nS+nB] = [I  -T_S] G(gamma(S), gamma(S)). */
+   C: complex128 [nS][nS+nB] = [I  -T_S] G(gamma(S), gamma(S)).  Maxwell:
+   nS and nB count unknowns (d per point, point-major: point i, component a
+   at i d + a), T and C are over those unknowns, offsets still list the
+   (nS + nB) / d points. */
 int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t* nB,
                     int32_t* offsets, void* T, void* C);
 

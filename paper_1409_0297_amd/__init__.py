@@ -6,7 +6,7 @@ the package does not touch the GPU; the library is loaded on first use and
 a missing build raises immediately -- there is no fallback path.
 """
 from .binding import (SPP_C128, SPP_C64_FRONTS, SPP_EBREAKDOWN, SPP_EHIP, SPP_EINVAL,  # noqa: F401
-                      SPP_ENOMEM, SPP_ENOTIMPL, SPP_ESINGULAR_SHIFT, SPP_HELMHOLTZ,
+                      SPP_ENOMEM, SPP_ENOTIMPL, SPP_ESINGULAR_SHIFT, SPP_HELMHOLTZ, SPP_MAXWELL,
                       SPP_NOT_CONVERGED, SPP_OK, SPP_ORDER_BISECT, SPP_ORDER_OCTREE,
                       SPP_SCHRODINGER, SPP_F_UNPRECONDITIONED, SPP_F_TIMING, SPP_F_PARTIAL_PIVOTING, SPP_F_GRAPHS, SPP_F_PERSISTENT, SPP_F_AUTOTUNE, KERNEL_CLASSES, SppError, Solver, BatchSolver, library,
                       library_path, spp_apply_green, spp_apply_operator, spp_apply_precond,

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 SPP_OK, SPP_EINVAL, SPP_ESINGULAR_SHIFT, SPP_EBREAKDOWN = 0, -1, -2, -3
 SPP_NOT_CONVERGED, SPP_ENOMEM, SPP_EHIP, SPP_ENOTIMPL = -4, -5, -6, -7
-SPP_HELMHOLTZ, SPP_SCHRODINGER = 0, 1
+SPP_HELMHOLTZ, SPP_SCHRODINGER, SPP_MAXWELL = 0, 1, 2
 SPP_C128, SPP_C64_FRONTS = 0, 1
 SPP_ORDER_OCTREE, SPP_ORDER_BISECT = 0, 1
 SPP_F_UNPRECONDITIONED = 1
@@ -291,8 +291,10 @@ def spp_last_error() -> str:
 class Solver:
     """One factorised problem: setup(grid, omega or E, c or V) -> factor; solve(f) -> u.
 
-    ``coeff``: c(x_j) (Helmholtz) or V(ell x_j) (Schroedinger) as a float64
-    tensor of shape (n,)*d on the GPU (numpy arrays are copied there).
+    ``coeff``: c(x_j) (Helmholtz), V(ell x_j) (Schroedinger) or eps(x_j)
+    (Maxwell) as a float64 tensor of shape (n,)*d on the GPU (numpy arrays are
+    copied there).  Maxwell fields have d components: vectors are
+    (nrhs, d n^d), component-major.
     """
 
     def __init__(self, kind: str, n: int, d: int, b: int, coeff, omega: float = 0.0,
@@ -305,11 +307,14 @@ class Solver:
         import torch
         self.torch = torch
         self.n, self.d, self.b = n, d, b
-        self.N = n ** d
+        self.nc = d if kind == "maxwell" else 1      # unknowns per grid point
+        self.npts = n ** d
+        self.N = self.nc * self.npts
         dev = torch.device("cuda")
         c = torch.as_tensor(coeff, dtype=torch.float64, device=dev).contiguous()
         self._coeff = c
-        pb = spp_problem(dim=d, n=n, b=b, kind=SPP_HELMHOLTZ if kind == "helmholtz" else SPP_SCHRODINGER,
+        kinds = {"helmholtz": SPP_HELMHOLTZ, "schrodinger": SPP_SCHRODINGER, "maxwell": SPP_MAXWELL}
+        pb = spp_problem(dim=d, n=n, b=b, kind=kinds[kind],
                          omega=omega, ell=ell, energy=energy, coeff=c.data_ptr())
         op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,
                          order=SPP_ORDER_OCTREE if order == "octree" else SPP_ORDER_BISECT,
@@ -369,7 +374,7 @@ class Solver:
         return z
 
     def coefficients(self):
-        q = self.torch.empty(self.N, dtype=self.torch.float64, device="cuda")
+        q = self.torch.empty(self.npts, dtype=self.torch.float64, device="cuda")
         s = spp_get_coefficients(self.handle, q.data_ptr())
         self.torch.cuda.synchronize()
         return s, q
@@ -377,7 +382,7 @@ class Solver:
     def stencil(self, set_type: int):
         import numpy as np
         nS, nB = spp_get_stencil(self.handle, set_type)
-        off = np.zeros((nS + nB, self.d), dtype=np.int32)
+        off = np.zeros(((nS + nB) // self.nc, self.d), dtype=np.int32)
         T = np.zeros((nS, nB), dtype=np.complex128)
         C = np.zeros((nS, nS + nB), dtype=np.complex128)
         spp_get_stencil(self.handle, set_type, off.ctypes.data, T.ctypes.data, C.ctypes.data)
@@ -437,8 +442,8 @@ class BatchSolver:
         for p in problems:
             c = torch.as_tensor(p["coeff"], dtype=torch.float64, device="cuda").contiguous().reshape(-1)
             self._coeffs.append(c)
-            pbs.append(spp_problem(dim=p["d"], n=p["n"], b=p["b"],
-                                   kind=SPP_HELMHOLTZ if p["kind"] == "helmholtz" else SPP_SCHRODINGER,
+            kinds = {"helmholtz": SPP_HELMHOLTZ, "schrodinger": SPP_SCHRODINGER, "maxwell": SPP_MAXWELL}
+            pbs.append(spp_problem(dim=p["d"], n=p["n"], b=p["b"], kind=kinds[p["kind"]],
                                    omega=p.get("omega", 0.0), ell=p.get("ell", 1.0), energy=p.get("energy", 0.0),
                                    coeff=c.data_ptr()))
         op = spp_options(prec=SPP_C128 if prec == "c128" else SPP_C64_FRONTS,

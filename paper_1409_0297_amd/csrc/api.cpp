@@ -79,7 +79,7 @@ double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-using Geom = std::tuple<int, int, int, int, int>;   // d, n, b, ordering, stencil pattern
+using Geom = std::tuple<int, int, int, int, int, int>;   // d, n, b, ordering, stencil pattern, unknowns per point
 
 // A nested-dissection plan (of one problem or of a batch) and its device-side
 // index arrays.  Plans depend only on the geometries, so they are built once
@@ -181,6 +181,7 @@ std::shared_ptr<Plan> host_plan_locked(const Geom& g) {
   if (it != g_host_plans.end()) return it->second;
   auto P = std::make_shared<Plan>();
   std::string err = build_plan(std::get<0>(g), std::get<1>(g), std::get<2>(g), std::get<3>(g), *P, std::get<4>(g));
+  if (err.empty()) err = expand_plan(*P, std::get<5>(g));
   if (!err.empty()) throw Error(SPP_EINVAL, err);
   g_host_plans[g] = P;
   return P;
@@ -271,7 +272,9 @@ struct SppInstance {
   int moves = 0;
   int d = 0, n = 0, b = 0, m = 0;
   int bs = 0;                        // box width of the stencil sets (b, or 1 for points)
-  int64_t N = 0, Noff = 0;
+  int nc = 1;                        // unknowns per grid point (Maxwell: d field components)
+  int64_t npts = 0;                  // grid points n^d
+  int64_t N = 0, Noff = 0;           // unknowns nc npts, and their offset in a batch vector
   std::shared_ptr<Plan> plan;        // the problem's own plan (set types)
   StencilDev sten[8]{};
   const double2* tw = nullptr;
@@ -282,6 +285,7 @@ struct SppInstance {
 struct SppGroup {
   int inst0 = 0, ninst = 0;
   int d = 0, n = 0;
+  int nc = 1;                        // grids per problem and right-hand side
   int64_t N = 0, Noff = 0;
   const double2* tw = nullptr;
 };
@@ -435,21 +439,25 @@ template <typename F> int guarded(F&& fn) {
 // min over wave numbers k in [-n/2, n/2)^d of |4 pi^2 |k|^2 - s|, relative to
 // |s|: the last coordinate is taken next to the square root of what the
 // others leave, so the scan is O(n^(d-1)).
-double shift_gap(int d, int n, double s) {
+// nyquist_zero: the wave numbers of first derivatives (the vector curl curl),
+// whose Nyquist entry -n/2 counts as 0.
+double shift_gap(int d, int n, double s, bool nyquist_zero = false) {
   const double c = 4.0 * M_PI * M_PI;
   const int h = n / 2;
+  const int top = nyquist_zero ? h - 1 : h;   // largest |k| of the last coordinate
+  auto sq = [&](int a) { return (nyquist_zero && a == -h) ? 0.0 : (double)a * a; };
   double best = INFINITY;
   auto last = [&](double partial) {   // partial = sum of the other squares
     const double rest = s / c - partial;
     const int k = rest > 0 ? (int)std::floor(std::sqrt(rest)) : 0;
-    for (int t = std::max(0, k - 1); t <= std::min(h, k + 2); ++t)
+    for (int t = std::max(0, k - 1); t <= std::min(top, k + 2); ++t)
       best = std::min(best, std::fabs(c * (partial + (double)t * t) - s));
   };
   if (d == 2) {
-    for (int a = -h; a < h; ++a) last((double)a * a);
+    for (int a = -h; a < h; ++a) last(sq(a));
   } else {
     for (int a = -h; a < h; ++a)
-      for (int b = -h; b < h; ++b) last((double)(a * a + b * b));
+      for (int b = -h; b < h; ++b) last(sq(a) + sq(b));
   }
   return best / std::fabs(s);
 }
@@ -505,19 +513,31 @@ void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
 }
 
 // w = (I + G q) z; one FFT call per group of equal grids, q and sigma per problem.
-void apply_operator(spp_factor* F, const double2* z, double2* w, int nrhs, hipStream_t st) {
+// A vector problem (Maxwell: one problem, d grids per right-hand side) runs
+// its transforms over all nrhs d grids with the d x d Green symbol in between.
+void apply_operator_to(spp_factor* F, const double2* z, double2* w, double2* tmp, int nrhs, hipStream_t st) {
   for (const SppGroup& g : F->groups) {
     const int64_t o = g.Noff * nrhs;
-    fft_multi(st, z + o, w + o, F->tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, F->q + g.Noff, F->sigma + g.Noff, z + o,
-              nrhs);
+    if (g.nc > 1)
+      fft_vector_green(st, z + o, w + o, tmp + o, g.tw, g.d, g.n, nrhs, F->inst[g.inst0].s, F->q + g.Noff, z + o);
+    else
+      fft_multi(st, z + o, w + o, tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, F->q + g.Noff, F->sigma + g.Noff, z + o,
+                nrhs);
   }
+}
+
+void apply_operator(spp_factor* F, const double2* z, double2* w, int nrhs, hipStream_t st) {
+  apply_operator_to(F, z, w, F->tmp, nrhs, st);
 }
 
 void apply_green(spp_factor* F, const double2* f, double2* gout, int nrhs, hipStream_t st) {
   for (const SppGroup& g : F->groups) {
     const int64_t o = g.Noff * nrhs;
-    fft_multi(st, f + o, gout + o, F->tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, nullptr, F->sigma + g.Noff, nullptr,
-              nrhs);
+    if (g.nc > 1)
+      fft_vector_green(st, f + o, gout + o, F->tmp + o, g.tw, g.d, g.n, nrhs, F->inst[g.inst0].s, nullptr, nullptr);
+    else
+      fft_multi(st, f + o, gout + o, F->tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, nullptr, F->sigma + g.Noff, nullptr,
+                nrhs);
   }
 }
 
@@ -576,17 +596,21 @@ constexpr double kTuneAppliesPerFactor = 20.0;
 
 void validate_problem(const spp_problem* pb) {
   if (!pb->coeff) throw Error(SPP_EINVAL, "coeff is null");
-  if (pb->kind != SPP_HELMHOLTZ && pb->kind != SPP_SCHRODINGER) throw Error(SPP_EINVAL, "unknown problem kind");
-  if (pb->kind == SPP_HELMHOLTZ && !(std::isfinite(pb->omega) && pb->omega > 0)) throw Error(SPP_EINVAL, "omega");
+  if (pb->kind != SPP_HELMHOLTZ && pb->kind != SPP_SCHRODINGER && pb->kind != SPP_MAXWELL)
+    throw Error(SPP_EINVAL, "unknown problem kind");
+  if ((pb->kind == SPP_HELMHOLTZ || pb->kind == SPP_MAXWELL) && !(std::isfinite(pb->omega) && pb->omega > 0))
+    throw Error(SPP_EINVAL, "omega");
   if (pb->kind == SPP_SCHRODINGER && !(std::isfinite(pb->ell) && pb->ell > 0 && std::isfinite(pb->energy)))
     throw Error(SPP_EINVAL, "ell / energy");
   if (!fft_supported(pb->n)) throw Error(SPP_EINVAL, "n must be of the form 2^a 3^b");
   std::string err = validate_grid(pb->dim, pb->n, pb->b);
   if (!err.empty()) throw Error(SPP_EINVAL, err);
   // Leaf sets are assembled and applied by one workgroup with their
-  // neighbourhood staged in LDS: |gamma(S)| <= 1024 (2D: b <= 30, 3D: b <= 9).
+  // neighbourhood's unknowns staged in LDS: nc |gamma(S)| <= 1024 (scalar
+  // 2D: b <= 30, 3D: b <= 9; Maxwell, nc = d: 2D b <= 21, 3D b <= 5).
+  const int nc = pb->kind == SPP_MAXWELL ? pb->dim : 1;
   const int g = (pb->dim == 2) ? (pb->b + 1) * (pb->b + 1) : (pb->b + 1) * (pb->b + 1) * (pb->b + 1);
-  if (g > 1024) throw Error(SPP_ENOTIMPL, "leaf box too large: (b + 1)^d must be <= 1024");
+  if (nc * g > 1024) throw Error(SPP_ENOTIMPL, "leaf box too large: unknowns per point times (b + 1)^d must be <= 1024");
 }
 
 // Times the candidate launch parameters of this factor's FFT passes and
@@ -612,7 +636,7 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
     flush = F->dalloc<char>(flush_bytes);
   };
   for (const SppGroup& g : F->groups) {
-    const int batch = g.ninst * nrhs;
+    const int batch = g.ninst * nrhs * g.nc;   // grids per pass
     const int64_t o = g.Noff * nrhs, n = g.n;
     std::vector<std::pair<int64_t, int64_t>> axes;
     if (g.d == 2) axes = {{n, 1}, {1, n}};
@@ -627,8 +651,8 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
         if (!fft_lines_valid(g.n, ax.first, ax.second, L)) continue;
         tune_force(key, L);
         const float t = tune_time(st, 3, [&] {
-          fft_axis(st, F->wk + o, F->tmp + o, g.tw, g.n, ax.first, ax.second, g.N, batch, -1, nullptr, nullptr,
-                   nullptr, nrhs);
+          fft_axis(st, F->wk + o, F->tmp + o, g.tw, g.n, ax.first, ax.second, g.N / g.nc, batch, -1, nullptr,
+                   nullptr, nullptr, nrhs * g.nc);
         });
         if (t < bt) { bt = t; best = L; }
       }
@@ -801,6 +825,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   for (int i = 0; i < count; ++i) {
     validate_problem(&pbs[i]);
     if (pbs[i].dim != pbs[0].dim) throw Error(SPP_EINVAL, "all problems of a batch must have the same dimension");
+    if (pbs[i].kind == SPP_MAXWELL && count > 1)
+      throw Error(SPP_ENOTIMPL, "Maxwell problems are set up one at a time (spp_setup)");
   }
   const double t0 = now_ms();
   auto F = std::make_unique<spp_factor>();
@@ -812,7 +838,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   if (op->flags & SPP_F_TIMING) F->timer = std::make_unique<KernelTimer>();
   TimerScope timer_scope(F.get());
   std::vector<Geom> geoms;
-  for (int i = 0; i < count; ++i) geoms.emplace_back(pbs[i].dim, pbs[i].n, pbs[i].b, op->order, op->pattern);
+  for (int i = 0; i < count; ++i) {
+    geoms.emplace_back(pbs[i].dim, pbs[i].n, pbs[i].b, op->order, op->pattern,
+                       pbs[i].kind == SPP_MAXWELL ? pbs[i].dim : 1);
+  }
   // Storage: every front resident unless asked for, or unless the resident
   // arena (sum of F^2 over all fronts) would not fit in 85% of what the
   // device has left.
@@ -841,7 +870,9 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     I.kind = pbs[i].kind; I.omega = pbs[i].omega; I.ell = pbs[i].ell; I.energy = pbs[i].energy;
     I.d = pbs[i].dim; I.n = pbs[i].n; I.b = pbs[i].b; I.m = I.n / I.b;
     I.bs = op->pattern == 1 ? 1 : I.b;
-    I.N = (I.d == 2) ? (int64_t)I.n * I.n : (int64_t)I.n * I.n * I.n;
+    I.nc = I.kind == SPP_MAXWELL ? I.d : 1;
+    I.npts = (I.d == 2) ? (int64_t)I.n * I.n : (int64_t)I.n * I.n * I.n;
+    I.N = I.nc * I.npts;
     I.Noff = Noff;
     I.plan = host_plan(geoms[i]);
     Noff += I.N;
@@ -852,7 +883,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     const SppInstance& I = F->inst[i];
     if (F->groups.empty() || F->groups.back().n != I.n) {
       SppGroup g;
-      g.inst0 = i; g.d = I.d; g.n = I.n; g.N = I.N; g.Noff = I.Noff;
+      g.inst0 = i; g.d = I.d; g.n = I.n; g.nc = I.nc; g.N = I.N; g.Noff = I.Noff;
       F->groups.push_back(g);
     }
     F->groups.back().ninst += 1;
@@ -861,13 +892,14 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   // alone, checked against what the device can still give before any launch.
   {
     size_t stencil_elems = 0;
-    int64_t Nmax_ = 0;
+    int64_t Nmax_ = 0;   // (Green symbols and kernels: nc^2 grids per problem)
     for (const SppInstance& I : F->inst) {
       size_t w = 0;
+      const size_t c = I.nc;
       for (const SetType& T : I.plan->types)
-        w += (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS) + 2 * (size_t)T.nS * T.nG;
+        w += c * c * ((size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS) + 2 * (size_t)T.nS * T.nG);
       stencil_elems += w;
-      Nmax_ = std::max(Nmax_, I.N);
+      Nmax_ = std::max<int64_t>(Nmax_, (int64_t)I.nc * I.nc * I.npts);
     }
     // Solve form and step schedule per level: the tuned choice where the
     // tuning table has one for the level's shape, else the heuristic.  A
@@ -943,65 +975,77 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   int* info = F->dalloc<int>(64);
   SPP_HIP(hipMemsetAsync(info, 0, 64 * sizeof(int), st));
   size_t work_elems = 0;
-  int64_t Nmax = 0;
+  int64_t Nmax = 0, Gmax = 0;   // grid points; entries of the nc^2 Green kernels
   for (const SppInstance& I : F->inst) {
-    Nmax = std::max(Nmax, I.N);
+    Nmax = std::max(Nmax, I.npts);
+    Gmax = std::max<int64_t>(Gmax, (int64_t)I.nc * I.nc * I.npts);
     size_t w = 0;
+    const size_t c = I.nc;
     for (const SetType& T : I.plan->types)
-      w += (size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS);
+      w += c * c * ((size_t)T.nG * T.nG + (size_t)T.nG * T.nB + (size_t)T.nB * (T.nB + T.nS));
     work_elems = std::max(work_elems, w);
   }
   double2* swork = F->dalloc<double2>(work_elems);
   const int nblk_max = coeff_reduce_blocks(Nmax);
   double* red = F->dalloc<double>(2 * nblk_max + 2);
   double* red_out = red + 2 * nblk_max;
-  double2* sig_c = F->dalloc<double2>(Nmax);
-  double2* sig2_c = F->dalloc<double2>(Nmax);
-  double2* g = F->dalloc<double2>(Nmax);
-  double2* g2 = F->dalloc<double2>(Nmax);
+  double2* sig_c = F->dalloc<double2>(Gmax);
+  double2* sig2_c = F->dalloc<double2>(Gmax);
+  double2* g = F->dalloc<double2>(Gmax);
+  double2* g2 = F->dalloc<double2>(Gmax);
   std::vector<InstDev> idev(count);
   for (int i = 0; i < count; ++i) {
     SppInstance& I = F->inst[i];
     const spp_problem& pb = pbs[i];
     // a1: shift and potential (eq. Dsq).
     // (per-problem block count: the same summation order as a batch of one)
-    coeff_reduce(st, pb.kind, pb.coeff, I.N, pb.omega, pb.ell, red, coeff_reduce_blocks(I.N), red_out);
+    coeff_reduce(st, pb.kind, pb.coeff, I.npts, pb.omega, pb.ell, red, coeff_reduce_blocks(I.npts), red_out);
     double hred[2];
     SPP_HIP(hipMemcpyAsync(hred, red_out, sizeof(hred), hipMemcpyDeviceToHost, st));
     SPP_HIP(hipStreamSynchronize(st));
-    if (hred[1] != 0) throw Error(SPP_EINVAL, "coeff has non-finite (or, for Helmholtz, non-positive) entries");
-    const double mean_w = hred[0] / (double)I.N;
-    double s = (pb.kind == SPP_HELMHOLTZ) ? mean_w : pb.ell * pb.ell * pb.energy - mean_w;
+    if (hred[1] != 0)
+      throw Error(SPP_EINVAL, "coeff has non-finite (or, for Helmholtz and Maxwell, non-positive) entries");
+    const double mean_w = hred[0] / (double)I.npts;
+    double s = (pb.kind == SPP_SCHRODINGER) ? pb.ell * pb.ell * pb.energy - mean_w : mean_w;
     int moves = 0;
-    while (shift_gap(I.d, I.n, s) < 1e-6) {
+    const bool vec = I.nc > 1;
+    while (shift_gap(I.d, I.n, s, vec) < 1e-6) {
       if (moves == 10) throw Error(SPP_ESINGULAR_SHIFT, "L - s stays singular after 10 perturbations");
       s += 4.0 * M_PI * M_PI * 1e-3;
       ++moves;
     }
     I.s = s;
     I.moves = moves;
-    coeff_finish(st, pb.kind, pb.coeff, I.N, I.d, I.n, pb.omega, pb.ell, pb.energy, s, F->q + I.Noff,
+    // (q for every kind; the scalar symbol arrays are overwritten below for
+    // a vector problem, whose q vector offset is 0: one problem per factor)
+    coeff_finish(st, pb.kind, pb.coeff, I.npts, I.d, I.n, pb.omega, pb.ell, pb.energy, s, F->q + I.Noff,
                  F->sigma + I.Noff, sig_c, sig2_c);
-    // a2: kernels of G and G G^H.
-    fft_inverse_all(st, sig_c, g, I.tw, I.d, I.n);
-    fft_inverse_all(st, sig2_c, g2, I.tw, I.d, I.n);
+    // a2: kernels of G and G G^H (vector problems: the nc^2 component pairs).
+    if (vec) maxwell_symbols(st, I.d, I.n, s, sig_c, sig2_c);
+    for (int ab = 0; ab < I.nc * I.nc; ++ab) {
+      fft_inverse_all(st, sig_c + ab * I.npts, g + ab * I.npts, I.tw, I.d, I.n);
+      fft_inverse_all(st, sig2_c + ab * I.npts, g2 + ab * I.npts, I.tw, I.d, I.n);
+    }
     // a3-a4: stencils per set type.
     InstDev& D = idev[i];
     // (the device side indexes stencil sets: boxes of the set width bs)
     D.d = I.d; D.n = I.n; D.b = I.bs; D.m = I.n / I.bs; D.N = I.N; D.Noff = I.Noff; D.q = F->q + I.Noff;
+    D.nc = I.nc;
+    D.npts = I.npts;
     const size_t ntypes = I.plan->types.size();
     for (size_t t = 0; t < ntypes; ++t) {
       const SetType& T = I.plan->types[t];
       StencilDev& S = I.sten[t];
-      S.nS = T.nS; S.nB = T.nB; S.nG = T.nG;
+      // (sizes in unknowns: nc per point, point-major; offsets per point)
+      S.nS = T.nS * I.nc; S.nB = T.nB * I.nc; S.nG = T.nG * I.nc;
       S.off = F->pd->type_off[i * ntypes + t];
-      S.T = F->dalloc<double2>((size_t)T.nS * T.nB);
-      S.C = F->dalloc<double2>((size_t)T.nS * T.nG);
-      S.Tt = F->dalloc<double2>((size_t)T.nS * T.nB);
-      S.Ct = F->dalloc<double2>((size_t)T.nS * T.nG);
+      S.T = F->dalloc<double2>((size_t)S.nS * S.nB);
+      S.C = F->dalloc<double2>((size_t)S.nS * S.nG);
+      S.Tt = F->dalloc<double2>((size_t)S.nS * S.nB);
+      S.Ct = F->dalloc<double2>((size_t)S.nS * S.nG);
       D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
     }
-    stencil_build(st, I.d, I.n, g, g2, I.sten, (int)ntypes, swork, info + 1);
+    stencil_build(st, I.d, I.n, g, g2, I.sten, (int)ntypes, swork, info + 1, I.nc);
   }
   F->inst_dev = F->dalloc<InstDev>(count);
   SPP_HIP(hipMemcpyAsync(F->inst_dev, idev.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, st));
@@ -1037,7 +1081,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     int64_t a = 1;
     for (int x = 0; x < I.d; ++x) a *= I.n / I.bs;
     mf.anchors_max = std::max(mf.anchors_max, a);
-    for (size_t t = 0; t < I.plan->types.size(); ++t) mf.nB_max[t] = std::max(mf.nB_max[t], I.plan->types[t].nB);
+    for (size_t t = 0; t < I.plan->types.size(); ++t)
+      mf.nB_max[t] = std::max(mf.nB_max[t], I.plan->types[t].nB * I.nc);   // (unknowns)
   }
   for (const Level& L : P.levels) {
     F->level_begin.push_back(L.begin);
@@ -1536,11 +1581,7 @@ int spp_apply_operator_noalloc(spp_factor* factor, const void* z, void* w, int32
     const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const double2* zz = static_cast<const double2*>(z);
     double2* ww = static_cast<double2*>(w);
-    for (const SppGroup& g : factor->groups) {
-      const int64_t o = g.Noff * nrhs;
-      fft_multi(st, zz + o, ww + o, tmp + o, g.tw, g.d, g.n, g.ninst * nrhs, factor->q + g.Noff,
-                factor->sigma + g.Noff, zz + o, nrhs);
-    }
+    apply_operator_to(factor, zz, ww, tmp, nrhs, st);
     g_timer = saved;
     return SPP_OK;
   });
@@ -1583,7 +1624,9 @@ int spp_get_coefficients(const spp_factor* factor, double* s, double* q) {
   return guarded([&] {
     if (!factor) throw Error(SPP_EINVAL, "null factor");
     if (s) *s = factor->inst[0].s;
-    if (q) SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * factor->Ntot, hipMemcpyDeviceToDevice));
+    int64_t pts = 0;   // q lives per grid point (every field component shares it)
+    for (const SppInstance& I : factor->inst) pts += I.npts;
+    if (q) SPP_HIP(hipMemcpy(q, factor->q, sizeof(double) * pts, hipMemcpyDeviceToDevice));
     return SPP_OK;
   });
 }
@@ -1606,11 +1649,11 @@ int spp_get_stencil(const spp_factor* factor, int32_t type, int32_t* nS, int32_t
     if (type < 0 || type >= (1 << I.d)) throw Error(SPP_EINVAL, "set type out of range");
     const SetType& ST = I.plan->types[type];
     const StencilDev& S = I.sten[type];
-    if (nS) *nS = ST.nS;
-    if (nB) *nB = ST.nB;
+    if (nS) *nS = S.nS;
+    if (nB) *nB = S.nB;
     if (offsets) std::memcpy(offsets, ST.off.data(), ST.off.size() * sizeof(int));
-    if (T) SPP_HIP(hipMemcpy(T, S.T, sizeof(double2) * ST.nS * ST.nB, hipMemcpyDeviceToHost));
-    if (C) SPP_HIP(hipMemcpy(C, S.C, sizeof(double2) * ST.nS * ST.nG, hipMemcpyDeviceToHost));
+    if (T) SPP_HIP(hipMemcpy(T, S.T, sizeof(double2) * S.nS * S.nB, hipMemcpyDeviceToHost));
+    if (C) SPP_HIP(hipMemcpy(C, S.C, sizeof(double2) * S.nS * S.nG, hipMemcpyDeviceToHost));
     return SPP_OK;
   });
 }
@@ -1625,6 +1668,7 @@ int spp_attach_cnn(spp_factor* factor, spp_cnn* net, double rho) {
     }
     if (factor->inst.size() != 1 || factor->inst[0].d != 2 || factor->inst[0].n != cnn_grid(net))
       throw Error(SPP_EINVAL, "the learned stage needs a single 2D problem on the network's grid");
+    if (factor->inst[0].nc != 1) throw Error(SPP_ENOTIMPL, "the learned stage takes scalar fields only");
     factor->cnn = net;
     factor->cnn_rho = rho;
     return SPP_OK;

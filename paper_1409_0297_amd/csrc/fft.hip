@@ -392,6 +392,62 @@ void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, co
   }
 }
 
+// Maxwell: w(k) = G(k) v(k) / N for the d components of each right-hand
+// side at every wave vector, in place (G's symbol as in maxwell_symbol_kernel:
+// first-derivative wave numbers with the Nyquist index dropped).
+__global__ void vector_symbol_kernel(double2* __restrict__ v, int d, int n, int64_t N, int nrhs, double s) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N * nrhs) return;
+  const int64_t rhs = t / N, j = t - rhs * N;
+  double kt[3] = {0, 0, 0};
+  int64_t r = j;
+  for (int a = d - 1; a >= 0; --a) {
+    const int ra = (int)(r % n);
+    r /= n;
+    kt[a] = (ra == n / 2) ? 0.0 : (double)((ra > n / 2) ? ra - n : ra);
+  }
+  double k2 = 0;
+  for (int a = 0; a < d; ++a) k2 += kt[a] * kt[a];
+  const double pi = 3.14159265358979323846;
+  const double trans = 1.0 / (4.0 * pi * pi * k2 - s) / (double)N, lon = 1.0 / (s * (double)N);
+  double2* x = v + rhs * d * N + j;
+  double2 in[3];
+  for (int a = 0; a < d; ++a) in[a] = x[a * N];
+  // G v = trans v - (trans + lon) kt (kt . v) / |kt|^2
+  double2 dot = cmake<double2>(0, 0);
+  for (int a = 0; a < d; ++a) dot = cmake<double2>(dot.x + kt[a] * in[a].x, dot.y + kt[a] * in[a].y);
+  const double f = k2 > 0 ? (trans + lon) / k2 : 0.0;
+  const double t0 = k2 > 0 ? trans : -lon;   // (kt = 0: G = -I / s)
+  for (int a = 0; a < d; ++a)
+    x[a * N] = cmake<double2>(t0 * in[a].x - f * kt[a] * dot.x, t0 * in[a].y - f * kt[a] * dot.y);
+}
+
+void fft_vector_green(hipStream_t st, const double2* in, double2* out, double2* tmp, const double2* tw, int d,
+                      int n, int nrhs, double s, const double* pre, const double2* add) {
+  const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
+  const int batch = nrhs * d;   // (pre: one array for every grid, per = batch)
+  if (d == 2) {
+    fft_axis(st, in, tmp, tw, n, n, 1, N, batch, -1, pre, nullptr, nullptr, batch);
+    fft_axis(st, tmp, tmp, tw, n, 1, n, N, batch, -1, nullptr, nullptr, nullptr, batch);
+  } else {
+    fft_axis(st, in, tmp, tw, n, (int64_t)n * n, 1, N, batch, -1, pre, nullptr, nullptr, batch);
+    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, -1, nullptr, nullptr, nullptr, batch);
+    fft_axis(st, tmp, tmp, tw, n, 1, (int64_t)n * n, N, batch, -1, nullptr, nullptr, nullptr, batch);
+  }
+  timer_begin(KC_FFT, st);
+  vector_symbol_kernel<<<(unsigned)ceil_div(N * nrhs, 256), 256, 0, st>>>(tmp, d, n, N, nrhs, s);
+  SPP_LAUNCH_CHECK();
+  timer_end(KC_FFT, st, 32.0 * N * batch, 0.0);
+  if (d == 2) {
+    fft_axis(st, tmp, tmp, tw, n, 1, n, N, batch, +1, nullptr, nullptr, nullptr, batch);
+    fft_axis(st, tmp, out, tw, n, n, 1, N, batch, +1, nullptr, nullptr, add, batch);
+  } else {
+    fft_axis(st, tmp, tmp, tw, n, 1, (int64_t)n * n, N, batch, +1, nullptr, nullptr, nullptr, batch);
+    fft_axis(st, tmp, tmp, tw, n, n, n, N, batch, +1, nullptr, nullptr, nullptr, batch);
+    fft_axis(st, tmp, out, tw, n, (int64_t)n * n, 1, N, batch, +1, nullptr, nullptr, add, batch);
+  }
+}
+
 // Unnormalised inverse transform over all axes (Green kernel construction).
 void fft_inverse_all(hipStream_t st, const double2* in, double2* out, const double2* tw, int d, int n) {
   const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;

@@ -37,6 +37,13 @@ void fft_multi(hipStream_t st, const double2* in, double2* out, double2* tmp, co
                int d, int n, int batch, const double* pre, const double* sigma, const double2* add,
                int per);
 void fft_inverse_all(hipStream_t st, const double2* in, double2* out, const double2* tw, int d, int n);
+// Vector fields (Maxwell, d components, component-major [nrhs][d][n^d]):
+// out = add + G (pre in), G = (curl curl - s)^{-1} applied per wave vector
+// as its d x d symbol (see maxwell_symbol_kernel) between a forward and an
+// inverse transform of the nrhs d grids; pre (real, n^d, shared by the
+// components) and add are optional.  tmp: nrhs d n^d entries.
+void fft_vector_green(hipStream_t st, const double2* in, double2* out, double2* tmp, const double2* tw, int d,
+                      int n, int nrhs, double s, const double* pre, const double2* add);
 
 // ------------------------------------------------------------- stencil.hip
 // Sum of w_j = omega^2 / c_j^2 (Helmholtz, kind 0) or ell^2 V_j (kind 1) over
@@ -52,8 +59,8 @@ void coeff_finish(hipStream_t st, int kind, const double* coeff, int64_t N, int 
                   double2* sig_c, double2* sig2_c);
 
 struct StencilDev {
-  int nS, nB, nG;
-  const int* off;      // nG * d offsets (device)
+  int nS, nB, nG;      // unknowns (nc per point, point-major)
+  const int* off;      // nG / nc points x d offsets (device)
   double2* T;          // nS x nB, row-major
   double2* C;          // nS x nG, row-major
   double2* Tt;         // nB x nS (T transposed), row-major
@@ -62,8 +69,13 @@ struct StencilDev {
 // Builds T_S and C_S for every set type from the kernels g (of G) and g2 (of
 // G G^H); the least-squares solves of all types run in one launch.  info[t]
 // is set for a singular Gram matrix of type t.
+// nc unknowns per point (vector fields): g and g2 hold nc^2 kernels (pair
+// (a, b) at (a nc + b) n^d), the types' sizes count unknowns (point-major).
 void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2,
-                   StencilDev* types, int ntypes, double2* work, int* info);
+                   StencilDev* types, int ntypes, double2* work, int* info, int nc = 1);
+// Maxwell: the d^2 symbols of G = (curl curl - s)^{-1} and of G G^H, each / N
+// (see maxwell_symbol_kernel), for fft_inverse_all per component pair.
+void maxwell_symbols(hipStream_t st, int d, int n, double s, double2* sig, double2* sig2);
 // Work entries one set type needs (stencil_build needs their sum over the types).
 size_t stencil_work_elems(const StencilDev& S);
 
@@ -104,10 +116,13 @@ struct TypeDev {       // per set type, for assembly / Q apply
 // starts at Noff * nrhs.
 struct InstDev {
   int d, n, b, m;
-  int64_t N;           // grid points
+  int64_t N;           // unknowns per right-hand side (nc npts)
   int64_t Noff;        // sum of N over the earlier instances
-  const double* q;
+  const double* q;     // per grid point
   TypeDev types[8];
+  int nc;              // unknowns per point (Maxwell: d components, stored
+                       // component-major: unknown (c, j) at c npts + j)
+  int64_t npts;        // grid points n^d
 };
 
 struct MfDev {

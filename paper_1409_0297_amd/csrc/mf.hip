@@ -68,13 +68,13 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
   const TypeDev& T = I.types[B.type];
   C* A = arena + f.off;
   // Column data of this block once per workgroup: front position and q at
-  // every point of gamma(S).
+  // every unknown of gamma(S) (q of its point: nc unknowns per point).
   __shared__ int cpos[1024];
   __shared__ double qg[1024];
   __shared__ int rpos[1024];
   for (int j = threadIdx.x; j < T.nG; j += blockDim.x) {
     cpos[j] = mf.pos[B.colpos + j];
-    qg[j] = I.q[anchor_point(I, B.anchor, T.off + j * I.d)];
+    qg[j] = I.q[anchor_point(I, B.anchor, T.off + (j / I.nc) * I.d)];
   }
   for (int i = threadIdx.x; i < T.nS; i += blockDim.x) rpos[i] = mf.pos[B.rowpos + i];
   __syncthreads();
@@ -1535,12 +1535,17 @@ __global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, O* __res
   const int64_t base = I.Noff * nrhs + (int64_t)rhs * I.N;
   const double2* rr = r + base;
   O* yy = y + base;
+  // Unknown u of a set list (point-major, nc per point) is component u % nc
+  // of point u / nc: vector entry (u % nc) npts + point.
+  const int nc = I.nc;
+  auto at = [&](int u) {
+    return (int64_t)(u % nc) * I.npts + anchor_point(I, anchor, T.off + (u / nc) * I.d);
+  };
   extern __shared__ double2 rb[];
-  for (int j = threadIdx.x; j < T.nB; j += blockDim.x)
-    rb[j] = rr[anchor_point(I, anchor, T.off + (T.nS + j) * I.d)];
+  for (int j = threadIdx.x; j < T.nB; j += blockDim.x) rb[j] = rr[at(T.nS + j)];
   __syncthreads();
   for (int i = threadIdx.x; i < T.nS; i += blockDim.x) {
-    const int g = anchor_point(I, anchor, T.off + i * I.d);
+    const int64_t g = at(i);
     double2 s = rr[g];
     for (int j = 0; j < T.nB; ++j) cfms(s, T.Tt[(int64_t)j * T.nS + i], rb[j]);
     yy[g].x = s.x;

@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <cstdlib>
 #include <sstream>
@@ -301,6 +302,58 @@ std::string build_plan(int d, int n, int b, int order, Plan& P, int pattern) {
     for (int k = 0; k < par.F; ++k) posmap[P.idx[par.idx + k]] = -1;
   }
 
+  layout_plan(P, 0);
+  return std::string();
+}
+
+std::string expand_plan(Plan& P, int nc) {
+  if (nc < 1 || nc > 3) return "unknowns per point must be 1, 2 or 3";
+  if (P.nc != 1) return "plan already expanded";
+  if (nc == 1) return std::string();
+  const int64_t N = P.N;
+  if ((int64_t)nc * N > INT32_MAX) return "grid too large for vector unknowns";
+  auto widen = [&](const std::vector<int>& src, int64_t b, int64_t cnt, std::vector<int>& dst, bool global) {
+    for (int64_t k = 0; k < cnt; ++k) {
+      const int v = src[b + k];
+      for (int c = 0; c < nc; ++c)
+        dst.push_back(v < 0 ? -1 : global ? static_cast<int>(c * N + v) : v * nc + c);
+    }
+  };
+  std::vector<int> idx, map, pos;
+  idx.reserve(P.idx.size() * nc);
+  map.reserve(P.map.size() * nc);
+  pos.reserve(P.pos.size() * nc);
+  for (Front& f : P.fronts) {
+    const int i0 = static_cast<int>(idx.size()), m0 = static_cast<int>(map.size());
+    widen(P.idx, f.idx, f.F, idx, true);
+    if (f.parent >= 0) widen(P.map, f.map, f.F - f.p, map, false);
+    f.idx = i0;
+    f.map = m0;
+    f.F *= nc;
+    f.p *= nc;
+  }
+  for (AsmBlock& B : P.blocks) {
+    const SetType& T = P.types[B.type];
+    if (B.rowpos >= 0) {
+      const int r0 = static_cast<int>(pos.size());
+      widen(P.pos, B.rowpos, T.nS, pos, false);
+      B.rowpos = r0;
+    }
+    if (B.colpos >= 0) {
+      const int c0 = static_cast<int>(pos.size());
+      widen(P.pos, B.colpos, T.nG, pos, false);
+      B.colpos = c0;
+    }
+  }
+  for (Level& L : P.levels) {
+    L.maxF *= nc;
+    L.maxP *= nc;
+    L.maxK *= nc;
+  }
+  P.idx.swap(idx);
+  P.map.swap(map);
+  P.pos.swap(pos);
+  P.nc = nc;
   layout_plan(P, 0);
   return std::string();
 }

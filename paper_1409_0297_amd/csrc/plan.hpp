@@ -63,7 +63,8 @@ struct Level {
 struct Plan {
   int d = 0, n = 0, b = 0, m = 0;
   int pattern = 0, bs = 0;      // stencil sets and their box width (see build_plan)
-  int64_t N = 0;
+  int nc = 1;                   // unknowns per grid point (see expand_plan)
+  int64_t N = 0;                // grid points
   int order = 0;
   std::vector<SetType> types;
   std::vector<Front> fronts;
@@ -141,6 +142,17 @@ std::string validate_grid(int d, int n, int b);
 // neighbourhood mu(j) = gamma({j}) (set boxes of width 1).  The fronts use
 // leaf boxes of width b either way.
 std::string build_plan(int d, int n, int b, int order, Plan& plan, int pattern = 0);
+
+// Vector fields (nc unknowns per grid point, e.g. the d components of the
+// Maxwell field): every front row of a point becomes nc rows, point-major
+// (row k nc + c for the point's row k and component c), and every list that
+// names points names their nc unknowns in the same order: the fronts' global
+// indices (unknown (c, j) of a component-major vector of nc N entries is
+// c N + j), the boundary maps and the assembly positions (set lists are
+// point-major too, matching stencils computed over the sets' unknowns in
+// that order).  Set types keep their point counts and offsets.  F, p and the
+// level sizes grow by nc; offsets and counts are laid out again (resident).
+std::string expand_plan(Plan& plan, int nc);
 
 // Concatenates the plans of a batch of problems level by level, aligned at
 // the leaves, so that one launch per level covers the fronts of every

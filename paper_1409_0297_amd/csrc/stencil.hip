@@ -7,7 +7,9 @@
 // sum over the whole grid minus a sum over gamma:
 //   G(X, gamma^c) G(Y, gamma^c)^H = (G G^H)(X, Y) - G(X, gamma) G(Y, gamma)^H.
 // G is the circulant with symbol sigma_k, so G G^H is the circulant with
-// symbol |sigma_k|^2, and for real sigma G(Y, gamma)^H = G(gamma, Y).  Hence
+// symbol |sigma_k|^2, and for real sigma G(Y, gamma)^H = G(gamma, Y).  (A
+// vector field's G has a real symmetric d x d symbol per wave vector: the
+// same holds over its unknowns, with G G^H of symbol G(k)^2.)  Hence
 //   T_S [ (G G^H)(beta, beta) - G(beta, gamma) G(gamma, beta) ]
 //       = (G G^H)(S, beta) - G(S, gamma) G(gamma, beta),
 // an |beta| x |beta| system, and C_S = [I  -T_S] G(gamma, gamma).
@@ -34,8 +36,10 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
+// w of eq. (Dsq): Helmholtz (0) omega^2 / c^2, Schroedinger (1) ell^2 V,
+// Maxwell (2) omega^2 eps.
 __device__ inline double coeff_w(int kind, double c, double omega, double ell) {
-  return kind == 0 ? omega * omega / (c * c) : ell * ell * c;
+  return kind == 0 ? omega * omega / (c * c) : kind == 2 ? omega * omega * c : ell * ell * c;
 }
 
 __global__ void coeff_partial_kernel(int kind, const double* __restrict__ coeff, int64_t N,
@@ -46,7 +50,7 @@ __global__ void coeff_partial_kernel(int kind, const double* __restrict__ coeff,
        i += (int64_t)gridDim.x * blockDim.x) {
     const double c = coeff[i];
     const double w = coeff_w(kind, c, omega, ell);
-    if (!isfinite(c) || !isfinite(w) || (kind == 0 && !(c > 0))) bad += 1;
+    if (!isfinite(c) || !isfinite(w) || (kind != 1 && !(c > 0))) bad += 1;
     else sum += w;
   }
   const double s = block_sum(sum, sh);
@@ -70,8 +74,8 @@ __global__ void coeff_finish_kernel(int kind, const double* __restrict__ coeff, 
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= N) return;
   const double w = coeff_w(kind, coeff[j], omega, ell);
-  // Helmholtz: q = s - omega^2/c^2.  Schroedinger: q = ell^2 V - ell^2 E + s.
-  q[j] = (kind == 0) ? s - w : w - ell * ell * energy + s;
+  // Helmholtz and Maxwell: q = s - w.  Schroedinger: q = ell^2 V - ell^2 E + s.
+  q[j] = (kind == 1) ? w - ell * ell * energy + s : s - w;
   int64_t r = j;
   double k2 = 0;
   for (int i = 0; i < d; ++i) {
@@ -87,17 +91,59 @@ __global__ void coeff_finish_kernel(int kind, const double* __restrict__ coeff, 
   sig2_c[j] = cmake<double2>(sg * sg * (double)N, 0.0);         // |sigma_k|^2 / N
 }
 
-// G-type block gather: out[i][j] = g[(off_rows[i] - off_cols[j]) mod n], row-major.
-__global__ void gather_block_kernel(const double2* __restrict__ g, int d, int n, const int* __restrict__ off,
-                                    int row0, int nrows, int col0, int ncols, double2* __restrict__ out) {
+// Maxwell (Section 4 extension): the d x d symbol of G = (curl curl - s)^{-1}
+// and of G G^H = G^2 per wave vector, / N, as nc^2 grids (component pair
+// (a, b) at (a nc + b) N).  curl is built from first derivatives, whose wave
+// numbers drop the Nyquist index: kt_a = k_a, 0 at r_a = n/2.  Then
+// G(k) = (I - kt kt^T / |kt|^2) / (4 pi^2 |kt|^2 - s) - kt kt^T / (|kt|^2 s),
+// and -I / s where kt = 0.
+__global__ void maxwell_symbol_kernel(int d, int n, int64_t N, double s, double2* __restrict__ sig,
+                                      double2* __restrict__ sig2) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double kt[3] = {0, 0, 0};
+  int64_t r = j;
+  for (int a = d - 1; a >= 0; --a) {   // C order: the last axis is fastest
+    const int ra = (int)(r % n);
+    r /= n;
+    kt[a] = (ra == n / 2) ? 0.0 : (double)((ra > n / 2) ? ra - n : ra);
+  }
+  double k2 = 0;
+  for (int a = 0; a < d; ++a) k2 += kt[a] * kt[a];
+  const double pi = 3.14159265358979323846;
+  const double trans = 1.0 / (4.0 * pi * pi * k2 - s);
+  double G[3][3];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      const double proj = k2 > 0 ? kt[a] * kt[b] / k2 : 0.0;
+      G[a][b] = ((a == b ? 1.0 : 0.0) - proj) * trans - proj / s;
+    }
+  const double inv_n = 1.0 / (double)N;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double g2 = 0;
+      for (int c = 0; c < d; ++c) g2 += G[a][c] * G[c][b];
+      sig[(int64_t)(a * d + b) * N + j] = cmake<double2>(G[a][b] * inv_n, 0.0);
+      sig2[(int64_t)(a * d + b) * N + j] = cmake<double2>(g2 * inv_n, 0.0);
+    }
+}
+
+// G-type block gather over the unknowns of a set's point list, point-major
+// (unknown u = point u / nc, component u % nc; nc = 1: the points):
+// out[i][j] = g_(ca, cb)[(off_rows[i] - off_cols[j]) mod n], row-major, the
+// nc^2 kernels N = n^d entries apart.
+__global__ void gather_block_kernel(const double2* __restrict__ g, int d, int n, int64_t N, int nc,
+                                    const int* __restrict__ off, int row0, int nrows, int col0, int ncols,
+                                    double2* __restrict__ out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows * ncols) return;
   const int i = t / ncols, j = t - i * ncols;
-  const int* a = off + (row0 + i) * d;
-  const int* b = off + (col0 + j) * d;
+  const int ur = row0 + i, uc = col0 + j;
+  const int* a = off + (ur / nc) * d;
+  const int* b = off + (uc / nc) * d;
   int64_t gi = 0;
   for (int x = 0; x < d; ++x) gi = gi * n + (((a[x] - b[x]) % n) + n) % n;
-  out[t] = g[gi];
+  out[t] = g[(int64_t)((ur % nc) * nc + uc % nc) * N + gi];
 }
 
 // C = beta C + alpha A B, all row-major, plain (setup-size) complex GEMM.
@@ -372,11 +418,18 @@ size_t stencil_work_elems(const StencilDev& S) {
   return (size_t)S.nG * S.nG + (size_t)S.nG * S.nB + (size_t)S.nB * (S.nB + S.nS);
 }
 
+void maxwell_symbols(hipStream_t st, int d, int n, double s, double2* sig, double2* sig2) {
+  const int64_t N = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
+  maxwell_symbol_kernel<<<ceil_div(N, 256), 256, 0, st>>>(d, n, N, s, sig, sig2);
+  SPP_LAUNCH_CHECK();
+}
+
 void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2* g2, StencilDev* types, int ntypes,
-                   double2* work, int* info) {
+                   double2* work, int* info, int nc) {
+  const int64_t Npts = (d == 2) ? (int64_t)n * n : (int64_t)n * n * n;
   if (ntypes > 8) throw Error(-7, "at most 8 set types");
   for (int t = 0; t < ntypes; ++t)
-    if (types[t].nB > 4096) throw Error(-7, "stencil boundary set larger than 4096 points");
+    if (types[t].nB > 4096) throw Error(-7, "stencil boundary set larger than 4096 unknowns");
   const int T = 256;
   SolveJobs jobs{};
   std::vector<double2*> ggg(ntypes), mm(ntypes);
@@ -394,9 +447,9 @@ void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2
     w += stencil_work_elems(S);
     ggg[t] = Ggg;
     mm[t] = M;
-    gather_block_kernel<<<ceil_div((int64_t)nG * nG, T), T, 0, st>>>(g, d, n, S.off, 0, nG, 0, nG, Ggg);
+    gather_block_kernel<<<ceil_div((int64_t)nG * nG, T), T, 0, st>>>(g, d, n, Npts, nc, S.off, 0, nG, 0, nG, Ggg);
     SPP_LAUNCH_CHECK();
-    gather_block_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(g2, d, n, S.off, 0, nG, nS, nB, M);
+    gather_block_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(g2, d, n, Npts, nc, S.off, 0, nG, nS, nB, M);
     SPP_LAUNCH_CHECK();
     small_gemm_kernel<<<ceil_div((int64_t)nG * nB, T), T, 0, st>>>(
         nG, nB, nG, cmake<double2>(-1.0, 0.0), Ggg, nG, Ggg + nS, nG, 1.0, M, nB);

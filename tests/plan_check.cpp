@@ -9,9 +9,10 @@
 // overlap.  Small plans also check that every entry of P is assembled
 // exactly once.
 //
-// usage: plan_check [-s] [-p] [-v] d,n,b,order [d,n,b,order ...]   (several:
-//        one batch; -s: streamed storage, see layout_plan; -p: point stencil
-//        pattern, see build_plan; -v: print the levels)
+// usage: plan_check [-s] [-p] [-v] [-c NC] d,n,b,order [d,n,b,order ...]
+//        (several: one batch; -s: streamed storage, see layout_plan; -p: point
+//        stencil pattern, see build_plan; -v: print the levels; -c: NC
+//        unknowns per grid point, see expand_plan)
 // Prints "ok ..." and exits 0, or prints the first violation and exits 1.
 #include <algorithm>
 #include <cstdio>
@@ -55,13 +56,14 @@ bool disjoint(std::vector<std::pair<int64_t, int64_t>> r, int64_t limit, std::st
 }  // namespace
 
 int main(int argc, char** argv) {
-  int first = 1, storage = 0, pattern = 0;
+  int first = 1, storage = 0, pattern = 0, nc = 1;
   bool verbose = false;
   while (first < argc && argv[first][0] == '-') {
     const std::string o = argv[first++];
     if (o == "-s") storage = 1;
     else if (o == "-p") pattern = 1;
     else if (o == "-v") verbose = true;
+    else if (o == "-c" && first < argc) nc = std::atoi(argv[first++]);
     else return fail("unknown option " + o);
   }
   if (argc <= first) return fail("no geometry given");
@@ -72,7 +74,9 @@ int main(int argc, char** argv) {
     if (std::sscanf(argv[a], "%d,%d,%d,%d", &d, &n, &b, &order) != 4) return fail("bad geometry " + std::string(argv[a]));
     std::string err = build_plan(d, n, b, order, plans[a - first], pattern);
     if (!err.empty()) return fail("build_plan: " + err);
-    Ns.push_back(plans[a - first].N);
+    err = expand_plan(plans[a - first], nc);
+    if (!err.empty()) return fail("expand_plan: " + err);
+    Ns.push_back(plans[a - first].N * nc);   // unknowns
   }
   Plan P;
   std::vector<int> inst;
@@ -240,26 +244,27 @@ int main(int argc, char** argv) {
     const Plan& own = plans[T.fronts[B.front].inst];
     if (B.type < 0 || B.type >= static_cast<int>(own.types.size())) return fail("block set type");
     const SetType& ST = own.types[B.type];
+    const int nS = ST.nS * own.nc, nG = ST.nG * own.nc;   // unknowns of the set lists
     int64_t anchors = 1;
     for (int i = 0; i < own.d; ++i) anchors *= own.n / own.bs;
     if (B.anchor < 0 || B.anchor >= anchors) return fail("block anchor");
-    if (B.rowpos < 0 || B.rowpos + ST.nS > static_cast<int64_t>(P.pos.size())) return fail("block row positions");
-    if (B.colpos < 0 || B.colpos + ST.nG > static_cast<int64_t>(P.pos.size())) return fail("block column positions");
+    if (B.rowpos < 0 || B.rowpos + nS > static_cast<int64_t>(P.pos.size())) return fail("block row positions");
+    if (B.colpos < 0 || B.colpos + nG > static_cast<int64_t>(P.pos.size())) return fail("block column positions");
     bool full = true;
-    for (int i = 0; i < ST.nS; ++i) {
+    for (int i = 0; i < nS; ++i) {
       const int r = P.pos[B.rowpos + i];
       if (r < 0 || r >= f.F) return fail("block row position outside the front");
       if (i == 0) full = r < f.p;
       if ((r < f.p) != full) return fail("block mixes pivot and boundary rows");
     }
-    for (int j = 0; j < ST.nG; ++j) {
+    for (int j = 0; j < nG; ++j) {
       const int c = P.pos[B.colpos + j];
       if (c < -1 || c >= f.F) return fail("block column position outside the front");
       if (!full && c >= f.p) return fail("boundary rows assembled outside the pivot columns");
     }
     if (small) {
-      for (int i = 0; i < ST.nS; ++i)
-        for (int j = 0; j < ST.nG; ++j) {
+      for (int i = 0; i < nS; ++i)
+        for (int j = 0; j < nG; ++j) {
           const int c = P.pos[B.colpos + j];
           if (c < 0) continue;
           const int64_t gr = P.idx[f.idx + P.pos[B.rowpos + i]], gc = P.idx[f.idx + c];

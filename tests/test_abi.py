@@ -131,3 +131,21 @@ def test_tuning_table_entries_round_trip(monkeypatch):
     v = ctypes.c_int32(0)
     assert lib.spp_tune_get(None, ctypes.byref(v)) == spp.SPP_EINVAL
     assert lib.spp_tune_get(key.encode(), None) == spp.SPP_EINVAL
+
+
+def test_maxwell_setup_rejects_bad_problems_on_host():
+    """Maxwell problems: omega > 0, leaf unknowns d (b + 1)^d <= 1024, and one
+    problem per factor: refused before any GPU work."""
+    lib = spp.library()
+    eps = ctypes.c_double(1.0)   # (never read: the checks come first)
+    op = binding.spp_options(prec=spp.SPP_C128, order=0, tol=1e-8, max_iter=10)
+    out = ctypes.c_void_p()
+    bad_omega = binding.spp_problem(dim=2, n=16, b=4, kind=spp.SPP_MAXWELL, omega=0.0,
+                                    coeff=ctypes.addressof(eps))
+    assert lib.spp_setup(ctypes.byref(bad_omega), ctypes.byref(op), None, ctypes.byref(out)) == spp.SPP_EINVAL
+    big_leaf = binding.spp_problem(dim=3, n=48, b=6, kind=spp.SPP_MAXWELL, omega=1.0,
+                                   coeff=ctypes.addressof(eps))   # 3 * 7^3 = 1029 unknowns
+    assert lib.spp_setup(ctypes.byref(big_leaf), ctypes.byref(op), None, ctypes.byref(out)) == spp.SPP_ENOTIMPL
+    ok = binding.spp_problem(dim=2, n=16, b=4, kind=spp.SPP_MAXWELL, omega=1.0, coeff=ctypes.addressof(eps))
+    arr = (binding.spp_problem * 2)(ok, ok)
+    assert lib.spp_setup_batch(arr, 2, ctypes.byref(op), None, ctypes.byref(out)) == spp.SPP_ENOTIMPL

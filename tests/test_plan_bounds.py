@@ -30,8 +30,9 @@ def checker(tmp_path_factory):
     return exe
 
 
-def run(exe, *geoms, streamed=False, points=False):
+def run(exe, *geoms, streamed=False, points=False, nc=1):
     r = subprocess.run([exe] + (["-s"] if streamed else []) + (["-p"] if points else [])
+                       + (["-c", str(nc)] if nc > 1 else [])
                        + [",".join(map(str, g)) for g in geoms], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
     return r.stdout
@@ -96,3 +97,12 @@ def test_point_pattern_plans(checker, geom):
 def test_bad_geometry_is_reported(checker):
     r = subprocess.run([checker, "2,30,8,0"], capture_output=True, text=True)
     assert r.returncode == 1 and "FAIL" in r.stdout
+
+
+@pytest.mark.parametrize("geom", [(2, 16, 4, OCT), (2, 64, 16, OCT), (2, 64, 8, OCT), (2, 128, 16, OCT),
+                                  (3, 8, 4, OCT), (3, 12, 3, BIS), (3, 20, 5, OCT)])
+def test_vector_field_plans(checker, geom):
+    """Maxwell plans: d unknowns per point (expand_plan)."""
+    out = run(checker, geom, nc=geom[0])
+    if geom[0] == 2 and geom[1] <= 64:
+        assert "P entries checked" in out
