@@ -50,8 +50,9 @@ def parse():
     ap.add_argument("--cpu-baseline", choices=["full", "sample", "off"], default="full",
                     help="full: the oracle timed on the benchmark workload itself (setup + solve); "
                          "sample: the scaled 256^2 estimate only")
-    ap.add_argument("--records", choices=["all", "none"], default="all",
-                    help="keyed records beside the headline (Gaussian source, batched Schroedinger)")
+    ap.add_argument("--records", choices=["all", "none", "maxwell"], default="all",
+                    help="keyed records beside the headline (Gaussian source, batched Schroedinger, Maxwell "
+                         "512^2, 3D 128^3); maxwell: that record only")
     ap.add_argument("--profile-only", action="store_true",
                     help="run the timed steps only (for rocprofv3): no timing pass, no other precision, no baseline")
     ap.add_argument("--workload", choices=["large2d", "schrodinger-batch", "helmholtz3d"], default="large2d",
@@ -289,6 +290,54 @@ def record_3d(args):
             "max_front": st["max_front"]}
 
 
+def record_maxwell(args, steps=3, warmup=1):
+    """The Maxwell (curl-curl) extension on the headline's grid: the 2D
+    in-plane field on 512^2, omega = 2 pi 32 (16 points per wavelength: at
+    the headline's 8 the iterations of this extension outgrow 400),
+    permittivity 1 / c^2 of the headline's 64-bump medium family, b = 16,
+    one vector source (two independent Gaussians of width 1/32), complex128
+    fronts (complex64 fronts lose the solve at this size), FP64 FGMRES to
+    the bench tolerance; one step = setup + solve."""
+    import torch
+
+    import workloads
+    import paper_1409_0297_amd as spp
+
+    W = workloads.maxwell_workload(512, 2, 16, 32.0, bumps=64, width=0.05, nrhs=1, config=2)
+    dev = torch.device("cuda:0")
+    coeff = torch.as_tensor(W.coeff, dtype=torch.float64, device=dev).contiguous()
+    f = torch.as_tensor(W.rhs.reshape(1, -1), dtype=torch.complex128, device=dev).contiguous()
+    u = torch.empty_like(f)
+    stream = torch.cuda.current_stream().cuda_stream
+    pb = spp.binding.spp_problem(dim=2, n=W.n, b=W.b, kind=spp.SPP_MAXWELL, omega=W.omega, ell=1.0, energy=0.0,
+                                 coeff=coeff.data_ptr())
+    op = spp.binding.spp_options(prec=spp.SPP_C128, order=spp.SPP_ORDER_OCTREE, tol=args.tol, max_iter=400,
+                                 flags=spp.SPP_F_AUTOTUNE if args.autotune else 0)
+    times, last = [], None
+    for k in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = spp.spp_setup(pb, op, stream)
+        code, iters, relres = spp.spp_solve(h, f.data_ptr(), 1, u.data_ptr(), stream)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            times.append(time.perf_counter() - t0)
+        if last is not None:
+            spp.spp_destroy(last)
+        last = h
+    st = spp.spp_stats(last)
+    spp.spp_destroy(last)
+    dt = sum(times) / len(times)
+    del u, f, coeff
+    torch.cuda.empty_cache()
+    return {"workload": "maxwell2d_n512_w32", "grid": [512, 512], "components": 2, "omega_over_2pi": 32,
+            "b": 16, "bumps": 64, "nrhs": 1, "fronts": "c128", "tol": args.tol, "steps": steps, "warmup": warmup,
+            "value": 1.0 / dt, "unit": "solves/s", "ms_per_step": dt * 1e3, "code": code, "gmres_iters": iters,
+            "relres": relres, "t_setup_ms": st["t_setup_ms"], "t_factor_ms": st["t_factor_ms"],
+            "t_solve_ms": st["t_solve_ms"], "factor_gb": st["factor_bytes"] / 1e9,
+            "factor_gflop": st["factor_flops"] / 1e9, "max_front": st["max_front"]}
+
+
 def batch_main(args):
     rec = batch_record(args, args.steps, args.warmup, [args.prec, "c128" if args.prec == "c64" else "c64"])
     out = {
@@ -402,9 +451,13 @@ def main():
                 "steps": args.steps, "warmup": 1}
             print("bench: timing the batched Schroedinger family", file=sys.stderr, flush=True)
             records["schrodinger_batch"] = batch_record(args, 3, 1, [args.prec])
+            print("bench: timing the 512^2 Maxwell (curl-curl) solve", file=sys.stderr, flush=True)
+            records["maxwell2d_512"] = record_maxwell(args)
             print("bench: timing one step of the 3D 128^3 configuration (about a minute)", file=sys.stderr,
                   flush=True)
             records["helmholtz3d_128"] = record_3d(args)
+        elif args.records == "maxwell":
+            records["maxwell2d_512"] = record_maxwell(args)
     out = {
         "metric": "solves/sec to rel. err 1e-8 (mixed vs FP64), GMRES iters, HBM/MFMA % peak",
         "value": 1.0 / dt,
