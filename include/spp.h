@@ -266,7 +266,9 @@ int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream);
                   0 LU in place, 1 inverses of L11 / U11, 2 side products;
      mf_steps     step schedule of that level: bit 0 paired steps (one
                   rank-64 update per two 32-column steps), bit 1 L21 / U12 on
-                  64 x 64 tiles (else 128 x 32 / 32 x 128).
+                  64 x 64 tiles (else 128 x 32 / 32 x 128), bit 2 (single
+                  steps) one launch per step, the trailing tiles forming their
+                  own L21 / U12 pieces.
    Setups (with SPP_F_AUTOTUNE and resident storage) fill the mf_ entries by
    timing every candidate on the factorisation itself; a level's solve form
    counts its substitution as 20 preconditioner applies per factorisation.

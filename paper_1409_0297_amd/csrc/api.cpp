@@ -714,8 +714,9 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
 //     where it is valid, scored as the level's factorisation time plus
 //     kTuneAppliesPerFactor times its substitution time (one right-hand
 //     side, forward and backward, the best of three);
-//  2. with those forms, each step schedule (single or paired steps, 64 x 64
-//     or 128 x 32 / 32 x 128 L21 / U12 tiles), scored by factorisation time.
+//  2. with those forms, each step schedule (single, fused single or paired
+//     steps; 64 x 64 or 128 x 32 / 32 x 128 L21 / U12 tiles), scored by
+//     factorisation time.
 // The choices go to the tuning table (keys mf_form / mf_steps with the
 // level's shape) and into F's level_form / level_var.  factor_all(forms,
 // vars, events) assembles and factors every level.
@@ -793,7 +794,7 @@ void tune_factorisation(spp_factor* F, FactorAll&& factor_all, hipStream_t st) {
   }
   std::vector<double> bt(nl, 1e30);
   std::vector<int> best_var = vars;
-  for (int v : {kVarTile64, 0, kVarPair, kVarPair | kVarTile64}) {
+  for (int v : {kVarTile64, 0, kVarPair, kVarPair | kVarTile64, kVarFused | kVarTile64, kVarFused}) {
     const std::vector<int> vc(nl, v);
     const std::vector<double> tf = factor_times(best_form, vc);
     for (int l = 0; l < nl; ++l)
@@ -917,7 +918,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
         if (tf >= 0 && form_valid(tf, L, F->csize, op->flags)) form = tf;
         else untuned = true;
         const int tv = tune_get(var_tune_key(F->csize, L), -1);
-        if (tv >= 0 && tv <= (kVarPair | kVarTile64)) var = tv;
+        if (tv >= 0 && tv <= kVarAll) var = tv;
         else untuned = true;
       }
       if (form == kFormSide && (op->flags & SPP_F_NO_SIDE)) form = kFormInverse;

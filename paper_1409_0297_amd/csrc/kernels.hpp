@@ -170,11 +170,15 @@ inline int64_t mf_tournament_ints(int nfronts, int maxP) { return 2LL * nfronts 
 //              then one rank-64 product); without it, one step per trailing
 //              update with the next diagonal block factored inside it;
 //  kVarTile64: L21 / U12 of each step on 64 x 64 tiles (twice the workgroups,
-//              shorter launches) instead of 128 x 32 / 32 x 128 tiles.
+//              shorter launches) instead of 128 x 32 / 32 x 128 tiles;
+//  kVarFused:  (single steps) one launch per step: the trailing tiles form
+//              their own L21 rows and U12 columns, the next diagonal block
+//              is factored and the previous step's L21 / U12 written in the
+//              same launch (gemm_fused_kernel).
 // mf_default_variant is the untuned choice: pairs on levels of more than 64
 // fronts (they fill the device, their trailing updates stream the fronts),
 // single steps with 64 x 64 L21 / U12 tiles on the others.
-constexpr int kVarPair = 1, kVarTile64 = 2;
+constexpr int kVarPair = 1, kVarTile64 = 2, kVarFused = 4, kVarAll = 7;
 inline int mf_default_variant(int nfronts) { return nfronts > 64 ? kVarPair : kVarTile64; }
 
 template <typename R>

@@ -658,13 +658,34 @@ __device__ __forceinline__ void tri_inv32(cplx_t<R> (*X)[kDB + 1], cplx_t<R>* __
   }
 }
 
+// One 16 x 16 block of a complex product on MFMA, k over [0, kmax) in steps
+// of 4: acc += A(16 rows) B(16 columns), operands fetched per lane through
+// a(row, k) and b(k, col) (row, col in 0..15); accumulator entry r of a lane
+// is output (lane & 15, mfma_row(lane, r)), as in gemm_tile_core.
+template <typename R, typename FA, typename FB>
+__device__ __forceinline__ void mfma_block16(typename Acc<R>::type& re, typename Acc<R>::type& im, int kmax, FA&& a,
+                                             FB&& b) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int kk = 0; kk < kmax; kk += 4) {
+    const cplx_t<R> av = a(lane & 15, kk + (lane >> 4));
+    const cplx_t<R> bv = b(kk + (lane >> 4), lane & 15);
+    re = mfma16(bv.x, av.x, re);
+    re = mfma16(-bv.y, av.y, re);
+    im = mfma16(bv.y, av.x, im);
+    im = mfma16(bv.x, av.y, im);
+  }
+}
+
 // The diagonal-block LU of block [k0, k0 + kb) of front fi by one workgroup
 // of 256 threads.  With kprev >= 0 the block first takes the trailing update
 // of the previous step (full block at kprev): A_kk -= L(k, prev) U(prev, k),
-// read from the L21 and U12 that step wrote.
+// read from the L21 and U12 that step wrote, or (fused) formed here from the
+// previous block's strips as they stand and its triangle inverses:
+// L(k, prev) = A(k, prev) U_prev^{-1}, U(prev, k) = L_prev^{-1} P A(prev, k).
 template <typename R>
 __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ dinv, int fi,
-                              int k0, int nb, int kprev, DiagLds<R>& S) {
+                              int k0, int nb, int kprev, DiagLds<R>& S, bool fused = false) {
   using C = cplx_t<R>;
   const FrontDev& f = mf.fronts[fi];
   const int p = f.p;
@@ -677,12 +698,48 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
   auto& X = S.X;
   auto& rsel = S.rsel;
   const int tid = threadIdx.x;
-  if (kprev >= 0) {
+  if (kprev >= 0 && !fused) {
     const C* base = arena + f.off;
     for (int t = tid; t < kDB * kDB; t += 256) {
       const int c = t / kDB, i = t - c * kDB;
       Lm[i][c] = (i < kb) ? base[(int64_t)(kprev + c) * F + k0 + i] : cmake<C>(0, 0);
       X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + kprev + i] : cmake<C>(0, 0);
+    }
+    __syncthreads();
+  } else if (kprev >= 0) {
+    // (the previous block is a full 32 x 32 one: kprev + 32 = k0 < p)
+    const C* base = arena + f.off;
+    const C* Lp = dinv + (int64_t)2 * kDB * kDB * (f.dblk + kprev / kDB);   // column-major
+    const C* Up = Lp + kDB * kDB;
+    const int* pr = mf.prow + f.perm + kprev;                               // front rows, pivot order
+    for (int t = tid; t < kDB * kDB; t += 256) {
+      const int c = t / kDB, i = t - c * kDB;
+      Lm[i][c] = (i < kb) ? base[(int64_t)(kprev + c) * F + k0 + i] : cmake<C>(0, 0);   // A(k, prev)
+      X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + pr[i]] : cmake<C>(0, 0);      // (P A)(prev, k)
+      D[i][c] = Lp[c * kDB + i];
+    }
+    __syncthreads();
+    // U(prev, k) = L_prev^{-1} X and L(k, prev) = A(k, prev) U_prev^{-1}: wave
+    // w forms the 16 x 16 block (w % 2, w / 2) of each on MFMA.
+    using V = typename Acc<R>::type;
+    const int w = tid >> 6, lane = tid & 63, ba = 16 * (w % 2), bb = 16 * (w / 2);
+    V ure = {}, uim = {}, lre = {}, lim = {};
+    mfma_block16<R>(ure, uim, kDB, [&](int r, int k) { return D[ba + r][k]; },
+                    [&](int k, int c) { return X[k][bb + c]; });
+    __syncthreads();
+    for (int t = tid; t < kDB * kDB; t += 256) {
+      const int c = t / kDB, i = t - c * kDB;
+      D[i][c] = Up[c * kDB + i];
+    }
+    __syncthreads();
+    mfma_block16<R>(lre, lim, kDB, [&](int r, int k) { return Lm[ba + r][k]; },
+                    [&](int k, int c) { return D[k][bb + c]; });
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ba + (lane & 15), col = bb + mfma_row(R(0), lane, r);
+      X[row][col] = cmake<C>(ure[r], uim[r]);
+      Lm[row][col] = cmake<C>(lre[r], lim[r]);
     }
     __syncthreads();
   }
@@ -1126,10 +1183,18 @@ __device__ inline void gemm_tile(const cplx_t<R>* __restrict__ Ap, int lda, cons
 //   mode 9: row strip of block k0 (its kb rows, columns [k0 + kb, F)) takes
 //           the same updates (left-looking inside an outer block whose
 //           trailing update then goes as one rank-(k0 - kf) product)
+// LDS bytes gemm_body<R, NEXT, mode> needs (the kernels that call it hold it).
+template <typename R, bool NEXT, int mode>
+constexpr size_t gemm_body_lds() {
+  constexpr bool kNarrow = mode == 3 || mode == 7 || mode == 8 || mode == 9;
+  constexpr size_t kGemm = kNarrow ? sizeof(GemmLds<R, 128, 32>) : sizeof(GemmLds<R>);
+  return NEXT ? (sizeof(DiagLds<R>) > kGemm ? sizeof(DiagLds<R>) : kGemm) : kGemm;
+}
+
 template <typename R, bool NEXT, int mode>
 __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                  cplx_t<R>* __restrict__ dinv, int f0, int step, int nb, int tiles_m, int bx, int by,
-                                 int kf = 0) {
+                                 unsigned char* __restrict__ lds, int kf = 0) {
   using C = cplx_t<R>;
   // Modes 3 and 7: products with one side of at most 32 take the 128 x 32
   // (tall) or 32 x 128 (wide) tile; tiles_m then counts 128-row tiles.
@@ -1137,9 +1202,6 @@ __device__ inline void gemm_body(const MfDev& mf, cplx_t<R>* __restrict__ arena,
   // its waves idle): shorter launches for levels of few fronts, where the
   // step's latency rather than its throughput counts.
   constexpr bool kNarrow = mode == 3 || mode == 7 || mode == 8 || mode == 9;
-  constexpr size_t kGemm = kNarrow ? sizeof(GemmLds<R, 128, 32>) : sizeof(GemmLds<R>);
-  constexpr size_t kLds = NEXT ? (sizeof(DiagLds<R>) > kGemm ? sizeof(DiagLds<R>) : kGemm) : kGemm;
-  __shared__ __align__(16) unsigned char lds[kLds];
   const FrontDev f = mf.fronts[f0 + by];
   int k0, kb;
   if (!step_range<R>(f, mode == 2 ? 2 : 0, step, nb, k0, kb)) return;
@@ -1261,7 +1323,8 @@ template <typename R, int MODE>
 __global__ void __launch_bounds__(256, kGemmWaves<R>) gemm_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ xwork,
                                                    cplx_t<R>* __restrict__ dinv, int f0, int step, int nb,
                                                    int tiles_m, int kf = 0) {
-  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, blockIdx.x, blockIdx.y, kf);
+  __shared__ __align__(16) unsigned char lds[gemm_body_lds<R, false, MODE>()];
+  gemm_body<R, false, MODE>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, blockIdx.x, blockIdx.y, lds, kf);
 }
 
 // Trailing update with the next diagonal block (mode 0, NEXT above); asks
@@ -1280,7 +1343,180 @@ __global__ void __launch_bounds__(256, 4) gemm_next_kernel(MfDev mf, cplx_t<R>* 
     by = (lin - nf) / per;
     bx = lin - nf - by * per;
   }
-  gemm_body<R, true, 0>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, bx, by);
+  __shared__ __align__(16) unsigned char lds[gemm_body_lds<R, true, 0>()];
+  gemm_body<R, true, 0>(mf, arena, xwork, dinv, f0, step, nb, tiles_m, bx, by, lds);
+}
+
+// ------------------------------------------------------------------ fused single steps
+// One launch per elimination step (levels of single steps, block-local
+// pivoting) instead of an L21 / U12 launch and a trailing-update launch:
+//  (a) one workgroup per front updates and factors the next diagonal block,
+//      forming its share of L21 / U12 itself (diag_lu_block, fused form);
+//  (b) each 64 x 64 trailing tile forms its own rows of L21 = A21 U_kk^{-1}
+//      and columns of U12 = L_kk^{-1} P A12 from the strips as they stand,
+//      then takes C -= L21 U12 on MFMA (the tile holding the next diagonal
+//      block skips it, as in the NEXT form);
+//  (c) the previous step's L21 / U12 are written into the front (gemm_body
+//      mode 6 of step - 1).  Nothing else in the launch reads or writes the
+//      strips of step - 1: the tiles and (a) read the strips of this step,
+//      and (b) writes only the trailing block.
+// After the last step one mode-6 (or 7) launch writes that step's L21 / U12.
+template <typename R>
+struct FusedLds {
+  cplx_t<R> Lt[kDB][kBM + 1];   // L21 rows of the tile by k (negated once formed)
+  cplx_t<R> Ut[kDB][kBN + 1];   // U12 columns of the tile by k
+};
+
+template <typename R>
+__device__ inline void fused_tile(const MfDev& mf, cplx_t<R>* __restrict__ arena, const cplx_t<R>* __restrict__ dinv,
+                                  const FrontDev& f, int k0, int kb, int skip, int tm, int tn, FusedLds<R>& L) {
+  using C = cplx_t<R>;
+  using V = typename Acc<R>::type;
+  const int F = f.F, k1 = k0 + kb;
+  const int m = F - k1;                     // trailing rows = columns
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  if (m <= 0 || m0 >= m || n0 >= m) return;
+  const int mt = m - m0, nt = m - n0;
+  C* base = arena + f.off;
+  const C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);   // column-major, valid for < kb
+  const C* Ui = Li + kDB * kDB;
+  const int* pr = mf.prow + f.perm + k0;                               // front rows, pivot order
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  auto& Lt = L.Lt;
+  auto& Ut = L.Ut;
+  for (int t = tid; t < kDB * kBM; t += 256) {
+    const int v = t / kBM, r = t - v * kBM;
+    Lt[v][r] = (v < kb && r < mt) ? base[(int64_t)(k0 + v) * F + k1 + m0 + r] : cmake<C>(0, 0);   // A21
+    Ut[v][r] = (v < kb && r < nt) ? base[(int64_t)(k1 + n0 + r) * F + pr[v]] : cmake<C>(0, 0);     // P A12
+  }
+  __syncthreads();
+  // On MFMA, wave w: L21 rows 16 w .. 16 w + 15 (all 32 columns u, two
+  // blocks) = A21 Uinv, and U12 columns 16 w .. 16 w + 15 (all 32 rows u) =
+  // Linv (P A12).  The inverses' entries come from global memory (a few KB,
+  // cache-resident); outside [0, kb) they are not written by the block LU,
+  // so the operands are masked there (A21 and P A12 are zero beyond kb).
+  // (each lane's inverse entries of a block are loaded together before its
+  // MFMA chain, so their latencies overlap)
+  using Vt = typename Acc<R>::type;
+  Vt lre[2] = {}, lim[2] = {}, ure[2] = {}, uim[2] = {};
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int u = 16 * b + li;
+    C uv[kDB / 4], lv[kDB / 4];
+#pragma unroll
+    for (int t = 0; t < kDB / 4; ++t) {
+      const int k = 4 * t + lk;
+      uv[t] = (k < kb && u < kb) ? Ui[u * kDB + k] : cmake<C>(0, 0);   // Uinv(k, u)
+      lv[t] = (k < kb && u < kb) ? Li[k * kDB + u] : cmake<C>(0, 0);   // Linv(u, k)
+    }
+    mfma_block16<R>(lre[b], lim[b], kDB, [&](int r, int k) { return Lt[k][16 * w + r]; },
+                    [&](int k, int) { return uv[k >> 2]; });
+    mfma_block16<R>(ure[b], uim[b], kDB, [&](int, int k) { return lv[k >> 2]; },
+                    [&](int k, int c) { return Ut[k][16 * w + c]; });
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lane & 15, j = mfma_row(R(0), lane, r);
+      Lt[16 * b + j][16 * w + i] = cmake<C>(-lre[b][r], -lim[b][r]);   // L21(16 w + i, 16 b + j), negated
+      Ut[16 * b + i][16 * w + j] = cmake<C>(ure[b][r], uim[b][r]);     // U12(16 b + i, 16 w + j)
+    }
+  __syncthreads();
+  // C -= L21 U12 over k < 32 (entries past kb are 0), waves of 32 x 32 as in
+  // gemm_tile_core: B takes the MFMA's first operand, lanes of one output
+  // column hold 16 consecutive rows.
+  const int wm = (w % 2) * 32, wn = (w / 2) * 32;
+  C* __restrict__ Ct = base + (int64_t)(k1 + n0) * F + k1 + m0;
+  V re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm + 16 * a + (lane & 15);
+        const int col = wn + 16 * b + mfma_row(R(0), lane, r);
+        C c0 = cmake<C>(0, 0);
+        if (row < mt && col < nt) c0 = Ct[(int64_t)col * F + row];
+        re[a][b][r] = c0.x;
+        im[a][b][r] = c0.y;
+      }
+#pragma unroll
+  for (int kk = 0; kk < kDB; kk += 4) {
+    C av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Lt[kk + (lane >> 4)][wm + 16 * a + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Ut[kk + (lane >> 4)][wn + 16 * b + (lane & 15)];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        re[a][b] = mfma16(bv[b].x, av[a].x, re[a][b]);
+        re[a][b] = mfma16(-bv[b].y, av[a].y, re[a][b]);
+        im[a][b] = mfma16(bv[b].y, av[a].x, im[a][b]);
+        im[a][b] = mfma16(bv[b].x, av[a].y, im[a][b]);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm + 16 * a + (lane & 15);
+        const int col = wn + 16 * b + mfma_row(R(0), lane, r);
+        if (row < mt && col < nt && !(m0 + row < skip && n0 + col < skip))
+          Ct[(int64_t)col * F + row] = cmake<C>(re[a][b][r], im[a][b][r]);
+      }
+}
+
+template <typename R>
+constexpr size_t fused_lds() {
+  constexpr size_t a = sizeof(DiagLds<R>), b = sizeof(FusedLds<R>), c = gemm_body_lds<R, false, 6>();
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+// Grid (ndiag + nwb + tiles^2, fronts), taken in linear order: the ndiag nf
+// diagonal-block workgroups first (they start first and overlap the tiles),
+// then the nwb nf write-back workgroups of step - 1, then the tiles.
+template <typename R>
+__global__ void __launch_bounds__(256, kGemmWaves<R>) gemm_fused_kernel(MfDev mf, cplx_t<R>* __restrict__ arena,
+                                                                        cplx_t<R>* __restrict__ xwork,
+                                                                        cplx_t<R>* __restrict__ dinv, int f0,
+                                                                        int step, int nb, int tiles, int ndiag,
+                                                                        int nwb) {
+  __shared__ __align__(16) unsigned char lds[fused_lds<R>()];
+  const int nf = gridDim.y;
+  int rest = blockIdx.x + gridDim.x * blockIdx.y;
+  if (rest < ndiag * nf) {
+    const int fi = f0 + rest;
+    const FrontDev& f = mf.fronts[fi];
+    int k0, kb;
+    if (!step_range<R>(f, 0, step, nb, k0, kb)) return;
+    if (k0 + kb < f.p)
+      diag_lu_block<R>(mf, arena, dinv, fi, k0 + kb, nb, k0, *reinterpret_cast<DiagLds<R>*>(lds), true);
+    return;
+  }
+  rest -= ndiag * nf;
+  if (rest < nwb * nf) {
+    const int by = rest / nwb, bx = rest - by * nwb;
+    gemm_body<R, false, 6>(mf, arena, xwork, dinv, f0, step - 1, nb, tiles, bx, by, lds);
+    return;
+  }
+  rest -= nwb * nf;
+  const int per = tiles * tiles;
+  const int by = rest / per, bx = rest - by * per;
+  const FrontDev f = mf.fronts[f0 + by];
+  int k0, kb;
+  if (!step_range<R>(f, 0, step, nb, k0, kb)) return;
+  const int k1 = k0 + kb;
+  const int skip = (ndiag && k1 < f.p) ? min(nb, f.p - k1) : 0;
+  fused_tile<R>(mf, arena, dinv, f, k0, kb, skip, bx % tiles, bx / tiles, *reinterpret_cast<FusedLds<R>*>(lds));
 }
 
 // Row interchanges of every 32-row diagonal block of a level's fronts applied
@@ -2219,6 +2455,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   const bool tournament = pivoting == kPivotTournament;
   const bool pair_steps = (variant & kVarPair) != 0;
   const bool tile64 = (variant & kVarTile64) != 0;
+  const bool fused = (variant & kVarFused) != 0 && !pair_steps && !partial_pivoting && !tournament;
   const bool invert = form == kFormInverse || form == kFormSide;
   using C = cplx_t<R>;
   C* arena = static_cast<C*>(arena_v);
@@ -2388,7 +2625,40 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
       }
     }
   }
-  for (int s = 0; s < steps && !tournament && (partial_pivoting || !pair_steps); ++s) {
+  for (int s = 0; s < steps && fused; ++s) {
+    // Trailing update of step s (8 mn^2 kb per front) and the L21 / U12 of
+    // step s - 1 (16 m kb^2), one launch (gemm_fused_kernel).
+    const int k0 = s * kNB;
+    double fl = 0;
+    if (g_timer)
+      for (int i = 0; i < nf; ++i) {
+        if (k0 < hP[i]) {
+          const double kb = std::min(kNB, hP[i] - k0), mn = hF[i] - k0 - kb;
+          fl += 8.0 * mn * mn * kb;
+        }
+        if (s > 0 && k0 - kNB < hP[i]) {
+          const double kb = std::min(kNB, hP[i] - (k0 - kNB)), m = hF[i] - (k0 - kNB) - kb;
+          fl += 16.0 * m * kb * kb;
+        }
+      }
+    const int ndiag = s + 1 < steps ? 1 : 0, nwb = s > 0 ? 2 * tiles : 0;
+    gemm_timed(fl, [&] {
+      gemm_fused_kernel<R><<<dim3(ndiag + nwb + tiles * tiles, nf), 256, 0, st>>>(mf, arena, xwork, dinv, f0, s, kNB,
+                                                                                  tiles, ndiag, nwb);
+    });
+  }
+  if (fused && steps > 0) {   // the last step's L21 / U12
+    const int k0 = (steps - 1) * kNB;
+    double fl = 0;
+    if (g_timer)
+      for (int i = 0; i < nf; ++i) {
+        if (k0 >= hP[i]) continue;
+        const double kb = std::min(kNB, hP[i] - k0), m = hF[i] - k0 - kb;
+        fl += 16.0 * m * kb * kb;
+      }
+    l21_u12(steps - 1, fl);
+  }
+  for (int s = 0; s < steps && !tournament && !fused && (partial_pivoting || !pair_steps); ++s) {
     const int k0 = s * kNB;
     if (partial_pivoting) {
       timer_begin(KC_PANEL, st);

@@ -11,17 +11,30 @@ import workloads
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+# mf_steps values: bit 0 paired steps, bit 1 64 x 64 L21 / U12 tiles, bit 2
+# fused single steps (one launch per step); every combination the tuner tries.
+SCHEDULES = [2, 0, 1, 3, 6, 4]
+
 
 def rel(a, b):
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
-def test_autotune_keeps_the_solution_and_writes_its_table(tmp_path, monkeypatch):
+def case(name):
+    if name == "2d_128":
+        return workloads.helmholtz_workload("mid", 5, 128, 2, 16.0, 16, 0.05, 8, nrhs=2), "octree"
+    if name == "3d_octree":
+        return workloads.small(12, 3, 3, waves=1.5, bumps=3, nrhs=2), "octree"
+    return workloads.small(24, 3, 3, waves=3.0, bumps=3, nrhs=2), "bisect"
+
+
+@pytest.mark.parametrize("name", ["2d_128", "3d_octree", "3d_bisect_24"])
+def test_autotune_and_every_schedule_keep_the_solution(tmp_path, monkeypatch, name):
     from paper_1409_0297_amd import Solver, binding
     path = tmp_path / "tune.txt"
     monkeypatch.setenv("SPP_TUNE_CACHE", str(path))
-    W = workloads.helmholtz_workload("mid", 5, 128, 2, 16.0, 16, 0.05, 8, nrhs=2)
-    kw = dict(omega=W.omega, tol=1e-11, max_iter=100)
+    W, order = case(name)
+    kw = dict(omega=W.omega, tol=1e-11, max_iter=100, order=order)
     B = Solver(W.kind, W.n, W.d, W.b, W.coeff, **kw)          # untuned: heuristic schedules
     ub, ib, rb, cb = B.solve(W.rhs)
     B.close()
@@ -42,7 +55,7 @@ def test_autotune_keeps_the_solution_and_writes_its_table(tmp_path, monkeypatch)
             assert int(value) in (0, 1, 2)
             mf_keys.append(key)
         elif key.startswith("mf_steps@"):
-            assert 0 <= int(value) <= 3
+            assert int(value) in SCHEDULES
             mf_keys.append(key)
         else:
             assert int(value) >= 1
@@ -51,7 +64,7 @@ def test_autotune_keeps_the_solution_and_writes_its_table(tmp_path, monkeypatch)
     # schedule and solve form on every level and compare with the untuned
     # solution (same tolerance, so equal to roundoff times the conditioning).
     try:
-        for steps, form in itertools.product(range(4), range(3)):
+        for steps, form in itertools.product(SCHEDULES, range(3)):
             for key in mf_keys:
                 binding.spp_tune_set(key, steps if key.startswith("mf_steps@") else form)
             C = Solver(W.kind, W.n, W.d, W.b, W.coeff, **kw)
@@ -61,7 +74,7 @@ def test_autotune_keeps_the_solution_and_writes_its_table(tmp_path, monkeypatch)
             assert cc == 0, (steps, form)
             assert all(abs(x - y) <= 1 for x, y in zip(ic, ib)), (steps, form, ic, ib)
             e = rel(uc, ub)
-            print(f"steps {steps} form {form}: iterations {ic}, vs untuned {e:.1e}")
+            print(f"{name}: steps {steps} form {form}: iterations {ic}, vs untuned {e:.1e}")
             assert e <= 1e-9, (steps, form, e)
     finally:
         for key in mf_keys:
