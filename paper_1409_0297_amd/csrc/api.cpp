@@ -1257,16 +1257,16 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
       double2* hcol = F->H + (int64_t)c0 * hrhs + (int64_t)j * ld;
       double2* h2 = F->h2 + (int64_t)c0 * ld;
       kr_dots(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, F->dpart, hcol, hrhs, 0, nullptr, 0);
-      kr_update(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, hcol, hrhs);
-      kr_dots(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, F->dpart, h2, ld, 0, hcol, hrhs);
-      kr_update(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, h2, ld);
+      // (the first update, the second projection, the second update and the
+      // norm's partial sums in two sweeps over V)
+      kr_cgs2_second(st, F->V + o, vstride, j + 1, F->wk + o, nc, g.N, hcol, hrhs, F->dpart, h2, ld, hcol, hrhs,
+                     F->rpart);
       // a10: the Givens update of the least-squares problem goes with the
       // normalisation of v_{j+1} (one launch per group).
       KrGivens gv;
       gv.H = F->H; gv.hcol = ld; gv.hrhs = hrhs; gv.cs = F->cs; gv.sn = F->sn; gv.g = F->gv;
       gv.j = j; gv.ldg = ld; gv.resid = F->resid; gv.resid_host = F->h_resid_dev; gv.c0 = c0;
-      kr_norm_scale(st, F->wk + o, F->V + (int64_t)(j + 1) * vstride + o, nc, g.N, F->rpart, hcol + (j + 1), hrhs,
-                    nullptr, 0, 0, gv);
+      kr_normalize(st, F->wk + o, F->V + (int64_t)(j + 1) * vstride + o, nc, g.N, F->rpart, hcol + (j + 1), hrhs, gv);
     }
     if (head_next) {
       SPP_HIP(hipEventRecord(F->resid_event, st));

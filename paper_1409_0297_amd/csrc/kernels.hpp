@@ -247,6 +247,16 @@ struct KrGivens {
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N,
                    double* partial, double2* h_sub, int hstride, const int* dj = nullptr,
                    int64_t v_jstride = 0, int64_t h_jstride = 0, const KrGivens& gv = KrGivens());
+// The rest of a CGS2 step after its first projection h1 (eager form):
+// w -= V h1 with the second projection's partial dots in the same pass,
+// h2 = V^H w (h_acc += h2), then w -= V h2 with the partial sums of |w|^2
+// (npart, as kr_norm_scale leaves them); kr_normalize then finishes
+// v = w / ||w||, the subdiagonal entry and the Givens step.
+void kr_cgs2_second(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w, int nrhs, int64_t N,
+                    const double2* h1, int h1stride, double2* dpart, double2* h2, int h2stride, double2* h_acc,
+                    int acc_stride, double* npart);
+void kr_normalize(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N, double* partial,
+                  double2* h_sub, int hstride, const KrGivens& gv = KrGivens());
 void kr_givens(hipStream_t st, double2* H, int hcol_stride, int hrhs_stride, double* cs, double2* sn,
                double2* g, int j, int nrhs, int ldg, double* resid, const int* active,
                const int* dj = nullptr);

@@ -140,6 +140,88 @@ __global__ void __launch_bounds__(kThreads) update_kernel(const double2* __restr
   w[rhs * N + e] = acc;
 }
 
+// CGS2 fused passes (eager iterations): w -= V h, then the partial dot
+// products of the updated w with every V_i in the layout of
+// dots_partial_kernel (each wave its own kPerThread * 64 entries: the wave
+// updates exactly the entries it then projects, so no other workgroup's
+// writes are involved).  The second sweep over V re-reads what the first
+// just read.
+__global__ void __launch_bounds__(kThreads) update_dots_kernel(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                               double2* __restrict__ w, int64_t N,
+                                                               const double2* __restrict__ h, int hstride,
+                                                               double2* __restrict__ partial) {
+  const int rhs = blockIdx.y;
+  __shared__ double2 hs[kMaxVec];
+  for (int i = threadIdx.x; i < nvec; i += kThreads) hs[i] = h[(int64_t)rhs * hstride + i];
+  __syncthreads();
+  const int nslot = gridDim.x * (kThreads / 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = blockIdx.x * (kThreads / 64) + wave;
+  const int64_t e0 = (int64_t)slot * 64 * kPerThread + lane;
+  double2* wr = w + rhs * N;
+  double2 wl[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t e = e0 + (int64_t)k * 64;
+    wl[k] = (e < N) ? wr[e] : cmake<double2>(0, 0);
+  }
+#pragma unroll 4
+  for (int i = 0; i < nvec; ++i) {
+    const double2* vr = V + (int64_t)i * vstride + rhs * N;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t e = e0 + (int64_t)k * 64;
+      if (e < N) cfms(wl[k], vr[e], hs[i]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t e = e0 + (int64_t)k * 64;
+    if (e < N) wr[e] = wl[k];
+  }
+  for (int i = 0; i < nvec; ++i) {
+    const double2* vr = V + (int64_t)i * vstride + rhs * N;
+    double2 s = cmake<double2>(0, 0);
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t e = e0 + (int64_t)k * 64;
+      if (e < N) s = cadd(s, cconjmul(vr[e], wl[k]));
+    }
+    s = wave_sum(s);
+    if (lane == 0) partial[((int64_t)rhs * nvec + i) * nslot + slot] = s;
+  }
+}
+
+// w -= V h, and the partial sums of |w|^2 for the normalisation (grid
+// (kNormBlocks, nrhs), the layout sumsq_partial_kernel writes).
+constexpr int kNormBlocks = 256;
+__global__ void __launch_bounds__(kThreads) update_sumsq_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                                int nvec, double2* __restrict__ w, int64_t N,
+                                                                const double2* __restrict__ h, int hstride,
+                                                                double* __restrict__ partial) {
+  const int rhs = blockIdx.y;
+  __shared__ double2 hs[kMaxVec];
+  for (int i = threadIdx.x; i < nvec; i += kThreads) hs[i] = h[(int64_t)rhs * hstride + i];
+  __syncthreads();
+  double s = 0;
+  for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < N; e += (int64_t)gridDim.x * kThreads) {
+    double2 acc = w[rhs * N + e];
+#pragma unroll 8
+    for (int i = 0; i < nvec; ++i) cfms(acc, V[(int64_t)i * vstride + rhs * N + e], hs[i]);
+    w[rhs * N + e] = acc;
+    s += cabs2(acc);
+  }
+  s = wave_sum(s);
+  __shared__ double sh[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < kThreads / 64; ++q) t += sh[q];
+    partial[(int64_t)rhs * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 __global__ void __launch_bounds__(kThreads) sumsq_partial_kernel(const double2* __restrict__ w, int64_t N,
                                                                  double* __restrict__ partial) {
   const int rhs = blockIdx.y;
@@ -361,6 +443,29 @@ void kr_update(hipStream_t st, const double2* V, int64_t vstride, int nvec, doub
   SPP_LAUNCH_CHECK();
 }
 
+void kr_cgs2_second(hipStream_t st, const double2* V, int64_t vstride, int nvec, double2* w, int nrhs, int64_t N,
+                    const double2* h1, int h1stride, double2* dpart, double2* h2, int h2stride, double2* h_acc,
+                    int acc_stride, double* npart) {
+  if (nvec > kMaxVec) throw Error(-7, "Krylov dimension exceeds the kernel limit");
+  const int nblk = dot_blocks(N);
+  update_dots_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, h1, h1stride, dpart);
+  SPP_LAUNCH_CHECK();
+  const int nslot = (int)kr_dot_slots(N);
+  dots_final_kernel<<<dim3(ceil_div(nvec, 4), nrhs), 256, 0, st>>>(dpart, nslot, nvec, h2, h2stride, 0, h_acc,
+                                                                       acc_stride, nullptr, 0, 0);
+  SPP_LAUNCH_CHECK();
+  update_sumsq_kernel<<<dim3(kNormBlocks, nrhs), kThreads, 0, st>>>(V, vstride, nvec, w, N, h2, h2stride, npart);
+  SPP_LAUNCH_CHECK();
+}
+
+void kr_normalize(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N, double* partial,
+                  double2* h_sub, int hstride, const KrGivens& gv) {
+  double* norms = partial + (int64_t)kNormBlocks * nrhs;
+  norm_scale_kernel<<<dim3(ceil_div(N, kThreads), nrhs), kThreads, 0, st>>>(w, v, partial, kNormBlocks, norms, h_sub,
+                                                                             hstride, N, nullptr, 0, 0, gv);
+  SPP_LAUNCH_CHECK();
+}
+
 void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* partial, double* out) {
   const int nblk = 256;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(v, N, partial);
@@ -373,7 +478,7 @@ void kr_norms(hipStream_t st, const double2* v, int nrhs, int64_t N, double* par
 void kr_norm_scale(hipStream_t st, const double2* w, double2* v, int nrhs, int64_t N, double* partial,
                    double2* h_sub, int hstride, const int* dj, int64_t v_jstride, int64_t h_jstride,
                    const KrGivens& gv) {
-  const int nblk = 256;
+  const int nblk = kNormBlocks;
   double* norms = partial + (int64_t)nblk * nrhs;
   sumsq_partial_kernel<<<dim3(nblk, nrhs), kThreads, 0, st>>>(w, N, partial);
   SPP_LAUNCH_CHECK();

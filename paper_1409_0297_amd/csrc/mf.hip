@@ -780,6 +780,10 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     }
   }
   if (fn > 0.f) {
+    // (reduced in the workgroup first: one atomic per statistic and block,
+    // not one per pivot and wave, as a launch over many fronts would send
+    // thousands of atomics to the same two words)
+    float rmin = 3.0e38f;
     if (tid < kb) {
       const float u = (float)sqrt(cabs2(X[tid][tid]));
       const float ratio = u / fn;
@@ -788,10 +792,19 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
         atomicExch(mf.info + 10, 1);
       }
       if (!(ratio >= mf.piv_warn)) atomicAdd(mf.info + 9, 1);
-      if (ratio >= 0.f) atomicMin(mf.pstat + 1, __float_as_uint(ratio));
+      if (ratio >= 0.f) rmin = ratio;
     }
-    for (int o = 32; o > 0; o >>= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o));
-    if ((tid & 63) == 0) atomicMax(mf.pstat, __float_as_uint(gmax / fn));
+    for (int o = 32; o > 0; o >>= 1) {   // (the kb <= 32 pivots are in wave 0)
+      rmin = fminf(rmin, __shfl_xor(rmin, o));
+      gmax = fmaxf(gmax, __shfl_xor(gmax, o));
+    }
+    __shared__ float gwave[4];
+    if ((tid & 63) == 0) gwave[tid >> 6] = gmax;
+    __syncthreads();
+    if (tid == 0) {
+      if (rmin < 3.0e38f) atomicMin(mf.pstat + 1, __float_as_uint(rmin));
+      atomicMax(mf.pstat, __float_as_uint(fmaxf(fmaxf(gwave[0], gwave[1]), fmaxf(gwave[2], gwave[3])) / fn));
+    }
   }
   C* Li = dinv + (int64_t)2 * kDB * kDB * (f.dblk + k0 / kDB);
   tri_inv32<R>(X, Li, Li + kDB * kDB, kb);
