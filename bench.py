@@ -60,7 +60,7 @@ def parse():
                          "schrodinger-batch: the 48-instance batched Schroedinger family, 16 sources each; "
                          "helmholtz3d: one step of the 128^3 3D configuration (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="before the steps, copy a MIB-MiB device buffer once (a plain copy kernel of known "
+                    help="after the warm-up steps, copy a MIB-MiB device buffer once (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
     return ap.parse_args()
 
@@ -399,11 +399,26 @@ def main():
         code, iters, relres = spp.spp_solve(h, rhs.data_ptr(), 1, u.data_ptr(), stream)
         return h, iters[0], relres[0]
 
-    def timed_run(prec, rhs, steps, warmup):
+    def calibration_copy():
+        # A device-to-device copy of known size just before the timed steps
+        # (after the warm-up and its tuning), so that counter runs can scale
+        # their readings and take the step's dispatches as those after it.
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: copied {nbytes} bytes device to device", file=sys.stderr, flush=True)
+        del src, dst
+
+    def timed_run(prec, rhs, steps, warmup, calibrate=False):
         plain = options(prec, base_flags)
         for _ in range(warmup):
             spp.spp_destroy(step(plain, rhs)[0])
         torch.cuda.synchronize()
+        if calibrate:
+            calibration_copy()
         # Timed region: K full steps (setup + solve), inputs already in HBM.
         t0 = time.perf_counter()
         rec = [step(plain, rhs) for _ in range(steps)]
@@ -414,16 +429,7 @@ def main():
             spp.spp_destroy(h)
         return dt, st, rec[-1][1], rec[-1][2]
 
-    if args.calibrate_copy > 0:
-        nbytes = args.calibrate_copy << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"bench: copied {nbytes} bytes device to device", file=sys.stderr, flush=True)
-        del src, dst
-    dt, st, iters, relres = timed_run(args.prec, f, args.steps, args.warmup)
+    dt, st, iters, relres = timed_run(args.prec, f, args.steps, args.warmup, calibrate=args.calibrate_copy > 0)
     # The same K steps again with per-kernel-class HIP events on the launch stream.
     timing = None
     other = None

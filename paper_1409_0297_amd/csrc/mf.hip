@@ -59,8 +59,12 @@ __device__ inline int anchor_point(const InstDev& I, int anchor, const int* off)
 }
 
 // ------------------------------------------------------------------ assembly
+// with_norm (levels without children, where assembly writes every nonzero
+// of a front exactly once): the largest |entry| written also goes to
+// mf.fnorm, as front_norm_kernel would find it, so that pass is skipped.
 template <typename R>
-__global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int blk0) {
+__global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __restrict__ arena, int blk0,
+                                                       int with_norm) {
   using C = cplx_t<R>;
   const AsmBlockDev B = mf.blocks[blk0 + blockIdx.x];
   const FrontDev f = mf.fronts[B.front];
@@ -81,6 +85,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
   // Consecutive threads take consecutive rows of one column: coalesced reads
   // of the transposed stencils and coalesced writes into the column-major front.
   const int total = T.nS * T.nG;
+  R m2 = 0;
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
     const int j = t / T.nS, i = t - j * T.nS;
     const int rp = rpos[i], cp = cpos[j];
@@ -94,8 +99,18 @@ __global__ void __launch_bounds__(256) assemble_kernel(MfDev mf, cplx_t<R>* __re
     // Every row of P belongs to one set instance and every (row, column)
     // pair of a block is distinct, so each front entry is written by at most
     // one thread: a plain store (no read of the zeroed arena).
-    A[(int64_t)cp * f.F + rp] = cconvert<C>(v);
+    const C c = cconvert<C>(v);
+    A[(int64_t)cp * f.F + rp] = c;
+    m2 = fmax(m2, cabs2(c));
   }
+  if (!with_norm) return;
+  float m = (float)sqrt((double)m2);
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __shared__ float wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(mf.fnorm + B.front, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 // ------------------------------------------------------------------ extend-add
@@ -712,11 +727,17 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     const C* Lp = dinv + (int64_t)2 * kDB * kDB * (f.dblk + kprev / kDB);   // column-major
     const C* Up = Lp + kDB * kDB;
     const int* pr = mf.prow + f.perm + kprev;                               // front rows, pivot order
-    for (int t = tid; t < kDB * kDB; t += 256) {
-      const int c = t / kDB, i = t - c * kDB;
+    // (U_prev^{-1} is loaded with the rest and kept in registers until D is
+    // free again, so the second product does not wait on memory)
+    constexpr int kPer = kDB * kDB / 256;
+    C up[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = tid + 256 * u, c = t / kDB, i = t - c * kDB;
       Lm[i][c] = (i < kb) ? base[(int64_t)(kprev + c) * F + k0 + i] : cmake<C>(0, 0);   // A(k, prev)
       X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + pr[i]] : cmake<C>(0, 0);      // (P A)(prev, k)
       D[i][c] = Lp[c * kDB + i];
+      up[u] = Up[c * kDB + i];
     }
     __syncthreads();
     // U(prev, k) = L_prev^{-1} X and L(k, prev) = A(k, prev) U_prev^{-1}: wave
@@ -727,9 +748,10 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     mfma_block16<R>(ure, uim, kDB, [&](int r, int k) { return D[ba + r][k]; },
                     [&](int k, int c) { return X[k][bb + c]; });
     __syncthreads();
-    for (int t = tid; t < kDB * kDB; t += 256) {
-      const int c = t / kDB, i = t - c * kDB;
-      D[i][c] = Up[c * kDB + i];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = tid + 256 * u, c = t / kDB, i = t - c * kDB;
+      D[i][c] = up[u];
     }
     __syncthreads();
     mfma_block16<R>(lre, lim, kDB, [&](int r, int k) { return Lm[ba + r][k]; },
@@ -2475,8 +2497,11 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
   C* xwork = static_cast<C*>(xwork_v);
   C* dinv = static_cast<C*>(dinv_v);
   const int nf = f1 - f0;
+  // (a level without children takes its fronts' largest entries from the
+  // assembly itself)
+  const bool norm_in_assembly = max_children == 0 && !partial_pivoting;
   if (blk1 > blk0) {
-    assemble_kernel<R><<<blk1 - blk0, 256, 0, st>>>(mf, arena, blk0);
+    assemble_kernel<R><<<blk1 - blk0, 256, 0, st>>>(mf, arena, blk0, norm_in_assembly ? 1 : 0);
     SPP_LAUNCH_CHECK();
   }
   for (int s = 0; s < max_children; ++s) {
@@ -2485,7 +2510,7 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     extend_add_kernel<R><<<grid, 256, 0, st>>>(mf, arena, f0, s, cols);
     SPP_LAUNCH_CHECK();
   }
-  if (!partial_pivoting) {
+  if (!partial_pivoting && !norm_in_assembly) {
     const int64_t chunk = 16384;
     front_norm_kernel<R><<<dim3((unsigned)ceil_div((int64_t)maxF * maxF, chunk), nf), 256, 0, st>>>(mf, arena, f0,
                                                                                                    chunk);
