@@ -1112,8 +1112,16 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     F->dkeep = dinv;
     mf.dkeep = dinv;
   }
-  SPP_HIP(hipStreamSynchronize(st));
-  for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p);
+  // The coefficient and Green buffers go back to the cache once the stream
+  // has drained: before a tuning pass (whose buffers may reuse them), else
+  // after the factorisation, so the host queues it behind the stencils.
+  bool setup_bufs_freed = false;
+  auto free_setup_bufs = [&] {
+    if (setup_bufs_freed) return;
+    SPP_HIP(hipStreamSynchronize(st));
+    for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p);
+    setup_bufs_freed = true;
+  };
   const int nl = static_cast<int>(P.levels.size());
   // Assembly and factorisation of every level with the given solve forms and
   // step schedules; fev (optional) gets two events per level around it.
@@ -1155,15 +1163,31 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       if (fev) SPP_HIP(hipEventRecord(fev[2 * l + 1], st));
     }
   };
-  if (tune_fac) tune_factorisation(F.get(), factor_all, st);
-  const double tf0 = now_ms();
+  if (tune_fac) {
+    free_setup_bufs();
+    tune_factorisation(F.get(), factor_all, st);
+  }
+  // (the factorisation's own time between two events: the stencils may
+  // still be running when the host has queued it)
+  struct FactorEvents {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~FactorEvents() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } fe;
+  for (hipEvent_t& x : fe.e) SPP_HIP(hipEventCreate(&x));
+  SPP_HIP(hipEventRecord(fe.e[0], st));
   factor_all(F->level_form, F->level_var, nullptr);
+  SPP_HIP(hipEventRecord(fe.e[1], st));
   int hinfo[16];
   unsigned hpstat[2];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
   SPP_HIP(hipMemcpyAsync(hpstat, mf.pstat, sizeof(hpstat), hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
-  const double tf1 = now_ms();
+  float factor_ms = 0.f;
+  SPP_HIP(hipEventElapsedTime(&factor_ms, fe.e[0], fe.e[1]));
+  free_setup_bufs();
   F->dfree(xwork);
   F->dfree(tbuf);
   F->dfree(tpbuf);
@@ -1184,7 +1208,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   F->stats.factor_entries = P.factor_entries;
   F->stats.factor_bytes = P.factor_entries * (int64_t)F->csize;
   F->stats.factor_flops = P.factor_flops;
-  F->stats.t_factor_ms = tf1 - tf0;
+  F->stats.t_factor_ms = factor_ms;
   F->stats.t_setup_ms = now_ms() - t0;
   F->stats.last_iters = 0;
   F->stats.last_cycles = 0;

@@ -177,16 +177,18 @@ struct SolveJobs {
   SolveJob job[8];
 };
 
-// Register-resident elimination for small systems (nB <= 64, nB + nS <= 320,
-// 1024 threads): wave w holds rows w, w + 16, ... and lane l columns l,
-// l + 64, ... of the augmented [A^T | Bm^T] (1024 threads measured faster
-// than 512 with twice the rows each); rows stay in place (the pivot
-// order is recorded) and each step exchanges only the pivot row and the
-// pivot column through LDS.
-constexpr int kRsWaves = 16, kRsRows = 4, kRsCols = 5;   // 1024 threads, nB <= 64, W <= 320
+// Register-resident elimination for small systems (nB <= 64, 1024 threads):
+// wave w holds rows w, w + 16, ... and lane l columns l and l + 64 of the
+// augmented [A^T | Bm^T(:, r0 : r0 + nR)] (1024 threads measured faster
+// than 512 with twice the rows each); rows stay in place (the pivot order
+// is recorded) and each step exchanges only the pivot row and the pivot
+// column through LDS.  The right-hand sides go in chunks of at most 64, one
+// workgroup each: every chunk repeats the same elimination of A^T (the same
+// pivots, the same arithmetic), so the result does not depend on the split.
+constexpr int kRsWaves = 16, kRsRows = 4, kRsCols = 2, kRsChunk = 64;   // nB <= 64, W <= 128
 
-__device__ void right_solve_regs(const SolveJob& J) {
-  const int nB = J.nB, nS = J.nS, W = nB + nS;
+__device__ void right_solve_regs(const SolveJob& J, int r0, int nR) {
+  const int nB = J.nB, W = nB + nR;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // ty < kRsWaves
   __shared__ double2 prow[kRsCols * 64];
   __shared__ double2 mcol[64];
@@ -202,7 +204,7 @@ __device__ void right_solve_regs(const SolveJob& J) {
     for (int b = 0; b < kRsCols; ++b) {
       const int r = ty + kRsWaves * a, c = tx + 64 * b;
       double2 x = cmake<double2>(0, 0);
-      if (r < nB && c < W) x = (c < nB) ? J.A[c * J.lda + r] : J.Bm[(c - nB) * J.ldb + r];
+      if (r < nB && c < W) x = (c < nB) ? J.A[c * J.lda + r] : J.Bm[(r0 + c - nB) * J.ldb + r];
       v[a][b] = x;
     }
   if (threadIdx.x < 2) keys[threadIdx.x] = 0;
@@ -238,6 +240,9 @@ __device__ void right_solve_regs(const SolveJob& J) {
     __syncthreads();
     done |= 1ULL << piv;
     const double2 pinv = crecip(prow[k]);
+    // (the lane holding column k + 1 posts one key for its rows: the
+    // largest, so 16 atomics a step rather than one per row)
+    unsigned long long kmax = 0;
 #pragma unroll
     for (int a = 0; a < kRsRows; ++a) {
       const int r = ty + kRsWaves * a;
@@ -248,10 +253,11 @@ __device__ void right_solve_regs(const SolveJob& J) {
         const int c = tx + 64 * b;
         if (c > k && c < W) {
           cfms(v[a][b], f, prow[c]);
-          if (c == k + 1) atomicMax(&keys[(k + 1) & 1], key_of(cabs2(v[a][b]), r));
+          if (c == k + 1) kmax = max(kmax, key_of(cabs2(v[a][b]), r));
         }
       }
     }
+    if (kmax) atomicMax(&keys[(k + 1) & 1], kmax);
     __syncthreads();
   }
   // Back substitution on the right-hand-side columns, last pivot first:
@@ -302,19 +308,22 @@ __device__ void right_solve_regs(const SolveJob& J) {
 #pragma unroll
     for (int b = 0; b < kRsCols; ++b) {
       const int c = tx + 64 * b;
-      if (c >= nB && c < W) J.X[(c - nB) * J.ldx + m] = v[a][b];
+      if (c >= nB && c < W) J.X[(r0 + c - nB) * J.ldx + m] = v[a][b];
     }
   }
 }
 
-// One workgroup per set type (blockIdx.x): the types' systems are independent.
+// One workgroup per set type (blockIdx.x) and chunk of right-hand sides
+// (blockIdx.y, register form only): the types' systems are independent.
 __global__ void __launch_bounds__(64 * kRsWaves) right_solve_kernel(SolveJobs jobs) {
   const SolveJob& J = jobs.job[blockIdx.x];
   if (J.nS == 0) return;   // (a set type with no points)
-  if (J.nB <= kRsWaves * kRsRows && J.nB + J.nS <= 64 * kRsCols) {   // (launched with 64 kRsWaves threads)
-    right_solve_regs(J);
+  if (J.nB <= kRsWaves * kRsRows) {   // (launched with 64 kRsWaves threads)
+    const int r0 = blockIdx.y * kRsChunk;
+    if (r0 < J.nS) right_solve_regs(J, r0, min(kRsChunk, J.nS - r0));
     return;
   }
+  if (blockIdx.y != 0) return;
   const int nB = J.nB, nS = J.nS, lda = J.lda, ldb = J.ldb, ldx = J.ldx;
   const double2* __restrict__ A = J.A;
   const double2* __restrict__ Bm = J.Bm;
@@ -457,7 +466,10 @@ void stencil_build(hipStream_t st, int d, int n, const double2* g, const double2
     // T_S M(beta, :) = M(S, :)
     jobs.job[t] = SolveJob{nB, nS, M + (size_t)nS * nB, nB, M, nB, aug, S.T, nB, info + t};
   }
-  right_solve_kernel<<<ntypes, 64 * kRsWaves, 0, st>>>(jobs);
+  int chunks = 1;
+  for (int t = 0; t < ntypes; ++t)
+    if (types[t].nB <= kRsWaves * kRsRows) chunks = std::max(chunks, (int)ceil_div(types[t].nS, kRsChunk));
+  right_solve_kernel<<<dim3(ntypes, chunks), 64 * kRsWaves, 0, st>>>(jobs);
   SPP_LAUNCH_CHECK();
   for (int t = 0; t < ntypes; ++t) {
     StencilDev& S = types[t];
