@@ -863,6 +863,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   F->planp = &F->pd->plan;
   const Plan& P = *F->planp;
   bool tune_fac = false;   // run the factorisation tuning pass (below)
+  size_t spare_bytes = 0;  // device memory the memory plan leaves over (0: caller-owned memory)
 
   // Problems, and groups of consecutive problems with equal grids.
   int64_t Noff = 0;
@@ -947,6 +948,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
         std::lock_guard<std::mutex> lk(g_mem_mu);
         cached = g_mem_cached;
       }
+      spare_bytes = freeb + cached > need ? freeb + cached - need : 0;
       // (the tuning pass, with the inverse work of every level and its own
       // solve vectors, runs only where that fits besides the rest)
       const size_t tune_extra = (size_t)(2 * P.vec_elems + 2 * F->Ntot + (1 << 20)) * cs;
@@ -1180,6 +1182,17 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   SPP_HIP(hipEventRecord(fe.e[0], st));
   factor_all(F->level_form, F->level_var, nullptr);
   SPP_HIP(hipEventRecord(fe.e[1], st));
+  // The buffers of a one-right-hand-side solve are set up while the GPU
+  // factors (host work that would otherwise stall the start of the first
+  // solve), when they are small against the free memory.
+  {
+    const int maxit = F->opt.max_iter;
+    const int cycle_len = F->opt.restart > 0 ? std::min(F->opt.restart, maxit) : maxit;
+    const size_t vec = (size_t)F->Ntot * sizeof(double2);
+    const size_t est = vec * (2 * (size_t)cycle_len + 10) + ((size_t)1 << 20) * F->csize +
+                       (size_t)2 * P.vec_elems * F->csize;
+    if (est <= ((size_t)4 << 30) && est <= spare_bytes / 8) ensure_solve_buffers(F.get(), 1, cycle_len);
+  }
   int hinfo[16];
   unsigned hpstat[2];
   SPP_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
@@ -1257,6 +1270,18 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
     kr_norms(st, F->g0 + g.Noff * nrhs, nc, g.N, F->rpart, F->norms + c0);
   }
+  const bool learned = F->cnn != nullptr && precond;
+  const bool use_graph = (F->opt.flags & SPP_F_GRAPHS) && !F->timer && !learned;
+  // The first cycle starts from r = g: its first basis vector, and in eager
+  // iterations the preconditioner head on it, go out before the host waits
+  // for beta0.
+  for (const SppGroup& g : F->groups) {
+    const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
+    const int64_t o = g.Noff * nrhs;
+    kr_scale_init(st, F->g0 + o, F->V + o, F->norms + c0, nc, g.N, F->gv + (int64_t)c0 * ld, ld);
+  }
+  const bool early_head = precond && !learned && !use_graph;
+  if (early_head) precond_head(F, F->V, nrhs, st);
   std::vector<double> beta0(cols);
   SPP_HIP(hipMemcpyAsync(beta0.data(), F->norms, sizeof(double) * cols, hipMemcpyDeviceToHost, st));
   SPP_HIP(hipStreamSynchronize(st));
@@ -1328,8 +1353,6 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     SPP_HIP(hipMemcpyAsync(F->h_resid, F->resid, sizeof(double) * cols, hipMemcpyDeviceToHost, s));
     kr_set_counter(s, F->dj, 1, true);
   };
-  const bool learned = F->cnn != nullptr && precond;
-  const bool use_graph = (F->opt.flags & SPP_F_GRAPHS) && !F->timer && !learned;
   if (use_graph && (!F->graph_exec || F->graph_nrhs != nrhs || F->graph_precond != precond)) {
     F->drop_graph();
     if (!F->gstream) SPP_HIP(hipStreamCreateWithFlags(&F->gstream, hipStreamNonBlocking));
@@ -1368,9 +1391,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   bool all_ok = false;
   for (;;) {
     for (const SppGroup& g : F->groups) {
+      if (cycles == 0) break;   // (queued before the wait for beta0)
       const int c0 = g.inst0 * nrhs, nc = g.ninst * nrhs;
       const int64_t o = g.Noff * nrhs;
-      if (cycles > 0) kr_norms(st, r + o, nc, g.N, F->rpart, F->norms + c0);
+      kr_norms(st, r + o, nc, g.N, F->rpart, F->norms + c0);
       kr_scale_init(st, r + o, F->V + o, F->norms + c0, nc, g.N, F->gv + (int64_t)c0 * ld, ld);
     }
     if (cycles == 0) {
@@ -1387,7 +1411,7 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
     }
     if (use_graph) kr_set_counter(st, F->dj, 0, false);
     std::vector<double> prev(beta);
-    head_ready = false;
+    head_ready = cycles == 0 && early_head;
     const int jmax = std::min(cycle_len, maxit - used);
     for (j = 0; j < jmax && done < cols; ++j) {
       double2* vj = F->V + (int64_t)j * vstride;
