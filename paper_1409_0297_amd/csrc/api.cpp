@@ -341,6 +341,10 @@ struct spp_factor {
   // the step index in device memory.
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t gstream = nullptr;
+  // Level inverses beside the next level's LU: one event marks a level's LU,
+  // the other the end of the inverse work.
+  hipEvent_t inv_event[2] = {nullptr, nullptr};
+  hipEvent_t zero_event = nullptr;   // the arena's zeroing on the side stream
   int graph_nrhs = 0;
   bool graph_precond = true;
   int* dj = nullptr;
@@ -399,6 +403,9 @@ struct spp_factor {
   ~spp_factor() {
     drop_graph();
     if (gstream) (void)hipStreamDestroy(gstream);
+    for (hipEvent_t e : inv_event)
+      if (e) (void)hipEventDestroy(e);
+    if (zero_event) (void)hipEventDestroy(zero_event);
     (void)hipDeviceSynchronize();
     for (void* p : hook_blocks) opt.free(p, opt.alloc_ctx);
     for (const auto& a : allocs) mem_put(a.first, a.second, device);
@@ -460,6 +467,20 @@ double shift_gap(int d, int n, double s, bool nyquist_zero = false) {
       for (int b = -h; b < h; ++b) last(sq(a) + sq(b));
   }
   return best / std::fabs(s);
+}
+
+// The stream that runs level inverses beside the factorisation, one per
+// device for the life of the process (default priority; work from
+// different factors is ordered on it by events only).
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {nullptr};
+  int dev = 0;
+  SPP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(-7, "device index beyond the side-stream table");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!streams[dev]) SPP_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
 }
 
 int total_cols(const spp_factor* F, int nrhs) { return static_cast<int>(F->inst.size()) * nrhs; }
@@ -1100,6 +1121,16 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
 
   const bool streamed = P.storage == 1;
   F->arena = F->big_alloc((size_t)P.arena_elems * F->csize);
+  // A resident arena from the library's own memory (no pending user of it)
+  // is zeroed on the side stream at once, beside the stencil work.
+  bool arena_zero_ahead = false;
+  if (!streamed && !F->opt.alloc) {
+    hipStream_t zs = side_stream();
+    if (!F->zero_event) SPP_HIP(hipEventCreateWithFlags(&F->zero_event, hipEventDisableTiming));
+    SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, zs));
+    SPP_HIP(hipEventRecord(F->zero_event, zs));
+    arena_zero_ahead = true;
+  }
   if (streamed) F->fstore = F->big_alloc((size_t)P.fstore_elems * F->csize);
   F->fac = streamed ? F->fstore : F->arena;
   void* xwork = F->dalloc<char>((size_t)F->xwork_elems * F->csize);
@@ -1133,7 +1164,21 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     SPP_HIP(hipMemsetAsync(info + 9, 0, 2 * sizeof(int), st));   // small pivots, fatal flag
     SPP_HIP(hipMemsetAsync(mf.pstat, 0, sizeof(unsigned), st));
     SPP_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(mf.pstat + 1), 0x7f7fffff, 1, st));
-    if (!streamed) SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
+    if (arena_zero_ahead) {
+      SPP_HIP(hipStreamWaitEvent(st, F->zero_event, 0));
+      arena_zero_ahead = false;
+    } else if (!streamed) {
+      SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, st));
+    }
+    // Resident storage, untimed: each level's inverses run on the side
+    // stream beside the next level's LU (joined below).
+    const bool overlap = !fev && !streamed && !F->timer && !partial_pivoting;
+    hipStream_t inv_st = nullptr;
+    if (overlap) {
+      inv_st = side_stream();
+      for (hipEvent_t& e : F->inv_event)
+        if (!e) SPP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     for (int l = 0; l < nl; ++l) {
       const Level& L = P.levels[l];
       const int* hF = F->pd->level_F[l].data();
@@ -1152,10 +1197,12 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
                       : forms[l] == kFormBlocked ? kPivotTournament : kPivotBlockLocal;
       if (F->opt.prec == SPP_C128)
         mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP,
-                                L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP);
+                                L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP, inv_st,
+                                F->inv_event[0]);
       else
         mf_factor_level<float>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP,
-                               L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP);
+                               L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP, inv_st,
+                               F->inv_event[0]);
       if (streamed) {
         if (F->opt.prec == SPP_C128)
           mf_store_factors<double>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
@@ -1163,6 +1210,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
           mf_store_factors<float>(st, mf, F->arena, F->fstore, L.begin, L.end - L.begin, L.maxF);
       }
       if (fev) SPP_HIP(hipEventRecord(fev[2 * l + 1], st));
+    }
+    if (overlap) {   // (the factor is complete once the last inverses are)
+      SPP_HIP(hipEventRecord(F->inv_event[1], inv_st));
+      SPP_HIP(hipStreamWaitEvent(st, F->inv_event[1], 0));
     }
   };
   if (tune_fac) {

@@ -181,11 +181,19 @@ inline int64_t mf_tournament_ints(int nfronts, int maxP) { return 2LL * nfronts 
 constexpr int kVarPair = 1, kVarTile64 = 2, kVarFused = 4, kVarAll = 7;
 inline int mf_default_variant(int nfronts) { return nfronts > 64 ? kVarPair : kVarTile64; }
 
+// inv_st / lu_done (optional): the explicit inverses of an Inverse or Side
+// level go to stream inv_st after the level's LU (lu_done recorded on st,
+// waited for on inv_st), so that they run beside the next level's
+// factorisation: they read and write only this level's pivot rows and
+// columns, L21 and U12 (the next level reads its children's Schur
+// complements), and xwork / tbuf, which no LU step of a block-locally
+// pivoted level uses.  The caller joins inv_st before the factor is used.
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena, void* xwork, void* tbuf, void* dinv, int* tpbuf,
                      int f0, int f1, int maxF, int maxP, int blk0, int blk1,
                      int max_children, int form, int pivoting, int variant,
-                     const int* hF, const int* hP);   // host: F and p of the level's fronts
+                     const int* hF, const int* hP,   // host: F and p of the level's fronts
+                     hipStream_t inv_st = nullptr, hipEvent_t lu_done = nullptr);
 // How a level's fronts are kept for the substitution:
 //  kFormLU:      LU in place, one workgroup per front solves;
 //  kFormInverse: L11^{-1}, U11^{-1} over the pivot block, L21 and U12 kept:

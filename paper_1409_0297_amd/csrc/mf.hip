@@ -2485,7 +2485,8 @@ constexpr int kOuterNB = 256;   // columns per outer block of the tournament-piv
 template <typename R>
 void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork_v, void* tbuf_v, void* dinv_v,
                      int* tpbuf, int f0, int f1, int maxF, int maxP, int blk0, int blk1, int max_children, int form,
-                     int pivoting, int variant, const int* hF, const int* hP) {
+                     int pivoting, int variant, const int* hF, const int* hP, hipStream_t inv_st,
+                     hipEvent_t lu_done) {
   const bool partial_pivoting = pivoting == kPivotPartial;
   const bool tournament = pivoting == kPivotTournament;
   const bool pair_steps = (variant & kVarPair) != 0;
@@ -2763,7 +2764,14 @@ void mf_factor_level(hipStream_t st, const MfDev& mf, void* arena_v, void* xwork
     }
   }
   if (!invert) return;
-  // Inverses of L11 and U11 for levels solved by matrix-vector products.
+  // Inverses of L11 and U11 for levels solved by matrix-vector products
+  // (on inv_st after the LU, where the caller runs them beside the next
+  // level; block-locally pivoted levels only).
+  if (inv_st && lu_done && !partial_pivoting && !tournament) {
+    SPP_HIP(hipEventRecord(lu_done, st));
+    SPP_HIP(hipStreamWaitEvent(inv_st, lu_done, 0));
+    st = inv_st;
+  }
   const int ptiles = (int)ceil_div(maxP, kBM);
   if (!partial_pivoting) {
     inv_init_kernel<R><<<dim3(ceil_div((int64_t)maxP * maxP, 256 * 4), nf), 256, 0, st>>>(mf, xwork, dinv, f0);
@@ -3130,9 +3138,9 @@ void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int 
 }
 
 template void mf_factor_level<double>(hipStream_t, const MfDev&, void*, void*, void*, void*, int*, int, int, int, int, int, int,
-                                      int, int, int, int, const int*, const int*);
+                                      int, int, int, int, const int*, const int*, hipStream_t, hipEvent_t);
 template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, void*, void*, int*, int, int, int, int, int, int,
-                                     int, int, int, int, const int*, const int*);
+                                     int, int, int, int, const int*, const int*, hipStream_t, hipEvent_t);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
                                int64_t, bool, hipEvent_t*);
