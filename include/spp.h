@@ -171,7 +171,11 @@ typedef struct {
   int64_t factor_bytes;     /* bytes the substitution reads per application      */
   double factor_flops;      /* real flops of the partial factorisations          */
   double t_setup_ms;        /* wall time of the last spp_setup                   */
-  double t_factor_ms;       /* of which the multifrontal factorisation (GPU time) */
+  double t_factor_ms;       /* of which the multifrontal factorisation: GPU time
+                               to its last LU step (the explicit inverses of the
+                               levels solved by products run beside it on a
+                               second stream and may end during the first
+                               solve, which waits for them)                    */
   double t_solve_ms;        /* wall time of the last spp_solve                   */
   int32_t last_iters;       /* GMRES iterations of the last solve (max over RHS) */
   int32_t breakdown_front;  /* front index of a pivot breakdown, else -1         */

@@ -345,6 +345,12 @@ struct spp_factor {
   // the other the end of the inverse work.
   hipEvent_t inv_event[2] = {nullptr, nullptr};
   hipEvent_t zero_event = nullptr;   // the arena's zeroing on the side stream
+  // The last level's inverses may still run on the side stream when setup
+  // returns (inv_event[1] marks their end): every use of the factor waits
+  // for that event first (factor_ready), and the work buffers they use are
+  // returned once it has passed (factor_settled).
+  bool inv_pending = false;
+  std::vector<void*> inv_buffers;
   int graph_nrhs = 0;
   bool graph_precond = true;
   int* dj = nullptr;
@@ -483,6 +489,18 @@ hipStream_t side_stream() {
   return streams[dev];
 }
 
+void factor_ready(spp_factor* F, hipStream_t st) {
+  if (F->inv_pending) SPP_HIP(hipStreamWaitEvent(st, F->inv_event[1], 0));
+}
+
+void factor_settled(spp_factor* F) {
+  if (!F->inv_pending) return;
+  SPP_HIP(hipEventSynchronize(F->inv_event[1]));
+  for (void* p : F->inv_buffers) F->dfree(p);
+  F->inv_buffers.clear();
+  F->inv_pending = false;
+}
+
 int total_cols(const spp_factor* F, int nrhs) { return static_cast<int>(F->inst.size()) * nrhs; }
 
 void ensure_solve_buffers(spp_factor* F, int nrhs, int iters) {
@@ -574,6 +592,7 @@ void precond_head(spp_factor* F, const double2* r, int nrhs, hipStream_t st) {
 }
 
 void precond_tail(spp_factor* F, double2* z, int nrhs, hipStream_t st, bool persistent) {
+  factor_ready(F, st);
   persistent = persistent && (F->opt.flags & SPP_F_PERSISTENT);
   const int nl = static_cast<int>(F->planp->levels.size());
   const double* ent = F->pd->level_ent.data();
@@ -638,6 +657,7 @@ void validate_problem(const spp_problem* pb) {
 // substitution products (right-hand-side count nrhs) and stores the fastest
 // in the process-wide tuning table (and its file, if SPP_TUNE_CACHE is set).
 void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
+  factor_ready(F, st);
   ensure_solve_buffers(F, nrhs, F->opt.max_iter);
   KernelTimer* saved = g_timer;
   g_timer = nullptr;
@@ -1158,6 +1178,9 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   const int nl = static_cast<int>(P.levels.size());
   // Assembly and factorisation of every level with the given solve forms and
   // step schedules; fev (optional) gets two events per level around it.
+  // defer_inverses: the final factorisation leaves its last inverses running
+  // on the side stream (see factor_ready).
+  bool defer_inverses = false;
   auto factor_all = [&](const std::vector<int>& forms, const std::vector<int>& vars, hipEvent_t* fev) {
     SPP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));           // breakdown front
     SPP_HIP(hipMemsetAsync(mf.fnorm, 0, sizeof(unsigned) * P.fronts.size(), st));
@@ -1213,7 +1236,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     }
     if (overlap) {   // (the factor is complete once the last inverses are)
       SPP_HIP(hipEventRecord(F->inv_event[1], inv_st));
-      SPP_HIP(hipStreamWaitEvent(st, F->inv_event[1], 0));
+      if (defer_inverses) F->inv_pending = true;
+      else SPP_HIP(hipStreamWaitEvent(st, F->inv_event[1], 0));
     }
   };
   if (tune_fac) {
@@ -1231,6 +1255,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   } fe;
   for (hipEvent_t& x : fe.e) SPP_HIP(hipEventCreate(&x));
   SPP_HIP(hipEventRecord(fe.e[0], st));
+  defer_inverses = true;
   factor_all(F->level_form, F->level_var, nullptr);
   SPP_HIP(hipEventRecord(fe.e[1], st));
   // The buffers of a one-right-hand-side solve are set up while the GPU
@@ -1252,10 +1277,15 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   float factor_ms = 0.f;
   SPP_HIP(hipEventElapsedTime(&factor_ms, fe.e[0], fe.e[1]));
   free_setup_bufs();
-  F->dfree(xwork);
-  F->dfree(tbuf);
+  if (F->inv_pending) {   // (still in use by the last inverses)
+    F->inv_buffers = {xwork, tbuf};
+    if (!any_blocked) F->inv_buffers.push_back(dinv);
+  } else {
+    F->dfree(xwork);
+    F->dfree(tbuf);
+    if (!any_blocked) F->dfree(dinv);
+  }
   F->dfree(tpbuf);
-  if (!any_blocked) F->dfree(dinv);
   F->dfree(swork);
   if (streamed) {   // the substitution reads the factor store only
     F->big_free(F->arena);
@@ -1323,6 +1353,7 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   }
   const bool learned = F->cnn != nullptr && precond;
   const bool use_graph = (F->opt.flags & SPP_F_GRAPHS) && !F->timer && !learned;
+  if (use_graph) factor_ready(F, st);   // (no event waits inside a capture)
   // The first cycle starts from r = g: its first basis vector, and in eager
   // iterations the preconditioner head on it, go out before the host waits
   // for beta0.
@@ -1556,6 +1587,7 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   F->stats.t_solve_ms = now_ms() - t0;
   F->last_iters_all = j;
   F->last_nrhs = nrhs;
+  factor_settled(F);   // (the solve's last synchronisation came after its wait)
   if (!all_ok) {
     g_last_error = "GMRES reached max_iter before the true residual met the tolerance";
     return SPP_NOT_CONVERGED;
