@@ -139,3 +139,39 @@ def test_pivot_statistics(prec, eps):
         assert (st["small_pivots"] > 0) == (st["min_pivot"] < 1e3 * eps)
         assert 0.0 < st["pivot_growth"] < 1e6, st["pivot_growth"]
         assert st["device_bytes"] > st["factor_entries"] * (16 if prec == "c128" else 8)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_factor_used_at_once_from_another_stream(prec):
+    """The explicit inverses of the levels solved by products run on the
+    library's second stream and may still run when setup returns.  A
+    preconditioner apply and a solve issued at once, on a stream other than
+    the setup's, wait for them: their results equal, bit for bit, those of
+    the same calls made after the device has drained."""
+    from paper_1409_0297_amd import Solver
+    W = workloads.small(256, 2, 16, 16.0, bumps=8)
+    rng = np.random.default_rng(41)
+    r = torch.as_tensor(rng.standard_normal((1, 256 * 256)) + 1j * rng.standard_normal((1, 256 * 256)),
+                        dtype=torch.complex128, device="cuda")
+    f = torch.as_tensor(W.rhs.reshape(1, -1), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    s_setup, s_use = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s_setup):
+        S = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, prec=prec, tol=1e-10, max_iter=100)
+    with torch.cuda.stream(s_use):
+        z_now = S.apply_precond(r)
+    torch.cuda.synchronize()
+    z_later = S.apply_precond(r)
+    torch.cuda.synchronize()
+    assert torch.equal(z_now, z_later)
+    S.close()
+    with torch.cuda.stream(s_setup):
+        S = Solver(W.kind, W.n, W.d, W.b, W.coeff, omega=W.omega, prec=prec, tol=1e-10, max_iter=100)
+    with torch.cuda.stream(s_use):
+        u_now, it_now, _, code_now = S.solve(f)
+    torch.cuda.synchronize()
+    u_later, it_later, _, code_later = S.solve(f)
+    torch.cuda.synchronize()
+    S.close()
+    assert code_now == 0 and code_later == 0 and it_now == it_later
+    assert torch.equal(u_now, u_later)
