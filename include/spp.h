@@ -41,7 +41,14 @@
  *    library never frees caller memory.  It owns only what a spp_factor
  *    holds (factors, stencils, work space), released by spp_destroy.
  *  - All GPU work is ordered on the hipStream_t passed in (0 = the null
- *    stream).  Calls returning host outputs synchronise that stream.
+ *    stream).  Calls returning host outputs synchronise that stream.  One
+ *    exception: during spp_setup of resident fronts, the zeroing of the front
+ *    arena and the explicit inverses of the levels solved by products run on
+ *    a second stream the library owns (one per device, default priority),
+ *    beside the stencils and the next level's LU.  spp_setup returns once
+ *    the LU is complete; the last inverses may still run.  Every later call
+ *    that reads the factor, on any stream, waits for them on that stream
+ *    first, so the caller needs no synchronisation of its own.
  *  - Every function returns SPP_OK (0) or a negative error code; no C++
  *    exception crosses this boundary.  spp_last_error() gives a message for
  *    the most recent failure on the calling thread.

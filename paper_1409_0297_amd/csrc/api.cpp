@@ -1353,7 +1353,10 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   }
   const bool learned = F->cnn != nullptr && precond;
   const bool use_graph = (F->opt.flags & SPP_F_GRAPHS) && !F->timer && !learned;
-  if (use_graph) factor_ready(F, st);   // (no event waits inside a capture)
+  if (use_graph) {   // (no event waits inside a capture: the factor is made complete first)
+    factor_ready(F, st);
+    factor_settled(F);
+  }
   // The first cycle starts from r = g: its first basis vector, and in eager
   // iterations the preconditioner head on it, go out before the host waits
   // for beta0.
@@ -1587,7 +1590,7 @@ int do_solve(spp_factor* F, const void* fv, int nrhs, void* uv, int32_t* iters, 
   F->stats.t_solve_ms = now_ms() - t0;
   F->last_iters_all = j;
   F->last_nrhs = nrhs;
-  factor_settled(F);   // (the solve's last synchronisation came after its wait)
+  factor_settled(F);   // (the last inverses are done by now: their buffers go back)
   if (!all_ok) {
     g_last_error = "GMRES reached max_iter before the true residual met the tolerance";
     return SPP_NOT_CONVERGED;
