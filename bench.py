@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--prec", choices=["c64", "c128"], default="c64",
                     help="front precision of the headline value")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--order", choices=["octree", "bisect"], default="octree",
+                    help="nested-dissection ordering above the leaves of the 512^2 headline (the same P^-1)")
     ap.add_argument("--graphs", action="store_true", help="replay FGMRES iterations from a HIP graph")
     ap.add_argument("--persistent", action="store_true",
                     help="cooperative launch for runs of small-front substitution levels")
@@ -392,7 +394,8 @@ def main():
 
     def options(prec, flags):
         return spp.binding.spp_options(prec=spp.SPP_C128 if prec == "c128" else spp.SPP_C64_FRONTS,
-                                       order=spp.SPP_ORDER_OCTREE, tol=args.tol, max_iter=200, flags=flags)
+                                       order=spp.SPP_ORDER_OCTREE if args.order == "octree" else spp.SPP_ORDER_BISECT,
+                                       tol=args.tol, max_iter=200, flags=flags)
 
     def step(op, rhs):
         h = spp.spp_setup(pb, op, stream)
@@ -479,7 +482,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.name, "grid": [W.n, W.n], "omega_over_2pi": 64, "b": W.b,
                    "bumps": 64, "rhs": "unit grid delta at the centre", "nrhs": 1, "tol": args.tol,
-                   "ordering": "octree", "fronts": args.prec, "outer": "f64", "graphs": args.graphs,
+                   "ordering": args.order, "fronts": args.prec, "outer": "f64", "graphs": args.graphs,
                    "persistent": args.persistent, "autotune": args.autotune},
         "gmres_iters": iters,
         "relres": relres,
