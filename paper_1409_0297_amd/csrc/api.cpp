@@ -723,7 +723,9 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
       prepare();
       int best = gemv_chunks_default(pr.rows, pr.cols, nf, nrhs, F->gpart_cap);
       float bt = 1e30f;
-      for (int c = 1; c <= std::max(1, pr.cols / 16) && c <= 256; c *= 2) {
+      // c = 0: 16-row tiles with the columns not split; c >= 1: 64-row tiles
+      // with the columns split over c workgroups.
+      for (int c = 0; c <= std::max(1, pr.cols / 16) && c <= 256; c = c ? 2 * c : 1) {
         if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
         const float t = tune_time(st, 3, [&] {
           if (F->opt.prec == SPP_C128)

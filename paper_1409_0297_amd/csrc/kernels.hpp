@@ -301,7 +301,8 @@ bool fft_lines_valid(int n, int64_t outer, int64_t inner, int L);
 std::string fft_tune_key(int n, int64_t outer, int64_t inner, int batch);
 
 // One substitution product (gemv_kernel mode) of a level of fronts with a
-// given split-K chunk count (0: tuned or heuristic); mf.hip.
+// given split-K chunk count over 64-row tiles (>= 1), or 16-row tiles with
+// the columns not split (0), or the tuned or heuristic choice (< 0); mf.hip.
 // xin: the forward input (read by mode 4, which gathers its own vector).
 template <typename R>
 void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena, void* W, void* Z, void* xout, const void* xin, int nrhs,

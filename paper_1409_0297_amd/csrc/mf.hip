@@ -1888,19 +1888,25 @@ __device__ inline cplx_t<R> gathered(const MfDev& mf, const FrontDev& f, const c
 //  mode 4: [z; w_bnd] = [Linv; -Lt] (P w_piv) + [0; w_bnd]
 //          rows [0,F), cols j < min(row, p) (+ unit diagonal for rows < p)
 //  mode 5: x(piv) = [Uinv, -Ut] [z; x(bnd)]  rows [0,p), cols [row, F)
-template <typename R, int NR>
+// RT rows per workgroup: 64 (one row per lane, the four waves splitting the
+// columns) or 16 (lanes 16 c + r take row r, sixteen column groups), the
+// narrow form giving few-front levels four times the workgroups without
+// splitting the columns.
+template <typename R, int NR, int RT>
 __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __restrict__ arena, cplx_t<R>* __restrict__ W,
                                                    cplx_t<R>* __restrict__ Z, cplx_t<R>* __restrict__ xout, int nrhs,
                                                    int r0, int f0, int mode, int nchunks, cplx_t<R>* __restrict__ partial,
                                                    int prow, const cplx_t<R>* __restrict__ xin) {
   using C = cplx_t<R>;
+  static_assert(RT == 64 || RT == 16, "row tiles of 64 or 16");
+  constexpr int CG = 256 / RT;   // column groups of a workgroup
   const FrontDev f = mf.fronts[f0 + blockIdx.y];
   const int F = f.F, p = f.p;
   const int nrows = (mode == 1) ? F - p : (mode == 4) ? F : p;
   const int chunk = blockIdx.x % nchunks;
-  const int row0 = (blockIdx.x / nchunks) * 64;
+  const int row0 = (blockIdx.x / nchunks) * RT;
   if (row0 >= nrows) return;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int lane = threadIdx.x % RT, grp = threadIdx.x / RT;   // row in the tile, column group
   const int row = row0 + lane;
   const C* A = arena + f.foff;   // first p columns, leading dimension F
   const C* U = arena + f.uoff;   // U12, leading dimension ldu
@@ -1913,7 +1919,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   C* xo = xout + I.Noff * nrhs;
   const int64_t NI = I.N;
   int jlo, jhi;
-  if (mode == 0 || mode == 4) { jlo = 0; jhi = min(p, row0 + 64); }
+  if (mode == 0 || mode == 4) { jlo = 0; jhi = min(p, row0 + RT); }
   else if (mode == 1) { jlo = 0; jhi = p; }
   else if (mode == 2) { jlo = 0; jhi = F - p; }
   else if (mode == 3) { jlo = row0; jhi = p; }
@@ -1945,7 +1951,7 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   constexpr int kPre = 8 / (NR == 4 ? 2 : 1) / (sizeof(R) == 8 ? 2 : 1);
   C apre[kPre];
 #pragma unroll
-  for (int u = 0; u < kPre; ++u) apre[u] = entry(jlo + grp + 4 * u);
+  for (int u = 0; u < kPre; ++u) apre[u] = entry(jlo + grp + CG * u);
   const int orow = ((mode == 3 || mode == 5) && live) ? idx[row] : 0;
   // Mode 4 without split: the finishing step's gathered entries of the
   // tile's rows are staged with the first tile (by the threads beyond its
@@ -1953,10 +1959,10 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
   const bool fin4 = mode == 4 && nchunks == 1;
   constexpr int kVT = 256;
   __shared__ C vs[kVT][NR];
-  __shared__ C gs[64][NR];
+  __shared__ C gs[RT][NR];
   for (int jt = jlo; jt < jhi || (fin4 && jt == jlo); jt += kVT) {
     const int jn = max(0, min(kVT, jhi - jt));
-    const int nst = jn * NR + ((fin4 && jt == jlo) ? 64 * NR : 0);
+    const int nst = jn * NR + ((fin4 && jt == jlo) ? RT * NR : 0);
     for (int t = threadIdx.x; t < nst; t += 256) {
       if (t >= jn * NR) {
         const int u = t - jn * NR, l = u / NR, r = u - l * NR, i = row0 + l;
@@ -1980,22 +1986,22 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
     if (jt == jlo) {
 #pragma unroll
       for (int u = 0; u < kPre; ++u) {
-        const int jj = grp + 4 * u;
+        const int jj = grp + CG * u;
         if (jj < jn)
 #pragma unroll
           for (int r = 0; r < NR; ++r) cfma(acc[r], apre[u], vs[jj][r]);
       }
-      jj0 = grp + 4 * kPre;
+      jj0 = grp + CG * kPre;
     }
 #pragma unroll 8
-    for (int jj = jj0; jj < jn; jj += 4) {
+    for (int jj = jj0; jj < jn; jj += CG) {
       const C a = entry(jt + jj);
 #pragma unroll
       for (int r = 0; r < NR; ++r) cfma(acc[r], a, vs[jj][r]);
     }
     __syncthreads();
   }
-  __shared__ C red[4][64][NR];
+  __shared__ C red[CG][RT][NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) red[grp][lane][r] = acc[r];
   __syncthreads();
@@ -2003,7 +2009,19 @@ __global__ void __launch_bounds__(256) gemv_kernel(MfDev mf, const cplx_t<R>* __
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r0 + r >= nrhs) break;
-    C s = cadd(cadd(red[0][lane][r], red[1][lane][r]), cadd(red[2][lane][r], red[3][lane][r]));
+    C s;
+    if constexpr (CG == 4) {
+      s = cadd(cadd(red[0][lane][r], red[1][lane][r]), cadd(red[2][lane][r], red[3][lane][r]));
+    } else {   // (pairwise, in a fixed order)
+      C h[CG / 2];
+#pragma unroll
+      for (int q = 0; q < CG / 2; ++q) h[q] = cadd(red[2 * q][lane][r], red[2 * q + 1][lane][r]);
+#pragma unroll
+      for (int w = CG / 4; w >= 1; w /= 2)
+#pragma unroll
+        for (int q = 0; q < w; ++q) h[q] = cadd(h[2 * q], h[2 * q + 1]);
+      s = h[0];
+    }
     const int rr = r0 + r;
     if (nchunks > 1) {
       partial[(((int64_t)blockIdx.y * nchunks + chunk) * prow + row) * nrhs + rr] = s;
@@ -2890,10 +2908,12 @@ void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, vo
   C* xout = static_cast<C*>(xout_v);
   const C* xin = static_cast<const C*>(xin_v);
   C* partial = static_cast<C*>(partial_v);
-  const int rtiles = (int)ceil_div(rows, 64);
-  if (nchunks <= 0)
+  if (nchunks < 0)
     nchunks = tune_get(gemv_tune_key(rows, cols, nf, mode, nrhs, (int)sizeof(C)),
                        gemv_chunks_default(rows, cols, nf, nrhs, partial_cap));
+  const bool narrow = nchunks == 0;   // (16-row tiles, columns not split)
+  const int rt = narrow ? 16 : 64;
+  const int rtiles = (int)ceil_div(rows, rt);
   nchunks = std::max(1, std::min(nchunks, std::max(1, cols)));
   while (nchunks > 1 && (int64_t)nf * nchunks * rows * nrhs > partial_cap) --nchunks;
   dim3 grid(rtiles * nchunks, nf);
@@ -2903,10 +2923,20 @@ void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, vo
   int r0 = 0;
   while (r0 < nrhs) {
     if (nrhs - r0 >= 4) {
-      gemv_kernel<R, 4><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows, xin);
+      if (narrow)
+        gemv_kernel<R, 4, 16><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows,
+                                                    xin);
+      else
+        gemv_kernel<R, 4, 64><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows,
+                                                    xin);
       r0 += 4;
     } else {
-      gemv_kernel<R, 1><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows, xin);
+      if (narrow)
+        gemv_kernel<R, 1, 16><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows,
+                                                    xin);
+      else
+        gemv_kernel<R, 1, 64><<<grid, 256, 0, st>>>(mf, arena, W, Z, xout, nrhs, r0, f0, mode, nchunks, partial, rows,
+                                                    xin);
       r0 += 1;
     }
     SPP_LAUNCH_CHECK();
@@ -2945,7 +2975,7 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
   // Row-tiled products; large fronts split their columns over several
   // workgroups (deterministic partial sums, then gemv_finish_kernel).
   auto gemv = [&](int f0, int nf, int rows, int cols, int mode, double ent) {
-    mf_gemv<R>(st, mf, arena, W, Z, xout, xin, nrhs, f0, nf, rows, cols, mode, ent, partial, partial_cap, 0);
+    mf_gemv<R>(st, mf, arena, W, Z, xout, xin, nrhs, f0, nf, rows, cols, mode, ent, partial, partial_cap, -1);
   };
   // Whole-front kernels of the levels solved with the LU in place.
   auto front = [&](int f0, int nf, int maxF, int maxP, int maxK, bool fwd, double ent) {

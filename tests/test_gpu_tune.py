@@ -48,7 +48,7 @@ def test_autotune_and_every_schedule_keep_the_solution(tmp_path, monkeypatch, na
     text = path.read_text()
     for kind in ("fft_lines@", "gemv_chunks@", "mf_form@", "mf_steps@"):
         assert kind in text, kind
-    mf_keys = []
+    mf_keys, gemv_keys = [], []
     for line in text.splitlines():
         key, value = line.split()
         if key.startswith("mf_form@"):
@@ -57,9 +57,30 @@ def test_autotune_and_every_schedule_keep_the_solution(tmp_path, monkeypatch, na
         elif key.startswith("mf_steps@"):
             assert int(value) in SCHEDULES
             mf_keys.append(key)
+        elif key.startswith("gemv_chunks@"):
+            assert int(value) >= 0   # (0: 16-row tiles, columns not split)
+            gemv_keys.append((key, int(value)))
         else:
             assert int(value) >= 1
         assert binding.spp_tune_get(key) == int(value)
+    # Every product shape of the substitution on 16-row tiles, then on 64-row
+    # tiles without a column split, then split in two: the same solution.
+    try:
+        for c in (0, 1, 2):
+            for key, _ in gemv_keys:
+                binding.spp_tune_set(key, c)
+            C = Solver(W.kind, W.n, W.d, W.b, W.coeff, **kw)
+            uc, ic, rc, cc = C.solve(W.rhs)
+            C.close()
+            torch.cuda.synchronize()
+            assert cc == 0, c
+            assert all(abs(x - y) <= 1 for x, y in zip(ic, ib)), (c, ic, ib)
+            e = rel(uc, ub)
+            print(f"{name}: substitution chunks {c}: iterations {ic}, vs untuned {e:.1e}")
+            assert e <= 1e-9, (c, e)
+    finally:
+        for key, v in gemv_keys:
+            binding.spp_tune_set(key, v)
     # Every candidate the tuner times is a valid factorisation: force each
     # schedule and solve form on every level and compare with the untuned
     # solution (same tolerance, so equal to roundoff times the conditioning).
