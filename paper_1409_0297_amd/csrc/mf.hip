@@ -453,9 +453,6 @@ struct DiagLds {
   cplx_t<R> D[kDB][kDB + 1];    // the block to factor
   cplx_t<R> Lm[kDB][kDB + 1];   // the previous step's L part (rows of this block)
   cplx_t<R> X[kDB][kDB + 1];    // the LU in pivot order
-  cplx_t<R> lbuf[2][kDB];       // each row's multiplier of an elimination step
-  int rpbuf[2];                 // the step's pivot row
-  int kofr[kDB];                // step at which each row became the pivot
   int rsel[kDB];                // pivot row of each step
 };
 
@@ -506,106 +503,134 @@ __device__ __forceinline__ double pos_recip(double x) { return x > 0.0 ? 1.0 / x
 // patterns are compared as integers: they order like the values for x >= 0,
 // -1 is below all of them, and a NaN is above every number, so a NaN entry
 // is the one chosen (and then reported).
+// (B = 32: the same over lanes 32 .. 63.)
+template <int B = 0>
 __device__ __forceinline__ float rows_max(float v) {
   int m = __float_as_int(v);
   m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x121, 0xF, 0xF, false));
   m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x122, 0xF, 0xF, false));
   m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x124, 0xF, 0xF, false));
   m = max(m, __builtin_amdgcn_update_dpp(0, m, 0x128, 0xF, 0xF, false));
-  return __int_as_float(max(__builtin_amdgcn_readlane(m, 0), __builtin_amdgcn_readlane(m, 16)));
+  return __int_as_float(max(__builtin_amdgcn_readlane(m, B), __builtin_amdgcn_readlane(m, B + 16)));
 }
+template <int B = 0>
 __device__ __forceinline__ double rows_max(double v) {
   auto mx = [](double a, double b) { return (a > b || a != a) ? a : b; };
   v = mx(v, row_ror<1>(v));
   v = mx(v, row_ror<2>(v));
   v = mx(v, row_ror<4>(v));
   v = mx(v, row_ror<8>(v));
-  return mx(lane_read(v, 0), lane_read(v, 16));
+  return mx(lane_read(v, B), lane_read(v, B + 16));
 }
 
-// Slot S (column 4 S + w) of step J of wg_lu32 in wave w: a_S -= l * (pivot
-// row)_S for the columns right of J, the pivot row's entry read from its lane
-// (l is zero on the rows not to eliminate).
-template <typename R, int J, int S>
-__device__ __forceinline__ void wg_lu_slot(cplx_t<R> (&a)[kDB / 4], cplx_t<R> l, int rp, int w) {
-  if constexpr (4 * S + 3 > J) {
-    if (4 * S > J || 4 * S + w > J) cfms4(a[S], l, lane_read(a[S], rp));
-  }
+// Value of lane src for each lane (src may differ between lanes; through
+// the LDS crossbar, no LDS memory).
+__device__ inline float lane_gather(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
 }
-template <typename R, int J, int... S>
-__device__ __forceinline__ void wg_lu_update(std::integer_sequence<int, S...>, cplx_t<R> (&a)[kDB / 4], cplx_t<R> l,
-                                             int rp, int w) {
-  (wg_lu_slot<R, J, S>(a, l, rp, w), ...);
+__device__ inline double lane_gather(double x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+template <typename C> __device__ inline C lane_gather(C x, int src) {
+  return cmake<C>(lane_gather(x.x, src), lane_gather(x.y, src));
 }
 
-// Step J of wg_lu32.  The wave owning column J picks the pivot, posts every
-// row's multiplier and the pivot row, and keeps the multipliers in column J;
-// after the barrier every wave eliminates its own columns right of J.
-template <typename R, int J>
-__device__ __forceinline__ void wg_lu_step(cplx_t<R> (&a)[kDB / 4], DiagLds<R>& S, int w, int lane, int r, int kb,
-                                           bool& done, bool& bad) {
+// One wave factors the 32 x 32 block (wave_lu32): lane r holds columns
+// 0, 2, .. 30 of row r and lane r + 32 columns 1, 3, .. 31 of the same row,
+// slot q of a lane being column 2 q + h (h = lane / 32).
+//
+// Slot Q of step J: a_Q -= l * (pivot row)_Q on the columns right of J.  The
+// slot of column J + 1, which the next pivot search waits for, reads the
+// pivot row's entries by scalar reads; the others by lane gathers, all of
+// a step's gathers issued before the first of its products (wave_lu_fetch),
+// so that their latencies overlap.
+template <typename R, int J, int Q>
+__device__ __forceinline__ void wave_lu_fetch(cplx_t<R> (&g)[kDB / 2], const cplx_t<R> (&a)[kDB / 2], int src) {
+  if constexpr (2 * Q + 1 > J && Q != (J + 1) / 2) g[Q] = lane_gather(a[Q], src);
+}
+template <typename R, int J, int Q>
+__device__ __forceinline__ void wave_lu_slot(cplx_t<R> (&a)[kDB / 2], const cplx_t<R> (&g)[kDB / 2], cplx_t<R> l,
+                                             int rp, bool hi) {
   using C = cplx_t<R>;
-  constexpr int owner = J & 3, js = J >> 2, b = J & 1;
-  C le = cmake<C>(0, 0);
-  if (w == owner) {
-    const C dj = a[js];
-    const R v2 = done ? R(-1) : cabs2(dj);
-    const R m = rows_max(v2);
-    // Equal bit patterns: exact ties go to the lowest row, a NaN maximum matches itself.
-    const unsigned hit = (unsigned)__builtin_amdgcn_ballot_w64(!done && memcmp_eq(v2, m));
-    const unsigned live = (unsigned)__builtin_amdgcn_ballot_w64(!done);
-    const int rp = __builtin_ctz(hit ? hit : live);
-    bad = bad | ((J < kb) & !(m > R(0) && m <= std::numeric_limits<R>::max()));
-    const C pv = lane_read(dj, rp);
-    const R inv = pos_recip(cabs2(pv));
-    const bool upd = !done && r != rp;
-    const C l = cmul(dj, cmake<C>(pv.x * inv, -pv.y * inv));
-    le = csel(upd, l, cmake<C>(0, 0));
-    a[js] = csel(upd, l, a[js]);
-    if (lane < 32) S.lbuf[b][r] = le;
-    if (lane == 0) {
-      S.rpbuf[b] = rp;
-      S.kofr[rp] = J;
-      S.rsel[J] = rp;
+  if constexpr (2 * Q + 1 > J) {
+    C pv;
+    if constexpr (Q == (J + 1) / 2) {
+      if constexpr (2 * Q == J) pv = lane_read(a[Q], rp + 32);   // (only column 2 Q + 1 = J + 1 moves)
+      else pv = csel(hi, lane_read(a[Q], rp + 32), lane_read(a[Q], rp));
+    } else {
+      pv = g[Q];
     }
+    C t = a[Q];
+    cfms4(t, l, pv);
+    a[Q] = (2 * Q == J) ? csel(hi, t, a[Q]) : t;
   }
-  __syncthreads();
-  const C lb = S.lbuf[b][r];                          // both reads issued together
-  const int rp = __builtin_amdgcn_readfirstlane(S.rpbuf[b]);
-  if (w != owner) le = lb;
+}
+
+// Step J: the remaining row of largest |d_rJ|^2 becomes the pivot (exact
+// ties to the lowest row, a NaN maximum matches itself); every other
+// remaining row keeps its multiplier in column J and eliminates column J
+// from its columns right of J.  Column J sits in the half H = J % 2; the
+// other half takes each row's d_rJ by a lane gather (during the search) and
+// forms the same multiplier.
+template <typename R, int J, int... Q>
+__device__ __forceinline__ void wave_lu_step(std::integer_sequence<int, Q...>, cplx_t<R> (&a)[kDB / 2], int r,
+                                             bool hi, int kb, bool& done, bool& bad, int& mystep) {
+  using C = cplx_t<R>;
+  constexpr int H = J & 1, QJ = J >> 1;
+  const bool mine = hi == (H == 1);
+  const C dj = a[QJ];
+  const C drj = lane_gather(dj, r + 32 * H);   // d_rJ in both halves
+  const R v2 = (done || !mine) ? R(-1) : cabs2(dj);
+  const R m = rows_max<32 * H>(v2);
+  const unsigned hit = (unsigned)(__builtin_amdgcn_ballot_w64(mine && !done && memcmp_eq(v2, m)) >> (32 * H));
+  const unsigned live = (unsigned)(__builtin_amdgcn_ballot_w64(mine && !done) >> (32 * H));
+  const int rp = __builtin_ctz(hit ? hit : live);
+  bad = bad | ((J < kb) & !(m > R(0) && m <= std::numeric_limits<R>::max()));
+  const C pv = lane_read(dj, rp + 32 * H);
+  const R inv = pos_recip(cabs2(pv));
+  const bool upd = !done && r != rp;
+  const C l = cmul(drj, cmake<C>(pv.x * inv, -pv.y * inv));
+  const C le = csel(upd, l, cmake<C>(0, 0));
+  if (mine) a[QJ] = csel(upd, l, a[QJ]);
+  mystep = r == rp ? J : mystep;
   done = done || r == rp;
-  wg_lu_update<R, J>(std::make_integer_sequence<int, kDB / 4>{}, a, le, rp, w);
+  C g[kDB / 2];
+  (wave_lu_fetch<R, J, Q>(g, a, rp + (hi ? 32 : 0)), ...);
+  (wave_lu_slot<R, J, Q>(a, g, le, rp, hi), ...);
 }
 
 template <typename R, int... J>
-__device__ __forceinline__ void wg_lu_steps(std::integer_sequence<int, J...>, cplx_t<R> (&a)[kDB / 4], DiagLds<R>& S,
-                                            int w, int lane, int r, int kb, bool& done, bool& bad) {
-  (wg_lu_step<R, J>(a, S, w, lane, r, kb, done, bad), ...);
+__device__ __forceinline__ void wave_lu_steps(std::integer_sequence<int, J...>, cplx_t<R> (&a)[kDB / 2], int r,
+                                              bool hi, int kb, bool& done, bool& bad, int& mystep) {
+  (wave_lu_step<R, J>(std::make_integer_sequence<int, kDB / 2>{}, a, r, hi, kb, done, bad, mystep), ...);
 }
 
-// LU with row pivoting of the 32 x 32 block S.D by the four waves of the
-// workgroup: wave w keeps the columns 4 s + w (s < 8) of every row, lane r
-// (and its twin r + 32, which repeats the work) holding row r.  Step j takes
-// as pivot the remaining row of largest |d_rj|^2 (ties to the lowest row) and
-// eliminates column j from the other remaining rows; each row keeps its
-// multipliers in place, so the row chosen at step k ends as row k of the LU
-// in pivot order: L left of column k, U from column k on.  Writes that LU to
-// S.X and the chosen rows to S.rsel; returns true (in the waves that owned
-// such a step) if a pivot among the first kb was zero or not finite.
+// LU with row pivoting of the 32 x 32 block S.D by the first wave of the
+// workgroup alone (no barrier between steps).  Step j takes as pivot the
+// remaining row of largest |d_rj|^2 and eliminates column j from the other
+// remaining rows; each row keeps its multipliers in place, so the row chosen
+// at step k ends as row k of the LU in pivot order: L left of column k, U
+// from column k on.  Writes that LU to S.X and the chosen rows to S.rsel
+// (the other waves go straight to the caller's barrier, after which both
+// may be read); returns true in the first wave if a pivot among the first
+// kb was zero or not finite.
 template <typename R>
-__device__ __forceinline__ bool wg_lu32(DiagLds<R>& S, int kb) {
+__device__ __forceinline__ bool wave_lu32(DiagLds<R>& S, int kb) {
   using C = cplx_t<R>;
-  const int lane = threadIdx.x & 63, r = lane & 31, w = threadIdx.x >> 6;
-  C a[kDB / 4];
+  if (threadIdx.x >= 64) return false;
+  const int lane = threadIdx.x, r = lane & 31;
+  const bool hi = lane >= 32;
+  C a[kDB / 2];
 #pragma unroll
-  for (int s = 0; s < kDB / 4; ++s) a[s] = S.D[r][4 * s + w];
+  for (int q = 0; q < kDB / 2; ++q) a[q] = S.D[r][2 * q + (hi ? 1 : 0)];
   bool done = false, bad = false;
-  wg_lu_steps<R>(std::make_integer_sequence<int, kDB>{}, a, S, w, lane, r, kb, done, bad);
-  const int kr = S.kofr[r];
-  if (lane < 32) {
+  int mystep = 0;   // the step at which row r became the pivot
+  wave_lu_steps<R>(std::make_integer_sequence<int, kDB>{}, a, r, hi, kb, done, bad, mystep);
 #pragma unroll
-    for (int s = 0; s < kDB / 4; ++s) S.X[kr][4 * s + w] = a[s];
-  }
+  for (int q = 0; q < kDB / 2; ++q) S.X[mystep][2 * q + (hi ? 1 : 0)] = a[q];
+  if (!hi) S.rsel[mystep] = r;   // (every row is the pivot of exactly one step)
   return bad;
 }
 
@@ -713,6 +738,7 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
   auto& X = S.X;
   auto& rsel = S.rsel;
   const int tid = threadIdx.x;
+  const float fn = __uint_as_float(mf.fnorm[fi]);   // (read here, used after the LU)
   if (kprev >= 0 && !fused) {
     const C* base = arena + f.off;
     for (int t = tid; t < kDB * kDB; t += 256) {
@@ -728,22 +754,33 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     const C* Up = Lp + kDB * kDB;
     const int* pr = mf.prow + f.perm + kprev;                               // front rows, pivot order
     // (U_prev^{-1} is loaded with the rest and kept in registers until D is
-    // free again, so the second product does not wait on memory)
+    // free again, so the second product does not wait on memory; the block's
+    // own entries come in with them, each lane taking those of its place in
+    // the last product's output)
+    // (each thread's pivot row goes out first: its loads wait on it, and the
+    // memory counter waits in issue order)
+    const int pri = pr[tid & (kDB - 1)];
+    using V = typename Acc<R>::type;
+    const int w = tid >> 6, lane = tid & 63, ba = 16 * (w % 2), bb = 16 * (w / 2);
+    C akk[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ba + (lane & 15), col = bb + mfma_row(R(0), lane, r);
+      akk[r] = (row < kb && col < kb) ? A[(int64_t)col * F + row] : cmake<C>(row == col ? 1 : 0, 0);
+    }
     constexpr int kPer = kDB * kDB / 256;
     C up[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int t = tid + 256 * u, c = t / kDB, i = t - c * kDB;
       Lm[i][c] = (i < kb) ? base[(int64_t)(kprev + c) * F + k0 + i] : cmake<C>(0, 0);   // A(k, prev)
-      X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + pr[i]] : cmake<C>(0, 0);      // (P A)(prev, k)
+      X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + pri] : cmake<C>(0, 0);        // (P A)(prev, k), i = tid % 32
       D[i][c] = Lp[c * kDB + i];
       up[u] = Up[c * kDB + i];
     }
     __syncthreads();
     // U(prev, k) = L_prev^{-1} X and L(k, prev) = A(k, prev) U_prev^{-1}: wave
     // w forms the 16 x 16 block (w % 2, w / 2) of each on MFMA.
-    using V = typename Acc<R>::type;
-    const int w = tid >> 6, lane = tid & 63, ba = 16 * (w % 2), bb = 16 * (w / 2);
     V ure = {}, uim = {}, lre = {}, lim = {};
     mfma_block16<R>(ure, uim, kDB, [&](int r, int k) { return D[ba + r][k]; },
                     [&](int k, int c) { return X[k][bb + c]; });
@@ -764,22 +801,35 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
       Lm[row][col] = cmake<C>(lre[r], lim[r]);
     }
     __syncthreads();
+    // A_kk - L(k, prev) U(prev, k), block (w % 2, w / 2) of wave w on MFMA
+    // (rows and columns past kb keep the identity: L and U are zero there).
+    V dre = {}, dim = {};
+    mfma_block16<R>(dre, dim, kDB, [&](int r, int k) { return Lm[ba + r][k]; },
+                    [&](int k, int c) { return X[k][bb + c]; });
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ba + (lane & 15), col = bb + mfma_row(R(0), lane, r);
+      D[row][col] = cmake<C>(akk[r].x - dre[r], akk[r].y - dim[r]);
+    }
+    __syncthreads();
   }
   // The block is padded to 32 x 32 with the identity so that every step is
   // uniform.  Rows stay where they are (physical order); the pivot chosen at
   // step j is recorded in rsel[j] and the LU is written back in pivot order.
-  for (int t = tid; t < kDB * kDB; t += 256) {
-    const int c = t / kDB, i = t - c * kDB;
-    C v = cmake<C>(i == c ? 1 : 0, 0);
-    if (i < kb && c < kb) {
-      v = A[(int64_t)c * F + i];
-      if (kprev >= 0)
-        for (int u = 0; u < kDB; ++u) cfms(v, Lm[i][u], X[u][c]);
+  if (!(kprev >= 0 && fused)) {
+    for (int t = tid; t < kDB * kDB; t += 256) {
+      const int c = t / kDB, i = t - c * kDB;
+      C v = cmake<C>(i == c ? 1 : 0, 0);
+      if (i < kb && c < kb) {
+        v = A[(int64_t)c * F + i];
+        if (kprev >= 0)
+          for (int u = 0; u < kDB; ++u) cfms(v, Lm[i][u], X[u][c]);
+      }
+      D[i][c] = v;
     }
-    D[i][c] = v;
+    __syncthreads();
   }
-  __syncthreads();
-  if (wg_lu32<R>(S, kb) && (tid & 63) == 0) atomicCAS(mf.info, 0, fi + 1);
+  if (wave_lu32<R>(S, kb) && tid == 0) atomicCAS(mf.info, 0, fi + 1);
   __syncthreads();
   // Block-local pivoting keeps every interchange inside the block, so the
   // row order is also the block's part of the front's final permutation.
@@ -792,7 +842,6 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
   // front + 1, info[10] = 1); one below piv_warn (1e3 eps of the front
   // precision) is counted in info[9]; the block's largest entry before and
   // after its LU feeds the growth statistic.
-  const float fn = __uint_as_float(mf.fnorm[fi]);
   float gmax = 0.f;
   for (int t = tid; t < kDB * kDB; t += 256) {
     const int c = t / kDB, i = t - c * kDB;
@@ -1420,50 +1469,47 @@ __device__ inline void fused_tile(const MfDev& mf, cplx_t<R>* __restrict__ arena
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   auto& Lt = L.Lt;
   auto& Ut = L.Ut;
+  // Loads in the order their waits come (the memory counter waits in issue
+  // order): each thread's pivot row of the P A12 strip, the strips, the
+  // inverse entries; the trailing tile C right after the products (before
+  // their write-back and barrier).
+  // On MFMA, wave w: L21 rows 16 w .. 16 w + 15 (all 32 columns u, two
+  // blocks) = A21 Uinv, and U12 columns 16 w .. 16 w + 15 (all 32 rows u) =
+  // Linv (P A12).  The inverses' entries come from global memory (a few KB);
+  // outside [0, kb) they are not written by the block LU, so the operands
+  // are masked there (A21 and P A12 are zero beyond kb).
+  const int pru = (tid & (kDB - 1)) < kb ? pr[tid & (kDB - 1)] : 0;
+  // (A21 by rows of a column, P A12 by pivot rows of a column: the rows
+  // pr[u] of the block are a permutation of 32 consecutive rows, so either
+  // way a wave reads whole column segments; u = tid % 32 in every pass)
   for (int t = tid; t < kDB * kBM; t += 256) {
     const int v = t / kBM, r = t - v * kBM;
     Lt[v][r] = (v < kb && r < mt) ? base[(int64_t)(k0 + v) * F + k1 + m0 + r] : cmake<C>(0, 0);   // A21
-    Ut[v][r] = (v < kb && r < nt) ? base[(int64_t)(k1 + n0 + r) * F + pr[v]] : cmake<C>(0, 0);     // P A12
+    const int c = t / kDB, u = t - c * kDB;
+    Ut[u][c] = (u < kb && c < nt) ? base[(int64_t)(k1 + n0 + c) * F + pru] : cmake<C>(0, 0);       // P A12
   }
-  __syncthreads();
-  // On MFMA, wave w: L21 rows 16 w .. 16 w + 15 (all 32 columns u, two
-  // blocks) = A21 Uinv, and U12 columns 16 w .. 16 w + 15 (all 32 rows u) =
-  // Linv (P A12).  The inverses' entries come from global memory (a few KB,
-  // cache-resident); outside [0, kb) they are not written by the block LU,
-  // so the operands are masked there (A21 and P A12 are zero beyond kb).
-  // (each lane's inverse entries of a block are loaded together before its
-  // MFMA chain, so their latencies overlap)
-  using Vt = typename Acc<R>::type;
-  Vt lre[2] = {}, lim[2] = {}, ure[2] = {}, uim[2] = {};
   const int li = lane & 15, lk = lane >> 4;
+  C uv[2][kDB / 4], lv[2][kDB / 4];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int u = 16 * b + li;
-    C uv[kDB / 4], lv[kDB / 4];
 #pragma unroll
     for (int t = 0; t < kDB / 4; ++t) {
       const int k = 4 * t + lk;
-      uv[t] = (k < kb && u < kb) ? Ui[u * kDB + k] : cmake<C>(0, 0);   // Uinv(k, u)
-      lv[t] = (k < kb && u < kb) ? Li[k * kDB + u] : cmake<C>(0, 0);   // Linv(u, k)
+      uv[b][t] = (k < kb && u < kb) ? Ui[u * kDB + k] : cmake<C>(0, 0);   // Uinv(k, u)
+      lv[b][t] = (k < kb && u < kb) ? Li[k * kDB + u] : cmake<C>(0, 0);   // Linv(u, k)
     }
-    mfma_block16<R>(lre[b], lim[b], kDB, [&](int r, int k) { return Lt[k][16 * w + r]; },
-                    [&](int k, int) { return uv[k >> 2]; });
-    mfma_block16<R>(ure[b], uim[b], kDB, [&](int, int k) { return lv[k >> 2]; },
-                    [&](int k, int c) { return Ut[k][16 * w + c]; });
   }
   __syncthreads();
+  using Vt = typename Acc<R>::type;
+  Vt lre[2] = {}, lim[2] = {}, ure[2] = {}, uim[2] = {};
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = lane & 15, j = mfma_row(R(0), lane, r);
-      Lt[16 * b + j][16 * w + i] = cmake<C>(-lre[b][r], -lim[b][r]);   // L21(16 w + i, 16 b + j), negated
-      Ut[16 * b + i][16 * w + j] = cmake<C>(ure[b][r], uim[b][r]);     // U12(16 b + i, 16 w + j)
-    }
-  __syncthreads();
-  // C -= L21 U12 over k < 32 (entries past kb are 0), waves of 32 x 32 as in
-  // gemm_tile_core: B takes the MFMA's first operand, lanes of one output
-  // column hold 16 consecutive rows.
+  for (int b = 0; b < 2; ++b) {
+    mfma_block16<R>(lre[b], lim[b], kDB, [&](int r, int k) { return Lt[k][16 * w + r]; },
+                    [&](int k, int) { return uv[b][k >> 2]; });
+    mfma_block16<R>(ure[b], uim[b], kDB, [&](int, int k) { return lv[b][k >> 2]; },
+                    [&](int k, int c) { return Ut[k][16 * w + c]; });
+  }
   const int wm = (w % 2) * 32, wn = (w / 2) * 32;
   C* __restrict__ Ct = base + (int64_t)(k1 + n0) * F + k1 + m0;
   V re[2][2], im[2][2];
@@ -1480,6 +1526,20 @@ __device__ inline void fused_tile(const MfDev& mf, cplx_t<R>* __restrict__ arena
         re[a][b][r] = c0.x;
         im[a][b][r] = c0.y;
       }
+  // (wave w has read and now writes only the columns 16 w .. 16 w + 15 of
+  // Lt and Ut, so no barrier is needed before these stores)
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lane & 15, j = mfma_row(R(0), lane, r);
+      Lt[16 * b + j][16 * w + i] = cmake<C>(-lre[b][r], -lim[b][r]);   // L21(16 w + i, 16 b + j), negated
+      Ut[16 * b + i][16 * w + j] = cmake<C>(ure[b][r], uim[b][r]);     // U12(16 b + i, 16 w + j)
+    }
+  __syncthreads();
+  // C -= L21 U12 over k < 32 (entries past kb are 0), waves of 32 x 32 as in
+  // gemm_tile_core: B takes the MFMA's first operand, lanes of one output
+  // column hold 16 consecutive rows.
 #pragma unroll
   for (int kk = 0; kk < kDB; kk += 4) {
     C av[2], bv[2];
