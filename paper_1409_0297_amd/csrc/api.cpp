@@ -1005,6 +1005,19 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     }
     if (tune_fac) F->xwork_elems = std::max(F->xwork_elems, xwork_all);
   }
+  const bool streamed = P.storage == 1;
+  F->arena = F->big_alloc((size_t)P.arena_elems * F->csize);
+  // A resident arena from the library's own memory (no pending user of it)
+  // is zeroed on the side stream at once, before any other work of the setup
+  // is queued, so that the fill runs beside the coefficient and stencil work.
+  bool arena_zero_ahead = false;
+  if (!streamed && !F->opt.alloc) {
+    hipStream_t zs = side_stream();
+    if (!F->zero_event) SPP_HIP(hipEventCreateWithFlags(&F->zero_event, hipEventDisableTiming));
+    SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, zs));
+    SPP_HIP(hipEventRecord(F->zero_event, zs));
+    arena_zero_ahead = true;
+  }
   F->q = F->dalloc<double>(F->Ntot);
   F->sigma = F->dalloc<double>(F->Ntot);
   for (SppInstance& I : F->inst) {
@@ -1039,7 +1052,39 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   double2* sig2_c = F->dalloc<double2>(Gmax);
   double2* g = F->dalloc<double2>(Gmax);
   double2* g2 = F->dalloc<double2>(Gmax);
+  // Device descriptors of the instances and their stencil buffers, uploaded
+  // before any work is queued, so that the host goes from queuing the
+  // stencil work straight to the factorisation.
   std::vector<InstDev> idev(count);
+  for (int i = 0; i < count; ++i) {
+    SppInstance& I = F->inst[i];
+    InstDev& D = idev[i];
+    // (the device side indexes stencil sets: boxes of the set width bs)
+    D.d = I.d; D.n = I.n; D.b = I.bs; D.m = I.n / I.bs; D.N = I.N; D.Noff = I.Noff; D.q = F->q + I.Noff;
+    D.nc = I.nc;
+    D.npts = I.npts;
+    const size_t ntypes = I.plan->types.size();
+    for (size_t t = 0; t < ntypes; ++t) {
+      const SetType& T = I.plan->types[t];
+      StencilDev& S = I.sten[t];
+      // (sizes in unknowns: nc per point, point-major; offsets per point)
+      S.nS = T.nS * I.nc; S.nB = T.nB * I.nc; S.nG = T.nG * I.nc;
+      S.off = F->pd->type_off[i * ntypes + t];
+      S.T = F->dalloc<double2>((size_t)S.nS * S.nB);
+      S.C = F->dalloc<double2>((size_t)S.nS * S.nG);
+      S.Tt = F->dalloc<double2>((size_t)S.nS * S.nB);
+      S.Ct = F->dalloc<double2>((size_t)S.nS * S.nG);
+      D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
+    }
+  }
+  F->inst_dev = F->dalloc<InstDev>(count);
+  SPP_HIP(hipMemcpyAsync(F->inst_dev, idev.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, st));
+  MfDev& mf = F->mf;
+  mf.perm = F->dalloc<int>(F->pd->perm_total);
+  mf.ipiv = F->dalloc<int>(F->pd->perm_total);
+  mf.prow = F->dalloc<int>(F->pd->perm_total);
+  mf.fnorm = F->dalloc<unsigned>(P.fronts.size());
+  mf.pstat = F->dalloc<unsigned>(2);
   for (int i = 0; i < count; ++i) {
     SppInstance& I = F->inst[i];
     const spp_problem& pb = pbs[i];
@@ -1073,31 +1118,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       fft_inverse_all(st, sig2_c + ab * I.npts, g2 + ab * I.npts, I.tw, I.d, I.n);
     }
     // a3-a4: stencils per set type.
-    InstDev& D = idev[i];
-    // (the device side indexes stencil sets: boxes of the set width bs)
-    D.d = I.d; D.n = I.n; D.b = I.bs; D.m = I.n / I.bs; D.N = I.N; D.Noff = I.Noff; D.q = F->q + I.Noff;
-    D.nc = I.nc;
-    D.npts = I.npts;
-    const size_t ntypes = I.plan->types.size();
-    for (size_t t = 0; t < ntypes; ++t) {
-      const SetType& T = I.plan->types[t];
-      StencilDev& S = I.sten[t];
-      // (sizes in unknowns: nc per point, point-major; offsets per point)
-      S.nS = T.nS * I.nc; S.nB = T.nB * I.nc; S.nG = T.nG * I.nc;
-      S.off = F->pd->type_off[i * ntypes + t];
-      S.T = F->dalloc<double2>((size_t)S.nS * S.nB);
-      S.C = F->dalloc<double2>((size_t)S.nS * S.nG);
-      S.Tt = F->dalloc<double2>((size_t)S.nS * S.nB);
-      S.Ct = F->dalloc<double2>((size_t)S.nS * S.nG);
-      D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
-    }
-    stencil_build(st, I.d, I.n, g, g2, I.sten, (int)ntypes, swork, info + 1, I.nc);
+    stencil_build(st, I.d, I.n, g, g2, I.sten, (int)I.plan->types.size(), swork, info + 1, I.nc);
   }
-  F->inst_dev = F->dalloc<InstDev>(count);
-  SPP_HIP(hipMemcpyAsync(F->inst_dev, idev.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, st));
 
   // a5-a6: assembly and factorisation on the shared plan.
-  MfDev& mf = F->mf;
   mf.fronts = F->pd->fronts;
   mf.blocks = F->pd->blocks;
   mf.pos = F->pd->pos;
@@ -1105,18 +1129,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   mf.map = F->pd->map;
   mf.gptr = F->pd->gptr;
   mf.gsrc = F->pd->gsrc;
-  mf.perm = F->dalloc<int>(F->pd->perm_total);
-  mf.ipiv = F->dalloc<int>(F->pd->perm_total);
-  mf.prow = F->dalloc<int>(F->pd->perm_total);
   mf.info = info;
-  mf.fnorm = F->dalloc<unsigned>(P.fronts.size());
-  mf.pstat = F->dalloc<unsigned>(2);
   mf.piv_tol = 1e3f * (float)std::numeric_limits<double>::epsilon();
   mf.piv_warn = 1e3f * (op->prec == SPP_C128 ? (float)std::numeric_limits<double>::epsilon()
                                               : std::numeric_limits<float>::epsilon());
-  SPP_HIP(hipMemsetAsync(mf.fnorm, 0, sizeof(unsigned) * P.fronts.size(), st));
-  SPP_HIP(hipMemsetAsync(mf.pstat, 0, sizeof(unsigned), st));
-  SPP_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(mf.pstat + 1), 0x7f7fffff, 1, st));
   mf.inst = F->inst_dev;
   mf.ninst = count;
   mf.d = pbs[0].dim;
@@ -1141,18 +1157,6 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   for (int form : F->level_form) any_blocked = any_blocked || form == kFormBlocked;
   const bool partial_pivoting = (F->opt.flags & SPP_F_PARTIAL_PIVOTING) != 0;
 
-  const bool streamed = P.storage == 1;
-  F->arena = F->big_alloc((size_t)P.arena_elems * F->csize);
-  // A resident arena from the library's own memory (no pending user of it)
-  // is zeroed on the side stream at once, beside the stencil work.
-  bool arena_zero_ahead = false;
-  if (!streamed && !F->opt.alloc) {
-    hipStream_t zs = side_stream();
-    if (!F->zero_event) SPP_HIP(hipEventCreateWithFlags(&F->zero_event, hipEventDisableTiming));
-    SPP_HIP(hipMemsetAsync(F->arena, 0, (size_t)P.arena_elems * F->csize, zs));
-    SPP_HIP(hipEventRecord(F->zero_event, zs));
-    arena_zero_ahead = true;
-  }
   if (streamed) F->fstore = F->big_alloc((size_t)P.fstore_elems * F->csize);
   F->fac = streamed ? F->fstore : F->arena;
   void* xwork = F->dalloc<char>((size_t)F->xwork_elems * F->csize);
@@ -1184,11 +1188,9 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   // on the side stream (see factor_ready).
   bool defer_inverses = false;
   auto factor_all = [&](const std::vector<int>& forms, const std::vector<int>& vars, hipEvent_t* fev) {
-    SPP_HIP(hipMemsetAsync(info, 0, sizeof(int), st));           // breakdown front
-    SPP_HIP(hipMemsetAsync(mf.fnorm, 0, sizeof(unsigned) * P.fronts.size(), st));
-    SPP_HIP(hipMemsetAsync(info + 9, 0, 2 * sizeof(int), st));   // small pivots, fatal flag
-    SPP_HIP(hipMemsetAsync(mf.pstat, 0, sizeof(unsigned), st));
-    SPP_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(mf.pstat + 1), 0x7f7fffff, 1, st));
+    // (breakdown front, small pivots, fatal flag, pivot statistics and the
+    // fronts' largest entries, in one launch)
+    mf_reset_status(st, mf, static_cast<int>(P.fronts.size()));
     if (arena_zero_ahead) {
       SPP_HIP(hipStreamWaitEvent(st, F->zero_event, 0));
       arena_zero_ahead = false;

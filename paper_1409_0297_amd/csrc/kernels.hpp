@@ -300,6 +300,12 @@ int fft_lines_default(int n, int64_t outer, int64_t inner);
 bool fft_lines_valid(int n, int64_t outer, int64_t inner, int L);
 std::string fft_tune_key(int n, int64_t outer, int64_t inner, int batch);
 
+// Clears the status words of a factorisation pass: info[0] (breakdown
+// front), info[9] and info[10] (small pivots, fatal flag), the pivot
+// statistics (largest growth 0, smallest pivot ratio FLT_MAX) and the
+// largest entry of each of the nfronts fronts; one launch (mf.hip).
+void mf_reset_status(hipStream_t st, const MfDev& mf, int nfronts);
+
 // One substitution product (gemv_kernel mode) of a level of fronts with a
 // given split-K chunk count over 64-row tiles (>= 1), or 16-row tiles with
 // the columns not split (0), or the tuned or heuristic choice (< 0); mf.hip.

@@ -2951,6 +2951,25 @@ int gemv_chunks_default(int rows, int cols, int nf, int nrhs, int64_t partial_ca
   return nchunks;
 }
 
+namespace {
+__global__ void reset_status_kernel(MfDev mf, int nfronts) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nfronts) mf.fnorm[t] = 0u;
+  if (t == 0) {
+    mf.info[0] = 0;
+    mf.info[9] = 0;
+    mf.info[10] = 0;
+    mf.pstat[0] = 0u;            // largest growth
+    mf.pstat[1] = 0x7f7fffffu;   // smallest pivot ratio: FLT_MAX
+  }
+}
+}  // namespace
+
+void mf_reset_status(hipStream_t st, const MfDev& mf, int nfronts) {
+  reset_status_kernel<<<(unsigned)ceil_div(std::max(nfronts, 1), 256), 256, 0, st>>>(mf, nfronts);
+  SPP_LAUNCH_CHECK();
+}
+
 std::string gemv_tune_key(int rows, int cols, int nf, int mode, int nrhs, int csize) {
   return tune_key("gemv_chunks", {rows, cols, nf, mode, nrhs, csize});
 }
