@@ -343,7 +343,7 @@ struct spp_factor {
   hipStream_t gstream = nullptr;
   // Level inverses beside the next level's LU: one event marks a level's LU,
   // the other the end of the inverse work.
-  hipEvent_t inv_event[2] = {nullptr, nullptr};
+  hipEvent_t inv_event[3] = {nullptr, nullptr, nullptr};
   hipEvent_t zero_event = nullptr;   // the arena's zeroing on the side stream
   // The last level's inverses may still run on the side stream when setup
   // returns (inv_event[1] marks their end): every use of the factor waits
@@ -377,13 +377,15 @@ struct spp_factor {
     allocs.push_back({p, bytes});
     return static_cast<T*>(p);
   }
-  void dfree(void* p) {
+  // idle: the caller has already waited for every queued use of p (else the
+  // whole device is drained first).
+  void dfree(void* p, bool idle = false) {
     if (!p) return;
     auto it = std::find_if(allocs.begin(), allocs.end(), [&](const std::pair<void*, size_t>& a) { return a.first == p; });
     if (it == allocs.end()) return;
     const size_t bytes = it->second;
     allocs.erase(it);
-    (void)hipDeviceSynchronize();   // (nothing queued may still use the block)
+    if (!idle) (void)hipDeviceSynchronize();   // (nothing queued may still use the block)
     mem_put(p, bytes, device);
   }
   // A large block of the factor: from the caller's hook if one was given.
@@ -592,16 +594,22 @@ void precond_head(spp_factor* F, const double2* r, int nrhs, hipStream_t st) {
 }
 
 void precond_tail(spp_factor* F, double2* z, int nrhs, hipStream_t st, bool persistent) {
-  factor_ready(F, st);
+  // (with inverses still in the making, the substitution waits for them only
+  // before the levels that read them: the earlier levels' before the first
+  // such level, the last level's before it)
+  hipEvent_t early = F->inv_pending ? F->inv_event[2] : nullptr;
+  hipEvent_t last = F->inv_pending ? F->inv_event[1] : nullptr;
   persistent = persistent && (F->opt.flags & SPP_F_PERSISTENT);
   const int nl = static_cast<int>(F->planp->levels.size());
   const double* ent = F->pd->level_ent.data();
   if (F->opt.prec == SPP_C128) {
     mf_solve<double>(st, F->mf, F->fac, F->wv, F->zv, F->qr, z, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
-                     F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
+                     F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent, nullptr,
+                     early, last);
   } else {
     mf_solve<float>(st, F->mf, F->fac, F->wv, F->zv, F->xc, F->xc, nrhs, F->level_begin.data(), F->level_maxF.data(), F->level_maxK.data(),
-                    F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent);
+                    F->level_maxP.data(), ent, F->level_form.data(), nl, F->gpart, F->gpart_cap, persistent, nullptr,
+                    early, last);
     cast_vectors<float>(st, F->xc, z, (int64_t)nrhs * F->Ntot, 1);
   }
 }
@@ -657,17 +665,18 @@ void validate_problem(const spp_problem* pb) {
 // substitution products (right-hand-side count nrhs) and stores the fastest
 // in the process-wide tuning table (and its file, if SPP_TUNE_CACHE is set).
 void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
-  factor_ready(F, st);
   ensure_solve_buffers(F, nrhs, F->opt.max_iter);
   KernelTimer* saved = g_timer;
   g_timer = nullptr;
   const int64_t vstride = (int64_t)nrhs * F->Ntot;
-  // Scratch contents and the cache-flushing buffer are set up only when some
-  // key is missing (a factor whose shapes are all tuned costs nothing here).
+  // Scratch contents and the cache-flushing buffer are set up, and the factor's
+  // pending inverses waited for, only when some key is missing (a factor
+  // whose shapes are all tuned costs nothing here).
   const size_t flush_bytes = (size_t)768 << 20;
   void* flush = nullptr;
   auto prepare = [&] {
     if (flush) return;
+    factor_ready(F, st);   // (the candidates run on the complete factor)
     SPP_HIP(hipMemsetAsync(F->wk, 0, sizeof(double2) * vstride, st));
     SPP_HIP(hipMemsetAsync(F->tmp, 0, sizeof(double2) * vstride, st));
     SPP_HIP(hipMemsetAsync(F->qr, 0, sizeof(double2) * vstride, st));
@@ -1177,8 +1186,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   bool setup_bufs_freed = false;
   auto free_setup_bufs = [&] {
     if (setup_bufs_freed) return;
+    // (only the stencil work on st used them: a device-wide drain here would
+    // also wait for the last level's inverses on the side stream)
     SPP_HIP(hipStreamSynchronize(st));
-    for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p);
+    for (void* p : {(void*)red, (void*)sig_c, (void*)sig2_c, (void*)g, (void*)g2}) F->dfree(p, true);
     setup_bufs_freed = true;
   };
   const int nl = static_cast<int>(P.levels.size());
@@ -1222,6 +1233,8 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       // updates, grow with the front.
       const int piv = partial_pivoting ? kPivotPartial
                       : forms[l] == kFormBlocked ? kPivotTournament : kPivotBlockLocal;
+      // (the side stream's work for the earlier levels ends here)
+      if (overlap && l == nl - 1) SPP_HIP(hipEventRecord(F->inv_event[2], inv_st));
       if (F->opt.prec == SPP_C128)
         mf_factor_level<double>(st, mf, F->arena, xwork, tbuf, dinv, tpbuf, L.begin, L.end, L.maxF, L.maxP,
                                 L.blk_begin, L.blk_end, L.max_children, forms[l], piv, vars[l], hF, hP, inv_st,
@@ -1284,13 +1297,13 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
   if (F->inv_pending) {   // (still in use by the last inverses)
     F->inv_buffers = {xwork, tbuf};
     if (!any_blocked) F->inv_buffers.push_back(dinv);
-  } else {
-    F->dfree(xwork);
-    F->dfree(tbuf);
-    if (!any_blocked) F->dfree(dinv);
+  } else {   // (the inverses, if any, were joined to st, which has drained)
+    F->dfree(xwork, true);
+    F->dfree(tbuf, true);
+    if (!any_blocked) F->dfree(dinv, true);
   }
-  F->dfree(tpbuf);
-  F->dfree(swork);
+  F->dfree(tpbuf, true);   // (used on st only)
+  F->dfree(swork, true);
   if (streamed) {   // the substitution reads the factor store only
     F->big_free(F->arena);
     F->arena = nullptr;

@@ -221,7 +221,12 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena, void* w, void*
               const int* level_begin, const int* level_maxF, const int* level_maxK,
               const int* level_maxP, const double* level_ent, const int* level_form, int nlevels,
               void* partial, int64_t partial_cap, bool persistent,
-              hipEvent_t* level_events = nullptr);   // optional: 4 per level, see mf_solve
+              hipEvent_t* level_events = nullptr,   // optional: 4 per level, see mf_solve
+              hipEvent_t inv_early = nullptr, hipEvent_t inv_last = nullptr);
+// (inv_early / inv_last, optional: the stream waits for inv_early before the
+// first level solved by products except the last one, and for inv_last
+// before the last level if that one is solved by products; the explicit
+// inverses of those levels may still be in the making on another stream.)
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double);

@@ -3032,7 +3032,8 @@ template <typename R>
 void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, void* z_v, const void* x_in,
               void* x_out, int nrhs, const int* level_begin, const int* level_maxF, const int* level_maxK,
               const int* level_maxP, const double* level_ent, const int* level_form, int nlevels, void* partial_v,
-              int64_t partial_cap, bool persistent, hipEvent_t* level_events) {
+              int64_t partial_cap, bool persistent, hipEvent_t* level_events, hipEvent_t inv_early,
+              hipEvent_t inv_last) {
   using C = cplx_t<R>;
   // level_events (tuning): events 4 l and 4 l + 1 bracket level l's forward
   // part, 4 l + 2 and 4 l + 3 its backward part (levels one at a time).
@@ -3176,6 +3177,11 @@ void mf_solve(hipStream_t st, const MfDev& mf, const void* arena_v, void* w_v, v
     const int f0 = level_begin[l], nf = level_begin[l + 1] - f0;
     const int mK = level_maxK[l], mP = level_maxP[l];
     const double* e = level_ent + 3 * l;
+    if (level_form[l] == kFormInverse || level_form[l] == kFormSide) {
+      hipEvent_t& w = (l == nlevels - 1) ? inv_last : inv_early;
+      if (w) SPP_HIP(hipStreamWaitEvent(st, w, 0));
+      w = nullptr;
+    }
     if (level_events) SPP_HIP(hipEventRecord(ev(l, 0), st));
     const Mark done{ev(l, 1), st};
     if (level_form[l] == kFormLU) {
@@ -3252,10 +3258,10 @@ template void mf_factor_level<float>(hipStream_t, const MfDev&, void*, void*, vo
                                      int, int, int, int, const int*, const int*, hipStream_t, hipEvent_t);
 template void mf_solve<double>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                                const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
-                               int64_t, bool, hipEvent_t*);
+                               int64_t, bool, hipEvent_t*, hipEvent_t, hipEvent_t);
 template void mf_solve<float>(hipStream_t, const MfDev&, const void*, void*, void*, const void*, void*, int,
                               const int*, const int*, const int*, const int*, const double*, const int*, int, void*,
-                              int64_t, bool, hipEvent_t*);
+                              int64_t, bool, hipEvent_t*, hipEvent_t, hipEvent_t);
 template void mf_gemv<double>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,
                               double, void*, int64_t, int);
 template void mf_gemv<float>(hipStream_t, const MfDev&, const void*, void*, void*, void*, const void*, int, int, int, int, int, int,
