@@ -48,7 +48,8 @@
  *    beside the stencils and the next level's LU.  spp_setup returns once
  *    the LU is complete; the last inverses may still run.  Every later call
  *    that reads the factor, on any stream, waits for them on that stream
- *    first, so the caller needs no synchronisation of its own.
+ *    before its first read of them, so the caller needs no synchronisation
+ *    of its own.
  *  - Every function returns SPP_OK (0) or a negative error code; no C++
  *    exception crosses this boundary.  spp_last_error() gives a message for
  *    the most recent failure on the calling thread.
