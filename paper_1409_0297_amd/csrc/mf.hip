@@ -454,6 +454,7 @@ struct DiagLds {
   cplx_t<R> Lm[kDB][kDB + 1];   // the previous step's L part (rows of this block)
   cplx_t<R> X[kDB][kDB + 1];    // the LU in pivot order
   int rsel[kDB];                // pivot row of each step
+  int kofr[kDB];                // pivot index of each row of the previous block
 };
 
 // Lane exchanges of one wave: the value of a uniform lane (a scalar read),
@@ -757,9 +758,11 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
     // free again, so the second product does not wait on memory; the block's
     // own entries come in with them, each lane taking those of its place in
     // the last product's output)
-    // (each thread's pivot row goes out first: its loads wait on it, and the
-    // memory counter waits in issue order)
-    const int pri = pr[tid & (kDB - 1)];
+    // ((P A)(prev, k) comes as the previous block's rows in their stored
+    // order, each landing at its pivot index, so those loads need not wait
+    // for pr)
+    const int i32 = tid & (kDB - 1);
+    const int pri = pr[i32];
     using V = typename Acc<R>::type;
     const int w = tid >> 6, lane = tid & 63, ba = 16 * (w % 2), bb = 16 * (w / 2);
     C akk[4];
@@ -769,14 +772,21 @@ __device__ __forceinline__ void diag_lu_block(const MfDev& mf, cplx_t<R>* __rest
       akk[r] = (row < kb && col < kb) ? A[(int64_t)col * F + row] : cmake<C>(row == col ? 1 : 0, 0);
     }
     constexpr int kPer = kDB * kDB / 256;
-    C up[kPer];
+    C up[kPer], xr[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int t = tid + 256 * u, c = t / kDB, i = t - c * kDB;
+      const int t = tid + 256 * u, c = t / kDB, i = t - c * kDB;   // (i = i32)
       Lm[i][c] = (i < kb) ? base[(int64_t)(kprev + c) * F + k0 + i] : cmake<C>(0, 0);   // A(k, prev)
-      X[i][c] = (c < kb) ? base[(int64_t)(k0 + c) * F + pri] : cmake<C>(0, 0);        // (P A)(prev, k), i = tid % 32
+      xr[u] = (c < kb) ? base[(int64_t)(k0 + c) * F + kprev + i] : cmake<C>(0, 0);      // A(prev, k), stored order
       D[i][c] = Lp[c * kDB + i];
       up[u] = Up[c * kDB + i];
+    }
+    if (tid < kDB) S.kofr[pri - kprev] = tid;
+    __syncthreads();
+    {
+      const int u_ = S.kofr[i32];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) X[u_][(tid + 256 * u) / kDB] = xr[u];   // (P A)(prev, k)
     }
     __syncthreads();
     // U(prev, k) = L_prev^{-1} X and L(k, prev) = A(k, prev) U_prev^{-1}: wave
@@ -1449,6 +1459,7 @@ template <typename R>
 struct FusedLds {
   cplx_t<R> Lt[kDB][kBM + 1];   // L21 rows of the tile by k (negated once formed)
   cplx_t<R> Ut[kDB][kBN + 1];   // U12 columns of the tile by k
+  int kofr[kDB];                // pivot index of each row of the block
 };
 
 template <typename R>
@@ -1478,15 +1489,22 @@ __device__ inline void fused_tile(const MfDev& mf, cplx_t<R>* __restrict__ arena
   // Linv (P A12).  The inverses' entries come from global memory (a few KB);
   // outside [0, kb) they are not written by the block LU, so the operands
   // are masked there (A21 and P A12 are zero beyond kb).
-  const int pru = (tid & (kDB - 1)) < kb ? pr[tid & (kDB - 1)] : 0;
-  // (A21 by rows of a column, P A12 by pivot rows of a column: the rows
-  // pr[u] of the block are a permutation of 32 consecutive rows, so either
-  // way a wave reads whole column segments; u = tid % 32 in every pass)
+  // A21 by rows of a column; P A12 as the block's rows k0 + i of a column
+  // in their stored order (the pivot rows pr[u] are a permutation of them),
+  // each landing in LDS at its pivot index: the loads need not wait for pr.
+  // (i = tid % 32 in every pass)
+  const int i32 = tid & (kDB - 1);
+  const int pru = i32 < kb ? pr[i32] : 0;
+  constexpr int kUp = kDB * kBN / 256;
+  C uraw[kUp];
+#pragma unroll
+  for (int q = 0; q < kUp; ++q) {
+    const int t = tid + 256 * q, c = t / kDB;
+    uraw[q] = (i32 < kb && c < nt) ? base[(int64_t)(k1 + n0 + c) * F + k0 + i32] : cmake<C>(0, 0);
+  }
   for (int t = tid; t < kDB * kBM; t += 256) {
     const int v = t / kBM, r = t - v * kBM;
     Lt[v][r] = (v < kb && r < mt) ? base[(int64_t)(k0 + v) * F + k1 + m0 + r] : cmake<C>(0, 0);   // A21
-    const int c = t / kDB, u = t - c * kDB;
-    Ut[u][c] = (u < kb && c < nt) ? base[(int64_t)(k1 + n0 + c) * F + pru] : cmake<C>(0, 0);       // P A12
   }
   const int li = lane & 15, lk = lane >> 4;
   C uv[2][kDB / 4], lv[2][kDB / 4];
@@ -1499,6 +1517,14 @@ __device__ inline void fused_tile(const MfDev& mf, cplx_t<R>* __restrict__ arena
       uv[b][t] = (k < kb && u < kb) ? Ui[u * kDB + k] : cmake<C>(0, 0);   // Uinv(k, u)
       lv[b][t] = (k < kb && u < kb) ? Li[k * kDB + u] : cmake<C>(0, 0);   // Linv(u, k)
     }
+  }
+  if (tid < kb) L.kofr[pru - k0] = tid;
+  __syncthreads();
+  {
+    // (rows past kb, of a ragged last block, stay zero at their own index)
+    const int u = i32 < kb ? L.kofr[i32] : i32;
+#pragma unroll
+    for (int q = 0; q < kUp; ++q) Ut[u][(tid + 256 * q) / kDB] = uraw[q];   // P A12
   }
   __syncthreads();
   using Vt = typename Acc<R>::type;
