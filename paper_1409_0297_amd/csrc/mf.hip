@@ -1166,6 +1166,11 @@ __device__ inline void gemm_tile_core(GemmLds<R, BM, BN>& L, const cplx_t<R>* __
   // Addresses are a tile base (uniform) plus 32-bit offsets inside the tile.
   C* __restrict__ Ct = Cp + (int64_t)n0 * ldc + m0;
   const int mt = m - m0, nt = n - n0;
+  kend = min(kend, k);
+  // (the first stage's row index of B goes out before the C tile: the memory
+  // counter waits in issue order, and the first B loads wait on it)
+  const int bkk = threadIdx.x % kBK;   // this thread's k row in every stage
+  const int brow0 = (brow && kbeg < kend) ? brow[bkk < kend - kbeg ? kbeg + bkk : 0] - brow_off : 0;
   V re[2][2], im[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -1180,7 +1185,6 @@ __device__ inline void gemm_tile_core(GemmLds<R, BM, BN>& L, const cplx_t<R>* __
         re[a][b][r] = c0.x;
         im[a][b][r] = c0.y;
       }
-  kend = min(kend, k);
   // Register prefetch: the next stage's operands are loaded while the
   // current stage runs on MFMA (one LDS buffer, two barriers per stage).
   constexpr int kPerA = BM * kBK / 256, kPerB = BN * kBK / 256;
@@ -1198,8 +1202,8 @@ __device__ inline void gemm_tile_core(GemmLds<R, BM, BN>& L, const cplx_t<R>* __
 #pragma unroll
     for (int u = 0; u < kPerB; ++u) {
       const int e = threadIdx.x + 256 * u;
-      const int kk = e % kBK, col = e / kBK;
-      const int br = brow ? brow[kk < kt ? kk0 + kk : 0] - brow_off : kk0 + kk;
+      const int kk = e % kBK, col = e / kBK;   // (kk = bkk)
+      const int br = brow ? (kk0 == kbeg ? brow0 : brow[kk < kt ? kk0 + kk : 0] - brow_off) : kk0 + kk;
       rb[u] = (kk < kt && col < nt) ? Bt[col * ldb + br] : cmake<C>(0, 0);
     }
   };
