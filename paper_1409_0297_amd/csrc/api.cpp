@@ -1083,7 +1083,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
       S.C = F->dalloc<double2>((size_t)S.nS * S.nG);
       S.Tt = F->dalloc<double2>((size_t)S.nS * S.nB);
       S.Ct = F->dalloc<double2>((size_t)S.nS * S.nG);
-      D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct};
+      // (complex64 fronts: the Q apply, whose output is complex64, reads T_S
+      // rounded to complex64, half the bytes per entry)
+      float2* tt32 = op->prec == SPP_C64_FRONTS ? F->dalloc<float2>((size_t)S.nS * S.nB) : nullptr;
+      D.types[t] = TypeDev{S.nS, S.nB, S.nG, S.off, S.T, S.C, S.Tt, S.Ct, tt32};
     }
   }
   F->inst_dev = F->dalloc<InstDev>(count);
@@ -1128,6 +1131,10 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     }
     // a3-a4: stencils per set type.
     stencil_build(st, I.d, I.n, g, g2, I.sten, (int)I.plan->types.size(), swork, info + 1, I.nc);
+    for (size_t t = 0; t < I.plan->types.size(); ++t)
+      if (idev[i].types[t].Tt32)
+        cast_vectors<float>(st, I.sten[t].Tt, const_cast<float2*>(idev[i].types[t].Tt32),
+                            (int64_t)I.sten[t].nS * I.sten[t].nB, 0);
   }
 
   // a5-a6: assembly and factorisation on the shared plan.

@@ -109,6 +109,7 @@ struct TypeDev {       // per set type, for assembly / Q apply
   const double2* C;
   const double2* Tt;
   const double2* Ct;
+  const float2* Tt32;   // Tt rounded to complex64 (factors of complex64 fronts), else null
 };
 
 // One problem of a batch: its grid, potential and stencils.  Grid vectors of

@@ -1908,7 +1908,14 @@ __global__ void q_apply_kernel(MfDev mf, const double2* __restrict__ r, O* __res
   for (int i = threadIdx.x; i < T.nS; i += blockDim.x) {
     const int64_t g = at(i);
     double2 s = rr[g];
-    for (int j = 0; j < T.nB; ++j) cfms(s, T.Tt[(int64_t)j * T.nS + i], rb[j]);
+    if (std::is_same<O, float2>::value && T.Tt32) {   // (accumulated in FP64 all the same)
+      for (int j = 0; j < T.nB; ++j) {
+        const float2 a = T.Tt32[(int64_t)j * T.nS + i];
+        cfms(s, make_double2(a.x, a.y), rb[j]);
+      }
+    } else {
+      for (int j = 0; j < T.nB; ++j) cfms(s, T.Tt[(int64_t)j * T.nS + i], rb[j]);
+    }
     yy[g].x = s.x;
     yy[g].y = s.y;
   }
