@@ -1132,7 +1132,7 @@ int do_setup(const spp_problem* pbs, int count, const spp_options* op, hipStream
     // a3-a4: stencils per set type.
     stencil_build(st, I.d, I.n, g, g2, I.sten, (int)I.plan->types.size(), swork, info + 1, I.nc);
     for (size_t t = 0; t < I.plan->types.size(); ++t)
-      if (idev[i].types[t].Tt32)
+      if (idev[i].types[t].Tt32 && (int64_t)I.sten[t].nS * I.sten[t].nB > 0)
         cast_vectors<float>(st, I.sten[t].Tt, const_cast<float2*>(idev[i].types[t].Tt32),
                             (int64_t)I.sten[t].nS * I.sten[t].nB, 0);
   }

@@ -3285,6 +3285,7 @@ void mf_store_factors(hipStream_t st, const MfDev& mf, const void* arena, void* 
 
 template <typename R>
 void cast_vectors(hipStream_t st, const void* in, void* out, int64_t count, int to_double) {
+  if (count <= 0) return;
   cast_kernel<R><<<ceil_div(count, 256), 256, 0, st>>>(in, out, count, to_double);
   SPP_LAUNCH_CHECK();
 }
