@@ -273,7 +273,8 @@ int spp_autotune(spp_factor* factor, int32_t nrhs, spp_stream_t stream);
    "<kind>@<arch>:<size>:<size>...", as the table file holds it.  Kinds:
      fft_lines    lines per workgroup of an FFT pass;
      gemv_chunks  column chunks of a substitution product over 64-row tiles
-                  (>= 1), or 0: 16-row tiles, columns not split;
+                  (1 .. 1023), or 0: 16-row tiles, columns not split, or
+                  1024 + c: 16-row tiles, columns split c ways;
      mf_form      solve form of a level, keyed by front bytes (8 complex64,
                   16 complex128), fronts, largest F, largest p:
                   0 LU in place, 1 inverses of L11 / U11, 2 side products;

@@ -733,18 +733,26 @@ void do_autotune(spp_factor* F, int nrhs, hipStream_t st) {
       int best = gemv_chunks_default(pr.rows, pr.cols, nf, nrhs, F->gpart_cap);
       float bt = 1e30f;
       // c = 0: 16-row tiles with the columns not split; c >= 1: 64-row tiles
-      // with the columns split over c workgroups.
-      for (int c = 0; c <= std::max(1, pr.cols / 16) && c <= 256; c = c ? 2 * c : 1) {
-        if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
+      // with the columns split over c workgroups; kGemvNarrowSplit + c (c >= 2):
+      // 16-row tiles with the columns split over c workgroups.
+      auto candidate = [&](int v) {
         const float t = tune_time(st, 3, [&] {
           if (F->opt.prec == SPP_C128)
             mf_gemv<double>(st, F->mf, F->fac, F->wv, F->zv, F->qr, F->qr, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
-                            0.0, F->gpart, F->gpart_cap, c);
+                            0.0, F->gpart, F->gpart_cap, v);
           else
             mf_gemv<float>(st, F->mf, F->fac, F->wv, F->zv, F->xc, F->xc, nrhs, L.begin, nf, pr.rows, pr.cols, pr.mode,
-                           0.0, F->gpart, F->gpart_cap, c);
+                           0.0, F->gpart, F->gpart_cap, v);
         }, flush, flush_bytes);
-        if (t < bt) { bt = t; best = c; }
+        if (t < bt) { bt = t; best = v; }
+      };
+      for (int c = 0; c <= std::max(1, pr.cols / 16) && c <= 256; c = c ? 2 * c : 1) {
+        if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
+        candidate(c);
+      }
+      for (int c = 2; c <= std::max(1, pr.cols / 64) && c <= 64; c *= 2) {
+        if ((int64_t)nf * c * pr.rows * nrhs > F->gpart_cap) break;
+        candidate(kGemvNarrowSplit + c);
       }
       tune_set(key, best);
     }

@@ -313,9 +313,11 @@ std::string fft_tune_key(int n, int64_t outer, int64_t inner, int batch);
 void mf_reset_status(hipStream_t st, const MfDev& mf, int nfronts);
 
 // One substitution product (gemv_kernel mode) of a level of fronts with a
-// given split-K chunk count over 64-row tiles (>= 1), or 16-row tiles with
-// the columns not split (0), or the tuned or heuristic choice (< 0); mf.hip.
+// given split-K chunk count over 64-row tiles (1 .. kGemvNarrowSplit - 1),
+// or 16-row tiles with the columns not split (0) or split c ways
+// (kGemvNarrowSplit + c), or the tuned or heuristic choice (< 0); mf.hip.
 // xin: the forward input (read by mode 4, which gathers its own vector).
+constexpr int kGemvNarrowSplit = 1024;
 template <typename R>
 void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena, void* W, void* Z, void* xout, const void* xin, int nrhs,
              int f0, int nf, int rows, int cols, int mode, double ent, void* partial, int64_t partial_cap, int nchunks);

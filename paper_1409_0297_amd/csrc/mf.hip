@@ -3027,7 +3027,13 @@ void mf_gemv(hipStream_t st, const MfDev& mf, const void* arena_v, void* W_v, vo
   if (nchunks < 0)
     nchunks = tune_get(gemv_tune_key(rows, cols, nf, mode, nrhs, (int)sizeof(C)),
                        gemv_chunks_default(rows, cols, nf, nrhs, partial_cap));
-  const bool narrow = nchunks == 0;   // (16-row tiles, columns not split)
+  // (0: 16-row tiles, columns not split; kGemvNarrowSplit + c: 16-row tiles,
+  // columns split c ways; else 64-row tiles, columns split nchunks ways)
+  bool narrow = nchunks == 0;
+  if (nchunks >= kGemvNarrowSplit) {
+    narrow = true;
+    nchunks -= kGemvNarrowSplit;
+  }
   const int rt = narrow ? 16 : 64;
   const int rtiles = (int)ceil_div(rows, rt);
   nchunks = std::max(1, std::min(nchunks, std::max(1, cols)));
