@@ -64,9 +64,10 @@ def test_autotune_and_every_schedule_keep_the_solution(tmp_path, monkeypatch, na
             assert int(value) >= 1
         assert binding.spp_tune_get(key) == int(value)
     # Every product shape of the substitution on 16-row tiles, then on 64-row
-    # tiles without a column split, then split in two: the same solution.
+    # tiles without a column split, then split in two, then on 16-row tiles
+    # split in two (1024 + 2): the same solution.
     try:
-        for c in (0, 1, 2):
+        for c in (0, 1, 2, 1026):
             for key, _ in gemv_keys:
                 binding.spp_tune_set(key, c)
             C = Solver(W.kind, W.n, W.d, W.b, W.coeff, **kw)
